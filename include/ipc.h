@@ -1,0 +1,180 @@
+/*
+ * ipc.h -- C-ABI of the MI355X (gfx950) incremental-potential contact solver.
+ *
+ * What the library computes: the implicit time step of the paper's IPC grasp
+ * simulator (GRIP, Sec. III-A "IPC Simulator with Parallel Environment"):
+ * for every environment, x^{n+1} = argmin of the incremental potential
+ *
+ *   Phi(x) = sum_i m_i |x_i - xhat_i|^2 / (2 dt^2)         inertia, xhat = x^n + dt v^n + dt^2 g
+ *          + sum_e V_e Psi_NH(F_e)                         Neo-Hookean tetrahedra
+ *          + kappa sum_k e_k b(d_k),  b(d) = -(d-dhat)^2 ln(d/dhat)  point-triangle / edge-edge barrier
+ *          + sum_k mu lambda_k f0(|u_k|)                   lagged smoothed friction (eps_v dt)
+ *
+ * solved by projected Newton with an additive-CCD step bound and a
+ * backtracking line search ("barrier augmentation, CCD and projected Newton
+ * with a step-size filter", Sec. II-C).  Environments are isolated: no
+ * contact pairs across environments, each has its own CCD step size and line
+ * search, its own stopping test, and a failure (no convergence within
+ * newton_max_iter = 100, Sec. III-D) freezes only that environment
+ * (problems (i)-(iv) of Sec. III-A).  Solver constants default to those of
+ * Sec. III-D: dt = 0.01 s, kappa = 3e6 kg/s^2, dhat = 1e-3 m, eps_v = 1e-3 m/s,
+ * FP64.
+ *
+ * Conventions
+ *   - All floating-point data are FP64, SI units.  Positions and velocities
+ *     are row-major [n][3]; indices are int32.
+ *   - Pointers passed in are host pointers unless stated; the library copies
+ *     every input at create time and never keeps a caller pointer.  Output
+ *     buffers are owned by the caller.
+ *   - Return value: 0 on success, a negative IPC_E_* code on error; the
+ *     message of the last error on the calling thread is ipc_last_error().
+ *   - One scene handle must not be used from two threads at once; distinct
+ *     handles may.  All scenes live on the current HIP device at creation.
+ */
+#ifndef IPC_MI355X_H
+#define IPC_MI355X_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define IPC_OK 0
+#define IPC_E_ARG (-1)          /* bad sizes, indices, NaN/Inf, dt <= 0, dhat <= 0, ...          */
+#define IPC_E_INVERTED (-2)     /* a tet has det(Dm) <= 0 at rest or J <= 0 initially            */
+#define IPC_E_INTERSECTING (-3) /* initial configuration intersects (IPC precondition, Sec. III-C) */
+#define IPC_E_NOMEM (-4)        /* device allocation failed / memory budget exceeded             */
+#define IPC_E_FAILED (-5)       /* environment failed (Sec. III-A, III-D); scene is frozen       */
+#define IPC_E_DEVICE (-6)       /* HIP runtime error                                             */
+
+/* fail_reason values reported in ipc_step_info */
+#define IPC_FAIL_NONE 0
+#define IPC_FAIL_MAXIT 1     /* Newton did not converge in newton_max_iter iterations (Sec. III-D) */
+#define IPC_FAIL_NONFINITE 2 /* non-finite gradient or search direction                          */
+#define IPC_FAIL_LS 3        /* more than 40 line-search halvings                                 */
+#define IPC_FAIL_DBC 4       /* prescribed kinematic move is not CCD-safe / inverts a tet         */
+
+#define IPC_FP64 0  /* every step in FP64 */
+#define IPC_MIXED 1 /* PCG matrix, preconditioner and vectors in FP32, dot products in FP64 */
+
+typedef struct ipc_scene_s *ipc_scene;
+
+typedef struct {
+  int32_t n_verts;
+  const double *rest_pos;   /* [n_verts*3] rest positions                                   */
+  const double *init_pos;   /* [n_verts*3] or NULL (= rest_pos)                             */
+  const double *init_vel;   /* [n_verts*3] or NULL (= 0)                                    */
+  int32_t n_tets;
+  const int32_t *tets;      /* [n_tets*4], positively oriented: det[X1-X0,X2-X0,X3-X0] > 0  */
+  const double *E, *nu, *rho; /* [n_tets] Young's modulus (Pa), Poisson ratio, density      */
+  int32_t n_tris;
+  const int32_t *tris;      /* [n_tris*3] kinematic-only surfaces (ground, rigid links)     */
+  const int32_t *kin_group; /* [n_verts] -1 = free vertex, g >= 0 = driven by group g        */
+  int32_t n_groups, n_motion_steps;
+  const double *motion;     /* [n_motion_steps][n_groups][12] row-major 3x4 [R|t]: the target
+                               of a group-g vertex at step n is R X + t, X = its rest position;
+                               step n uses row min(n, n_motion_steps-1)                      */
+  const double *gravity;    /* [n_motion_steps][3]; the step n -> n+1 uses row min(n, last)   */
+  double dt, dhat, kappa, mu, eps_v; /* 0.01, 1e-3, 3e6, friction coefficient, 1e-3          */
+  double newton_tol;        /* converged when |p|_inf <= newton_tol * dt (p = Newton step)   */
+  int32_t newton_max_iter;  /* 100 (Sec. III-D)                                             */
+  double pcg_rel_tol;       /* PCG stops at |r|_2 <= pcg_rel_tol |g|_2 (1e-4 default, 1e-8 for parity) */
+  int32_t precision;        /* IPC_FP64 or IPC_MIXED                                        */
+} ipc_scene_desc;
+
+typedef struct {
+  int32_t steps_done;       /* time steps completed by this call                             */
+  int32_t status;           /* IPC_OK or IPC_E_FAILED                                        */
+  int32_t fail_reason;      /* IPC_FAIL_*                                                    */
+  int32_t newton_iters;     /* total Newton iterations (search directions computed)          */
+  int32_t max_newton_iters; /* largest per-step count                                        */
+  int32_t ls_halvings;      /* total line-search halvings                                    */
+  int64_t pcg_iters;        /* total PCG iterations                                          */
+  int64_t n_active_last;    /* active contact pairs at the last accepted iterate             */
+  double min_dist_last;     /* unused by the GPU path (0)                                     */
+  double energy_last;       /* Phi at the last accepted iterate                              */
+} ipc_step_info;
+
+/* Create a scene from host data (copied).  Validates sizes, finiteness,
+ * orientation (IPC_E_INVERTED) and that the initial configuration is free of
+ * intersections (IPC_E_INTERSECTING): the IPC precondition of Sec. III-C.
+ * Allocates device memory on the current device (IPC_E_NOMEM on failure). */
+int ipc_create_scene(const ipc_scene_desc *desc, ipc_scene *out);
+
+/* Advance one scene by n_steps time steps (Sec. III-A).  info may be NULL.
+ * Returns IPC_E_FAILED if the scene fails; it is then frozen at its last
+ * accepted step and later calls return IPC_E_FAILED without changing it. */
+int ipc_step(ipc_scene s, int32_t n_steps, ipc_step_info *info);
+
+/* Advance n scenes together: every kernel covers all of them, while each
+ * keeps its own CCD bound, line search, stopping test and failure state
+ * (Sec. III-A).  infos may be NULL or point to n records.  Returns IPC_OK if
+ * every scene completed all steps, else IPC_E_FAILED (see infos). */
+int ipc_step_batch(ipc_scene *scenes, int32_t n, int32_t n_steps, ipc_step_info *infos);
+
+/* Copy the current state to host buffers: pos [n_verts*3]; vel [n_verts*3]
+ * or NULL; cauchy [n_tets*6] (xx,yy,zz,yz,xz,xy) or NULL; von_mises
+ * [n_tets] or NULL (per-tet stress output, Sec. IV-D). */
+int ipc_get_state(ipc_scene s, double *pos, double *vel, double *cauchy, double *von_mises);
+
+/* Overwrite positions/velocities (vel NULL = 0) and the step index; clears a
+ * failed flag.  Used for checkpoint / resume. */
+int ipc_set_state(ipc_scene s, const double *pos, const double *vel, int32_t step);
+
+void ipc_destroy_scene(ipc_scene s);
+const char *ipc_last_error(void);
+
+/* Sizes of a scene: out[0] verts, out[1] tets, out[2] surface triangles,
+ * out[3] surface edges, out[4] surface vertices, out[5] current step index,
+ * out[6] failed flag. */
+int ipc_scene_sizes(ipc_scene s, int64_t out[7]);
+
+/* ---------------------------------------------------------------------------
+ * Inspection entry points.  Each runs the same device kernels the step uses,
+ * on host-supplied positions, so callers can check individual stages.
+ * Pair rows are (kind, v0, v1, v2, v3): kind 0 = point-triangle (v0 the
+ * point, v1<v2<v3 the triangle), kind 1 = edge-edge (v0<v1 and v2<v3 the
+ * edges, (v0,v1) < (v2,v3)).
+ * ------------------------------------------------------------------------- */
+
+/* Candidate pairs whose d-hat-widened boxes overlap at x (p == NULL) or over
+ * the sweep x -> x+p.  Writes min(count, cap) rows to out [cap*5]; returns
+ * the count or a negative error. */
+int64_t ipc_debug_candidates(ipc_scene s, const double *x, const double *p, int32_t *out, int64_t cap);
+
+/* Active pairs (d^2 < dhat^2) at x: rows (kind, v0..v3, type) into out
+ * [cap*6], squared distances into d2 [cap] (may be NULL). */
+int64_t ipc_debug_active(ipc_scene s, const double *x, int32_t *out, double *d2, int64_t cap);
+
+/* Prepare the step n -> n+1 at the current state (kinematic targets,
+ * predicted positions, lagged friction, Dirichlet move) without advancing;
+ * the starting iterate is written to x_start [n_verts*3] (may be NULL). */
+int ipc_debug_begin_step(ipc_scene s, double *x_start);
+
+/* Gradient of Phi at x (kinematic rows 0) for the prepared step. */
+int ipc_debug_gradient(ipc_scene s, const double *x, double *g);
+
+/* Phi at x for the prepared step (+inf if infeasible). */
+double ipc_debug_energy(ipc_scene s, const double *x);
+
+/* y = H v with H the PSD-projected Hessian at x (kinematic rows: identity). */
+int ipc_debug_hessian_apply(ipc_scene s, const double *x, const double *v, double *y);
+
+/* Newton search direction at x (solves H p = -g with block-Jacobi PCG). */
+int ipc_debug_newton_dir(ipc_scene s, const double *x, double *p, int64_t *pcg_iters);
+
+/* CCD step bound min(1, additive-CCD time of impact) over the sweep x -> x+p. */
+double ipc_debug_ccd_bound(ipc_scene s, const double *x, const double *p);
+
+/* Element routines evaluated by device code (one element per call). */
+int ipc_debug_classify(int32_t kind, int64_t n, const double *x12, int32_t *types, double *d2);
+int ipc_debug_pair_barrier(int32_t kind, int32_t type, const double *x12, double dhat, double kappa,
+                           double eps_x, int32_t project, double *energy, double *g12, double *H144);
+int ipc_debug_tet_elastic(const double *X12, const double *x12, double E, double nu, int32_t project,
+                          double *energy, double *g12, double *H144);
+int64_t ipc_debug_accd(int32_t kind, int64_t n, const double *x12, const double *p12, double s, double *t);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,640 @@
+// device_math.h -- per-element device routines of the IPC time step.
+//
+// Distances, barrier, mollifier, friction, Neo-Hookean elasticity, PSD
+// projection and additive CCD for one element.  The derivative formulas here
+// are derived by hand (see the comments); they are independent of the CPU
+// oracle, which differentiates the energies automatically.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define DEV __device__ __forceinline__
+#define HD __host__ __device__ inline
+
+namespace ipcdev {
+
+constexpr double kInf = __builtin_huge_val();
+
+struct d3 {
+  double x, y, z;
+};
+HD d3 ld3(const double *p) { return {p[0], p[1], p[2]}; }
+
+// -- exact-sequence vector ops (no contraction: the classification and the
+//    active test must reproduce the host's rounding bit for bit) -------------
+HD d3 sub3(d3 a, d3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+HD double dot3(d3 a, d3 b) {
+#pragma clang fp contract(off)
+  return a.x * b.x + a.y * b.y + a.z * b.z;
+}
+HD d3 cross3(d3 a, d3 b) {
+#pragma clang fp contract(off)
+  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+
+// -- pair classification ------------------------------------------------------
+// PT pair (p, t0, t1, t2): 0 interior, 1..3 point-edge (t0,t1),(t1,t2),(t2,t0),
+// 4..6 point-point t0,t1,t2.  EE pair (a0, a1, b0, b1): 0 interior, 1 a0|b,
+// 2 a1|b, 3 b0|a, 4 b1|a, 5 a0-b0, 6 a0-b1, 7 a1-b0, 8 a1-b1.
+enum { PS_A = 0, PS_B = 1, PS_E = 2 };
+
+HD int point_seg(d3 p, d3 a, d3 b, double *d2) {
+#pragma clang fp contract(off)
+  d3 e = sub3(b, a);
+  d3 w = sub3(p, a);
+  double ee = dot3(e, e);
+  if (!(ee > 0.0)) {
+    *d2 = dot3(w, w);
+    return PS_A;
+  }
+  double s = dot3(w, e) / ee;
+  if (s <= 0.0) {
+    *d2 = dot3(w, w);
+    return PS_A;
+  }
+  if (s >= 1.0) {
+    d3 q = sub3(p, b);
+    *d2 = dot3(q, q);
+    return PS_B;
+  }
+  d3 c = cross3(w, e);
+  *d2 = dot3(c, c) / ee;
+  return PS_E;
+}
+
+HD int classify_pt(d3 p, d3 t0, d3 t1, d3 t2, double *d2out) {
+#pragma clang fp contract(off)
+  d3 e1 = sub3(t1, t0), e2 = sub3(t2, t0), w = sub3(p, t0);
+  double a = dot3(e1, e1), b = dot3(e1, e2), c = dot3(e2, e2), d = dot3(e1, w), e = dot3(e2, w);
+  double det = a * c - b * b;
+  if (det > 0.0) {
+    double b1 = (c * d - b * e) / det;
+    double b2 = (a * e - b * d) / det;
+    if (b1 >= 0.0 && b2 >= 0.0 && b1 + b2 <= 1.0) {
+      d3 n = cross3(e1, e2);
+      double wn = dot3(w, n);
+      *d2out = wn * wn / dot3(n, n);
+      return 0;
+    }
+  }
+  double best = kInf;
+  int type = -1;
+  d3 T[3] = {t0, t1, t2};
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    double d2;
+    int k = point_seg(p, T[j], T[j == 2 ? 0 : j + 1], &d2);
+    if (d2 < best) {
+      best = d2;
+      type = (k == PS_E) ? 1 + j : (k == PS_A ? 4 + j : 4 + (j == 2 ? 0 : j + 1));
+    }
+  }
+  *d2out = best;
+  return type;
+}
+
+HD int classify_ee(d3 a0, d3 a1, d3 b0, d3 b1, double *d2out) {
+#pragma clang fp contract(off)
+  d3 ea = sub3(a1, a0), eb = sub3(b1, b0), w = sub3(a0, b0);
+  d3 n = cross3(ea, eb);
+  double nn = dot3(n, n);
+  double A = dot3(ea, ea), B = dot3(ea, eb), C = dot3(eb, eb), D = dot3(ea, w), E = dot3(eb, w);
+  if (nn > 1e-12 * A * C) {
+    double det = A * C - B * B;
+    double s = (B * E - C * D) / det;
+    double t = (A * E - B * D) / det;
+    if (s > 0.0 && s < 1.0 && t > 0.0 && t < 1.0) {
+      double wn = dot3(w, n);
+      *d2out = wn * wn / nn;
+      return 0;
+    }
+  }
+  const int ppA[4] = {5, 7, 5, 6}, ppB[4] = {6, 8, 7, 8};
+  d3 P[4] = {a0, a1, b0, b1};
+  double best = kInf;
+  int type = -1;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    double d2;
+    int r = (k < 2) ? point_seg(P[k], b0, b1, &d2) : point_seg(P[k], a0, a1, &d2);
+    if (d2 < best) {
+      best = d2;
+      type = (r == PS_E) ? 1 + k : (r == PS_A ? ppA[k] : ppB[k]);
+    }
+  }
+  *d2out = best;
+  return type;
+}
+
+HD int classify(int kind, const double *x, double *d2) {
+  return kind == 0 ? classify_pt(ld3(x), ld3(x + 3), ld3(x + 6), ld3(x + 9), d2)
+                   : classify_ee(ld3(x), ld3(x + 3), ld3(x + 6), ld3(x + 9), d2);
+}
+
+// -- squared distance of a classified pair with derivatives --------------------
+// Every type is d^2(x) = min_beta |r(x, beta)|^2 with r = sum_i c_i(beta) x_i
+// and c affine in the parameters beta (none for point-point, the segment
+// parameter for point-edge, the barycentric pair for point-triangle, the two
+// segment parameters for edge-edge).  At the minimiser (envelope theorem):
+//   grad_i d^2   = 2 c_i r
+//   hess_ij d^2  = 2 c_i c_j I - 2 sum_kl Ginv_kl u_ik u_jl^T,
+//   q_k = sum_i (dc_i/dbeta_k) x_i,  G_kl = q_k . q_l,  u_ik = c_i q_k + (dc_i/dbeta_k) r.
+struct TypeGeo {
+  int nb;           // number of parameters
+  double c[4];      // coefficient of each pair slot
+  double dc[2][4];  // d c / d beta_k
+  int n_involved;
+  int involved[4];
+};
+
+DEV void type_geometry(int kind, int type, const double *x, TypeGeo &T) {
+  for (int i = 0; i < 4; ++i) {
+    T.c[i] = 0.0;
+    T.dc[0][i] = 0.0;
+    T.dc[1][i] = 0.0;
+  }
+  d3 P[4] = {ld3(x), ld3(x + 3), ld3(x + 6), ld3(x + 9)};
+  if (type == 0) {
+    T.n_involved = 4;
+    for (int i = 0; i < 4; ++i) T.involved[i] = i;
+    T.nb = 2;
+    if (kind == 0) {  // r = p - t0 - b1 (t1 - t0) - b2 (t2 - t0)
+      d3 e1 = sub3(P[2], P[1]), e2 = sub3(P[3], P[1]), w = sub3(P[0], P[1]);
+      double a = dot3(e1, e1), b = dot3(e1, e2), c = dot3(e2, e2), d = dot3(e1, w), e = dot3(e2, w);
+      double det = a * c - b * b;
+      double b1 = (c * d - b * e) / det, b2 = (a * e - b * d) / det;
+      T.c[0] = 1.0;
+      T.c[1] = -(1.0 - b1 - b2);
+      T.c[2] = -b1;
+      T.c[3] = -b2;
+      T.dc[0][1] = 1.0;
+      T.dc[0][2] = -1.0;
+      T.dc[1][1] = 1.0;
+      T.dc[1][3] = -1.0;
+    } else {  // r = a0 + s (a1 - a0) - b0 - t (b1 - b0)
+      d3 ea = sub3(P[1], P[0]), eb = sub3(P[3], P[2]), w = sub3(P[0], P[2]);
+      double A = dot3(ea, ea), B = dot3(ea, eb), C = dot3(eb, eb), D = dot3(ea, w), E = dot3(eb, w);
+      double det = A * C - B * B;
+      double s = (B * E - C * D) / det, t = (A * E - B * D) / det;
+      T.c[0] = 1.0 - s;
+      T.c[1] = s;
+      T.c[2] = -(1.0 - t);
+      T.c[3] = -t;
+      T.dc[0][0] = -1.0;
+      T.dc[0][1] = 1.0;
+      T.dc[1][2] = 1.0;
+      T.dc[1][3] = -1.0;
+    }
+    return;
+  }
+  // sub-types: point-edge (point, a, b) or point-point (point, other)
+  int sp, sa, sb = -1;
+  if (kind == 0) {
+    if (type <= 3) {
+      sp = 0;
+      sa = type;
+      sb = (type == 3) ? 1 : type + 1;
+    } else {
+      sp = 0;
+      sa = type - 3;
+    }
+  } else {
+    const int pe[4][3] = {{0, 2, 3}, {1, 2, 3}, {2, 0, 1}, {3, 0, 1}};
+    const int pp[4][2] = {{0, 2}, {0, 3}, {1, 2}, {1, 3}};
+    if (type <= 4) {
+      sp = pe[type - 1][0];
+      sa = pe[type - 1][1];
+      sb = pe[type - 1][2];
+    } else {
+      sp = pp[type - 5][0];
+      sa = pp[type - 5][1];
+    }
+  }
+  if (sb < 0) {  // r = p - q
+    T.nb = 0;
+    T.n_involved = 2;
+    T.involved[0] = sp;
+    T.involved[1] = sa;
+    T.c[sp] = 1.0;
+    T.c[sa] = -1.0;
+    return;
+  }
+  // r = p - a - s (b - a)
+  d3 e = sub3(P[sb], P[sa]), w = sub3(P[sp], P[sa]);
+  double s = dot3(w, e) / dot3(e, e);
+  T.nb = 1;
+  T.n_involved = 3;
+  T.involved[0] = sp;
+  T.involved[1] = sa;
+  T.involved[2] = sb;
+  T.c[sp] = 1.0;
+  T.c[sa] = -(1.0 - s);
+  T.c[sb] = -s;
+  T.dc[0][sa] = 1.0;
+  T.dc[0][sb] = -1.0;
+}
+
+// z = d^2, gz[12], Hz[144] (row-major, zero outside the involved slots).
+DEV void d2_derivs(const double *x, const TypeGeo &T, double *z, double *gz, double *Hz) {
+  double r[3] = {0, 0, 0}, q[2][3] = {{0, 0, 0}, {0, 0, 0}};
+  for (int i = 0; i < 4; ++i)
+    for (int k = 0; k < 3; ++k) {
+      r[k] += T.c[i] * x[3 * i + k];
+      q[0][k] += T.dc[0][i] * x[3 * i + k];
+      q[1][k] += T.dc[1][i] * x[3 * i + k];
+    }
+  *z = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+  for (int i = 0; i < 4; ++i)
+    for (int k = 0; k < 3; ++k) gz[3 * i + k] = 2.0 * T.c[i] * r[k];
+  double Gi[2][2] = {{0, 0}, {0, 0}};
+  if (T.nb == 1) {
+    Gi[0][0] = 1.0 / (q[0][0] * q[0][0] + q[0][1] * q[0][1] + q[0][2] * q[0][2]);
+  } else if (T.nb == 2) {
+    double g00 = q[0][0] * q[0][0] + q[0][1] * q[0][1] + q[0][2] * q[0][2];
+    double g01 = q[0][0] * q[1][0] + q[0][1] * q[1][1] + q[0][2] * q[1][2];
+    double g11 = q[1][0] * q[1][0] + q[1][1] * q[1][1] + q[1][2] * q[1][2];
+    double id = 1.0 / (g00 * g11 - g01 * g01);
+    Gi[0][0] = g11 * id;
+    Gi[1][1] = g00 * id;
+    Gi[0][1] = Gi[1][0] = -g01 * id;
+  }
+  double u[4][2][3];
+  for (int i = 0; i < 4; ++i)
+    for (int k = 0; k < 2; ++k)
+      for (int m = 0; m < 3; ++m) u[i][k][m] = T.c[i] * q[k][m] + T.dc[k][i] * r[m];
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j)
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+          double v = (a == b) ? 2.0 * T.c[i] * T.c[j] : 0.0;
+          for (int k = 0; k < T.nb; ++k)
+            for (int l = 0; l < T.nb; ++l) v -= 2.0 * Gi[k][l] * u[i][k][a] * u[j][l][b];
+          Hz[(3 * i + a) * 12 + 3 * j + b] = v;
+        }
+}
+
+// -- barrier ----------------------------------------------------------------
+DEV void barrier_b(double d, double dhat, double *b0, double *b1, double *b2) {
+  if (d >= dhat) {
+    *b0 = *b1 = *b2 = 0.0;
+    return;
+  }
+  double r = d - dhat, L = log(d / dhat);
+  *b0 = -r * r * L;
+  *b1 = -2.0 * r * L - r * r / d;
+  *b2 = -2.0 * L - 4.0 * r / d + r * r / (d * d);
+}
+
+// c = |ea x eb|^2 and its derivatives in the 12 pair coordinates:
+//   grad_ea c = 2 eb x n, grad_eb c = 2 n x ea;
+//   Hess over (ea, eb) = 2 M^T M + [[0, -2[n]x], [2[n]x, 0]],  M = [-[eb]x, [ea]x].
+DEV void cross_norm2_derivs(const double *x, double *c, double *gc, double *Hc) {
+  d3 ea = sub3(ld3(x + 3), ld3(x)), eb = sub3(ld3(x + 9), ld3(x + 6));
+  d3 n = cross3(ea, eb);
+  *c = dot3(n, n);
+  d3 ga = cross3(eb, n), gb = cross3(n, ea);
+  double GA[3] = {2 * ga.x, 2 * ga.y, 2 * ga.z}, GB[3] = {2 * gb.x, 2 * gb.y, 2 * gb.z};
+  for (int k = 0; k < 3; ++k) {
+    gc[k] = -GA[k];
+    gc[3 + k] = GA[k];
+    gc[6 + k] = -GB[k];
+    gc[9 + k] = GB[k];
+  }
+  // M = [-[eb]x, [ea]x] (3x6); [v]x w = v x w
+  double EA[3] = {ea.x, ea.y, ea.z}, EB[3] = {eb.x, eb.y, eb.z}, N[3] = {n.x, n.y, n.z};
+  double M[3][6];
+  auto skew = [](const double *v, double S[3][3]) {
+    S[0][0] = 0;
+    S[0][1] = -v[2];
+    S[0][2] = v[1];
+    S[1][0] = v[2];
+    S[1][1] = 0;
+    S[1][2] = -v[0];
+    S[2][0] = -v[1];
+    S[2][1] = v[0];
+    S[2][2] = 0;
+  };
+  double SA[3][3], SB[3][3], SN[3][3];
+  skew(EA, SA);
+  skew(EB, SB);
+  skew(N, SN);
+  for (int r = 0; r < 3; ++r)
+    for (int k = 0; k < 3; ++k) {
+      M[r][k] = -SB[r][k];
+      M[r][3 + k] = SA[r][k];
+    }
+  double H6[6][6];
+  for (int a = 0; a < 6; ++a)
+    for (int b = 0; b < 6; ++b) {
+      double s = 0.0;
+      for (int r = 0; r < 3; ++r) s += M[r][a] * M[r][b];
+      H6[a][b] = 2.0 * s;
+    }
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      H6[a][3 + b] += -2.0 * SN[a][b];
+      H6[3 + a][b] += 2.0 * SN[a][b];
+    }
+  // map (ea, eb) -> (a0, a1, b0, b1): ea = a1 - a0, eb = b1 - b0
+  const double sgn[4] = {-1.0, 1.0, -1.0, 1.0};
+  const int grp[4] = {0, 0, 1, 1};
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j)
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+          Hc[(3 * i + a) * 12 + 3 * j + b] = sgn[i] * sgn[j] * H6[3 * grp[i] + a][3 * grp[j] + b];
+}
+
+// -- PSD projection: cyclic Jacobi, negative eigenvalues clamped to 0 ----------
+// A is n x n row-major with leading dimension ld; V is scratch of n*n.
+DEV void psd_project(int n, double *A, int ld, double *V) {
+  double fro = 0.0;
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) fro += A[i * ld + j] * A[i * ld + j];
+  if (fro == 0.0) return;
+  fro = sqrt(fro);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) V[i * n + j] = (i == j) ? 1.0 : 0.0;
+  for (int sweep = 0; sweep < 50; ++sweep) {
+    double off = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = i + 1; j < n; ++j) off += 2.0 * A[i * ld + j] * A[i * ld + j];
+    if (sqrt(off) <= 1e-15 * fro) break;
+    for (int p = 0; p < n - 1; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        double apq = A[p * ld + q];
+        if (apq == 0.0) continue;
+        double theta = (A[q * ld + q] - A[p * ld + p]) / (2.0 * apq);
+        double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+        double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+        for (int k = 0; k < n; ++k) {
+          double akp = A[k * ld + p], akq = A[k * ld + q];
+          A[k * ld + p] = c * akp - s * akq;
+          A[k * ld + q] = s * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {
+          double apk = A[p * ld + k], aqk = A[q * ld + k];
+          A[p * ld + k] = c * apk - s * aqk;
+          A[q * ld + k] = s * apk + c * aqk;
+        }
+        for (int k = 0; k < n; ++k) {
+          double vkp = V[k * n + p], vkq = V[k * n + q];
+          V[k * n + p] = c * vkp - s * vkq;
+          V[k * n + q] = s * vkp + c * vkq;
+        }
+      }
+  }
+  double lam[12];
+  for (int k = 0; k < n; ++k) lam[k] = fmax(A[k * ld + k], 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int j = i; j < n; ++j) {
+      double acc = 0.0;
+      for (int k = 0; k < n; ++k) acc += V[i * n + k] * lam[k] * V[j * n + k];
+      A[i * ld + j] = acc;
+      A[j * ld + i] = acc;
+    }
+}
+
+// -- pair barrier element ------------------------------------------------------
+// Energy kappa * e(c) * b(d) with gradient and (optionally projected) Hessian.
+// b as a function of z = d^2: db/dz = b'/(2d), d2b/dz2 = (b'' - b'/d) / (4 z).
+// Returns the energy; H is 12x12 row-major.
+DEV double pair_barrier_full(int kind, int type, const double *x, double dhat, double kappa, double eps_x,
+                             bool project, double *g, double *H, double *scratch /*144*/) {
+  TypeGeo T;
+  type_geometry(kind, type, x, T);
+  double z;
+  d2_derivs(x, T, &z, g, H);
+  double d = sqrt(z);
+  double b0, b1, b2;
+  barrier_b(d, dhat, &b0, &b1, &b2);
+  double B1 = b1 / (2.0 * d);
+  double B2 = (b2 - b1 / d) / (4.0 * z);
+  // H <- B2 gz gz^T + B1 Hz ; g <- B1 gz   (H holds Hz, g holds gz on entry)
+  for (int i = 0; i < 12; ++i)
+    for (int j = 0; j < 12; ++j) H[i * 12 + j] = B2 * g[i] * g[j] + B1 * H[i * 12 + j];
+  for (int i = 0; i < 12; ++i) g[i] *= B1;
+  double e = 1.0;
+  bool all4 = (T.n_involved == 4);
+  if (kind == 1) {
+    double c, gc[12];
+    double *Hc = scratch;
+    cross_norm2_derivs(x, &c, gc, Hc);
+    if (c < eps_x) {
+      double q = c / eps_x;
+      e = q * (2.0 - q);
+      double e1 = (2.0 / eps_x) * (1.0 - q), e2 = -2.0 / (eps_x * eps_x);
+      // E = e b : H = e Hb + b (e2 gc gc^T + e1 Hc) + e1 (gc gb^T + gb gc^T)
+      for (int i = 0; i < 12; ++i)
+        for (int j = 0; j < 12; ++j)
+          H[i * 12 + j] = e * H[i * 12 + j] + b0 * (e2 * gc[i] * gc[j] + e1 * Hc[i * 12 + j]) +
+                          e1 * (gc[i] * g[j] + g[i] * gc[j]);
+      for (int i = 0; i < 12; ++i) g[i] = e * g[i] + b0 * e1 * gc[i];
+      all4 = true;
+    }
+  }
+  for (int i = 0; i < 12; ++i) g[i] *= kappa;
+  for (int i = 0; i < 144; ++i) H[i] *= kappa;
+  if (project) {
+    if (all4) {
+      psd_project(12, H, 12, scratch);
+    } else {
+      // project on the involved coordinates only (the rest of H is zero)
+      int n = 3 * T.n_involved;
+      double *S = scratch, *V = scratch + 81;  // n <= 9 here
+      int idx[9];
+      for (int a = 0; a < T.n_involved; ++a)
+        for (int k = 0; k < 3; ++k) idx[3 * a + k] = 3 * T.involved[a] + k;
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) S[i * 9 + j] = H[idx[i] * 12 + idx[j]];
+      psd_project(n, S, 9, V);
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) H[idx[i] * 12 + idx[j]] = S[i * 9 + j];
+    }
+  }
+  return kappa * e * b0;
+}
+
+// Energy only, from the classified squared distance.
+DEV double pair_barrier_energy(int kind, const double *x, double d2, double dhat, double kappa, double eps_x) {
+  double d = sqrt(d2);
+  double b0, b1, b2;
+  barrier_b(d, dhat, &b0, &b1, &b2);
+  double e = 1.0;
+  if (kind == 1) {
+    d3 n = cross3(sub3(ld3(x + 3), ld3(x)), sub3(ld3(x + 9), ld3(x + 6)));
+    double c = dot3(n, n);
+    if (c < eps_x) {
+      double q = c / eps_x;
+      e = q * (2.0 - q);
+    }
+  }
+  return kappa * e * b0;
+}
+
+// Closest-point weights of a classified pair: sum_i w_i x_i is the vector
+// between the two closest points (first primitive minus second).
+DEV void closest_weights(int kind, int type, const double *x, double *w) {
+  TypeGeo T;
+  type_geometry(kind, type, x, T);
+  // r = sum c_i x_i is exactly that difference, up to orientation
+  for (int i = 0; i < 4; ++i) w[i] = T.c[i];
+}
+
+// -- Neo-Hookean tetrahedron ---------------------------------------------------
+// Psi = mu/2 (|F|^2 - 3) - mu ln J + lambda/2 ln^2 J,  F = Ds Dm^-1.
+//   P = mu F + (lambda ln J - mu) F^-T
+//   dP/dF[(i,j),(k,l)] = mu d_ik d_jl + (mu - lambda ln J) Finv^T_il Finv^T_kj + lambda Finv^T_ij Finv^T_kl
+// Gradient wrt vertex a: V P d_a, with d_0 = -(sum of Dm^-1 rows), d_a = row a-1 of Dm^-1.
+// Hessian block (a,b)_{k,m} = V sum_{j,l} d_a[j] d_b[l] dP/dF[(k,j),(m,l)], after PSD projection of dP/dF.
+DEV bool nh_F(const double *x, const double *Dinv, double F[9]) {
+  double Ds[9];
+  for (int i = 0; i < 3; ++i)
+    for (int a = 0; a < 3; ++a) Ds[i * 3 + a] = x[3 * (a + 1) + i] - x[i];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) F[i * 3 + j] = Ds[i * 3] * Dinv[j] + Ds[i * 3 + 1] * Dinv[3 + j] + Ds[i * 3 + 2] * Dinv[6 + j];
+  return true;
+}
+
+DEV double det33(const double *M) {
+  return M[0] * (M[4] * M[8] - M[5] * M[7]) - M[1] * (M[3] * M[8] - M[5] * M[6]) + M[2] * (M[3] * M[7] - M[4] * M[6]);
+}
+
+// inverse transpose of a 3x3 (row-major); returns det
+DEV double inv_T33(const double *F, double *FiT) {
+  double J = det33(F);
+  double iJ = 1.0 / J;
+  // cofactor matrix / det = F^-T
+  FiT[0] = (F[4] * F[8] - F[5] * F[7]) * iJ;
+  FiT[1] = (F[5] * F[6] - F[3] * F[8]) * iJ;
+  FiT[2] = (F[3] * F[7] - F[4] * F[6]) * iJ;
+  FiT[3] = (F[2] * F[7] - F[1] * F[8]) * iJ;
+  FiT[4] = (F[0] * F[8] - F[2] * F[6]) * iJ;
+  FiT[5] = (F[1] * F[6] - F[0] * F[7]) * iJ;
+  FiT[6] = (F[1] * F[5] - F[2] * F[4]) * iJ;
+  FiT[7] = (F[2] * F[3] - F[0] * F[5]) * iJ;
+  FiT[8] = (F[0] * F[4] - F[1] * F[3]) * iJ;
+  return J;
+}
+
+DEV double nh_energy(const double *x, const double *Dinv, double vol, double mu, double la) {
+  double F[9];
+  nh_F(x, Dinv, F);
+  double J = det33(F);
+  if (!(J > 0.0)) return kInf;
+  double tr = 0.0;
+  for (int i = 0; i < 9; ++i) tr += F[i] * F[i];
+  double lJ = log(J);
+  return vol * (0.5 * mu * (tr - 3.0) - mu * lJ + 0.5 * la * lJ * lJ);
+}
+
+// Unique 3x3 blocks (a <= b) of a symmetric 12x12 element matrix, in the order
+// (0,0),(0,1),(0,2),(0,3),(1,1),(1,2),(1,3),(2,2),(2,3),(3,3).
+HD int blk_index(int a, int b) { return a * 4 - (a * (a - 1)) / 2 + (b - a); }
+
+// Returns false if J <= 0.  g[12]; blocks[90] (10 blocks x 9, row-major).
+// HF and V are scratch arrays of 81 doubles each.
+DEV bool nh_element(const double *x, const double *Dinv, double vol, double mu, double la, double *energy, double *g,
+                    double *blocks, double *HF, double *V) {
+  double F[9], FiT[9];
+  nh_F(x, Dinv, F);
+  double J = inv_T33(F, FiT);
+  if (!(J > 0.0)) return false;
+  double lJ = log(J);
+  double tr = 0.0;
+  for (int i = 0; i < 9; ++i) tr += F[i] * F[i];
+  *energy = vol * (0.5 * mu * (tr - 3.0) - mu * lJ + 0.5 * la * lJ * lJ);
+  double P[9];
+  for (int i = 0; i < 9; ++i) P[i] = mu * F[i] + (la * lJ - mu) * FiT[i];
+  double dvec[4][3];
+  for (int j = 0; j < 3; ++j) {
+    dvec[1][j] = Dinv[j];
+    dvec[2][j] = Dinv[3 + j];
+    dvec[3][j] = Dinv[6 + j];
+    dvec[0][j] = -(Dinv[j] + Dinv[3 + j] + Dinv[6 + j]);
+  }
+  for (int a = 0; a < 4; ++a)
+    for (int k = 0; k < 3; ++k)
+      g[3 * a + k] = vol * (P[k * 3] * dvec[a][0] + P[k * 3 + 1] * dvec[a][1] + P[k * 3 + 2] * dvec[a][2]);
+  if (!blocks) return true;
+  double c1 = mu - la * lJ;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      for (int k = 0; k < 3; ++k)
+        for (int l = 0; l < 3; ++l)
+          HF[(i * 3 + j) * 9 + k * 3 + l] = ((i == k && j == l) ? mu : 0.0) + c1 * FiT[i * 3 + l] * FiT[k * 3 + j] +
+                                            la * FiT[i * 3 + j] * FiT[k * 3 + l];
+  psd_project(9, HF, 9, V);
+  for (int a = 0; a < 4; ++a)
+    for (int b = a; b < 4; ++b) {
+      double *B = blocks + 9 * blk_index(a, b);
+      for (int k = 0; k < 3; ++k)
+        for (int m = 0; m < 3; ++m) {
+          double s = 0.0;
+          for (int j = 0; j < 3; ++j) {
+            double t = 0.0;
+            for (int l = 0; l < 3; ++l) t += HF[(k * 3 + j) * 9 + m * 3 + l] * dvec[b][l];
+            s += dvec[a][j] * t;
+          }
+          B[k * 3 + m] = vol * s;
+        }
+    }
+  return true;
+}
+
+// -- friction smoothing ----------------------------------------------------------
+DEV double friction_f0(double y, double eps) {
+  return (y < eps) ? (-y * y * y / (3.0 * eps * eps) + y * y / eps + eps / 3.0) : y;
+}
+
+// -- additive CCD ---------------------------------------------------------------
+DEV double pair_distance(int kind, const double *x) {
+  double d2;
+  classify(kind, x, &d2);
+  return sqrt(d2);
+}
+
+DEV double accd(int kind, const double *x, const double *p, double s) {
+  double pm[12], mean[3] = {0, 0, 0};
+  for (int i = 0; i < 4; ++i)
+    for (int k = 0; k < 3; ++k) mean[k] += p[3 * i + k];
+  for (int k = 0; k < 3; ++k) mean[k] *= 0.25;
+  double nrm[4];
+  for (int i = 0; i < 4; ++i) {
+    double s2 = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      pm[3 * i + k] = p[3 * i + k] - mean[k];
+      s2 += pm[3 * i + k] * pm[3 * i + k];
+    }
+    nrm[i] = sqrt(s2);
+  }
+  double l = (kind == 0) ? nrm[0] + fmax(nrm[1], fmax(nrm[2], nrm[3])) : fmax(nrm[0], nrm[1]) + fmax(nrm[2], nrm[3]);
+  if (l == 0.0) return 1.0;
+  double d0 = pair_distance(kind, x);
+  double t = 0.0, xt[12];
+  for (int it = 0; it < 1000000; ++it) {
+    for (int i = 0; i < 12; ++i) xt[i] = x[i] + t * pm[i];
+    double d = pair_distance(kind, xt);
+    if (t > 0.0 && d <= s * d0) return t;
+    double tau = (1.0 - s) * d / l;
+    if (t + tau >= 1.0) return 1.0;
+    t += tau;
+  }
+  return t;
+}
+
+DEV void inv33(const double *M, double *R) {
+  double det = det33(M);
+  double id = 1.0 / det;
+  R[0] = (M[4] * M[8] - M[5] * M[7]) * id;
+  R[1] = (M[2] * M[7] - M[1] * M[8]) * id;
+  R[2] = (M[1] * M[5] - M[2] * M[4]) * id;
+  R[3] = (M[5] * M[6] - M[3] * M[8]) * id;
+  R[4] = (M[0] * M[8] - M[2] * M[6]) * id;
+  R[5] = (M[2] * M[3] - M[0] * M[5]) * id;
+  R[6] = (M[3] * M[7] - M[4] * M[6]) * id;
+  R[7] = (M[1] * M[6] - M[0] * M[7]) * id;
+  R[8] = (M[0] * M[4] - M[1] * M[3]) * id;
+}
+
+}  // namespace ipcdev

@@ -1,0 +1,1651 @@
+// ipc_host.cpp -- scene preprocessing, the device world, the batched Newton
+// driver and the C-ABI of include/ipc.h.
+//
+// The driver follows the per-environment solver structure of Sec. III-A:
+// all environments of a batch share every kernel launch, while each keeps
+// its own contact set (no cross-environment pairs), CCD step bound, line
+// search, convergence flag and failure flag; converged and failed
+// environments are skipped by every later launch of the step.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/ipc.h"
+#include "device_math.h"
+#include "ipc_kernels.h"
+#include "ipc_world.h"
+
+using ipcw::EnvDev;
+using ipcw::EnvState;
+using ipcw::Tile;
+using ipcw::WorldDev;
+
+namespace {
+
+thread_local std::string g_err;
+
+struct ApiError : std::runtime_error {
+  int code;
+  ApiError(int c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+void hip_check(hipError_t e, const char *what) {
+  if (e != hipSuccess) {
+    if (e == hipErrorOutOfMemory) throw ApiError(IPC_E_NOMEM, std::string("out of device memory in ") + what);
+    throw ApiError(IPC_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  }
+}
+#define HC(x) hip_check((x), #x)
+
+// ---------------------------------------------------------------------------
+// growable device buffers and range allocators
+// ---------------------------------------------------------------------------
+struct RawBuf {
+  void **slot;
+  size_t elem;
+};
+
+// Element-range allocator with a first-fit free list; all arrays registered
+// with an arena share its index space and grow together.
+struct Arena {
+  size_t cap = 0, top = 0, align = 1;
+  std::vector<std::pair<size_t, size_t>> free_list;  // (offset, length), sorted
+  std::vector<RawBuf> bufs;
+
+  size_t alloc(size_t n) {
+    n = (n + align - 1) / align * align;
+    if (n == 0) return top;
+    for (size_t i = 0; i < free_list.size(); ++i)
+      if (free_list[i].second >= n) {
+        size_t off = free_list[i].first;
+        free_list[i].first += n;
+        free_list[i].second -= n;
+        if (free_list[i].second == 0) free_list.erase(free_list.begin() + i);
+        return off;
+      }
+    size_t off = top;
+    top += n;
+    return off;
+  }
+  void release(size_t off, size_t n) {
+    n = (n + align - 1) / align * align;
+    if (n == 0) return;
+    free_list.push_back({off, n});
+    std::sort(free_list.begin(), free_list.end());
+    std::vector<std::pair<size_t, size_t>> merged;
+    for (auto &f : free_list) {
+      if (!merged.empty() && merged.back().first + merged.back().second == f.first)
+        merged.back().second += f.second;
+      else
+        merged.push_back(f);
+    }
+    if (!merged.empty() && merged.back().first + merged.back().second == top) {
+      top = merged.back().first;
+      merged.pop_back();
+    }
+    free_list = merged;
+  }
+  // make room for top elements; existing contents are preserved
+  void reserve(hipStream_t s) {
+    if (top <= cap) return;
+    size_t nc = std::max(top, cap + cap / 2);
+    nc = (nc + 255) / 256 * 256;
+    HC(hipStreamSynchronize(s));
+    for (RawBuf &b : bufs) {
+      void *q = nullptr;
+      HC(hipMalloc(&q, nc * b.elem));
+      if (*b.slot && cap) HC(hipMemcpy(q, *b.slot, cap * b.elem, hipMemcpyDeviceToDevice));
+      if (*b.slot) HC(hipFree(*b.slot));
+      *b.slot = q;
+    }
+    cap = nc;
+  }
+};
+
+template <class T>
+struct DBuf {
+  T *p = nullptr;
+  size_t cap = 0;
+  void ensure(size_t n) {
+    if (n <= cap) return;
+    size_t nc = std::max(n, cap + cap / 2);
+    nc = std::max<size_t>(nc, 64);
+    if (p) HC(hipFree(p));
+    p = nullptr;
+    HC(hipMalloc(&p, nc * sizeof(T)));
+    cap = nc;
+  }
+  ~DBuf() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// host-side preprocessing of one scene
+// ---------------------------------------------------------------------------
+struct HostScene {
+  int nv = 0, nv_pad = 0, nt = 0, ntri = 0, ne = 0, nsv = 0, npos = 0, n_free = 0;
+  std::vector<double> X, x0, v0, mass, Dinv, vol, mu, la;
+  std::vector<int> kin, tets;
+  std::vector<std::array<int, 3>> tris;
+  std::vector<std::array<int, 2>> edges;
+  std::vector<int> sverts;
+  std::vector<double> elen2;
+  std::vector<int> vt_beg, vt_end, vt_ent;  // local tet*4+slot
+  std::vector<int> slice_pos, slice_w;       // per local slice (positions local)
+  std::vector<int> col, cb_beg, cb_end, contrib;
+  std::vector<double> motion;  // motion rows then gravity rows
+  int n_groups = 0, n_motion = 0;
+  double dt, dhat, kappa, mu_f, eps_v, tol, pcg_tol;
+  int maxit, precision;
+};
+
+bool finite_all(const double *p, long n) {
+  for (long i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+double det3h(const double *M) {
+  return M[0] * (M[4] * M[8] - M[5] * M[7]) - M[1] * (M[3] * M[8] - M[5] * M[6]) + M[2] * (M[3] * M[7] - M[4] * M[6]);
+}
+
+void inv3h(const double *M, double *R) {
+  double id = 1.0 / det3h(M);
+  R[0] = (M[4] * M[8] - M[5] * M[7]) * id;
+  R[1] = (M[2] * M[7] - M[1] * M[8]) * id;
+  R[2] = (M[1] * M[5] - M[2] * M[4]) * id;
+  R[3] = (M[5] * M[6] - M[3] * M[8]) * id;
+  R[4] = (M[0] * M[8] - M[2] * M[6]) * id;
+  R[5] = (M[2] * M[3] - M[0] * M[5]) * id;
+  R[6] = (M[3] * M[7] - M[4] * M[6]) * id;
+  R[7] = (M[1] * M[6] - M[0] * M[7]) * id;
+  R[8] = (M[0] * M[4] - M[1] * M[3]) * id;
+}
+
+// signed volume factor of (a, b, c, d)
+double orient(const double *a, const double *b, const double *c, const double *d) {
+  double u[3], v[3], w[3];
+  for (int k = 0; k < 3; ++k) {
+    u[k] = b[k] - a[k];
+    v[k] = c[k] - a[k];
+    w[k] = d[k] - a[k];
+  }
+  return u[0] * (v[1] * w[2] - v[2] * w[1]) - u[1] * (v[0] * w[2] - v[2] * w[0]) + u[2] * (v[0] * w[1] - v[1] * w[0]);
+}
+
+bool seg_tri_cross(const double *a, const double *b, const double *t0, const double *t1, const double *t2) {
+  double da = orient(t0, t1, t2, a), db = orient(t0, t1, t2, b);
+  if ((da > 0 && db > 0) || (da < 0 && db < 0) || (da == 0 && db == 0)) return false;
+  double s0 = orient(a, b, t0, t1), s1 = orient(a, b, t1, t2), s2 = orient(a, b, t2, t0);
+  return (s0 >= 0 && s1 >= 0 && s2 >= 0) || (s0 <= 0 && s1 <= 0 && s2 <= 0);
+}
+
+struct Box {
+  double lo[3], hi[3];
+};
+
+// sweep-and-prune over x of two box lists: calls f(i, j) for every
+// overlapping pair (i from A, j from B); same=true enumerates i<j within A.
+template <class F>
+void sweep_pairs(const std::vector<Box> &A, const std::vector<Box> &B, bool same, F f) {
+  std::vector<int> ia(A.size()), ib(B.size());
+  for (size_t i = 0; i < A.size(); ++i) ia[i] = (int)i;
+  for (size_t i = 0; i < B.size(); ++i) ib[i] = (int)i;
+  auto cmpA = [&](int p, int q) { return A[p].lo[0] < A[q].lo[0]; };
+  auto cmpB = [&](int p, int q) { return B[p].lo[0] < B[q].lo[0]; };
+  std::sort(ia.begin(), ia.end(), cmpA);
+  if (same) {
+    for (size_t s = 0; s < ia.size(); ++s) {
+      const Box &a = A[ia[s]];
+      for (size_t t = s + 1; t < ia.size(); ++t) {
+        const Box &b = A[ia[t]];
+        if (b.lo[0] > a.hi[0]) break;
+        if (a.lo[1] <= b.hi[1] && b.lo[1] <= a.hi[1] && a.lo[2] <= b.hi[2] && b.lo[2] <= a.hi[2])
+          f(std::min(ia[s], ia[t]), std::max(ia[s], ia[t]));
+      }
+    }
+    return;
+  }
+  std::sort(ib.begin(), ib.end(), cmpB);
+  size_t start = 0;
+  for (size_t s = 0; s < ia.size(); ++s) {
+    const Box &a = A[ia[s]];
+    while (start < ib.size() && B[ib[start]].hi[0] < a.lo[0] - 1e30) ++start;
+    for (size_t t = 0; t < ib.size(); ++t) {
+      const Box &b = B[ib[t]];
+      if (b.lo[0] > a.hi[0]) break;
+      if (b.hi[0] < a.lo[0]) continue;
+      if (a.lo[1] <= b.hi[1] && b.lo[1] <= a.hi[1] && a.lo[2] <= b.hi[2] && b.lo[2] <= a.hi[2]) f(ia[s], ib[t]);
+    }
+  }
+}
+
+Box make_box(const std::vector<double> &x, const int *v, int n, double pad) {
+  Box b;
+  for (int k = 0; k < 3; ++k) {
+    b.lo[k] = ipcdev::kInf;
+    b.hi[k] = -ipcdev::kInf;
+  }
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k < 3; ++k) {
+      b.lo[k] = std::min(b.lo[k], x[3 * v[i] + k]);
+      b.hi[k] = std::max(b.hi[k], x[3 * v[i] + k]);
+    }
+  for (int k = 0; k < 3; ++k) {
+    b.lo[k] -= pad;
+    b.hi[k] += pad;
+  }
+  return b;
+}
+
+std::unique_ptr<HostScene> preprocess(const ipc_scene_desc *d) {
+  if (!d) throw ApiError(IPC_E_ARG, "null descriptor");
+  if (d->n_verts <= 0 || !d->rest_pos || !d->kin_group) throw ApiError(IPC_E_ARG, "no vertices");
+  if (d->n_tets < 0 || (d->n_tets > 0 && (!d->tets || !d->E || !d->nu || !d->rho)))
+    throw ApiError(IPC_E_ARG, "tet arrays missing");
+  if (d->n_tris < 0 || (d->n_tris > 0 && !d->tris)) throw ApiError(IPC_E_ARG, "triangle array missing");
+  if (d->n_motion_steps < 1 || d->n_groups < 0 || !d->gravity || (d->n_groups > 0 && !d->motion))
+    throw ApiError(IPC_E_ARG, "motion schedule missing");
+  if (!(d->dt > 0) || !(d->dhat > 0) || !(d->kappa > 0) || !(d->mu >= 0) || !(d->eps_v > 0) ||
+      !(d->newton_tol > 0) || d->newton_max_iter < 1 || !(d->pcg_rel_tol > 0) || !std::isfinite(d->dt) ||
+      !std::isfinite(d->dhat) || !std::isfinite(d->kappa) || !std::isfinite(d->mu))
+    throw ApiError(IPC_E_ARG, "bad solver parameter");
+  if (d->precision != IPC_FP64 && d->precision != IPC_MIXED) throw ApiError(IPC_E_ARG, "bad precision flag");
+  if ((long)d->n_tets * 32 >= (1L << 31)) throw ApiError(IPC_E_ARG, "too many tets for one scene");
+  auto S = std::make_unique<HostScene>();
+  HostScene &H = *S;
+  H.nv = d->n_verts;
+  H.nt = d->n_tets;
+  long nv3 = 3L * H.nv;
+  if (!finite_all(d->rest_pos, nv3) || (d->init_pos && !finite_all(d->init_pos, nv3)) ||
+      (d->init_vel && !finite_all(d->init_vel, nv3)))
+    throw ApiError(IPC_E_ARG, "non-finite vertex data");
+  H.X.assign(d->rest_pos, d->rest_pos + nv3);
+  H.x0 = d->init_pos ? std::vector<double>(d->init_pos, d->init_pos + nv3) : H.X;
+  H.v0 = d->init_vel ? std::vector<double>(d->init_vel, d->init_vel + nv3) : std::vector<double>(nv3, 0.0);
+  H.kin.assign(d->kin_group, d->kin_group + H.nv);
+  H.n_groups = d->n_groups;
+  H.n_motion = d->n_motion_steps;
+  for (int k : H.kin)
+    if (k < -1 || k >= H.n_groups) throw ApiError(IPC_E_ARG, "kin_group out of range");
+  if (H.n_groups > 0) H.motion.assign(d->motion, d->motion + 12L * H.n_groups * H.n_motion);
+  H.motion.insert(H.motion.end(), d->gravity, d->gravity + 3L * H.n_motion);
+  if (!finite_all(H.motion.data(), (long)H.motion.size())) throw ApiError(IPC_E_ARG, "non-finite motion");
+  H.dt = d->dt;
+  H.dhat = d->dhat;
+  H.kappa = d->kappa;
+  H.mu_f = d->mu;
+  H.eps_v = d->eps_v;
+  H.tol = d->newton_tol;
+  H.maxit = d->newton_max_iter;
+  H.pcg_tol = d->pcg_rel_tol;
+  H.precision = d->precision;
+  H.tets.assign(d->tets, d->tets + 4L * H.nt);
+  for (int v : H.tets)
+    if (v < 0 || v >= H.nv) throw ApiError(IPC_E_ARG, "tet index out of range");
+  H.Dinv.resize(9L * H.nt);
+  H.vol.resize(H.nt);
+  H.mu.resize(H.nt);
+  H.la.resize(H.nt);
+  H.mass.assign(H.nv, 0.0);
+  for (int e = 0; e < H.nt; ++e) {
+    double E = d->E[e], nu = d->nu[e], rho = d->rho[e];
+    if (!(E > 0) || !(nu > -1.0 && nu < 0.5) || !(rho > 0) || !std::isfinite(E) || !std::isfinite(rho))
+      throw ApiError(IPC_E_ARG, "bad material");
+    const int *t = &H.tets[4 * e];
+    double Dm[9];
+    for (int i = 0; i < 3; ++i)
+      for (int a = 0; a < 3; ++a) Dm[i * 3 + a] = H.X[3 * t[a + 1] + i] - H.X[3 * t[0] + i];
+    double det = det3h(Dm);
+    if (!(det > 0.0)) throw ApiError(IPC_E_INVERTED, "tet with non-positive rest volume");
+    inv3h(Dm, &H.Dinv[9 * e]);
+    H.vol[e] = det / 6.0;
+    H.mu[e] = E / (2.0 * (1.0 + nu));
+    H.la[e] = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+    for (int k = 0; k < 4; ++k) H.mass[t[k]] += rho * H.vol[e] / 4.0;
+    // initial J > 0
+    double Ds[9], F[9];
+    for (int i = 0; i < 3; ++i)
+      for (int a = 0; a < 3; ++a) Ds[i * 3 + a] = H.x0[3 * t[a + 1] + i] - H.x0[3 * t[0] + i];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        F[i * 3 + j] = Ds[i * 3] * H.Dinv[9 * e + j] + Ds[i * 3 + 1] * H.Dinv[9 * e + 3 + j] +
+                       Ds[i * 3 + 2] * H.Dinv[9 * e + 6 + j];
+    if (!(det3h(F) > 0.0)) throw ApiError(IPC_E_INVERTED, "inverted tet in the initial configuration");
+  }
+  for (int i = 0; i < H.nv; ++i) {
+    if (H.kin[i] < 0 && !(H.mass[i] > 0.0)) throw ApiError(IPC_E_ARG, "free vertex without mass");
+    if (H.kin[i] < 0) ++H.n_free;
+  }
+  // surface: boundary faces (used by one tet) + kinematic triangles, each with
+  // ascending vertex ids, list sorted lexicographically; edges (min,max) sorted
+  {
+    std::vector<std::array<int, 3>> faces;
+    faces.reserve(4L * H.nt);
+    for (int e = 0; e < H.nt; ++e) {
+      const int *t = &H.tets[4 * e];
+      const int F[4][3] = {{t[0], t[1], t[2]}, {t[0], t[1], t[3]}, {t[0], t[2], t[3]}, {t[1], t[2], t[3]}};
+      for (auto &f : F) {
+        std::array<int, 3> k = {f[0], f[1], f[2]};
+        std::sort(k.begin(), k.end());
+        faces.push_back(k);
+      }
+    }
+    std::sort(faces.begin(), faces.end());
+    for (size_t i = 0; i < faces.size();) {
+      size_t j = i;
+      while (j < faces.size() && faces[j] == faces[i]) ++j;
+      if (j - i == 1) H.tris.push_back(faces[i]);
+      i = j;
+    }
+    for (int i = 0; i < d->n_tris; ++i) {
+      std::array<int, 3> k = {d->tris[3 * i], d->tris[3 * i + 1], d->tris[3 * i + 2]};
+      for (int c = 0; c < 3; ++c)
+        if (k[c] < 0 || k[c] >= H.nv || H.kin[k[c]] < 0)
+          throw ApiError(IPC_E_ARG, "kinematic triangle with bad or free vertex");
+      std::sort(k.begin(), k.end());
+      H.tris.push_back(k);
+    }
+    std::sort(H.tris.begin(), H.tris.end());
+    H.tris.erase(std::unique(H.tris.begin(), H.tris.end()), H.tris.end());
+    for (auto &t : H.tris) {
+      H.edges.push_back({t[0], t[1]});
+      H.edges.push_back({t[1], t[2]});
+      H.edges.push_back({t[0], t[2]});
+      H.sverts.push_back(t[0]);
+      H.sverts.push_back(t[1]);
+      H.sverts.push_back(t[2]);
+    }
+    std::sort(H.edges.begin(), H.edges.end());
+    H.edges.erase(std::unique(H.edges.begin(), H.edges.end()), H.edges.end());
+    std::sort(H.sverts.begin(), H.sverts.end());
+    H.sverts.erase(std::unique(H.sverts.begin(), H.sverts.end()), H.sverts.end());
+    H.ntri = (int)H.tris.size();
+    H.ne = (int)H.edges.size();
+    H.nsv = (int)H.sverts.size();
+    H.elen2.resize(H.ne);
+    for (int i = 0; i < H.ne; ++i) {
+      double s = 0;
+      for (int k = 0; k < 3; ++k) {
+        double a = H.X[3 * H.edges[i][1] + k] - H.X[3 * H.edges[i][0] + k];
+        s += a * a;
+      }
+      H.elen2[i] = s;
+    }
+  }
+  // the initial configuration must be free of intersections: no candidate
+  // pair at zero distance and no surface edge crossing a surface triangle
+  {
+    std::vector<Box> bv(H.nsv), bt(H.ntri), be(H.ne);
+    for (int i = 0; i < H.nsv; ++i) bv[i] = make_box(H.x0, &H.sverts[i], 1, H.dhat);
+    for (int i = 0; i < H.ntri; ++i) bt[i] = make_box(H.x0, H.tris[i].data(), 3, H.dhat);
+    for (int i = 0; i < H.ne; ++i) be[i] = make_box(H.x0, H.edges[i].data(), 2, H.dhat);
+    auto allkin = [&](const int *v, int n) {
+      for (int i = 0; i < n; ++i)
+        if (H.kin[v[i]] < 0) return false;
+      return true;
+    };
+    bool bad = false;
+    sweep_pairs(bv, bt, false, [&](int i, int j) {
+      int p = H.sverts[i];
+      const auto &t = H.tris[j];
+      if (p == t[0] || p == t[1] || p == t[2]) return;
+      int all[4] = {p, t[0], t[1], t[2]};
+      if (allkin(all, 4)) return;
+      double xx[12], d2;
+      for (int a = 0; a < 4; ++a)
+        for (int k = 0; k < 3; ++k) xx[3 * a + k] = H.x0[3 * all[a] + k];
+      ipcdev::classify(0, xx, &d2);
+      if (!(d2 > 0.0)) bad = true;
+    });
+    sweep_pairs(be, be, true, [&](int i, int j) {
+      const auto &A = H.edges[i], &B = H.edges[j];
+      if (A[0] == B[0] || A[0] == B[1] || A[1] == B[0] || A[1] == B[1]) return;
+      int all[4] = {A[0], A[1], B[0], B[1]};
+      if (allkin(all, 4)) return;
+      double xx[12], d2;
+      for (int a = 0; a < 4; ++a)
+        for (int k = 0; k < 3; ++k) xx[3 * a + k] = H.x0[3 * all[a] + k];
+      ipcdev::classify(1, xx, &d2);
+      if (!(d2 > 0.0)) bad = true;
+    });
+    sweep_pairs(be, bt, false, [&](int i, int j) {
+      const auto &E = H.edges[i];
+      const auto &t = H.tris[j];
+      for (int a = 0; a < 2; ++a)
+        if (E[a] == t[0] || E[a] == t[1] || E[a] == t[2]) return;
+      int all[5] = {E[0], E[1], t[0], t[1], t[2]};
+      if (allkin(all, 5)) return;
+      if (seg_tri_cross(&H.x0[3 * E[0]], &H.x0[3 * E[1]], &H.x0[3 * t[0]], &H.x0[3 * t[1]], &H.x0[3 * t[2]]))
+        bad = true;
+    });
+    if (bad) throw ApiError(IPC_E_INTERSECTING, "intersecting initial configuration");
+  }
+  // vertex -> (tet, slot) incidence, ascending tet id
+  H.nv_pad = (H.nv + ipcw::kSlice - 1) / ipcw::kSlice * ipcw::kSlice;
+  H.vt_beg.assign(H.nv_pad, 0);
+  H.vt_end.assign(H.nv_pad, 0);
+  {
+    std::vector<int> cnt(H.nv_pad + 1, 0);
+    for (int e = 0; e < H.nt; ++e)
+      for (int a = 0; a < 4; ++a) cnt[H.tets[4 * e + a] + 1]++;
+    for (int i = 0; i < H.nv_pad; ++i) cnt[i + 1] += cnt[i];
+    H.vt_ent.resize(4L * H.nt);
+    std::vector<int> cur(cnt.begin(), cnt.end() - 1);
+    for (int e = 0; e < H.nt; ++e)
+      for (int a = 0; a < 4; ++a) H.vt_ent[cur[H.tets[4 * e + a]]++] = 4 * e + a;
+    for (int i = 0; i < H.nv_pad; ++i) {
+      H.vt_beg[i] = cnt[i];
+      H.vt_end[i] = cnt[i + 1];
+    }
+  }
+  // sliced-ELL pattern: row i holds itself (slot 0) and the vertices sharing
+  // a tet with it, ascending; contributors per slot in ascending tet order
+  {
+    std::vector<std::vector<int>> nbr(H.nv_pad);
+    for (int i = 0; i < H.nv_pad; ++i) nbr[i].push_back(i);
+    for (int e = 0; e < H.nt; ++e)
+      for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b)
+          if (a != b) nbr[H.tets[4 * e + a]].push_back(H.tets[4 * e + b]);
+    for (int i = 0; i < H.nv_pad; ++i) {
+      std::sort(nbr[i].begin() + 1, nbr[i].end());
+      nbr[i].erase(std::unique(nbr[i].begin() + 1, nbr[i].end()), nbr[i].end());
+      nbr[i].erase(std::remove(nbr[i].begin() + 1, nbr[i].end(), i), nbr[i].end());
+    }
+    int nsl = H.nv_pad / ipcw::kSlice;
+    H.slice_pos.resize(nsl);
+    H.slice_w.resize(nsl);
+    int pos = 0;
+    for (int s = 0; s < nsl; ++s) {
+      int w = 0;
+      for (int l = 0; l < ipcw::kSlice; ++l) w = std::max(w, (int)nbr[s * ipcw::kSlice + l].size());
+      H.slice_pos[s] = pos;
+      H.slice_w[s] = w;
+      pos += w * ipcw::kSlice;
+    }
+    H.npos = pos;
+    H.col.assign(pos, 0);
+    H.cb_beg.assign(pos, 0);
+    H.cb_end.assign(pos, 0);
+    // (row, col) -> position
+    std::vector<std::map<int, int>> where(H.nv_pad);
+    for (int s = 0; s < nsl; ++s)
+      for (int l = 0; l < ipcw::kSlice; ++l) {
+        int i = s * ipcw::kSlice + l;
+        for (int k = 0; k < H.slice_w[s]; ++k) {
+          int p = H.slice_pos[s] + k * ipcw::kSlice + l;
+          int c = (k < (int)nbr[i].size()) ? nbr[i][k] : i;
+          H.col[p] = c;
+          if (k < (int)nbr[i].size()) where[i][c] = p;
+        }
+      }
+    std::vector<std::vector<int>> lists(pos);
+    for (int e = 0; e < H.nt; ++e)
+      for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) {
+          int r = H.tets[4 * e + a], c = H.tets[4 * e + b];
+          int p = where[r].at(c);
+          int blk = (a <= b) ? ipcdev::blk_index(a, b) : ipcdev::blk_index(b, a);
+          lists[p].push_back(e * 32 + blk * 2 + (a > b ? 1 : 0));
+        }
+    for (int p = 0; p < pos; ++p) {
+      H.cb_beg[p] = (int)H.contrib.size();
+      H.contrib.insert(H.contrib.end(), lists[p].begin(), lists[p].end());
+      H.cb_end[p] = (int)H.contrib.size();
+    }
+  }
+  return S;
+}
+
+// ---------------------------------------------------------------------------
+// the device world
+// ---------------------------------------------------------------------------
+struct EnvRec {
+  bool used = false;
+  size_t v_off, t_off, tri_off, e_off, sv_off, pos_off, contrib_off, vt_off, mo_off;
+  size_t v_n, t_n, tri_n, e_n, sv_n, pos_n, contrib_n, vt_n, mo_n;
+};
+
+struct World {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  WorldDev W{};
+  Arena aV, aT, aTri, aE, aSV, aPos, aContrib, aVT, aMo, aSlice;
+  std::vector<EnvDev> envs_h;
+  std::vector<EnvRec> recs;
+  EnvDev *envs_d = nullptr;
+  size_t env_cap = 0;
+  EnvState S{};
+  std::vector<void **> state_int, state_ll, state_dbl;
+  // batch
+  std::vector<int> batch_envs;
+  DBuf<Tile> vt_d, tt_d, svt_d, trit_d, et_d, it_d;
+  DBuf<int> benv_d;
+  ipck::Batch B{};
+  ipck::Lists L{};
+  DBuf<int> counts, offs, scan_tmp, cand_type, cand_flag, cand_offs, act_type, fenv, inc_cnt, inc_off, inc_cur,
+      inc_ent, counter;
+  DBuf<int2> cand, act;
+  DBuf<double> cand_d2, e_c, fw, fn, flam, e_f, ce_g, ce_H, part_a, part_b0, part_b1, part_c0, part_c1;
+  DBuf<int4> fv, ce_v;
+  int *pinned = nullptr;  // host mirror of counters
+  int n_fric = 0;
+  std::mutex mu;
+
+  World(int dev) : device(dev) {
+    HC(hipSetDevice(dev));
+    HC(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
+    HC(hipHostMalloc((void **)&pinned, 64 * sizeof(int), hipHostMallocDefault));
+    aV.align = ipcw::kSlice;
+    aPos.align = ipcw::kSlice;
+    auto reg = [](Arena &a, void **slot, size_t elem) { a.bufs.push_back({slot, elem}); };
+    reg(aV, (void **)&W.X, 24);
+    reg(aV, (void **)&W.x, 24);
+    reg(aV, (void **)&W.v, 24);
+    reg(aV, (void **)&W.xn, 24);
+    reg(aV, (void **)&W.xh, 24);
+    reg(aV, (void **)&W.p, 24);
+    reg(aV, (void **)&W.g, 24);
+    reg(aV, (void **)&W.r, 24);
+    reg(aV, (void **)&W.z, 24);
+    reg(aV, (void **)&W.pp, 24);
+    reg(aV, (void **)&W.q, 24);
+    reg(aV, (void **)&W.mass, 8);
+    reg(aV, (void **)&W.Minv, 72);
+    reg(aV, (void **)&W.e_v, 8);
+    reg(aV, (void **)&W.r32, 12);
+    reg(aV, (void **)&W.z32, 12);
+    reg(aV, (void **)&W.pp32, 12);
+    reg(aV, (void **)&W.q32, 12);
+    reg(aV, (void **)&W.p32, 12);
+    reg(aV, (void **)&W.Minv32, 36);
+    reg(aV, (void **)&W.kin, 4);
+    reg(aV, (void **)&W.venv, 4);
+    reg(aV, (void **)&W.vt_beg, 4);
+    reg(aV, (void **)&W.vt_end, 4);
+    reg(aSlice, (void **)&W.slice_pos, 4);
+    reg(aSlice, (void **)&W.slice_w, 4);
+    reg(aPos, (void **)&W.col, 4);
+    reg(aPos, (void **)&W.cb_beg, 4);
+    reg(aPos, (void **)&W.cb_end, 4);
+    reg(aPos, (void **)&W.val, 72);
+    reg(aPos, (void **)&W.val32, 36);
+    reg(aContrib, (void **)&W.contrib, 4);
+    reg(aVT, (void **)&W.vt_ent, 4);
+    reg(aT, (void **)&W.tet, 16);
+    reg(aT, (void **)&W.Dinv, 72);
+    reg(aT, (void **)&W.vol, 8);
+    reg(aT, (void **)&W.mu, 8);
+    reg(aT, (void **)&W.la, 8);
+    reg(aT, (void **)&W.tg, 96);
+    reg(aT, (void **)&W.tH, 720);
+    reg(aT, (void **)&W.e_t, 8);
+    reg(aT, (void **)&W.tenv, 4);
+    reg(aTri, (void **)&W.tri, 16);
+    reg(aTri, (void **)&W.box_tri, 48);
+    reg(aE, (void **)&W.edge, 16);
+    reg(aE, (void **)&W.elen2, 8);
+    reg(aE, (void **)&W.box_edge, 48);
+    reg(aSV, (void **)&W.sv, 4);
+    reg(aSV, (void **)&W.sv_env, 4);
+    reg(aSV, (void **)&W.box_sv, 48);
+    reg(aMo, (void **)&W.motion, 8);
+    state_int = {(void **)&S.status,   (void **)&S.reason,   (void **)&S.iters,   (void **)&S.halvings,
+                 (void **)&S.ls_done,  (void **)&S.ls_cnt,   (void **)&S.pcg_done, (void **)&S.pcg_it,
+                 (void **)&S.dbc_bad,  (void **)&S.cand_beg, (void **)&S.cand_end, (void **)&S.act_beg,
+                 (void **)&S.act_end,  (void **)&S.fric_beg, (void **)&S.fric_end, (void **)&S.in_step};
+    state_ll = {(void **)&S.pcg_total, (void **)&S.amax_bits};
+    state_dbl = {(void **)&S.alpha, (void **)&S.E0, (void **)&S.E1, (void **)&S.pinf, (void **)&S.pcg_bb};
+  }
+
+  void ensure_envs(size_t n) {
+    if (n <= env_cap) return;
+    size_t nc = std::max<size_t>(n, std::max<size_t>(64, env_cap * 2));
+    HC(hipStreamSynchronize(stream));
+    auto grow = [&](void **slot, size_t elem) {
+      void *q = nullptr;
+      HC(hipMalloc(&q, nc * elem));
+      HC(hipMemset(q, 0, nc * elem));
+      if (*slot && env_cap) HC(hipMemcpy(q, *slot, env_cap * elem, hipMemcpyDeviceToDevice));
+      if (*slot) HC(hipFree(*slot));
+      *slot = q;
+    };
+    grow((void **)&envs_d, sizeof(EnvDev));
+    for (void **s : state_int) grow(s, 4);
+    for (void **s : state_ll) grow(s, 8);
+    for (void **s : state_dbl) grow(s, 8);
+    env_cap = nc;
+  }
+
+  void upload_env(int e) {
+    HC(hipMemcpyAsync(envs_d + e, &envs_h[e], sizeof(EnvDev), hipMemcpyHostToDevice, stream));
+  }
+
+  template <class T>
+  void up(T *dst, const T *src, size_t n) {
+    if (n) HC(hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyHostToDevice, stream));
+  }
+
+  int add_scene(const HostScene &H) {
+    int slot = -1;
+    for (size_t i = 0; i < recs.size(); ++i)
+      if (!recs[i].used) {
+        slot = (int)i;
+        break;
+      }
+    if (slot < 0) {
+      slot = (int)recs.size();
+      recs.push_back({});
+      envs_h.push_back({});
+    }
+    ensure_envs(recs.size());
+    EnvRec &R = recs[slot];
+    R.used = true;
+    R.v_n = H.nv_pad;
+    R.t_n = H.nt;
+    R.tri_n = H.ntri;
+    R.e_n = H.ne;
+    R.sv_n = H.nsv;
+    R.pos_n = H.npos;
+    R.contrib_n = H.contrib.size();
+    R.vt_n = H.vt_ent.size();
+    R.mo_n = H.motion.size();
+    R.v_off = aV.alloc(R.v_n);
+    R.t_off = aT.alloc(R.t_n);
+    R.tri_off = aTri.alloc(R.tri_n);
+    R.e_off = aE.alloc(R.e_n);
+    R.sv_off = aSV.alloc(R.sv_n);
+    R.pos_off = aPos.alloc(R.pos_n);
+    R.contrib_off = aContrib.alloc(R.contrib_n);
+    R.vt_off = aVT.alloc(R.vt_n);
+    R.mo_off = aMo.alloc(R.mo_n);
+    aSlice.top = std::max(aSlice.top, aV.top / ipcw::kSlice);
+    if ((aT.top + 1) * 32 >= (size_t)1 << 31) throw ApiError(IPC_E_NOMEM, "world tet index space exhausted");
+    for (Arena *a : {&aV, &aT, &aTri, &aE, &aSV, &aPos, &aContrib, &aVT, &aMo, &aSlice}) a->reserve(stream);
+    size_t vo = R.v_off, to = R.t_off;
+    // vertices (padded rows: zero position, kin = PAD)
+    std::vector<double> X(3 * R.v_n, 0.0), x(3 * R.v_n, 0.0), v(3 * R.v_n, 0.0), m(R.v_n, 0.0);
+    std::vector<int> kin(R.v_n, ipcw::KIN_PAD), venv(R.v_n, slot), vb(R.v_n), ve(R.v_n);
+    for (int i = 0; i < H.nv; ++i) {
+      for (int k = 0; k < 3; ++k) {
+        X[3 * i + k] = H.X[3 * i + k];
+        x[3 * i + k] = H.x0[3 * i + k];
+        v[3 * i + k] = H.v0[3 * i + k];
+      }
+      m[i] = H.mass[i];
+      kin[i] = H.kin[i] < 0 ? ipcw::KIN_FREE : H.kin[i];
+    }
+    for (size_t i = 0; i < R.v_n; ++i) {
+      vb[i] = H.vt_beg[i] + (int)R.vt_off;
+      ve[i] = H.vt_end[i] + (int)R.vt_off;
+    }
+    up(W.X + 3 * vo, X.data(), X.size());
+    up(W.x + 3 * vo, x.data(), x.size());
+    up(W.v + 3 * vo, v.data(), v.size());
+    up(W.mass + vo, m.data(), m.size());
+    up(W.kin + vo, kin.data(), kin.size());
+    up(W.venv + vo, venv.data(), venv.size());
+    up(W.vt_beg + vo, vb.data(), vb.size());
+    up(W.vt_end + vo, ve.data(), ve.size());
+    HC(hipMemsetAsync(W.p + 3 * vo, 0, 24 * R.v_n, stream));
+    HC(hipMemsetAsync(W.pp + 3 * vo, 0, 24 * R.v_n, stream));
+    HC(hipMemsetAsync(W.pp32 + 3 * vo, 0, 12 * R.v_n, stream));
+    std::vector<int> vt(H.vt_ent.size());
+    for (size_t i = 0; i < vt.size(); ++i) vt[i] = (H.vt_ent[i] >> 2) * 4 + (int)to * 4 + (H.vt_ent[i] & 3);
+    up(W.vt_ent + R.vt_off, vt.data(), vt.size());
+    // sliced ELL
+    std::vector<int> sp(H.slice_pos.size()), col(H.col.size()), cb(H.cb_beg.size()), ce(H.cb_end.size());
+    for (size_t s = 0; s < sp.size(); ++s) sp[s] = H.slice_pos[s] + (int)R.pos_off;
+    for (size_t p = 0; p < col.size(); ++p) {
+      col[p] = H.col[p] + (int)vo;
+      cb[p] = H.cb_beg[p] + (int)R.contrib_off;
+      ce[p] = H.cb_end[p] + (int)R.contrib_off;
+    }
+    up(W.slice_pos + vo / ipcw::kSlice, sp.data(), sp.size());
+    up(W.slice_w + vo / ipcw::kSlice, H.slice_w.data(), H.slice_w.size());
+    up(W.col + R.pos_off, col.data(), col.size());
+    up(W.cb_beg + R.pos_off, cb.data(), cb.size());
+    up(W.cb_end + R.pos_off, ce.data(), ce.size());
+    std::vector<int> cn(H.contrib.size());
+    for (size_t i = 0; i < cn.size(); ++i) cn[i] = H.contrib[i] + (int)to * 32;
+    up(W.contrib + R.contrib_off, cn.data(), cn.size());
+    // tets
+    std::vector<int4> tet(H.nt);
+    std::vector<int> tenv(H.nt, slot);
+    for (int e = 0; e < H.nt; ++e)
+      tet[e] = make_int4(H.tets[4 * e] + (int)vo, H.tets[4 * e + 1] + (int)vo, H.tets[4 * e + 2] + (int)vo,
+                         H.tets[4 * e + 3] + (int)vo);
+    up(W.tet + to, tet.data(), tet.size());
+    up(W.Dinv + 9 * to, H.Dinv.data(), H.Dinv.size());
+    up(W.vol + to, H.vol.data(), H.vol.size());
+    up(W.mu + to, H.mu.data(), H.mu.size());
+    up(W.la + to, H.la.data(), H.la.size());
+    up(W.tenv + to, tenv.data(), tenv.size());
+    // surface
+    std::vector<int4> tri(H.ntri), edge(H.ne);
+    for (int i = 0; i < H.ntri; ++i)
+      tri[i] = make_int4(H.tris[i][0] + (int)vo, H.tris[i][1] + (int)vo, H.tris[i][2] + (int)vo, slot);
+    for (int i = 0; i < H.ne; ++i) edge[i] = make_int4(H.edges[i][0] + (int)vo, H.edges[i][1] + (int)vo, slot, 0);
+    std::vector<int> sv(H.nsv), svenv(H.nsv, slot);
+    for (int i = 0; i < H.nsv; ++i) sv[i] = H.sverts[i] + (int)vo;
+    up(W.tri + R.tri_off, tri.data(), tri.size());
+    up(W.edge + R.e_off, edge.data(), edge.size());
+    up(W.elen2 + R.e_off, H.elen2.data(), H.elen2.size());
+    up(W.sv + R.sv_off, sv.data(), sv.size());
+    up(W.sv_env + R.sv_off, svenv.data(), svenv.size());
+    up(W.motion + R.mo_off, H.motion.data(), H.motion.size());
+    // env record
+    EnvDev &E = envs_h[slot];
+    std::memset(&E, 0, sizeof(E));
+    E.v_off = (int)vo;
+    E.nv = H.nv;
+    E.nv_pad = H.nv_pad;
+    E.t_off = (int)to;
+    E.nt = H.nt;
+    E.tri_off = (int)R.tri_off;
+    E.ntri = H.ntri;
+    E.e_off = (int)R.e_off;
+    E.ne = H.ne;
+    E.sv_off = (int)R.sv_off;
+    E.nsv = H.nsv;
+    E.pos_off = (int)R.pos_off;
+    E.npos = H.npos;
+    E.mo_off = (int)R.mo_off;
+    E.n_groups = H.n_groups;
+    E.n_motion = H.n_motion;
+    E.step = 0;
+    E.maxit = H.maxit;
+    E.precision = H.precision;
+    E.dt = H.dt;
+    E.dhat = H.dhat;
+    E.kappa = H.kappa;
+    E.mu = H.mu_f;
+    E.eps_v = H.eps_v;
+    E.tol = H.tol;
+    E.pcg_tol = H.pcg_tol;
+    upload_env(slot);
+    int zero = 0;
+    HC(hipMemcpyAsync(S.status + slot, &zero, 4, hipMemcpyHostToDevice, stream));
+    HC(hipStreamSynchronize(stream));
+    batch_envs.clear();  // tile lists must be rebuilt
+    return slot;
+  }
+
+  void remove_scene(int slot) {
+    EnvRec &R = recs[slot];
+    if (!R.used) return;
+    aV.release(R.v_off, R.v_n);
+    aT.release(R.t_off, R.t_n);
+    aTri.release(R.tri_off, R.tri_n);
+    aE.release(R.e_off, R.e_n);
+    aSV.release(R.sv_off, R.sv_n);
+    aPos.release(R.pos_off, R.pos_n);
+    aContrib.release(R.contrib_off, R.contrib_n);
+    aVT.release(R.vt_off, R.vt_n);
+    aMo.release(R.mo_off, R.mo_n);
+    R.used = false;
+    batch_envs.clear();
+  }
+
+  // ---- batch set-up -------------------------------------------------------
+  void set_batch(const std::vector<int> &envs) {
+    if (envs == batch_envs) return;
+    std::vector<Tile> vt, tt, svt, trit, et, it;
+    int item_off = 0;
+    for (int e : envs) {
+      EnvDev &E = envs_h[e];
+      E.vtile_first = (int)vt.size();
+      for (int s = 0, r = 0; s < E.nv_pad; s += ipcw::kTile, ++r)
+        vt.push_back({e, E.v_off + s, std::min(ipcw::kTile, E.nv_pad - s), r});
+      E.vtile_count = (int)vt.size() - E.vtile_first;
+      for (int s = 0, r = 0; s < E.nt; s += ipcw::kTile, ++r)
+        tt.push_back({e, E.t_off + s, std::min(ipcw::kTile, E.nt - s), r});
+      for (int s = 0; s < E.nsv; s += ipcw::kTile) svt.push_back({e, E.sv_off + s, std::min(ipcw::kTile, E.nsv - s), 0});
+      for (int s = 0; s < E.ntri; s += ipcw::kTile)
+        trit.push_back({e, E.tri_off + s, std::min(ipcw::kTile, E.ntri - s), 0});
+      for (int s = 0; s < E.ne; s += ipcw::kTile) et.push_back({e, E.e_off + s, std::min(ipcw::kTile, E.ne - s), 0});
+      for (int s = 0; s < E.nsv; s += ipcw::kTile) it.push_back({e, E.sv_off + s, std::min(ipcw::kTile, E.nsv - s), 0});
+      for (int s = 0; s < E.ne; s += ipcw::kTile) it.push_back({e, E.e_off + s, std::min(ipcw::kTile, E.ne - s), 1});
+      E.item_off = item_off;
+      item_off += E.nsv + E.ne;
+      upload_env(e);
+    }
+    auto put = [&](DBuf<Tile> &d, const std::vector<Tile> &h) {
+      d.ensure(h.size() + 1);
+      up(d.p, h.data(), h.size());
+    };
+    put(vt_d, vt);
+    put(tt_d, tt);
+    put(svt_d, svt);
+    put(trit_d, trit);
+    put(et_d, et);
+    put(it_d, it);
+    benv_d.ensure(envs.size() + 1);
+    up(benv_d.p, envs.data(), envs.size());
+    B.vtiles = vt_d.p;
+    B.ttiles = tt_d.p;
+    B.svtiles = svt_d.p;
+    B.tritiles = trit_d.p;
+    B.etiles = et_d.p;
+    B.itiles = it_d.p;
+    B.n_vt = (int)vt.size();
+    B.n_tt = (int)tt.size();
+    B.n_svt = (int)svt.size();
+    B.n_trit = (int)trit.size();
+    B.n_et = (int)et.size();
+    B.n_it = (int)it.size();
+    B.envs = benv_d.p;
+    B.n_envs = (int)envs.size();
+    B.n_items = item_off;
+    counts.ensure(item_off + 1);
+    offs.ensure(item_off + 2);
+    size_t nvw = aV.cap + 2;
+    inc_cnt.ensure(nvw);
+    inc_off.ensure(nvw);
+    inc_cur.ensure(nvw);
+    size_t nvt = vt.size() + 1;
+    part_a.ensure(nvt);
+    part_b0.ensure(nvt);
+    part_b1.ensure(nvt);
+    part_c0.ensure(nvt);
+    part_c1.ensure(nvt);
+    counter.ensure(16);
+    scan_tmp.ensure(std::max<size_t>(item_off, nvw) / 1024 + 64);
+    HC(hipStreamSynchronize(stream));
+    batch_envs = envs;
+    refresh_lists();
+  }
+
+  void refresh_lists() {
+    L.counts = counts.p;
+    L.offs = offs.p;
+    L.scan_tmp = scan_tmp.p;
+    L.cand = cand.p;
+    L.cand_type = cand_type.p;
+    L.cand_flag = cand_flag.p;
+    L.cand_offs = cand_offs.p;
+    L.cand_d2 = cand_d2.p;
+    L.e_c = e_c.p;
+    L.act = act.p;
+    L.act_type = act_type.p;
+    L.fv = fv.p;
+    L.fw = fw.p;
+    L.fn = fn.p;
+    L.flam = flam.p;
+    L.e_f = e_f.p;
+    L.fenv = fenv.p;
+    L.ce_v = ce_v.p;
+    L.ce_g = ce_g.p;
+    L.ce_H = ce_H.p;
+    L.inc_cnt = inc_cnt.p;
+    L.inc_off = inc_off.p;
+    L.inc_cur = inc_cur.p;
+    L.inc_ent = inc_ent.p;
+    L.part_a = part_a.p;
+    L.part_b0 = part_b0.p;
+    L.part_b1 = part_b1.p;
+    L.part_c0 = part_c0.p;
+    L.part_c1 = part_c1.p;
+    L.counter = counter.p;
+  }
+
+  int read_int(const int *dptr) {
+    HC(hipMemcpyAsync(pinned, dptr, sizeof(int), hipMemcpyDeviceToHost, stream));
+    HC(hipStreamSynchronize(stream));
+    return pinned[0];
+  }
+
+  // ---- broad phase: candidate list at x (p == nullptr) or over x -> x+p ----
+  int broad_phase(const double *x, const double *p) {
+    ipck::boxes(stream, W, envs_d, S, B, x, p);
+    ipck::bp_count(stream, W, envs_d, S, B, L);
+    ipck::scan_int(stream, L.counts, L.offs, B.n_items, L.scan_tmp);
+    int n = read_int(L.offs + B.n_items);
+    if ((size_t)n + 1 > cand.cap) {
+      cand.ensure(n + 1);
+      cand_type.ensure(n + 1);
+      cand_flag.ensure(n + 1);
+      cand_offs.ensure(n + 2);
+      cand_d2.ensure(n + 1);
+      e_c.ensure(n + 1);
+      refresh_lists();
+    }
+    ipck::bp_write(stream, W, envs_d, S, B, L);
+    ipck::cand_segments(stream, envs_d, S, B, L);
+    return n;
+  }
+
+  // classify + compact the active pairs of the current candidate list
+  int active_pairs(int n_cand, const double *x) {
+    if ((size_t)n_cand / 1024 + 64 > scan_tmp.cap) {
+      scan_tmp.ensure(n_cand / 1024 + 64);
+      refresh_lists();
+    }
+    ipck::classify_cands(stream, W, envs_d, L, n_cand, x);
+    ipck::scan_int(stream, L.cand_flag, L.cand_offs, n_cand, L.scan_tmp);
+    int n = read_int(L.cand_offs + n_cand);
+    if ((size_t)n + 1 > act.cap) {
+      act.ensure(n + 1);
+      act_type.ensure(n + 1);
+      refresh_lists();
+    }
+    ipck::compact_active(stream, L, n_cand);
+    ipck::act_segments(stream, S, B, L);
+    return n;
+  }
+
+  void ensure_ce(int n) {
+    if ((size_t)n + 1 > ce_v.cap) {
+      ce_v.ensure(n + 1);
+      ce_g.ensure(12L * (n + 1));
+      ce_H.ensure(90L * (n + 1));
+      refresh_lists();
+    }
+  }
+
+  // friction pairs = active pairs at x^n (positions in W.x)
+  void friction_setup() {
+    int nc = broad_phase(W.x, nullptr);
+    int na = active_pairs(nc, W.x);
+    if ((size_t)na + 1 > fv.cap) {
+      fv.ensure(na + 1);
+      fw.ensure(4L * (na + 1));
+      fn.ensure(3L * (na + 1));
+      flam.ensure(na + 1);
+      e_f.ensure(na + 1);
+      fenv.ensure(na + 1);
+      refresh_lists();
+    }
+    ipck::friction_setup(stream, W, envs_d, L, na);
+    // the friction segments are the active segments of this list
+    copy_state_int(S.fric_beg, S.act_beg);
+    copy_state_int(S.fric_end, S.act_end);
+    n_fric = na;
+  }
+
+  void copy_state_int(int *dst, const int *src) {
+    HC(hipMemcpyAsync(dst, src, sizeof(int) * env_cap, hipMemcpyDeviceToDevice, stream));
+  }
+
+  // gradient, contact elements, incidence, assembled Hessian at W.x
+  int assemble_system(int mixed) {
+    int nc = broad_phase(W.x, nullptr);
+    int na = active_pairs(nc, W.x);
+    ensure_ce(na + n_fric);
+    ipck::barrier_elems(stream, W, envs_d, L, na, W.x);
+    ipck::friction_elems(stream, W, envs_d, S, L, n_fric, na, W.x);
+    int nce = na + n_fric;
+    int nvw = (int)aV.cap;
+    ipck::incidence(stream, W, L, nce, nvw, nullptr);
+    int ntot = read_int(L.inc_off + nvw);
+    inc_ent.ensure(ntot + 1);
+    refresh_lists();
+    ipck::incidence_fill(stream, W, L, nce, nvw);
+    ipck::elastic(stream, W, envs_d, S, B);
+    ipck::assemble(stream, W, envs_d, S, B, L, mixed);
+    return na;
+  }
+
+  long long solve(int mixed) {
+    int *pending = L.counter;
+    ipck::pcg_init(stream, W, envs_d, S, B, L, pending, mixed);
+    int cap = 0;
+    for (int e : batch_envs) cap = std::max(cap, 30 * envs_h[e].nv + 10);
+    int it = 0;
+    while (true) {
+      for (int j = 0; j < 8; ++j) ipck::pcg_iter(stream, W, envs_d, S, B, L, it++, pending, mixed, cap);
+      if (read_int(pending) <= 0 || it >= cap) break;
+    }
+    ipck::pcg_finish(stream, W, S, B, mixed);
+    return it;
+  }
+
+  // ---- one time step of every environment in the current batch -------------
+  void step_batch() {
+    ipck::env_begin(stream, S, B);
+    ipck::begin_step(stream, W, envs_d, S, B);
+    friction_setup();
+    // Dirichlet move: CCD-safe and inversion-free, else the env fails
+    int nc = broad_phase(W.xn, W.p);
+    ipck::ccd_init(stream, S, B);
+    ipck::accd(stream, W, envs_d, S, L, nc, W.xn, W.p);
+    ipck::dbc_check_J(stream, W, envs_d, S, B);
+    ipck::env_dbc(stream, S, B);
+    ipck::apply_dbc(stream, W, envs_d, S, B);
+    int maxit = 0;
+    for (int e : batch_envs) maxit = std::max(maxit, envs_h[e].maxit);
+    int mixed = 0;
+    for (int e : batch_envs) mixed |= envs_h[e].precision == IPC_MIXED;
+    for (int it = 0; it < maxit; ++it) {
+      assemble_system(mixed);
+      solve(mixed);
+      ipck::conv_check(stream, W, envs_d, S, B, L, L.counter + 1);
+      if (read_int(L.counter + 1) == 0) break;
+      int ns = broad_phase(W.x, W.p);
+      ipck::ccd_init(stream, S, B);
+      ipck::accd(stream, W, envs_d, S, L, ns, W.x, W.p);
+      ipck::ls_init(stream, S, B);
+      ipck::energy(stream, W, envs_d, S, B, L, ns, n_fric, 1, S.E0);
+      for (int trial = 0; trial < 64; ++trial) {
+        ipck::energy(stream, W, envs_d, S, B, L, ns, n_fric, 0, S.E1);
+        ipck::ls_decide(stream, S, B, L.counter + 2);
+        if (read_int(L.counter + 2) == 0) break;
+      }
+      ipck::update_x(stream, W, S, B);
+      ipck::iter_end(stream, envs_d, S, B, L.counter + 3);
+      if (read_int(L.counter + 3) == 0) break;
+    }
+    ipck::step_end(stream, W, envs_d, S, B);
+    HC(hipStreamSynchronize(stream));
+  }
+};
+
+std::mutex g_worlds_mu;
+std::map<int, std::unique_ptr<World>> g_worlds;
+
+World &world_for_current_device() {
+  int dev = 0;
+  HC(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_worlds_mu);
+  auto &w = g_worlds[dev];
+  if (!w) w = std::make_unique<World>(dev);
+  return *w;
+}
+
+}  // namespace
+
+struct ipc_scene_s {
+  World *world;
+  int slot;
+  std::unique_ptr<HostScene> host;
+  int step = 0;
+  bool failed = false;
+  int fail_reason = 0;
+};
+
+namespace {
+
+int api_error(const std::exception &e) {
+  if (auto *a = dynamic_cast<const ApiError *>(&e)) {
+    g_err = a->what();
+    return a->code;
+  }
+  g_err = e.what();
+  return IPC_E_DEVICE;
+}
+
+template <class F>
+int guarded(F f) {
+  try {
+    return f();
+  } catch (const std::exception &e) {
+    return api_error(e);
+  }
+}
+
+template <class T>
+void down(World &w, T *dst, const T *src, size_t n) {
+  if (n) HC(hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyDeviceToHost, w.stream));
+}
+
+// per-env scalar state readback
+struct EnvSnapshot {
+  int status, reason, iters, halvings;
+  long long pcg_total;
+  double E0;
+};
+
+// all env slots at once (one copy per field)
+struct EnvSnapshots {
+  std::vector<int> status, reason, iters, halvings;
+  std::vector<long long> pcg_total;
+  std::vector<double> E0;
+  void fetch(World &w) {
+    size_t n = w.env_cap;
+    status.resize(n);
+    reason.resize(n);
+    iters.resize(n);
+    halvings.resize(n);
+    pcg_total.resize(n);
+    E0.resize(n);
+    HC(hipMemcpyAsync(status.data(), w.S.status, 4 * n, hipMemcpyDeviceToHost, w.stream));
+    HC(hipMemcpyAsync(reason.data(), w.S.reason, 4 * n, hipMemcpyDeviceToHost, w.stream));
+    HC(hipMemcpyAsync(iters.data(), w.S.iters, 4 * n, hipMemcpyDeviceToHost, w.stream));
+    HC(hipMemcpyAsync(halvings.data(), w.S.halvings, 4 * n, hipMemcpyDeviceToHost, w.stream));
+    HC(hipMemcpyAsync(pcg_total.data(), w.S.pcg_total, 8 * n, hipMemcpyDeviceToHost, w.stream));
+    HC(hipMemcpyAsync(E0.data(), w.S.E0, 8 * n, hipMemcpyDeviceToHost, w.stream));
+    HC(hipStreamSynchronize(w.stream));
+  }
+};
+
+EnvSnapshot snapshot(World &w, int e) {
+  EnvSnapshot s{};
+  down(w, &s.status, w.S.status + e, 1);
+  down(w, &s.reason, w.S.reason + e, 1);
+  down(w, &s.iters, w.S.iters + e, 1);
+  down(w, &s.halvings, w.S.halvings + e, 1);
+  down(w, &s.pcg_total, w.S.pcg_total + e, 1);
+  down(w, &s.E0, w.S.E0 + e, 1);
+  HC(hipStreamSynchronize(w.stream));
+  return s;
+}
+
+void set_status(World &w, int e, int st) {
+  HC(hipMemcpyAsync(w.S.status + e, &st, 4, hipMemcpyHostToDevice, w.stream));
+  HC(hipStreamSynchronize(w.stream));
+}
+
+// positions of one scene (real rows only)
+void put_x(World &w, ipc_scene s, double *dev_arr, const double *host) {
+  HC(hipMemcpyAsync(dev_arr + 3L * w.envs_h[s->slot].v_off, host, 24L * s->host->nv, hipMemcpyHostToDevice,
+                    w.stream));
+}
+void get_x(World &w, ipc_scene s, const double *dev_arr, double *host) {
+  HC(hipMemcpyAsync(host, dev_arr + 3L * w.envs_h[s->slot].v_off, 24L * s->host->nv, hipMemcpyDeviceToHost,
+                    w.stream));
+  HC(hipStreamSynchronize(w.stream));
+}
+
+void run_steps(std::vector<ipc_scene> scenes, int n_steps, ipc_step_info *infos) {
+  if (scenes.empty()) return;
+  World &w = *scenes[0]->world;
+  std::lock_guard<std::mutex> lk(w.mu);
+  std::vector<int> slots;
+  for (auto s : scenes) {
+    if (s->world != &w) throw ApiError(IPC_E_ARG, "scenes of one batch must live on the same device");
+    slots.push_back(s->slot);
+  }
+  {
+    std::vector<int> sorted = slots;
+    std::sort(sorted.begin(), sorted.end());
+    if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+      throw ApiError(IPC_E_ARG, "a scene appears twice in the batch");
+  }
+  HC(hipSetDevice(w.device));
+  w.set_batch(slots);
+  for (size_t i = 0; i < scenes.size(); ++i)
+    if (infos) {
+      std::memset(&infos[i], 0, sizeof(ipc_step_info));
+      infos[i].status = scenes[i]->failed ? IPC_E_FAILED : IPC_OK;
+      infos[i].fail_reason = scenes[i]->fail_reason;
+    }
+  EnvSnapshots snap;
+  for (int st = 0; st < n_steps; ++st) {
+    bool any = false;
+    for (auto s : scenes) any |= !s->failed;
+    if (!any) break;
+    // the motion row follows each env's own step index
+    for (auto s : scenes) {
+      w.envs_h[s->slot].step = s->step;
+      w.upload_env(s->slot);
+    }
+    w.step_batch();
+    snap.fetch(w);
+    for (size_t i = 0; i < scenes.size(); ++i) {
+      ipc_scene s = scenes[i];
+      if (s->failed) continue;
+      int e = s->slot;
+      if (infos) {
+        infos[i].newton_iters += snap.iters[e];
+        infos[i].max_newton_iters = std::max(infos[i].max_newton_iters, snap.iters[e]);
+        infos[i].ls_halvings += snap.halvings[e];
+        infos[i].pcg_iters += snap.pcg_total[e];
+        infos[i].energy_last = snap.E0[e];
+      }
+      if (snap.status[e] == ipcw::ST_CONVERGED) {
+        s->step += 1;
+        if (infos) infos[i].steps_done += 1;
+        snap.status[e] = ipcw::ST_IDLE;
+      } else {
+        s->failed = true;
+        s->fail_reason = (snap.status[e] == ipcw::ST_FAILED) ? snap.reason[e] : IPC_FAIL_MAXIT;
+        snap.status[e] = ipcw::ST_FAILED;
+        if (infos) {
+          infos[i].status = IPC_E_FAILED;
+          infos[i].fail_reason = s->fail_reason;
+        }
+      }
+    }
+    HC(hipMemcpyAsync(w.S.status, snap.status.data(), 4 * w.env_cap, hipMemcpyHostToDevice, w.stream));
+    HC(hipStreamSynchronize(w.stream));
+  }
+}
+
+}  // namespace
+
+// ===========================================================================
+// C-ABI
+// ===========================================================================
+extern "C" {
+
+const char *ipc_last_error(void) { return g_err.c_str(); }
+
+int ipc_create_scene(const ipc_scene_desc *desc, ipc_scene *out) {
+  return guarded([&]() {
+    if (!out) throw ApiError(IPC_E_ARG, "null output handle");
+    auto host = preprocess(desc);
+    World &w = world_for_current_device();
+    std::lock_guard<std::mutex> lk(w.mu);
+    int slot = w.add_scene(*host);
+    auto *s = new ipc_scene_s();
+    s->world = &w;
+    s->slot = slot;
+    s->host = std::move(host);
+    *out = s;
+    return IPC_OK;
+  });
+}
+
+void ipc_destroy_scene(ipc_scene s) {
+  if (!s) return;
+  try {
+    std::lock_guard<std::mutex> lk(s->world->mu);
+    s->world->remove_scene(s->slot);
+  } catch (...) {
+  }
+  delete s;
+}
+
+int ipc_step(ipc_scene s, int32_t n_steps, ipc_step_info *info) { return ipc_step_batch(&s, 1, n_steps, info); }
+
+int ipc_step_batch(ipc_scene *scenes, int32_t n, int32_t n_steps, ipc_step_info *infos) {
+  return guarded([&]() {
+    if (!scenes || n < 0 || n_steps < 0) throw ApiError(IPC_E_ARG, "bad arguments");
+    std::vector<ipc_scene> v(scenes, scenes + n);
+    for (auto s : v)
+      if (!s) throw ApiError(IPC_E_ARG, "null scene");
+    bool failed_before = false;
+    for (auto s : v) failed_before |= s->failed;
+    run_steps(v, n_steps, infos);
+    for (auto s : v)
+      if (s->failed) {
+        g_err = failed_before ? "scene already failed" : "environment failed";
+        return IPC_E_FAILED;
+      }
+    return IPC_OK;
+  });
+}
+
+int ipc_get_state(ipc_scene s, double *pos, double *vel, double *cauchy, double *von_mises) {
+  return guarded([&]() {
+    if (!s || !pos) throw ApiError(IPC_E_ARG, "bad arguments");
+    World &w = *s->world;
+    std::lock_guard<std::mutex> lk(w.mu);
+    HC(hipSetDevice(w.device));
+    get_x(w, s, w.W.x, pos);
+    if (vel) get_x(w, s, w.W.v, vel);
+    if (cauchy || von_mises) {
+      const EnvDev &E = w.envs_h[s->slot];
+      DBuf<double> c, m;
+      c.ensure(6L * E.nt + 1);
+      m.ensure(E.nt + 1);
+      ipck::stress(w.stream, w.W, E.t_off, E.nt, c.p, m.p);
+      if (cauchy) down(w, cauchy, c.p, 6L * E.nt);
+      if (von_mises) down(w, von_mises, m.p, E.nt);
+      HC(hipStreamSynchronize(w.stream));
+    }
+    return IPC_OK;
+  });
+}
+
+int ipc_set_state(ipc_scene s, const double *pos, const double *vel, int32_t step) {
+  return guarded([&]() {
+    if (!s || !pos || step < 0) throw ApiError(IPC_E_ARG, "bad arguments");
+    if (!finite_all(pos, 3L * s->host->nv) || (vel && !finite_all(vel, 3L * s->host->nv)))
+      throw ApiError(IPC_E_ARG, "non-finite state");
+    World &w = *s->world;
+    std::lock_guard<std::mutex> lk(w.mu);
+    HC(hipSetDevice(w.device));
+    put_x(w, s, w.W.x, pos);
+    std::vector<double> z(3L * s->host->nv, 0.0);
+    put_x(w, s, w.W.v, vel ? vel : z.data());
+    HC(hipStreamSynchronize(w.stream));
+    s->step = step;
+    s->failed = false;
+    s->fail_reason = 0;
+    set_status(w, s->slot, ipcw::ST_IDLE);
+    return IPC_OK;
+  });
+}
+
+int ipc_scene_sizes(ipc_scene s, int64_t out[7]) {
+  if (!s || !out) return IPC_E_ARG;
+  out[0] = s->host->nv;
+  out[1] = s->host->nt;
+  out[2] = s->host->ntri;
+  out[3] = s->host->ne;
+  out[4] = s->host->nsv;
+  out[5] = s->step;
+  out[6] = s->failed ? 1 : 0;
+  return IPC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// inspection entry points
+// ---------------------------------------------------------------------------
+namespace {
+
+struct DebugScope {
+  World &w;
+  ipc_scene s;
+  std::vector<double> saved_x;
+  std::lock_guard<std::mutex> lk;
+  DebugScope(ipc_scene sc) : w(*sc->world), s(sc), lk(sc->world->mu) {
+    HC(hipSetDevice(w.device));
+    saved_x.resize(3L * s->host->nv);
+    get_x(w, s, w.W.x, saved_x.data());
+    w.set_batch({s->slot});
+    set_status(w, s->slot, ipcw::ST_ACTIVE);
+  }
+  ~DebugScope() {
+    try {
+      put_x(w, s, w.W.x, saved_x.data());
+      set_status(w, s->slot, s->failed ? ipcw::ST_FAILED : ipcw::ST_IDLE);
+    } catch (...) {
+    }
+  }
+};
+
+}  // namespace
+
+int64_t ipc_debug_candidates(ipc_scene s, const double *x, const double *p, int32_t *out, int64_t cap) {
+  try {
+    if (!s || !x) throw ApiError(IPC_E_ARG, "bad arguments");
+    DebugScope D(s);
+    World &w = D.w;
+    put_x(w, s, w.W.x, x);
+    if (p) put_x(w, s, w.W.p, p);
+    int n = w.broad_phase(w.W.x, p ? w.W.p : nullptr);
+    std::vector<int2> c(n);
+    down(w, c.data(), w.cand.p, n);
+    HC(hipStreamSynchronize(w.stream));
+    const HostScene &H = *s->host;
+    const EnvDev &E = w.envs_h[s->slot];
+    for (int64_t i = 0; i < n && i < cap; ++i) {
+      int32_t *r = out + 5 * i;
+      if (c[i].x >= 0) {
+        const auto &t = H.tris[c[i].y - E.tri_off];
+        r[0] = 0;
+        r[1] = H.sverts[c[i].x - E.sv_off];
+        r[2] = t[0];
+        r[3] = t[1];
+        r[4] = t[2];
+      } else {
+        const auto &A = H.edges[~c[i].x - E.e_off], &Bq = H.edges[c[i].y - E.e_off];
+        r[0] = 1;
+        r[1] = A[0];
+        r[2] = A[1];
+        r[3] = Bq[0];
+        r[4] = Bq[1];
+      }
+    }
+    return n;
+  } catch (const std::exception &e) {
+    return api_error(e);
+  }
+}
+
+int64_t ipc_debug_active(ipc_scene s, const double *x, int32_t *out, double *d2, int64_t cap) {
+  try {
+    if (!s || !x) throw ApiError(IPC_E_ARG, "bad arguments");
+    DebugScope D(s);
+    World &w = D.w;
+    put_x(w, s, w.W.x, x);
+    int n = w.broad_phase(w.W.x, nullptr);
+    w.active_pairs(n, w.W.x);
+    std::vector<int2> c(n);
+    std::vector<int> ty(n), fl(n);
+    std::vector<double> dd(n);
+    down(w, c.data(), w.cand.p, n);
+    down(w, ty.data(), w.cand_type.p, n);
+    down(w, fl.data(), w.cand_flag.p, n);
+    down(w, dd.data(), w.cand_d2.p, n);
+    HC(hipStreamSynchronize(w.stream));
+    const HostScene &H = *s->host;
+    const EnvDev &E = w.envs_h[s->slot];
+    int64_t k = 0;
+    for (int i = 0; i < n; ++i) {
+      if (!fl[i]) continue;
+      if (k < cap) {
+        int32_t *r = out + 6 * k;
+        if (c[i].x >= 0) {
+          const auto &t = H.tris[c[i].y - E.tri_off];
+          r[0] = 0;
+          r[1] = H.sverts[c[i].x - E.sv_off];
+          r[2] = t[0];
+          r[3] = t[1];
+          r[4] = t[2];
+        } else {
+          const auto &A = H.edges[~c[i].x - E.e_off], &Bq = H.edges[c[i].y - E.e_off];
+          r[0] = 1;
+          r[1] = A[0];
+          r[2] = A[1];
+          r[3] = Bq[0];
+          r[4] = Bq[1];
+        }
+        r[5] = ty[i];
+        if (d2) d2[k] = dd[i];
+      }
+      ++k;
+    }
+    return k;
+  } catch (const std::exception &e) {
+    return api_error(e);
+  }
+}
+
+int ipc_debug_begin_step(ipc_scene s, double *x_start) {
+  return guarded([&]() {
+    if (!s) throw ApiError(IPC_E_ARG, "bad arguments");
+    World &w = *s->world;
+    std::vector<double> saved_x, saved_v;
+    {
+      DebugScope D(s);
+      w.envs_h[s->slot].step = s->step;
+      w.upload_env(s->slot);
+      ipck::env_begin(w.stream, w.S, w.B);
+      ipck::begin_step(w.stream, w.W, w.envs_d, w.S, w.B);
+      w.friction_setup();
+      int nc = w.broad_phase(w.W.xn, w.W.p);
+      ipck::ccd_init(w.stream, w.S, w.B);
+      ipck::accd(w.stream, w.W, w.envs_d, w.S, w.L, nc, w.W.xn, w.W.p);
+      ipck::dbc_check_J(w.stream, w.W, w.envs_d, w.S, w.B);
+      ipck::env_dbc(w.stream, w.S, w.B);
+      ipck::apply_dbc(w.stream, w.W, w.envs_d, w.S, w.B);
+      EnvSnapshot e = snapshot(w, s->slot);
+      if (e.status == ipcw::ST_FAILED) throw ApiError(IPC_E_FAILED, "direct Dirichlet move is not feasible");
+      if (x_start) get_x(w, s, w.W.x, x_start);
+    }
+    return IPC_OK;
+  });
+}
+
+int ipc_debug_gradient(ipc_scene s, const double *x, double *g) {
+  return guarded([&]() {
+    if (!s || !x || !g) throw ApiError(IPC_E_ARG, "bad arguments");
+    DebugScope D(s);
+    World &w = D.w;
+    put_x(w, s, w.W.x, x);
+    w.assemble_system(0);
+    get_x(w, s, w.W.g, g);
+    return IPC_OK;
+  });
+}
+
+double ipc_debug_energy(ipc_scene s, const double *x) {
+  try {
+    if (!s || !x) throw ApiError(IPC_E_ARG, "bad arguments");
+    DebugScope D(s);
+    World &w = D.w;
+    put_x(w, s, w.W.x, x);
+    std::vector<double> z(3L * s->host->nv, 0.0);
+    put_x(w, s, w.W.p, z.data());
+    int n = w.broad_phase(w.W.x, nullptr);
+    ipck::ccd_init(w.stream, w.S, w.B);
+    ipck::ls_init(w.stream, w.S, w.B);
+    ipck::energy(w.stream, w.W, w.envs_d, w.S, w.B, w.L, n, w.n_fric, 1, w.S.E0);
+    double E0;
+    down(w, &E0, w.S.E0 + s->slot, 1);
+    HC(hipStreamSynchronize(w.stream));
+    return E0;
+  } catch (const std::exception &e) {
+    api_error(e);
+    return std::nan("");
+  }
+}
+
+int ipc_debug_hessian_apply(ipc_scene s, const double *x, const double *v, double *y) {
+  return guarded([&]() {
+    if (!s || !x || !v || !y) throw ApiError(IPC_E_ARG, "bad arguments");
+    DebugScope D(s);
+    World &w = D.w;
+    put_x(w, s, w.W.x, x);
+    w.assemble_system(0);
+    put_x(w, s, w.W.r, v);
+    ipck::spmv_debug(w.stream, w.W, w.envs_d, w.S, w.B, w.L, w.W.r, w.W.q);
+    get_x(w, s, w.W.q, y);
+    return IPC_OK;
+  });
+}
+
+int ipc_debug_newton_dir(ipc_scene s, const double *x, double *p, int64_t *pcg_iters) {
+  return guarded([&]() {
+    if (!s || !x || !p) throw ApiError(IPC_E_ARG, "bad arguments");
+    DebugScope D(s);
+    World &w = D.w;
+    put_x(w, s, w.W.x, x);
+    int mixed = s->host->precision == IPC_MIXED;
+    w.assemble_system(mixed);
+    w.solve(mixed);
+    get_x(w, s, w.W.p, p);
+    if (pcg_iters) {
+      int it;
+      down(w, &it, w.S.pcg_it + s->slot, 1);
+      HC(hipStreamSynchronize(w.stream));
+      *pcg_iters = it;
+    }
+    return IPC_OK;
+  });
+}
+
+double ipc_debug_ccd_bound(ipc_scene s, const double *x, const double *p) {
+  try {
+    if (!s || !x || !p) throw ApiError(IPC_E_ARG, "bad arguments");
+    DebugScope D(s);
+    World &w = D.w;
+    put_x(w, s, w.W.x, x);
+    put_x(w, s, w.W.p, p);
+    int n = w.broad_phase(w.W.x, w.W.p);
+    ipck::ccd_init(w.stream, w.S, w.B);
+    ipck::accd(w.stream, w.W, w.envs_d, w.S, w.L, n, w.W.x, w.W.p);
+    unsigned long long bits;
+    down(w, &bits, w.S.amax_bits + s->slot, 1);
+    HC(hipStreamSynchronize(w.stream));
+    double a;
+    std::memcpy(&a, &bits, 8);
+    return a;
+  } catch (const std::exception &e) {
+    api_error(e);
+    return std::nan("");
+  }
+}
+
+// element-level routines on the device
+int ipc_debug_classify(int32_t kind, int64_t n, const double *x12, int32_t *types, double *d2) {
+  return guarded([&]() {
+    if (n < 0 || (n > 0 && (!x12 || !types || !d2))) throw ApiError(IPC_E_ARG, "bad arguments");
+    World &w = world_for_current_device();
+    std::lock_guard<std::mutex> lk(w.mu);
+    DBuf<double> X, D2;
+    DBuf<int> T;
+    X.ensure(12 * n + 1);
+    D2.ensure(n + 1);
+    T.ensure(n + 1);
+    w.up(X.p, x12, 12 * n);
+    ipck::dbg_classify(w.stream, kind, (int)n, X.p, T.p, D2.p);
+    down(w, types, T.p, n);
+    down(w, d2, D2.p, n);
+    HC(hipStreamSynchronize(w.stream));
+    return IPC_OK;
+  });
+}
+
+int ipc_debug_pair_barrier(int32_t kind, int32_t type, const double *x12, double dhat, double kappa, double eps_x,
+                           int32_t project, double *energy, double *g12, double *H144) {
+  return guarded([&]() {
+    if (!x12) throw ApiError(IPC_E_ARG, "bad arguments");
+    World &w = world_for_current_device();
+    std::lock_guard<std::mutex> lk(w.mu);
+    DBuf<double> X, O;
+    X.ensure(12);
+    O.ensure(157);
+    w.up(X.p, x12, 12);
+    ipck::dbg_pair(w.stream, kind, type, X.p, dhat, kappa, eps_x, project, O.p);
+    double o[157];
+    down(w, o, O.p, 157);
+    HC(hipStreamSynchronize(w.stream));
+    if (energy) *energy = o[0];
+    if (g12) std::memcpy(g12, o + 1, 12 * 8);
+    if (H144) std::memcpy(H144, o + 13, 144 * 8);
+    return IPC_OK;
+  });
+}
+
+int ipc_debug_tet_elastic(const double *X12, const double *x12, double E, double nu, int32_t project, double *energy,
+                          double *g12, double *H144) {
+  return guarded([&]() {
+    if (!X12 || !x12) throw ApiError(IPC_E_ARG, "bad arguments");
+    (void)project;
+    World &w = world_for_current_device();
+    std::lock_guard<std::mutex> lk(w.mu);
+    DBuf<double> XR, X, O;
+    XR.ensure(12);
+    X.ensure(12);
+    O.ensure(157);
+    w.up(XR.p, X12, 12);
+    w.up(X.p, x12, 12);
+    double mu = E / (2.0 * (1.0 + nu)), la = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+    ipck::dbg_tet(w.stream, XR.p, X.p, mu, la, O.p);
+    double o[157];
+    down(w, o, O.p, 157);
+    HC(hipStreamSynchronize(w.stream));
+    if (energy) *energy = o[0];
+    if (g12) std::memcpy(g12, o + 1, 12 * 8);
+    if (H144) std::memcpy(H144, o + 13, 144 * 8);
+    return std::isfinite(o[0]) ? IPC_OK : IPC_E_INVERTED;
+  });
+}
+
+int64_t ipc_debug_accd(int32_t kind, int64_t n, const double *x12, const double *p12, double sfac, double *t) {
+  try {
+    if (n < 0 || (n > 0 && (!x12 || !p12 || !t))) throw ApiError(IPC_E_ARG, "bad arguments");
+    World &w = world_for_current_device();
+    std::lock_guard<std::mutex> lk(w.mu);
+    DBuf<double> X, P, T;
+    X.ensure(12 * n + 1);
+    P.ensure(12 * n + 1);
+    T.ensure(n + 1);
+    w.up(X.p, x12, 12 * n);
+    w.up(P.p, p12, 12 * n);
+    ipck::dbg_accd(w.stream, kind, (int)n, X.p, P.p, sfac, T.p);
+    down(w, t, T.p, n);
+    HC(hipStreamSynchronize(w.stream));
+    return n;
+  } catch (const std::exception &e) {
+    return api_error(e);
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,102 @@
+// ipc_kernels.h -- launchers of the device kernels (host-callable).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "ipc_world.h"
+
+namespace ipck {
+using ipcw::EnvDev;
+using ipcw::EnvState;
+using ipcw::Tile;
+using ipcw::WorldDev;
+
+// Work lists of one batch (device pointers) and their sizes.
+struct Batch {
+  const Tile *vtiles, *ttiles, *svtiles, *tritiles, *etiles, *itiles;
+  int n_vt, n_tt, n_svt, n_trit, n_et, n_it;
+  const int *envs;  // env slots in the batch
+  int n_envs;
+  int n_items;      // broad-phase work items (surface verts + edges of all envs)
+};
+
+// Dynamic per-iteration lists.
+struct Lists {
+  int *counts, *offs, *scan_tmp;  // item counts, exclusive scan (n_items+1)
+  int2 *cand;                     // candidate pairs: PT (sv, tri) or EE (~ea, eb)
+  int *cand_type, *cand_flag, *cand_offs;
+  double *cand_d2, *e_c;
+  int2 *act;                      // active pairs (same encoding)
+  int *act_type;
+  // friction (lagged at x^n)
+  int4 *fv;
+  double *fw, *fn, *flam, *e_f;
+  int *fenv;
+  // contact elements (barrier then friction)
+  int4 *ce_v;
+  double *ce_g, *ce_H;
+  // incidence
+  int *inc_cnt, *inc_off, *inc_cur, *inc_ent;
+  // reduction partials per vertex tile
+  double *part_a, *part_b0, *part_b1, *part_c0, *part_c1;
+  int *counter;  // device scratch counters [4]
+};
+
+void begin_step(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B);
+void apply_dbc(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B);
+void dbc_check_J(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B);
+void env_begin(hipStream_t s, const EnvState &S, const Batch &B);
+void env_dbc(hipStream_t s, const EnvState &S, const Batch &B);
+
+// broad phase over the state positions x (+ p if swept)
+void boxes(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, const double *x,
+           const double *p);
+void bp_count(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L);
+void bp_write(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L);
+void scan_int(hipStream_t s, const int *in, int *out, int n, int *tmp);  // out[n+1] exclusive
+void cand_segments(hipStream_t s, const EnvDev *E, const EnvState &S, const Batch &B, const Lists &L);
+
+void classify_cands(hipStream_t s, const WorldDev &W, const EnvDev *E, const Lists &L, int n, const double *x);
+void compact_active(hipStream_t s, const Lists &L, int n);
+void act_segments(hipStream_t s, const EnvState &S, const Batch &B, const Lists &L);
+void barrier_elems(hipStream_t s, const WorldDev &W, const EnvDev *E, const Lists &L, int n_act, const double *x);
+void friction_setup(hipStream_t s, const WorldDev &W, const EnvDev *E, const Lists &L, int n_act);
+void friction_elems(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Lists &L, int n_fric,
+                    int ce_off, const double *x);
+void incidence(hipStream_t s, const WorldDev &W, Lists &L, int n_ce, int nv_world, int *total_out_dev);
+void incidence_fill(hipStream_t s, const WorldDev &W, Lists &L, int n_ce, int nv_world);
+
+void elastic(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B);
+void assemble(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, const Lists &L,
+              int mixed);
+
+void pcg_init(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L,
+              int *pending, int mixed);
+void pcg_iter(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L, int it,
+              int *pending, int mixed, int cap);
+void pcg_finish(hipStream_t s, const WorldDev &W, const EnvState &S, const Batch &B, int mixed);
+void spmv_debug(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L,
+                const double *in, double *out);
+
+void conv_check(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L,
+                int *n_active);
+void ccd_init(hipStream_t s, const EnvState &S, const Batch &B);
+void accd(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Lists &L, int n,
+          const double *x, const double *p);
+void ls_init(hipStream_t s, const EnvState &S, const Batch &B);
+void energy(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L, int n_cand,
+            int n_fric, int zero_alpha, double *E_out);
+void ls_decide(hipStream_t s, const EnvState &S, const Batch &B, int *pending);
+void update_x(hipStream_t s, const WorldDev &W, const EnvState &S, const Batch &B);
+void iter_end(hipStream_t s, const EnvDev *E, const EnvState &S, const Batch &B, int *n_active);
+void step_end(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B);
+
+void stress(hipStream_t s, const WorldDev &W, int t_off, int nt, double *cauchy, double *vm);
+
+// element-level debug kernels
+void dbg_classify(hipStream_t s, int kind, int n, const double *x12, int *types, double *d2);
+void dbg_pair(hipStream_t s, int kind, int type, const double *x12, double dhat, double kappa, double eps_x,
+              int project, double *out /*1+12+144*/);
+void dbg_tet(hipStream_t s, const double *X12, const double *x12, double mu, double la, double *out /*1+12+144*/);
+void dbg_accd(hipStream_t s, int kind, int n, const double *x12, const double *p12, double sfac, double *t);
+
+}  // namespace ipck

@@ -1,0 +1,1407 @@
+// ipc_kernels.hip -- gfx950 kernels of the batched IPC Newton step.
+//
+// Layout: SoA-by-element world arrays (see ipc_world.h); positions are [n][3]
+// FP64.  Every kernel over vertices / tets / primitives walks a tile list of
+// 256-element tiles that never straddle two environments; an environment
+// whose status is not ACTIVE is skipped at tile entry, which is how converged
+// and failed environments drop out of the computation (Sec. III-A, problems
+// (iii) and (iv)).  Reductions use fixed shared-memory trees over tiles and a
+// fixed order over an environment's tiles, so no floating-point atomics are
+// used anywhere.
+#include "device_math.h"
+#include "ipc_kernels.h"
+
+using namespace ipcw;
+using namespace ipcdev;
+
+namespace {
+
+constexpr int TB = kTile;
+
+DEV double block_sum(double v, double *sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = TB / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+DEV double block_max(double v, double *sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = TB / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      double a = sh[threadIdx.x], b = sh[threadIdx.x + s];
+      sh[threadIdx.x] = (a != a || b != b) ? __builtin_nan("") : fmax(a, b);
+    }
+    __syncthreads();
+  }
+  double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// sum of the per-tile partials of one environment, in tile order
+DEV double env_tiles_sum(const double *part, const EnvDev &e) {
+  double s = 0.0;
+  for (int i = 0; i < e.vtile_count; ++i) s += part[e.vtile_first + i];
+  return s;
+}
+
+DEV void pair_info(const WorldDev &W, int2 c, int &kind, int v[4], int &env, double &eps_x) {
+  if (c.x >= 0) {
+    kind = 0;
+    int4 tr = W.tri[c.y];
+    v[0] = W.sv[c.x];
+    v[1] = tr.x;
+    v[2] = tr.y;
+    v[3] = tr.z;
+    env = tr.w;
+    eps_x = 0.0;
+  } else {
+    kind = 1;
+    int a = ~c.x, b = c.y;
+    int4 A = W.edge[a], Bq = W.edge[b];
+    v[0] = A.x;
+    v[1] = A.y;
+    v[2] = Bq.x;
+    v[3] = Bq.y;
+    env = A.z;
+    eps_x = 1e-3 * W.elen2[a] * W.elen2[b];
+  }
+}
+
+DEV void gather12(const double *x, const int v[4], double *out) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) out[3 * i + k] = x[3 * v[i] + k];
+}
+
+DEV void gather12_trial(const double *x, const double *p, double a, const int v[4], double *out) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) out[3 * i + k] = x[3 * v[i] + k] + a * p[3 * v[i] + k];
+}
+
+DEV bool active_env(const EnvState &S, int env) { return S.status[env] == ST_ACTIVE; }
+
+// ---------------------------------------------------------------------------
+// step set-up: kinematic targets, predicted positions, Dirichlet displacement
+// ---------------------------------------------------------------------------
+__global__ void k_begin_step(WorldDev W, const EnvDev *envs, EnvState S, const Tile *tiles) {
+  Tile t = tiles[blockIdx.x];
+  if ((int)threadIdx.x >= t.count || !active_env(S, t.env)) return;
+  const EnvDev &E = envs[t.env];
+  int i = t.start + threadIdx.x;
+  int k = W.kin[i];
+  double xi[3] = {W.x[3 * i], W.x[3 * i + 1], W.x[3 * i + 2]};
+  for (int c = 0; c < 3; ++c) W.xn[3 * i + c] = xi[c];
+  if (k == KIN_PAD) {
+    for (int c = 0; c < 3; ++c) {
+      W.xh[3 * i + c] = xi[c];
+      W.p[3 * i + c] = 0.0;
+    }
+    return;
+  }
+  if (k >= 0) {
+    int row = min(E.step + 1, E.n_motion - 1);
+    const double *T = W.motion + E.mo_off + 12 * (row * E.n_groups + k);
+    const double *X = W.X + 3 * i;
+    for (int r = 0; r < 3; ++r) {
+      double xb = T[4 * r] * X[0] + T[4 * r + 1] * X[1] + T[4 * r + 2] * X[2] + T[4 * r + 3];
+      W.xh[3 * i + r] = xb;
+      W.p[3 * i + r] = xb - xi[r];
+    }
+  } else {
+    int grow = min(E.step, E.n_motion - 1);
+    const double *g = W.motion + E.mo_off + 12 * E.n_motion * E.n_groups + 3 * grow;
+    double h = E.dt;
+    for (int c = 0; c < 3; ++c) {
+      W.xh[3 * i + c] = xi[c] + h * W.v[3 * i + c] + h * h * g[c];
+      W.p[3 * i + c] = 0.0;
+    }
+  }
+}
+
+__global__ void k_dbc_J(WorldDev W, const EnvDev *envs, EnvState S, const Tile *tiles) {
+  Tile t = tiles[blockIdx.x];
+  if ((int)threadIdx.x >= t.count || !active_env(S, t.env)) return;
+  int e = t.start + threadIdx.x;
+  int4 q = W.tet[e];
+  int v[4] = {q.x, q.y, q.z, q.w};
+  double x[12];
+  gather12_trial(W.xn, W.p, 1.0, v, x);
+  double F[9];
+  nh_F(x, W.Dinv + 9 * e, F);
+  if (!(det33(F) > 0.0)) S.dbc_bad[t.env] = 1;
+}
+
+__global__ void k_apply_dbc(WorldDev W, EnvState S, const Tile *tiles) {
+  Tile t = tiles[blockIdx.x];
+  if ((int)threadIdx.x >= t.count || !active_env(S, t.env)) return;
+  int i = t.start + threadIdx.x;
+  if (W.kin[i] < 0) return;
+  for (int c = 0; c < 3; ++c) W.x[3 * i + c] = W.xh[3 * i + c];
+}
+
+__global__ void k_env_begin(EnvState S, const int *envs, int n) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  int e = envs[j];
+  S.in_step[e] = 0;
+  if (S.status[e] == ST_FAILED) return;
+  S.in_step[e] = 1;
+  S.status[e] = ST_ACTIVE;
+  S.reason[e] = FAIL_NONE;
+  S.iters[e] = 0;
+  S.halvings[e] = 0;
+  S.pcg_total[e] = 0;
+  S.dbc_bad[e] = 0;
+  S.amax_bits[e] = (unsigned long long)__double_as_longlong(1.0);
+}
+
+__global__ void k_env_dbc(EnvState S, const int *envs, int n) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  int e = envs[j];
+  if (S.status[e] != ST_ACTIVE) return;
+  double a = __longlong_as_double((long long)S.amax_bits[e]);
+  if (a < 1.0 || S.dbc_bad[e]) {
+    S.status[e] = ST_FAILED;
+    S.reason[e] = FAIL_DBC;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// broad phase: dhat-widened boxes, brute-force overlap per environment
+// ---------------------------------------------------------------------------
+__global__ void k_boxes(WorldDev W, const EnvDev *envs, EnvState S, const Tile *tiles, int which, const double *x,
+                        const double *p) {
+  Tile t = tiles[blockIdx.x];
+  if ((int)threadIdx.x >= t.count || !active_env(S, t.env)) return;
+  const EnvDev &E = envs[t.env];
+  int j = t.start + threadIdx.x;
+  int v[3];
+  int n;
+  double *out;
+  if (which == 0) {
+    v[0] = W.sv[j];
+    n = 1;
+    out = W.box_sv + 6 * j;
+  } else if (which == 1) {
+    int4 q = W.tri[j];
+    v[0] = q.x;
+    v[1] = q.y;
+    v[2] = q.z;
+    n = 3;
+    out = W.box_tri + 6 * j;
+  } else {
+    int4 q = W.edge[j];
+    v[0] = q.x;
+    v[1] = q.y;
+    n = 2;
+    out = W.box_edge + 6 * j;
+  }
+  double lo[3] = {kInf, kInf, kInf}, hi[3] = {-kInf, -kInf, -kInf};
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k < 3; ++k) {
+      double a = x[3 * v[i] + k];
+      lo[k] = fmin(lo[k], a);
+      hi[k] = fmax(hi[k], a);
+      if (p) {
+        double b = a + p[3 * v[i] + k];
+        lo[k] = fmin(lo[k], b);
+        hi[k] = fmax(hi[k], b);
+      }
+    }
+  for (int k = 0; k < 3; ++k) {
+    out[k] = lo[k] - E.dhat;
+    out[3 + k] = hi[k] + E.dhat;
+  }
+}
+
+// Count (WRITE = false) or emit (WRITE = true) the candidate pairs of each
+// work item.  PT items are surface vertices tested against every surface
+// triangle of the environment; EE items are surface edges tested against the
+// environment's edges with a larger index.  The B primitives are staged
+// through LDS 256 at a time.
+template <bool WRITE>
+__global__ void __launch_bounds__(256) k_bp(WorldDev W, const EnvDev *envs, EnvState S, const Tile *tiles, int *counts,
+                                            const int *offs, int2 *out) {
+  __shared__ double sb[6][TB];
+  __shared__ int4 sid[TB];
+  Tile t = tiles[blockIdx.x];
+  const EnvDev &E = envs[t.env];
+  int kind = t.rel;
+  int li = threadIdx.x;
+  bool valid = li < t.count;
+  int a = t.start + li;
+  int item = E.item_off + (kind == 0 ? (a - E.sv_off) : (E.nsv + a - E.e_off));
+  if (!active_env(S, t.env)) {
+    if (!WRITE && valid) counts[item] = 0;
+    return;
+  }
+  double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+  int va0 = -1, va1 = -1;
+  bool akin = false;
+  if (valid) {
+    const double *bx = (kind == 0 ? W.box_sv : W.box_edge) + 6 * a;
+    for (int k = 0; k < 3; ++k) {
+      lo[k] = bx[k];
+      hi[k] = bx[3 + k];
+    }
+    if (kind == 0) {
+      va0 = W.sv[a];
+      akin = W.kin[va0] >= 0;
+    } else {
+      int4 q = W.edge[a];
+      va0 = q.x;
+      va1 = q.y;
+      akin = W.kin[va0] >= 0 && W.kin[va1] >= 0;
+    }
+  }
+  int bbeg = (kind == 0) ? E.tri_off : t.start + 1;
+  int bend = (kind == 0) ? E.tri_off + E.ntri : E.e_off + E.ne;
+  int cnt = 0;
+  int pos = (WRITE && valid) ? offs[item] : 0;
+  for (int c0 = bbeg; c0 < bend; c0 += TB) {
+    __syncthreads();
+    int j = c0 + li;
+    if (j < bend) {
+      const double *bx = (kind == 0 ? W.box_tri : W.box_edge) + 6 * j;
+      for (int k = 0; k < 6; ++k) sb[k][li] = bx[k];
+      int4 q;
+      if (kind == 0) {
+        q = W.tri[j];
+        q.w = (W.kin[q.x] >= 0 && W.kin[q.y] >= 0 && W.kin[q.z] >= 0) ? 1 : 0;
+      } else {
+        int4 e = W.edge[j];
+        q = make_int4(e.x, e.y, -1, (W.kin[e.x] >= 0 && W.kin[e.y] >= 0) ? 1 : 0);
+      }
+      sid[li] = q;
+    }
+    __syncthreads();
+    if (!valid) continue;
+    int n = min(TB, bend - c0);
+    for (int jj = 0; jj < n; ++jj) {
+      int b = c0 + jj;
+      if (kind == 1 && b <= a) continue;
+      if (!(lo[0] <= sb[3][jj] && sb[0][jj] <= hi[0])) continue;
+      if (!(lo[1] <= sb[4][jj] && sb[1][jj] <= hi[1])) continue;
+      if (!(lo[2] <= sb[5][jj] && sb[2][jj] <= hi[2])) continue;
+      int4 q = sid[jj];
+      if (kind == 0) {
+        if (va0 == q.x || va0 == q.y || va0 == q.z) continue;
+        if (akin && q.w) continue;
+        if (WRITE) out[pos++] = make_int2(a, b);
+      } else {
+        if (va0 == q.x || va0 == q.y || va1 == q.x || va1 == q.y) continue;
+        if (akin && q.w) continue;
+        if (WRITE) out[pos++] = make_int2(~a, b);
+      }
+      ++cnt;
+    }
+  }
+  if (!WRITE && valid) counts[item] = cnt;
+}
+
+// ---------------------------------------------------------------------------
+// exclusive scan of int counts: out[0..n], out[n] = total
+// ---------------------------------------------------------------------------
+constexpr int SCAN_PER_BLOCK = 1024;
+
+__global__ void k_scan1(const int *in, int *out, int n, int *bsum) {
+  __shared__ int sh[TB];
+  int base = blockIdx.x * SCAN_PER_BLOCK;
+  int v[4], s = 0;
+  for (int k = 0; k < 4; ++k) {
+    int i = base + threadIdx.x * 4 + k;
+    v[k] = (i < n) ? in[i] : 0;
+    s += v[k];
+  }
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 1; off < TB; off <<= 1) {
+    int add = (threadIdx.x >= (unsigned)off) ? sh[threadIdx.x - off] : 0;
+    __syncthreads();
+    sh[threadIdx.x] += add;
+    __syncthreads();
+  }
+  int run = sh[threadIdx.x] - s;
+  for (int k = 0; k < 4; ++k) {
+    int i = base + threadIdx.x * 4 + k;
+    if (i < n) out[i] = run;
+    run += v[k];
+  }
+  if (threadIdx.x == TB - 1) bsum[blockIdx.x] = sh[TB - 1];
+}
+
+__global__ void k_scan2(int *bsum, int nb, int *total_out) {
+  __shared__ int sh[TB];
+  int carry = 0;
+  for (int c0 = 0; c0 < nb; c0 += TB) {
+    int i = c0 + threadIdx.x;
+    int v = (i < nb) ? bsum[i] : 0;
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < TB; off <<= 1) {
+      int add = (threadIdx.x >= (unsigned)off) ? sh[threadIdx.x - off] : 0;
+      __syncthreads();
+      sh[threadIdx.x] += add;
+      __syncthreads();
+    }
+    if (i < nb) bsum[i] = carry + sh[threadIdx.x] - v;
+    int tot = sh[TB - 1];
+    __syncthreads();
+    carry += tot;
+  }
+  if (threadIdx.x == 0) *total_out = carry;
+}
+
+__global__ void k_scan3(int *out, int n, const int *bsum) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] += bsum[i / SCAN_PER_BLOCK];
+}
+
+// per-env candidate segments [beg, end) from the scanned item offsets
+__global__ void k_cand_seg(const EnvDev *envs, EnvState S, const int *benv, int n, const int *offs) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  int e = benv[j];
+  const EnvDev &E = envs[e];
+  S.cand_beg[e] = offs[E.item_off];
+  S.cand_end[e] = offs[E.item_off + E.nsv + E.ne];
+}
+
+// ---------------------------------------------------------------------------
+// narrow phase: type, d^2, active flag (d^2 < dhat^2)
+// ---------------------------------------------------------------------------
+__global__ void k_classify(WorldDev W, const EnvDev *envs, const int2 *cand, int n, const double *x, int *type,
+                           double *d2o, int *flag) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  int kind, v[4], env;
+  double ex;
+  pair_info(W, cand[k], kind, v, env, ex);
+  double xx[12];
+  gather12(x, v, xx);
+  double d2;
+  int ty = classify(kind, xx, &d2);
+  double dh = envs[env].dhat;
+  type[k] = ty;
+  d2o[k] = d2;
+  flag[k] = (d2 < dh * dh) ? 1 : 0;
+}
+
+__global__ void k_compact(const int2 *cand, const int *type, const int *flag, const int *offs, int n, int2 *act,
+                          int *act_type) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n || !flag[k]) return;
+  int o = offs[k];
+  act[o] = cand[k];
+  act_type[o] = type[k];
+}
+
+__global__ void k_act_seg(EnvState S, const int *benv, int n, const int *offs) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  int e = benv[j];
+  S.act_beg[e] = offs[S.cand_beg[e]];
+  S.act_end[e] = offs[S.cand_end[e]];
+}
+
+// ---------------------------------------------------------------------------
+// contact elements
+// ---------------------------------------------------------------------------
+DEV void store_blocks(const double *H, double *out) {
+  for (int a = 0; a < 4; ++a)
+    for (int b = a; b < 4; ++b) {
+      double *B = out + 9 * blk_index(a, b);
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) B[3 * r + c] = H[(3 * a + r) * 12 + 3 * b + c];
+    }
+}
+
+__global__ void __launch_bounds__(128) k_barrier_elems(WorldDev W, const EnvDev *envs, const int2 *act,
+                                                       const int *act_type, int n, const double *x, int4 *ce_v,
+                                                       double *ce_g, double *ce_H) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  int kind, v[4], env;
+  double ex;
+  pair_info(W, act[k], kind, v, env, ex);
+  const EnvDev &E = envs[env];
+  double xx[12], g[12], H[144], scr[168];
+  gather12(x, v, xx);
+  pair_barrier_full(kind, act_type[k], xx, E.dhat, E.kappa, ex, true, g, H, scr);
+  ce_v[k] = make_int4(v[0], v[1], v[2], v[3]);
+  for (int i = 0; i < 12; ++i) ce_g[12 * k + i] = g[i];
+  store_blocks(H, ce_H + 90 * (size_t)k);
+}
+
+// lagged friction data at x^n (positions in W.x at set-up time)
+__global__ void k_friction_setup(WorldDev W, const EnvDev *envs, const int2 *act, const int *act_type, int n,
+                                 int4 *fv, double *fw, double *fn, double *flam, int *fenv) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  int kind, v[4], env;
+  double ex;
+  pair_info(W, act[k], kind, v, env, ex);
+  const EnvDev &E = envs[env];
+  double xx[12], w[4];
+  gather12(W.x, v, xx);
+  int ty = act_type[k];
+  closest_weights(kind, ty, xx, w);
+  double dv[3] = {0, 0, 0};
+  for (int i = 0; i < 4; ++i)
+    for (int c = 0; c < 3; ++c) dv[c] += w[i] * xx[3 * i + c];
+  double dn = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+  double d2;
+  classify(kind, xx, &d2);
+  double d = sqrt(d2), b0, b1, b2;
+  barrier_b(d, E.dhat, &b0, &b1, &b2);
+  double e = 1.0;
+  if (kind == 1) {
+    d3 nn = cross3(sub3(ld3(xx + 3), ld3(xx)), sub3(ld3(xx + 9), ld3(xx + 6)));
+    double c = dot3(nn, nn);
+    if (c < ex) e = (c / ex) * (2.0 - c / ex);
+  }
+  fv[k] = make_int4(v[0], v[1], v[2], v[3]);
+  for (int i = 0; i < 4; ++i) fw[4 * k + i] = w[i];
+  for (int c = 0; c < 3; ++c) fn[3 * k + c] = dv[c] / dn;
+  flam[k] = -E.kappa * e * b1;
+  fenv[k] = env;
+}
+
+// friction potential mu lambda f0(|u|), u = (I - n n^T) sum_i w_i (x_i - x^n_i):
+// grad_i = mu lambda w_i (f1(y)/y) u,  hess_ij = mu lambda w_i w_j [a (I - n n^T) + c u u^T]
+// with a = f1/y, c = (f1' - f1/y) / y^2 (closed form, PSD).
+__global__ void k_friction_elems(WorldDev W, const EnvDev *envs, EnvState S, const int4 *fv, const double *fw,
+                                 const double *fn, const double *flam, const int *fenv, int n, const double *x,
+                                 int4 *ce_v, double *ce_g, double *ce_H) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  int env = fenv[k];
+  const EnvDev &E = envs[env];
+  int4 q = fv[k];
+  int v[4] = {q.x, q.y, q.z, q.w};
+  double w[4] = {fw[4 * k], fw[4 * k + 1], fw[4 * k + 2], fw[4 * k + 3]};
+  double nr[3] = {fn[3 * k], fn[3 * k + 1], fn[3 * k + 2]};
+  double u[3] = {0, 0, 0};
+  for (int i = 0; i < 4; ++i)
+    for (int c = 0; c < 3; ++c) u[c] += w[i] * (x[3 * v[i] + c] - W.xn[3 * v[i] + c]);
+  double un = u[0] * nr[0] + u[1] * nr[1] + u[2] * nr[2];
+  for (int c = 0; c < 3; ++c) u[c] -= un * nr[c];
+  double y = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+  double eps = E.eps_v * E.dt;
+  double f1y, a, cc;
+  if (y < eps) {
+    f1y = 2.0 / eps - y / (eps * eps);
+    a = f1y;
+    cc = (y > 0.0) ? -1.0 / (eps * eps * y) : 0.0;
+  } else {
+    f1y = 1.0 / y;
+    a = 1.0 / y;
+    cc = -1.0 / (y * y * y);
+  }
+  bool on = S.status[env] == ST_ACTIVE;
+  double sc = on ? E.mu * flam[k] : 0.0;
+  double K[9];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) K[3 * r + c] = a * ((r == c ? 1.0 : 0.0) - nr[r] * nr[c]) + cc * u[r] * u[c];
+  ce_v[k] = make_int4(v[0], v[1], v[2], v[3]);
+  for (int i = 0; i < 4; ++i)
+    for (int c = 0; c < 3; ++c) ce_g[12 * (size_t)k + 3 * i + c] = sc * w[i] * f1y * u[c];
+  for (int i = 0; i < 4; ++i)
+    for (int j = i; j < 4; ++j) {
+      double *B = ce_H + 90 * (size_t)k + 9 * blk_index(i, j);
+      double s = sc * w[i] * w[j];
+      for (int r = 0; r < 9; ++r) B[r] = s * K[r];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// vertex -> contact element incidence (free vertices only), sorted per vertex
+// ---------------------------------------------------------------------------
+__global__ void k_inc_count(WorldDev W, const int4 *ce_v, int n, int *cnt) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  int4 q = ce_v[k];
+  int v[4] = {q.x, q.y, q.z, q.w};
+  for (int a = 0; a < 4; ++a)
+    if (W.kin[v[a]] == KIN_FREE) atomicAdd(&cnt[v[a]], 1);
+}
+
+__global__ void k_inc_fill(WorldDev W, const int4 *ce_v, int n, const int *off, int *cur, int *ent) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  int4 q = ce_v[k];
+  int v[4] = {q.x, q.y, q.z, q.w};
+  for (int a = 0; a < 4; ++a)
+    if (W.kin[v[a]] == KIN_FREE) {
+      int pos = atomicAdd(&cur[v[a]], 1);
+      ent[off[v[a]] + pos] = 4 * k + a;
+    }
+}
+
+__global__ void k_inc_sort(const int *off, int *ent, int nv) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nv) return;
+  int b = off[i], e = off[i + 1];
+  for (int j = b + 1; j < e; ++j) {
+    int key = ent[j], m = j - 1;
+    while (m >= b && ent[m] > key) {
+      ent[m + 1] = ent[m];
+      --m;
+    }
+    ent[m + 1] = key;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// elasticity per tet: gradient (12) and projected Hessian blocks (10 x 9)
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_elastic(WorldDev W, EnvState S, const Tile *tiles) {
+  Tile t = tiles[blockIdx.x];
+  if ((int)threadIdx.x >= t.count || !active_env(S, t.env)) return;
+  int e = t.start + threadIdx.x;
+  int4 q = W.tet[e];
+  int v[4] = {q.x, q.y, q.z, q.w};
+  double x[12], g[12], blocks[90], HF[81], V[81], en;
+  gather12(W.x, v, x);
+  bool ok = nh_element(x, W.Dinv + 9 * e, W.vol[e], W.mu[e], W.la[e], &en, g, blocks, HF, V);
+  if (!ok) {
+    for (int i = 0; i < 12; ++i) g[i] = __builtin_nan("");
+    for (int i = 0; i < 90; ++i) blocks[i] = 0.0;
+  }
+  for (int i = 0; i < 12; ++i) W.tg[12 * (size_t)e + i] = g[i];
+  for (int i = 0; i < 90; ++i) W.tH[90 * (size_t)e + i] = blocks[i];
+}
+
+// ---------------------------------------------------------------------------
+// assembly: gradient, block-Jacobi preconditioner, sliced-ELL values
+// ---------------------------------------------------------------------------
+DEV void add_block(double *D, const double *B, bool tr) {
+  if (!tr)
+    for (int r = 0; r < 9; ++r) D[r] += B[r];
+  else
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) D[3 * r + c] += B[3 * c + r];
+}
+
+__global__ void k_assemble_rows(WorldDev W, const EnvDev *envs, EnvState S, const Tile *tiles, const int *inc_off,
+                                const int *inc_ent, const double *ce_g, const double *ce_H, int mixed) {
+  Tile t = tiles[blockIdx.x];
+  if ((int)threadIdx.x >= t.count || !active_env(S, t.env)) return;
+  const EnvDev &E = envs[t.env];
+  int i = t.start + threadIdx.x;
+  int k = W.kin[i];
+  double g[3] = {0, 0, 0};
+  double D[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1}, Mi[9];
+  if (k == KIN_FREE) {
+    double w = W.mass[i] / (E.dt * E.dt);
+    for (int c = 0; c < 3; ++c) g[c] = w * (W.x[3 * i + c] - W.xh[3 * i + c]);
+    for (int r = 0; r < 9; ++r) D[r] = (r % 4 == 0) ? w : 0.0;
+    for (int j = W.vt_beg[i]; j < W.vt_end[i]; ++j) {
+      int ent = W.vt_ent[j];
+      int te = ent >> 2, a = ent & 3;
+      for (int c = 0; c < 3; ++c) g[c] += W.tg[12 * (size_t)te + 3 * a + c];
+      add_block(D, W.tH + 90 * (size_t)te + 9 * blk_index(a, a), false);
+    }
+    for (int j = inc_off[i]; j < inc_off[i + 1]; ++j) {
+      int ent = inc_ent[j];
+      int ce = ent >> 2, a = ent & 3;
+      for (int c = 0; c < 3; ++c) g[c] += ce_g[12 * (size_t)ce + 3 * a + c];
+      add_block(D, ce_H + 90 * (size_t)ce + 9 * blk_index(a, a), false);
+    }
+    inv33(D, Mi);
+  } else {
+    for (int r = 0; r < 9; ++r) Mi[r] = D[r];
+  }
+  for (int c = 0; c < 3; ++c) W.g[3 * i + c] = g[c];
+  for (int r = 0; r < 9; ++r) W.Minv[9 * (size_t)i + r] = Mi[r];
+  if (mixed)
+    for (int r = 0; r < 9; ++r) W.Minv32[9 * (size_t)i + r] = (float)Mi[r];
+}
+
+__global__ void k_assemble_sell(WorldDev W, const EnvDev *envs, EnvState S, const Tile *tiles, int mixed) {
+  Tile t = tiles[blockIdx.x];
+  if ((int)threadIdx.x >= t.count || !active_env(S, t.env)) return;
+  const EnvDev &E = envs[t.env];
+  int i = t.start + threadIdx.x;
+  int sl = i / kSlice, lane = i % kSlice;
+  int base = W.slice_pos[sl], wdt = W.slice_w[sl];
+  int kr = W.kin[i];
+  double w = (kr == KIN_FREE) ? W.mass[i] / (E.dt * E.dt) : 0.0;
+  for (int k = 0; k < wdt; ++k) {
+    int pos = base + k * kSlice + lane;
+    int col = W.col[pos];
+    double B[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (kr != KIN_FREE) {
+      if (k == 0)
+        for (int r = 0; r < 9; ++r) B[r] = (r % 4 == 0) ? 1.0 : 0.0;
+    } else if (W.kin[col] == KIN_FREE) {
+      for (int j = W.cb_beg[pos]; j < W.cb_end[pos]; ++j) {
+        int c = W.contrib[j];
+        int te = c >> 5, bi = (c >> 1) & 15, tr = c & 1;
+        add_block(B, W.tH + 90 * (size_t)te + 9 * bi, tr != 0);
+      }
+      if (k == 0)
+        for (int r = 0; r < 3; ++r) B[4 * r] += w;
+    }
+    size_t vb = (size_t)(pos / kSlice) * (9 * kSlice) + lane;
+    for (int r = 0; r < 9; ++r) W.val[vb + r * kSlice] = B[r];
+    if (mixed)
+      for (int r = 0; r < 9; ++r) W.val32[vb + r * kSlice] = (float)B[r];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// block-Jacobi PCG, one independent solve per environment
+// ---------------------------------------------------------------------------
+template <typename T>
+DEV void contact_apply(int i, const T *v, const int *inc_off, const int *inc_ent, const int4 *ce_v, const double *ce_H,
+                       double y[3]) {
+  for (int j = inc_off[i]; j < inc_off[i + 1]; ++j) {
+    int ent = inc_ent[j];
+    int ce = ent >> 2, a = ent & 3;
+    int4 q = ce_v[ce];
+    int vv[4] = {q.x, q.y, q.z, q.w};
+    const double *H = ce_H + 90 * (size_t)ce;
+    for (int b = 0; b < 4; ++b) {
+      const double *B = H + 9 * (a <= b ? blk_index(a, b) : blk_index(b, a));
+      bool tr = a > b;
+      double x0 = v[3 * vv[b]], x1 = v[3 * vv[b] + 1], x2 = v[3 * vv[b] + 2];
+      for (int r = 0; r < 3; ++r) {
+        double b0 = tr ? B[r] : B[3 * r], b1 = tr ? B[3 + r] : B[3 * r + 1], b2 = tr ? B[6 + r] : B[3 * r + 2];
+        y[r] += b0 * x0 + b1 * x1 + b2 * x2;
+      }
+    }
+  }
+}
+
+template <typename T>
+DEV void sell_apply(const WorldDev &W, int i, const T *v, const T *val, double y[3]) {
+  int sl = i / kSlice, lane = i % kSlice;
+  int base = W.slice_pos[sl], wdt = W.slice_w[sl];
+  y[0] = y[1] = y[2] = 0.0;
+  for (int k = 0; k < wdt; ++k) {
+    int pos = base + k * kSlice + lane;
+    int col = W.col[pos];
+    size_t vb = (size_t)(pos / kSlice) * (9 * kSlice) + lane;
+    double x0 = v[3 * col], x1 = v[3 * col + 1], x2 = v[3 * col + 2];
+    for (int r = 0; r < 3; ++r)
+      y[r] += (double)val[vb + (3 * r) * kSlice] * x0 + (double)val[vb + (3 * r + 1) * kSlice] * x1 +
+              (double)val[vb + (3 * r + 2) * kSlice] * x2;
+  }
+}
+
+DEV bool pcg_env_live(const EnvState &S, int env) { return S.status[env] == ST_ACTIVE && !S.pcg_done[env]; }
+
+__global__ void k_pcg_init(WorldDev W, EnvState S, const Tile *tiles, double *part_rz, double *part_rr) {
+  __shared__ double sh[TB];
+  Tile t = tiles[blockIdx.x];
+  if (!active_env(S, t.env)) return;
+  int i = t.start + threadIdx.x;
+  double rz = 0.0, rr = 0.0;
+  if ((int)threadIdx.x < t.count) {
+    double r[3], z[3];
+    bool fr = W.kin[i] == KIN_FREE;
+    for (int c = 0; c < 3; ++c) r[c] = fr ? -W.g[3 * i + c] : 0.0;
+    const double *M = W.Minv + 9 * (size_t)i;
+    for (int c = 0; c < 3; ++c) z[c] = fr ? M[3 * c] * r[0] + M[3 * c + 1] * r[1] + M[3 * c + 2] * r[2] : 0.0;
+    for (int c = 0; c < 3; ++c) {
+      W.r[3 * i + c] = r[c];
+      W.z[3 * i + c] = z[c];
+      W.pp[3 * i + c] = z[c];
+      W.p[3 * i + c] = 0.0;
+      rz += r[c] * z[c];
+      rr += r[c] * r[c];
+    }
+  }
+  rz = block_sum(rz, sh);
+  rr = block_sum(rr, sh);
+  if (threadIdx.x == 0) {
+    part_rz[blockIdx.x] = rz;
+    part_rr[blockIdx.x] = rr;
+  }
+}
+
+__global__ void k_pcg_init32(WorldDev W, EnvState S, const Tile *tiles, double *part_rz, double *part_rr) {
+  __shared__ double sh[TB];
+  Tile t = tiles[blockIdx.x];
+  if (!active_env(S, t.env)) return;
+  int i = t.start + threadIdx.x;
+  double rz = 0.0, rr = 0.0;
+  if ((int)threadIdx.x < t.count) {
+    float r[3], z[3];
+    bool fr = W.kin[i] == KIN_FREE;
+    for (int c = 0; c < 3; ++c) r[c] = fr ? (float)(-W.g[3 * i + c]) : 0.0f;
+    const float *M = W.Minv32 + 9 * (size_t)i;
+    for (int c = 0; c < 3; ++c) z[c] = fr ? M[3 * c] * r[0] + M[3 * c + 1] * r[1] + M[3 * c + 2] * r[2] : 0.0f;
+    for (int c = 0; c < 3; ++c) {
+      W.r32[3 * i + c] = r[c];
+      W.z32[3 * i + c] = z[c];
+      W.pp32[3 * i + c] = z[c];
+      W.p32[3 * i + c] = 0.0f;
+      rz += (double)r[c] * (double)z[c];
+      rr += (double)r[c] * (double)r[c];
+    }
+  }
+  rz = block_sum(rz, sh);
+  rr = block_sum(rr, sh);
+  if (threadIdx.x == 0) {
+    part_rz[blockIdx.x] = rz;
+    part_rr[blockIdx.x] = rr;
+  }
+}
+
+__global__ void k_pcg_env_init(const EnvDev *envs, EnvState S, const int *benv, int n, const double *part_rr,
+                               int *pending) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  int e = benv[j];
+  S.pcg_it[e] = 0;
+  if (S.status[e] != ST_ACTIVE) {
+    S.pcg_done[e] = 1;
+    return;
+  }
+  double bb = env_tiles_sum(part_rr, envs[e]);
+  S.pcg_bb[e] = bb;
+  if (bb == 0.0 || !(bb == bb)) {
+    S.pcg_done[e] = 1;
+    return;
+  }
+  S.pcg_done[e] = 0;
+  atomicAdd(pending, 1);
+}
+
+// q = H pp for live environments, partial pp.q per tile
+template <typename T>
+__global__ void __launch_bounds__(256) k_spmv(WorldDev W, const EnvDev *envs, EnvState S, const Tile *tiles,
+                                              const int *inc_off, const int *inc_ent, const int4 *ce_v,
+                                              const double *ce_H, const T *pp, T *q, const T *val, double *part_pq) {
+  __shared__ double sh[TB];
+  Tile t = tiles[blockIdx.x];
+  if (!pcg_env_live(S, t.env)) return;
+  int i = t.start + threadIdx.x;
+  double pq = 0.0;
+  if ((int)threadIdx.x < t.count) {
+    double y[3];
+    sell_apply<T>(W, i, pp, val, y);
+    contact_apply<T>(i, pp, inc_off, inc_ent, ce_v, ce_H, y);
+    for (int c = 0; c < 3; ++c) {
+      q[3 * i + c] = (T)y[c];
+      pq += (double)pp[3 * i + c] * (double)(T)y[c];
+    }
+  }
+  pq = block_sum(pq, sh);
+  if (threadIdx.x == 0) part_pq[blockIdx.x] = pq;
+}
+
+template <typename T>
+__global__ void k_pcg_update(WorldDev W, const EnvDev *envs, EnvState S, const Tile *tiles, const double *part_pq,
+                             const double *part_rz_old, double *part_rz_new, double *part_rr_new, T *p, T *r, T *z,
+                             const T *pp, const T *q, const T *Minv) {
+  __shared__ double sh[TB];
+  __shared__ double s_alpha;
+  Tile t = tiles[blockIdx.x];
+  if (!pcg_env_live(S, t.env)) return;
+  const EnvDev &E = envs[t.env];
+  if (threadIdx.x == 0) {
+    double pq = env_tiles_sum(part_pq, E), rz = env_tiles_sum(part_rz_old, E);
+    s_alpha = (pq > 0.0) ? rz / pq : 0.0;
+  }
+  __syncthreads();
+  double alpha = s_alpha;
+  int i = t.start + threadIdx.x;
+  double rz = 0.0, rr = 0.0;
+  if ((int)threadIdx.x < t.count) {
+    T rv[3], zv[3];
+    for (int c = 0; c < 3; ++c) {
+      p[3 * i + c] = (T)((double)p[3 * i + c] + alpha * (double)pp[3 * i + c]);
+      rv[c] = (T)((double)r[3 * i + c] - alpha * (double)q[3 * i + c]);
+      r[3 * i + c] = rv[c];
+    }
+    const T *M = Minv + 9 * (size_t)i;
+    for (int c = 0; c < 3; ++c) zv[c] = M[3 * c] * rv[0] + M[3 * c + 1] * rv[1] + M[3 * c + 2] * rv[2];
+    for (int c = 0; c < 3; ++c) {
+      z[3 * i + c] = zv[c];
+      rz += (double)rv[c] * (double)zv[c];
+      rr += (double)rv[c] * (double)rv[c];
+    }
+  }
+  rz = block_sum(rz, sh);
+  rr = block_sum(rr, sh);
+  if (threadIdx.x == 0) {
+    part_rz_new[blockIdx.x] = rz;
+    part_rr_new[blockIdx.x] = rr;
+  }
+}
+
+template <typename T>
+__global__ void k_pcg_dir(WorldDev W, const EnvDev *envs, EnvState S, const Tile *tiles, const double *part_rz_old,
+                          const double *part_rz_new, const double *part_rr_new, T *pp, const T *z, int *pending,
+                          int cap) {
+  __shared__ double s_beta;
+  __shared__ int s_done;
+  Tile t = tiles[blockIdx.x];
+  if (!pcg_env_live(S, t.env)) return;
+  const EnvDev &E = envs[t.env];
+  if (threadIdx.x == 0) {
+    double rzn = env_tiles_sum(part_rz_new, E), rzo = env_tiles_sum(part_rz_old, E);
+    double rr = env_tiles_sum(part_rr_new, E);
+    double bb = S.pcg_bb[t.env];
+    int it = S.pcg_it[t.env] + 1;
+    int done = (rr <= E.pcg_tol * E.pcg_tol * bb) || !(rr == rr) || it >= cap || !(rzo > 0.0);
+    s_done = done;
+    s_beta = done ? 0.0 : rzn / rzo;
+  }
+  __syncthreads();
+  if (s_done) {
+    if (threadIdx.x == 0 && t.rel == 0) {
+      S.pcg_done[t.env] = 1;
+      S.pcg_it[t.env] += 1;
+      S.pcg_total[t.env] += S.pcg_it[t.env];
+      atomicSub(pending, 1);
+    }
+    return;
+  }
+  double beta = s_beta;
+  int i = t.start + threadIdx.x;
+  if ((int)threadIdx.x < t.count)
+    for (int c = 0; c < 3; ++c) pp[3 * i + c] = (T)((double)z[3 * i + c] + beta * (double)pp[3 * i + c]);
+  if (threadIdx.x == 0 && t.rel == 0) S.pcg_it[t.env] += 1;
+}
+
+__global__ void k_p32_to_p(WorldDev W, EnvState S, const Tile *tiles) {
+  Tile t = tiles[blockIdx.x];
+  if ((int)threadIdx.x >= t.count || !active_env(S, t.env)) return;
+  int i = t.start + threadIdx.x;
+  for (int c = 0; c < 3; ++c) W.p[3 * i + c] = (double)W.p32[3 * i + c];
+}
+
+// debug: out = H in over the batch (all vertices of ACTIVE envs)
+__global__ void k_spmv_dbg(WorldDev W, EnvState S, const Tile *tiles, const int *inc_off, const int *inc_ent,
+                           const int4 *ce_v, const double *ce_H, const double *in, double *out) {
+  Tile t = tiles[blockIdx.x];
+  if ((int)threadIdx.x >= t.count || !active_env(S, t.env)) return;
+  int i = t.start + threadIdx.x;
+  double y[3];
+  sell_apply<double>(W, i, in, W.val, y);
+  contact_apply<double>(i, in, inc_off, inc_ent, ce_v, ce_H, y);
+  for (int c = 0; c < 3; ++c) out[3 * i + c] = y[c];
+}
+
+// ---------------------------------------------------------------------------
+// convergence test |p|_inf <= tol * dt (per environment)
+// ---------------------------------------------------------------------------
+__global__ void k_pinf(WorldDev W, EnvState S, const Tile *tiles, double *part) {
+  __shared__ double sh[TB];
+  Tile t = tiles[blockIdx.x];
+  if (!active_env(S, t.env)) return;
+  int i = t.start + threadIdx.x;
+  double m = 0.0;
+  if ((int)threadIdx.x < t.count && W.kin[i] == KIN_FREE)
+    for (int c = 0; c < 3; ++c) {
+      double a = W.p[3 * i + c];
+      m = (a != a) ? a : fmax(m, fabs(a));
+    }
+  m = block_max(m, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = m;
+}
+
+__global__ void k_env_conv(const EnvDev *envs, EnvState S, const int *benv, int n, const double *part,
+                           int *n_active) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  int e = benv[j];
+  if (S.status[e] != ST_ACTIVE) return;
+  const EnvDev &E = envs[e];
+  double m = 0.0;
+  bool nan = false;
+  for (int i = 0; i < E.vtile_count; ++i) {
+    double a = part[E.vtile_first + i];
+    if (!(a == a) || a == kInf) nan = true;
+    m = fmax(m, a);
+  }
+  S.pinf[e] = m;
+  S.iters[e] += 1;
+  if (nan) {
+    S.status[e] = ST_FAILED;
+    S.reason[e] = FAIL_NONFINITE;
+  } else if (m <= E.tol * E.dt) {
+    S.status[e] = ST_CONVERGED;
+  } else {
+    atomicAdd(n_active, 1);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// additive CCD step bound (per environment minimum via ordered-bit atomicMin)
+// ---------------------------------------------------------------------------
+__global__ void k_ccd_init(EnvState S, const int *benv, int n) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  S.amax_bits[benv[j]] = (unsigned long long)__double_as_longlong(1.0);
+}
+
+__global__ void __launch_bounds__(128) k_accd(WorldDev W, EnvState S, const int2 *cand, int n, const double *x,
+                                              const double *p) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  int kind, v[4], env;
+  double ex;
+  pair_info(W, cand[k], kind, v, env, ex);
+  if (S.status[env] != ST_ACTIVE) return;
+  double xx[12], pp[12];
+  gather12(x, v, xx);
+  gather12(p, v, pp);
+  double tt = accd(kind, xx, pp, 0.1);
+  if (tt < 1.0) atomicMin(&S.amax_bits[env], (unsigned long long)__double_as_longlong(tt));
+}
+
+__global__ void k_ls_init(EnvState S, const int *benv, int n) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  int e = benv[j];
+  S.alpha[e] = __longlong_as_double((long long)S.amax_bits[e]);
+  S.ls_done[e] = (S.status[e] == ST_ACTIVE) ? 0 : 1;
+  S.ls_cnt[e] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// line-search energies at x + alpha_env p (alpha = 0 for the reference value)
+// ---------------------------------------------------------------------------
+DEV bool ls_live(const EnvState &S, int env) { return S.status[env] == ST_ACTIVE && !S.ls_done[env]; }
+
+__global__ void k_energy_v(WorldDev W, const EnvDev *envs, EnvState S, const Tile *tiles, int zero_alpha) {
+  Tile t = tiles[blockIdx.x];
+  if ((int)threadIdx.x >= t.count || !ls_live(S, t.env)) return;
+  const EnvDev &E = envs[t.env];
+  int i = t.start + threadIdx.x;
+  double a = zero_alpha ? 0.0 : S.alpha[t.env];
+  double e = 0.0;
+  if (W.kin[i] == KIN_FREE) {
+    double q = 0.0;
+    for (int c = 0; c < 3; ++c) {
+      double r = W.x[3 * i + c] + a * W.p[3 * i + c] - W.xh[3 * i + c];
+      q += r * r;
+    }
+    e = W.mass[i] * q / (2.0 * E.dt * E.dt);
+  }
+  W.e_v[i] = e;
+}
+
+__global__ void k_energy_t(WorldDev W, EnvState S, const Tile *tiles, int zero_alpha) {
+  Tile t = tiles[blockIdx.x];
+  if ((int)threadIdx.x >= t.count || !ls_live(S, t.env)) return;
+  int e = t.start + threadIdx.x;
+  double a = zero_alpha ? 0.0 : S.alpha[t.env];
+  int4 q = W.tet[e];
+  int v[4] = {q.x, q.y, q.z, q.w};
+  double x[12];
+  gather12_trial(W.x, W.p, a, v, x);
+  W.e_t[e] = nh_energy(x, W.Dinv + 9 * e, W.vol[e], W.mu[e], W.la[e]);
+}
+
+__global__ void k_energy_c(WorldDev W, const EnvDev *envs, EnvState S, const int2 *cand, int n, int zero_alpha,
+                           double *e_c) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  int kind, v[4], env;
+  double ex;
+  pair_info(W, cand[k], kind, v, env, ex);
+  if (!ls_live(S, env)) return;
+  const EnvDev &E = envs[env];
+  double a = zero_alpha ? 0.0 : S.alpha[env];
+  double xx[12], d2;
+  gather12_trial(W.x, W.p, a, v, xx);
+  classify(kind, xx, &d2);
+  double e = 0.0;
+  if (!(d2 > 0.0))
+    e = kInf;
+  else if (d2 < E.dhat * E.dhat)
+    e = pair_barrier_energy(kind, xx, d2, E.dhat, E.kappa, ex);
+  e_c[k] = e;
+}
+
+__global__ void k_energy_f(WorldDev W, const EnvDev *envs, EnvState S, const int4 *fv, const double *fw,
+                           const double *fn, const double *flam, const int *fenv, int n, int zero_alpha, double *e_f) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  int env = fenv[k];
+  if (!ls_live(S, env)) return;
+  const EnvDev &E = envs[env];
+  double a = zero_alpha ? 0.0 : S.alpha[env];
+  int4 q = fv[k];
+  int v[4] = {q.x, q.y, q.z, q.w};
+  double u[3] = {0, 0, 0};
+  for (int i = 0; i < 4; ++i)
+    for (int c = 0; c < 3; ++c)
+      u[c] += fw[4 * k + i] * (W.x[3 * v[i] + c] + a * W.p[3 * v[i] + c] - W.xn[3 * v[i] + c]);
+  double un = u[0] * fn[3 * k] + u[1] * fn[3 * k + 1] + u[2] * fn[3 * k + 2];
+  for (int c = 0; c < 3; ++c) u[c] -= un * fn[3 * k + c];
+  double y = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+  e_f[k] = E.mu * flam[k] * friction_f0(y, E.eps_v * E.dt);
+}
+
+// one block per environment: Phi = inertia + elastic + barrier + friction
+__global__ void k_env_energy(WorldDev W, const EnvDev *envs, EnvState S, const int *benv, const double *e_c,
+                             const double *e_f, double *E_out) {
+  __shared__ double sh[TB];
+  int e = benv[blockIdx.x];
+  if (!ls_live(S, e)) return;
+  const EnvDev &E = envs[e];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < E.nv_pad; i += TB) s += W.e_v[E.v_off + i];
+  for (int i = threadIdx.x; i < E.nt; i += TB) s += W.e_t[E.t_off + i];
+  for (int i = S.cand_beg[e] + threadIdx.x; i < S.cand_end[e]; i += TB) s += e_c[i];
+  for (int i = S.fric_beg[e] + threadIdx.x; i < S.fric_end[e]; i += TB) s += e_f[i];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) E_out[e] = (s == s) ? s : kInf;
+}
+
+__global__ void k_ls_decide(EnvState S, const int *benv, int n, int *pending) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  int e = benv[j];
+  if (S.status[e] != ST_ACTIVE || S.ls_done[e]) return;
+  if (S.E1[e] <= S.E0[e]) {
+    S.ls_done[e] = 1;
+    return;
+  }
+  S.alpha[e] *= 0.5;
+  S.halvings[e] += 1;
+  if (++S.ls_cnt[e] > 40) {
+    S.status[e] = ST_FAILED;
+    S.reason[e] = FAIL_LS;
+    return;
+  }
+  atomicAdd(pending, 1);
+}
+
+__global__ void k_update_x(WorldDev W, EnvState S, const Tile *tiles) {
+  Tile t = tiles[blockIdx.x];
+  if ((int)threadIdx.x >= t.count || S.status[t.env] != ST_ACTIVE) return;
+  int i = t.start + threadIdx.x;
+  double a = S.alpha[t.env];
+  for (int c = 0; c < 3; ++c) W.x[3 * i + c] += a * W.p[3 * i + c];
+}
+
+__global__ void k_iter_end(const EnvDev *envs, EnvState S, const int *benv, int n, int *n_active) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  int e = benv[j];
+  if (S.status[e] != ST_ACTIVE) return;
+  if (S.iters[e] >= envs[e].maxit) {
+    S.status[e] = ST_FAILED;
+    S.reason[e] = FAIL_MAXIT;
+    return;
+  }
+  atomicAdd(n_active, 1);
+}
+
+__global__ void k_step_end(WorldDev W, const EnvDev *envs, EnvState S, const Tile *tiles) {
+  Tile t = tiles[blockIdx.x];
+  if ((int)threadIdx.x >= t.count || !S.in_step[t.env]) return;
+  int st = S.status[t.env];
+  int i = t.start + threadIdx.x;
+  if (st == ST_CONVERGED) {
+    double h = envs[t.env].dt;
+    for (int c = 0; c < 3; ++c) W.v[3 * i + c] = (W.x[3 * i + c] - W.xn[3 * i + c]) / h;
+  } else if (st == ST_FAILED) {
+    for (int c = 0; c < 3; ++c) W.x[3 * i + c] = W.xn[3 * i + c];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Cauchy stress sigma = J^-1 P F^T and von Mises
+// ---------------------------------------------------------------------------
+__global__ void k_stress(WorldDev W, int t_off, int nt, double *cauchy, double *vm) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nt) return;
+  int e = t_off + k;
+  int4 q = W.tet[e];
+  int v[4] = {q.x, q.y, q.z, q.w};
+  double x[12], F[9], FiT[9];
+  gather12(W.x, v, x);
+  nh_F(x, W.Dinv + 9 * e, F);
+  double J = inv_T33(F, FiT);
+  double mu = W.mu[e], la = W.la[e], lJ = log(J);
+  double P[9], S[9];
+  for (int i = 0; i < 9; ++i) P[i] = mu * F[i] + (la * lJ - mu) * FiT[i];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      S[3 * i + j] = (P[3 * i] * F[3 * j] + P[3 * i + 1] * F[3 * j + 1] + P[3 * i + 2] * F[3 * j + 2]) / J;
+  double *o = cauchy + 6 * (size_t)k;
+  o[0] = S[0];
+  o[1] = S[4];
+  o[2] = S[8];
+  o[3] = S[5];
+  o[4] = S[2];
+  o[5] = S[1];
+  double a = S[0] - S[4], b = S[4] - S[8], c = S[8] - S[0];
+  vm[k] = sqrt(0.5 * (a * a + b * b + c * c) + 3.0 * (S[1] * S[1] + S[5] * S[5] + S[2] * S[2]));
+}
+
+// ---------------------------------------------------------------------------
+// element-level debug kernels
+// ---------------------------------------------------------------------------
+__global__ void k_dbg_classify(int kind, int n, const double *x12, int *types, double *d2) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  types[k] = classify(kind, x12 + 12 * (size_t)k, &d2[k]);
+}
+
+__global__ void k_dbg_pair(int kind, int type, const double *x12, double dhat, double kappa, double eps_x, int project,
+                           double *out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double x[12], g[12], H[144], scr[168];
+  for (int i = 0; i < 12; ++i) x[i] = x12[i];
+  out[0] = pair_barrier_full(kind, type, x, dhat, kappa, eps_x, project != 0, g, H, scr);
+  for (int i = 0; i < 12; ++i) out[1 + i] = g[i];
+  for (int i = 0; i < 144; ++i) out[13 + i] = H[i];
+}
+
+__global__ void k_dbg_tet(const double *X12, const double *x12, double mu, double la, double *out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double Dm[9], Dinv[9];
+  for (int i = 0; i < 3; ++i)
+    for (int a = 0; a < 3; ++a) Dm[i * 3 + a] = X12[3 * (a + 1) + i] - X12[i];
+  inv33(Dm, Dinv);
+  double vol = det33(Dm) / 6.0;
+  double x[12], g[12], blocks[90], HF[81], V[81], en;
+  for (int i = 0; i < 12; ++i) x[i] = x12[i];
+  if (!nh_element(x, Dinv, vol, mu, la, &en, g, blocks, HF, V)) {
+    out[0] = kInf;
+    return;
+  }
+  out[0] = en;
+  for (int i = 0; i < 12; ++i) out[1 + i] = g[i];
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b)
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+          const double *B = blocks + 9 * (a <= b ? blk_index(a, b) : blk_index(b, a));
+          out[13 + (3 * a + r) * 12 + 3 * b + c] = (a <= b) ? B[3 * r + c] : B[3 * c + r];
+        }
+}
+
+__global__ void k_dbg_accd(int kind, int n, const double *x12, const double *p12, double sfac, double *t) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  t[k] = accd(kind, x12 + 12 * (size_t)k, p12 + 12 * (size_t)k, sfac);
+}
+
+__global__ void k_fill_int(int *p, int n, int v) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+inline int nblk(int n, int b) { return (n + b - 1) / b; }
+
+}  // namespace
+
+// ===========================================================================
+// launchers
+// ===========================================================================
+namespace ipck {
+
+void begin_step(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B) {
+  if (B.n_vt) k_begin_step<<<B.n_vt, TB, 0, s>>>(W, E, S, B.vtiles);
+}
+void dbc_check_J(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B) {
+  if (B.n_tt) k_dbc_J<<<B.n_tt, TB, 0, s>>>(W, E, S, B.ttiles);
+}
+void apply_dbc(hipStream_t s, const WorldDev &W, const EnvDev *, const EnvState &S, const Batch &B) {
+  if (B.n_vt) k_apply_dbc<<<B.n_vt, TB, 0, s>>>(W, S, B.vtiles);
+}
+void env_begin(hipStream_t s, const EnvState &S, const Batch &B) {
+  k_env_begin<<<nblk(B.n_envs, 64), 64, 0, s>>>(S, B.envs, B.n_envs);
+}
+void env_dbc(hipStream_t s, const EnvState &S, const Batch &B) {
+  k_env_dbc<<<nblk(B.n_envs, 64), 64, 0, s>>>(S, B.envs, B.n_envs);
+}
+
+void boxes(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, const double *x,
+           const double *p) {
+  if (B.n_svt) k_boxes<<<B.n_svt, TB, 0, s>>>(W, E, S, B.svtiles, 0, x, p);
+  if (B.n_trit) k_boxes<<<B.n_trit, TB, 0, s>>>(W, E, S, B.tritiles, 1, x, p);
+  if (B.n_et) k_boxes<<<B.n_et, TB, 0, s>>>(W, E, S, B.etiles, 2, x, p);
+}
+
+void bp_count(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L) {
+  if (B.n_it) k_bp<false><<<B.n_it, TB, 0, s>>>(W, E, S, B.itiles, L.counts, nullptr, nullptr);
+}
+void bp_write(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L) {
+  if (B.n_it) k_bp<true><<<B.n_it, TB, 0, s>>>(W, E, S, B.itiles, nullptr, L.offs, L.cand);
+}
+
+void scan_int(hipStream_t s, const int *in, int *out, int n, int *tmp) {
+  int nb = nblk(n, SCAN_PER_BLOCK);
+  if (nb > 0) k_scan1<<<nb, TB, 0, s>>>(in, out, n, tmp);
+  k_scan2<<<1, TB, 0, s>>>(tmp, nb, out + n);
+  if (n > 0) k_scan3<<<nblk(n, TB), TB, 0, s>>>(out, n, tmp);
+}
+
+void cand_segments(hipStream_t s, const EnvDev *E, const EnvState &S, const Batch &B, const Lists &L) {
+  k_cand_seg<<<nblk(B.n_envs, 64), 64, 0, s>>>(E, S, B.envs, B.n_envs, L.offs);
+}
+
+void classify_cands(hipStream_t s, const WorldDev &W, const EnvDev *E, const Lists &L, int n, const double *x) {
+  if (n) k_classify<<<nblk(n, TB), TB, 0, s>>>(W, E, L.cand, n, x, L.cand_type, L.cand_d2, L.cand_flag);
+}
+void compact_active(hipStream_t s, const Lists &L, int n) {
+  if (n) k_compact<<<nblk(n, TB), TB, 0, s>>>(L.cand, L.cand_type, L.cand_flag, L.cand_offs, n, L.act, L.act_type);
+}
+void act_segments(hipStream_t s, const EnvState &S, const Batch &B, const Lists &L) {
+  k_act_seg<<<nblk(B.n_envs, 64), 64, 0, s>>>(S, B.envs, B.n_envs, L.cand_offs);
+}
+void barrier_elems(hipStream_t s, const WorldDev &W, const EnvDev *E, const Lists &L, int n_act, const double *x) {
+  if (n_act)
+    k_barrier_elems<<<nblk(n_act, 128), 128, 0, s>>>(W, E, L.act, L.act_type, n_act, x, L.ce_v, L.ce_g, L.ce_H);
+}
+void friction_setup(hipStream_t s, const WorldDev &W, const EnvDev *E, const Lists &L, int n_act) {
+  if (n_act)
+    k_friction_setup<<<nblk(n_act, TB), TB, 0, s>>>(W, E, L.act, L.act_type, n_act, L.fv, L.fw, L.fn, L.flam, L.fenv);
+}
+void friction_elems(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Lists &L, int n_fric,
+                    int ce_off, const double *x) {
+  if (n_fric)
+    k_friction_elems<<<nblk(n_fric, TB), TB, 0, s>>>(W, E, S, L.fv, L.fw, L.fn, L.flam, L.fenv, n_fric, x,
+                                                      L.ce_v + ce_off, L.ce_g + 12 * (size_t)ce_off,
+                                                      L.ce_H + 90 * (size_t)ce_off);
+}
+
+void incidence(hipStream_t s, const WorldDev &W, Lists &L, int n_ce, int nv_world, int *total_out_dev) {
+  k_fill_int<<<nblk(nv_world + 1, TB), TB, 0, s>>>(L.inc_cnt, nv_world + 1, 0);
+  k_fill_int<<<nblk(nv_world + 1, TB), TB, 0, s>>>(L.inc_cur, nv_world + 1, 0);
+  if (n_ce) k_inc_count<<<nblk(n_ce, TB), TB, 0, s>>>(W, L.ce_v, n_ce, L.inc_cnt);
+  scan_int(s, L.inc_cnt, L.inc_off, nv_world, L.scan_tmp);
+  (void)total_out_dev;
+}
+void incidence_fill(hipStream_t s, const WorldDev &W, Lists &L, int n_ce, int nv_world) {
+  if (n_ce) {
+    k_inc_fill<<<nblk(n_ce, TB), TB, 0, s>>>(W, L.ce_v, n_ce, L.inc_off, L.inc_cur, L.inc_ent);
+    k_inc_sort<<<nblk(nv_world, TB), TB, 0, s>>>(L.inc_off, L.inc_ent, nv_world);
+  }
+}
+
+void elastic(hipStream_t s, const WorldDev &W, const EnvDev *, const EnvState &S, const Batch &B) {
+  if (B.n_tt) k_elastic<<<B.n_tt, TB, 0, s>>>(W, S, B.ttiles);
+}
+
+void assemble(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, const Lists &L,
+              int mixed) {
+  if (!B.n_vt) return;
+  k_assemble_rows<<<B.n_vt, TB, 0, s>>>(W, E, S, B.vtiles, L.inc_off, L.inc_ent, L.ce_g, L.ce_H, mixed);
+  k_assemble_sell<<<B.n_vt, TB, 0, s>>>(W, E, S, B.vtiles, mixed);
+}
+
+void pcg_init(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L,
+              int *pending, int mixed) {
+  k_fill_int<<<1, 64, 0, s>>>(pending, 1, 0);
+  if (B.n_vt && !mixed) k_pcg_init<<<B.n_vt, TB, 0, s>>>(W, S, B.vtiles, L.part_b0, L.part_c0);
+  if (B.n_vt && mixed) k_pcg_init32<<<B.n_vt, TB, 0, s>>>(W, S, B.vtiles, L.part_b0, L.part_c0);
+  k_pcg_env_init<<<nblk(B.n_envs, 64), 64, 0, s>>>(E, S, B.envs, B.n_envs, L.part_c0, pending);
+}
+
+void pcg_iter(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L, int it,
+              int *pending, int mixed, int cap) {
+  if (!B.n_vt) return;
+  double *rz_old = (it & 1) ? L.part_b1 : L.part_b0;
+  double *rz_new = (it & 1) ? L.part_b0 : L.part_b1;
+  double *rr_new = (it & 1) ? L.part_c0 : L.part_c1;
+  if (!mixed) {
+    k_spmv<double><<<B.n_vt, TB, 0, s>>>(W, E, S, B.vtiles, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, W.pp, W.q, W.val,
+                                         L.part_a);
+    k_pcg_update<double><<<B.n_vt, TB, 0, s>>>(W, E, S, B.vtiles, L.part_a, rz_old, rz_new, rr_new, W.p, W.r, W.z,
+                                               W.pp, W.q, W.Minv);
+    k_pcg_dir<double><<<B.n_vt, TB, 0, s>>>(W, E, S, B.vtiles, rz_old, rz_new, rr_new, W.pp, W.z, pending, cap);
+  } else {
+    k_spmv<float><<<B.n_vt, TB, 0, s>>>(W, E, S, B.vtiles, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, W.pp32, W.q32,
+                                        W.val32, L.part_a);
+    k_pcg_update<float><<<B.n_vt, TB, 0, s>>>(W, E, S, B.vtiles, L.part_a, rz_old, rz_new, rr_new, W.p32, W.r32,
+                                              W.z32, W.pp32, W.q32, W.Minv32);
+    k_pcg_dir<float><<<B.n_vt, TB, 0, s>>>(W, E, S, B.vtiles, rz_old, rz_new, rr_new, W.pp32, W.z32, pending, cap);
+  }
+}
+
+void pcg_finish(hipStream_t s, const WorldDev &W, const EnvState &S, const Batch &B, int mixed) {
+  if (mixed && B.n_vt) k_p32_to_p<<<B.n_vt, TB, 0, s>>>(W, S, B.vtiles);
+}
+
+void spmv_debug(hipStream_t s, const WorldDev &W, const EnvDev *, const EnvState &S, const Batch &B, Lists &L,
+                const double *in, double *out) {
+  if (B.n_vt) k_spmv_dbg<<<B.n_vt, TB, 0, s>>>(W, S, B.vtiles, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, in, out);
+}
+
+void conv_check(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L,
+                int *n_active) {
+  k_fill_int<<<1, 64, 0, s>>>(n_active, 1, 0);
+  if (B.n_vt) k_pinf<<<B.n_vt, TB, 0, s>>>(W, S, B.vtiles, L.part_a);
+  k_env_conv<<<nblk(B.n_envs, 64), 64, 0, s>>>(E, S, B.envs, B.n_envs, L.part_a, n_active);
+}
+
+void ccd_init(hipStream_t s, const EnvState &S, const Batch &B) {
+  k_ccd_init<<<nblk(B.n_envs, 64), 64, 0, s>>>(S, B.envs, B.n_envs);
+}
+void accd(hipStream_t s, const WorldDev &W, const EnvDev *, const EnvState &S, const Lists &L, int n, const double *x,
+          const double *p) {
+  if (n) k_accd<<<nblk(n, 128), 128, 0, s>>>(W, S, L.cand, n, x, p);
+}
+void ls_init(hipStream_t s, const EnvState &S, const Batch &B) {
+  k_ls_init<<<nblk(B.n_envs, 64), 64, 0, s>>>(S, B.envs, B.n_envs);
+}
+
+void energy(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L, int n_cand,
+            int n_fric, int zero_alpha, double *E_out) {
+  if (B.n_vt) k_energy_v<<<B.n_vt, TB, 0, s>>>(W, E, S, B.vtiles, zero_alpha);
+  if (B.n_tt) k_energy_t<<<B.n_tt, TB, 0, s>>>(W, S, B.ttiles, zero_alpha);
+  if (n_cand) k_energy_c<<<nblk(n_cand, TB), TB, 0, s>>>(W, E, S, L.cand, n_cand, zero_alpha, L.e_c);
+  if (n_fric)
+    k_energy_f<<<nblk(n_fric, TB), TB, 0, s>>>(W, E, S, L.fv, L.fw, L.fn, L.flam, L.fenv, n_fric, zero_alpha, L.e_f);
+  k_env_energy<<<B.n_envs, TB, 0, s>>>(W, E, S, B.envs, L.e_c, L.e_f, E_out);
+}
+
+void ls_decide(hipStream_t s, const EnvState &S, const Batch &B, int *pending) {
+  k_fill_int<<<1, 64, 0, s>>>(pending, 1, 0);
+  k_ls_decide<<<nblk(B.n_envs, 64), 64, 0, s>>>(S, B.envs, B.n_envs, pending);
+}
+void update_x(hipStream_t s, const WorldDev &W, const EnvState &S, const Batch &B) {
+  if (B.n_vt) k_update_x<<<B.n_vt, TB, 0, s>>>(W, S, B.vtiles);
+}
+void iter_end(hipStream_t s, const EnvDev *E, const EnvState &S, const Batch &B, int *n_active) {
+  k_fill_int<<<1, 64, 0, s>>>(n_active, 1, 0);
+  k_iter_end<<<nblk(B.n_envs, 64), 64, 0, s>>>(E, S, B.envs, B.n_envs, n_active);
+}
+void step_end(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B) {
+  if (B.n_vt) k_step_end<<<B.n_vt, TB, 0, s>>>(W, E, S, B.vtiles);
+}
+
+void stress(hipStream_t s, const WorldDev &W, int t_off, int nt, double *cauchy, double *vm) {
+  if (nt) k_stress<<<nblk(nt, TB), TB, 0, s>>>(W, t_off, nt, cauchy, vm);
+}
+
+void dbg_classify(hipStream_t s, int kind, int n, const double *x12, int *types, double *d2) {
+  if (n) k_dbg_classify<<<nblk(n, TB), TB, 0, s>>>(kind, n, x12, types, d2);
+}
+void dbg_pair(hipStream_t s, int kind, int type, const double *x12, double dhat, double kappa, double eps_x,
+              int project, double *out) {
+  k_dbg_pair<<<1, 64, 0, s>>>(kind, type, x12, dhat, kappa, eps_x, project, out);
+}
+void dbg_tet(hipStream_t s, const double *X12, const double *x12, double mu, double la, double *out) {
+  k_dbg_tet<<<1, 64, 0, s>>>(X12, x12, mu, la, out);
+}
+void dbg_accd(hipStream_t s, int kind, int n, const double *x12, const double *p12, double sfac, double *t) {
+  if (n) k_dbg_accd<<<nblk(n, 128), 128, 0, s>>>(kind, n, x12, p12, sfac, t);
+}
+
+}  // namespace ipck

@@ -1,0 +1,89 @@
+// ipc_world.h -- device-side data layout shared by the host driver and kernels.
+//
+// All scenes on a device live in one "world": every per-vertex, per-tet and
+// per-surface-primitive array is one flat device allocation, and each scene
+// (environment) owns a contiguous range in each of them.  Vertex ranges are
+// aligned to 64 so that a 64-row slice of the sliced-ELL Hessian never mixes
+// environments.  Kernels walk per-environment tiles, so every reduction is
+// taken in an order relative to the environment's own start: an environment
+// produces the same bits alone or in any batch.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ipcw {
+
+constexpr int kTile = 256;     // elements per work tile (one 256-thread block)
+constexpr int kSlice = 64;     // rows per sliced-ELL slice (one wavefront)
+
+enum Status { ST_IDLE = 0, ST_ACTIVE = 1, ST_CONVERGED = 2, ST_FAILED = 3 };
+enum Fail { FAIL_NONE = 0, FAIL_MAXIT = 1, FAIL_NONFINITE = 2, FAIL_LS = 3, FAIL_DBC = 4 };
+
+// vertex kind codes in kin[]: >= 0 kinematic group, -1 free, -2 padding row
+constexpr int KIN_FREE = -1;
+constexpr int KIN_PAD = -2;
+
+struct Tile {
+  int env;    // environment slot
+  int start;  // first global element index
+  int count;  // elements in this tile (<= kTile)
+  int rel;    // tile index relative to the environment's first tile
+};
+
+// Static description of one environment (device copy, indexed by slot).
+struct EnvDev {
+  int v_off, nv, nv_pad;
+  int t_off, nt;
+  int tri_off, ntri;
+  int e_off, ne;
+  int sv_off, nsv;
+  int pos_off, npos;
+  int mo_off, n_groups, n_motion;
+  int step;
+  int maxit, precision;
+  int vtile_first, vtile_count;  // this env's tiles in the batch vertex-tile list
+  int item_off;                  // first broad-phase work item in the batch
+  double dt, dhat, kappa, mu, eps_v, tol, pcg_tol;
+};
+
+// Per-environment solver state (device arrays indexed by slot).
+struct EnvState {
+  int *status, *reason, *iters, *halvings, *ls_done, *ls_cnt, *pcg_done, *pcg_it, *dbc_bad;
+  long long *pcg_total;
+  double *alpha, *E0, *E1, *pinf;
+  unsigned long long *amax_bits;  // CCD bound as ordered bits of a non-negative double
+  int *cand_beg, *cand_end, *act_beg, *act_end, *fric_beg, *fric_end;
+  int *in_step;                   // 1 if the env takes part in the current step
+  double *pcg_bb;                 // |g|^2 of the current solve
+};
+
+// Flat device arrays of the world (element-indexed).
+struct WorldDev {
+  // per vertex
+  double *X, *x, *v, *xn, *xh, *p, *g, *r, *z, *pp, *q, *mass, *Minv, *e_v;
+  float *r32, *z32, *pp32, *q32, *p32, *Minv32;
+  int *kin, *venv, *vt_beg, *vt_end;
+  // per slice (vertex / 64)
+  int *slice_pos, *slice_w;
+  // per sliced-ELL position
+  int *col, *cb_beg, *cb_end;
+  double *val;   // [pos/64][9][64]
+  float *val32;  // same layout
+  // contributor entries and vertex->tet incidence
+  int *contrib, *vt_ent;
+  // per tet
+  int4 *tet;
+  double *Dinv, *vol, *mu, *la, *tg, *tH, *e_t;
+  int *tenv;
+  // surface primitives
+  int4 *tri;    // x,y,z vertex ids (ascending), w = env
+  int4 *edge;   // x,y vertex ids (ascending), z = env
+  double *elen2;
+  int *sv;      // vertex id
+  int *sv_env;
+  double *box_sv, *box_tri, *box_edge;  // [6] lo.xyz hi.xyz
+  // motion / gravity (per env ranges)
+  double *motion;
+};
+
+}  // namespace ipcw

@@ -1,0 +1,315 @@
+"""Python binding of the C-ABI in include/ipc.h (argument marshalling only).
+
+Every computation runs in the HIP library ``libipc_mi355x.so``; this module
+only converts numpy arrays to pointers.  Loading fails loudly when the
+library has not been built: there is no other implementation behind it.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libipc_mi355x.so")
+
+IPC_OK = 0
+IPC_E_ARG = -1
+IPC_E_INVERTED = -2
+IPC_E_INTERSECTING = -3
+IPC_E_NOMEM = -4
+IPC_E_FAILED = -5
+IPC_E_DEVICE = -6
+IPC_FP64 = 0
+IPC_MIXED = 1
+FAIL_REASONS = {0: "none", 1: "maxit", 2: "nonfinite", 3: "line-search", 4: "dirichlet"}
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+
+
+class ipc_scene_desc(C.Structure):
+    _fields_ = [
+        ("n_verts", C.c_int32), ("rest_pos", _dp), ("init_pos", _dp), ("init_vel", _dp),
+        ("n_tets", C.c_int32), ("tets", _ip), ("E", _dp), ("nu", _dp), ("rho", _dp),
+        ("n_tris", C.c_int32), ("tris", _ip), ("kin_group", _ip),
+        ("n_groups", C.c_int32), ("n_motion_steps", C.c_int32), ("motion", _dp), ("gravity", _dp),
+        ("dt", C.c_double), ("dhat", C.c_double), ("kappa", C.c_double), ("mu", C.c_double),
+        ("eps_v", C.c_double), ("newton_tol", C.c_double), ("newton_max_iter", C.c_int32),
+        ("pcg_rel_tol", C.c_double), ("precision", C.c_int32),
+    ]
+
+
+class ipc_step_info(C.Structure):
+    _fields_ = [
+        ("steps_done", C.c_int32), ("status", C.c_int32), ("fail_reason", C.c_int32),
+        ("newton_iters", C.c_int32), ("max_newton_iters", C.c_int32), ("ls_halvings", C.c_int32),
+        ("pcg_iters", C.c_int64), ("n_active_last", C.c_int64), ("min_dist_last", C.c_double),
+        ("energy_last", C.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+EXPORTS = [
+    "ipc_create_scene", "ipc_step", "ipc_step_batch", "ipc_get_state", "ipc_set_state", "ipc_destroy_scene",
+    "ipc_last_error", "ipc_scene_sizes", "ipc_debug_candidates", "ipc_debug_active", "ipc_debug_begin_step",
+    "ipc_debug_gradient", "ipc_debug_energy", "ipc_debug_hessian_apply", "ipc_debug_newton_dir",
+    "ipc_debug_ccd_bound", "ipc_debug_classify", "ipc_debug_pair_barrier", "ipc_debug_tet_elastic",
+    "ipc_debug_accd",
+]
+
+_lib = None
+
+
+def lib():
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2503_05020_amd.build.build()")
+    L = C.CDLL(LIB_PATH)
+    vp = C.c_void_p
+    L.ipc_create_scene.argtypes = [C.POINTER(ipc_scene_desc), C.POINTER(vp)]
+    L.ipc_step.argtypes = [vp, C.c_int32, C.POINTER(ipc_step_info)]
+    L.ipc_step_batch.argtypes = [C.POINTER(vp), C.c_int32, C.c_int32, C.POINTER(ipc_step_info)]
+    L.ipc_get_state.argtypes = [vp, _dp, _dp, _dp, _dp]
+    L.ipc_set_state.argtypes = [vp, _dp, _dp, C.c_int32]
+    L.ipc_destroy_scene.argtypes = [vp]
+    L.ipc_destroy_scene.restype = None
+    L.ipc_last_error.restype = C.c_char_p
+    L.ipc_scene_sizes.argtypes = [vp, C.POINTER(C.c_int64)]
+    L.ipc_debug_candidates.argtypes = [vp, _dp, _dp, _ip, C.c_int64]
+    L.ipc_debug_candidates.restype = C.c_int64
+    L.ipc_debug_active.argtypes = [vp, _dp, _ip, _dp, C.c_int64]
+    L.ipc_debug_active.restype = C.c_int64
+    L.ipc_debug_begin_step.argtypes = [vp, _dp]
+    L.ipc_debug_gradient.argtypes = [vp, _dp, _dp]
+    L.ipc_debug_energy.argtypes = [vp, _dp]
+    L.ipc_debug_energy.restype = C.c_double
+    L.ipc_debug_hessian_apply.argtypes = [vp, _dp, _dp, _dp]
+    L.ipc_debug_newton_dir.argtypes = [vp, _dp, _dp, C.POINTER(C.c_int64)]
+    L.ipc_debug_ccd_bound.argtypes = [vp, _dp, _dp]
+    L.ipc_debug_ccd_bound.restype = C.c_double
+    L.ipc_debug_classify.argtypes = [C.c_int32, C.c_int64, _dp, _ip, _dp]
+    L.ipc_debug_pair_barrier.argtypes = [C.c_int32, C.c_int32, _dp, C.c_double, C.c_double, C.c_double, C.c_int32,
+                                         _dp, _dp, _dp]
+    L.ipc_debug_tet_elastic.argtypes = [_dp, _dp, C.c_double, C.c_double, C.c_int32, _dp, _dp, _dp]
+    L.ipc_debug_accd.argtypes = [C.c_int32, C.c_int64, _dp, _dp, C.c_double, _dp]
+    L.ipc_debug_accd.restype = C.c_int64
+    _lib = L
+    return L
+
+
+class IPCError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"ipc error {code}: {msg}")
+        self.code = code
+
+
+def _check(rc):
+    if rc < 0:
+        raise IPCError(rc, lib().ipc_last_error().decode())
+    return rc
+
+
+def _d(a):
+    return None if a is None else a.ctypes.data_as(_dp)
+
+
+def _i(a):
+    return None if a is None else a.ctypes.data_as(_ip)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def ipc_last_error() -> str:
+    return lib().ipc_last_error().decode()
+
+
+def make_desc(sc: dict, precision: int = IPC_FP64, pcg_rel_tol: float = 1e-4, **overrides):
+    """Build an ipc_scene_desc from a scene dict; returns (desc, keep-alive arrays)."""
+    p = dict(sc)
+    p.update(overrides)
+    keep = dict(
+        rest=_f64(p["rest_pos"]).reshape(-1),
+        init=_f64(p.get("init_pos", p["rest_pos"])).reshape(-1),
+        vel=_f64(p.get("init_vel", np.zeros_like(p["rest_pos"]))).reshape(-1),
+        tets=np.ascontiguousarray(p["tets"], np.int32).reshape(-1),
+        E=_f64(p["E"]), nu=_f64(p["nu"]), rho=_f64(p["rho"]),
+        tris=np.ascontiguousarray(p["tris"], np.int32).reshape(-1),
+        kin=np.ascontiguousarray(p["kin_group"], np.int32),
+        motion=_f64(p["motion"]).reshape(-1), gravity=_f64(p["gravity"]).reshape(-1),
+    )
+    motion = np.asarray(p["motion"])
+    d = ipc_scene_desc(
+        len(keep["kin"]), _d(keep["rest"]), _d(keep["init"]), _d(keep["vel"]),
+        len(keep["E"]), _i(keep["tets"]), _d(keep["E"]), _d(keep["nu"]), _d(keep["rho"]),
+        len(keep["tris"]) // 3, _i(keep["tris"]), _i(keep["kin"]),
+        motion.shape[1], motion.shape[0], _d(keep["motion"]), _d(keep["gravity"]),
+        p["dt"], p["dhat"], p["kappa"], p["mu"], p["eps_v"], p["newton_tol"], int(p["newton_max_iter"]),
+        pcg_rel_tol, precision)
+    return d, keep
+
+
+def ipc_create_scene(sc: dict, precision: int = IPC_FP64, pcg_rel_tol: float = 1e-4, **overrides) -> "Scene":
+    d, keep = make_desc(sc, precision, pcg_rel_tol, **overrides)
+    h = C.c_void_p()
+    _check(lib().ipc_create_scene(C.byref(d), C.byref(h)))
+    return Scene(h, len(keep["kin"]), len(keep["E"]))
+
+
+def ipc_step(scene: "Scene", n_steps: int = 1):
+    info = ipc_step_info()
+    rc = lib().ipc_step(scene.h, n_steps, C.byref(info))
+    if rc < 0 and rc != IPC_E_FAILED:
+        _check(rc)
+    return rc, info.as_dict()
+
+
+def ipc_step_batch(scenes, n_steps: int = 1):
+    arr = (C.c_void_p * len(scenes))(*[s.h.value for s in scenes])
+    infos = (ipc_step_info * max(1, len(scenes)))()
+    rc = lib().ipc_step_batch(arr, len(scenes), n_steps, infos)
+    if rc < 0 and rc != IPC_E_FAILED:
+        _check(rc)
+    return rc, [infos[i].as_dict() for i in range(len(scenes))]
+
+
+def ipc_get_state(scene: "Scene", stress: bool = False):
+    pos = np.zeros((scene.nv, 3))
+    vel = np.zeros((scene.nv, 3))
+    cau = np.zeros((scene.nt, 6)) if stress else None
+    vm = np.zeros(scene.nt) if stress else None
+    _check(lib().ipc_get_state(scene.h, _d(pos), _d(vel), _d(cau), _d(vm)))
+    return (pos, vel, cau, vm) if stress else (pos, vel)
+
+
+def ipc_set_state(scene: "Scene", pos, vel=None, step: int = 0):
+    v = None if vel is None else _f64(vel)
+    _check(lib().ipc_set_state(scene.h, _d(_f64(pos)), _d(v), step))
+
+
+def ipc_destroy_scene(scene: "Scene"):
+    if scene.h is not None and _lib is not None:
+        _lib.ipc_destroy_scene(scene.h)
+        scene.h = None
+
+
+def ipc_scene_sizes(scene: "Scene"):
+    out = (C.c_int64 * 7)()
+    _check(lib().ipc_scene_sizes(scene.h, out))
+    return list(out)
+
+
+class Scene:
+    """Handle of a scene living in device memory."""
+
+    def __init__(self, h, nv, nt):
+        self.h, self.nv, self.nt = h, nv, nt
+
+    def __del__(self):
+        try:
+            ipc_destroy_scene(self)
+        except Exception:
+            pass
+
+    # convenience wrappers
+    def step(self, n=1):
+        return ipc_step(self, n)
+
+    def state(self, stress=False):
+        return ipc_get_state(self, stress)
+
+
+# --- inspection entry points -------------------------------------------------
+def ipc_debug_candidates(scene, x, p=None):
+    x = _f64(x)
+    p = None if p is None else _f64(p)
+    n = _check(lib().ipc_debug_candidates(scene.h, _d(x), _d(p), None, 0))
+    out = np.zeros((max(n, 1), 5), np.int32)
+    _check(lib().ipc_debug_candidates(scene.h, _d(x), _d(p), _i(out), n))
+    return out[:n]
+
+
+def ipc_debug_active(scene, x):
+    x = _f64(x)
+    n = _check(lib().ipc_debug_active(scene.h, _d(x), None, None, 0))
+    out = np.zeros((max(n, 1), 6), np.int32)
+    d2 = np.zeros(max(n, 1))
+    _check(lib().ipc_debug_active(scene.h, _d(x), _i(out), _d(d2), n))
+    return out[:n], d2[:n]
+
+
+def ipc_debug_begin_step(scene):
+    x0 = np.zeros((scene.nv, 3))
+    _check(lib().ipc_debug_begin_step(scene.h, _d(x0)))
+    return x0
+
+
+def ipc_debug_gradient(scene, x):
+    g = np.zeros((scene.nv, 3))
+    _check(lib().ipc_debug_gradient(scene.h, _d(_f64(x)), _d(g)))
+    return g
+
+
+def ipc_debug_energy(scene, x):
+    return lib().ipc_debug_energy(scene.h, _d(_f64(x)))
+
+
+def ipc_debug_hessian_apply(scene, x, v):
+    y = np.zeros((scene.nv, 3))
+    _check(lib().ipc_debug_hessian_apply(scene.h, _d(_f64(x)), _d(_f64(v)), _d(y)))
+    return y
+
+
+def ipc_debug_newton_dir(scene, x):
+    p = np.zeros((scene.nv, 3))
+    it = C.c_int64()
+    _check(lib().ipc_debug_newton_dir(scene.h, _d(_f64(x)), _d(p), C.byref(it)))
+    return p, it.value
+
+
+def ipc_debug_ccd_bound(scene, x, p):
+    return lib().ipc_debug_ccd_bound(scene.h, _d(_f64(x)), _d(_f64(p)))
+
+
+def ipc_debug_classify(kind, x12):
+    x12 = _f64(x12).reshape(-1, 12)
+    n = len(x12)
+    t = np.zeros(n, np.int32)
+    d2 = np.zeros(n)
+    _check(lib().ipc_debug_classify(kind, n, _d(x12), _i(t), _d(d2)))
+    return t, d2
+
+
+def ipc_debug_pair_barrier(kind, type_, x12, dhat, kappa, eps_x=0.0, project=True):
+    e = C.c_double()
+    g = np.zeros(12)
+    H = np.zeros(144)
+    _check(lib().ipc_debug_pair_barrier(kind, type_, _d(_f64(x12).reshape(-1)), dhat, kappa, eps_x, int(project),
+                                        C.byref(e), _d(g), _d(H)))
+    return e.value, g, H.reshape(12, 12)
+
+
+def ipc_debug_tet_elastic(X12, x12, E, nu):
+    e = C.c_double()
+    g = np.zeros(12)
+    H = np.zeros(144)
+    rc = lib().ipc_debug_tet_elastic(_d(_f64(X12).reshape(-1)), _d(_f64(x12).reshape(-1)), E, nu, 1, C.byref(e),
+                                     _d(g), _d(H))
+    return rc, e.value, g, H.reshape(12, 12)
+
+
+def ipc_debug_accd(kind, x12, p12, s=0.1):
+    x12 = _f64(x12).reshape(-1, 12)
+    p12 = _f64(p12).reshape(-1, 12)
+    n = len(x12)
+    t = np.zeros(n)
+    _check(lib().ipc_debug_accd(kind, n, _d(x12), _d(p12), s, _d(t)))
+    return t
