@@ -1,0 +1,147 @@
+"""Throughput of the batched IPC Newton step on one MI355X.
+
+Workload (default): 256 grasp environments stepped together in every launch --
+soft superquadric objects (tet count lognormal, median 5k, clipped to
+[1k, 20k]) squeezed by a two-slab soft gripper, dt = 0.01 s, dhat = 1e-3 m,
+100-step horizon (closing 60 steps, then lifting 40).  A bench "step" is one
+time step of every environment; the metric is converged environment-steps per
+second.  Inputs are seeded synthetic scenes shaped like the paper's grasp
+validations (Sec. III-D); they are resident in device memory before timing.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_2503_05020_amd import ipc as G  # noqa: E402
+from paper_2503_05020_amd import scenes as S  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_scenes(workload: str, n_envs: int):
+    if workload == "superquadric_batch":
+        return [S.superquadric_grasp(i) for i in range(n_envs)]
+    if workload == "sphere_grasp":
+        return [S.parallel_jaw_sphere(seed=i) for i in range(n_envs)]
+    if workload == "cube_drop":
+        return [S.soft_cube_drop(seed=i) for i in range(n_envs)]
+    raise SystemExit(f"unknown workload {workload}")
+
+
+def run_gpu(scs, precision, warmup, steps, pcg_tol):
+    t0 = time.time()
+    gs = [G.ipc_create_scene(sc, precision=precision, pcg_rel_tol=pcg_tol) for sc in scs]
+    log(f"created {len(gs)} scenes in {time.time() - t0:.1f}s")
+    for k in range(warmup):
+        rc, infos = G.ipc_step_batch(gs, 1)
+        log(f"warmup step {k}: rc={rc} newton(max)={max(i['max_newton_iters'] for i in infos)}")
+    G.ipc_prof_reset()
+    t0 = time.perf_counter()
+    converged = 0
+    newton = pcg = 0
+    for k in range(steps):
+        rc, infos = G.ipc_step_batch(gs, 1)
+        converged += sum(i["steps_done"] for i in infos)
+        newton += sum(i["newton_iters"] for i in infos)
+        pcg += sum(i["pcg_iters"] for i in infos)
+        log(f"timed step {k}: rc={rc} done={sum(i['steps_done'] for i in infos)}")
+    wall = time.perf_counter() - t0
+    prof = G.ipc_prof_read()
+    failed = sum(1 for g in gs if G.ipc_scene_sizes(g)[6])
+    return dict(wall=wall, converged=converged, newton=newton, pcg=pcg, prof=prof, failed=failed, gs=gs)
+
+
+def cpu_baseline(scs, budget_s=20.0):
+    """The oracle (single thread) on the first environments of the same workload."""
+    import oracle as O
+    t_start = time.perf_counter()
+    done = 0
+    env = 0
+    while time.perf_counter() - t_start < budget_s and env < len(scs):
+        o = O.Scene(scs[env], pcg_rel_tol=1e-4)
+        while time.perf_counter() - t_start < budget_s:
+            rc, info = o.step(1)
+            if rc != 0:
+                break
+            done += 1
+        env += 1
+    wall = time.perf_counter() - t_start
+    return dict(value=done / wall, unit="converged env-steps/s", cores=1, kind="oracle",
+                sample=f"{done} env-steps of environments 0..{env - 1} from step 0, one thread, {wall:.1f}s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=8)
+    ap.add_argument("--warmup", type=int, default=12)
+    ap.add_argument("--envs", type=int, default=256)
+    ap.add_argument("--workload", default="superquadric_batch")
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--pcg-tol", type=float, default=1e-4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: environments are independent and would be sharded across GPUs "
+              "without any collective; only --gpus 1 is supported on this box.", file=sys.stderr)
+        sys.exit(2)
+    import torch  # device selection only
+    assert torch.cuda.is_available(), "no GPU"
+    torch.cuda.set_device(0)
+    scs = make_scenes(args.workload, args.envs)
+    ntets = sum(len(sc["E"]) for sc in scs)
+    log(f"workload {args.workload}: {len(scs)} envs, {ntets} tets")
+    prec = G.IPC_MIXED if args.precision == "mixed" else G.IPC_FP64
+    G.ipc_prof_enable(1)
+    torch.cuda.synchronize()
+    r = run_gpu(scs, prec, args.warmup, args.steps, args.pcg_tol)
+    value = r["converged"] / r["wall"]
+    prof = r["prof"]
+    roof = None
+    if prof["spmv_launches"] > 0 and prof["spmv_ms"] > 0:
+        avg_ms = prof["spmv_ms"] / prof["spmv_launches"]
+        bytes_per_launch = prof["spmv_bytes"] / prof["spmv_launches"]
+        achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_spmv",
+                "avg_launch_us": round(avg_ms * 1e3, 2), "bytes_per_launch": int(bytes_per_launch)}
+    cpu = None if args.no_cpu_baseline else cpu_baseline(scs)
+    out = {
+        "metric": "converged sim steps/s over batched scenes",
+        "value": round(value, 2),
+        "unit": "converged env-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * r["wall"] / args.steps, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == G.IPC_FP64 else "f64+f32pcg",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "envs": len(scs), "tets": ntets, "precision": args.precision,
+                   "pcg_rel_tol": args.pcg_tol, "first_timed_step": args.warmup},
+        "newton_iters": r["newton"],
+        "pcg_iters": r["pcg"],
+        "failed_envs": r["failed"],
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

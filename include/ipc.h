@@ -129,6 +129,17 @@ const char *ipc_last_error(void);
  * out[6] failed flag. */
 int ipc_scene_sizes(ipc_scene s, int64_t out[7]);
 
+/* Measurement of the PCG matrix-vector product on the current device: when
+ * enabled, every launch of that kernel is bracketed by HIP events on the
+ * library's stream and the kernel adds the algorithmic bytes it moves (stored
+ * blocks and column indices, one read and one write of a vector row, contact
+ * blocks applied) to a device counter.  ipc_prof_read writes out[0] total
+ * event-timed milliseconds, out[1] number of launches, out[2] bytes,
+ * out[3] reserved. */
+int ipc_prof_enable(int32_t on);
+int ipc_prof_reset(void);
+int ipc_prof_read(double *out);
+
 /* ---------------------------------------------------------------------------
  * Inspection entry points.  Each runs the same device kernels the step uses,
  * on host-supplied positions, so callers can check individual stages.

@@ -147,6 +147,8 @@ class Scene:
         self.nv = len(k["kin"])
         self.nt = len(k["E"])
         motion = np.asarray(p["motion"])
+        if motion.ndim != 3 or motion.shape[2] != 12 or np.asarray(p["gravity"]).reshape(-1, 3).shape[0] != motion.shape[0]:
+            raise ValueError("motion must be [steps][groups][12] with one gravity row per step")
         d = Desc(self.nv, _d(k["rest"]), _d(k["init"]), _d(k["vel"]), self.nt, _i(k["tets"]), _d(k["E"]),
                  _d(k["nu"]), _d(k["rho"]), len(k["tris"]) // 3, _i(k["tris"]), _i(k["kin"]),
                  motion.shape[1], motion.shape[0], _d(k["motion"]), _d(k["gravity"]),

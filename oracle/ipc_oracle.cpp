@@ -812,12 +812,24 @@ double eps_cross(const Scene &s, const Pair &p) {
 // Orientation of d relative to the plane through a, b, c (sign of the triple product).
 double orient3d(V3 a, V3 b, V3 c, V3 d) { return dot(sub(b, a), cross(sub(c, a), sub(d, a))); }
 
-// True if segment (a, b) properly crosses triangle (t0, t1, t2).
+// True if segment (a, b) crosses triangle (t0, t1, t2) with a margin: the
+// endpoints lie strictly on opposite sides of the triangle's plane and the
+// segment's line passes strictly inside the triangle, each test beyond
+// 1e-9 L^3 (L = longest edge involved).  Touching and coplanar configurations
+// (orientations at rounding level) do not count as crossings.
 bool segment_crosses_triangle(V3 a, V3 b, V3 t0, V3 t1, V3 t2) {
+  V3 P[5] = {a, b, t0, t1, t2};
+  double L2 = 0.0;
+  for (int i = 0; i < 5; ++i)
+    for (int j = i + 1; j < 5; ++j) {
+      V3 d = sub(P[i], P[j]);
+      L2 = std::max(L2, dot(d, d));
+    }
+  double eps = 1e-9 * L2 * std::sqrt(L2);
   double da = orient3d(t0, t1, t2, a), db = orient3d(t0, t1, t2, b);
-  if ((da > 0 && db > 0) || (da < 0 && db < 0) || (da == 0 && db == 0)) return false;
+  if (!((da > eps && db < -eps) || (da < -eps && db > eps))) return false;
   double s0 = orient3d(a, b, t0, t1), s1 = orient3d(a, b, t1, t2), s2 = orient3d(a, b, t2, t0);
-  return (s0 >= 0 && s1 >= 0 && s2 >= 0) || (s0 <= 0 && s1 <= 0 && s2 <= 0);
+  return (s0 > eps && s1 > eps && s2 > eps) || (s0 < -eps && s1 < -eps && s2 < -eps);
 }
 
 bool finite(const double *p, long n) {

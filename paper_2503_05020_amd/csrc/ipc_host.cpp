@@ -142,6 +142,7 @@ struct HostScene {
   std::vector<int> sverts;
   std::vector<double> elen2;
   std::vector<int> vt_beg, vt_end, vt_ent;  // local tet*4+slot
+  std::vector<int> row_nnz;                  // stored blocks per row (without ELL padding)
   std::vector<int> slice_pos, slice_w;       // per local slice (positions local)
   std::vector<int> col, cb_beg, cb_end, contrib;
   std::vector<double> motion;  // motion rows then gravity rows
@@ -184,11 +185,24 @@ double orient(const double *a, const double *b, const double *c, const double *d
   return u[0] * (v[1] * w[2] - v[2] * w[1]) - u[1] * (v[0] * w[2] - v[2] * w[0]) + u[2] * (v[0] * w[1] - v[1] * w[0]);
 }
 
+// Segment (a, b) crosses triangle (t0, t1, t2): strict opposite sides of the
+// plane and strictly inside the triangle, each by more than 1e-9 L^3 with L
+// the longest distance among the five points, so that coplanar or touching
+// neighbours of a valid mesh (orientations at rounding level) are not flagged.
 bool seg_tri_cross(const double *a, const double *b, const double *t0, const double *t1, const double *t2) {
+  const double *P[5] = {a, b, t0, t1, t2};
+  double L2 = 0.0;
+  for (int i = 0; i < 5; ++i)
+    for (int j = i + 1; j < 5; ++j) {
+      double s = 0.0;
+      for (int k = 0; k < 3; ++k) s += (P[i][k] - P[j][k]) * (P[i][k] - P[j][k]);
+      L2 = std::max(L2, s);
+    }
+  double eps = 1e-9 * L2 * std::sqrt(L2);
   double da = orient(t0, t1, t2, a), db = orient(t0, t1, t2, b);
-  if ((da > 0 && db > 0) || (da < 0 && db < 0) || (da == 0 && db == 0)) return false;
+  if (!((da > eps && db < -eps) || (da < -eps && db > eps))) return false;
   double s0 = orient(a, b, t0, t1), s1 = orient(a, b, t1, t2), s2 = orient(a, b, t2, t0);
-  return (s0 >= 0 && s1 >= 0 && s2 >= 0) || (s0 <= 0 && s1 <= 0 && s2 <= 0);
+  return (s0 > eps && s1 > eps && s2 > eps) || (s0 < -eps && s1 < -eps && s2 < -eps);
 }
 
 struct Box {
@@ -464,6 +478,8 @@ std::unique_ptr<HostScene> preprocess(const ipc_scene_desc *d) {
       nbr[i].erase(std::unique(nbr[i].begin() + 1, nbr[i].end()), nbr[i].end());
       nbr[i].erase(std::remove(nbr[i].begin() + 1, nbr[i].end(), i), nbr[i].end());
     }
+    H.row_nnz.resize(H.nv_pad);
+    for (int i = 0; i < H.nv_pad; ++i) H.row_nnz[i] = (int)nbr[i].size();
     int nsl = H.nv_pad / ipcw::kSlice;
     H.slice_pos.resize(nsl);
     H.slice_w.resize(nsl);
@@ -541,6 +557,12 @@ struct World {
   DBuf<double> cand_d2, e_c, fw, fn, flam, e_f, ce_g, ce_H, part_a, part_b0, part_b1, part_c0, part_c1;
   DBuf<int4> fv, ce_v;
   int *pinned = nullptr;  // host mirror of counters
+  // profiling of the PCG matrix product (HIP events on this stream)
+  bool prof_on = false;
+  DBuf<unsigned long long> prof_bytes;
+  std::vector<hipEvent_t> ev_pool;
+  double prof_ms = 0.0;
+  long long prof_launches = 0;
   int n_fric = 0;
   std::mutex mu;
 
@@ -575,6 +597,7 @@ struct World {
     reg(aV, (void **)&W.venv, 4);
     reg(aV, (void **)&W.vt_beg, 4);
     reg(aV, (void **)&W.vt_end, 4);
+    reg(aV, (void **)&W.row_nnz, 4);
     reg(aSlice, (void **)&W.slice_pos, 4);
     reg(aSlice, (void **)&W.slice_w, 4);
     reg(aPos, (void **)&W.col, 4);
@@ -699,6 +722,7 @@ struct World {
     up(W.venv + vo, venv.data(), venv.size());
     up(W.vt_beg + vo, vb.data(), vb.size());
     up(W.vt_end + vo, ve.data(), ve.size());
+    up(W.row_nnz + vo, H.row_nnz.data(), H.row_nnz.size());
     HC(hipMemsetAsync(W.p + 3 * vo, 0, 24 * R.v_n, stream));
     HC(hipMemsetAsync(W.pp + 3 * vo, 0, 24 * R.v_n, stream));
     HC(hipMemsetAsync(W.pp32 + 3 * vo, 0, 12 * R.v_n, stream));
@@ -899,6 +923,35 @@ struct World {
     L.part_c0 = part_c0.p;
     L.part_c1 = part_c1.p;
     L.counter = counter.p;
+    L.prof = prof_on ? prof_bytes.p : nullptr;
+  }
+
+  void set_prof(bool on) {
+    prof_on = on;
+    if (on && !prof_bytes.p) {
+      prof_bytes.ensure(4);
+      HC(hipMemsetAsync(prof_bytes.p, 0, 8 * prof_bytes.cap, stream));
+      HC(hipStreamSynchronize(stream));
+    }
+    refresh_lists();
+  }
+
+  void prof_reset() {
+    prof_ms = 0.0;
+    prof_launches = 0;
+    if (prof_bytes.p) {
+      HC(hipMemsetAsync(prof_bytes.p, 0, 8, stream));
+      HC(hipStreamSynchronize(stream));
+    }
+  }
+
+  hipEvent_t pool_event(size_t i) {
+    while (ev_pool.size() <= i) {
+      hipEvent_t e;
+      HC(hipEventCreate(&e));
+      ev_pool.push_back(e);
+    }
+    return ev_pool[i];
   }
 
   int read_int(const int *dptr) {
@@ -1004,11 +1057,28 @@ struct World {
     int cap = 0;
     for (int e : batch_envs) cap = std::max(cap, 30 * envs_h[e].nv + 10);
     int it = 0;
+    size_t nev = 0;
     while (true) {
-      for (int j = 0; j < 8; ++j) ipck::pcg_iter(stream, W, envs_d, S, B, L, it++, pending, mixed, cap);
+      for (int j = 0; j < 8; ++j) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (prof_on) {
+          e0 = pool_event(nev++);
+          e1 = pool_event(nev++);
+        }
+        ipck::pcg_iter(stream, W, envs_d, S, B, L, it++, pending, mixed, cap, e0, e1);
+      }
       if (read_int(pending) <= 0 || it >= cap) break;
     }
     ipck::pcg_finish(stream, W, S, B, mixed);
+    if (prof_on) {
+      HC(hipStreamSynchronize(stream));
+      for (size_t k = 0; k + 1 < nev; k += 2) {
+        float ms = 0.f;
+        HC(hipEventElapsedTime(&ms, ev_pool[k], ev_pool[k + 1]));
+        prof_ms += ms;
+        prof_launches += 1;
+      }
+    }
     return it;
   }
 
@@ -1316,6 +1386,42 @@ int ipc_set_state(ipc_scene s, const double *pos, const double *vel, int32_t ste
     s->failed = false;
     s->fail_reason = 0;
     set_status(w, s->slot, ipcw::ST_IDLE);
+    return IPC_OK;
+  });
+}
+
+int ipc_prof_enable(int32_t on) {
+  return guarded([&]() {
+    World &w = world_for_current_device();
+    std::lock_guard<std::mutex> lk(w.mu);
+    w.set_prof(on != 0);
+    return IPC_OK;
+  });
+}
+
+int ipc_prof_reset(void) {
+  return guarded([&]() {
+    World &w = world_for_current_device();
+    std::lock_guard<std::mutex> lk(w.mu);
+    w.prof_reset();
+    return IPC_OK;
+  });
+}
+
+int ipc_prof_read(double *out) {
+  return guarded([&]() {
+    if (!out) throw ApiError(IPC_E_ARG, "null output");
+    World &w = world_for_current_device();
+    std::lock_guard<std::mutex> lk(w.mu);
+    unsigned long long b = 0;
+    if (w.prof_bytes.p) {
+      HC(hipMemcpyAsync(&b, w.prof_bytes.p, 8, hipMemcpyDeviceToHost, w.stream));
+      HC(hipStreamSynchronize(w.stream));
+    }
+    out[0] = w.prof_ms;
+    out[1] = (double)w.prof_launches;
+    out[2] = (double)b;
+    out[3] = 0.0;
     return IPC_OK;
   });
 }

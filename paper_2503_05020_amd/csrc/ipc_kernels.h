@@ -39,6 +39,7 @@ struct Lists {
   // reduction partials per vertex tile
   double *part_a, *part_b0, *part_b1, *part_c0, *part_c1;
   int *counter;  // device scratch counters [4]
+  unsigned long long *prof;  // algorithmic bytes moved by profiled kernels (nullptr = off)
 };
 
 void begin_step(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B);
@@ -72,7 +73,7 @@ void assemble(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState 
 void pcg_init(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L,
               int *pending, int mixed);
 void pcg_iter(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L, int it,
-              int *pending, int mixed, int cap);
+              int *pending, int mixed, int cap, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 void pcg_finish(hipStream_t s, const WorldDev &W, const EnvState &S, const Batch &B, int mixed);
 void spmv_debug(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L,
                 const double *in, double *out);

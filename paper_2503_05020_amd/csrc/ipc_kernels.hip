@@ -786,7 +786,8 @@ __global__ void k_pcg_env_init(const EnvDev *envs, EnvState S, const int *benv, 
 template <typename T>
 __global__ void __launch_bounds__(256) k_spmv(WorldDev W, const EnvDev *envs, EnvState S, const Tile *tiles,
                                               const int *inc_off, const int *inc_ent, const int4 *ce_v,
-                                              const double *ce_H, const T *pp, T *q, const T *val, double *part_pq) {
+                                              const double *ce_H, const T *pp, T *q, const T *val, double *part_pq,
+                                              unsigned long long *prof) {
   __shared__ double sh[TB];
   Tile t = tiles[blockIdx.x];
   if (!pcg_env_live(S, t.env)) return;
@@ -803,6 +804,18 @@ __global__ void __launch_bounds__(256) k_spmv(WorldDev W, const EnvDev *envs, En
   }
   pq = block_sum(pq, sh);
   if (threadIdx.x == 0) part_pq[blockIdx.x] = pq;
+  if (prof) {
+    // algorithmic bytes of this tile: stored blocks + column indices, one read
+    // of pp and one write of q per row, and the contact blocks it applies
+    double b = 0.0;
+    if ((int)threadIdx.x < t.count) {
+      int nnz = W.row_nnz[i];
+      int ninc = inc_off[i + 1] - inc_off[i];
+      b = (double)nnz * (9.0 * sizeof(T) + 4.0) + 6.0 * sizeof(T) + ninc * (4.0 * 72.0 + 16.0);
+    }
+    b = block_sum(b, sh);
+    if (threadIdx.x == 0) atomicAdd(prof, (unsigned long long)b);
+  }
 }
 
 template <typename T>
@@ -1314,20 +1327,24 @@ void pcg_init(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState 
 }
 
 void pcg_iter(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L, int it,
-              int *pending, int mixed, int cap) {
+              int *pending, int mixed, int cap, hipEvent_t ev0, hipEvent_t ev1) {
   if (!B.n_vt) return;
   double *rz_old = (it & 1) ? L.part_b1 : L.part_b0;
   double *rz_new = (it & 1) ? L.part_b0 : L.part_b1;
   double *rr_new = (it & 1) ? L.part_c0 : L.part_c1;
   if (!mixed) {
+    if (ev0) hipEventRecord(ev0, s);
     k_spmv<double><<<B.n_vt, TB, 0, s>>>(W, E, S, B.vtiles, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, W.pp, W.q, W.val,
-                                         L.part_a);
+                                         L.part_a, L.prof);
+    if (ev1) hipEventRecord(ev1, s);
     k_pcg_update<double><<<B.n_vt, TB, 0, s>>>(W, E, S, B.vtiles, L.part_a, rz_old, rz_new, rr_new, W.p, W.r, W.z,
                                                W.pp, W.q, W.Minv);
     k_pcg_dir<double><<<B.n_vt, TB, 0, s>>>(W, E, S, B.vtiles, rz_old, rz_new, rr_new, W.pp, W.z, pending, cap);
   } else {
+    if (ev0) hipEventRecord(ev0, s);
     k_spmv<float><<<B.n_vt, TB, 0, s>>>(W, E, S, B.vtiles, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, W.pp32, W.q32,
-                                        W.val32, L.part_a);
+                                        W.val32, L.part_a, L.prof);
+    if (ev1) hipEventRecord(ev1, s);
     k_pcg_update<float><<<B.n_vt, TB, 0, s>>>(W, E, S, B.vtiles, L.part_a, rz_old, rz_new, rr_new, W.p32, W.r32,
                                               W.z32, W.pp32, W.q32, W.Minv32);
     k_pcg_dir<float><<<B.n_vt, TB, 0, s>>>(W, E, S, B.vtiles, rz_old, rz_new, rr_new, W.pp32, W.z32, pending, cap);

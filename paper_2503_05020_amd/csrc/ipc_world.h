@@ -62,7 +62,7 @@ struct WorldDev {
   // per vertex
   double *X, *x, *v, *xn, *xh, *p, *g, *r, *z, *pp, *q, *mass, *Minv, *e_v;
   float *r32, *z32, *pp32, *q32, *p32, *Minv32;
-  int *kin, *venv, *vt_beg, *vt_end;
+  int *kin, *venv, *vt_beg, *vt_end, *row_nnz;
   // per slice (vertex / 64)
   int *slice_pos, *slice_w;
   // per sliced-ELL position

@@ -58,7 +58,7 @@ EXPORTS = [
     "ipc_last_error", "ipc_scene_sizes", "ipc_debug_candidates", "ipc_debug_active", "ipc_debug_begin_step",
     "ipc_debug_gradient", "ipc_debug_energy", "ipc_debug_hessian_apply", "ipc_debug_newton_dir",
     "ipc_debug_ccd_bound", "ipc_debug_classify", "ipc_debug_pair_barrier", "ipc_debug_tet_elastic",
-    "ipc_debug_accd",
+    "ipc_debug_accd", "ipc_prof_enable", "ipc_prof_reset", "ipc_prof_read",
 ]
 
 _lib = None
@@ -100,6 +100,8 @@ def lib():
     L.ipc_debug_tet_elastic.argtypes = [_dp, _dp, C.c_double, C.c_double, C.c_int32, _dp, _dp, _dp]
     L.ipc_debug_accd.argtypes = [C.c_int32, C.c_int64, _dp, _dp, C.c_double, _dp]
     L.ipc_debug_accd.restype = C.c_int64
+    L.ipc_prof_enable.argtypes = [C.c_int32]
+    L.ipc_prof_read.argtypes = [_dp]
     _lib = L
     return L
 
@@ -147,6 +149,8 @@ def make_desc(sc: dict, precision: int = IPC_FP64, pcg_rel_tol: float = 1e-4, **
         motion=_f64(p["motion"]).reshape(-1), gravity=_f64(p["gravity"]).reshape(-1),
     )
     motion = np.asarray(p["motion"])
+    if motion.ndim != 3 or motion.shape[2] != 12 or np.asarray(p["gravity"]).reshape(-1, 3).shape[0] != motion.shape[0]:
+        raise ValueError("motion must be [steps][groups][12] with one gravity row per step")
     d = ipc_scene_desc(
         len(keep["kin"]), _d(keep["rest"]), _d(keep["init"]), _d(keep["vel"]),
         len(keep["E"]), _i(keep["tets"]), _d(keep["E"]), _d(keep["nu"]), _d(keep["rho"]),
@@ -225,6 +229,21 @@ class Scene:
 
     def state(self, stress=False):
         return ipc_get_state(self, stress)
+
+
+# --- measurement ----------------------------------------------------------------
+def ipc_prof_enable(on=1):
+    _check(lib().ipc_prof_enable(int(on)))
+
+
+def ipc_prof_reset():
+    _check(lib().ipc_prof_reset())
+
+
+def ipc_prof_read():
+    out = np.zeros(4)
+    _check(lib().ipc_prof_read(_d(out)))
+    return {"spmv_ms": float(out[0]), "spmv_launches": int(out[1]), "spmv_bytes": float(out[2])}
 
 
 # --- inspection entry points -------------------------------------------------

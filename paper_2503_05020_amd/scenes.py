@@ -195,6 +195,11 @@ class _Builder:
         kin = np.concatenate(self.kin, 0)
         free = kin < 0
         lo, hi = verts[free].min(0), verts[free].max(0)
+        motion = np.asarray(motion, np.float64)
+        gravity = np.asarray(gravity, np.float64).reshape(-1, 3)
+        if len(gravity) == 1 and len(motion) > 1:
+            gravity = np.repeat(gravity, len(motion), 0)
+        assert len(gravity) == len(motion), "one gravity row per motion row"
         sc = dict(
             rest_pos=np.ascontiguousarray(verts),
             init_vel=np.zeros_like(verts),
@@ -290,7 +295,9 @@ def _add_gripper(b: _Builder, obj_verts, centre, u, w, a, gap=0.002, close_speed
         off = sup + sign * gap
         world = (centre + np.outer(off + sign * x_local, u) + np.outer(sv[:, 1], w) + np.outer(sv[:, 2], a))
         kin = np.where(np.isclose(x_local, x_local.max()), first_group + side, -1).astype(np.int32)
-        b.add_body(world, st, E, nu, rho, kin)
+        tets = st.copy()
+        _orient(world, tets)  # the mirrored slab flips orientation
+        b.add_body(world, tets, E, nu, rho, kin)
         for n in range(n_steps):
             nc = min(n, close_steps)
             nl = max(0, n - close_steps)
