@@ -8,7 +8,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#define DEV __device__ __forceinline__
+#define DEV __host__ __device__ inline
 #define HD __host__ __device__ inline
 
 namespace ipcdev {

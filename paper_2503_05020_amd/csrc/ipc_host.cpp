@@ -10,6 +10,8 @@
 
 #include <algorithm>
 #include <array>
+#include <chrono>
+#include <cstdlib>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -1083,7 +1085,21 @@ struct World {
   }
 
   // ---- one time step of every environment in the current batch -------------
+  // IPC_TRACE=1 prints one line per Newton iteration to stderr.
+  static bool tracing() {
+    static int t = -1;
+    if (t < 0) {
+      const char *e = std::getenv("IPC_TRACE");
+      t = (e && e[0] && e[0] != '0') ? 1 : 0;
+    }
+    return t == 1;
+  }
+
   void step_batch() {
+    auto t0 = std::chrono::steady_clock::now();
+    auto ms = [&]() {
+      return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    };
     ipck::env_begin(stream, S, B);
     ipck::begin_step(stream, W, envs_d, S, B);
     friction_setup();
@@ -1099,20 +1115,27 @@ struct World {
     int mixed = 0;
     for (int e : batch_envs) mixed |= envs_h[e].precision == IPC_MIXED;
     for (int it = 0; it < maxit; ++it) {
-      assemble_system(mixed);
-      solve(mixed);
+      int na = assemble_system(mixed);
+      long long pit = solve(mixed);
       ipck::conv_check(stream, W, envs_d, S, B, L, L.counter + 1);
-      if (read_int(L.counter + 1) == 0) break;
+      int still = read_int(L.counter + 1);
+      if (tracing())
+        std::fprintf(stderr, "[ipc] newton %d: active pairs %d friction %d pcg %lld envs-left %d  %.1f ms\n", it, na,
+                     n_fric, pit, still, ms());
+      if (still == 0) break;
       int ns = broad_phase(W.x, W.p);
       ipck::ccd_init(stream, S, B);
       ipck::accd(stream, W, envs_d, S, L, ns, W.x, W.p);
       ipck::ls_init(stream, S, B);
       ipck::energy(stream, W, envs_d, S, B, L, ns, n_fric, 1, S.E0);
+      int trials = 0;
       for (int trial = 0; trial < 64; ++trial) {
         ipck::energy(stream, W, envs_d, S, B, L, ns, n_fric, 0, S.E1);
         ipck::ls_decide(stream, S, B, L.counter + 2);
+        ++trials;
         if (read_int(L.counter + 2) == 0) break;
       }
+      if (tracing()) std::fprintf(stderr, "[ipc]   swept %d line-search trials %d  %.1f ms\n", ns, trials, ms());
       ipck::update_x(stream, W, S, B);
       ipck::iter_end(stream, envs_d, S, B, L.counter + 3);
       if (read_int(L.counter + 3) == 0) break;
