@@ -118,14 +118,17 @@ template <class T>
 struct DBuf {
   T *p = nullptr;
   size_t cap = 0;
-  void ensure(size_t n) {
-    if (n <= cap) return;
+  // grows to hold at least n elements (contents are not kept); returns true
+  // if the buffer moved
+  bool ensure(size_t n) {
+    if (n <= cap) return false;
     size_t nc = std::max(n, cap + cap / 2);
     nc = std::max<size_t>(nc, 64);
     if (p) HC(hipFree(p));
     p = nullptr;
     HC(hipMalloc(&p, nc * sizeof(T)));
     cap = nc;
+    return true;
   }
   ~DBuf() {
     if (p) (void)hipFree(p);
@@ -968,15 +971,14 @@ struct World {
     ipck::bp_count(stream, W, envs_d, S, B, L);
     ipck::scan_int(stream, L.counts, L.offs, B.n_items, L.scan_tmp);
     int n = read_int(L.offs + B.n_items);
-    if ((size_t)n + 1 > cand.cap) {
-      cand.ensure(n + 1);
-      cand_type.ensure(n + 1);
-      cand_flag.ensure(n + 1);
-      cand_offs.ensure(n + 2);
-      cand_d2.ensure(n + 1);
-      e_c.ensure(n + 1);
-      refresh_lists();
-    }
+    // each list is sized on its own: capacities are rounded independently
+    bool moved = cand.ensure(n + 1);
+    moved |= cand_type.ensure(n + 1);
+    moved |= cand_flag.ensure(n + 1);
+    moved |= cand_offs.ensure(n + 2);
+    moved |= cand_d2.ensure(n + 1);
+    moved |= e_c.ensure(n + 1);
+    if (moved) refresh_lists();
     ipck::bp_write(stream, W, envs_d, S, B, L);
     ipck::cand_segments(stream, envs_d, S, B, L);
     return n;
@@ -984,45 +986,36 @@ struct World {
 
   // classify + compact the active pairs of the current candidate list
   int active_pairs(int n_cand, const double *x) {
-    if ((size_t)n_cand / 1024 + 64 > scan_tmp.cap) {
-      scan_tmp.ensure(n_cand / 1024 + 64);
-      refresh_lists();
-    }
+    if (scan_tmp.ensure(n_cand / 1024 + 64)) refresh_lists();
     ipck::classify_cands(stream, W, envs_d, L, n_cand, x);
     ipck::scan_int(stream, L.cand_flag, L.cand_offs, n_cand, L.scan_tmp);
     int n = read_int(L.cand_offs + n_cand);
-    if ((size_t)n + 1 > act.cap) {
-      act.ensure(n + 1);
-      act_type.ensure(n + 1);
-      refresh_lists();
-    }
+    bool moved = act.ensure(n + 1);
+    moved |= act_type.ensure(n + 1);
+    if (moved) refresh_lists();
     ipck::compact_active(stream, L, n_cand);
     ipck::act_segments(stream, S, B, L);
     return n;
   }
 
   void ensure_ce(int n) {
-    if ((size_t)n + 1 > ce_v.cap) {
-      ce_v.ensure(n + 1);
-      ce_g.ensure(12L * (n + 1));
-      ce_H.ensure(90L * (n + 1));
-      refresh_lists();
-    }
+    bool moved = ce_v.ensure(n + 1);
+    moved |= ce_g.ensure(12L * (n + 1));
+    moved |= ce_H.ensure(90L * (n + 1));
+    if (moved) refresh_lists();
   }
 
   // friction pairs = active pairs at x^n (positions in W.x)
   void friction_setup() {
     int nc = broad_phase(W.x, nullptr);
     int na = active_pairs(nc, W.x);
-    if ((size_t)na + 1 > fv.cap) {
-      fv.ensure(na + 1);
-      fw.ensure(4L * (na + 1));
-      fn.ensure(3L * (na + 1));
-      flam.ensure(na + 1);
-      e_f.ensure(na + 1);
-      fenv.ensure(na + 1);
-      refresh_lists();
-    }
+    bool moved = fv.ensure(na + 1);
+    moved |= fw.ensure(4L * (na + 1));
+    moved |= fn.ensure(3L * (na + 1));
+    moved |= flam.ensure(na + 1);
+    moved |= e_f.ensure(na + 1);
+    moved |= fenv.ensure(na + 1);
+    if (moved) refresh_lists();
     ipck::friction_setup(stream, W, envs_d, L, na);
     // the friction segments are the active segments of this list
     copy_state_int(S.fric_beg, S.act_beg);
@@ -1045,8 +1038,7 @@ struct World {
     int nvw = (int)aV.cap;
     ipck::incidence(stream, W, L, nce, nvw, nullptr);
     int ntot = read_int(L.inc_off + nvw);
-    inc_ent.ensure(ntot + 1);
-    refresh_lists();
+    if (inc_ent.ensure(ntot + 1)) refresh_lists();
     ipck::incidence_fill(stream, W, L, nce, nvw);
     ipck::elastic(stream, W, envs_d, S, B);
     ipck::assemble(stream, W, envs_d, S, B, L, mixed);

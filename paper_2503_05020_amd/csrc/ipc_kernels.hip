@@ -11,6 +11,10 @@
 #include "device_math.h"
 #include "ipc_kernels.h"
 
+#ifndef IPC_LAUNCH
+#define IPC_LAUNCH(kernel, grid, block, stream) kernel<<<(grid), (block), 0, (stream)>>>
+#endif
+
 using namespace ipcw;
 using namespace ipcdev;
 
@@ -1228,102 +1232,102 @@ inline int nblk(int n, int b) { return (n + b - 1) / b; }
 namespace ipck {
 
 void begin_step(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B) {
-  if (B.n_vt) k_begin_step<<<B.n_vt, TB, 0, s>>>(W, E, S, B.vtiles);
+  if (B.n_vt) IPC_LAUNCH(k_begin_step, B.n_vt, TB, s)(W, E, S, B.vtiles);
 }
 void dbc_check_J(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B) {
-  if (B.n_tt) k_dbc_J<<<B.n_tt, TB, 0, s>>>(W, E, S, B.ttiles);
+  if (B.n_tt) IPC_LAUNCH(k_dbc_J, B.n_tt, TB, s)(W, E, S, B.ttiles);
 }
 void apply_dbc(hipStream_t s, const WorldDev &W, const EnvDev *, const EnvState &S, const Batch &B) {
-  if (B.n_vt) k_apply_dbc<<<B.n_vt, TB, 0, s>>>(W, S, B.vtiles);
+  if (B.n_vt) IPC_LAUNCH(k_apply_dbc, B.n_vt, TB, s)(W, S, B.vtiles);
 }
 void env_begin(hipStream_t s, const EnvState &S, const Batch &B) {
-  k_env_begin<<<nblk(B.n_envs, 64), 64, 0, s>>>(S, B.envs, B.n_envs);
+  IPC_LAUNCH(k_env_begin, nblk(B.n_envs, 64), 64, s)(S, B.envs, B.n_envs);
 }
 void env_dbc(hipStream_t s, const EnvState &S, const Batch &B) {
-  k_env_dbc<<<nblk(B.n_envs, 64), 64, 0, s>>>(S, B.envs, B.n_envs);
+  IPC_LAUNCH(k_env_dbc, nblk(B.n_envs, 64), 64, s)(S, B.envs, B.n_envs);
 }
 
 void boxes(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, const double *x,
            const double *p) {
-  if (B.n_svt) k_boxes<<<B.n_svt, TB, 0, s>>>(W, E, S, B.svtiles, 0, x, p);
-  if (B.n_trit) k_boxes<<<B.n_trit, TB, 0, s>>>(W, E, S, B.tritiles, 1, x, p);
-  if (B.n_et) k_boxes<<<B.n_et, TB, 0, s>>>(W, E, S, B.etiles, 2, x, p);
+  if (B.n_svt) IPC_LAUNCH(k_boxes, B.n_svt, TB, s)(W, E, S, B.svtiles, 0, x, p);
+  if (B.n_trit) IPC_LAUNCH(k_boxes, B.n_trit, TB, s)(W, E, S, B.tritiles, 1, x, p);
+  if (B.n_et) IPC_LAUNCH(k_boxes, B.n_et, TB, s)(W, E, S, B.etiles, 2, x, p);
 }
 
 void bp_count(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L) {
-  if (B.n_it) k_bp<false><<<B.n_it, TB, 0, s>>>(W, E, S, B.itiles, L.counts, nullptr, nullptr);
+  if (B.n_it) IPC_LAUNCH(k_bp<false>, B.n_it, TB, s)(W, E, S, B.itiles, L.counts, nullptr, nullptr);
 }
 void bp_write(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L) {
-  if (B.n_it) k_bp<true><<<B.n_it, TB, 0, s>>>(W, E, S, B.itiles, nullptr, L.offs, L.cand);
+  if (B.n_it) IPC_LAUNCH(k_bp<true>, B.n_it, TB, s)(W, E, S, B.itiles, nullptr, L.offs, L.cand);
 }
 
 void scan_int(hipStream_t s, const int *in, int *out, int n, int *tmp) {
   int nb = nblk(n, SCAN_PER_BLOCK);
-  if (nb > 0) k_scan1<<<nb, TB, 0, s>>>(in, out, n, tmp);
-  k_scan2<<<1, TB, 0, s>>>(tmp, nb, out + n);
-  if (n > 0) k_scan3<<<nblk(n, TB), TB, 0, s>>>(out, n, tmp);
+  if (nb > 0) IPC_LAUNCH(k_scan1, nb, TB, s)(in, out, n, tmp);
+  IPC_LAUNCH(k_scan2, 1, TB, s)(tmp, nb, out + n);
+  if (n > 0) IPC_LAUNCH(k_scan3, nblk(n, TB), TB, s)(out, n, tmp);
 }
 
 void cand_segments(hipStream_t s, const EnvDev *E, const EnvState &S, const Batch &B, const Lists &L) {
-  k_cand_seg<<<nblk(B.n_envs, 64), 64, 0, s>>>(E, S, B.envs, B.n_envs, L.offs);
+  IPC_LAUNCH(k_cand_seg, nblk(B.n_envs, 64), 64, s)(E, S, B.envs, B.n_envs, L.offs);
 }
 
 void classify_cands(hipStream_t s, const WorldDev &W, const EnvDev *E, const Lists &L, int n, const double *x) {
-  if (n) k_classify<<<nblk(n, TB), TB, 0, s>>>(W, E, L.cand, n, x, L.cand_type, L.cand_d2, L.cand_flag);
+  if (n) IPC_LAUNCH(k_classify, nblk(n, TB), TB, s)(W, E, L.cand, n, x, L.cand_type, L.cand_d2, L.cand_flag);
 }
 void compact_active(hipStream_t s, const Lists &L, int n) {
-  if (n) k_compact<<<nblk(n, TB), TB, 0, s>>>(L.cand, L.cand_type, L.cand_flag, L.cand_offs, n, L.act, L.act_type);
+  if (n) IPC_LAUNCH(k_compact, nblk(n, TB), TB, s)(L.cand, L.cand_type, L.cand_flag, L.cand_offs, n, L.act, L.act_type);
 }
 void act_segments(hipStream_t s, const EnvState &S, const Batch &B, const Lists &L) {
-  k_act_seg<<<nblk(B.n_envs, 64), 64, 0, s>>>(S, B.envs, B.n_envs, L.cand_offs);
+  IPC_LAUNCH(k_act_seg, nblk(B.n_envs, 64), 64, s)(S, B.envs, B.n_envs, L.cand_offs);
 }
 void barrier_elems(hipStream_t s, const WorldDev &W, const EnvDev *E, const Lists &L, int n_act, const double *x) {
   if (n_act)
-    k_barrier_elems<<<nblk(n_act, 128), 128, 0, s>>>(W, E, L.act, L.act_type, n_act, x, L.ce_v, L.ce_g, L.ce_H);
+    IPC_LAUNCH(k_barrier_elems, nblk(n_act, 128), 128, s)(W, E, L.act, L.act_type, n_act, x, L.ce_v, L.ce_g, L.ce_H);
 }
 void friction_setup(hipStream_t s, const WorldDev &W, const EnvDev *E, const Lists &L, int n_act) {
   if (n_act)
-    k_friction_setup<<<nblk(n_act, TB), TB, 0, s>>>(W, E, L.act, L.act_type, n_act, L.fv, L.fw, L.fn, L.flam, L.fenv);
+    IPC_LAUNCH(k_friction_setup, nblk(n_act, TB), TB, s)(W, E, L.act, L.act_type, n_act, L.fv, L.fw, L.fn, L.flam, L.fenv);
 }
 void friction_elems(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Lists &L, int n_fric,
                     int ce_off, const double *x) {
   if (n_fric)
-    k_friction_elems<<<nblk(n_fric, TB), TB, 0, s>>>(W, E, S, L.fv, L.fw, L.fn, L.flam, L.fenv, n_fric, x,
+    IPC_LAUNCH(k_friction_elems, nblk(n_fric, TB), TB, s)(W, E, S, L.fv, L.fw, L.fn, L.flam, L.fenv, n_fric, x,
                                                       L.ce_v + ce_off, L.ce_g + 12 * (size_t)ce_off,
                                                       L.ce_H + 90 * (size_t)ce_off);
 }
 
 void incidence(hipStream_t s, const WorldDev &W, Lists &L, int n_ce, int nv_world, int *total_out_dev) {
-  k_fill_int<<<nblk(nv_world + 1, TB), TB, 0, s>>>(L.inc_cnt, nv_world + 1, 0);
-  k_fill_int<<<nblk(nv_world + 1, TB), TB, 0, s>>>(L.inc_cur, nv_world + 1, 0);
-  if (n_ce) k_inc_count<<<nblk(n_ce, TB), TB, 0, s>>>(W, L.ce_v, n_ce, L.inc_cnt);
+  IPC_LAUNCH(k_fill_int, nblk(nv_world + 1, TB), TB, s)(L.inc_cnt, nv_world + 1, 0);
+  IPC_LAUNCH(k_fill_int, nblk(nv_world + 1, TB), TB, s)(L.inc_cur, nv_world + 1, 0);
+  if (n_ce) IPC_LAUNCH(k_inc_count, nblk(n_ce, TB), TB, s)(W, L.ce_v, n_ce, L.inc_cnt);
   scan_int(s, L.inc_cnt, L.inc_off, nv_world, L.scan_tmp);
   (void)total_out_dev;
 }
 void incidence_fill(hipStream_t s, const WorldDev &W, Lists &L, int n_ce, int nv_world) {
   if (n_ce) {
-    k_inc_fill<<<nblk(n_ce, TB), TB, 0, s>>>(W, L.ce_v, n_ce, L.inc_off, L.inc_cur, L.inc_ent);
-    k_inc_sort<<<nblk(nv_world, TB), TB, 0, s>>>(L.inc_off, L.inc_ent, nv_world);
+    IPC_LAUNCH(k_inc_fill, nblk(n_ce, TB), TB, s)(W, L.ce_v, n_ce, L.inc_off, L.inc_cur, L.inc_ent);
+    IPC_LAUNCH(k_inc_sort, nblk(nv_world, TB), TB, s)(L.inc_off, L.inc_ent, nv_world);
   }
 }
 
 void elastic(hipStream_t s, const WorldDev &W, const EnvDev *, const EnvState &S, const Batch &B) {
-  if (B.n_tt) k_elastic<<<B.n_tt, TB, 0, s>>>(W, S, B.ttiles);
+  if (B.n_tt) IPC_LAUNCH(k_elastic, B.n_tt, TB, s)(W, S, B.ttiles);
 }
 
 void assemble(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, const Lists &L,
               int mixed) {
   if (!B.n_vt) return;
-  k_assemble_rows<<<B.n_vt, TB, 0, s>>>(W, E, S, B.vtiles, L.inc_off, L.inc_ent, L.ce_g, L.ce_H, mixed);
-  k_assemble_sell<<<B.n_vt, TB, 0, s>>>(W, E, S, B.vtiles, mixed);
+  IPC_LAUNCH(k_assemble_rows, B.n_vt, TB, s)(W, E, S, B.vtiles, L.inc_off, L.inc_ent, L.ce_g, L.ce_H, mixed);
+  IPC_LAUNCH(k_assemble_sell, B.n_vt, TB, s)(W, E, S, B.vtiles, mixed);
 }
 
 void pcg_init(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L,
               int *pending, int mixed) {
-  k_fill_int<<<1, 64, 0, s>>>(pending, 1, 0);
-  if (B.n_vt && !mixed) k_pcg_init<<<B.n_vt, TB, 0, s>>>(W, S, B.vtiles, L.part_b0, L.part_c0);
-  if (B.n_vt && mixed) k_pcg_init32<<<B.n_vt, TB, 0, s>>>(W, S, B.vtiles, L.part_b0, L.part_c0);
-  k_pcg_env_init<<<nblk(B.n_envs, 64), 64, 0, s>>>(E, S, B.envs, B.n_envs, L.part_c0, pending);
+  IPC_LAUNCH(k_fill_int, 1, 64, s)(pending, 1, 0);
+  if (B.n_vt && !mixed) IPC_LAUNCH(k_pcg_init, B.n_vt, TB, s)(W, S, B.vtiles, L.part_b0, L.part_c0);
+  if (B.n_vt && mixed) IPC_LAUNCH(k_pcg_init32, B.n_vt, TB, s)(W, S, B.vtiles, L.part_b0, L.part_c0);
+  IPC_LAUNCH(k_pcg_env_init, nblk(B.n_envs, 64), 64, s)(E, S, B.envs, B.n_envs, L.part_c0, pending);
 }
 
 void pcg_iter(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L, int it,
@@ -1334,91 +1338,91 @@ void pcg_iter(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState 
   double *rr_new = (it & 1) ? L.part_c0 : L.part_c1;
   if (!mixed) {
     if (ev0) hipEventRecord(ev0, s);
-    k_spmv<double><<<B.n_vt, TB, 0, s>>>(W, E, S, B.vtiles, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, W.pp, W.q, W.val,
+    IPC_LAUNCH(k_spmv<double>, B.n_vt, TB, s)(W, E, S, B.vtiles, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, W.pp, W.q, W.val,
                                          L.part_a, L.prof);
     if (ev1) hipEventRecord(ev1, s);
-    k_pcg_update<double><<<B.n_vt, TB, 0, s>>>(W, E, S, B.vtiles, L.part_a, rz_old, rz_new, rr_new, W.p, W.r, W.z,
+    IPC_LAUNCH(k_pcg_update<double>, B.n_vt, TB, s)(W, E, S, B.vtiles, L.part_a, rz_old, rz_new, rr_new, W.p, W.r, W.z,
                                                W.pp, W.q, W.Minv);
-    k_pcg_dir<double><<<B.n_vt, TB, 0, s>>>(W, E, S, B.vtiles, rz_old, rz_new, rr_new, W.pp, W.z, pending, cap);
+    IPC_LAUNCH(k_pcg_dir<double>, B.n_vt, TB, s)(W, E, S, B.vtiles, rz_old, rz_new, rr_new, W.pp, W.z, pending, cap);
   } else {
     if (ev0) hipEventRecord(ev0, s);
-    k_spmv<float><<<B.n_vt, TB, 0, s>>>(W, E, S, B.vtiles, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, W.pp32, W.q32,
+    IPC_LAUNCH(k_spmv<float>, B.n_vt, TB, s)(W, E, S, B.vtiles, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, W.pp32, W.q32,
                                         W.val32, L.part_a, L.prof);
     if (ev1) hipEventRecord(ev1, s);
-    k_pcg_update<float><<<B.n_vt, TB, 0, s>>>(W, E, S, B.vtiles, L.part_a, rz_old, rz_new, rr_new, W.p32, W.r32,
+    IPC_LAUNCH(k_pcg_update<float>, B.n_vt, TB, s)(W, E, S, B.vtiles, L.part_a, rz_old, rz_new, rr_new, W.p32, W.r32,
                                               W.z32, W.pp32, W.q32, W.Minv32);
-    k_pcg_dir<float><<<B.n_vt, TB, 0, s>>>(W, E, S, B.vtiles, rz_old, rz_new, rr_new, W.pp32, W.z32, pending, cap);
+    IPC_LAUNCH(k_pcg_dir<float>, B.n_vt, TB, s)(W, E, S, B.vtiles, rz_old, rz_new, rr_new, W.pp32, W.z32, pending, cap);
   }
 }
 
 void pcg_finish(hipStream_t s, const WorldDev &W, const EnvState &S, const Batch &B, int mixed) {
-  if (mixed && B.n_vt) k_p32_to_p<<<B.n_vt, TB, 0, s>>>(W, S, B.vtiles);
+  if (mixed && B.n_vt) IPC_LAUNCH(k_p32_to_p, B.n_vt, TB, s)(W, S, B.vtiles);
 }
 
 void spmv_debug(hipStream_t s, const WorldDev &W, const EnvDev *, const EnvState &S, const Batch &B, Lists &L,
                 const double *in, double *out) {
-  if (B.n_vt) k_spmv_dbg<<<B.n_vt, TB, 0, s>>>(W, S, B.vtiles, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, in, out);
+  if (B.n_vt) IPC_LAUNCH(k_spmv_dbg, B.n_vt, TB, s)(W, S, B.vtiles, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, in, out);
 }
 
 void conv_check(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L,
                 int *n_active) {
-  k_fill_int<<<1, 64, 0, s>>>(n_active, 1, 0);
-  if (B.n_vt) k_pinf<<<B.n_vt, TB, 0, s>>>(W, S, B.vtiles, L.part_a);
-  k_env_conv<<<nblk(B.n_envs, 64), 64, 0, s>>>(E, S, B.envs, B.n_envs, L.part_a, n_active);
+  IPC_LAUNCH(k_fill_int, 1, 64, s)(n_active, 1, 0);
+  if (B.n_vt) IPC_LAUNCH(k_pinf, B.n_vt, TB, s)(W, S, B.vtiles, L.part_a);
+  IPC_LAUNCH(k_env_conv, nblk(B.n_envs, 64), 64, s)(E, S, B.envs, B.n_envs, L.part_a, n_active);
 }
 
 void ccd_init(hipStream_t s, const EnvState &S, const Batch &B) {
-  k_ccd_init<<<nblk(B.n_envs, 64), 64, 0, s>>>(S, B.envs, B.n_envs);
+  IPC_LAUNCH(k_ccd_init, nblk(B.n_envs, 64), 64, s)(S, B.envs, B.n_envs);
 }
 void accd(hipStream_t s, const WorldDev &W, const EnvDev *, const EnvState &S, const Lists &L, int n, const double *x,
           const double *p) {
-  if (n) k_accd<<<nblk(n, 128), 128, 0, s>>>(W, S, L.cand, n, x, p);
+  if (n) IPC_LAUNCH(k_accd, nblk(n, 128), 128, s)(W, S, L.cand, n, x, p);
 }
 void ls_init(hipStream_t s, const EnvState &S, const Batch &B) {
-  k_ls_init<<<nblk(B.n_envs, 64), 64, 0, s>>>(S, B.envs, B.n_envs);
+  IPC_LAUNCH(k_ls_init, nblk(B.n_envs, 64), 64, s)(S, B.envs, B.n_envs);
 }
 
 void energy(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L, int n_cand,
             int n_fric, int zero_alpha, double *E_out) {
-  if (B.n_vt) k_energy_v<<<B.n_vt, TB, 0, s>>>(W, E, S, B.vtiles, zero_alpha);
-  if (B.n_tt) k_energy_t<<<B.n_tt, TB, 0, s>>>(W, S, B.ttiles, zero_alpha);
-  if (n_cand) k_energy_c<<<nblk(n_cand, TB), TB, 0, s>>>(W, E, S, L.cand, n_cand, zero_alpha, L.e_c);
+  if (B.n_vt) IPC_LAUNCH(k_energy_v, B.n_vt, TB, s)(W, E, S, B.vtiles, zero_alpha);
+  if (B.n_tt) IPC_LAUNCH(k_energy_t, B.n_tt, TB, s)(W, S, B.ttiles, zero_alpha);
+  if (n_cand) IPC_LAUNCH(k_energy_c, nblk(n_cand, TB), TB, s)(W, E, S, L.cand, n_cand, zero_alpha, L.e_c);
   if (n_fric)
-    k_energy_f<<<nblk(n_fric, TB), TB, 0, s>>>(W, E, S, L.fv, L.fw, L.fn, L.flam, L.fenv, n_fric, zero_alpha, L.e_f);
-  k_env_energy<<<B.n_envs, TB, 0, s>>>(W, E, S, B.envs, L.e_c, L.e_f, E_out);
+    IPC_LAUNCH(k_energy_f, nblk(n_fric, TB), TB, s)(W, E, S, L.fv, L.fw, L.fn, L.flam, L.fenv, n_fric, zero_alpha, L.e_f);
+  IPC_LAUNCH(k_env_energy, B.n_envs, TB, s)(W, E, S, B.envs, L.e_c, L.e_f, E_out);
 }
 
 void ls_decide(hipStream_t s, const EnvState &S, const Batch &B, int *pending) {
-  k_fill_int<<<1, 64, 0, s>>>(pending, 1, 0);
-  k_ls_decide<<<nblk(B.n_envs, 64), 64, 0, s>>>(S, B.envs, B.n_envs, pending);
+  IPC_LAUNCH(k_fill_int, 1, 64, s)(pending, 1, 0);
+  IPC_LAUNCH(k_ls_decide, nblk(B.n_envs, 64), 64, s)(S, B.envs, B.n_envs, pending);
 }
 void update_x(hipStream_t s, const WorldDev &W, const EnvState &S, const Batch &B) {
-  if (B.n_vt) k_update_x<<<B.n_vt, TB, 0, s>>>(W, S, B.vtiles);
+  if (B.n_vt) IPC_LAUNCH(k_update_x, B.n_vt, TB, s)(W, S, B.vtiles);
 }
 void iter_end(hipStream_t s, const EnvDev *E, const EnvState &S, const Batch &B, int *n_active) {
-  k_fill_int<<<1, 64, 0, s>>>(n_active, 1, 0);
-  k_iter_end<<<nblk(B.n_envs, 64), 64, 0, s>>>(E, S, B.envs, B.n_envs, n_active);
+  IPC_LAUNCH(k_fill_int, 1, 64, s)(n_active, 1, 0);
+  IPC_LAUNCH(k_iter_end, nblk(B.n_envs, 64), 64, s)(E, S, B.envs, B.n_envs, n_active);
 }
 void step_end(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B) {
-  if (B.n_vt) k_step_end<<<B.n_vt, TB, 0, s>>>(W, E, S, B.vtiles);
+  if (B.n_vt) IPC_LAUNCH(k_step_end, B.n_vt, TB, s)(W, E, S, B.vtiles);
 }
 
 void stress(hipStream_t s, const WorldDev &W, int t_off, int nt, double *cauchy, double *vm) {
-  if (nt) k_stress<<<nblk(nt, TB), TB, 0, s>>>(W, t_off, nt, cauchy, vm);
+  if (nt) IPC_LAUNCH(k_stress, nblk(nt, TB), TB, s)(W, t_off, nt, cauchy, vm);
 }
 
 void dbg_classify(hipStream_t s, int kind, int n, const double *x12, int *types, double *d2) {
-  if (n) k_dbg_classify<<<nblk(n, TB), TB, 0, s>>>(kind, n, x12, types, d2);
+  if (n) IPC_LAUNCH(k_dbg_classify, nblk(n, TB), TB, s)(kind, n, x12, types, d2);
 }
 void dbg_pair(hipStream_t s, int kind, int type, const double *x12, double dhat, double kappa, double eps_x,
               int project, double *out) {
-  k_dbg_pair<<<1, 64, 0, s>>>(kind, type, x12, dhat, kappa, eps_x, project, out);
+  IPC_LAUNCH(k_dbg_pair, 1, 64, s)(kind, type, x12, dhat, kappa, eps_x, project, out);
 }
 void dbg_tet(hipStream_t s, const double *X12, const double *x12, double mu, double la, double *out) {
-  k_dbg_tet<<<1, 64, 0, s>>>(X12, x12, mu, la, out);
+  IPC_LAUNCH(k_dbg_tet, 1, 64, s)(X12, x12, mu, la, out);
 }
 void dbg_accd(hipStream_t s, int kind, int n, const double *x12, const double *p12, double sfac, double *t) {
-  if (n) k_dbg_accd<<<nblk(n, 128), 128, 0, s>>>(kind, n, x12, p12, sfac, t);
+  if (n) IPC_LAUNCH(k_dbg_accd, nblk(n, 128), 128, s)(kind, n, x12, p12, sfac, t);
 }
 
 }  // namespace ipck
