@@ -152,6 +152,7 @@ struct HostScene {
   std::vector<int> col, cb_beg, cb_end, contrib;
   std::vector<double> motion;  // motion rows then gravity rows
   int n_groups = 0, n_motion = 0;
+  double cell = 0.0;  // hash-grid cell size
   double dt, dhat, kappa, mu_f, eps_v, tol, pcg_tol;
   int maxit, precision;
 };
@@ -402,6 +403,15 @@ std::unique_ptr<HostScene> preprocess(const ipc_scene_desc *d) {
       }
       H.elen2[i] = s;
     }
+    // grid cell: median surface edge length plus the two dhat margins, so a
+    // typical widened edge box spans at most two cells per axis
+    if (H.ne > 0) {
+      std::vector<double> len(H.elen2);
+      std::nth_element(len.begin(), len.begin() + len.size() / 2, len.end());
+      H.cell = std::sqrt(len[len.size() / 2]) + 2.0 * H.dhat;
+    } else {
+      H.cell = 1.0;
+    }
   }
   // the initial configuration must be free of intersections: no candidate
   // pair at zero distance and no surface edge crossing a surface triangle
@@ -552,13 +562,15 @@ struct World {
   std::vector<void **> state_int, state_ll, state_dbl;
   // batch
   std::vector<int> batch_envs;
-  DBuf<Tile> vt_d, tt_d, svt_d, trit_d, et_d, it_d;
+  DBuf<Tile> vt_d, tt_d, svt_d, trit_d, et_d, it_d, bt_d;
   DBuf<int> benv_d;
   ipck::Batch B{};
   ipck::Lists L{};
   DBuf<int> counts, offs, scan_tmp, cand_type, cand_flag, cand_offs, act_type, fenv, inc_cnt, inc_off, inc_cur,
       inc_ent, counter;
   DBuf<int2> cand, act;
+  DBuf<int> g_ncell, g_big, g_eoff, g_bigoff, g_ebucket, g_bcnt, g_boff, g_bcur, g_bigl;
+  DBuf<int4> g_ent, g_sorted;
   DBuf<double> cand_d2, e_c, fw, fn, flam, e_f, ce_g, ce_H, part_a, part_b0, part_b1, part_c0, part_c1;
   DBuf<int4> fv, ce_v;
   int *pinned = nullptr;  // host mirror of counters
@@ -633,7 +645,8 @@ struct World {
     state_int = {(void **)&S.status,   (void **)&S.reason,   (void **)&S.iters,   (void **)&S.halvings,
                  (void **)&S.ls_done,  (void **)&S.ls_cnt,   (void **)&S.pcg_done, (void **)&S.pcg_it,
                  (void **)&S.dbc_bad,  (void **)&S.cand_beg, (void **)&S.cand_end, (void **)&S.act_beg,
-                 (void **)&S.act_end,  (void **)&S.fric_beg, (void **)&S.fric_end, (void **)&S.in_step};
+                 (void **)&S.act_end,  (void **)&S.fric_beg, (void **)&S.fric_end, (void **)&S.in_step,
+                 (void **)&S.big_beg,  (void **)&S.big_end};
     state_ll = {(void **)&S.pcg_total, (void **)&S.amax_bits};
     state_dbl = {(void **)&S.alpha, (void **)&S.E0, (void **)&S.E1, (void **)&S.pinf, (void **)&S.pcg_bb};
   }
@@ -804,6 +817,7 @@ struct World {
     E.eps_v = H.eps_v;
     E.tol = H.tol;
     E.pcg_tol = H.pcg_tol;
+    E.cell = H.cell;
     upload_env(slot);
     int zero = 0;
     HC(hipMemcpyAsync(S.status + slot, &zero, 4, hipMemcpyHostToDevice, stream));
@@ -831,8 +845,8 @@ struct World {
   // ---- batch set-up -------------------------------------------------------
   void set_batch(const std::vector<int> &envs) {
     if (envs == batch_envs) return;
-    std::vector<Tile> vt, tt, svt, trit, et, it;
-    int item_off = 0;
+    std::vector<Tile> vt, tt, svt, trit, et, it, bt;
+    int item_off = 0, bitem_off = 0;
     for (int e : envs) {
       EnvDev &E = envs_h[e];
       E.vtile_first = (int)vt.size();
@@ -847,8 +861,12 @@ struct World {
       for (int s = 0; s < E.ne; s += ipcw::kTile) et.push_back({e, E.e_off + s, std::min(ipcw::kTile, E.ne - s), 0});
       for (int s = 0; s < E.nsv; s += ipcw::kTile) it.push_back({e, E.sv_off + s, std::min(ipcw::kTile, E.nsv - s), 0});
       for (int s = 0; s < E.ne; s += ipcw::kTile) it.push_back({e, E.e_off + s, std::min(ipcw::kTile, E.ne - s), 1});
+      for (int s = 0; s < E.ntri; s += ipcw::kTile) bt.push_back({e, E.tri_off + s, std::min(ipcw::kTile, E.ntri - s), 0});
+      for (int s = 0; s < E.ne; s += ipcw::kTile) bt.push_back({e, E.e_off + s, std::min(ipcw::kTile, E.ne - s), 1});
       E.item_off = item_off;
       item_off += E.nsv + E.ne;
+      E.bitem_off = bitem_off;
+      bitem_off += E.ntri + E.ne;
       upload_env(e);
     }
     auto put = [&](DBuf<Tile> &d, const std::vector<Tile> &h) {
@@ -861,6 +879,7 @@ struct World {
     put(trit_d, trit);
     put(et_d, et);
     put(it_d, it);
+    put(bt_d, bt);
     benv_d.ensure(envs.size() + 1);
     up(benv_d.p, envs.data(), envs.size());
     B.vtiles = vt_d.p;
@@ -869,6 +888,9 @@ struct World {
     B.tritiles = trit_d.p;
     B.etiles = et_d.p;
     B.itiles = it_d.p;
+    B.btiles = bt_d.p;
+    B.n_bt = (int)bt.size();
+    B.n_bitems = bitem_off;
     B.n_vt = (int)vt.size();
     B.n_tt = (int)tt.size();
     B.n_svt = (int)svt.size();
@@ -880,6 +902,11 @@ struct World {
     B.n_items = item_off;
     counts.ensure(item_off + 1);
     offs.ensure(item_off + 2);
+    g_ncell.ensure(bitem_off + 1);
+    g_big.ensure(bitem_off + 1);
+    g_eoff.ensure(bitem_off + 2);
+    g_bigoff.ensure(bitem_off + 2);
+    g_bigl.ensure(bitem_off + 1);
     size_t nvw = aV.cap + 2;
     inc_cnt.ensure(nvw);
     inc_off.ensure(nvw);
@@ -891,7 +918,7 @@ struct World {
     part_c0.ensure(nvt);
     part_c1.ensure(nvt);
     counter.ensure(16);
-    scan_tmp.ensure(std::max<size_t>(item_off, nvw) / 1024 + 64);
+    scan_tmp.ensure(std::max<size_t>(std::max<size_t>(item_off, bitem_off), nvw) / 1024 + 64);
     HC(hipStreamSynchronize(stream));
     batch_envs = envs;
     refresh_lists();
@@ -929,6 +956,17 @@ struct World {
     L.part_c1 = part_c1.p;
     L.counter = counter.p;
     L.prof = prof_on ? prof_bytes.p : nullptr;
+    L.g_ncell = g_ncell.p;
+    L.g_big = g_big.p;
+    L.g_eoff = g_eoff.p;
+    L.g_bigoff = g_bigoff.p;
+    L.g_ebucket = g_ebucket.p;
+    L.g_bcnt = g_bcnt.p;
+    L.g_boff = g_boff.p;
+    L.g_bcur = g_bcur.p;
+    L.g_bigl = g_bigl.p;
+    L.g_ent = g_ent.p;
+    L.g_sorted = g_sorted.p;
   }
 
   void set_prof(bool on) {
@@ -968,18 +1006,35 @@ struct World {
   // ---- broad phase: candidate list at x (p == nullptr) or over x -> x+p ----
   int broad_phase(const double *x, const double *p) {
     ipck::boxes(stream, W, envs_d, S, B, x, p);
-    ipck::bp_count(stream, W, envs_d, S, B, L);
+    // bin triangles and edges into the per-environment hash grids
+    ipck::grid_count(stream, W, envs_d, S, B, L);
+    ipck::scan_int(stream, L.g_ncell, L.g_eoff, B.n_bitems, L.scan_tmp);
+    ipck::scan_int(stream, L.g_big, L.g_bigoff, B.n_bitems, L.scan_tmp);
+    int n_ent = read_int(L.g_eoff + B.n_bitems);
+    unsigned nb = 1024;
+    while (nb < 2u * (unsigned)n_ent) nb <<= 1;
+    bool moved = g_ent.ensure(n_ent + 1);
+    moved |= g_sorted.ensure(n_ent + 1);
+    moved |= g_ebucket.ensure(n_ent + 1);
+    moved |= g_bcnt.ensure(nb + 1);
+    moved |= g_boff.ensure(nb + 2);
+    moved |= g_bcur.ensure(nb + 1);
+    moved |= scan_tmp.ensure(nb / 1024 + 64);
+    if (moved) refresh_lists();
+    ipck::grid_fill(stream, W, envs_d, S, B, L, n_ent, nb);
+    // query: count, scan, write
+    ipck::bp_grid_count(stream, W, envs_d, S, B, L, nb);
     ipck::scan_int(stream, L.counts, L.offs, B.n_items, L.scan_tmp);
     int n = read_int(L.offs + B.n_items);
     // each list is sized on its own: capacities are rounded independently
-    bool moved = cand.ensure(n + 1);
+    moved = cand.ensure(n + 1);
     moved |= cand_type.ensure(n + 1);
     moved |= cand_flag.ensure(n + 1);
     moved |= cand_offs.ensure(n + 2);
     moved |= cand_d2.ensure(n + 1);
     moved |= e_c.ensure(n + 1);
     if (moved) refresh_lists();
-    ipck::bp_write(stream, W, envs_d, S, B, L);
+    ipck::bp_grid_write(stream, W, envs_d, S, B, L, nb);
     ipck::cand_segments(stream, envs_d, S, B, L);
     return n;
   }

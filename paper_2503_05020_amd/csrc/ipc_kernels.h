@@ -12,8 +12,9 @@ using ipcw::WorldDev;
 
 // Work lists of one batch (device pointers) and their sizes.
 struct Batch {
-  const Tile *vtiles, *ttiles, *svtiles, *tritiles, *etiles, *itiles;
-  int n_vt, n_tt, n_svt, n_trit, n_et, n_it;
+  const Tile *vtiles, *ttiles, *svtiles, *tritiles, *etiles, *itiles, *btiles;
+  int n_vt, n_tt, n_svt, n_trit, n_et, n_it, n_bt;
+  int n_bitems;     // grid items (surface tris + edges of all envs)
   const int *envs;  // env slots in the batch
   int n_envs;
   int n_items;      // broad-phase work items (surface verts + edges of all envs)
@@ -39,6 +40,9 @@ struct Lists {
   // reduction partials per vertex tile
   double *part_a, *part_b0, *part_b1, *part_c0, *part_c1;
   int *counter;  // device scratch counters [4]
+  // hash grid
+  int *g_ncell, *g_big, *g_eoff, *g_bigoff, *g_ebucket, *g_bcnt, *g_boff, *g_bcur, *g_bigl;
+  int4 *g_ent, *g_sorted;
   unsigned long long *prof;  // algorithmic bytes moved by profiled kernels (nullptr = off)
 };
 
@@ -54,6 +58,13 @@ void boxes(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S,
 void bp_count(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L);
 void bp_write(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L);
 void scan_int(hipStream_t s, const int *in, int *out, int n, int *tmp);  // out[n+1] exclusive
+void grid_count(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L);
+void grid_fill(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L,
+               int n_ent, unsigned nbuckets);
+void bp_grid_count(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L,
+                   unsigned nbuckets);
+void bp_grid_write(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L,
+                   unsigned nbuckets);
 void cand_segments(hipStream_t s, const EnvDev *E, const EnvState &S, const Batch &B, const Lists &L);
 
 void classify_cands(hipStream_t s, const WorldDev &W, const EnvDev *E, const Lists &L, int n, const double *x);

@@ -316,6 +316,236 @@ __global__ void __launch_bounds__(256) k_bp(WorldDev W, const EnvDev *envs, EnvS
 }
 
 // ---------------------------------------------------------------------------
+// hash-grid broad phase.  Each environment's triangles and edges are binned
+// into cubic cells of size E.cell (their dhat-widened boxes cover at most 4
+// cells per axis; larger boxes go to a per-environment "big" list).  A query
+// primitive visits the cells its box covers and reports a pair only from the
+// cell that holds the lower corner of the two boxes' intersection, so every
+// overlapping pair is found exactly once; buckets are sorted, so the order of
+// the output is deterministic.  The result is the same set as testing all
+// pairs.
+// ---------------------------------------------------------------------------
+constexpr int kMaxSpan = 4;
+
+DEV bool cell_range(const double *box, double h, int lo[3], int hi[3]) {
+  bool big = false;
+  for (int k = 0; k < 3; ++k) {
+    double a = floor(box[k] / h), b = floor(box[3 + k] / h);
+    if (!(a > -1e9 && b < 1e9)) {  // also catches NaN
+      big = true;
+      lo[k] = hi[k] = 0;
+      continue;
+    }
+    lo[k] = (int)a;
+    hi[k] = (int)b;
+    if (hi[k] - lo[k] >= kMaxSpan) big = true;
+  }
+  return big;
+}
+
+DEV unsigned cell_hash(int kind, int env, int cx, int cy, int cz, unsigned mask) {
+  unsigned h = (unsigned)cx * 73856093u ^ (unsigned)cy * 19349663u ^ (unsigned)cz * 83492791u ^
+               (unsigned)env * 2654435761u ^ (unsigned)kind * 0x9E3779B9u;
+  h ^= h >> 15;
+  h *= 0x2C1B3C6Du;
+  h ^= h >> 12;
+  return h & mask;
+}
+
+DEV int bitem_index(const EnvDev &E, int kind, int b) {
+  return E.bitem_off + (kind == 0 ? (b - E.tri_off) : (E.ntri + b - E.e_off));
+}
+
+__global__ void k_grid_count(WorldDev W, const EnvDev *envs, EnvState S, const Tile *tiles, int *ncell, int *isbig) {
+  Tile t = tiles[blockIdx.x];
+  if ((int)threadIdx.x >= t.count) return;
+  const EnvDev &E = envs[t.env];
+  int kind = t.rel, b = t.start + threadIdx.x;
+  int it = bitem_index(E, kind, b);
+  if (!active_env(S, t.env)) {
+    ncell[it] = 0;
+    isbig[it] = 0;
+    return;
+  }
+  const double *box = (kind == 0 ? W.box_tri : W.box_edge) + 6 * b;
+  int lo[3], hi[3];
+  bool big = cell_range(box, E.cell, lo, hi);
+  isbig[it] = big ? 1 : 0;
+  ncell[it] = big ? 0 : (hi[0] - lo[0] + 1) * (hi[1] - lo[1] + 1) * (hi[2] - lo[2] + 1);
+}
+
+__global__ void k_grid_fill(WorldDev W, const EnvDev *envs, EnvState S, const Tile *tiles, const int *eoff,
+                            const int *bigoff, int4 *ent, int *ebucket, int *bcnt, int *bigl, unsigned mask) {
+  Tile t = tiles[blockIdx.x];
+  if ((int)threadIdx.x >= t.count || !active_env(S, t.env)) return;
+  const EnvDev &E = envs[t.env];
+  int kind = t.rel, b = t.start + threadIdx.x;
+  int it = bitem_index(E, kind, b);
+  int code = (kind == 0) ? b : ~b;
+  const double *box = (kind == 0 ? W.box_tri : W.box_edge) + 6 * b;
+  int lo[3], hi[3];
+  if (cell_range(box, E.cell, lo, hi)) {
+    bigl[bigoff[it]] = code;
+    return;
+  }
+  int o = eoff[it];
+  for (int cx = lo[0]; cx <= hi[0]; ++cx)
+    for (int cy = lo[1]; cy <= hi[1]; ++cy)
+      for (int cz = lo[2]; cz <= hi[2]; ++cz) {
+        unsigned h = cell_hash(kind, t.env, cx, cy, cz, mask);
+        ent[o] = make_int4(code, cx, cy, cz);
+        ebucket[o] = (int)h;
+        atomicAdd(&bcnt[h], 1);
+        ++o;
+      }
+}
+
+__global__ void k_grid_place(const int4 *ent, const int *ebucket, int n, const int *boff, int *bcur, int4 *sorted) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  int h = ebucket[k];
+  sorted[boff[h] + atomicAdd(&bcur[h], 1)] = ent[k];
+}
+
+DEV bool ent_less(int4 a, int4 b) {
+  if (a.x != b.x) return a.x < b.x;
+  if (a.y != b.y) return a.y < b.y;
+  if (a.z != b.z) return a.z < b.z;
+  return a.w < b.w;
+}
+
+__global__ void k_grid_sort(const int *boff, int4 *sorted, int nb) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nb) return;
+  int b = boff[i], e = boff[i + 1];
+  for (int j = b + 1; j < e; ++j) {
+    int4 key = sorted[j];
+    int m = j - 1;
+    while (m >= b && ent_less(key, sorted[m])) {
+      sorted[m + 1] = sorted[m];
+      --m;
+    }
+    sorted[m + 1] = key;
+  }
+}
+
+__global__ void k_big_seg(const EnvDev *envs, EnvState S, const int *benv, int n, const int *bigoff) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  int e = benv[j];
+  const EnvDev &E = envs[e];
+  S.big_beg[e] = bigoff[E.bitem_off];
+  S.big_end[e] = bigoff[E.bitem_off + E.ntri + E.ne];
+}
+
+struct QueryPrim {
+  double lo[3], hi[3];
+  int v0, v1;
+  bool akin;
+};
+
+// exclusions + emission of one candidate pair (a query, b candidate)
+DEV bool accept_pair(const WorldDev &W, int kind, const QueryPrim &A, int b) {
+  if (kind == 0) {
+    int4 q = W.tri[b];
+    if (A.v0 == q.x || A.v0 == q.y || A.v0 == q.z) return false;
+    if (A.akin && W.kin[q.x] >= 0 && W.kin[q.y] >= 0 && W.kin[q.z] >= 0) return false;
+  } else {
+    int4 q = W.edge[b];
+    if (A.v0 == q.x || A.v0 == q.y || A.v1 == q.x || A.v1 == q.y) return false;
+    if (A.akin && W.kin[q.x] >= 0 && W.kin[q.y] >= 0) return false;
+  }
+  return true;
+}
+
+DEV bool boxes_overlap(const QueryPrim &A, const double *bx) {
+  return A.lo[0] <= bx[3] && bx[0] <= A.hi[0] && A.lo[1] <= bx[4] && bx[1] <= A.hi[1] && A.lo[2] <= bx[5] &&
+         bx[2] <= A.hi[2];
+}
+
+template <bool WRITE>
+__global__ void __launch_bounds__(256) k_bp_grid(WorldDev W, const EnvDev *envs, EnvState S, const Tile *tiles,
+                                                 int *counts, const int *offs, int2 *out, const int4 *sorted,
+                                                 const int *boff, const int *bigl, unsigned mask) {
+  Tile t = tiles[blockIdx.x];
+  if ((int)threadIdx.x >= t.count) return;
+  const EnvDev &E = envs[t.env];
+  int kind = t.rel;
+  int a = t.start + threadIdx.x;
+  int item = E.item_off + (kind == 0 ? (a - E.sv_off) : (E.nsv + a - E.e_off));
+  if (!active_env(S, t.env)) {
+    if (!WRITE) counts[item] = 0;
+    return;
+  }
+  QueryPrim A;
+  const double *bx = (kind == 0 ? W.box_sv : W.box_edge) + 6 * a;
+  for (int k = 0; k < 3; ++k) {
+    A.lo[k] = bx[k];
+    A.hi[k] = bx[3 + k];
+  }
+  if (kind == 0) {
+    A.v0 = W.sv[a];
+    A.v1 = -1;
+    A.akin = W.kin[A.v0] >= 0;
+  } else {
+    int4 q = W.edge[a];
+    A.v0 = q.x;
+    A.v1 = q.y;
+    A.akin = W.kin[q.x] >= 0 && W.kin[q.y] >= 0;
+  }
+  const double h = E.cell;
+  int cnt = 0;
+  int pos = WRITE ? offs[item] : 0;
+  int lo[3], hi[3];
+  bool big = cell_range(bx, h, lo, hi);
+  if (big) {
+    // every candidate of the environment, like an all-pairs test
+    int bbeg = (kind == 0) ? E.tri_off : a + 1;
+    int bend = (kind == 0) ? E.tri_off + E.ntri : E.e_off + E.ne;
+    for (int b = bbeg; b < bend; ++b) {
+      const double *bb = (kind == 0 ? W.box_tri : W.box_edge) + 6 * b;
+      if (!boxes_overlap(A, bb) || !accept_pair(W, kind, A, b)) continue;
+      if (WRITE) out[pos++] = kind == 0 ? make_int2(a, b) : make_int2(~a, b);
+      ++cnt;
+    }
+  } else {
+    for (int cx = lo[0]; cx <= hi[0]; ++cx)
+      for (int cy = lo[1]; cy <= hi[1]; ++cy)
+        for (int cz = lo[2]; cz <= hi[2]; ++cz) {
+          unsigned hh = cell_hash(kind, t.env, cx, cy, cz, mask);
+          for (int e = boff[hh]; e < boff[hh + 1]; ++e) {
+            int4 en = sorted[e];
+            if (en.y != cx || en.z != cy || en.w != cz) continue;
+            if ((kind == 0) != (en.x >= 0)) continue;
+            int b = (kind == 0) ? en.x : ~en.x;
+            if (kind == 1 && b <= a) continue;
+            const double *bb = (kind == 0 ? W.box_tri : W.box_edge) + 6 * b;
+            int benv = (kind == 0) ? W.tri[b].w : W.edge[b].z;
+            if (benv != t.env || !boxes_overlap(A, bb)) continue;
+            // owner cell: the one holding the lower corner of the intersection
+            if ((int)floor(fmax(A.lo[0], bb[0]) / h) != cx || (int)floor(fmax(A.lo[1], bb[1]) / h) != cy ||
+                (int)floor(fmax(A.lo[2], bb[2]) / h) != cz)
+              continue;
+            if (!accept_pair(W, kind, A, b)) continue;
+            if (WRITE) out[pos++] = kind == 0 ? make_int2(a, b) : make_int2(~a, b);
+            ++cnt;
+          }
+        }
+    for (int j = S.big_beg[t.env]; j < S.big_end[t.env]; ++j) {
+      int code = bigl[j];
+      if ((kind == 0) != (code >= 0)) continue;
+      int b = (kind == 0) ? code : ~code;
+      if (kind == 1 && b <= a) continue;
+      const double *bb = (kind == 0 ? W.box_tri : W.box_edge) + 6 * b;
+      if (!boxes_overlap(A, bb) || !accept_pair(W, kind, A, b)) continue;
+      if (WRITE) out[pos++] = kind == 0 ? make_int2(a, b) : make_int2(~a, b);
+      ++cnt;
+    }
+  }
+  if (!WRITE) counts[item] = cnt;
+}
+
+// ---------------------------------------------------------------------------
 // exclusive scan of int counts: out[0..n], out[n] = total
 // ---------------------------------------------------------------------------
 constexpr int SCAN_PER_BLOCK = 1024;
@@ -1259,6 +1489,34 @@ void bp_count(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState 
 }
 void bp_write(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L) {
   if (B.n_it) IPC_LAUNCH(k_bp<true>, B.n_it, TB, s)(W, E, S, B.itiles, nullptr, L.offs, L.cand);
+}
+
+void grid_count(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L) {
+  if (B.n_bt) IPC_LAUNCH(k_grid_count, B.n_bt, TB, s)(W, E, S, B.btiles, L.g_ncell, L.g_big);
+}
+void grid_fill(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L,
+               int n_ent, unsigned nbuckets) {
+  IPC_LAUNCH(k_fill_int, nblk(nbuckets + 1, TB), TB, s)(L.g_bcnt, nbuckets + 1, 0);
+  IPC_LAUNCH(k_fill_int, nblk(nbuckets + 1, TB), TB, s)(L.g_bcur, nbuckets + 1, 0);
+  if (B.n_bt)
+    IPC_LAUNCH(k_grid_fill, B.n_bt, TB, s)(W, E, S, B.btiles, L.g_eoff, L.g_bigoff, L.g_ent, L.g_ebucket, L.g_bcnt,
+                                          L.g_bigl, nbuckets - 1);
+  IPC_LAUNCH(k_big_seg, nblk(B.n_envs, 64), 64, s)(E, S, B.envs, B.n_envs, L.g_bigoff);
+  scan_int(s, L.g_bcnt, L.g_boff, (int)nbuckets, L.scan_tmp);
+  if (n_ent) IPC_LAUNCH(k_grid_place, nblk(n_ent, TB), TB, s)(L.g_ent, L.g_ebucket, n_ent, L.g_boff, L.g_bcur, L.g_sorted);
+  IPC_LAUNCH(k_grid_sort, nblk(nbuckets, TB), TB, s)(L.g_boff, L.g_sorted, (int)nbuckets);
+}
+void bp_grid_count(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L,
+                   unsigned nbuckets) {
+  if (B.n_it)
+    IPC_LAUNCH(k_bp_grid<false>, B.n_it, TB, s)(W, E, S, B.itiles, L.counts, nullptr, nullptr, L.g_sorted, L.g_boff,
+                                               L.g_bigl, nbuckets - 1);
+}
+void bp_grid_write(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L,
+                   unsigned nbuckets) {
+  if (B.n_it)
+    IPC_LAUNCH(k_bp_grid<true>, B.n_it, TB, s)(W, E, S, B.itiles, nullptr, L.offs, L.cand, L.g_sorted, L.g_boff,
+                                              L.g_bigl, nbuckets - 1);
 }
 
 void scan_int(hipStream_t s, const int *in, int *out, int n, int *tmp) {

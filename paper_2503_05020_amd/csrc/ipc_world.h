@@ -42,8 +42,10 @@ struct EnvDev {
   int step;
   int maxit, precision;
   int vtile_first, vtile_count;  // this env's tiles in the batch vertex-tile list
-  int item_off;                  // first broad-phase work item in the batch
+  int item_off;                  // first broad-phase query item (surface verts, then edges) in the batch
+  int bitem_off;                 // first broad-phase grid item (surface tris, then edges) in the batch
   double dt, dhat, kappa, mu, eps_v, tol, pcg_tol;
+  double cell;                   // hash-grid cell size of this environment
 };
 
 // Per-environment solver state (device arrays indexed by slot).
@@ -52,7 +54,7 @@ struct EnvState {
   long long *pcg_total;
   double *alpha, *E0, *E1, *pinf;
   unsigned long long *amax_bits;  // CCD bound as ordered bits of a non-negative double
-  int *cand_beg, *cand_end, *act_beg, *act_end, *fric_beg, *fric_end;
+  int *cand_beg, *cand_end, *act_beg, *act_end, *fric_beg, *fric_end, *big_beg, *big_end;
   int *in_step;                   // 1 if the env takes part in the current step
   double *pcg_bb;                 // |g|^2 of the current solve
 };

@@ -135,6 +135,29 @@ def test_candidates_and_active_sets_bit_exact(name):
     assert mg == mo
 
 
+@pytest.mark.parametrize("name", ["sphere", "superquadric7"])
+def test_candidate_sets_bit_exact_on_workload_scenes(name):
+    """Grid broad phase vs the oracle's all-pairs test on scenes with huge (ground) and rotated primitives."""
+    say("workload sets", name)
+    sc = S.parallel_jaw_sphere() if name == "sphere" else S.superquadric_grasp(7)
+    g = G.ipc_create_scene(sc)
+    o = O.Scene(sc)
+    rng = np.random.default_rng(9)
+    free = (sc["kin_group"] < 0)[:, None]
+    # squeeze the scene a little so that many pairs come within dhat
+    c = sc["rest_pos"][free[:, 0]].mean(0)
+    x = sc["rest_pos"] + (c - sc["rest_pos"]) * 0.01 * free + rng.normal(scale=2e-4, size=sc["rest_pos"].shape) * free
+    assert rows(G.ipc_debug_candidates(g, x)) == rows(o.candidates(x))
+    p = rng.normal(scale=2e-3, size=x.shape) * free
+    assert rows(G.ipc_debug_candidates(g, x, p)) == rows(o.candidates(x, p))
+    big = rng.normal(scale=3e-2, size=x.shape) * free  # large sweeps take the all-pairs path
+    assert rows(G.ipc_debug_candidates(g, x, big)) == rows(o.candidates(x, big))
+    ag, dg = G.ipc_debug_active(g, x)
+    ao, do = o.active(x)
+    assert {tuple(r) for r in ag.tolist()} == {tuple(r) for r in ao.tolist()}
+    assert sorted(dg.tolist()) == sorted(do.tolist())
+
+
 def _begin(sc, steps_before=0, **kw):
     g = G.ipc_create_scene(sc, pcg_rel_tol=1e-8, **kw)
     o = O.Scene(sc, pcg_rel_tol=1e-8, **kw)
