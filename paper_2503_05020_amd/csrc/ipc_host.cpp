@@ -563,7 +563,8 @@ struct World {
   // batch
   std::vector<int> batch_envs;
   DBuf<Tile> vt_d, tt_d, svt_d, trit_d, et_d, it_d, bt_d;
-  DBuf<int> benv_d;
+  DBuf<int> benv_d, fenv_d;
+  std::vector<int> fused_h;  // batch envs whose PCG runs in one workgroup
   ipck::Batch B{};
   ipck::Lists L{};
   DBuf<int> counts, offs, scan_tmp, cand_type, cand_flag, cand_offs, act_type, fenv, inc_cnt, inc_off, inc_cur,
@@ -847,6 +848,7 @@ struct World {
     if (envs == batch_envs) return;
     std::vector<Tile> vt, tt, svt, trit, et, it, bt;
     int item_off = 0, bitem_off = 0;
+    fused_h.clear();
     for (int e : envs) {
       EnvDev &E = envs_h[e];
       E.vtile_first = (int)vt.size();
@@ -867,6 +869,8 @@ struct World {
       item_off += E.nsv + E.ne;
       E.bitem_off = bitem_off;
       bitem_off += E.ntri + E.ne;
+      E.fused = (E.nv_pad <= ipcw::kFusedRows && !no_fused()) ? 1 : 0;
+      if (E.fused) fused_h.push_back(e);
       upload_env(e);
     }
     auto put = [&](DBuf<Tile> &d, const std::vector<Tile> &h) {
@@ -882,6 +886,8 @@ struct World {
     put(bt_d, bt);
     benv_d.ensure(envs.size() + 1);
     up(benv_d.p, envs.data(), envs.size());
+    fenv_d.ensure(fused_h.size() + 1);
+    up(fenv_d.p, fused_h.data(), fused_h.size());
     B.vtiles = vt_d.p;
     B.ttiles = tt_d.p;
     B.svtiles = svt_d.p;
@@ -1100,8 +1106,30 @@ struct World {
     return na;
   }
 
+  // IPC_NO_FUSED_PCG=1 keeps every environment on the tiled PCG path
+  static bool no_fused() {
+    static int t = -1;
+    if (t < 0) {
+      const char *e = std::getenv("IPC_NO_FUSED_PCG");
+      t = (e && e[0] && e[0] != '0') ? 1 : 0;
+    }
+    return t == 1;
+  }
+
   long long solve(int mixed) {
     int *pending = L.counter;
+    ipck::pcg_fused(stream, W, envs_d, S, fenv_d.p, (int)fused_h.size(), L, mixed);
+    if (fused_h.size() == batch_envs.size()) {
+      ipck::pcg_finish(stream, W, S, B, mixed);
+      HC(hipStreamSynchronize(stream));
+      if (!tracing()) return 0;
+      std::vector<int> its(env_cap);
+      HC(hipMemcpyAsync(its.data(), S.pcg_it, 4 * env_cap, hipMemcpyDeviceToHost, stream));
+      HC(hipStreamSynchronize(stream));
+      int mx = 0;
+      for (int e : fused_h) mx = std::max(mx, its[e]);
+      return mx;
+    }
     ipck::pcg_init(stream, W, envs_d, S, B, L, pending, mixed);
     int cap = 0;
     for (int e : batch_envs) cap = std::max(cap, 30 * envs_h[e].nv + 10);

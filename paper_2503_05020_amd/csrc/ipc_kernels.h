@@ -86,6 +86,9 @@ void pcg_init(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState 
 void pcg_iter(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L, int it,
               int *pending, int mixed, int cap, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 void pcg_finish(hipStream_t s, const WorldDev &W, const EnvState &S, const Batch &B, int mixed);
+// one workgroup per environment for the environments flagged `fused`
+void pcg_fused(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const int *fenv, int n_fenv,
+               Lists &L, int mixed);
 void spmv_debug(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L,
                 const double *in, double *out);
 

@@ -938,10 +938,11 @@ DEV void sell_apply(const WorldDev &W, int i, const T *v, const T *val, double y
 
 DEV bool pcg_env_live(const EnvState &S, int env) { return S.status[env] == ST_ACTIVE && !S.pcg_done[env]; }
 
-__global__ void k_pcg_init(WorldDev W, EnvState S, const Tile *tiles, double *part_rz, double *part_rr) {
+__global__ void k_pcg_init(WorldDev W, const EnvDev *envs, EnvState S, const Tile *tiles, double *part_rz,
+                           double *part_rr) {
   __shared__ double sh[TB];
   Tile t = tiles[blockIdx.x];
-  if (!active_env(S, t.env)) return;
+  if (!active_env(S, t.env) || envs[t.env].fused) return;
   int i = t.start + threadIdx.x;
   double rz = 0.0, rr = 0.0;
   if ((int)threadIdx.x < t.count) {
@@ -967,10 +968,11 @@ __global__ void k_pcg_init(WorldDev W, EnvState S, const Tile *tiles, double *pa
   }
 }
 
-__global__ void k_pcg_init32(WorldDev W, EnvState S, const Tile *tiles, double *part_rz, double *part_rr) {
+__global__ void k_pcg_init32(WorldDev W, const EnvDev *envs, EnvState S, const Tile *tiles, double *part_rz,
+                             double *part_rr) {
   __shared__ double sh[TB];
   Tile t = tiles[blockIdx.x];
-  if (!active_env(S, t.env)) return;
+  if (!active_env(S, t.env) || envs[t.env].fused) return;
   int i = t.start + threadIdx.x;
   double rz = 0.0, rr = 0.0;
   if ((int)threadIdx.x < t.count) {
@@ -1001,6 +1003,7 @@ __global__ void k_pcg_env_init(const EnvDev *envs, EnvState S, const int *benv, 
   int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
   int e = benv[j];
+  if (envs[e].fused) return;  // solved by the fused kernel
   S.pcg_it[e] = 0;
   if (S.status[e] != ST_ACTIVE) {
     S.pcg_done[e] = 1;
@@ -1125,6 +1128,127 @@ __global__ void k_pcg_dir(WorldDev W, const EnvDev *envs, EnvState S, const Tile
   if ((int)threadIdx.x < t.count)
     for (int c = 0; c < 3; ++c) pp[3 * i + c] = (T)((double)z[3 * i + c] + beta * (double)pp[3 * i + c]);
   if (threadIdx.x == 0 && t.rel == 0) S.pcg_it[t.env] += 1;
+}
+
+// ---------------------------------------------------------------------------
+// Fused PCG: one 1024-thread workgroup runs a whole environment's solve to
+// convergence inside one launch (environments up to kFusedRows rows).  Thread
+// t owns rows t, t+1024, ...; a wavefront therefore owns one 64-row slice of
+// the sliced-ELL matrix.  Reductions: wavefront shuffles, then the 16 wave
+// partials summed in order by every thread (deterministic).
+// ---------------------------------------------------------------------------
+constexpr int FB = 1024;
+
+DEV double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+// sums a and b over the workgroup; every thread gets the totals
+DEV void block_sum2(double &a, double &b, double (*sh)[FB / 64]) {
+  a = wave_sum(a);
+  b = wave_sum(b);
+  int w = threadIdx.x / 64;
+  if ((threadIdx.x & 63) == 0) {
+    sh[0][w] = a;
+    sh[1][w] = b;
+  }
+  __syncthreads();
+  a = 0.0;
+  b = 0.0;
+  for (int i = 0; i < FB / 64; ++i) {
+    a += sh[0][i];
+    b += sh[1][i];
+  }
+  __syncthreads();
+}
+
+template <typename T>
+__global__ void __launch_bounds__(1024) k_pcg_fused(WorldDev W, const EnvDev *envs, EnvState S, const int *fenv,
+                                                    const int *inc_off, const int *inc_ent, const int4 *ce_v,
+                                                    const double *ce_H, T *p, T *r, T *z, T *pp, T *q, const T *val,
+                                                    const T *Minv, unsigned long long *prof) {
+  __shared__ double sh[2][FB / 64];
+  int e = fenv[blockIdx.x];
+  if (S.status[e] != ST_ACTIVE) return;
+  const EnvDev &E = envs[e];
+  const int r0 = E.v_off, r1 = E.v_off + E.nv_pad;
+  const int cap = 30 * E.nv + 10;
+  const double tol2 = E.pcg_tol * E.pcg_tol;
+  double rz = 0.0, bb = 0.0;
+  for (int i = r0 + threadIdx.x; i < r1; i += FB) {
+    bool fr = W.kin[i] == KIN_FREE;
+    T rv[3], zv[3];
+    for (int c = 0; c < 3; ++c) rv[c] = fr ? (T)(-W.g[3 * i + c]) : (T)0;
+    const T *M = Minv + 9 * (size_t)i;
+    for (int c = 0; c < 3; ++c) zv[c] = fr ? M[3 * c] * rv[0] + M[3 * c + 1] * rv[1] + M[3 * c + 2] * rv[2] : (T)0;
+    for (int c = 0; c < 3; ++c) {
+      r[3 * i + c] = rv[c];
+      z[3 * i + c] = zv[c];
+      pp[3 * i + c] = zv[c];
+      p[3 * i + c] = (T)0;
+      rz += (double)rv[c] * (double)zv[c];
+      bb += (double)rv[c] * (double)rv[c];
+    }
+  }
+  block_sum2(rz, bb, sh);
+  int it = 0;
+  double bytes = 0.0;
+  if (bb > 0.0 && bb == bb) {
+    for (;;) {
+      // q = H pp and pp.q
+      double pq = 0.0, dummy = 0.0;
+      for (int i = r0 + threadIdx.x; i < r1; i += FB) {
+        double y[3];
+        sell_apply<T>(W, i, pp, val, y);
+        contact_apply<T>(i, pp, inc_off, inc_ent, ce_v, ce_H, y);
+        for (int c = 0; c < 3; ++c) {
+          q[3 * i + c] = (T)y[c];
+          pq += (double)pp[3 * i + c] * (double)(T)y[c];
+        }
+        if (prof)
+          bytes += (double)W.row_nnz[i] * (9.0 * sizeof(T) + 4.0) + 6.0 * sizeof(T) +
+                   (inc_off[i + 1] - inc_off[i]) * (4.0 * 72.0 + 16.0);
+      }
+      block_sum2(pq, dummy, sh);
+      double alpha = (pq > 0.0) ? rz / pq : 0.0;
+      // x, r, z updates and the new dots
+      double rzn = 0.0, rrn = 0.0;
+      for (int i = r0 + threadIdx.x; i < r1; i += FB) {
+        T rv[3], zv[3];
+        for (int c = 0; c < 3; ++c) {
+          p[3 * i + c] = (T)((double)p[3 * i + c] + alpha * (double)pp[3 * i + c]);
+          rv[c] = (T)((double)r[3 * i + c] - alpha * (double)q[3 * i + c]);
+          r[3 * i + c] = rv[c];
+        }
+        const T *M = Minv + 9 * (size_t)i;
+        for (int c = 0; c < 3; ++c) zv[c] = M[3 * c] * rv[0] + M[3 * c + 1] * rv[1] + M[3 * c + 2] * rv[2];
+        for (int c = 0; c < 3; ++c) {
+          z[3 * i + c] = zv[c];
+          rzn += (double)rv[c] * (double)zv[c];
+          rrn += (double)rv[c] * (double)rv[c];
+        }
+      }
+      block_sum2(rzn, rrn, sh);
+      ++it;
+      if (rrn <= tol2 * bb || !(rrn == rrn) || it >= cap || !(rz > 0.0)) break;
+      double beta = rzn / rz;
+      rz = rzn;
+      for (int i = r0 + threadIdx.x; i < r1; i += FB)
+        for (int c = 0; c < 3; ++c) pp[3 * i + c] = (T)((double)z[3 * i + c] + beta * (double)pp[3 * i + c]);
+      __syncthreads();
+    }
+  }
+  if (prof) {
+    double dummy = 0.0;
+    block_sum2(bytes, dummy, sh);
+  }
+  if (threadIdx.x == 0) {
+    S.pcg_it[e] = it;
+    S.pcg_total[e] += it;
+    S.pcg_done[e] = 1;
+    if (prof) atomicAdd(prof, (unsigned long long)bytes);
+  }
 }
 
 __global__ void k_p32_to_p(WorldDev W, EnvState S, const Tile *tiles) {
@@ -1583,8 +1707,8 @@ void assemble(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState 
 void pcg_init(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L,
               int *pending, int mixed) {
   IPC_LAUNCH(k_fill_int, 1, 64, s)(pending, 1, 0);
-  if (B.n_vt && !mixed) IPC_LAUNCH(k_pcg_init, B.n_vt, TB, s)(W, S, B.vtiles, L.part_b0, L.part_c0);
-  if (B.n_vt && mixed) IPC_LAUNCH(k_pcg_init32, B.n_vt, TB, s)(W, S, B.vtiles, L.part_b0, L.part_c0);
+  if (B.n_vt && !mixed) IPC_LAUNCH(k_pcg_init, B.n_vt, TB, s)(W, E, S, B.vtiles, L.part_b0, L.part_c0);
+  if (B.n_vt && mixed) IPC_LAUNCH(k_pcg_init32, B.n_vt, TB, s)(W, E, S, B.vtiles, L.part_b0, L.part_c0);
   IPC_LAUNCH(k_pcg_env_init, nblk(B.n_envs, 64), 64, s)(E, S, B.envs, B.n_envs, L.part_c0, pending);
 }
 
@@ -1611,6 +1735,17 @@ void pcg_iter(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState 
                                               W.z32, W.pp32, W.q32, W.Minv32);
     IPC_LAUNCH(k_pcg_dir<float>, B.n_vt, TB, s)(W, E, S, B.vtiles, rz_old, rz_new, rr_new, W.pp32, W.z32, pending, cap);
   }
+}
+
+void pcg_fused(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const int *fenv, int n_fenv,
+               Lists &L, int mixed) {
+  if (!n_fenv) return;
+  if (!mixed)
+    IPC_LAUNCH(k_pcg_fused<double>, n_fenv, FB, s)(W, E, S, fenv, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, W.p, W.r, W.z,
+                                                  W.pp, W.q, W.val, W.Minv, L.prof);
+  else
+    IPC_LAUNCH(k_pcg_fused<float>, n_fenv, FB, s)(W, E, S, fenv, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, W.p32, W.r32,
+                                                 W.z32, W.pp32, W.q32, W.val32, W.Minv32, L.prof);
 }
 
 void pcg_finish(hipStream_t s, const WorldDev &W, const EnvState &S, const Batch &B, int mixed) {

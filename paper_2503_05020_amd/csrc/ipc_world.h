@@ -15,6 +15,7 @@ namespace ipcw {
 
 constexpr int kTile = 256;     // elements per work tile (one 256-thread block)
 constexpr int kSlice = 64;     // rows per sliced-ELL slice (one wavefront)
+constexpr int kFusedRows = 8192;  // environments up to this many rows solve in one workgroup
 
 enum Status { ST_IDLE = 0, ST_ACTIVE = 1, ST_CONVERGED = 2, ST_FAILED = 3 };
 enum Fail { FAIL_NONE = 0, FAIL_MAXIT = 1, FAIL_NONFINITE = 2, FAIL_LS = 3, FAIL_DBC = 4 };
@@ -44,6 +45,7 @@ struct EnvDev {
   int vtile_first, vtile_count;  // this env's tiles in the batch vertex-tile list
   int item_off;                  // first broad-phase query item (surface verts, then edges) in the batch
   int bitem_off;                 // first broad-phase grid item (surface tris, then edges) in the batch
+  int fused;                     // 1: the PCG solve runs in one workgroup (nv_pad <= kFusedRows)
   double dt, dhat, kappa, mu, eps_v, tol, pcg_tol;
   double cell;                   // hash-grid cell size of this environment
 };
