@@ -395,6 +395,79 @@ DEV void psd_project(int n, double *A, int ld, double *V) {
     }
 }
 
+// -- exact PSD projection of a barrier Hessian on its range -----------------------
+// Without the mollifier, H = kappa (B2 gz gz^T + B1 Hz) with gz = 2 c (x) r and
+// Hz = 2 (c c^T) (x) I - 2 sum Ginv_kl u_k u_l^T, u_k = c (x) q_k + dc_k (x) r.
+// Writing dc_k = w_k + c (c.dc_k)/|c|^2 with w_k orthogonal to c gives
+// u_k = c (x) (q_k + ...) + w_k (x) r, so range(H) lies in
+//   span{ c (x) e_1, c (x) e_2, c (x) e_3, w_k (x) r }   (dimension 3 + nb <= 5).
+// With Q an orthonormal basis of that span, Proj(H) = Q Proj(Q^T H Q) Q^T.
+DEV bool subspace_project(const TypeGeo &T, const double *x, double *H) {
+  double r[3] = {0, 0, 0};
+  for (int i = 0; i < 4; ++i)
+    for (int k = 0; k < 3; ++k) r[k] += T.c[i] * x[3 * i + k];
+  double cn2 = T.c[0] * T.c[0] + T.c[1] * T.c[1] + T.c[2] * T.c[2] + T.c[3] * T.c[3];
+  double rn = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+  if (!(cn2 > 0.0) || !(rn > 0.0)) return false;
+  double Q[5][12];
+  int D = 0;
+  double ci = 1.0 / sqrt(cn2);
+  for (int m = 0; m < 3; ++m, ++D)
+    for (int i = 0; i < 4; ++i)
+      for (int k = 0; k < 3; ++k) Q[D][3 * i + k] = (k == m) ? T.c[i] * ci : 0.0;
+  double om[2][4];
+  int nw = 0;
+  for (int kk = 0; kk < T.nb; ++kk) {
+    double w[4], cd = 0.0, dn = 0.0;
+    for (int i = 0; i < 4; ++i) {
+      cd += T.c[i] * T.dc[kk][i];
+      dn += T.dc[kk][i] * T.dc[kk][i];
+    }
+    for (int i = 0; i < 4; ++i) w[i] = T.dc[kk][i] - T.c[i] * cd / cn2;
+    for (int j = 0; j < nw; ++j) {
+      double pr = 0.0;
+      for (int i = 0; i < 4; ++i) pr += w[i] * om[j][i];
+      for (int i = 0; i < 4; ++i) w[i] -= pr * om[j][i];
+    }
+    double wn = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2] + w[3] * w[3]);
+    if (!(wn > 1e-12 * sqrt(dn))) continue;
+    for (int i = 0; i < 4; ++i) om[nw][i] = w[i] / wn;
+    for (int i = 0; i < 4; ++i)
+      for (int k = 0; k < 3; ++k) Q[D][3 * i + k] = om[nw][i] * r[k] / rn;
+    ++nw;
+    ++D;
+  }
+  // M = Q^T H Q
+  double HQ[12][5], M[25], V[25];
+  for (int a = 0; a < 12; ++a)
+    for (int j = 0; j < D; ++j) {
+      double s = 0.0;
+      for (int b = 0; b < 12; ++b) s += H[a * 12 + b] * Q[j][b];
+      HQ[a][j] = s;
+    }
+  for (int i = 0; i < D; ++i)
+    for (int j = 0; j < D; ++j) {
+      double s = 0.0;
+      for (int a = 0; a < 12; ++a) s += Q[i][a] * HQ[a][j];
+      M[i * D + j] = s;
+    }
+  for (int i = 0; i < D; ++i)  // symmetrise rounding
+    for (int j = i + 1; j < D; ++j) M[i * D + j] = M[j * D + i] = 0.5 * (M[i * D + j] + M[j * D + i]);
+  psd_project(D, M, D, V);
+  for (int a = 0; a < 12; ++a)
+    for (int b = a; b < 12; ++b) {
+      double s = 0.0;
+      for (int i = 0; i < D; ++i) {
+        double t = 0.0;
+        for (int j = 0; j < D; ++j) t += M[i * D + j] * Q[j][b];
+        s += Q[i][a] * t;
+      }
+      H[a * 12 + b] = s;
+      H[b * 12 + a] = s;
+    }
+  return true;
+}
+
 // -- pair barrier element ------------------------------------------------------
 // Energy kappa * e(c) * b(d) with gradient and (optionally projected) Hessian.
 // b as a function of z = d^2: db/dz = b'/(2d), d2b/dz2 = (b'' - b'/d) / (4 z).
@@ -415,7 +488,7 @@ DEV double pair_barrier_full(int kind, int type, const double *x, double dhat, d
     for (int j = 0; j < 12; ++j) H[i * 12 + j] = B2 * g[i] * g[j] + B1 * H[i * 12 + j];
   for (int i = 0; i < 12; ++i) g[i] *= B1;
   double e = 1.0;
-  bool all4 = (T.n_involved == 4);
+  bool all4 = (T.n_involved == 4), mollified = false;
   if (kind == 1) {
     double c, gc[12];
     double *Hc = scratch;
@@ -431,12 +504,15 @@ DEV double pair_barrier_full(int kind, int type, const double *x, double dhat, d
                           e1 * (gc[i] * g[j] + g[i] * gc[j]);
       for (int i = 0; i < 12; ++i) g[i] = e * g[i] + b0 * e1 * gc[i];
       all4 = true;
+      mollified = true;
     }
   }
   for (int i = 0; i < 12; ++i) g[i] *= kappa;
   for (int i = 0; i < 144; ++i) H[i] *= kappa;
   if (project) {
-    if (all4) {
+    if (!mollified && subspace_project(T, x, H)) {
+      // exact projection on the (3 + nb)-dimensional range, see above
+    } else if (all4) {
       psd_project(12, H, 12, scratch);
     } else {
       // project on the involved coordinates only (the rest of H is zero)
