@@ -563,7 +563,8 @@ struct World {
   // batch
   std::vector<int> batch_envs;
   DBuf<Tile> vt_d, tt_d, svt_d, trit_d, et_d, it_d, bt_d;
-  DBuf<int> benv_d, fenv_d;
+  DBuf<int> benv_d, fenv_d, live_flag, live_offs;
+  DBuf<Tile> live_d;
   std::vector<int> fused_h;  // batch envs whose PCG runs in one workgroup
   ipck::Batch B{};
   ipck::Lists L{};
@@ -869,7 +870,7 @@ struct World {
       item_off += E.nsv + E.ne;
       E.bitem_off = bitem_off;
       bitem_off += E.ntri + E.ne;
-      E.fused = (E.nv_pad <= ipcw::kFusedRows && !no_fused()) ? 1 : 0;
+      E.fused = (E.nv_pad <= ipcw::kFusedRows && use_fused()) ? 1 : 0;
       if (E.fused) fused_h.push_back(e);
       upload_env(e);
     }
@@ -888,6 +889,9 @@ struct World {
     up(benv_d.p, envs.data(), envs.size());
     fenv_d.ensure(fused_h.size() + 1);
     up(fenv_d.p, fused_h.data(), fused_h.size());
+    live_d.ensure(vt.size() + 1);
+    live_flag.ensure(vt.size() + 1);
+    live_offs.ensure(vt.size() + 2);
     B.vtiles = vt_d.p;
     B.ttiles = tt_d.p;
     B.svtiles = svt_d.p;
@@ -1106,11 +1110,13 @@ struct World {
     return na;
   }
 
-  // IPC_NO_FUSED_PCG=1 keeps every environment on the tiled PCG path
-  static bool no_fused() {
+  // IPC_FUSED_PCG=1 solves environments of up to kFusedRows rows in one
+  // workgroup each (default: the tiled path, faster on the batched grasp
+  // workload because the slowest solve then spreads over several CUs)
+  static bool use_fused() {
     static int t = -1;
     if (t < 0) {
-      const char *e = std::getenv("IPC_NO_FUSED_PCG");
+      const char *e = std::getenv("IPC_FUSED_PCG");
       t = (e && e[0] && e[0] != '0') ? 1 : 0;
     }
     return t == 1;
@@ -1135,6 +1141,10 @@ struct World {
     for (int e : batch_envs) cap = std::max(cap, 30 * envs_h[e].nv + 10);
     int it = 0;
     size_t nev = 0;
+    // iterate over the tiles of environments still solving; the list is
+    // compacted whenever an environment has converged since the last poll
+    const Tile *tl = B.vtiles;
+    int ntl = B.n_vt, last_pending = -1;
     while (true) {
       for (int j = 0; j < 8; ++j) {
         hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1142,9 +1152,16 @@ struct World {
           e0 = pool_event(nev++);
           e1 = pool_event(nev++);
         }
-        ipck::pcg_iter(stream, W, envs_d, S, B, L, it++, pending, mixed, cap, e0, e1);
+        ipck::pcg_iter(stream, W, envs_d, S, B, L, it++, pending, mixed, cap, e0, e1, tl, ntl);
       }
-      if (read_int(pending) <= 0 || it >= cap) break;
+      int pend = read_int(pending);
+      if (pend <= 0 || it >= cap) break;
+      if (pend != last_pending) {
+        ipck::live_tiles(stream, S, B, L, live_d.p, live_flag.p, live_offs.p);
+        ntl = read_int(live_offs.p + B.n_vt);
+        tl = live_d.p;
+        last_pending = pend;
+      }
     }
     ipck::pcg_finish(stream, W, S, B, mixed);
     if (prof_on) {

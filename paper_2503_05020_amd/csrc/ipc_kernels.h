@@ -84,7 +84,9 @@ void assemble(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState 
 void pcg_init(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L,
               int *pending, int mixed);
 void pcg_iter(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L, int it,
-              int *pending, int mixed, int cap, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+              int *pending, int mixed, int cap, hipEvent_t ev0, hipEvent_t ev1, const Tile *tiles, int n_tiles);
+// tiles of environments whose PCG still iterates -> out (count at offs[B.n_vt])
+void live_tiles(hipStream_t s, const EnvState &S, const Batch &B, Lists &L, Tile *out, int *flag, int *offs);
 void pcg_finish(hipStream_t s, const WorldDev &W, const EnvState &S, const Batch &B, int mixed);
 // one workgroup per environment for the environments flagged `fused`
 void pcg_fused(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const int *fenv, int n_fenv,

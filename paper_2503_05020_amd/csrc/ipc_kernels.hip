@@ -920,23 +920,54 @@ DEV void contact_apply(int i, const T *v, const int *inc_off, const int *inc_ent
   }
 }
 
+// Sliced-ELL row product, four slots per round so that their column loads,
+// block loads and vector gathers are in flight together.
 template <typename T>
 DEV void sell_apply(const WorldDev &W, int i, const T *v, const T *val, double y[3]) {
-  int sl = i / kSlice, lane = i % kSlice;
-  int base = W.slice_pos[sl], wdt = W.slice_w[sl];
-  y[0] = y[1] = y[2] = 0.0;
-  for (int k = 0; k < wdt; ++k) {
-    int pos = base + k * kSlice + lane;
-    int col = W.col[pos];
-    size_t vb = (size_t)(pos / kSlice) * (9 * kSlice) + lane;
-    double x0 = v[3 * col], x1 = v[3 * col + 1], x2 = v[3 * col + 2];
-    for (int r = 0; r < 3; ++r)
-      y[r] += (double)val[vb + (3 * r) * kSlice] * x0 + (double)val[vb + (3 * r + 1) * kSlice] * x1 +
-              (double)val[vb + (3 * r + 2) * kSlice] * x2;
+  const int sl = i / kSlice, lane = i % kSlice;
+  const int base = W.slice_pos[sl], wdt = W.slice_w[sl];
+  const int *colp = W.col + base + lane;
+  const T *vp = val + (size_t)(base / kSlice) * (9 * kSlice) + lane;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  int k = 0;
+  for (; k + 4 <= wdt; k += 4) {
+    int c[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) c[u] = colp[(k + u) * kSlice];
+    double m[4][9], x[4][3];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const T *b = vp + (size_t)(k + u) * (9 * kSlice);
+#pragma unroll
+      for (int r = 0; r < 9; ++r) m[u][r] = (double)b[r * kSlice];
+#pragma unroll
+      for (int r = 0; r < 3; ++r) x[u][r] = (double)v[3 * c[u] + r];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a0 += m[u][0] * x[u][0] + m[u][1] * x[u][1] + m[u][2] * x[u][2];
+      a1 += m[u][3] * x[u][0] + m[u][4] * x[u][1] + m[u][5] * x[u][2];
+      a2 += m[u][6] * x[u][0] + m[u][7] * x[u][1] + m[u][8] * x[u][2];
+    }
   }
+  for (; k < wdt; ++k) {
+    int c = colp[k * kSlice];
+    const T *b = vp + (size_t)k * (9 * kSlice);
+    double x0 = v[3 * c], x1 = v[3 * c + 1], x2 = v[3 * c + 2];
+    a0 += (double)b[0] * x0 + (double)b[kSlice] * x1 + (double)b[2 * kSlice] * x2;
+    a1 += (double)b[3 * kSlice] * x0 + (double)b[4 * kSlice] * x1 + (double)b[5 * kSlice] * x2;
+    a2 += (double)b[6 * kSlice] * x0 + (double)b[7 * kSlice] * x1 + (double)b[8 * kSlice] * x2;
+  }
+  y[0] = a0;
+  y[1] = a1;
+  y[2] = a2;
 }
 
 DEV bool pcg_env_live(const EnvState &S, int env) { return S.status[env] == ST_ACTIVE && !S.pcg_done[env]; }
+
+// slot of a vertex tile in the per-tile partial arrays: its index in the
+// batch's full tile list (kernels may run over a compacted copy of the list)
+DEV int tile_slot(const EnvDev *envs, const Tile &t) { return envs[t.env].vtile_first + t.rel; }
 
 __global__ void k_pcg_init(WorldDev W, const EnvDev *envs, EnvState S, const Tile *tiles, double *part_rz,
                            double *part_rr) {
@@ -963,8 +994,8 @@ __global__ void k_pcg_init(WorldDev W, const EnvDev *envs, EnvState S, const Til
   rz = block_sum(rz, sh);
   rr = block_sum(rr, sh);
   if (threadIdx.x == 0) {
-    part_rz[blockIdx.x] = rz;
-    part_rr[blockIdx.x] = rr;
+    part_rz[tile_slot(envs, t)] = rz;
+    part_rr[tile_slot(envs, t)] = rr;
   }
 }
 
@@ -993,8 +1024,8 @@ __global__ void k_pcg_init32(WorldDev W, const EnvDev *envs, EnvState S, const T
   rz = block_sum(rz, sh);
   rr = block_sum(rr, sh);
   if (threadIdx.x == 0) {
-    part_rz[blockIdx.x] = rz;
-    part_rr[blockIdx.x] = rr;
+    part_rz[tile_slot(envs, t)] = rz;
+    part_rr[tile_slot(envs, t)] = rr;
   }
 }
 
@@ -1040,7 +1071,7 @@ __global__ void __launch_bounds__(256) k_spmv(WorldDev W, const EnvDev *envs, En
     }
   }
   pq = block_sum(pq, sh);
-  if (threadIdx.x == 0) part_pq[blockIdx.x] = pq;
+  if (threadIdx.x == 0) part_pq[tile_slot(envs, t)] = pq;
   if (prof) {
     // algorithmic bytes of this tile: stored blocks + column indices, one read
     // of pp and one write of q per row, and the contact blocks it applies
@@ -1090,8 +1121,8 @@ __global__ void k_pcg_update(WorldDev W, const EnvDev *envs, EnvState S, const T
   rz = block_sum(rz, sh);
   rr = block_sum(rr, sh);
   if (threadIdx.x == 0) {
-    part_rz_new[blockIdx.x] = rz;
-    part_rr_new[blockIdx.x] = rr;
+    part_rz_new[tile_slot(envs, t)] = rz;
+    part_rr_new[tile_slot(envs, t)] = rr;
   }
 }
 
@@ -1249,6 +1280,17 @@ __global__ void __launch_bounds__(1024) k_pcg_fused(WorldDev W, const EnvDev *en
     S.pcg_done[e] = 1;
     if (prof) atomicAdd(prof, (unsigned long long)bytes);
   }
+}
+
+// flags of the vertex tiles whose environment still iterates its PCG
+__global__ void k_live_flags(EnvState S, const Tile *tiles, int n, int *flag) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < n) flag[j] = pcg_env_live(S, tiles[j].env) ? 1 : 0;
+}
+
+__global__ void k_live_compact(const Tile *tiles, int n, const int *flag, const int *offs, Tile *out) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < n && flag[j]) out[offs[j]] = tiles[j];
 }
 
 __global__ void k_p32_to_p(WorldDev W, EnvState S, const Tile *tiles) {
@@ -1712,28 +1754,35 @@ void pcg_init(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState 
   IPC_LAUNCH(k_pcg_env_init, nblk(B.n_envs, 64), 64, s)(E, S, B.envs, B.n_envs, L.part_c0, pending);
 }
 
-void pcg_iter(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L, int it,
-              int *pending, int mixed, int cap, hipEvent_t ev0, hipEvent_t ev1) {
+void live_tiles(hipStream_t s, const EnvState &S, const Batch &B, Lists &L, Tile *out, int *flag, int *offs) {
   if (!B.n_vt) return;
+  IPC_LAUNCH(k_live_flags, nblk(B.n_vt, TB), TB, s)(S, B.vtiles, B.n_vt, flag);
+  scan_int(s, flag, offs, B.n_vt, L.scan_tmp);
+  IPC_LAUNCH(k_live_compact, nblk(B.n_vt, TB), TB, s)(B.vtiles, B.n_vt, flag, offs, out);
+}
+
+void pcg_iter(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L, int it,
+              int *pending, int mixed, int cap, hipEvent_t ev0, hipEvent_t ev1, const Tile *tiles, int n_tiles) {
+  if (!n_tiles) return;
   double *rz_old = (it & 1) ? L.part_b1 : L.part_b0;
   double *rz_new = (it & 1) ? L.part_b0 : L.part_b1;
   double *rr_new = (it & 1) ? L.part_c0 : L.part_c1;
   if (!mixed) {
     if (ev0) hipEventRecord(ev0, s);
-    IPC_LAUNCH(k_spmv<double>, B.n_vt, TB, s)(W, E, S, B.vtiles, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, W.pp, W.q, W.val,
+    IPC_LAUNCH(k_spmv<double>, n_tiles, TB, s)(W, E, S, tiles, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, W.pp, W.q, W.val,
                                          L.part_a, L.prof);
     if (ev1) hipEventRecord(ev1, s);
-    IPC_LAUNCH(k_pcg_update<double>, B.n_vt, TB, s)(W, E, S, B.vtiles, L.part_a, rz_old, rz_new, rr_new, W.p, W.r, W.z,
+    IPC_LAUNCH(k_pcg_update<double>, n_tiles, TB, s)(W, E, S, tiles, L.part_a, rz_old, rz_new, rr_new, W.p, W.r, W.z,
                                                W.pp, W.q, W.Minv);
-    IPC_LAUNCH(k_pcg_dir<double>, B.n_vt, TB, s)(W, E, S, B.vtiles, rz_old, rz_new, rr_new, W.pp, W.z, pending, cap);
+    IPC_LAUNCH(k_pcg_dir<double>, n_tiles, TB, s)(W, E, S, tiles, rz_old, rz_new, rr_new, W.pp, W.z, pending, cap);
   } else {
     if (ev0) hipEventRecord(ev0, s);
-    IPC_LAUNCH(k_spmv<float>, B.n_vt, TB, s)(W, E, S, B.vtiles, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, W.pp32, W.q32,
+    IPC_LAUNCH(k_spmv<float>, n_tiles, TB, s)(W, E, S, tiles, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, W.pp32, W.q32,
                                         W.val32, L.part_a, L.prof);
     if (ev1) hipEventRecord(ev1, s);
-    IPC_LAUNCH(k_pcg_update<float>, B.n_vt, TB, s)(W, E, S, B.vtiles, L.part_a, rz_old, rz_new, rr_new, W.p32, W.r32,
+    IPC_LAUNCH(k_pcg_update<float>, n_tiles, TB, s)(W, E, S, tiles, L.part_a, rz_old, rz_new, rr_new, W.p32, W.r32,
                                               W.z32, W.pp32, W.q32, W.Minv32);
-    IPC_LAUNCH(k_pcg_dir<float>, B.n_vt, TB, s)(W, E, S, B.vtiles, rz_old, rz_new, rr_new, W.pp32, W.z32, pending, cap);
+    IPC_LAUNCH(k_pcg_dir<float>, n_tiles, TB, s)(W, E, S, tiles, rz_old, rz_new, rr_new, W.pp32, W.z32, pending, cap);
   }
 }
 
