@@ -7,6 +7,13 @@ soft superquadric objects (tet count lognormal, median 5k, clipped to
 time step of every environment; the metric is converged environment-steps per
 second.  Inputs are seeded synthetic scenes shaped like the paper's grasp
 validations (Sec. III-D); they are resident in device memory before timing.
+
+The same scenes are run with FP64 PCG and with mixed precision (FP32 PCG
+matrix/vectors, FP64 dot products; everything else FP64).  `value` is the
+mixed-precision throughput; the FP64 figure is reported beside it.  The
+paper's speedup notion (N environments batched vs the same N run one after
+another, Sec. IV-A) is reported as context from a sequential single-environment
+run on the same GPU.
 """
 from __future__ import annotations
 
@@ -15,8 +22,6 @@ import json
 import os
 import sys
 import time
-
-import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -41,27 +46,48 @@ def make_scenes(workload: str, n_envs: int):
     raise SystemExit(f"unknown workload {workload}")
 
 
-def run_gpu(scs, precision, warmup, steps, pcg_tol):
+def run_gpu(scs, precision, warmup, steps, pcg_tol, label):
+    import torch
     t0 = time.time()
     gs = [G.ipc_create_scene(sc, precision=precision, pcg_rel_tol=pcg_tol) for sc in scs]
-    log(f"created {len(gs)} scenes in {time.time() - t0:.1f}s")
+    log(f"[{label}] created {len(gs)} scenes in {time.time() - t0:.1f}s")
     for k in range(warmup):
         rc, infos = G.ipc_step_batch(gs, 1)
-        log(f"warmup step {k}: rc={rc} newton(max)={max(i['max_newton_iters'] for i in infos)}")
+        log(f"[{label}] warmup step {k}: newton(max)={max(i['max_newton_iters'] for i in infos)}")
+    torch.cuda.synchronize()
     G.ipc_prof_reset()
     t0 = time.perf_counter()
-    converged = 0
-    newton = pcg = 0
+    converged = newton = pcg = 0
     for k in range(steps):
         rc, infos = G.ipc_step_batch(gs, 1)
-        converged += sum(i["steps_done"] for i in infos)
+        done = sum(i["steps_done"] for i in infos)
+        converged += done
         newton += sum(i["newton_iters"] for i in infos)
         pcg += sum(i["pcg_iters"] for i in infos)
-        log(f"timed step {k}: rc={rc} done={sum(i['steps_done'] for i in infos)}")
+        log(f"[{label}] timed step {k}: converged {done}/{len(gs)}")
+    torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     prof = G.ipc_prof_read()
     failed = sum(1 for g in gs if G.ipc_scene_sizes(g)[6])
-    return dict(wall=wall, converged=converged, newton=newton, pcg=pcg, prof=prof, failed=failed, gs=gs)
+    for g in gs:
+        G.ipc_destroy_scene(g)
+    return dict(wall=wall, converged=converged, newton=newton, pcg=pcg, prof=prof, failed=failed,
+                value=converged / wall, ms_per_step=1e3 * wall / steps)
+
+
+def sequential_gpu(scs, precision, warmup, steps, pcg_tol, n):
+    """The same environments run one after another (the paper's baseline for its speedup)."""
+    done = 0
+    wall = 0.0
+    for sc in scs[:n]:
+        g = G.ipc_create_scene(sc, precision=precision, pcg_rel_tol=pcg_tol)
+        G.ipc_step(g, warmup)
+        t0 = time.perf_counter()
+        rc, info = G.ipc_step(g, steps)
+        wall += time.perf_counter() - t0
+        done += info["steps_done"]
+        G.ipc_destroy_scene(g)
+    return dict(value=done / wall, envs=n)
 
 
 def cpu_baseline(scs, budget_s=20.0):
@@ -79,8 +105,20 @@ def cpu_baseline(scs, budget_s=20.0):
             done += 1
         env += 1
     wall = time.perf_counter() - t_start
-    return dict(value=done / wall, unit="converged env-steps/s", cores=1, kind="oracle",
-                sample=f"{done} env-steps of environments 0..{env - 1} from step 0, one thread, {wall:.1f}s")
+    return dict(value=round(done / wall, 3), unit="converged env-steps/s", cores=1, kind="oracle",
+                sample=f"{done} env-steps of environment(s) 0..{env - 1} from step 0 (contact from step ~12), "
+                       f"one thread, {wall:.1f}s")
+
+
+def roofline(prof):
+    if prof["spmv_launches"] <= 0 or prof["spmv_ms"] <= 0:
+        return None
+    avg_ms = prof["spmv_ms"] / prof["spmv_launches"]
+    bytes_per_launch = prof["spmv_bytes"] / prof["spmv_launches"]
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_spmv",
+            "avg_launch_us": round(avg_ms * 1e3, 2), "bytes_per_launch": int(bytes_per_launch)}
 
 
 def main():
@@ -90,8 +128,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=12)
     ap.add_argument("--envs", type=int, default=256)
     ap.add_argument("--workload", default="superquadric_batch")
-    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--precision", choices=["fp64", "mixed", "both"], default="both")
     ap.add_argument("--pcg-tol", type=float, default=1e-4)
+    ap.add_argument("--sequential-envs", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -104,42 +143,49 @@ def main():
     scs = make_scenes(args.workload, args.envs)
     ntets = sum(len(sc["E"]) for sc in scs)
     log(f"workload {args.workload}: {len(scs)} envs, {ntets} tets")
-    prec = G.IPC_MIXED if args.precision == "mixed" else G.IPC_FP64
     G.ipc_prof_enable(1)
-    torch.cuda.synchronize()
-    r = run_gpu(scs, prec, args.warmup, args.steps, args.pcg_tol)
-    value = r["converged"] / r["wall"]
-    prof = r["prof"]
-    roof = None
-    if prof["spmv_launches"] > 0 and prof["spmv_ms"] > 0:
-        avg_ms = prof["spmv_ms"] / prof["spmv_launches"]
-        bytes_per_launch = prof["spmv_bytes"] / prof["spmv_launches"]
-        achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_spmv",
-                "avg_launch_us": round(avg_ms * 1e3, 2), "bytes_per_launch": int(bytes_per_launch)}
+    results = {}
+    precs = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
+    for p in precs:
+        results[p] = run_gpu(scs, G.IPC_MIXED if p == "mixed" else G.IPC_FP64, args.warmup, args.steps,
+                             args.pcg_tol, p)
+        log(f"[{p}] {results[p]['value']:.1f} converged env-steps/s, {results[p]['ms_per_step']:.1f} ms/step")
+    main_p = "mixed" if "mixed" in results else precs[0]
+    r = results[main_p]
+    seq = None
+    if args.sequential_envs > 0:
+        seq = sequential_gpu(scs, G.IPC_MIXED if main_p == "mixed" else G.IPC_FP64, args.warmup, args.steps,
+                             args.pcg_tol, min(args.sequential_envs, len(scs)))
+        log(f"sequential single-env: {seq['value']:.2f} env-steps/s")
     cpu = None if args.no_cpu_baseline else cpu_baseline(scs)
     out = {
         "metric": "converged sim steps/s over batched scenes",
-        "value": round(value, 2),
+        "value": round(r["value"], 2),
         "unit": "converged env-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(1e3 * r["wall"] / args.steps, 2),
+        "ms_per_step": round(r["ms_per_step"], 2),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if prec == G.IPC_FP64 else "f64+f32pcg",
+        "dtype": "f64+f32pcg" if main_p == "mixed" else "f64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "envs": len(scs), "tets": ntets, "precision": args.precision,
+        "config": {"workload": args.workload, "envs": len(scs), "tets": ntets, "precision": main_p,
                    "pcg_rel_tol": args.pcg_tol, "first_timed_step": args.warmup},
         "newton_iters": r["newton"],
         "pcg_iters": r["pcg"],
         "failed_envs": r["failed"],
-        "roofline": roof,
+        "roofline": roofline(r["prof"]),
         "cpu_baseline": cpu,
     }
+    if "fp64" in results and main_p != "fp64":
+        f = results["fp64"]
+        out["fp64"] = {"value": round(f["value"], 2), "ms_per_step": round(f["ms_per_step"], 2),
+                       "failed_envs": f["failed"], "roofline": roofline(f["prof"])}
+    if seq:
+        out["sequential_single_env"] = {"value": round(seq["value"], 3), "envs": seq["envs"],
+                                        "speedup_batched_vs_sequential": round(r["value"] / seq["value"], 2)}
     print(json.dumps(out), flush=True)
 
 
