@@ -715,9 +715,16 @@ struct Scene {
   bool ctx = false;
   std::vector<double> xn, xhat, xbar;
   std::vector<FricPair> fric;
+  // augmented-Lagrangian Dirichlet mode (kinematic vertices are unknowns)
+  double mbar = 0.0;  // mean free-vertex mass
+  bool al = false;
+  double kA = 0.0, w_al = 0.0, viol_prev = 0.0;
+  std::vector<double> Lam;
 };
 
 bool is_kin(const Scene &s, int i) { return s.kin[i] >= 0; }
+// unknowns of the Newton solve: free vertices, plus kinematic ones in AL mode
+bool is_dof(const Scene &s, int i) { return !is_kin(s, i) || s.al; }
 
 void gather12(const std::vector<double> &x, const int v[4], double out[12]) {
   for (int i = 0; i < 4; ++i)
@@ -914,11 +921,18 @@ int build_scene(const ipco_desc *d, Scene **out) {
     double m = d->rho[e] * s->vol[e] / 4.0;
     for (int k = 0; k < 4; ++k) s->mass[s->tet[4 * e + k]] += m;
   }
-  for (int i = 0; i < s->nv; ++i)
+  int nfree = 0;
+  for (int i = 0; i < s->nv; ++i) {
     if (!is_kin(*s, i) && !(s->mass[i] > 0.0)) {
       delete s;
       return fail(E_ARG, "free vertex without mass");
     }
+    if (!is_kin(*s, i)) {
+      s->mbar += s->mass[i];
+      ++nfree;
+    }
+  }
+  s->mbar = nfree > 0 ? s->mbar / nfree : 1.0;
   // Surface: tet faces used by exactly one tet, plus the kinematic triangles.
   // Canonical form: triangle vertices ascending, list sorted; edges (min,max).
   std::map<std::array<int, 3>, int> faces;
@@ -1021,6 +1035,19 @@ double energy(const Scene &s, const std::vector<double> &x) {
     }
     Ein += s.mass[i] * q / (2.0 * h2);
   }
+  // AL penalty on the prescribed vertices:
+  //   sum_K  kA w/2 |x - xbar|^2 - sqrt(w) Lam . (x - xbar)
+  if (s.al)
+    for (int i = 0; i < s.nv; ++i) {
+      if (!is_kin(s, i)) continue;
+      double q = 0.0, l = 0.0;
+      for (int k = 0; k < 3; ++k) {
+        double r = x[3 * i + k] - s.xbar[3 * i + k];
+        q += r * r;
+        l += s.Lam[3 * i + k] * r;
+      }
+      Ein += 0.5 * s.kA * s.w_al * q - std::sqrt(s.w_al) * l;
+    }
   double Eel = 0.0;
   for (int e = 0; e < s.nt; ++e) {
     double xe[12], en;
@@ -1067,14 +1094,14 @@ struct BlockMat {
 void add_element(const Scene &s, const int v[4], const double g[12], const double H[144], std::vector<double> &G,
                  std::vector<double> *Gabs, BlockMat *M) {
   for (int a = 0; a < 4; ++a) {
-    if (is_kin(s, v[a])) continue;
+    if (!is_dof(s, v[a])) continue;
     for (int k = 0; k < 3; ++k) {
       G[3 * v[a] + k] += g[3 * a + k];
       if (Gabs) (*Gabs)[3 * v[a] + k] += std::fabs(g[3 * a + k]);
     }
     if (!M) continue;
     for (int b = 0; b < 4; ++b) {
-      if (is_kin(s, v[b])) continue;
+      if (!is_dof(s, v[b])) continue;
       double blk[9];
       for (int r = 0; r < 3; ++r)
         for (int c = 0; c < 3; ++c) blk[r * 3 + c] = H[(3 * a + r) * 12 + 3 * b + c];
@@ -1102,6 +1129,20 @@ bool grad_hess(const Scene &s, const std::vector<double> &x, std::vector<double>
       M->add(i, i, blk, 1.0);
     }
   }
+  if (s.al)
+    for (int i = 0; i < s.nv; ++i) {
+      if (!is_kin(s, i)) continue;
+      double w = s.kA * s.w_al, sw = std::sqrt(s.w_al);
+      for (int k = 0; k < 3; ++k) {
+        double gi = w * (x[3 * i + k] - s.xbar[3 * i + k]) - sw * s.Lam[3 * i + k];
+        G[3 * i + k] += gi;
+        if (Gabs) (*Gabs)[3 * i + k] += std::fabs(gi);
+      }
+      if (M) {
+        double blk[9] = {w, 0, 0, 0, w, 0, 0, 0, w};
+        M->add(i, i, blk, 1.0);
+      }
+    }
   for (int e = 0; e < s.nt; ++e) {
     double xe[12], en, g[12], H[144];
     gather12(x, &s.tet[4 * e], xe);
@@ -1167,7 +1208,7 @@ Csr to_csr(const Scene &s, const BlockMat &M, std::vector<int> &dof_of, std::vec
   dof_of.assign(s.nv, -1);
   vert_of.clear();
   for (int i = 0; i < s.nv; ++i)
-    if (!is_kin(s, i)) {
+    if (is_dof(s, i)) {
       dof_of[i] = (int)vert_of.size();
       vert_of.push_back(i);
     }
@@ -1387,11 +1428,29 @@ int begin_step(Scene &s, std::vector<double> &x0) {
         if (dp[3 * i + k] != 0.0) any = true;
       }
   s.ctx = true;
-  if (any) {
-    if (ccd_bound(s, s.xn, dp) < 1.0 || !all_tets_positive(s, y)) return FAIL_DBC;
+  s.al = false;
+  if (any && (ccd_bound(s, s.xn, dp) < 1.0 || !all_tets_positive(s, y))) {
+    // the prescribed move is not feasible in one go: the kinematic vertices
+    // become unknowns pulled to their targets by an augmented Lagrangian
+    s.al = true;
+    s.kA = 1e3;
+    s.w_al = s.mbar / (h * h);
+    s.viol_prev = kInf;
+    s.Lam.assign(3 * s.nv, 0.0);
+    x0 = s.xn;
+    return FAIL_NONE;
   }
   x0 = y;
   return FAIL_NONE;
+}
+
+// Largest distance of a prescribed vertex from its target (AL mode).
+double dbc_violation(const Scene &s, const std::vector<double> &x) {
+  double v = 0.0;
+  for (int i = 0; i < s.nv; ++i)
+    if (is_kin(s, i))
+      for (int k = 0; k < 3; ++k) v = std::max(v, std::fabs(x[3 * i + k] - s.xbar[3 * i + k]));
+  return v;
 }
 
 void min_dist(const Scene &s, const std::vector<double> &x, double *dmin, long *nact) {
@@ -1435,8 +1494,35 @@ int step_one(Scene &s, ipco_info *info) {
     double pinf = 0.0;
     for (double v : p) pinf = std::max(pinf, std::fabs(v));
     if (pinf <= tolh) {
-      converged = true;
-      break;
+      if (!s.al) {
+        converged = true;
+        break;
+      }
+      // AL mode: the inner problem converged.  Snap to the targets once they
+      // are within 1e-2 dhat and the move is CCD-safe; otherwise update the
+      // multipliers (and double kA unless the violation fell tenfold).
+      double viol = dbc_violation(s, x);
+      if (viol <= 1e-2 * s.dhat) {
+        std::vector<double> dp(3 * s.nv, 0.0), y = x;
+        for (int i = 0; i < s.nv; ++i)
+          if (is_kin(s, i))
+            for (int k = 0; k < 3; ++k) {
+              dp[3 * i + k] = s.xbar[3 * i + k] - x[3 * i + k];
+              y[3 * i + k] = s.xbar[3 * i + k];
+            }
+        if (ccd_bound(s, x, dp) >= 1.0 && all_tets_positive(s, y)) {
+          x = y;
+          s.al = false;
+          continue;
+        }
+      }
+      double sw = std::sqrt(s.w_al);
+      for (int i = 0; i < s.nv; ++i)
+        if (is_kin(s, i))
+          for (int k = 0; k < 3; ++k) s.Lam[3 * i + k] -= s.kA * sw * (x[3 * i + k] - s.xbar[3 * i + k]);
+      if (viol > 0.1 * s.viol_prev) s.kA *= 2.0;
+      s.viol_prev = viol;
+      continue;
     }
     double alpha = ccd_bound(s, x, p);
     double E0 = energy(s, x);
@@ -1667,7 +1753,7 @@ int ipco_hessian_dense(void *h, const double *x, double *H) {
   long N = 3L * s->nv;
   std::fill(H, H + N * N, 0.0);
   for (int i = 0; i < s->nv; ++i)
-    if (is_kin(*s, i))
+    if (!is_dof(*s, i))
       for (int k = 0; k < 3; ++k) H[(3 * i + k) * N + 3 * i + k] = 1.0;
   for (auto &kv : M.b)
     for (int r = 0; r < 3; ++r)

@@ -153,6 +153,7 @@ struct HostScene {
   std::vector<double> motion;  // motion rows then gravity rows
   int n_groups = 0, n_motion = 0;
   double cell = 0.0;  // hash-grid cell size
+  double mbar = 1.0;  // mean free-vertex mass
   double dt, dhat, kappa, mu_f, eps_v, tol, pcg_tol;
   int maxit, precision;
 };
@@ -344,10 +345,15 @@ std::unique_ptr<HostScene> preprocess(const ipc_scene_desc *d) {
                        Ds[i * 3 + 2] * H.Dinv[9 * e + 6 + j];
     if (!(det3h(F) > 0.0)) throw ApiError(IPC_E_INVERTED, "inverted tet in the initial configuration");
   }
+  double msum = 0.0;
   for (int i = 0; i < H.nv; ++i) {
     if (H.kin[i] < 0 && !(H.mass[i] > 0.0)) throw ApiError(IPC_E_ARG, "free vertex without mass");
-    if (H.kin[i] < 0) ++H.n_free;
+    if (H.kin[i] < 0) {
+      ++H.n_free;
+      msum += H.mass[i];
+    }
   }
+  H.mbar = H.n_free > 0 ? msum / H.n_free : 1.0;
   // surface: boundary faces (used by one tet) + kinematic triangles, each with
   // ascending vertex ids, list sorted lexicographically; edges (min,max) sorted
   {
@@ -606,6 +612,7 @@ struct World {
     reg(aV, (void **)&W.mass, 8);
     reg(aV, (void **)&W.Minv, 72);
     reg(aV, (void **)&W.e_v, 8);
+    reg(aV, (void **)&W.lam, 24);
     reg(aV, (void **)&W.r32, 12);
     reg(aV, (void **)&W.z32, 12);
     reg(aV, (void **)&W.pp32, 12);
@@ -648,9 +655,11 @@ struct World {
                  (void **)&S.ls_done,  (void **)&S.ls_cnt,   (void **)&S.pcg_done, (void **)&S.pcg_it,
                  (void **)&S.dbc_bad,  (void **)&S.cand_beg, (void **)&S.cand_end, (void **)&S.act_beg,
                  (void **)&S.act_end,  (void **)&S.fric_beg, (void **)&S.fric_end, (void **)&S.in_step,
-                 (void **)&S.big_beg,  (void **)&S.big_end};
+                 (void **)&S.big_beg,  (void **)&S.big_end,  (void **)&S.al,       (void **)&S.al_action,
+                 (void **)&S.snap_bad};
     state_ll = {(void **)&S.pcg_total, (void **)&S.amax_bits};
-    state_dbl = {(void **)&S.alpha, (void **)&S.E0, (void **)&S.E1, (void **)&S.pinf, (void **)&S.pcg_bb};
+    state_dbl = {(void **)&S.alpha, (void **)&S.E0,  (void **)&S.E1,       (void **)&S.pinf,
+                 (void **)&S.pcg_bb, (void **)&S.kA, (void **)&S.viol, (void **)&S.viol_prev};
   }
 
   void ensure_envs(size_t n) {
@@ -746,6 +755,7 @@ struct World {
     HC(hipMemsetAsync(W.p + 3 * vo, 0, 24 * R.v_n, stream));
     HC(hipMemsetAsync(W.pp + 3 * vo, 0, 24 * R.v_n, stream));
     HC(hipMemsetAsync(W.pp32 + 3 * vo, 0, 12 * R.v_n, stream));
+    HC(hipMemsetAsync(W.lam + 3 * vo, 0, 24 * R.v_n, stream));
     std::vector<int> vt(H.vt_ent.size());
     for (size_t i = 0; i < vt.size(); ++i) vt[i] = (H.vt_ent[i] >> 2) * 4 + (int)to * 4 + (H.vt_ent[i] & 3);
     up(W.vt_ent + R.vt_off, vt.data(), vt.size());
@@ -820,6 +830,7 @@ struct World {
     E.tol = H.tol;
     E.pcg_tol = H.pcg_tol;
     E.cell = H.cell;
+    E.mbar = H.mbar;
     upload_env(slot);
     int zero = 0;
     HC(hipMemcpyAsync(S.status + slot, &zero, 4, hipMemcpyHostToDevice, stream));
@@ -1101,10 +1112,10 @@ struct World {
     ipck::friction_elems(stream, W, envs_d, S, L, n_fric, na, W.x);
     int nce = na + n_fric;
     int nvw = (int)aV.cap;
-    ipck::incidence(stream, W, L, nce, nvw, nullptr);
+    ipck::incidence(stream, W, S, L, nce, nvw);
     int ntot = read_int(L.inc_off + nvw);
     if (inc_ent.ensure(ntot + 1)) refresh_lists();
-    ipck::incidence_fill(stream, W, L, nce, nvw);
+    ipck::incidence_fill(stream, W, S, L, nce, nvw);
     ipck::elastic(stream, W, envs_d, S, B);
     ipck::assemble(stream, W, envs_d, S, B, L, mixed);
     return na;
@@ -1120,6 +1131,17 @@ struct World {
       t = (e && e[0] && e[0] != '0') ? 1 : 0;
     }
     return t == 1;
+  }
+
+  // live vertex tiles at or below which the tiled PCG hands the remaining
+  // environments to one workgroup each (IPC_TAIL_TILES, default 128; 0 = never)
+  static int tail_tiles() {
+    static int t = -1;
+    if (t < 0) {
+      const char *e = std::getenv("IPC_TAIL_TILES");
+      t = (e && e[0]) ? std::max(0, std::atoi(e)) : 128;
+    }
+    return t;
   }
 
   long long solve(int mixed) {
@@ -1161,6 +1183,12 @@ struct World {
         ntl = read_int(live_offs.p + B.n_vt);
         tl = live_d.p;
         last_pending = pend;
+        if (ntl <= tail_tiles()) {
+          // few tiles left: their launches would be latency-bound, so one
+          // workgroup per environment finishes the solves in one launch
+          ipck::pcg_resume(stream, W, envs_d, S, L, tl, ntl, it, cap, mixed);
+          break;
+        }
       }
     }
     ipck::pcg_finish(stream, W, S, B, mixed);
@@ -1215,9 +1243,11 @@ struct World {
         std::fprintf(stderr, "[ipc] newton %d: active pairs %d friction %d pcg %lld envs-left %d  %.1f ms\n", it, na,
                      n_fric, pit, still, ms());
       if (still == 0) break;
+      ipck::al_prepare(stream, W, S, B);
       int ns = broad_phase(W.x, W.p);
       ipck::ccd_init(stream, S, B);
       ipck::accd(stream, W, envs_d, S, L, ns, W.x, W.p);
+      ipck::snap_J(stream, W, S, B);
       ipck::ls_init(stream, S, B);
       ipck::energy(stream, W, envs_d, S, B, L, ns, n_fric, 1, S.E0);
       int trials = 0;
@@ -1228,6 +1258,7 @@ struct World {
         if (read_int(L.counter + 2) == 0) break;
       }
       if (tracing()) std::fprintf(stderr, "[ipc]   swept %d line-search trials %d  %.1f ms\n", ns, trials, ms());
+      ipck::al_finish(stream, W, envs_d, S, B);
       ipck::update_x(stream, W, S, B);
       ipck::iter_end(stream, envs_d, S, B, L.counter + 3);
       if (read_int(L.counter + 3) == 0) break;
@@ -1685,8 +1716,6 @@ int ipc_debug_begin_step(ipc_scene s, double *x_start) {
       ipck::dbc_check_J(w.stream, w.W, w.envs_d, w.S, w.B);
       ipck::env_dbc(w.stream, w.S, w.B);
       ipck::apply_dbc(w.stream, w.W, w.envs_d, w.S, w.B);
-      EnvSnapshot e = snapshot(w, s->slot);
-      if (e.status == ipcw::ST_FAILED) throw ApiError(IPC_E_FAILED, "direct Dirichlet move is not feasible");
       if (x_start) get_x(w, s, w.W.x, x_start);
     }
     return IPC_OK;

@@ -74,8 +74,8 @@ void barrier_elems(hipStream_t s, const WorldDev &W, const EnvDev *E, const List
 void friction_setup(hipStream_t s, const WorldDev &W, const EnvDev *E, const Lists &L, int n_act);
 void friction_elems(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Lists &L, int n_fric,
                     int ce_off, const double *x);
-void incidence(hipStream_t s, const WorldDev &W, Lists &L, int n_ce, int nv_world, int *total_out_dev);
-void incidence_fill(hipStream_t s, const WorldDev &W, Lists &L, int n_ce, int nv_world);
+void incidence(hipStream_t s, const WorldDev &W, const EnvState &S, Lists &L, int n_ce, int nv_world);
+void incidence_fill(hipStream_t s, const WorldDev &W, const EnvState &S, Lists &L, int n_ce, int nv_world);
 
 void elastic(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B);
 void assemble(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, const Lists &L,
@@ -87,6 +87,10 @@ void pcg_iter(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState 
               int *pending, int mixed, int cap, hipEvent_t ev0, hipEvent_t ev1, const Tile *tiles, int n_tiles);
 // tiles of environments whose PCG still iterates -> out (count at offs[B.n_vt])
 void live_tiles(hipStream_t s, const EnvState &S, const Batch &B, Lists &L, Tile *out, int *flag, int *offs);
+// continues the PCG of the environments whose tiles are listed (one workgroup
+// each) to convergence; `it` = tiled iterations done so far
+void pcg_resume(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, Lists &L, const Tile *tiles,
+                int n_tiles, int it, int cap, int mixed);
 void pcg_finish(hipStream_t s, const WorldDev &W, const EnvState &S, const Batch &B, int mixed);
 // one workgroup per environment for the environments flagged `fused`
 void pcg_fused(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const int *fenv, int n_fenv,
@@ -96,6 +100,12 @@ void spmv_debug(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvStat
 
 void conv_check(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L,
                 int *n_active);
+// augmented-Lagrangian Dirichlet mode: after the convergence test, set the
+// displacement to check (snap) / zero (multiplier update); after the swept CCD
+// pass, accept the snap or update multipliers and kA
+void al_prepare(hipStream_t s, const WorldDev &W, const EnvState &S, const Batch &B);
+void snap_J(hipStream_t s, const WorldDev &W, const EnvState &S, const Batch &B);
+void al_finish(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B);
 void ccd_init(hipStream_t s, const EnvState &S, const Batch &B);
 void accd(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Lists &L, int n,
           const double *x, const double *p);

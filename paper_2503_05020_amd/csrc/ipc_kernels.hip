@@ -95,6 +95,13 @@ DEV void gather12_trial(const double *x, const double *p, double a, const int v[
 
 DEV bool active_env(const EnvState &S, int env) { return S.status[env] == ST_ACTIVE; }
 
+// unknowns of the Newton solve: free vertices, plus the kinematic vertices of
+// an environment in augmented-Lagrangian Dirichlet mode
+DEV bool is_dof(const WorldDev &W, const EnvState &S, int i, int env) {
+  int k = W.kin[i];
+  return k == KIN_FREE || (k >= 0 && S.al[env]);
+}
+
 // ---------------------------------------------------------------------------
 // step set-up: kinematic targets, predicted positions, Dirichlet displacement
 // ---------------------------------------------------------------------------
@@ -151,6 +158,10 @@ __global__ void k_apply_dbc(WorldDev W, EnvState S, const Tile *tiles) {
   if ((int)threadIdx.x >= t.count || !active_env(S, t.env)) return;
   int i = t.start + threadIdx.x;
   if (W.kin[i] < 0) return;
+  if (S.al[t.env]) {
+    for (int c = 0; c < 3; ++c) W.lam[3 * i + c] = 0.0;  // multipliers start at zero
+    return;
+  }
   for (int c = 0; c < 3; ++c) W.x[3 * i + c] = W.xh[3 * i + c];
 }
 
@@ -167,6 +178,8 @@ __global__ void k_env_begin(EnvState S, const int *envs, int n) {
   S.halvings[e] = 0;
   S.pcg_total[e] = 0;
   S.dbc_bad[e] = 0;
+  S.al[e] = 0;
+  S.al_action[e] = 0;
   S.amax_bits[e] = (unsigned long long)__double_as_longlong(1.0);
 }
 
@@ -177,8 +190,11 @@ __global__ void k_env_dbc(EnvState S, const int *envs, int n) {
   if (S.status[e] != ST_ACTIVE) return;
   double a = __longlong_as_double((long long)S.amax_bits[e]);
   if (a < 1.0 || S.dbc_bad[e]) {
-    S.status[e] = ST_FAILED;
-    S.reason[e] = FAIL_DBC;
+    // the prescribed move is not feasible in one go: the kinematic vertices
+    // become unknowns pulled to their targets by an augmented Lagrangian
+    S.al[e] = 1;
+    S.kA[e] = 1e3;
+    S.viol_prev[e] = kInf;
   }
 }
 
@@ -321,9 +337,9 @@ __global__ void __launch_bounds__(256) k_bp(WorldDev W, const EnvDev *envs, EnvS
 // cells per axis; larger boxes go to a per-environment "big" list).  A query
 // primitive visits the cells its box covers and reports a pair only from the
 // cell that holds the lower corner of the two boxes' intersection, so every
-// overlapping pair is found exactly once; buckets are sorted, so the order of
-// the output is deterministic.  The result is the same set as testing all
-// pairs.
+// overlapping pair is found exactly once; each query sorts its own hits, so
+// the order of the output is deterministic.  The result is the same set as
+// testing all pairs.
 // ---------------------------------------------------------------------------
 constexpr int kMaxSpan = 4;
 
@@ -407,27 +423,6 @@ __global__ void k_grid_place(const int4 *ent, const int *ebucket, int n, const i
   sorted[boff[h] + atomicAdd(&bcur[h], 1)] = ent[k];
 }
 
-DEV bool ent_less(int4 a, int4 b) {
-  if (a.x != b.x) return a.x < b.x;
-  if (a.y != b.y) return a.y < b.y;
-  if (a.z != b.z) return a.z < b.z;
-  return a.w < b.w;
-}
-
-__global__ void k_grid_sort(const int *boff, int4 *sorted, int nb) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nb) return;
-  int b = boff[i], e = boff[i + 1];
-  for (int j = b + 1; j < e; ++j) {
-    int4 key = sorted[j];
-    int m = j - 1;
-    while (m >= b && ent_less(key, sorted[m])) {
-      sorted[m + 1] = sorted[m];
-      --m;
-    }
-    sorted[m + 1] = key;
-  }
-}
 
 __global__ void k_big_seg(const EnvDev *envs, EnvState S, const int *benv, int n, const int *bigoff) {
   int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -531,6 +526,20 @@ __global__ void __launch_bounds__(256) k_bp_grid(WorldDev W, const EnvDev *envs,
             ++cnt;
           }
         }
+    if (WRITE) {
+      // bucket order depends on atomics: put this query's cell hits in
+      // candidate-index order so the output is deterministic
+      int p0 = offs[item];
+      for (int j = p0 + 1; j < pos; ++j) {
+        int2 key = out[j];
+        int m = j - 1;
+        while (m >= p0 && out[m].y > key.y) {
+          out[m + 1] = out[m];
+          --m;
+        }
+        out[m + 1] = key;
+      }
+    }
     for (int j = S.big_beg[t.env]; j < S.big_end[t.env]; ++j) {
       int code = bigl[j];
       if ((kind == 0) != (code >= 0)) continue;
@@ -763,22 +772,22 @@ __global__ void k_friction_elems(WorldDev W, const EnvDev *envs, EnvState S, con
 // ---------------------------------------------------------------------------
 // vertex -> contact element incidence (free vertices only), sorted per vertex
 // ---------------------------------------------------------------------------
-__global__ void k_inc_count(WorldDev W, const int4 *ce_v, int n, int *cnt) {
+__global__ void k_inc_count(WorldDev W, EnvState S, const int4 *ce_v, int n, int *cnt) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   int4 q = ce_v[k];
   int v[4] = {q.x, q.y, q.z, q.w};
   for (int a = 0; a < 4; ++a)
-    if (W.kin[v[a]] == KIN_FREE) atomicAdd(&cnt[v[a]], 1);
+    if (is_dof(W, S, v[a], W.venv[v[a]])) atomicAdd(&cnt[v[a]], 1);
 }
 
-__global__ void k_inc_fill(WorldDev W, const int4 *ce_v, int n, const int *off, int *cur, int *ent) {
+__global__ void k_inc_fill(WorldDev W, EnvState S, const int4 *ce_v, int n, const int *off, int *cur, int *ent) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   int4 q = ce_v[k];
   int v[4] = {q.x, q.y, q.z, q.w};
   for (int a = 0; a < 4; ++a)
-    if (W.kin[v[a]] == KIN_FREE) {
+    if (is_dof(W, S, v[a], W.venv[v[a]])) {
       int pos = atomicAdd(&cur[v[a]], 1);
       ent[off[v[a]] + pos] = 4 * k + a;
     }
@@ -838,10 +847,16 @@ __global__ void k_assemble_rows(WorldDev W, const EnvDev *envs, EnvState S, cons
   int k = W.kin[i];
   double g[3] = {0, 0, 0};
   double D[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1}, Mi[9];
-  if (k == KIN_FREE) {
-    double w = W.mass[i] / (E.dt * E.dt);
-    for (int c = 0; c < 3; ++c) g[c] = w * (W.x[3 * i + c] - W.xh[3 * i + c]);
-    for (int r = 0; r < 9; ++r) D[r] = (r % 4 == 0) ? w : 0.0;
+  if (is_dof(W, S, i, t.env)) {
+    if (k == KIN_FREE) {  // inertia
+      double w = W.mass[i] / (E.dt * E.dt);
+      for (int c = 0; c < 3; ++c) g[c] = w * (W.x[3 * i + c] - W.xh[3 * i + c]);
+      for (int r = 0; r < 9; ++r) D[r] = (r % 4 == 0) ? w : 0.0;
+    } else {  // AL penalty kA w/2 |x - xbar|^2 - sqrt(w) lam.(x - xbar), w = mbar/dt^2
+      double w0 = E.mbar / (E.dt * E.dt), w = S.kA[t.env] * w0, sw = sqrt(w0);
+      for (int c = 0; c < 3; ++c) g[c] = w * (W.x[3 * i + c] - W.xh[3 * i + c]) - sw * W.lam[3 * i + c];
+      for (int r = 0; r < 9; ++r) D[r] = (r % 4 == 0) ? w : 0.0;
+    }
     for (int j = W.vt_beg[i]; j < W.vt_end[i]; ++j) {
       int ent = W.vt_ent[j];
       int te = ent >> 2, a = ent & 3;
@@ -872,15 +887,17 @@ __global__ void k_assemble_sell(WorldDev W, const EnvDev *envs, EnvState S, cons
   int sl = i / kSlice, lane = i % kSlice;
   int base = W.slice_pos[sl], wdt = W.slice_w[sl];
   int kr = W.kin[i];
-  double w = (kr == KIN_FREE) ? W.mass[i] / (E.dt * E.dt) : 0.0;
+  bool rdof = is_dof(W, S, i, t.env);
+  double w = (kr == KIN_FREE) ? W.mass[i] / (E.dt * E.dt)
+                              : (rdof ? S.kA[t.env] * E.mbar / (E.dt * E.dt) : 0.0);
   for (int k = 0; k < wdt; ++k) {
     int pos = base + k * kSlice + lane;
     int col = W.col[pos];
     double B[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    if (kr != KIN_FREE) {
+    if (!rdof) {
       if (k == 0)
         for (int r = 0; r < 9; ++r) B[r] = (r % 4 == 0) ? 1.0 : 0.0;
-    } else if (W.kin[col] == KIN_FREE) {
+    } else if (is_dof(W, S, col, t.env)) {
       for (int j = W.cb_beg[pos]; j < W.cb_end[pos]; ++j) {
         int c = W.contrib[j];
         int te = c >> 5, bi = (c >> 1) & 15, tr = c & 1;
@@ -978,7 +995,7 @@ __global__ void k_pcg_init(WorldDev W, const EnvDev *envs, EnvState S, const Til
   double rz = 0.0, rr = 0.0;
   if ((int)threadIdx.x < t.count) {
     double r[3], z[3];
-    bool fr = W.kin[i] == KIN_FREE;
+    bool fr = is_dof(W, S, i, t.env);
     for (int c = 0; c < 3; ++c) r[c] = fr ? -W.g[3 * i + c] : 0.0;
     const double *M = W.Minv + 9 * (size_t)i;
     for (int c = 0; c < 3; ++c) z[c] = fr ? M[3 * c] * r[0] + M[3 * c + 1] * r[1] + M[3 * c + 2] * r[2] : 0.0;
@@ -1008,7 +1025,7 @@ __global__ void k_pcg_init32(WorldDev W, const EnvDev *envs, EnvState S, const T
   double rz = 0.0, rr = 0.0;
   if ((int)threadIdx.x < t.count) {
     float r[3], z[3];
-    bool fr = W.kin[i] == KIN_FREE;
+    bool fr = is_dof(W, S, i, t.env);
     for (int c = 0; c < 3; ++c) r[c] = fr ? (float)(-W.g[3 * i + c]) : 0.0f;
     const float *M = W.Minv32 + 9 * (size_t)i;
     for (int c = 0; c < 3; ++c) z[c] = fr ? M[3 * c] * r[0] + M[3 * c + 1] * r[1] + M[3 * c + 2] * r[2] : 0.0f;
@@ -1194,6 +1211,61 @@ DEV void block_sum2(double &a, double &b, double (*sh)[FB / 64]) {
   __syncthreads();
 }
 
+// PCG iterations of environment e by one workgroup, from the state (p, r, z,
+// pp, rz) until the relative residual reaches the tolerance, a non-finite
+// value appears or the iteration count reaches cap.  Returns the count.
+template <typename T>
+DEV int fused_iterate(const WorldDev &W, const EnvDev &E, const int *inc_off, const int *inc_ent, const int4 *ce_v,
+                      const double *ce_H, T *p, T *r, T *z, T *pp, T *q, const T *val, const T *Minv, double rz,
+                      double bb, int it, int cap, double &bytes, bool prof, double (*sh)[FB / 64]) {
+  const int r0 = E.v_off, r1 = E.v_off + E.nv_pad;
+  const double tol2 = E.pcg_tol * E.pcg_tol;
+  for (;;) {
+    // q = H pp and pp.q
+    double pq = 0.0, dummy = 0.0;
+    for (int i = r0 + threadIdx.x; i < r1; i += FB) {
+      double y[3];
+      sell_apply<T>(W, i, pp, val, y);
+      contact_apply<T>(i, pp, inc_off, inc_ent, ce_v, ce_H, y);
+      for (int c = 0; c < 3; ++c) {
+        q[3 * i + c] = (T)y[c];
+        pq += (double)pp[3 * i + c] * (double)(T)y[c];
+      }
+      if (prof)
+        bytes += (double)W.row_nnz[i] * (9.0 * sizeof(T) + 4.0) + 6.0 * sizeof(T) +
+                 (inc_off[i + 1] - inc_off[i]) * (4.0 * 72.0 + 16.0);
+    }
+    block_sum2(pq, dummy, sh);
+    double alpha = (pq > 0.0) ? rz / pq : 0.0;
+    // x, r, z updates and the new dots
+    double rzn = 0.0, rrn = 0.0;
+    for (int i = r0 + threadIdx.x; i < r1; i += FB) {
+      T rv[3], zv[3];
+      for (int c = 0; c < 3; ++c) {
+        p[3 * i + c] = (T)((double)p[3 * i + c] + alpha * (double)pp[3 * i + c]);
+        rv[c] = (T)((double)r[3 * i + c] - alpha * (double)q[3 * i + c]);
+        r[3 * i + c] = rv[c];
+      }
+      const T *M = Minv + 9 * (size_t)i;
+      for (int c = 0; c < 3; ++c) zv[c] = M[3 * c] * rv[0] + M[3 * c + 1] * rv[1] + M[3 * c + 2] * rv[2];
+      for (int c = 0; c < 3; ++c) {
+        z[3 * i + c] = zv[c];
+        rzn += (double)rv[c] * (double)zv[c];
+        rrn += (double)rv[c] * (double)rv[c];
+      }
+    }
+    block_sum2(rzn, rrn, sh);
+    ++it;
+    if (rrn <= tol2 * bb || !(rrn == rrn) || it >= cap || !(rz > 0.0)) break;
+    double beta = rzn / rz;
+    rz = rzn;
+    for (int i = r0 + threadIdx.x; i < r1; i += FB)
+      for (int c = 0; c < 3; ++c) pp[3 * i + c] = (T)((double)z[3 * i + c] + beta * (double)pp[3 * i + c]);
+    __syncthreads();
+  }
+  return it;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(1024) k_pcg_fused(WorldDev W, const EnvDev *envs, EnvState S, const int *fenv,
                                                     const int *inc_off, const int *inc_ent, const int4 *ce_v,
@@ -1204,11 +1276,9 @@ __global__ void __launch_bounds__(1024) k_pcg_fused(WorldDev W, const EnvDev *en
   if (S.status[e] != ST_ACTIVE) return;
   const EnvDev &E = envs[e];
   const int r0 = E.v_off, r1 = E.v_off + E.nv_pad;
-  const int cap = 30 * E.nv + 10;
-  const double tol2 = E.pcg_tol * E.pcg_tol;
   double rz = 0.0, bb = 0.0;
   for (int i = r0 + threadIdx.x; i < r1; i += FB) {
-    bool fr = W.kin[i] == KIN_FREE;
+    bool fr = is_dof(W, S, i, e);
     T rv[3], zv[3];
     for (int c = 0; c < 3; ++c) rv[c] = fr ? (T)(-W.g[3 * i + c]) : (T)0;
     const T *M = Minv + 9 * (size_t)i;
@@ -1225,51 +1295,41 @@ __global__ void __launch_bounds__(1024) k_pcg_fused(WorldDev W, const EnvDev *en
   block_sum2(rz, bb, sh);
   int it = 0;
   double bytes = 0.0;
-  if (bb > 0.0 && bb == bb) {
-    for (;;) {
-      // q = H pp and pp.q
-      double pq = 0.0, dummy = 0.0;
-      for (int i = r0 + threadIdx.x; i < r1; i += FB) {
-        double y[3];
-        sell_apply<T>(W, i, pp, val, y);
-        contact_apply<T>(i, pp, inc_off, inc_ent, ce_v, ce_H, y);
-        for (int c = 0; c < 3; ++c) {
-          q[3 * i + c] = (T)y[c];
-          pq += (double)pp[3 * i + c] * (double)(T)y[c];
-        }
-        if (prof)
-          bytes += (double)W.row_nnz[i] * (9.0 * sizeof(T) + 4.0) + 6.0 * sizeof(T) +
-                   (inc_off[i + 1] - inc_off[i]) * (4.0 * 72.0 + 16.0);
-      }
-      block_sum2(pq, dummy, sh);
-      double alpha = (pq > 0.0) ? rz / pq : 0.0;
-      // x, r, z updates and the new dots
-      double rzn = 0.0, rrn = 0.0;
-      for (int i = r0 + threadIdx.x; i < r1; i += FB) {
-        T rv[3], zv[3];
-        for (int c = 0; c < 3; ++c) {
-          p[3 * i + c] = (T)((double)p[3 * i + c] + alpha * (double)pp[3 * i + c]);
-          rv[c] = (T)((double)r[3 * i + c] - alpha * (double)q[3 * i + c]);
-          r[3 * i + c] = rv[c];
-        }
-        const T *M = Minv + 9 * (size_t)i;
-        for (int c = 0; c < 3; ++c) zv[c] = M[3 * c] * rv[0] + M[3 * c + 1] * rv[1] + M[3 * c + 2] * rv[2];
-        for (int c = 0; c < 3; ++c) {
-          z[3 * i + c] = zv[c];
-          rzn += (double)rv[c] * (double)zv[c];
-          rrn += (double)rv[c] * (double)rv[c];
-        }
-      }
-      block_sum2(rzn, rrn, sh);
-      ++it;
-      if (rrn <= tol2 * bb || !(rrn == rrn) || it >= cap || !(rz > 0.0)) break;
-      double beta = rzn / rz;
-      rz = rzn;
-      for (int i = r0 + threadIdx.x; i < r1; i += FB)
-        for (int c = 0; c < 3; ++c) pp[3 * i + c] = (T)((double)z[3 * i + c] + beta * (double)pp[3 * i + c]);
-      __syncthreads();
-    }
+  if (bb > 0.0 && bb == bb)
+    it = fused_iterate<T>(W, E, inc_off, inc_ent, ce_v, ce_H, p, r, z, pp, q, val, Minv, rz, bb, 0, 30 * E.nv + 10,
+                          bytes, prof != nullptr, sh);
+  if (prof) {
+    double dummy = 0.0;
+    block_sum2(bytes, dummy, sh);
   }
+  if (threadIdx.x == 0) {
+    S.pcg_it[e] = it;
+    S.pcg_total[e] += it;
+    S.pcg_done[e] = 1;
+    if (prof) atomicAdd(prof, (unsigned long long)bytes);
+  }
+}
+
+// Tail of the tiled PCG: once few tiles are still iterating, the first tile
+// of each live environment continues its solve in one workgroup from the
+// state the tiled kernels left (direction already updated, rz in part_rz),
+// with the same stopping rule and iteration cap.
+template <typename T>
+__global__ void __launch_bounds__(1024) k_pcg_resume(WorldDev W, const EnvDev *envs, EnvState S, const Tile *tiles,
+                                                     const double *part_rz, int cap, const int *inc_off,
+                                                     const int *inc_ent, const int4 *ce_v, const double *ce_H, T *p,
+                                                     T *r, T *z, T *pp, T *q, const T *val, const T *Minv,
+                                                     unsigned long long *prof) {
+  __shared__ double sh[2][FB / 64];
+  Tile t = tiles[blockIdx.x];
+  if (t.rel != 0 || !pcg_env_live(S, t.env)) return;
+  const int e = t.env;
+  const EnvDev &E = envs[e];
+  double rz = env_tiles_sum(part_rz, E);
+  double bb = S.pcg_bb[e];
+  double bytes = 0.0;
+  int it = fused_iterate<T>(W, E, inc_off, inc_ent, ce_v, ce_H, p, r, z, pp, q, val, Minv, rz, bb, S.pcg_it[e], cap,
+                            bytes, prof != nullptr, sh);
   if (prof) {
     double dummy = 0.0;
     block_sum2(bytes, dummy, sh);
@@ -1315,23 +1375,29 @@ __global__ void k_spmv_dbg(WorldDev W, EnvState S, const Tile *tiles, const int 
 // ---------------------------------------------------------------------------
 // convergence test |p|_inf <= tol * dt (per environment)
 // ---------------------------------------------------------------------------
-__global__ void k_pinf(WorldDev W, EnvState S, const Tile *tiles, double *part) {
+__global__ void k_pinf(WorldDev W, EnvState S, const Tile *tiles, double *part, double *part_viol) {
   __shared__ double sh[TB];
   Tile t = tiles[blockIdx.x];
   if (!active_env(S, t.env)) return;
   int i = t.start + threadIdx.x;
-  double m = 0.0;
-  if ((int)threadIdx.x < t.count && W.kin[i] == KIN_FREE)
+  double m = 0.0, v = 0.0;
+  if ((int)threadIdx.x < t.count && is_dof(W, S, i, t.env))
     for (int c = 0; c < 3; ++c) {
       double a = W.p[3 * i + c];
       m = (a != a) ? a : fmax(m, fabs(a));
     }
+  if ((int)threadIdx.x < t.count && W.kin[i] >= 0 && S.al[t.env])
+    for (int c = 0; c < 3; ++c) v = fmax(v, fabs(W.x[3 * i + c] - W.xh[3 * i + c]));
   m = block_max(m, sh);
-  if (threadIdx.x == 0) part[blockIdx.x] = m;
+  v = block_max(v, sh);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = m;
+    part_viol[blockIdx.x] = v;
+  }
 }
 
 __global__ void k_env_conv(const EnvDev *envs, EnvState S, const int *benv, int n, const double *part,
-                           int *n_active) {
+                           const double *part_viol, int *n_active) {
   int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
   int e = benv[j];
@@ -1346,13 +1412,85 @@ __global__ void k_env_conv(const EnvDev *envs, EnvState S, const int *benv, int 
   }
   S.pinf[e] = m;
   S.iters[e] += 1;
+  S.al_action[e] = 0;
   if (nan) {
     S.status[e] = ST_FAILED;
     S.reason[e] = FAIL_NONFINITE;
-  } else if (m <= E.tol * E.dt) {
+  } else if (m <= E.tol * E.dt && !S.al[e]) {
     S.status[e] = ST_CONVERGED;
   } else {
+    if (m <= E.tol * E.dt) {
+      // AL mode, inner problem converged: snap to the targets once within
+      // 1e-2 dhat (if CCD-safe), otherwise update the multipliers
+      double v = 0.0;
+      for (int i = 0; i < E.vtile_count; ++i) v = fmax(v, part_viol[E.vtile_first + i]);
+      S.viol[e] = v;
+      S.al_action[e] = (v <= 1e-2 * E.dhat) ? 2 : 1;
+    }
     atomicAdd(n_active, 1);
+  }
+}
+
+// AL actions: the displacement the swept CCD pass must check (snap) or none
+__global__ void k_al_prepare(WorldDev W, EnvState S, const Tile *tiles) {
+  Tile t = tiles[blockIdx.x];
+  if ((int)threadIdx.x >= t.count || !active_env(S, t.env)) return;
+  int act = S.al_action[t.env];
+  if (act == 0) return;
+  int i = t.start + threadIdx.x;
+  bool snap = (act == 2) && W.kin[i] >= 0;
+  for (int c = 0; c < 3; ++c) W.p[3 * i + c] = snap ? W.xh[3 * i + c] - W.x[3 * i + c] : 0.0;
+  if (threadIdx.x == 0 && t.rel == 0) S.snap_bad[t.env] = 0;
+}
+
+__global__ void k_snap_J(WorldDev W, EnvState S, const Tile *tiles) {
+  Tile t = tiles[blockIdx.x];
+  if ((int)threadIdx.x >= t.count || !active_env(S, t.env) || S.al_action[t.env] != 2) return;
+  int e = t.start + threadIdx.x;
+  int4 q = W.tet[e];
+  int v[4] = {q.x, q.y, q.z, q.w};
+  double x[12];
+  gather12_trial(W.x, W.p, 1.0, v, x);
+  double F[9];
+  nh_F(x, W.Dinv + 9 * e, F);
+  if (!(det33(F) > 0.0)) S.snap_bad[t.env] = 1;
+}
+
+__global__ void k_al_decide(EnvState S, const int *benv, int n) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  int e = benv[j];
+  if (S.status[e] != ST_ACTIVE || S.al_action[e] != 2) return;
+  double a = __longlong_as_double((long long)S.amax_bits[e]);
+  S.al_action[e] = (a >= 1.0 && !S.snap_bad[e]) ? 3 : 1;
+}
+
+__global__ void k_al_vertex(const EnvDev *envs, WorldDev W, EnvState S, const Tile *tiles) {
+  Tile t = tiles[blockIdx.x];
+  if ((int)threadIdx.x >= t.count || !active_env(S, t.env)) return;
+  int act = S.al_action[t.env];
+  int i = t.start + threadIdx.x;
+  if (W.kin[i] < 0 || (act != 1 && act != 3)) return;
+  if (act == 3) {
+    for (int c = 0; c < 3; ++c) W.x[3 * i + c] = W.xh[3 * i + c];
+  } else {
+    const EnvDev &E = envs[t.env];
+    double sw = sqrt(E.mbar / (E.dt * E.dt)), kA = S.kA[t.env];
+    for (int c = 0; c < 3; ++c) W.lam[3 * i + c] -= kA * sw * (W.x[3 * i + c] - W.xh[3 * i + c]);
+  }
+}
+
+__global__ void k_al_env(EnvState S, const int *benv, int n) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  int e = benv[j];
+  if (S.status[e] != ST_ACTIVE) return;
+  int act = S.al_action[e];
+  if (act == 3) {
+    S.al[e] = 0;
+  } else if (act == 1) {
+    if (S.viol[e] > 0.1 * S.viol_prev[e]) S.kA[e] *= 2.0;
+    S.viol_prev[e] = S.viol[e];
   }
 }
 
@@ -1385,7 +1523,7 @@ __global__ void k_ls_init(EnvState S, const int *benv, int n) {
   if (j >= n) return;
   int e = benv[j];
   S.alpha[e] = __longlong_as_double((long long)S.amax_bits[e]);
-  S.ls_done[e] = (S.status[e] == ST_ACTIVE) ? 0 : 1;
+  S.ls_done[e] = (S.status[e] == ST_ACTIVE && S.al_action[e] == 0) ? 0 : 1;
   S.ls_cnt[e] = 0;
 }
 
@@ -1408,6 +1546,14 @@ __global__ void k_energy_v(WorldDev W, const EnvDev *envs, EnvState S, const Til
       q += r * r;
     }
     e = W.mass[i] * q / (2.0 * E.dt * E.dt);
+  } else if (W.kin[i] >= 0 && S.al[t.env]) {
+    double w0 = E.mbar / (E.dt * E.dt), q = 0.0, l = 0.0;
+    for (int c = 0; c < 3; ++c) {
+      double r = W.x[3 * i + c] + a * W.p[3 * i + c] - W.xh[3 * i + c];
+      q += r * r;
+      l += W.lam[3 * i + c] * r;
+    }
+    e = 0.5 * S.kA[t.env] * w0 * q - sqrt(w0) * l;
   }
   W.e_v[i] = e;
 }
@@ -1502,7 +1648,7 @@ __global__ void k_ls_decide(EnvState S, const int *benv, int n, int *pending) {
 
 __global__ void k_update_x(WorldDev W, EnvState S, const Tile *tiles) {
   Tile t = tiles[blockIdx.x];
-  if ((int)threadIdx.x >= t.count || S.status[t.env] != ST_ACTIVE) return;
+  if ((int)threadIdx.x >= t.count || S.status[t.env] != ST_ACTIVE || S.al_action[t.env] != 0) return;
   int i = t.start + threadIdx.x;
   double a = S.alpha[t.env];
   for (int c = 0; c < 3; ++c) W.x[3 * i + c] += a * W.p[3 * i + c];
@@ -1670,7 +1816,6 @@ void grid_fill(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState
   IPC_LAUNCH(k_big_seg, nblk(B.n_envs, 64), 64, s)(E, S, B.envs, B.n_envs, L.g_bigoff);
   scan_int(s, L.g_bcnt, L.g_boff, (int)nbuckets, L.scan_tmp);
   if (n_ent) IPC_LAUNCH(k_grid_place, nblk(n_ent, TB), TB, s)(L.g_ent, L.g_ebucket, n_ent, L.g_boff, L.g_bcur, L.g_sorted);
-  IPC_LAUNCH(k_grid_sort, nblk(nbuckets, TB), TB, s)(L.g_boff, L.g_sorted, (int)nbuckets);
 }
 void bp_grid_count(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L,
                    unsigned nbuckets) {
@@ -1721,16 +1866,15 @@ void friction_elems(hipStream_t s, const WorldDev &W, const EnvDev *E, const Env
                                                       L.ce_H + 90 * (size_t)ce_off);
 }
 
-void incidence(hipStream_t s, const WorldDev &W, Lists &L, int n_ce, int nv_world, int *total_out_dev) {
+void incidence(hipStream_t s, const WorldDev &W, const EnvState &S, Lists &L, int n_ce, int nv_world) {
   IPC_LAUNCH(k_fill_int, nblk(nv_world + 1, TB), TB, s)(L.inc_cnt, nv_world + 1, 0);
   IPC_LAUNCH(k_fill_int, nblk(nv_world + 1, TB), TB, s)(L.inc_cur, nv_world + 1, 0);
-  if (n_ce) IPC_LAUNCH(k_inc_count, nblk(n_ce, TB), TB, s)(W, L.ce_v, n_ce, L.inc_cnt);
+  if (n_ce) IPC_LAUNCH(k_inc_count, nblk(n_ce, TB), TB, s)(W, S, L.ce_v, n_ce, L.inc_cnt);
   scan_int(s, L.inc_cnt, L.inc_off, nv_world, L.scan_tmp);
-  (void)total_out_dev;
 }
-void incidence_fill(hipStream_t s, const WorldDev &W, Lists &L, int n_ce, int nv_world) {
+void incidence_fill(hipStream_t s, const WorldDev &W, const EnvState &S, Lists &L, int n_ce, int nv_world) {
   if (n_ce) {
-    IPC_LAUNCH(k_inc_fill, nblk(n_ce, TB), TB, s)(W, L.ce_v, n_ce, L.inc_off, L.inc_cur, L.inc_ent);
+    IPC_LAUNCH(k_inc_fill, nblk(n_ce, TB), TB, s)(W, S, L.ce_v, n_ce, L.inc_off, L.inc_cur, L.inc_ent);
     IPC_LAUNCH(k_inc_sort, nblk(nv_world, TB), TB, s)(L.inc_off, L.inc_ent, nv_world);
   }
 }
@@ -1797,6 +1941,18 @@ void pcg_fused(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState
                                                  W.z32, W.pp32, W.q32, W.val32, W.Minv32, L.prof);
 }
 
+void pcg_resume(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, Lists &L, const Tile *tiles,
+                int n_tiles, int it, int cap, int mixed) {
+  if (!n_tiles) return;
+  const double *rz = (it & 1) ? L.part_b1 : L.part_b0;  // rz after `it` tiled iterations
+  if (!mixed)
+    IPC_LAUNCH(k_pcg_resume<double>, n_tiles, FB, s)(W, E, S, tiles, rz, cap, L.inc_off, L.inc_ent, L.ce_v, L.ce_H,
+                                                     W.p, W.r, W.z, W.pp, W.q, W.val, W.Minv, L.prof);
+  else
+    IPC_LAUNCH(k_pcg_resume<float>, n_tiles, FB, s)(W, E, S, tiles, rz, cap, L.inc_off, L.inc_ent, L.ce_v, L.ce_H,
+                                                    W.p32, W.r32, W.z32, W.pp32, W.q32, W.val32, W.Minv32, L.prof);
+}
+
 void pcg_finish(hipStream_t s, const WorldDev &W, const EnvState &S, const Batch &B, int mixed) {
   if (mixed && B.n_vt) IPC_LAUNCH(k_p32_to_p, B.n_vt, TB, s)(W, S, B.vtiles);
 }
@@ -1809,8 +1965,20 @@ void spmv_debug(hipStream_t s, const WorldDev &W, const EnvDev *, const EnvState
 void conv_check(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L,
                 int *n_active) {
   IPC_LAUNCH(k_fill_int, 1, 64, s)(n_active, 1, 0);
-  if (B.n_vt) IPC_LAUNCH(k_pinf, B.n_vt, TB, s)(W, S, B.vtiles, L.part_a);
-  IPC_LAUNCH(k_env_conv, nblk(B.n_envs, 64), 64, s)(E, S, B.envs, B.n_envs, L.part_a, n_active);
+  if (B.n_vt) IPC_LAUNCH(k_pinf, B.n_vt, TB, s)(W, S, B.vtiles, L.part_a, L.part_b0);
+  IPC_LAUNCH(k_env_conv, nblk(B.n_envs, 64), 64, s)(E, S, B.envs, B.n_envs, L.part_a, L.part_b0, n_active);
+}
+
+void al_prepare(hipStream_t s, const WorldDev &W, const EnvState &S, const Batch &B) {
+  if (B.n_vt) IPC_LAUNCH(k_al_prepare, B.n_vt, TB, s)(W, S, B.vtiles);
+}
+void snap_J(hipStream_t s, const WorldDev &W, const EnvState &S, const Batch &B) {
+  if (B.n_tt) IPC_LAUNCH(k_snap_J, B.n_tt, TB, s)(W, S, B.ttiles);
+}
+void al_finish(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B) {
+  IPC_LAUNCH(k_al_decide, nblk(B.n_envs, 64), 64, s)(S, B.envs, B.n_envs);
+  if (B.n_vt) IPC_LAUNCH(k_al_vertex, B.n_vt, TB, s)(E, W, S, B.vtiles);
+  IPC_LAUNCH(k_al_env, nblk(B.n_envs, 64), 64, s)(S, B.envs, B.n_envs);
 }
 
 void ccd_init(hipStream_t s, const EnvState &S, const Batch &B) {

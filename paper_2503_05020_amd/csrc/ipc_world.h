@@ -48,6 +48,7 @@ struct EnvDev {
   int fused;                     // 1: the PCG solve runs in one workgroup (nv_pad <= kFusedRows)
   double dt, dhat, kappa, mu, eps_v, tol, pcg_tol;
   double cell;                   // hash-grid cell size of this environment
+  double mbar;                   // mean free-vertex mass (augmented-Lagrangian weight mbar / dt^2)
 };
 
 // Per-environment solver state (device arrays indexed by slot).
@@ -58,13 +59,18 @@ struct EnvState {
   unsigned long long *amax_bits;  // CCD bound as ordered bits of a non-negative double
   int *cand_beg, *cand_end, *act_beg, *act_end, *fric_beg, *fric_end, *big_beg, *big_end;
   int *in_step;                   // 1 if the env takes part in the current step
+  // augmented-Lagrangian Dirichlet mode: al = 1 while the kinematic vertices
+  // are unknowns; al_action per Newton iteration: 0 line search, 1 multiplier
+  // update, 2 snap attempt, 3 snap accepted
+  int *al, *al_action, *snap_bad;
+  double *kA, *viol, *viol_prev;
   double *pcg_bb;                 // |g|^2 of the current solve
 };
 
 // Flat device arrays of the world (element-indexed).
 struct WorldDev {
   // per vertex
-  double *X, *x, *v, *xn, *xh, *p, *g, *r, *z, *pp, *q, *mass, *Minv, *e_v;
+  double *X, *x, *v, *xn, *xh, *p, *g, *r, *z, *pp, *q, *mass, *Minv, *e_v, *lam;
   float *r32, *z32, *pp32, *q32, *p32, *Minv32;
   int *kin, *venv, *vt_beg, *vt_end, *row_nnz;
   // per slice (vertex / 64)

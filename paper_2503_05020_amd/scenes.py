@@ -449,3 +449,36 @@ def random_pt(rng, scale=1.0):
 
 def random_ee(rng, scale=1.0):
     return rng.uniform(-scale, scale, (4, 3))
+
+
+def press_block(speed: float = 0.3, gap: float = 1.5e-3, cells: int = 2, edge: float = 0.02, steps: int = 8,
+                E: float = 1e5, jitter: float = 0.05, seed: int = 0, **params):
+    """A kinematic square plate pressed down onto a soft block resting on a ground plane.
+
+    The plate starts `gap` above the block and moves down at `speed` for
+    `steps` steps, then stops; at 0.3 m/s it covers 3 mm per step, more than
+    the gap, so the prescribed move cannot be applied in one go.  The block's
+    vertices are moved sideways by a seeded `jitter` (fraction of a cell):
+    a perfectly symmetric block can twist either way under the press, and the
+    branch taken would then be decided by rounding.
+    """
+    dhat = params.get("dhat", DEFAULT_PARAMS["dhat"])
+    v, t = voxel_tet_mesh(np.ones((cells,) * 3, bool), edge / cells, (-edge / 2, -edge / 2, 1.2 * dhat))
+    rng = np.random.default_rng(seed)
+    v = v.copy()
+    v[:, :2] += rng.uniform(-1.0, 1.0, (len(v), 2)) * jitter * edge / cells
+    b = _Builder()
+    b.add_body(v, t, E, 0.4, 1000.0)
+    top = v[:, 2].max()
+    hp = edge  # plate half-size: twice the block
+    pv = np.array([[-hp, -hp, top + gap], [hp, -hp, top + gap], [hp, hp, top + gap], [-hp, hp, top + gap]])
+    b.add_kinematic_mesh(pv, np.array([[0, 1, 2], [0, 2, 3]]), 1)
+    gv, gt = ground_plane()
+    b.add_kinematic_mesh(gv, gt, 0)
+    dt = params.get("dt", DEFAULT_PARAMS["dt"])
+    n = steps + 4
+    motion = np.zeros((n, 2, 12))
+    for k in range(n):
+        motion[k, 0] = IDENTITY12
+        motion[k, 1] = translation((0.0, 0.0, -speed * dt * min(k, steps)))
+    return b.build(motion, [[0.0, 0.0, -9.81]], **params)

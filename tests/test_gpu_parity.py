@@ -229,6 +229,31 @@ def test_cube_drop_trajectory_parity():
     assert pg[: len(pg) - 4, 2].min() > 0
 
 
+def test_augmented_lagrangian_press_parity():
+    """Plate pressed onto a block faster than the gap allows: the augmented-Lagrangian Dirichlet mode
+    (Sec. III-B) must end each step with the plate on target and match the oracle's trajectory."""
+    sc = S.press_block(steps=4)
+    g = G.ipc_create_scene(sc, pcg_rel_tol=1e-8)
+    o = O.Scene(sc, pcg_rel_tol=1e-8)
+    kin = sc["kin_group"]
+    X = sc["rest_pos"]
+    L = sc["env_bbox_diag"]
+    for k in range(6):
+        rg, ig = G.ipc_step(g, 1)
+        ro, io = o.step(1)
+        assert rg == 0 and ro == 0, (k, ig, io)
+        pg, _ = G.ipc_get_state(g)
+        po, _ = o.state()
+        err = np.abs(pg - po).max() / L
+        say(f"step {k}: err {err:.2e} newton {ig['newton_iters']}/{io['newton_iters']}")
+        assert err <= 1e-6
+        target = X[kin == 1, 2] - 0.3 * sc["dt"] * min(k + 1, 4)
+        assert np.array_equal(pg[kin == 1, 2], target)
+        assert pg[kin < 0, 2].max() < target.min()
+    x = pg[sc["tets"]]
+    assert np.linalg.det(np.stack([x[:, 1] - x[:, 0], x[:, 2] - x[:, 0], x[:, 3] - x[:, 0]], 2)).min() > 0
+
+
 def test_alone_equals_batch_bitwise():
     say("alone vs batch")
     scs = [S.soft_cube_drop(cells=2, edge=0.04, height=0.002 + 0.001 * i, seed=i) for i in range(3)]
