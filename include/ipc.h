@@ -140,6 +140,23 @@ int ipc_prof_enable(int32_t on);
 int ipc_prof_reset(void);
 int ipc_prof_read(double *out);
 
+/* Execution knobs of the current device's solver.  They change how work is
+ * scheduled, never a result: the tiled PCG kernels and the per-environment
+ * PCG kernel reduce in the same order and produce the same bits.
+ *   IPC_TUNE_TAIL_TILES: once at most this many vertex tiles (256 rows each)
+ *     of a batch are still iterating their PCG, the remaining environments
+ *     are finished by one workgroup each in a single launch (default 0 =
+ *     never: one CU's bandwidth makes that slower than the tiled launches on
+ *     environments of a few thousand rows; initial value from the environment
+ *     variable IPC_TAIL_TILES).
+ *   IPC_TUNE_FUSED_PCG: 1 = every environment of up to 8192 rows runs its
+ *     whole PCG in one workgroup from the start (default 0; IPC_FUSED_PCG).
+ * Returns IPC_OK, or IPC_E_ARG for an unknown key or a negative value. */
+#define IPC_TUNE_TAIL_TILES 1
+#define IPC_TUNE_FUSED_PCG 2
+int ipc_set_tuning(int32_t key, int64_t value);
+int ipc_get_tuning(int32_t key, int64_t *value);
+
 /* ---------------------------------------------------------------------------
  * Inspection entry points.  Each runs the same device kernels the step uses,
  * on host-supplied positions, so callers can check individual stages.

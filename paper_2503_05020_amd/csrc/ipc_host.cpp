@@ -1121,27 +1121,23 @@ struct World {
     return na;
   }
 
-  // IPC_FUSED_PCG=1 solves environments of up to kFusedRows rows in one
-  // workgroup each (default: the tiled path, faster on the batched grasp
-  // workload because the slowest solve then spreads over several CUs)
-  static bool use_fused() {
-    static int t = -1;
-    if (t < 0) {
-      const char *e = std::getenv("IPC_FUSED_PCG");
-      t = (e && e[0] && e[0] != '0') ? 1 : 0;
-    }
-    return t == 1;
+  // execution knobs (ipc_set_tuning); initial values from the environment
+  static int env_knob(const char *name, int dflt) {
+    const char *e = std::getenv(name);
+    return (e && e[0]) ? std::max(0, std::atoi(e)) : dflt;
   }
-
+  // 1: environments of up to kFusedRows rows run their whole PCG in one
+  // workgroup each (default 0: tiled, faster on the batched grasp workload
+  // because large solves then spread over several CUs)
+  int fused_pcg = env_knob("IPC_FUSED_PCG", 0) ? 1 : 0;
   // live vertex tiles at or below which the tiled PCG hands the remaining
-  // environments to one workgroup each (IPC_TAIL_TILES, default 128; 0 = never)
-  static int tail_tiles() {
-    static int t = -1;
-    if (t < 0) {
-      const char *e = std::getenv("IPC_TAIL_TILES");
-      t = (e && e[0]) ? std::max(0, std::atoi(e)) : 128;
-    }
-    return t;
+  // environments to one workgroup each (0 = never)
+  int tail_tiles = env_knob("IPC_TAIL_TILES", 0);
+  bool use_fused() const { return fused_pcg == 1; }
+  void set_fused(int on) {
+    if ((on != 0) == use_fused()) return;
+    fused_pcg = on ? 1 : 0;
+    batch_envs.clear();  // E.fused is decided when a batch is laid out
   }
 
   long long solve(int mixed) {
@@ -1183,10 +1179,10 @@ struct World {
         ntl = read_int(live_offs.p + B.n_vt);
         tl = live_d.p;
         last_pending = pend;
-        if (ntl <= tail_tiles()) {
+        if (ntl <= tail_tiles) {
           // few tiles left: their launches would be latency-bound, so one
           // workgroup per environment finishes the solves in one launch
-          ipck::pcg_resume(stream, W, envs_d, S, L, tl, ntl, it, cap, mixed);
+          ipck::pcg_resume(stream, W, envs_d, S, L, tl, ntl, it, mixed);
           break;
         }
       }
@@ -1541,6 +1537,36 @@ int ipc_prof_enable(int32_t on) {
     World &w = world_for_current_device();
     std::lock_guard<std::mutex> lk(w.mu);
     w.set_prof(on != 0);
+    return IPC_OK;
+  });
+}
+
+int ipc_set_tuning(int32_t key, int64_t value) {
+  return guarded([&]() {
+    if (value < 0) throw ApiError(IPC_E_ARG, "tuning value must be >= 0");
+    World &w = world_for_current_device();
+    std::lock_guard<std::mutex> lk(w.mu);
+    if (key == IPC_TUNE_TAIL_TILES)
+      w.tail_tiles = (int)std::min<int64_t>(value, 1 << 30);
+    else if (key == IPC_TUNE_FUSED_PCG)
+      w.set_fused(value != 0);
+    else
+      throw ApiError(IPC_E_ARG, "unknown tuning key");
+    return IPC_OK;
+  });
+}
+
+int ipc_get_tuning(int32_t key, int64_t *value) {
+  return guarded([&]() {
+    if (!value) throw ApiError(IPC_E_ARG, "null output");
+    World &w = world_for_current_device();
+    std::lock_guard<std::mutex> lk(w.mu);
+    if (key == IPC_TUNE_TAIL_TILES)
+      *value = w.tail_tiles;
+    else if (key == IPC_TUNE_FUSED_PCG)
+      *value = w.fused_pcg;
+    else
+      throw ApiError(IPC_E_ARG, "unknown tuning key");
     return IPC_OK;
   });
 }

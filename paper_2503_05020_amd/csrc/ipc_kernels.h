@@ -90,7 +90,7 @@ void live_tiles(hipStream_t s, const EnvState &S, const Batch &B, Lists &L, Tile
 // continues the PCG of the environments whose tiles are listed (one workgroup
 // each) to convergence; `it` = tiled iterations done so far
 void pcg_resume(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, Lists &L, const Tile *tiles,
-                int n_tiles, int it, int cap, int mixed);
+                int n_tiles, int it, int mixed);
 void pcg_finish(hipStream_t s, const WorldDev &W, const EnvState &S, const Batch &B, int mixed);
 // one workgroup per environment for the environments flagged `fused`
 void pcg_fused(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const int *fenv, int n_fenv,

@@ -986,58 +986,83 @@ DEV bool pcg_env_live(const EnvState &S, int env) { return S.status[env] == ST_A
 // batch's full tile list (kernels may run over a compacted copy of the list)
 DEV int tile_slot(const EnvDev *envs, const Tile &t) { return envs[t.env].vtile_first + t.rel; }
 
-__global__ void k_pcg_init(WorldDev W, const EnvDev *envs, EnvState S, const Tile *tiles, double *part_rz,
-                           double *part_rr) {
-  __shared__ double sh[TB];
-  Tile t = tiles[blockIdx.x];
-  if (!active_env(S, t.env) || envs[t.env].fused) return;
-  int i = t.start + threadIdx.x;
-  double rz = 0.0, rr = 0.0;
-  if ((int)threadIdx.x < t.count) {
-    double r[3], z[3];
-    bool fr = is_dof(W, S, i, t.env);
-    for (int c = 0; c < 3; ++c) r[c] = fr ? -W.g[3 * i + c] : 0.0;
-    const double *M = W.Minv + 9 * (size_t)i;
-    for (int c = 0; c < 3; ++c) z[c] = fr ? M[3 * c] * r[0] + M[3 * c + 1] * r[1] + M[3 * c + 2] * r[2] : 0.0;
-    for (int c = 0; c < 3; ++c) {
-      W.r[3 * i + c] = r[c];
-      W.z[3 * i + c] = z[c];
-      W.pp[3 * i + c] = z[c];
-      W.p[3 * i + c] = 0.0;
-      rz += r[c] * z[c];
-      rr += r[c] * r[c];
-    }
-  }
-  rz = block_sum(rz, sh);
-  rr = block_sum(rr, sh);
-  if (threadIdx.x == 0) {
-    part_rz[tile_slot(envs, t)] = rz;
-    part_rr[tile_slot(envs, t)] = rr;
+// ---------------------------------------------------------------------------
+// Block-Jacobi PCG.  The per-row pieces below are shared by the tiled kernels
+// (one 256-row tile per workgroup, three launches per iteration) and the
+// per-environment kernels (one 1024-thread workgroup iterating a whole
+// environment), and both reduce dot products per 256-row tile with the same
+// tree and then over the environment's tiles in order: the two paths produce
+// the same bits, so where the tiled solve hands over to the per-environment
+// kernel does not change any result.
+// ---------------------------------------------------------------------------
+template <typename T>
+DEV void row_init(const WorldDev &W, bool fr, int i, T *p, T *r, T *z, T *pp, const T *Minv, double &rz,
+                  double &rr) {
+  T rv[3], zv[3];
+  for (int c = 0; c < 3; ++c) rv[c] = fr ? (T)(-W.g[3 * i + c]) : (T)0;
+  const T *M = Minv + 9 * (size_t)i;
+  for (int c = 0; c < 3; ++c) zv[c] = fr ? M[3 * c] * rv[0] + M[3 * c + 1] * rv[1] + M[3 * c + 2] * rv[2] : (T)0;
+  for (int c = 0; c < 3; ++c) {
+    r[3 * i + c] = rv[c];
+    z[3 * i + c] = zv[c];
+    pp[3 * i + c] = zv[c];
+    p[3 * i + c] = (T)0;
+    rz += (double)rv[c] * (double)zv[c];
+    rr += (double)rv[c] * (double)rv[c];
   }
 }
 
-__global__ void k_pcg_init32(WorldDev W, const EnvDev *envs, EnvState S, const Tile *tiles, double *part_rz,
-                             double *part_rr) {
+// q_i = (H pp)_i; returns pp_i . q_i
+template <typename T>
+DEV double row_spmv(const WorldDev &W, int i, const int *inc_off, const int *inc_ent, const int4 *ce_v,
+                    const double *ce_H, const T *pp, T *q, const T *val) {
+  double y[3], pq = 0.0;
+  sell_apply<T>(W, i, pp, val, y);
+  contact_apply<T>(i, pp, inc_off, inc_ent, ce_v, ce_H, y);
+  for (int c = 0; c < 3; ++c) {
+    q[3 * i + c] = (T)y[c];
+    pq += (double)pp[3 * i + c] * (double)(T)y[c];
+  }
+  return pq;
+}
+
+template <typename T>
+DEV void row_update(int i, double alpha, T *p, T *r, T *z, const T *pp, const T *q, const T *Minv, double &rz,
+                    double &rr) {
+  T rv[3], zv[3];
+  for (int c = 0; c < 3; ++c) {
+    p[3 * i + c] = (T)((double)p[3 * i + c] + alpha * (double)pp[3 * i + c]);
+    rv[c] = (T)((double)r[3 * i + c] - alpha * (double)q[3 * i + c]);
+    r[3 * i + c] = rv[c];
+  }
+  const T *M = Minv + 9 * (size_t)i;
+  for (int c = 0; c < 3; ++c) zv[c] = M[3 * c] * rv[0] + M[3 * c + 1] * rv[1] + M[3 * c + 2] * rv[2];
+  for (int c = 0; c < 3; ++c) {
+    z[3 * i + c] = zv[c];
+    rz += (double)rv[c] * (double)zv[c];
+    rr += (double)rv[c] * (double)rv[c];
+  }
+}
+
+template <typename T>
+DEV void row_dir(int i, double beta, T *pp, const T *z) {
+  for (int c = 0; c < 3; ++c) pp[3 * i + c] = (T)((double)z[3 * i + c] + beta * (double)pp[3 * i + c]);
+}
+
+// stopping rule of one environment after `it` iterations
+DEV bool pcg_stop(const EnvDev &E, double rr, double bb, double rz_old, int it) {
+  return (rr <= E.pcg_tol * E.pcg_tol * bb) || !(rr == rr) || it >= 30 * E.nv + 10 || !(rz_old > 0.0);
+}
+
+template <typename T>
+__global__ void k_pcg_init(WorldDev W, const EnvDev *envs, EnvState S, const Tile *tiles, T *p, T *r, T *z, T *pp,
+                           const T *Minv, double *part_rz, double *part_rr) {
   __shared__ double sh[TB];
   Tile t = tiles[blockIdx.x];
   if (!active_env(S, t.env) || envs[t.env].fused) return;
   int i = t.start + threadIdx.x;
   double rz = 0.0, rr = 0.0;
-  if ((int)threadIdx.x < t.count) {
-    float r[3], z[3];
-    bool fr = is_dof(W, S, i, t.env);
-    for (int c = 0; c < 3; ++c) r[c] = fr ? (float)(-W.g[3 * i + c]) : 0.0f;
-    const float *M = W.Minv32 + 9 * (size_t)i;
-    for (int c = 0; c < 3; ++c) z[c] = fr ? M[3 * c] * r[0] + M[3 * c + 1] * r[1] + M[3 * c + 2] * r[2] : 0.0f;
-    for (int c = 0; c < 3; ++c) {
-      W.r32[3 * i + c] = r[c];
-      W.z32[3 * i + c] = z[c];
-      W.pp32[3 * i + c] = z[c];
-      W.p32[3 * i + c] = 0.0f;
-      rz += (double)r[c] * (double)z[c];
-      rr += (double)r[c] * (double)r[c];
-    }
-  }
+  if ((int)threadIdx.x < t.count) row_init<T>(W, is_dof(W, S, i, t.env), i, p, r, z, pp, Minv, rz, rr);
   rz = block_sum(rz, sh);
   rr = block_sum(rr, sh);
   if (threadIdx.x == 0) {
@@ -1078,15 +1103,7 @@ __global__ void __launch_bounds__(256) k_spmv(WorldDev W, const EnvDev *envs, En
   if (!pcg_env_live(S, t.env)) return;
   int i = t.start + threadIdx.x;
   double pq = 0.0;
-  if ((int)threadIdx.x < t.count) {
-    double y[3];
-    sell_apply<T>(W, i, pp, val, y);
-    contact_apply<T>(i, pp, inc_off, inc_ent, ce_v, ce_H, y);
-    for (int c = 0; c < 3; ++c) {
-      q[3 * i + c] = (T)y[c];
-      pq += (double)pp[3 * i + c] * (double)(T)y[c];
-    }
-  }
+  if ((int)threadIdx.x < t.count) pq = row_spmv<T>(W, i, inc_off, inc_ent, ce_v, ce_H, pp, q, val);
   pq = block_sum(pq, sh);
   if (threadIdx.x == 0) part_pq[tile_slot(envs, t)] = pq;
   if (prof) {
@@ -1120,21 +1137,7 @@ __global__ void k_pcg_update(WorldDev W, const EnvDev *envs, EnvState S, const T
   double alpha = s_alpha;
   int i = t.start + threadIdx.x;
   double rz = 0.0, rr = 0.0;
-  if ((int)threadIdx.x < t.count) {
-    T rv[3], zv[3];
-    for (int c = 0; c < 3; ++c) {
-      p[3 * i + c] = (T)((double)p[3 * i + c] + alpha * (double)pp[3 * i + c]);
-      rv[c] = (T)((double)r[3 * i + c] - alpha * (double)q[3 * i + c]);
-      r[3 * i + c] = rv[c];
-    }
-    const T *M = Minv + 9 * (size_t)i;
-    for (int c = 0; c < 3; ++c) zv[c] = M[3 * c] * rv[0] + M[3 * c + 1] * rv[1] + M[3 * c + 2] * rv[2];
-    for (int c = 0; c < 3; ++c) {
-      z[3 * i + c] = zv[c];
-      rz += (double)rv[c] * (double)zv[c];
-      rr += (double)rv[c] * (double)rv[c];
-    }
-  }
+  if ((int)threadIdx.x < t.count) row_update<T>(i, alpha, p, r, z, pp, q, Minv, rz, rr);
   rz = block_sum(rz, sh);
   rr = block_sum(rr, sh);
   if (threadIdx.x == 0) {
@@ -1145,8 +1148,7 @@ __global__ void k_pcg_update(WorldDev W, const EnvDev *envs, EnvState S, const T
 
 template <typename T>
 __global__ void k_pcg_dir(WorldDev W, const EnvDev *envs, EnvState S, const Tile *tiles, const double *part_rz_old,
-                          const double *part_rz_new, const double *part_rr_new, T *pp, const T *z, int *pending,
-                          int cap) {
+                          const double *part_rz_new, const double *part_rr_new, T *pp, const T *z, int *pending) {
   __shared__ double s_beta;
   __shared__ int s_done;
   Tile t = tiles[blockIdx.x];
@@ -1155,9 +1157,7 @@ __global__ void k_pcg_dir(WorldDev W, const EnvDev *envs, EnvState S, const Tile
   if (threadIdx.x == 0) {
     double rzn = env_tiles_sum(part_rz_new, E), rzo = env_tiles_sum(part_rz_old, E);
     double rr = env_tiles_sum(part_rr_new, E);
-    double bb = S.pcg_bb[t.env];
-    int it = S.pcg_it[t.env] + 1;
-    int done = (rr <= E.pcg_tol * E.pcg_tol * bb) || !(rr == rr) || it >= cap || !(rzo > 0.0);
+    int done = pcg_stop(E, rr, S.pcg_bb[t.env], rzo, S.pcg_it[t.env] + 1);
     s_done = done;
     s_beta = done ? 0.0 : rzn / rzo;
   }
@@ -1173,135 +1173,116 @@ __global__ void k_pcg_dir(WorldDev W, const EnvDev *envs, EnvState S, const Tile
   }
   double beta = s_beta;
   int i = t.start + threadIdx.x;
-  if ((int)threadIdx.x < t.count)
-    for (int c = 0; c < 3; ++c) pp[3 * i + c] = (T)((double)z[3 * i + c] + beta * (double)pp[3 * i + c]);
+  if ((int)threadIdx.x < t.count) row_dir<T>(i, beta, pp, z);
   if (threadIdx.x == 0 && t.rel == 0) S.pcg_it[t.env] += 1;
 }
 
 // ---------------------------------------------------------------------------
-// Fused PCG: one 1024-thread workgroup runs a whole environment's solve to
-// convergence inside one launch (environments up to kFusedRows rows).  Thread
-// t owns rows t, t+1024, ...; a wavefront therefore owns one 64-row slice of
-// the sliced-ELL matrix.  Reductions: wavefront shuffles, then the 16 wave
-// partials summed in order by every thread (deterministic).
+// Per-environment PCG: one 1024-thread workgroup iterates a whole
+// environment inside one launch.  Thread t handles rows t, t+1024, ...; each
+// 256-thread quarter therefore covers one vertex tile per pass and reduces it
+// with the tiled kernels' tree; tile partials go to the same per-tile arrays
+// and are summed in tile order.
 // ---------------------------------------------------------------------------
 constexpr int FB = 1024;
 
-DEV double wave_sum(double v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  return v;
-}
-
-// sums a and b over the workgroup; every thread gets the totals
-DEV void block_sum2(double &a, double &b, double (*sh)[FB / 64]) {
-  a = wave_sum(a);
-  b = wave_sum(b);
-  int w = threadIdx.x / 64;
-  if ((threadIdx.x & 63) == 0) {
-    sh[0][w] = a;
-    sh[1][w] = b;
+// tree sums of a and b over each 256-thread quarter (the block_sum tree);
+// thread 0 of each quarter stores them for tile `tile0 + quarter` if that
+// tile exists
+DEV void tile_sums2(double a, double b, double (*sh)[FB], const EnvDev &E, int tile0, double *pa, double *pb) {
+  const int q = threadIdx.x / TB, l = threadIdx.x % TB;
+  sh[0][threadIdx.x] = a;
+  sh[1][threadIdx.x] = b;
+  __syncthreads();
+  for (int s = TB / 2; s > 0; s >>= 1) {
+    if (l < s) {
+      sh[0][threadIdx.x] += sh[0][threadIdx.x + s];
+      sh[1][threadIdx.x] += sh[1][threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (l == 0 && tile0 + q < E.vtile_count) {
+    if (pa) pa[E.vtile_first + tile0 + q] = sh[0][q * TB];
+    if (pb) pb[E.vtile_first + tile0 + q] = sh[1][q * TB];
   }
   __syncthreads();
-  a = 0.0;
-  b = 0.0;
-  for (int i = 0; i < FB / 64; ++i) {
-    a += sh[0][i];
-    b += sh[1][i];
-  }
-  __syncthreads();
 }
 
-// PCG iterations of environment e by one workgroup, from the state (p, r, z,
-// pp, rz) until the relative residual reaches the tolerance, a non-finite
-// value appears or the iteration count reaches cap.  Returns the count.
+// PCG iterations of one environment from the state (p, r, z, pp, rz) until
+// pcg_stop; returns the iteration count
 template <typename T>
-DEV int fused_iterate(const WorldDev &W, const EnvDev &E, const int *inc_off, const int *inc_ent, const int4 *ce_v,
-                      const double *ce_H, T *p, T *r, T *z, T *pp, T *q, const T *val, const T *Minv, double rz,
-                      double bb, int it, int cap, double &bytes, bool prof, double (*sh)[FB / 64]) {
+DEV int env_iterate(const WorldDev &W, const EnvDev &E, const int *inc_off, const int *inc_ent, const int4 *ce_v,
+                    const double *ce_H, T *p, T *r, T *z, T *pp, T *q, const T *val, const T *Minv, double rz,
+                    double bb, int it, double *part_pq, double *part_rz, double *part_rr, double &bytes, bool prof,
+                    double (*sh)[FB]) {
   const int r0 = E.v_off, r1 = E.v_off + E.nv_pad;
-  const double tol2 = E.pcg_tol * E.pcg_tol;
   for (;;) {
-    // q = H pp and pp.q
-    double pq = 0.0, dummy = 0.0;
-    for (int i = r0 + threadIdx.x; i < r1; i += FB) {
-      double y[3];
-      sell_apply<T>(W, i, pp, val, y);
-      contact_apply<T>(i, pp, inc_off, inc_ent, ce_v, ce_H, y);
-      for (int c = 0; c < 3; ++c) {
-        q[3 * i + c] = (T)y[c];
-        pq += (double)pp[3 * i + c] * (double)(T)y[c];
+    for (int base = r0; base < r1; base += FB) {
+      int i = base + threadIdx.x;
+      double pq = 0.0;
+      if (i < r1) {
+        pq = row_spmv<T>(W, i, inc_off, inc_ent, ce_v, ce_H, pp, q, val);
+        if (prof)
+          bytes += (double)W.row_nnz[i] * (9.0 * sizeof(T) + 4.0) + 6.0 * sizeof(T) +
+                   (inc_off[i + 1] - inc_off[i]) * (4.0 * 72.0 + 16.0);
       }
-      if (prof)
-        bytes += (double)W.row_nnz[i] * (9.0 * sizeof(T) + 4.0) + 6.0 * sizeof(T) +
-                 (inc_off[i + 1] - inc_off[i]) * (4.0 * 72.0 + 16.0);
+      tile_sums2(pq, 0.0, sh, E, (base - r0) / TB, part_pq, nullptr);
     }
-    block_sum2(pq, dummy, sh);
+    double pq = env_tiles_sum(part_pq, E);
     double alpha = (pq > 0.0) ? rz / pq : 0.0;
-    // x, r, z updates and the new dots
-    double rzn = 0.0, rrn = 0.0;
-    for (int i = r0 + threadIdx.x; i < r1; i += FB) {
-      T rv[3], zv[3];
-      for (int c = 0; c < 3; ++c) {
-        p[3 * i + c] = (T)((double)p[3 * i + c] + alpha * (double)pp[3 * i + c]);
-        rv[c] = (T)((double)r[3 * i + c] - alpha * (double)q[3 * i + c]);
-        r[3 * i + c] = rv[c];
-      }
-      const T *M = Minv + 9 * (size_t)i;
-      for (int c = 0; c < 3; ++c) zv[c] = M[3 * c] * rv[0] + M[3 * c + 1] * rv[1] + M[3 * c + 2] * rv[2];
-      for (int c = 0; c < 3; ++c) {
-        z[3 * i + c] = zv[c];
-        rzn += (double)rv[c] * (double)zv[c];
-        rrn += (double)rv[c] * (double)rv[c];
-      }
+    for (int base = r0; base < r1; base += FB) {
+      int i = base + threadIdx.x;
+      double rzi = 0.0, rri = 0.0;
+      if (i < r1) row_update<T>(i, alpha, p, r, z, pp, q, Minv, rzi, rri);
+      tile_sums2(rzi, rri, sh, E, (base - r0) / TB, part_rz, part_rr);
     }
-    block_sum2(rzn, rrn, sh);
+    double rzn = env_tiles_sum(part_rz, E), rrn = env_tiles_sum(part_rr, E);
     ++it;
-    if (rrn <= tol2 * bb || !(rrn == rrn) || it >= cap || !(rz > 0.0)) break;
+    if (pcg_stop(E, rrn, bb, rz, it)) break;
     double beta = rzn / rz;
     rz = rzn;
-    for (int i = r0 + threadIdx.x; i < r1; i += FB)
-      for (int c = 0; c < 3; ++c) pp[3 * i + c] = (T)((double)z[3 * i + c] + beta * (double)pp[3 * i + c]);
+    for (int i = r0 + threadIdx.x; i < r1; i += FB) row_dir<T>(i, beta, pp, z);
     __syncthreads();
   }
   return it;
+}
+
+DEV double block_total(double v, double (*sh)[FB]) {
+  sh[0][threadIdx.x] = v;
+  __syncthreads();
+  for (int s = FB / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[0][threadIdx.x] += sh[0][threadIdx.x + s];
+    __syncthreads();
+  }
+  double t = sh[0][0];
+  __syncthreads();
+  return t;
 }
 
 template <typename T>
 __global__ void __launch_bounds__(1024) k_pcg_fused(WorldDev W, const EnvDev *envs, EnvState S, const int *fenv,
                                                     const int *inc_off, const int *inc_ent, const int4 *ce_v,
                                                     const double *ce_H, T *p, T *r, T *z, T *pp, T *q, const T *val,
-                                                    const T *Minv, unsigned long long *prof) {
-  __shared__ double sh[2][FB / 64];
+                                                    const T *Minv, double *part_pq, double *part_rz, double *part_rr,
+                                                    unsigned long long *prof) {
+  __shared__ double sh[2][FB];
   int e = fenv[blockIdx.x];
   if (S.status[e] != ST_ACTIVE) return;
   const EnvDev &E = envs[e];
   const int r0 = E.v_off, r1 = E.v_off + E.nv_pad;
-  double rz = 0.0, bb = 0.0;
-  for (int i = r0 + threadIdx.x; i < r1; i += FB) {
-    bool fr = is_dof(W, S, i, e);
-    T rv[3], zv[3];
-    for (int c = 0; c < 3; ++c) rv[c] = fr ? (T)(-W.g[3 * i + c]) : (T)0;
-    const T *M = Minv + 9 * (size_t)i;
-    for (int c = 0; c < 3; ++c) zv[c] = fr ? M[3 * c] * rv[0] + M[3 * c + 1] * rv[1] + M[3 * c + 2] * rv[2] : (T)0;
-    for (int c = 0; c < 3; ++c) {
-      r[3 * i + c] = rv[c];
-      z[3 * i + c] = zv[c];
-      pp[3 * i + c] = zv[c];
-      p[3 * i + c] = (T)0;
-      rz += (double)rv[c] * (double)zv[c];
-      bb += (double)rv[c] * (double)rv[c];
-    }
+  for (int base = r0; base < r1; base += FB) {
+    int i = base + threadIdx.x;
+    double rzi = 0.0, rri = 0.0;
+    if (i < r1) row_init<T>(W, is_dof(W, S, i, e), i, p, r, z, pp, Minv, rzi, rri);
+    tile_sums2(rzi, rri, sh, E, (base - r0) / TB, part_rz, part_rr);
   }
-  block_sum2(rz, bb, sh);
+  double rz = env_tiles_sum(part_rz, E), bb = env_tiles_sum(part_rr, E);
   int it = 0;
   double bytes = 0.0;
-  if (bb > 0.0 && bb == bb)
-    it = fused_iterate<T>(W, E, inc_off, inc_ent, ce_v, ce_H, p, r, z, pp, q, val, Minv, rz, bb, 0, 30 * E.nv + 10,
-                          bytes, prof != nullptr, sh);
-  if (prof) {
-    double dummy = 0.0;
-    block_sum2(bytes, dummy, sh);
-  }
+  if (!(bb == 0.0 || !(bb == bb)))
+    it = env_iterate<T>(W, E, inc_off, inc_ent, ce_v, ce_H, p, r, z, pp, q, val, Minv, rz, bb, 0, part_pq, part_rz,
+                        part_rr, bytes, prof != nullptr, sh);
+  if (prof) bytes = block_total(bytes, sh);
   if (threadIdx.x == 0) {
     S.pcg_it[e] = it;
     S.pcg_total[e] += it;
@@ -1312,28 +1293,24 @@ __global__ void __launch_bounds__(1024) k_pcg_fused(WorldDev W, const EnvDev *en
 
 // Tail of the tiled PCG: once few tiles are still iterating, the first tile
 // of each live environment continues its solve in one workgroup from the
-// state the tiled kernels left (direction already updated, rz in part_rz),
-// with the same stopping rule and iteration cap.
+// state the tiled kernels left (direction already updated, rz in part_rz_cur).
 template <typename T>
 __global__ void __launch_bounds__(1024) k_pcg_resume(WorldDev W, const EnvDev *envs, EnvState S, const Tile *tiles,
-                                                     const double *part_rz, int cap, const int *inc_off,
+                                                     const double *part_rz_cur, const int *inc_off,
                                                      const int *inc_ent, const int4 *ce_v, const double *ce_H, T *p,
                                                      T *r, T *z, T *pp, T *q, const T *val, const T *Minv,
+                                                     double *part_pq, double *part_rz, double *part_rr,
                                                      unsigned long long *prof) {
-  __shared__ double sh[2][FB / 64];
+  __shared__ double sh[2][FB];
   Tile t = tiles[blockIdx.x];
   if (t.rel != 0 || !pcg_env_live(S, t.env)) return;
   const int e = t.env;
   const EnvDev &E = envs[e];
-  double rz = env_tiles_sum(part_rz, E);
-  double bb = S.pcg_bb[e];
+  double rz = env_tiles_sum(part_rz_cur, E);
   double bytes = 0.0;
-  int it = fused_iterate<T>(W, E, inc_off, inc_ent, ce_v, ce_H, p, r, z, pp, q, val, Minv, rz, bb, S.pcg_it[e], cap,
-                            bytes, prof != nullptr, sh);
-  if (prof) {
-    double dummy = 0.0;
-    block_sum2(bytes, dummy, sh);
-  }
+  int it = env_iterate<T>(W, E, inc_off, inc_ent, ce_v, ce_H, p, r, z, pp, q, val, Minv, rz, S.pcg_bb[e],
+                          S.pcg_it[e], part_pq, part_rz, part_rr, bytes, prof != nullptr, sh);
+  if (prof) bytes = block_total(bytes, sh);
   if (threadIdx.x == 0) {
     S.pcg_it[e] = it;
     S.pcg_total[e] += it;
@@ -1893,8 +1870,12 @@ void assemble(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState 
 void pcg_init(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L,
               int *pending, int mixed) {
   IPC_LAUNCH(k_fill_int, 1, 64, s)(pending, 1, 0);
-  if (B.n_vt && !mixed) IPC_LAUNCH(k_pcg_init, B.n_vt, TB, s)(W, E, S, B.vtiles, L.part_b0, L.part_c0);
-  if (B.n_vt && mixed) IPC_LAUNCH(k_pcg_init32, B.n_vt, TB, s)(W, E, S, B.vtiles, L.part_b0, L.part_c0);
+  if (B.n_vt && !mixed)
+    IPC_LAUNCH(k_pcg_init<double>, B.n_vt, TB, s)(W, E, S, B.vtiles, W.p, W.r, W.z, W.pp, W.Minv, L.part_b0,
+                                                  L.part_c0);
+  if (B.n_vt && mixed)
+    IPC_LAUNCH(k_pcg_init<float>, B.n_vt, TB, s)(W, E, S, B.vtiles, W.p32, W.r32, W.z32, W.pp32, W.Minv32,
+                                                 L.part_b0, L.part_c0);
   IPC_LAUNCH(k_pcg_env_init, nblk(B.n_envs, 64), 64, s)(E, S, B.envs, B.n_envs, L.part_c0, pending);
 }
 
@@ -1918,7 +1899,7 @@ void pcg_iter(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState 
     if (ev1) hipEventRecord(ev1, s);
     IPC_LAUNCH(k_pcg_update<double>, n_tiles, TB, s)(W, E, S, tiles, L.part_a, rz_old, rz_new, rr_new, W.p, W.r, W.z,
                                                W.pp, W.q, W.Minv);
-    IPC_LAUNCH(k_pcg_dir<double>, n_tiles, TB, s)(W, E, S, tiles, rz_old, rz_new, rr_new, W.pp, W.z, pending, cap);
+    IPC_LAUNCH(k_pcg_dir<double>, n_tiles, TB, s)(W, E, S, tiles, rz_old, rz_new, rr_new, W.pp, W.z, pending);
   } else {
     if (ev0) hipEventRecord(ev0, s);
     IPC_LAUNCH(k_spmv<float>, n_tiles, TB, s)(W, E, S, tiles, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, W.pp32, W.q32,
@@ -1926,7 +1907,7 @@ void pcg_iter(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState 
     if (ev1) hipEventRecord(ev1, s);
     IPC_LAUNCH(k_pcg_update<float>, n_tiles, TB, s)(W, E, S, tiles, L.part_a, rz_old, rz_new, rr_new, W.p32, W.r32,
                                               W.z32, W.pp32, W.q32, W.Minv32);
-    IPC_LAUNCH(k_pcg_dir<float>, n_tiles, TB, s)(W, E, S, tiles, rz_old, rz_new, rr_new, W.pp32, W.z32, pending, cap);
+    IPC_LAUNCH(k_pcg_dir<float>, n_tiles, TB, s)(W, E, S, tiles, rz_old, rz_new, rr_new, W.pp32, W.z32, pending);
   }
 }
 
@@ -1935,22 +1916,29 @@ void pcg_fused(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState
   if (!n_fenv) return;
   if (!mixed)
     IPC_LAUNCH(k_pcg_fused<double>, n_fenv, FB, s)(W, E, S, fenv, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, W.p, W.r, W.z,
-                                                  W.pp, W.q, W.val, W.Minv, L.prof);
+                                                  W.pp, W.q, W.val, W.Minv, L.part_a, L.part_b0, L.part_c0, L.prof);
   else
     IPC_LAUNCH(k_pcg_fused<float>, n_fenv, FB, s)(W, E, S, fenv, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, W.p32, W.r32,
-                                                 W.z32, W.pp32, W.q32, W.val32, W.Minv32, L.prof);
+                                                 W.z32, W.pp32, W.q32, W.val32, W.Minv32, L.part_a, L.part_b0,
+                                                 L.part_c0, L.prof);
 }
 
 void pcg_resume(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, Lists &L, const Tile *tiles,
-                int n_tiles, int it, int cap, int mixed) {
+                int n_tiles, int it, int mixed) {
   if (!n_tiles) return;
-  const double *rz = (it & 1) ? L.part_b1 : L.part_b0;  // rz after `it` tiled iterations
+  // after `it` tiled iterations the current rz partials are in part_b1 (odd)
+  // or part_b0 (even); the per-environment loop then uses the other pair
+  const double *rz = (it & 1) ? L.part_b1 : L.part_b0;
+  double *rz_tmp = (it & 1) ? L.part_b0 : L.part_b1;
+  double *rr_tmp = (it & 1) ? L.part_c0 : L.part_c1;
   if (!mixed)
-    IPC_LAUNCH(k_pcg_resume<double>, n_tiles, FB, s)(W, E, S, tiles, rz, cap, L.inc_off, L.inc_ent, L.ce_v, L.ce_H,
-                                                     W.p, W.r, W.z, W.pp, W.q, W.val, W.Minv, L.prof);
+    IPC_LAUNCH(k_pcg_resume<double>, n_tiles, FB, s)(W, E, S, tiles, rz, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, W.p,
+                                                     W.r, W.z, W.pp, W.q, W.val, W.Minv, L.part_a, rz_tmp, rr_tmp,
+                                                     L.prof);
   else
-    IPC_LAUNCH(k_pcg_resume<float>, n_tiles, FB, s)(W, E, S, tiles, rz, cap, L.inc_off, L.inc_ent, L.ce_v, L.ce_H,
-                                                    W.p32, W.r32, W.z32, W.pp32, W.q32, W.val32, W.Minv32, L.prof);
+    IPC_LAUNCH(k_pcg_resume<float>, n_tiles, FB, s)(W, E, S, tiles, rz, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, W.p32,
+                                                    W.r32, W.z32, W.pp32, W.q32, W.val32, W.Minv32, L.part_a, rz_tmp,
+                                                    rr_tmp, L.prof);
 }
 
 void pcg_finish(hipStream_t s, const WorldDev &W, const EnvState &S, const Batch &B, int mixed) {

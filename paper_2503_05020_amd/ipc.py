@@ -23,6 +23,8 @@ IPC_E_FAILED = -5
 IPC_E_DEVICE = -6
 IPC_FP64 = 0
 IPC_MIXED = 1
+IPC_TUNE_TAIL_TILES = 1
+IPC_TUNE_FUSED_PCG = 2
 FAIL_REASONS = {0: "none", 1: "maxit", 2: "nonfinite", 3: "line-search", 4: "dirichlet"}
 
 _dp = C.POINTER(C.c_double)
@@ -58,7 +60,7 @@ EXPORTS = [
     "ipc_last_error", "ipc_scene_sizes", "ipc_debug_candidates", "ipc_debug_active", "ipc_debug_begin_step",
     "ipc_debug_gradient", "ipc_debug_energy", "ipc_debug_hessian_apply", "ipc_debug_newton_dir",
     "ipc_debug_ccd_bound", "ipc_debug_classify", "ipc_debug_pair_barrier", "ipc_debug_tet_elastic",
-    "ipc_debug_accd", "ipc_prof_enable", "ipc_prof_reset", "ipc_prof_read",
+    "ipc_debug_accd", "ipc_prof_enable", "ipc_prof_reset", "ipc_prof_read", "ipc_set_tuning", "ipc_get_tuning",
 ]
 
 _lib = None
@@ -102,6 +104,8 @@ def lib():
     L.ipc_debug_accd.restype = C.c_int64
     L.ipc_prof_enable.argtypes = [C.c_int32]
     L.ipc_prof_read.argtypes = [_dp]
+    L.ipc_set_tuning.argtypes = [C.c_int32, C.c_int64]
+    L.ipc_get_tuning.argtypes = [C.c_int32, C.POINTER(C.c_int64)]
     _lib = L
     return L
 
@@ -244,6 +248,16 @@ def ipc_prof_read():
     out = np.zeros(4)
     _check(lib().ipc_prof_read(_d(out)))
     return {"spmv_ms": float(out[0]), "spmv_launches": int(out[1]), "spmv_bytes": float(out[2])}
+
+
+def ipc_set_tuning(key: int, value: int):
+    _check(lib().ipc_set_tuning(key, int(value)))
+
+
+def ipc_get_tuning(key: int) -> int:
+    out = C.c_int64()
+    _check(lib().ipc_get_tuning(key, C.byref(out)))
+    return int(out.value)
 
 
 # --- inspection entry points -------------------------------------------------

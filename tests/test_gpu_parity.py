@@ -254,6 +254,29 @@ def test_augmented_lagrangian_press_parity():
     assert np.linalg.det(np.stack([x[:, 1] - x[:, 0], x[:, 2] - x[:, 0], x[:, 3] - x[:, 0]], 2)).min() > 0
 
 
+@pytest.mark.parametrize("precision", [G.IPC_FP64, G.IPC_MIXED])
+def test_pcg_paths_same_bits(precision):
+    """Tiled PCG, tiled with the per-environment tail hand-off at the first poll, and the fully
+    per-environment PCG reduce in the same order: the trajectories must be bitwise identical."""
+    scs = [S.soft_cube_drop(cells=3, edge=0.05, height=0.003 + 0.001 * i, seed=i) for i in range(3)]
+    runs = []
+    for tail, fused in ((0, 0), (1 << 30, 0), (0, 1)):
+        G.ipc_set_tuning(G.IPC_TUNE_TAIL_TILES, tail)
+        G.ipc_set_tuning(G.IPC_TUNE_FUSED_PCG, fused)
+        gs = [G.ipc_create_scene(sc, precision=precision) for sc in scs]
+        for _ in range(8):
+            rc, _ = G.ipc_step_batch(gs, 1)
+            assert rc == 0
+        runs.append([G.ipc_get_state(g)[0] for g in gs])
+        for g in gs:
+            G.ipc_destroy_scene(g)
+    G.ipc_set_tuning(G.IPC_TUNE_TAIL_TILES, 0)
+    G.ipc_set_tuning(G.IPC_TUNE_FUSED_PCG, 0)
+    for k in (1, 2):
+        for a, b in zip(runs[0], runs[k]):
+            assert np.array_equal(a, b), k
+
+
 def test_alone_equals_batch_bitwise():
     say("alone vs batch")
     scs = [S.soft_cube_drop(cells=2, edge=0.04, height=0.002 + 0.001 * i, seed=i) for i in range(3)]
