@@ -14,6 +14,14 @@ mixed-precision throughput; the FP64 figure is reported beside it.  The
 paper's speedup notion (N environments batched vs the same N run one after
 another, Sec. IV-A) is reported as context from a sequential single-environment
 run on the same GPU.
+
+Serving (`serving` object): a bounded sample of the request stream -- sphere
+grasps (tet count lognormal, median 10k, clipped to [2k, 50k], 100 steps each)
+arriving as a Poisson process at 50 requests/s -- submitted at their arrival
+times to the library's continuous-batching server (200 GB budget, slot cap
+tuned by the server), mixed precision; p50/p99 latency is completion time
+minus arrival time, throughput is converged steps over the span from the first
+arrival to the last completion.
 """
 from __future__ import annotations
 
@@ -110,6 +118,42 @@ def cpu_baseline(scs, budget_s=20.0):
                        f"one thread, {wall:.1f}s")
 
 
+def serving(n_req, rate, budget, slots, precision, n_steps=100):
+    reqs = S.serving_requests(n_req, rate=rate, seed=1)
+    scs = [S.serving_scene(r) for r in reqs]
+    log(f"[serving] {n_req} requests, {sum(len(sc['tets']) for sc in scs)} tets in total")
+    srv = G.ipc_server_create(budget, slots)
+    try:
+        t0 = time.perf_counter()
+        ids = []
+        for r, sc in zip(reqs, scs):
+            dt = t0 + r["arrival"] - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+            ids.append(G.ipc_server_submit(srv, sc, n_steps, precision))
+        infos = []
+        for k, i in enumerate(ids):
+            infos.append(G.ipc_server_wait(srv, i, 3600.0))
+            if k % 8 == 7:
+                st = G.ipc_server_stats(srv)
+                log(f"[serving] {k + 1} done, running {st['running']:.0f}, queued {st['queued']:.0f}, "
+                    f"cap {st['slot_cap']:.0f}")
+        st = G.ipc_server_stats(srv)
+    finally:
+        G.ipc_server_destroy(srv)
+    lat = sorted(i["t_done"] - i["t_submit"] for i in infos)
+    span = max(i["t_done"] for i in infos) - min(i["t_submit"] for i in infos)
+    steps = sum(i["steps_done"] for i in infos)
+
+    def pct(q):
+        return lat[min(len(lat) - 1, int(round(q * (len(lat) - 1))))]
+    return {"requests": n_req, "arrival_rate_per_s": rate, "steps_per_request": n_steps,
+            "p50_latency_s": round(pct(0.5), 3), "p99_latency_s": round(pct(0.99), 3),
+            "converged_steps_per_s": round(steps / span, 2), "failed": sum(i["status"] == G.IPC_REQ_FAILED for i in infos),
+            "slot_cap": int(st["slot_cap"]), "budget_bytes": budget,
+            "tets_total": int(sum(len(sc["tets"]) for sc in scs))}
+
+
 def roofline(prof):
     if prof["spmv_launches"] <= 0 or prof["spmv_ms"] <= 0:
         return None
@@ -132,6 +176,8 @@ def main():
     ap.add_argument("--pcg-tol", type=float, default=1e-4)
     ap.add_argument("--sequential-envs", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=48, help="0 skips the serving run")
+    ap.add_argument("--serve-slots", type=int, default=0, help="0 = slot cap tuned by the server")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: environments are independent and would be sharded across GPUs "
@@ -157,6 +203,10 @@ def main():
         seq = sequential_gpu(scs, G.IPC_MIXED if main_p == "mixed" else G.IPC_FP64, args.warmup, args.steps,
                              args.pcg_tol, min(args.sequential_envs, len(scs)))
         log(f"sequential single-env: {seq['value']:.2f} env-steps/s")
+    serve = None
+    if args.serve_requests > 0:
+        serve = serving(args.serve_requests, 50.0, 200 << 30, args.serve_slots, G.IPC_MIXED)
+        log(f"[serving] {serve}")
     cpu = None if args.no_cpu_baseline else cpu_baseline(scs)
     out = {
         "metric": "converged sim steps/s over batched scenes",
@@ -178,6 +228,7 @@ def main():
         "failed_envs": r["failed"],
         "roofline": roofline(r["prof"]),
         "cpu_baseline": cpu,
+        "serving": serve,
     }
     if "fp64" in results and main_p != "fp64":
         f = results["fp64"]

@@ -129,13 +129,14 @@ const char *ipc_last_error(void);
  * out[6] failed flag. */
 int ipc_scene_sizes(ipc_scene s, int64_t out[7]);
 
-/* Measurement of the PCG matrix-vector product on the current device: when
- * enabled, every launch of that kernel is bracketed by HIP events on the
- * library's stream and the kernel adds the algorithmic bytes it moves (stored
- * blocks and column indices, one read and one write of a vector row, contact
- * blocks applied) to a device counter.  ipc_prof_read writes out[0] total
- * event-timed milliseconds, out[1] number of launches, out[2] bytes,
- * out[3] reserved. */
+/* Measurement of the tiled PCG matrix-vector product on the current device:
+ * when enabled, every 16th launch of that kernel (iterations 5, 21, 37, ...
+ * of each solve) is bracketed by HIP events on the library's stream, and
+ * those launches add the algorithmic bytes they move (stored blocks and
+ * column indices, one read and one write of a vector row, contact blocks
+ * applied) to a device counter.  ipc_prof_read writes out[0] total
+ * event-timed milliseconds, out[1] number of timed launches, out[2] their
+ * bytes, out[3] reserved. */
 int ipc_prof_enable(int32_t on);
 int ipc_prof_reset(void);
 int ipc_prof_read(double *out);
@@ -151,9 +152,13 @@ int ipc_prof_read(double *out);
  *     variable IPC_TAIL_TILES).
  *   IPC_TUNE_FUSED_PCG: 1 = every environment of up to 8192 rows runs its
  *     whole PCG in one workgroup from the start (default 0; IPC_FUSED_PCG).
+ *   IPC_TUNE_FOLD_DIR: 1 = the tiled PCG forms the next search direction
+ *     inside the following matrix-vector product (two launches per
+ *     iteration; default), 0 = a separate direction kernel (IPC_FOLD_DIR).
  * Returns IPC_OK, or IPC_E_ARG for an unknown key or a negative value. */
 #define IPC_TUNE_TAIL_TILES 1
 #define IPC_TUNE_FUSED_PCG 2
+#define IPC_TUNE_FOLD_DIR 3
 int ipc_set_tuning(int32_t key, int64_t value);
 int ipc_get_tuning(int32_t key, int64_t *value);
 
@@ -201,6 +206,76 @@ int ipc_debug_pair_barrier(int32_t kind, int32_t type, const double *x12, double
 int ipc_debug_tet_elastic(const double *X12, const double *x12, double E, double nu, int32_t project,
                           double *energy, double *g12, double *H144);
 int64_t ipc_debug_accd(int32_t kind, int64_t n, const double *x12, const double *p12, double s, double *t);
+
+/* ===========================================================================
+ * Serving: continuous batching of simulation requests on one device.
+ *
+ * A server owns a worker thread.  Each tick it (1) admits queued requests, in
+ * submission order, while fewer than max_slots are running and the device
+ * bytes of their resident state (positions and velocities, meshes, sparsity
+ * pattern, PCG vectors: ipc_request_info.bytes) fit in budget_bytes; (2)
+ * advances every running request by one time step, all of them in one batch
+ * through the same kernels as ipc_step_batch; (3) retires the requests that
+ * completed their steps or failed, keeping their final state for
+ * ipc_server_result and freeing their slot and memory.  Requests thus join and
+ * leave the batch between time steps while the others keep running, and a
+ * request's result is bitwise the same as when it runs alone.  Per-step
+ * contact and candidate lists are shared work buffers of the device and are
+ * not counted in the budget.
+ *
+ * The paper (Sec. IV) runs its grasp pipeline as many independent
+ * environments; this interface serves such environments as they arrive.
+ * =========================================================================== */
+typedef struct ipc_server_s *ipc_server;
+
+#define IPC_REQ_QUEUED 0
+#define IPC_REQ_RUNNING 1
+#define IPC_REQ_DONE 2
+#define IPC_REQ_FAILED 3
+
+typedef struct {
+  int32_t status;       /* IPC_REQ_*                                                       */
+  int32_t steps_done;   /* converged time steps                                             */
+  int32_t n_steps;      /* steps requested                                                  */
+  int32_t fail_reason;  /* IPC_FAIL_* once FAILED (IPC_FAIL_DEVICE: the server stopped)     */
+  double t_submit;      /* seconds since the server was created, at entry to submit        */
+  double t_admit;       /* -1 while queued                                                 */
+  double t_done;        /* -1 until DONE / FAILED; latency = t_done - t_submit             */
+  int64_t newton_iters; /* summed over the request's steps                                  */
+  int64_t pcg_iters;
+  int64_t bytes;        /* resident device bytes of the request's scene                     */
+} ipc_request_info;
+
+#define IPC_FAIL_DEVICE 5 /* the server's worker hit a device error and stopped */
+
+/* Creates a server on the current device.  budget_bytes > 0; max_slots >= 1
+ * fixes the slot cap, max_slots = 0 lets the server tune it: starting at 8,
+ * while requests are waiting it raises the cap by half after every 16 ticks
+ * whose converged steps/s beat the best window so far by 3%, and otherwise
+ * settles on the best cap. */
+int ipc_server_create(int64_t budget_bytes, int32_t max_slots, ipc_server *out);
+/* Validates and copies the scene (as ipc_create_scene; same error codes, and
+ * IPC_E_NOMEM if it alone exceeds the budget) and queues it for n_steps >= 1
+ * time steps; *id identifies the request. */
+int ipc_server_submit(ipc_server srv, const ipc_scene_desc *desc, int32_t n_steps, int64_t *id);
+/* Current record of a request (IPC_E_ARG for an unknown id). */
+int ipc_server_poll(ipc_server srv, int64_t id, ipc_request_info *info);
+/* Waits up to timeout_s seconds for the request to be DONE or FAILED, then
+ * fills *info (nullable) as ipc_server_poll does. */
+int ipc_server_wait(ipc_server srv, int64_t id, double timeout_s, ipc_request_info *info);
+/* Positions [n_verts*3] and velocities (nullable) of a finished request: the
+ * last converged step (IPC_E_ARG if it has not finished). */
+int ipc_server_result(ipc_server srv, int64_t id, double *pos, double *vel);
+/* Forgets a finished request and its stored result. */
+int ipc_server_release(ipc_server srv, int64_t id);
+/* Fixes the slot cap (takes effect at the next admission; ends tuning). */
+int ipc_server_set_slots(ipc_server srv, int32_t max_slots);
+/* Totals: out[0] requests finished, out[1] failed, out[2] converged steps,
+ * out[3] ticks, out[4] running now, out[5] queued now, out[6] resident bytes
+ * in use, out[7] seconds since creation, out[8] current slot cap. */
+int ipc_server_stats(ipc_server srv, double *out);
+/* Stops the worker after its current tick; unfinished requests are dropped. */
+void ipc_server_destroy(ipc_server srv);
 
 #ifdef __cplusplus
 }

@@ -17,7 +17,10 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <condition_variable>
+#include <deque>
 #include <mutex>
+#include <thread>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -578,7 +581,7 @@ struct World {
       inc_ent, counter;
   DBuf<int2> cand, act;
   DBuf<int> g_ncell, g_big, g_eoff, g_bigoff, g_ebucket, g_bcnt, g_boff, g_bcur, g_bigl;
-  DBuf<int4> g_ent, g_sorted;
+  DBuf<ipck::GridEnt> g_ent, g_sorted;
   DBuf<double> cand_d2, e_c, fw, fn, flam, e_f, ce_g, ce_H, part_a, part_b0, part_b1, part_c0, part_c1;
   DBuf<int4> fv, ce_v;
   int *pinned = nullptr;  // host mirror of counters
@@ -608,6 +611,7 @@ struct World {
     reg(aV, (void **)&W.r, 24);
     reg(aV, (void **)&W.z, 24);
     reg(aV, (void **)&W.pp, 24);
+    reg(aV, (void **)&W.pp2, 24);
     reg(aV, (void **)&W.q, 24);
     reg(aV, (void **)&W.mass, 8);
     reg(aV, (void **)&W.Minv, 72);
@@ -616,6 +620,7 @@ struct World {
     reg(aV, (void **)&W.r32, 12);
     reg(aV, (void **)&W.z32, 12);
     reg(aV, (void **)&W.pp32, 12);
+    reg(aV, (void **)&W.pp2_32, 12);
     reg(aV, (void **)&W.q32, 12);
     reg(aV, (void **)&W.p32, 12);
     reg(aV, (void **)&W.Minv32, 36);
@@ -684,10 +689,28 @@ struct World {
   void upload_env(int e) {
     HC(hipMemcpyAsync(envs_d + e, &envs_h[e], sizeof(EnvDev), hipMemcpyHostToDevice, stream));
   }
+  // every environment record in one copy
+  void upload_envs() {
+    if (!envs_h.empty())
+      HC(hipMemcpyAsync(envs_d, envs_h.data(), envs_h.size() * sizeof(EnvDev), hipMemcpyHostToDevice, stream));
+  }
 
   template <class T>
   void up(T *dst, const T *src, size_t n) {
     if (n) HC(hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyHostToDevice, stream));
+  }
+
+  // device bytes of a scene's resident state (every array registered with
+  // the arenas, at the scene's element counts)
+  size_t scene_bytes(const HostScene &H) const {
+    auto ab = [](const Arena &a, size_t n) {
+      size_t e = 0;
+      for (const RawBuf &b : a.bufs) e += b.elem;
+      return (n + a.align - 1) / a.align * a.align * e;
+    };
+    return ab(aV, H.nv_pad) + ab(aT, H.nt) + ab(aTri, H.ntri) + ab(aE, H.ne) + ab(aSV, H.nsv) + ab(aPos, H.npos) +
+           ab(aContrib, H.contrib.size()) + ab(aVT, H.vt_ent.size()) + ab(aMo, H.motion.size()) +
+           ab(aSlice, (H.nv_pad + ipcw::kSlice - 1) / ipcw::kSlice);
   }
 
   int add_scene(const HostScene &H) {
@@ -755,6 +778,8 @@ struct World {
     HC(hipMemsetAsync(W.p + 3 * vo, 0, 24 * R.v_n, stream));
     HC(hipMemsetAsync(W.pp + 3 * vo, 0, 24 * R.v_n, stream));
     HC(hipMemsetAsync(W.pp32 + 3 * vo, 0, 12 * R.v_n, stream));
+    HC(hipMemsetAsync(W.pp2 + 3 * vo, 0, 24 * R.v_n, stream));
+    HC(hipMemsetAsync(W.pp2_32 + 3 * vo, 0, 12 * R.v_n, stream));
     HC(hipMemsetAsync(W.lam + 3 * vo, 0, 24 * R.v_n, stream));
     std::vector<int> vt(H.vt_ent.size());
     for (size_t i = 0; i < vt.size(); ++i) vt[i] = (H.vt_ent[i] >> 2) * 4 + (int)to * 4 + (H.vt_ent[i] & 3);
@@ -883,8 +908,8 @@ struct World {
       bitem_off += E.ntri + E.ne;
       E.fused = (E.nv_pad <= ipcw::kFusedRows && use_fused()) ? 1 : 0;
       if (E.fused) fused_h.push_back(e);
-      upload_env(e);
     }
+    upload_envs();
     auto put = [&](DBuf<Tile> &d, const std::vector<Tile> &h) {
       d.ensure(h.size() + 1);
       up(d.p, h.data(), h.size());
@@ -1133,6 +1158,9 @@ struct World {
   // live vertex tiles at or below which the tiled PCG hands the remaining
   // environments to one workgroup each (0 = never)
   int tail_tiles = env_knob("IPC_TAIL_TILES", 0);
+  // 1: the direction update is folded into the next product (two launches
+  // per PCG iteration); 0: a separate direction kernel every iteration
+  int fold_dir = env_knob("IPC_FOLD_DIR", 1) ? 1 : 0;
   bool use_fused() const { return fused_pcg == 1; }
   void set_fused(int on) {
     if ((on != 0) == use_fused()) return;
@@ -1163,16 +1191,33 @@ struct World {
     // compacted whenever an environment has converged since the last poll
     const Tile *tl = B.vtiles;
     int ntl = B.n_vt, last_pending = -1;
+    int cur = 0;  // pp buffer holding the current direction
+    const bool tr = tracing();
+    double t_launch = 0.0, t_wait = 0.0;
+    auto now = []() { return std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now().time_since_epoch()).count(); };
     while (true) {
+      double t0 = tr ? now() : 0.0;
+      // a block of 8 iterations: the first product reads the stored
+      // direction, the next 7 form it on the fly, the last update is
+      // followed by the stopping test + direction kernel before the poll
       for (int j = 0; j < 8; ++j) {
         hipEvent_t e0 = nullptr, e1 = nullptr;
-        if (prof_on) {
+        // every 16th iteration is timed (an event pair costs a few us of
+        // dispatch gap, which would slow the solve it measures)
+        if (prof_on && (it & 15) == 5) {
           e0 = pool_event(nev++);
           e1 = pool_event(nev++);
         }
-        ipck::pcg_iter(stream, W, envs_d, S, B, L, it++, pending, mixed, cap, e0, e1, tl, ntl);
+        const bool dir = fold_dir && j > 0;
+        ipck::pcg_iter(stream, W, envs_d, S, L, it++, pending, mixed, dir, cur, !fold_dir || j == 7, e0, e1, tl, ntl);
+        if (dir) cur = 1 - cur;
       }
+      double t1 = tr ? now() : 0.0;
       int pend = read_int(pending);
+      if (tr) {
+        t_launch += t1 - t0;
+        t_wait += now() - t1;
+      }
       if (pend <= 0 || it >= cap) break;
       if (pend != last_pending) {
         ipck::live_tiles(stream, S, B, L, live_d.p, live_flag.p, live_offs.p);
@@ -1182,12 +1227,14 @@ struct World {
         if (ntl <= tail_tiles) {
           // few tiles left: their launches would be latency-bound, so one
           // workgroup per environment finishes the solves in one launch
-          ipck::pcg_resume(stream, W, envs_d, S, L, tl, ntl, it, mixed);
+          ipck::pcg_resume(stream, W, envs_d, S, L, tl, ntl, it, cur, mixed);
           break;
         }
       }
     }
     ipck::pcg_finish(stream, W, S, B, mixed);
+    if (tr)
+      std::fprintf(stderr, "[ipc]   pcg %d iterations: host launching %.0f us, waiting %.0f us\n", it, t_launch, t_wait);
     if (prof_on) {
       HC(hipStreamSynchronize(stream));
       for (size_t k = 0; k + 1 < nev; k += 2) {
@@ -1230,6 +1277,7 @@ struct World {
     for (int e : batch_envs) maxit = std::max(maxit, envs_h[e].maxit);
     int mixed = 0;
     for (int e : batch_envs) mixed |= envs_h[e].precision == IPC_MIXED;
+    const std::vector<int> step_envs = batch_envs;
     for (int it = 0; it < maxit; ++it) {
       int na = assemble_system(mixed);
       long long pit = solve(mixed);
@@ -1239,6 +1287,7 @@ struct World {
         std::fprintf(stderr, "[ipc] newton %d: active pairs %d friction %d pcg %lld envs-left %d  %.1f ms\n", it, na,
                      n_fric, pit, still, ms());
       if (still == 0) break;
+      if (2 * still <= (int)batch_envs.size()) narrow_batch();
       ipck::al_prepare(stream, W, S, B);
       int ns = broad_phase(W.x, W.p);
       ipck::ccd_init(stream, S, B);
@@ -1259,8 +1308,23 @@ struct World {
       ipck::iter_end(stream, envs_d, S, B, L.counter + 3);
       if (read_int(L.counter + 3) == 0) break;
     }
+    set_batch(step_envs);
     ipck::step_end(stream, W, envs_d, S, B);
     HC(hipStreamSynchronize(stream));
+  }
+
+  // Once at most half of the batch is still iterating, lay the batch out
+  // again with those environments only, so that every per-iteration launch
+  // covers their tiles alone.  Each environment's sums run over its own tiles
+  // in their own order, so this changes no result.
+  void narrow_batch() {
+    std::vector<int> st(env_cap);
+    HC(hipMemcpyAsync(st.data(), S.status, 4 * env_cap, hipMemcpyDeviceToHost, stream));
+    HC(hipStreamSynchronize(stream));
+    std::vector<int> live;
+    for (int e : batch_envs)
+      if (st[e] == ipcw::ST_ACTIVE) live.push_back(e);
+    set_batch(live);
   }
 };
 
@@ -1399,10 +1463,8 @@ void run_steps(std::vector<ipc_scene> scenes, int n_steps, ipc_step_info *infos)
     for (auto s : scenes) any |= !s->failed;
     if (!any) break;
     // the motion row follows each env's own step index
-    for (auto s : scenes) {
-      w.envs_h[s->slot].step = s->step;
-      w.upload_env(s->slot);
-    }
+    for (auto s : scenes) w.envs_h[s->slot].step = s->step;
+    w.upload_envs();
     w.step_batch();
     snap.fetch(w);
     for (size_t i = 0; i < scenes.size(); ++i) {
@@ -1434,6 +1496,201 @@ void run_steps(std::vector<ipc_scene> scenes, int n_steps, ipc_step_info *infos)
     HC(hipStreamSynchronize(w.stream));
   }
 }
+
+// ---------------------------------------------------------------------------
+// serving: a worker thread admits queued requests by slot count and memory,
+// steps all running ones together one time step per tick, retires finished
+// ones between ticks
+// ---------------------------------------------------------------------------
+struct Request {
+  int64_t id = 0;
+  std::unique_ptr<HostScene> host;  // until admitted
+  ipc_scene scene = nullptr;        // while running
+  int32_t n_steps = 0, status = IPC_REQ_QUEUED, steps_done = 0, fail_reason = 0;
+  double t_submit = 0.0, t_admit = -1.0, t_done = -1.0;
+  int64_t newton = 0, pcg = 0, bytes = 0;
+  int nv = 0;
+  std::vector<double> pos, vel;  // once finished
+};
+
+}  // namespace
+
+struct ipc_server_s {
+  World *w = nullptr;
+  int64_t budget = 0;
+  int32_t max_slots = 1;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<Request *> queue;
+  std::vector<Request *> running;
+  std::map<int64_t, std::unique_ptr<Request>> reqs;
+  int64_t next_id = 1, used = 0;
+  bool stop = false, dead = false;
+  std::string error;
+  long long finished = 0, failed = 0, conv_steps = 0, ticks = 0;
+  // slot-cap autotuner (max_slots = 0 at creation): while requests wait,
+  // grow the cap by half every window of 16 ticks as long as converged
+  // steps/s keep rising by 3%, then settle on the best cap seen
+  bool auto_slots = false, settled = false;
+  int32_t best_cap = 0;
+  double best_thr = 0.0, win_t0 = 0.0;
+  long long win_ticks = 0, win_steps = 0;
+  std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+  std::thread worker;
+  double now() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
+};
+
+namespace {
+
+void retire(ipc_server_s *sv, Request *r, bool failed, int reason) {
+  // caller holds sv->mu
+  r->status = failed ? IPC_REQ_FAILED : IPC_REQ_DONE;
+  r->fail_reason = failed ? reason : IPC_FAIL_NONE;
+  r->t_done = sv->now();
+  sv->used -= r->bytes;
+  if (failed)
+    ++sv->failed;
+  else
+    ++sv->finished;
+}
+
+void server_loop(ipc_server_s *sv) {
+  std::vector<ipc_step_info> infos;
+  try {
+    HC(hipSetDevice(sv->w->device));
+    while (true) {
+      std::vector<Request *> admit;
+      {
+        std::unique_lock<std::mutex> lk(sv->mu);
+        sv->cv_work.wait(lk, [&]() { return sv->stop || !sv->queue.empty() || !sv->running.empty(); });
+        if (sv->stop) return;
+        while (!sv->queue.empty() && (int)(sv->running.size() + admit.size()) < sv->max_slots &&
+               sv->used + sv->queue.front()->bytes <= sv->budget) {
+          Request *r = sv->queue.front();
+          sv->queue.pop_front();
+          sv->used += r->bytes;
+          admit.push_back(r);
+        }
+      }
+      for (Request *r : admit) {
+        auto *sc = new ipc_scene_s();
+        sc->world = sv->w;
+        {
+          std::lock_guard<std::mutex> lk(sv->w->mu);
+          try {
+            sc->slot = sv->w->add_scene(*r->host);
+          } catch (...) {
+            delete sc;
+            throw;
+          }
+        }
+        sc->host = std::move(r->host);
+        std::lock_guard<std::mutex> lk(sv->mu);
+        r->scene = sc;
+        r->status = IPC_REQ_RUNNING;
+        r->t_admit = sv->now();
+        sv->running.push_back(r);
+      }
+      std::vector<Request *> run;
+      {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        run = sv->running;
+      }
+      if (run.empty()) continue;
+      std::vector<ipc_scene> scenes;
+      for (Request *r : run) scenes.push_back(r->scene);
+      infos.assign(run.size(), ipc_step_info{});
+      run_steps(scenes, 1, infos.data());
+      std::vector<Request *> done;
+      for (size_t i = 0; i < run.size(); ++i) {
+        Request *r = run[i];
+        bool fin = r->scene->failed || r->steps_done + infos[i].steps_done >= r->n_steps;
+        if (fin) {
+          r->pos.resize(3 * (size_t)r->nv);
+          r->vel.resize(3 * (size_t)r->nv);
+          std::lock_guard<std::mutex> lk(sv->w->mu);
+          get_x(*sv->w, r->scene, sv->w->W.x, r->pos.data());
+          get_x(*sv->w, r->scene, sv->w->W.v, r->vel.data());
+          sv->w->remove_scene(r->scene->slot);
+          done.push_back(r);
+        }
+      }
+      std::lock_guard<std::mutex> lk(sv->mu);
+      long long tick_steps = 0;
+      for (size_t i = 0; i < run.size(); ++i) {
+        Request *r = run[i];
+        r->steps_done += infos[i].steps_done;
+        r->newton += infos[i].newton_iters;
+        r->pcg += infos[i].pcg_iters;
+        tick_steps += infos[i].steps_done;
+      }
+      sv->conv_steps += tick_steps;
+      if (sv->auto_slots && !sv->settled) {
+        sv->win_steps += tick_steps;
+        if (++sv->win_ticks >= 16) {
+          double t = sv->now(), thr = sv->win_steps / std::max(t - sv->win_t0, 1e-9);
+          if (!sv->queue.empty()) {  // demand above the cap: the cap is what limits
+            if (thr > 1.03 * sv->best_thr) {
+              sv->best_thr = thr;
+              sv->best_cap = sv->max_slots;
+              sv->max_slots = std::min(1024, sv->max_slots + std::max(1, sv->max_slots / 2));
+            } else {
+              sv->max_slots = sv->best_cap;
+              sv->settled = true;
+            }
+          }
+          sv->win_ticks = 0;
+          sv->win_steps = 0;
+          sv->win_t0 = t;
+        }
+      }
+      for (Request *r : done) {
+        retire(sv, r, r->scene->failed, r->scene->fail_reason);
+        delete r->scene;
+        r->scene = nullptr;
+        sv->running.erase(std::find(sv->running.begin(), sv->running.end(), r));
+      }
+      ++sv->ticks;
+      sv->cv_done.notify_all();
+    }
+  } catch (const std::exception &e) {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->dead = true;
+    sv->error = e.what();
+    for (Request *r : sv->running) {
+      retire(sv, r, true, IPC_FAIL_DEVICE);
+      r->scene = nullptr;  // left with the device's world
+    }
+    for (Request *r : sv->queue) {
+      sv->used += r->bytes;  // retire() subtracts it again
+      retire(sv, r, true, IPC_FAIL_DEVICE);
+    }
+    sv->running.clear();
+    sv->queue.clear();
+    sv->cv_done.notify_all();
+  }
+}
+
+void fill_info(const Request &r, ipc_request_info *info) {
+  info->status = r.status;
+  info->steps_done = r.steps_done;
+  info->n_steps = r.n_steps;
+  info->fail_reason = r.fail_reason;
+  info->t_submit = r.t_submit;
+  info->t_admit = r.t_admit;
+  info->t_done = r.t_done;
+  info->newton_iters = r.newton;
+  info->pcg_iters = r.pcg;
+  info->bytes = r.bytes;
+}
+
+Request &find_req(ipc_server srv, int64_t id) {
+  auto it = srv->reqs.find(id);
+  if (it == srv->reqs.end()) throw ApiError(IPC_E_ARG, "unknown request id");
+  return *it->second;
+}
+
+bool finished(const Request &r) { return r.status == IPC_REQ_DONE || r.status == IPC_REQ_FAILED; }
 
 }  // namespace
 
@@ -1550,6 +1807,8 @@ int ipc_set_tuning(int32_t key, int64_t value) {
       w.tail_tiles = (int)std::min<int64_t>(value, 1 << 30);
     else if (key == IPC_TUNE_FUSED_PCG)
       w.set_fused(value != 0);
+    else if (key == IPC_TUNE_FOLD_DIR)
+      w.fold_dir = value != 0;
     else
       throw ApiError(IPC_E_ARG, "unknown tuning key");
     return IPC_OK;
@@ -1565,6 +1824,8 @@ int ipc_get_tuning(int32_t key, int64_t *value) {
       *value = w.tail_tiles;
     else if (key == IPC_TUNE_FUSED_PCG)
       *value = w.fused_pcg;
+    else if (key == IPC_TUNE_FOLD_DIR)
+      *value = w.fold_dir;
     else
       throw ApiError(IPC_E_ARG, "unknown tuning key");
     return IPC_OK;
@@ -1922,6 +2183,137 @@ int64_t ipc_debug_accd(int32_t kind, int64_t n, const double *x12, const double 
   } catch (const std::exception &e) {
     return api_error(e);
   }
+}
+
+int ipc_server_create(int64_t budget_bytes, int32_t max_slots, ipc_server *out) {
+  return guarded([&]() {
+    if (!out || budget_bytes <= 0 || max_slots < 0) throw ApiError(IPC_E_ARG, "bad server arguments");
+    auto sv = std::make_unique<ipc_server_s>();
+    sv->w = &world_for_current_device();
+    sv->budget = budget_bytes;
+    sv->auto_slots = max_slots == 0;
+    sv->max_slots = sv->auto_slots ? 8 : max_slots;
+    sv->best_cap = sv->max_slots;
+    sv->worker = std::thread(server_loop, sv.get());
+    *out = sv.release();
+    return IPC_OK;
+  });
+}
+
+int ipc_server_submit(ipc_server srv, const ipc_scene_desc *desc, int32_t n_steps, int64_t *id) {
+  return guarded([&]() {
+    if (!srv || !id || n_steps < 1) throw ApiError(IPC_E_ARG, "bad arguments");
+    const double t_arrival = srv->now();  // validation and copying count toward latency
+    auto host = preprocess(desc);
+    auto r = std::make_unique<Request>();
+    r->bytes = (int64_t)srv->w->scene_bytes(*host);
+    if (r->bytes > srv->budget) throw ApiError(IPC_E_NOMEM, "scene exceeds the server's memory budget");
+    r->nv = host->nv;
+    r->n_steps = n_steps;
+    r->host = std::move(host);
+    std::lock_guard<std::mutex> lk(srv->mu);
+    if (srv->dead) throw ApiError(IPC_E_DEVICE, "server stopped: " + srv->error);
+    r->id = srv->next_id++;
+    r->t_submit = t_arrival;
+    *id = r->id;
+    srv->queue.push_back(r.get());
+    srv->reqs[r->id] = std::move(r);
+    srv->cv_work.notify_one();
+    return IPC_OK;
+  });
+}
+
+int ipc_server_poll(ipc_server srv, int64_t id, ipc_request_info *info) {
+  return guarded([&]() {
+    if (!srv || !info) throw ApiError(IPC_E_ARG, "bad arguments");
+    std::lock_guard<std::mutex> lk(srv->mu);
+    fill_info(find_req(srv, id), info);
+    return IPC_OK;
+  });
+}
+
+int ipc_server_wait(ipc_server srv, int64_t id, double timeout_s, ipc_request_info *info) {
+  return guarded([&]() {
+    if (!srv || !(timeout_s >= 0)) throw ApiError(IPC_E_ARG, "bad arguments");
+    std::unique_lock<std::mutex> lk(srv->mu);
+    Request &r = find_req(srv, id);
+    srv->cv_done.wait_for(lk, std::chrono::duration<double>(std::min(timeout_s, 1e7)), [&]() { return finished(r); });
+    if (info) fill_info(r, info);
+    return IPC_OK;
+  });
+}
+
+int ipc_server_result(ipc_server srv, int64_t id, double *pos, double *vel) {
+  return guarded([&]() {
+    if (!srv || !pos) throw ApiError(IPC_E_ARG, "bad arguments");
+    std::lock_guard<std::mutex> lk(srv->mu);
+    Request &r = find_req(srv, id);
+    if (!finished(r)) throw ApiError(IPC_E_ARG, "request has not finished");
+    if (r.pos.empty() && r.nv > 0) throw ApiError(IPC_E_DEVICE, "no state kept: the server stopped");
+    std::memcpy(pos, r.pos.data(), r.pos.size() * sizeof(double));
+    if (vel) std::memcpy(vel, r.vel.data(), r.vel.size() * sizeof(double));
+    return IPC_OK;
+  });
+}
+
+int ipc_server_release(ipc_server srv, int64_t id) {
+  return guarded([&]() {
+    if (!srv) throw ApiError(IPC_E_ARG, "bad arguments");
+    std::lock_guard<std::mutex> lk(srv->mu);
+    Request &r = find_req(srv, id);
+    if (!finished(r)) throw ApiError(IPC_E_ARG, "request has not finished");
+    srv->reqs.erase(id);
+    return IPC_OK;
+  });
+}
+
+int ipc_server_set_slots(ipc_server srv, int32_t max_slots) {
+  return guarded([&]() {
+    if (!srv || max_slots < 1) throw ApiError(IPC_E_ARG, "bad arguments");
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->max_slots = max_slots;
+    srv->auto_slots = false;
+    srv->cv_work.notify_one();
+    return IPC_OK;
+  });
+}
+
+int ipc_server_stats(ipc_server srv, double *out) {
+  return guarded([&]() {
+    if (!srv || !out) throw ApiError(IPC_E_ARG, "bad arguments");
+    std::lock_guard<std::mutex> lk(srv->mu);
+    out[0] = (double)srv->finished;
+    out[1] = (double)srv->failed;
+    out[2] = (double)srv->conv_steps;
+    out[3] = (double)srv->ticks;
+    out[4] = (double)srv->running.size();
+    out[5] = (double)srv->queue.size();
+    out[6] = (double)srv->used;
+    out[7] = srv->now();
+    out[8] = (double)srv->max_slots;
+    return IPC_OK;
+  });
+}
+
+void ipc_server_destroy(ipc_server srv) {
+  if (!srv) return;
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->stop = true;
+  }
+  srv->cv_work.notify_all();
+  if (srv->worker.joinable()) srv->worker.join();
+  try {
+    std::lock_guard<std::mutex> lk(srv->w->mu);
+    for (Request *r : srv->running)
+      if (r->scene) {
+        srv->w->remove_scene(r->scene->slot);
+        delete r->scene;
+        r->scene = nullptr;
+      }
+  } catch (...) {
+  }
+  delete srv;
 }
 
 }  // extern "C"

@@ -21,6 +21,14 @@ struct Batch {
 };
 
 // Dynamic per-iteration lists.
+// one hash-grid entry: a surface primitive registered in one cell, with its
+// box rounded outward to float for a quick rejection test
+struct GridEnt {
+  int code, cx, cy, cz;  // triangle id (>= 0) or ~edge id; cell coordinates
+  float lo[3], hi[3];
+  int env, pad;
+};
+
 struct Lists {
   int *counts, *offs, *scan_tmp;  // item counts, exclusive scan (n_items+1)
   int2 *cand;                     // candidate pairs: PT (sv, tri) or EE (~ea, eb)
@@ -42,7 +50,7 @@ struct Lists {
   int *counter;  // device scratch counters [4]
   // hash grid
   int *g_ncell, *g_big, *g_eoff, *g_bigoff, *g_ebucket, *g_bcnt, *g_boff, *g_bcur, *g_bigl;
-  int4 *g_ent, *g_sorted;
+  GridEnt *g_ent, *g_sorted;
   unsigned long long *prof;  // algorithmic bytes moved by profiled kernels (nullptr = off)
 };
 
@@ -83,14 +91,18 @@ void assemble(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState 
 
 void pcg_init(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L,
               int *pending, int mixed);
-void pcg_iter(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L, int it,
-              int *pending, int mixed, int cap, hipEvent_t ev0, hipEvent_t ev1, const Tile *tiles, int n_tiles);
+// one tiled PCG iteration: product (dir: with the stopping test of the last
+// update and the next direction formed from pp buffer `cur` into the other
+// one), update, and with `last` the stopping test + direction in place
+void pcg_iter(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, Lists &L, int it, int *pending,
+              int mixed, bool dir, int cur, bool last, hipEvent_t ev0, hipEvent_t ev1, const Tile *tiles,
+              int n_tiles);
 // tiles of environments whose PCG still iterates -> out (count at offs[B.n_vt])
 void live_tiles(hipStream_t s, const EnvState &S, const Batch &B, Lists &L, Tile *out, int *flag, int *offs);
 // continues the PCG of the environments whose tiles are listed (one workgroup
 // each) to convergence; `it` = tiled iterations done so far
 void pcg_resume(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, Lists &L, const Tile *tiles,
-                int n_tiles, int it, int mixed);
+                int n_tiles, int it, int cur, int mixed);
 void pcg_finish(hipStream_t s, const WorldDev &W, const EnvState &S, const Batch &B, int mixed);
 // one workgroup per environment for the environments flagged `fused`
 void pcg_fused(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const int *fenv, int n_fenv,

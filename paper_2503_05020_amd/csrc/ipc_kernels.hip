@@ -17,6 +17,7 @@
 
 using namespace ipcw;
 using namespace ipcdev;
+using ipck::GridEnt;
 
 namespace {
 
@@ -368,6 +369,16 @@ DEV unsigned cell_hash(int kind, int env, int cx, int cy, int cz, unsigned mask)
   return h & mask;
 }
 
+// float bounds that enclose a double interval
+DEV float f_down(double v) {
+  float f = (float)v;
+  return ((double)f > v) ? nextafterf(f, -INFINITY) : f;
+}
+DEV float f_up(double v) {
+  float f = (float)v;
+  return ((double)f < v) ? nextafterf(f, INFINITY) : f;
+}
+
 DEV int bitem_index(const EnvDev &E, int kind, int b) {
   return E.bitem_off + (kind == 0 ? (b - E.tri_off) : (E.ntri + b - E.e_off));
 }
@@ -391,7 +402,7 @@ __global__ void k_grid_count(WorldDev W, const EnvDev *envs, EnvState S, const T
 }
 
 __global__ void k_grid_fill(WorldDev W, const EnvDev *envs, EnvState S, const Tile *tiles, const int *eoff,
-                            const int *bigoff, int4 *ent, int *ebucket, int *bcnt, int *bigl, unsigned mask) {
+                            const int *bigoff, GridEnt *ent, int *ebucket, int *bcnt, int *bigl, unsigned mask) {
   Tile t = tiles[blockIdx.x];
   if ((int)threadIdx.x >= t.count || !active_env(S, t.env)) return;
   const EnvDev &E = envs[t.env];
@@ -405,18 +416,30 @@ __global__ void k_grid_fill(WorldDev W, const EnvDev *envs, EnvState S, const Ti
     return;
   }
   int o = eoff[it];
+  GridEnt g;
+  g.code = code;
+  g.env = t.env;
+  g.pad = 0;
+  for (int k = 0; k < 3; ++k) {
+    g.lo[k] = f_down(box[k]);
+    g.hi[k] = f_up(box[3 + k]);
+  }
   for (int cx = lo[0]; cx <= hi[0]; ++cx)
     for (int cy = lo[1]; cy <= hi[1]; ++cy)
       for (int cz = lo[2]; cz <= hi[2]; ++cz) {
         unsigned h = cell_hash(kind, t.env, cx, cy, cz, mask);
-        ent[o] = make_int4(code, cx, cy, cz);
+        g.cx = cx;
+        g.cy = cy;
+        g.cz = cz;
+        ent[o] = g;
         ebucket[o] = (int)h;
         atomicAdd(&bcnt[h], 1);
         ++o;
       }
 }
 
-__global__ void k_grid_place(const int4 *ent, const int *ebucket, int n, const int *boff, int *bcur, int4 *sorted) {
+__global__ void k_grid_place(const GridEnt *ent, const int *ebucket, int n, const int *boff, int *bcur,
+                             GridEnt *sorted) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   int h = ebucket[k];
@@ -435,6 +458,7 @@ __global__ void k_big_seg(const EnvDev *envs, EnvState S, const int *benv, int n
 
 struct QueryPrim {
   double lo[3], hi[3];
+  float flo[3], fhi[3];
   int v0, v1;
   bool akin;
 };
@@ -460,7 +484,7 @@ DEV bool boxes_overlap(const QueryPrim &A, const double *bx) {
 
 template <bool WRITE>
 __global__ void __launch_bounds__(256) k_bp_grid(WorldDev W, const EnvDev *envs, EnvState S, const Tile *tiles,
-                                                 int *counts, const int *offs, int2 *out, const int4 *sorted,
+                                                 int *counts, const int *offs, int2 *out, const GridEnt *sorted,
                                                  const int *boff, const int *bigl, unsigned mask) {
   Tile t = tiles[blockIdx.x];
   if ((int)threadIdx.x >= t.count) return;
@@ -477,6 +501,8 @@ __global__ void __launch_bounds__(256) k_bp_grid(WorldDev W, const EnvDev *envs,
   for (int k = 0; k < 3; ++k) {
     A.lo[k] = bx[k];
     A.hi[k] = bx[3 + k];
+    A.flo[k] = f_down(bx[k]);
+    A.fhi[k] = f_up(bx[3 + k]);
   }
   if (kind == 0) {
     A.v0 = W.sv[a];
@@ -509,14 +535,17 @@ __global__ void __launch_bounds__(256) k_bp_grid(WorldDev W, const EnvDev *envs,
         for (int cz = lo[2]; cz <= hi[2]; ++cz) {
           unsigned hh = cell_hash(kind, t.env, cx, cy, cz, mask);
           for (int e = boff[hh]; e < boff[hh + 1]; ++e) {
-            int4 en = sorted[e];
-            if (en.y != cx || en.z != cy || en.w != cz) continue;
-            if ((kind == 0) != (en.x >= 0)) continue;
-            int b = (kind == 0) ? en.x : ~en.x;
+            const GridEnt &en = sorted[e];
+            if (en.cx != cx || en.cy != cy || en.cz != cz || en.env != t.env) continue;
+            if ((kind == 0) != (en.code >= 0)) continue;
+            // outward-rounded float boxes: no overlap here means none in FP64
+            if (A.flo[0] > en.hi[0] || en.lo[0] > A.fhi[0] || A.flo[1] > en.hi[1] || en.lo[1] > A.fhi[1] ||
+                A.flo[2] > en.hi[2] || en.lo[2] > A.fhi[2])
+              continue;
+            int b = (kind == 0) ? en.code : ~en.code;
             if (kind == 1 && b <= a) continue;
             const double *bb = (kind == 0 ? W.box_tri : W.box_edge) + 6 * b;
-            int benv = (kind == 0) ? W.tri[b].w : W.edge[b].z;
-            if (benv != t.env || !boxes_overlap(A, bb)) continue;
+            if (!boxes_overlap(A, bb)) continue;
             // owner cell: the one holding the lower corner of the intersection
             if ((int)floor(fmax(A.lo[0], bb[0]) / h) != cx || (int)floor(fmax(A.lo[1], bb[1]) / h) != cy ||
                 (int)floor(fmax(A.lo[2], bb[2]) / h) != cz)
@@ -916,8 +945,28 @@ __global__ void k_assemble_sell(WorldDev W, const EnvDev *envs, EnvState S, cons
 // ---------------------------------------------------------------------------
 // block-Jacobi PCG, one independent solve per environment
 // ---------------------------------------------------------------------------
+// new search direction z + beta pp, rounded once (fma) so that every kernel
+// that forms it gets the same bits
 template <typename T>
-DEV void contact_apply(int i, const T *v, const int *inc_off, const int *inc_ent, const int4 *ce_v, const double *ce_H,
+DEV T dir_value(T z, T pp, double beta) {
+  return (T)fma(beta, (double)pp, (double)z);
+}
+
+// the vector a product reads: stored, or the next direction formed on the fly
+template <typename T>
+struct StoredVec {
+  const T *v;
+  DEV double operator[](int k) const { return (double)v[k]; }
+};
+template <typename T>
+struct DirVec {
+  const T *z, *pp;
+  double beta;
+  DEV double operator[](int k) const { return (double)dir_value<T>(z[k], pp[k], beta); }
+};
+
+template <typename V>
+DEV void contact_apply(int i, const V &v, const int *inc_off, const int *inc_ent, const int4 *ce_v, const double *ce_H,
                        double y[3]) {
   for (int j = inc_off[i]; j < inc_off[i + 1]; ++j) {
     int ent = inc_ent[j];
@@ -939,8 +988,8 @@ DEV void contact_apply(int i, const T *v, const int *inc_off, const int *inc_ent
 
 // Sliced-ELL row product, four slots per round so that their column loads,
 // block loads and vector gathers are in flight together.
-template <typename T>
-DEV void sell_apply(const WorldDev &W, int i, const T *v, const T *val, double y[3]) {
+template <typename T, typename V>
+DEV void sell_apply(const WorldDev &W, int i, const V &v, const T *val, double y[3]) {
   const int sl = i / kSlice, lane = i % kSlice;
   const int base = W.slice_pos[sl], wdt = W.slice_w[sl];
   const int *colp = W.col + base + lane;
@@ -958,7 +1007,7 @@ DEV void sell_apply(const WorldDev &W, int i, const T *v, const T *val, double y
 #pragma unroll
       for (int r = 0; r < 9; ++r) m[u][r] = (double)b[r * kSlice];
 #pragma unroll
-      for (int r = 0; r < 3; ++r) x[u][r] = (double)v[3 * c[u] + r];
+      for (int r = 0; r < 3; ++r) x[u][r] = v[3 * c[u] + r];
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -1012,16 +1061,18 @@ DEV void row_init(const WorldDev &W, bool fr, int i, T *p, T *r, T *z, T *pp, co
   }
 }
 
-// q_i = (H pp)_i; returns pp_i . q_i
-template <typename T>
+// q_i = (H v)_i; returns v_i . q_i.  With pp_out, v_i is also stored there.
+template <typename T, typename V>
 DEV double row_spmv(const WorldDev &W, int i, const int *inc_off, const int *inc_ent, const int4 *ce_v,
-                    const double *ce_H, const T *pp, T *q, const T *val) {
+                    const double *ce_H, const V &v, T *q, const T *val, T *pp_out) {
   double y[3], pq = 0.0;
-  sell_apply<T>(W, i, pp, val, y);
-  contact_apply<T>(i, pp, inc_off, inc_ent, ce_v, ce_H, y);
+  sell_apply<T>(W, i, v, val, y);
+  contact_apply(i, v, inc_off, inc_ent, ce_v, ce_H, y);
   for (int c = 0; c < 3; ++c) {
+    double vi = v[3 * i + c];
+    if (pp_out) pp_out[3 * i + c] = (T)vi;
     q[3 * i + c] = (T)y[c];
-    pq += (double)pp[3 * i + c] * (double)(T)y[c];
+    pq += vi * (double)(T)y[c];
   }
   return pq;
 }
@@ -1046,7 +1097,7 @@ DEV void row_update(int i, double alpha, T *p, T *r, T *z, const T *pp, const T 
 
 template <typename T>
 DEV void row_dir(int i, double beta, T *pp, const T *z) {
-  for (int c = 0; c < 3; ++c) pp[3 * i + c] = (T)((double)z[3 * i + c] + beta * (double)pp[3 * i + c]);
+  for (int c = 0; c < 3; ++c) pp[3 * i + c] = dir_value<T>(z[3 * i + c], pp[3 * i + c], beta);
 }
 
 // stopping rule of one environment after `it` iterations
@@ -1092,28 +1143,68 @@ __global__ void k_pcg_env_init(const EnvDev *envs, EnvState S, const int *benv, 
   atomicAdd(pending, 1);
 }
 
-// q = H pp for live environments, partial pp.q per tile
-template <typename T>
+// Stopping test of a live environment after an update (thread 0 of a tile):
+// returns 1 if it stops, else sets beta.  Only the environment's first tile
+// writes the bookkeeping; the iteration counter is advanced by the update
+// kernel, so every tile of this launch reads the same count.
+DEV int pcg_check(const EnvDev &E, EnvState &S, const Tile &t, const double *part_rz_old, const double *part_rz_new,
+                  const double *part_rr_new, int *pending, double &beta) {
+  double rzn = env_tiles_sum(part_rz_new, E), rzo = env_tiles_sum(part_rz_old, E);
+  double rr = env_tiles_sum(part_rr_new, E);
+  int it = S.pcg_it[t.env];
+  int done = pcg_stop(E, rr, S.pcg_bb[t.env], rzo, it);
+  beta = done ? 0.0 : rzn / rzo;
+  if (done && t.rel == 0) {
+    S.pcg_done[t.env] = 1;
+    S.pcg_total[t.env] += it;
+    atomicSub(pending, 1);
+  }
+  return done;
+}
+
+// q = H v for live environments, partial v.q per tile.  DIR = false: v = pp
+// (stored direction).  DIR = true: first the stopping test of the last
+// update, then v = z + beta pp formed on the fly and stored in pp_out.
+template <typename T, bool DIR>
 __global__ void __launch_bounds__(256) k_spmv(WorldDev W, const EnvDev *envs, EnvState S, const Tile *tiles,
                                               const int *inc_off, const int *inc_ent, const int4 *ce_v,
-                                              const double *ce_H, const T *pp, T *q, const T *val, double *part_pq,
+                                              const double *ce_H, const T *pp, const T *z, T *pp_out, T *q,
+                                              const T *val, double *part_pq, const double *part_rz_old,
+                                              const double *part_rz_new, const double *part_rr_new, int *pending,
                                               unsigned long long *prof) {
   __shared__ double sh[TB];
+  __shared__ double s_beta;
+  __shared__ int s_done;
   Tile t = tiles[blockIdx.x];
   if (!pcg_env_live(S, t.env)) return;
+  if (DIR) {
+    if (threadIdx.x == 0) {
+      double beta;
+      s_done = pcg_check(envs[t.env], S, t, part_rz_old, part_rz_new, part_rr_new, pending, beta);
+      s_beta = beta;
+    }
+    __syncthreads();
+    if (s_done) return;
+  }
   int i = t.start + threadIdx.x;
   double pq = 0.0;
-  if ((int)threadIdx.x < t.count) pq = row_spmv<T>(W, i, inc_off, inc_ent, ce_v, ce_H, pp, q, val);
+  if ((int)threadIdx.x < t.count) {
+    if (DIR)
+      pq = row_spmv<T>(W, i, inc_off, inc_ent, ce_v, ce_H, DirVec<T>{z, pp, s_beta}, q, val, pp_out);
+    else
+      pq = row_spmv<T>(W, i, inc_off, inc_ent, ce_v, ce_H, StoredVec<T>{pp}, q, val, (T *)nullptr);
+  }
   pq = block_sum(pq, sh);
   if (threadIdx.x == 0) part_pq[tile_slot(envs, t)] = pq;
   if (prof) {
-    // algorithmic bytes of this tile: stored blocks + column indices, one read
-    // of pp and one write of q per row, and the contact blocks it applies
+    // algorithmic bytes of this tile: stored blocks + column indices, the
+    // vector rows read and written (v and q; with DIR also z, pp and pp_out),
+    // and the contact blocks it applies
     double b = 0.0;
     if ((int)threadIdx.x < t.count) {
       int nnz = W.row_nnz[i];
       int ninc = inc_off[i + 1] - inc_off[i];
-      b = (double)nnz * (9.0 * sizeof(T) + 4.0) + 6.0 * sizeof(T) + ninc * (4.0 * 72.0 + 16.0);
+      b = (double)nnz * (9.0 * sizeof(T) + 4.0) + (DIR ? 12.0 : 6.0) * sizeof(T) + ninc * (4.0 * 72.0 + 16.0);
     }
     b = block_sum(b, sh);
     if (threadIdx.x == 0) atomicAdd(prof, (unsigned long long)b);
@@ -1143,9 +1234,11 @@ __global__ void k_pcg_update(WorldDev W, const EnvDev *envs, EnvState S, const T
   if (threadIdx.x == 0) {
     part_rz_new[tile_slot(envs, t)] = rz;
     part_rr_new[tile_slot(envs, t)] = rr;
+    if (t.rel == 0) S.pcg_it[t.env] += 1;
   }
 }
 
+// stopping test and pp = z + beta pp in place (last iteration of a block)
 template <typename T>
 __global__ void k_pcg_dir(WorldDev W, const EnvDev *envs, EnvState S, const Tile *tiles, const double *part_rz_old,
                           const double *part_rz_new, const double *part_rr_new, T *pp, const T *z, int *pending) {
@@ -1153,28 +1246,15 @@ __global__ void k_pcg_dir(WorldDev W, const EnvDev *envs, EnvState S, const Tile
   __shared__ int s_done;
   Tile t = tiles[blockIdx.x];
   if (!pcg_env_live(S, t.env)) return;
-  const EnvDev &E = envs[t.env];
   if (threadIdx.x == 0) {
-    double rzn = env_tiles_sum(part_rz_new, E), rzo = env_tiles_sum(part_rz_old, E);
-    double rr = env_tiles_sum(part_rr_new, E);
-    int done = pcg_stop(E, rr, S.pcg_bb[t.env], rzo, S.pcg_it[t.env] + 1);
-    s_done = done;
-    s_beta = done ? 0.0 : rzn / rzo;
+    double beta;
+    s_done = pcg_check(envs[t.env], S, t, part_rz_old, part_rz_new, part_rr_new, pending, beta);
+    s_beta = beta;
   }
   __syncthreads();
-  if (s_done) {
-    if (threadIdx.x == 0 && t.rel == 0) {
-      S.pcg_done[t.env] = 1;
-      S.pcg_it[t.env] += 1;
-      S.pcg_total[t.env] += S.pcg_it[t.env];
-      atomicSub(pending, 1);
-    }
-    return;
-  }
-  double beta = s_beta;
+  if (s_done) return;
   int i = t.start + threadIdx.x;
-  if ((int)threadIdx.x < t.count) row_dir<T>(i, beta, pp, z);
-  if (threadIdx.x == 0 && t.rel == 0) S.pcg_it[t.env] += 1;
+  if ((int)threadIdx.x < t.count) row_dir<T>(i, s_beta, pp, z);
 }
 
 // ---------------------------------------------------------------------------
@@ -1221,7 +1301,7 @@ DEV int env_iterate(const WorldDev &W, const EnvDev &E, const int *inc_off, cons
       int i = base + threadIdx.x;
       double pq = 0.0;
       if (i < r1) {
-        pq = row_spmv<T>(W, i, inc_off, inc_ent, ce_v, ce_H, pp, q, val);
+        pq = row_spmv<T>(W, i, inc_off, inc_ent, ce_v, ce_H, StoredVec<T>{pp}, q, val, (T *)nullptr);
         if (prof)
           bytes += (double)W.row_nnz[i] * (9.0 * sizeof(T) + 4.0) + 6.0 * sizeof(T) +
                    (inc_off[i + 1] - inc_off[i]) * (4.0 * 72.0 + 16.0);
@@ -1344,8 +1424,9 @@ __global__ void k_spmv_dbg(WorldDev W, EnvState S, const Tile *tiles, const int 
   if ((int)threadIdx.x >= t.count || !active_env(S, t.env)) return;
   int i = t.start + threadIdx.x;
   double y[3];
-  sell_apply<double>(W, i, in, W.val, y);
-  contact_apply<double>(i, in, inc_off, inc_ent, ce_v, ce_H, y);
+  StoredVec<double> v{in};
+  sell_apply<double>(W, i, v, W.val, y);
+  contact_apply(i, v, inc_off, inc_ent, ce_v, ce_H, y);
   for (int c = 0; c < 3; ++c) out[3 * i + c] = y[c];
 }
 
@@ -1886,28 +1967,52 @@ void live_tiles(hipStream_t s, const EnvState &S, const Batch &B, Lists &L, Tile
   IPC_LAUNCH(k_live_compact, nblk(B.n_vt, TB), TB, s)(B.vtiles, B.n_vt, flag, offs, out);
 }
 
-void pcg_iter(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L, int it,
-              int *pending, int mixed, int cap, hipEvent_t ev0, hipEvent_t ev1, const Tile *tiles, int n_tiles) {
+void pcg_iter(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, Lists &L, int it, int *pending,
+              int mixed, bool dir, int cur, bool last, hipEvent_t ev0, hipEvent_t ev1, const Tile *tiles,
+              int n_tiles) {
   if (!n_tiles) return;
-  double *rz_old = (it & 1) ? L.part_b1 : L.part_b0;
-  double *rz_new = (it & 1) ? L.part_b0 : L.part_b1;
-  double *rr_new = (it & 1) ? L.part_c0 : L.part_c1;
+  // bytes are counted only for the launches that are timed
+  unsigned long long *prof = ev0 ? L.prof : nullptr;
+  // per-tile partials, two slots each used alternately: rz_cur / rr_cur from
+  // the last update (rz_cur gives alpha), rz_prev from the one before it;
+  // this iteration's update writes rz_new (over rz_prev) and rr_new
+  double *rz_prev = (it & 1) ? L.part_b0 : L.part_b1;
+  double *rz_cur = (it & 1) ? L.part_b1 : L.part_b0;
+  double *rr_cur = (it & 1) ? L.part_c1 : L.part_c0;
+  double *rz_new = rz_prev, *rr_new = (it & 1) ? L.part_c0 : L.part_c1;
+  const int nxt = dir ? 1 - cur : cur;
   if (!mixed) {
+    double *ppi = cur ? W.pp2 : W.pp, *ppo = nxt ? W.pp2 : W.pp;
     if (ev0) hipEventRecord(ev0, s);
-    IPC_LAUNCH(k_spmv<double>, n_tiles, TB, s)(W, E, S, tiles, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, W.pp, W.q, W.val,
-                                         L.part_a, L.prof);
+    if (dir)
+      IPC_LAUNCH((k_spmv<double, true>), n_tiles, TB, s)(W, E, S, tiles, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, ppi,
+                                                        W.z, ppo, W.q, W.val, L.part_a, rz_prev, rz_cur, rr_cur,
+                                                        pending, prof);
+    else
+      IPC_LAUNCH((k_spmv<double, false>), n_tiles, TB, s)(W, E, S, tiles, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, ppi,
+                                                         W.z, nullptr, W.q, W.val, L.part_a, nullptr, nullptr,
+                                                         nullptr, pending, prof);
     if (ev1) hipEventRecord(ev1, s);
-    IPC_LAUNCH(k_pcg_update<double>, n_tiles, TB, s)(W, E, S, tiles, L.part_a, rz_old, rz_new, rr_new, W.p, W.r, W.z,
-                                               W.pp, W.q, W.Minv);
-    IPC_LAUNCH(k_pcg_dir<double>, n_tiles, TB, s)(W, E, S, tiles, rz_old, rz_new, rr_new, W.pp, W.z, pending);
+    IPC_LAUNCH(k_pcg_update<double>, n_tiles, TB, s)(W, E, S, tiles, L.part_a, rz_cur, rz_new, rr_new, W.p, W.r, W.z,
+                                                     ppo, W.q, W.Minv);
+    if (last)
+      IPC_LAUNCH(k_pcg_dir<double>, n_tiles, TB, s)(W, E, S, tiles, rz_cur, rz_new, rr_new, ppo, W.z, pending);
   } else {
+    float *ppi = cur ? W.pp2_32 : W.pp32, *ppo = nxt ? W.pp2_32 : W.pp32;
     if (ev0) hipEventRecord(ev0, s);
-    IPC_LAUNCH(k_spmv<float>, n_tiles, TB, s)(W, E, S, tiles, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, W.pp32, W.q32,
-                                        W.val32, L.part_a, L.prof);
+    if (dir)
+      IPC_LAUNCH((k_spmv<float, true>), n_tiles, TB, s)(W, E, S, tiles, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, ppi,
+                                                       W.z32, ppo, W.q32, W.val32, L.part_a, rz_prev, rz_cur, rr_cur,
+                                                       pending, prof);
+    else
+      IPC_LAUNCH((k_spmv<float, false>), n_tiles, TB, s)(W, E, S, tiles, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, ppi,
+                                                        W.z32, nullptr, W.q32, W.val32, L.part_a, nullptr, nullptr,
+                                                        nullptr, pending, prof);
     if (ev1) hipEventRecord(ev1, s);
-    IPC_LAUNCH(k_pcg_update<float>, n_tiles, TB, s)(W, E, S, tiles, L.part_a, rz_old, rz_new, rr_new, W.p32, W.r32,
-                                              W.z32, W.pp32, W.q32, W.Minv32);
-    IPC_LAUNCH(k_pcg_dir<float>, n_tiles, TB, s)(W, E, S, tiles, rz_old, rz_new, rr_new, W.pp32, W.z32, pending);
+    IPC_LAUNCH(k_pcg_update<float>, n_tiles, TB, s)(W, E, S, tiles, L.part_a, rz_cur, rz_new, rr_new, W.p32, W.r32,
+                                                    W.z32, ppo, W.q32, W.Minv32);
+    if (last)
+      IPC_LAUNCH(k_pcg_dir<float>, n_tiles, TB, s)(W, E, S, tiles, rz_cur, rz_new, rr_new, ppo, W.z32, pending);
   }
 }
 
@@ -1916,15 +2021,15 @@ void pcg_fused(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState
   if (!n_fenv) return;
   if (!mixed)
     IPC_LAUNCH(k_pcg_fused<double>, n_fenv, FB, s)(W, E, S, fenv, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, W.p, W.r, W.z,
-                                                  W.pp, W.q, W.val, W.Minv, L.part_a, L.part_b0, L.part_c0, L.prof);
+                                                  W.pp, W.q, W.val, W.Minv, L.part_a, L.part_b0, L.part_c0, nullptr);
   else
     IPC_LAUNCH(k_pcg_fused<float>, n_fenv, FB, s)(W, E, S, fenv, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, W.p32, W.r32,
                                                  W.z32, W.pp32, W.q32, W.val32, W.Minv32, L.part_a, L.part_b0,
-                                                 L.part_c0, L.prof);
+                                                 L.part_c0, nullptr);
 }
 
 void pcg_resume(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, Lists &L, const Tile *tiles,
-                int n_tiles, int it, int mixed) {
+                int n_tiles, int it, int cur, int mixed) {
   if (!n_tiles) return;
   // after `it` tiled iterations the current rz partials are in part_b1 (odd)
   // or part_b0 (even); the per-environment loop then uses the other pair
@@ -1933,12 +2038,12 @@ void pcg_resume(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvStat
   double *rr_tmp = (it & 1) ? L.part_c0 : L.part_c1;
   if (!mixed)
     IPC_LAUNCH(k_pcg_resume<double>, n_tiles, FB, s)(W, E, S, tiles, rz, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, W.p,
-                                                     W.r, W.z, W.pp, W.q, W.val, W.Minv, L.part_a, rz_tmp, rr_tmp,
-                                                     L.prof);
+                                                     W.r, W.z, cur ? W.pp2 : W.pp, W.q, W.val, W.Minv, L.part_a, rz_tmp, rr_tmp,
+                                                     nullptr);
   else
     IPC_LAUNCH(k_pcg_resume<float>, n_tiles, FB, s)(W, E, S, tiles, rz, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, W.p32,
-                                                    W.r32, W.z32, W.pp32, W.q32, W.val32, W.Minv32, L.part_a, rz_tmp,
-                                                    rr_tmp, L.prof);
+                                                    W.r32, W.z32, cur ? W.pp2_32 : W.pp32, W.q32, W.val32, W.Minv32, L.part_a, rz_tmp,
+                                                    rr_tmp, nullptr);
 }
 
 void pcg_finish(hipStream_t s, const WorldDev &W, const EnvState &S, const Batch &B, int mixed) {

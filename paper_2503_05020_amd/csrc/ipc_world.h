@@ -70,8 +70,8 @@ struct EnvState {
 // Flat device arrays of the world (element-indexed).
 struct WorldDev {
   // per vertex
-  double *X, *x, *v, *xn, *xh, *p, *g, *r, *z, *pp, *q, *mass, *Minv, *e_v, *lam;
-  float *r32, *z32, *pp32, *q32, *p32, *Minv32;
+  double *X, *x, *v, *xn, *xh, *p, *g, *r, *z, *pp, *pp2, *q, *mass, *Minv, *e_v, *lam;
+  float *r32, *z32, *pp32, *pp2_32, *q32, *p32, *Minv32;
   int *kin, *venv, *vt_beg, *vt_end, *row_nnz;
   // per slice (vertex / 64)
   int *slice_pos, *slice_w;

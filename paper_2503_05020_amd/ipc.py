@@ -25,6 +25,7 @@ IPC_FP64 = 0
 IPC_MIXED = 1
 IPC_TUNE_TAIL_TILES = 1
 IPC_TUNE_FUSED_PCG = 2
+IPC_TUNE_FOLD_DIR = 3
 FAIL_REASONS = {0: "none", 1: "maxit", 2: "nonfinite", 3: "line-search", 4: "dirichlet"}
 
 _dp = C.POINTER(C.c_double)
@@ -61,7 +62,22 @@ EXPORTS = [
     "ipc_debug_gradient", "ipc_debug_energy", "ipc_debug_hessian_apply", "ipc_debug_newton_dir",
     "ipc_debug_ccd_bound", "ipc_debug_classify", "ipc_debug_pair_barrier", "ipc_debug_tet_elastic",
     "ipc_debug_accd", "ipc_prof_enable", "ipc_prof_reset", "ipc_prof_read", "ipc_set_tuning", "ipc_get_tuning",
+    "ipc_server_create", "ipc_server_submit", "ipc_server_poll", "ipc_server_wait", "ipc_server_result",
+    "ipc_server_release", "ipc_server_set_slots", "ipc_server_stats", "ipc_server_destroy",
 ]
+
+IPC_REQ_QUEUED, IPC_REQ_RUNNING, IPC_REQ_DONE, IPC_REQ_FAILED = 0, 1, 2, 3
+
+
+class ipc_request_info(C.Structure):
+    _fields_ = [
+        ("status", C.c_int32), ("steps_done", C.c_int32), ("n_steps", C.c_int32), ("fail_reason", C.c_int32),
+        ("t_submit", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double),
+        ("newton_iters", C.c_int64), ("pcg_iters", C.c_int64), ("bytes", C.c_int64),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 _lib = None
 
@@ -106,6 +122,16 @@ def lib():
     L.ipc_prof_read.argtypes = [_dp]
     L.ipc_set_tuning.argtypes = [C.c_int32, C.c_int64]
     L.ipc_get_tuning.argtypes = [C.c_int32, C.POINTER(C.c_int64)]
+    L.ipc_server_create.argtypes = [C.c_int64, C.c_int32, C.POINTER(vp)]
+    L.ipc_server_submit.argtypes = [vp, C.POINTER(ipc_scene_desc), C.c_int32, C.POINTER(C.c_int64)]
+    L.ipc_server_poll.argtypes = [vp, C.c_int64, C.POINTER(ipc_request_info)]
+    L.ipc_server_wait.argtypes = [vp, C.c_int64, C.c_double, C.POINTER(ipc_request_info)]
+    L.ipc_server_result.argtypes = [vp, C.c_int64, _dp, _dp]
+    L.ipc_server_release.argtypes = [vp, C.c_int64]
+    L.ipc_server_set_slots.argtypes = [vp, C.c_int32]
+    L.ipc_server_stats.argtypes = [vp, _dp]
+    L.ipc_server_destroy.argtypes = [vp]
+    L.ipc_server_destroy.restype = None
     _lib = L
     return L
 
@@ -258,6 +284,73 @@ def ipc_get_tuning(key: int) -> int:
     out = C.c_int64()
     _check(lib().ipc_get_tuning(key, C.byref(out)))
     return int(out.value)
+
+
+# --- serving -----------------------------------------------------------------
+class Server:
+    """Handle of a serving loop on the current device (see ipc_server_* in ipc.h)."""
+
+    def __init__(self, h):
+        self.h = h
+        self.nv = {}
+
+
+def ipc_server_create(budget_bytes: int, max_slots: int) -> Server:
+    h = C.c_void_p()
+    _check(lib().ipc_server_create(int(budget_bytes), int(max_slots), C.byref(h)))
+    return Server(h)
+
+
+def ipc_server_submit(srv: Server, sc: dict, n_steps: int, precision: int = IPC_FP64, pcg_rel_tol: float = 1e-4,
+                      **overrides) -> int:
+    d, keep = make_desc(sc, precision, pcg_rel_tol, **overrides)
+    rid = C.c_int64()
+    _check(lib().ipc_server_submit(srv.h, C.byref(d), int(n_steps), C.byref(rid)))
+    srv.nv[rid.value] = len(keep["kin"])
+    return int(rid.value)
+
+
+def ipc_server_poll(srv: Server, rid: int) -> dict:
+    info = ipc_request_info()
+    _check(lib().ipc_server_poll(srv.h, int(rid), C.byref(info)))
+    return info.as_dict()
+
+
+def ipc_server_wait(srv: Server, rid: int, timeout_s: float = 1e6) -> dict:
+    info = ipc_request_info()
+    _check(lib().ipc_server_wait(srv.h, int(rid), float(timeout_s), C.byref(info)))
+    return info.as_dict()
+
+
+def ipc_server_result(srv: Server, rid: int):
+    n = srv.nv[int(rid)]
+    pos = np.zeros((n, 3))
+    vel = np.zeros((n, 3))
+    _check(lib().ipc_server_result(srv.h, int(rid), _d(pos), _d(vel)))
+    return pos, vel
+
+
+def ipc_server_release(srv: Server, rid: int):
+    _check(lib().ipc_server_release(srv.h, int(rid)))
+    srv.nv.pop(int(rid), None)
+
+
+def ipc_server_set_slots(srv: Server, max_slots: int):
+    _check(lib().ipc_server_set_slots(srv.h, int(max_slots)))
+
+
+def ipc_server_stats(srv: Server) -> dict:
+    out = np.zeros(9)
+    _check(lib().ipc_server_stats(srv.h, _d(out)))
+    keys = ["finished", "failed", "converged_steps", "ticks", "running", "queued", "bytes_in_use", "seconds",
+            "slot_cap"]
+    return dict(zip(keys, out.tolist()))
+
+
+def ipc_server_destroy(srv: Server):
+    if srv.h is not None and _lib is not None:
+        _lib.ipc_server_destroy(srv.h)
+        srv.h = None
 
 
 # --- inspection entry points -------------------------------------------------

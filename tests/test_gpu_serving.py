@@ -1,0 +1,117 @@
+"""Serving loop (continuous batching) on the GPU: admission by slots and memory, requests joining
+and leaving a running batch, and results that are bitwise the same alone and in the mix."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_2503_05020_amd import ipc as G
+from paper_2503_05020_amd import scenes as S
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def _cube(i, steps_height=0.002):
+    return S.soft_cube_drop(cells=2, edge=0.04, height=steps_height + 0.001 * i, seed=i)
+
+
+def _run_alone(sc, n_steps):
+    g = G.ipc_create_scene(sc)
+    rc, info = G.ipc_step(g, n_steps)
+    pos, vel = G.ipc_get_state(g)
+    G.ipc_destroy_scene(g)
+    return rc, info, pos, vel
+
+
+def test_server_result_same_alone_and_in_mix():
+    say("server alone vs mix")
+    scs = [_cube(i) for i in range(5)]
+    steps = [6, 9, 4, 7, 5]
+    # request 2 through the plain API and through a server on its own
+    rc, info, ref_pos, ref_vel = _run_alone(scs[2], steps[2])
+    assert rc == 0 and info["steps_done"] == steps[2]
+    srv = G.ipc_server_create(1 << 30, 4)
+    try:
+        rid = G.ipc_server_submit(srv, scs[2], steps[2])
+        inf = G.ipc_server_wait(srv, rid, 120.0)
+        assert inf["status"] == G.IPC_REQ_DONE and inf["steps_done"] == steps[2], inf
+        pos, vel = G.ipc_server_result(srv, rid)
+        assert np.array_equal(pos, ref_pos) and np.array_equal(vel, ref_vel)
+    finally:
+        G.ipc_server_destroy(srv)
+    # the same request in a mix: staggered arrivals, a slot cap of 3 and a budget that holds only two
+    # scenes, so requests queue, join a running batch and leave it at different steps
+    srv = G.ipc_server_create(1 << 30, 3)
+    try:
+        ids = []
+        for k, (sc, n) in enumerate(zip(scs, steps)):
+            ids.append(G.ipc_server_submit(srv, sc, n))
+            time.sleep(0.02 * k)
+        infos = [G.ipc_server_wait(srv, i, 300.0) for i in ids]
+        for i, inf in zip(ids, infos):
+            assert inf["status"] == G.IPC_REQ_DONE, inf
+        assert [inf["steps_done"] for inf in infos] == steps
+        pos, vel = G.ipc_server_result(srv, ids[2])
+        assert np.array_equal(pos, ref_pos) and np.array_equal(vel, ref_vel)
+        # every request matches its own alone run
+        for sc, n, i in zip(scs, steps, ids):
+            _, _, p_alone, _ = _run_alone(sc, n)
+            assert np.array_equal(G.ipc_server_result(srv, i)[0], p_alone)
+        st = G.ipc_server_stats(srv)
+        say(st)
+        assert st["finished"] == 5 and st["failed"] == 0 and st["converged_steps"] == sum(steps)
+        assert st["running"] == 0 and st["queued"] == 0 and st["bytes_in_use"] == 0
+        for inf in infos:
+            assert 0 <= inf["t_submit"] <= inf["t_admit"] <= inf["t_done"]
+    finally:
+        G.ipc_server_destroy(srv)
+
+
+def test_server_admits_by_memory():
+    scs = [_cube(i) for i in range(4)]
+    probe = G.ipc_server_create(1 << 30, 1)
+    try:
+        rid = G.ipc_server_submit(probe, scs[0], 1)
+        one = G.ipc_server_wait(probe, rid, 120.0)["bytes"]
+    finally:
+        G.ipc_server_destroy(probe)
+    assert one > 0
+    budget = int(2.5 * max(one, 1))  # two of these scenes fit, a third does not
+    srv = G.ipc_server_create(budget, 8)
+    try:
+        ids = [G.ipc_server_submit(srv, sc, 3) for sc in scs]
+        infos = [G.ipc_server_wait(srv, i, 300.0) for i in ids]
+        assert all(inf["status"] == G.IPC_REQ_DONE for inf in infos)
+        # at most two ran at once: the third was admitted only after one of the first two finished
+        done_sorted = sorted(inf["t_done"] for inf in infos[:2])
+        assert infos[2]["t_admit"] >= done_sorted[0]
+        with pytest.raises(G.IPCError) as e:
+            G.ipc_server_submit(srv, S.soft_cube_drop(cells=5), 1)  # larger than the whole budget
+        assert e.value.code == G.IPC_E_NOMEM
+    finally:
+        G.ipc_server_destroy(srv)
+
+
+def test_server_failure_is_isolated():
+    scs = [_cube(i) for i in range(3)]
+    srv = G.ipc_server_create(1 << 30, 4)
+    try:
+        ok1 = G.ipc_server_submit(srv, scs[0], 8)
+        bad = G.ipc_server_submit(srv, scs[1], 8, newton_max_iter=1)
+        ok2 = G.ipc_server_submit(srv, scs[2], 8)
+        i_bad = G.ipc_server_wait(srv, bad, 120.0)
+        assert i_bad["status"] == G.IPC_REQ_FAILED and i_bad["fail_reason"] == 1
+        for rid, sc in ((ok1, scs[0]), (ok2, scs[2])):
+            inf = G.ipc_server_wait(srv, rid, 120.0)
+            assert inf["status"] == G.IPC_REQ_DONE and inf["steps_done"] == 8
+            _, _, p_alone, _ = _run_alone(sc, 8)
+            assert np.array_equal(G.ipc_server_result(srv, rid)[0], p_alone)
+        G.ipc_server_release(srv, ok1)
+        with pytest.raises(G.IPCError):
+            G.ipc_server_poll(srv, ok1)
+    finally:
+        G.ipc_server_destroy(srv)
