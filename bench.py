@@ -178,6 +178,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=48, help="0 skips the serving run")
     ap.add_argument("--serve-slots", type=int, default=0, help="0 = slot cap tuned by the server")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="only run a plain device copy of this many MiB, 5 times (calibrates HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: environments are independent and would be sharded across GPUs "
@@ -186,6 +188,15 @@ def main():
     import torch  # device selection only
     assert torch.cuda.is_available(), "no GPU"
     torch.cuda.set_device(0)
+    if args.copy_probe > 0:
+        n = args.copy_probe << 20
+        src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": n, "copy_probe_bytes_written": n, "launches": 5}), flush=True)
+        return
     scs = make_scenes(args.workload, args.envs)
     ntets = sum(len(sc["E"]) for sc in scs)
     log(f"workload {args.workload}: {len(scs)} envs, {ntets} tets")

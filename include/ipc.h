@@ -154,11 +154,16 @@ int ipc_prof_read(double *out);
  *     whole PCG in one workgroup from the start (default 0; IPC_FUSED_PCG).
  *   IPC_TUNE_FOLD_DIR: 1 = the tiled PCG forms the next search direction
  *     inside the following matrix-vector product (two launches per
- *     iteration; default), 0 = a separate direction kernel (IPC_FOLD_DIR).
+ *     iteration), 0 = a separate direction kernel (default; the extra
+ *     vector gathers cost more than the launch they save; IPC_FOLD_DIR).
+ *   IPC_TUNE_NARROW: 1 = once at most half of a batch still iterates its
+ *     Newton loop, the batch is laid out again with those environments only
+ *     (default), 0 = never (IPC_NARROW).
  * Returns IPC_OK, or IPC_E_ARG for an unknown key or a negative value. */
 #define IPC_TUNE_TAIL_TILES 1
 #define IPC_TUNE_FUSED_PCG 2
 #define IPC_TUNE_FOLD_DIR 3
+#define IPC_TUNE_NARROW 4
 int ipc_set_tuning(int32_t key, int64_t value);
 int ipc_get_tuning(int32_t key, int64_t *value);
 
@@ -250,9 +255,9 @@ typedef struct {
 
 /* Creates a server on the current device.  budget_bytes > 0; max_slots >= 1
  * fixes the slot cap, max_slots = 0 lets the server tune it: starting at 8,
- * while requests are waiting it raises the cap by half after every 16 ticks
- * whose converged steps/s beat the best window so far by 3%, and otherwise
- * settles on the best cap. */
+ * while requests are waiting it raises the cap by half after every window of
+ * 16 ticks, unless that window's seconds per converged step exceed 1.5x the
+ * best window's, in which case it settles on the best window's cap. */
 int ipc_server_create(int64_t budget_bytes, int32_t max_slots, ipc_server *out);
 /* Validates and copies the scene (as ipc_create_scene; same error codes, and
  * IPC_E_NOMEM if it alone exceeds the budget) and queues it for n_steps >= 1

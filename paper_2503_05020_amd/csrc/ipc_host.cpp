@@ -883,6 +883,7 @@ struct World {
   // ---- batch set-up -------------------------------------------------------
   void set_batch(const std::vector<int> &envs) {
     if (envs == batch_envs) return;
+    swept_n = -1;  // candidate lists follow the batch layout
     std::vector<Tile> vt, tt, svt, trit, et, it, bt;
     int item_off = 0, bitem_off = 0;
     fused_h.clear();
@@ -1128,9 +1129,17 @@ struct World {
     HC(hipMemcpyAsync(dst, src, sizeof(int) * env_cap, hipMemcpyDeviceToDevice, stream));
   }
 
+  // Candidate list left by the last swept pass (x -> x + p, d̂-widened) when
+  // every environment of the batch has since moved to x + a p with a in
+  // [0, 1] (or kept x): the boxes of a static pass at the new x lie inside
+  // those swept boxes, so the list holds every pair a static pass would find,
+  // and the exact d² < d̂² test picks the same active set.  -1: none.
+  int swept_n = -1;
+
   // gradient, contact elements, incidence, assembled Hessian at W.x
   int assemble_system(int mixed) {
-    int nc = broad_phase(W.x, nullptr);
+    int nc = swept_n >= 0 ? swept_n : broad_phase(W.x, nullptr);
+    swept_n = -1;
     int na = active_pairs(nc, W.x);
     ensure_ce(na + n_fric);
     ipck::barrier_elems(stream, W, envs_d, L, na, W.x);
@@ -1160,7 +1169,10 @@ struct World {
   int tail_tiles = env_knob("IPC_TAIL_TILES", 0);
   // 1: the direction update is folded into the next product (two launches
   // per PCG iteration); 0: a separate direction kernel every iteration
-  int fold_dir = env_knob("IPC_FOLD_DIR", 1) ? 1 : 0;
+  int fold_dir = env_knob("IPC_FOLD_DIR", 0) ? 1 : 0;
+  // 1: re-lay the batch out with the still-iterating environments once at
+  // most half of it iterates (narrow_batch)
+  int narrow = env_knob("IPC_NARROW", 1) ? 1 : 0;
   bool use_fused() const { return fused_pcg == 1; }
   void set_fused(int on) {
     if ((on != 0) == use_fused()) return;
@@ -1263,6 +1275,7 @@ struct World {
     auto ms = [&]() {
       return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     };
+    swept_n = -1;
     ipck::env_begin(stream, S, B);
     ipck::begin_step(stream, W, envs_d, S, B);
     friction_setup();
@@ -1273,6 +1286,7 @@ struct World {
     ipck::dbc_check_J(stream, W, envs_d, S, B);
     ipck::env_dbc(stream, S, B);
     ipck::apply_dbc(stream, W, envs_d, S, B);
+    swept_n = nc;  // x is xn, or the targets on kinematic rows: inside these boxes
     int maxit = 0;
     for (int e : batch_envs) maxit = std::max(maxit, envs_h[e].maxit);
     int mixed = 0;
@@ -1287,7 +1301,7 @@ struct World {
         std::fprintf(stderr, "[ipc] newton %d: active pairs %d friction %d pcg %lld envs-left %d  %.1f ms\n", it, na,
                      n_fric, pit, still, ms());
       if (still == 0) break;
-      if (2 * still <= (int)batch_envs.size()) narrow_batch();
+      if (narrow && 2 * still <= (int)batch_envs.size()) narrow_batch();
       ipck::al_prepare(stream, W, S, B);
       int ns = broad_phase(W.x, W.p);
       ipck::ccd_init(stream, S, B);
@@ -1305,9 +1319,11 @@ struct World {
       if (tracing()) std::fprintf(stderr, "[ipc]   swept %d line-search trials %d  %.1f ms\n", ns, trials, ms());
       ipck::al_finish(stream, W, envs_d, S, B);
       ipck::update_x(stream, W, S, B);
+      swept_n = ns;  // x moved by a p with a <= 1, snapped inside the swept boxes, or stayed
       ipck::iter_end(stream, envs_d, S, B, L.counter + 3);
       if (read_int(L.counter + 3) == 0) break;
     }
+    swept_n = -1;
     set_batch(step_envs);
     ipck::step_end(stream, W, envs_d, S, B);
     HC(hipStreamSynchronize(stream));
@@ -1529,11 +1545,13 @@ struct ipc_server_s {
   std::string error;
   long long finished = 0, failed = 0, conv_steps = 0, ticks = 0;
   // slot-cap autotuner (max_slots = 0 at creation): while requests wait,
-  // grow the cap by half every window of 16 ticks as long as converged
-  // steps/s keep rising by 3%, then settle on the best cap seen
+  // grow the cap by half after every window of 16 ticks, unless the window's
+  // seconds per converged step exceed 1.5x the best window's: then settle on
+  // the best window's cap.  A tick costs about its slowest environment's
+  // step, so more slots raise throughput until the device saturates.
   bool auto_slots = false, settled = false;
   int32_t best_cap = 0;
-  double best_thr = 0.0, win_t0 = 0.0;
+  double best_cost = 0.0, win_t0 = 0.0;
   long long win_ticks = 0, win_steps = 0;
   std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
   std::thread worker;
@@ -1628,15 +1646,18 @@ void server_loop(ipc_server_s *sv) {
       if (sv->auto_slots && !sv->settled) {
         sv->win_steps += tick_steps;
         if (++sv->win_ticks >= 16) {
-          double t = sv->now(), thr = sv->win_steps / std::max(t - sv->win_t0, 1e-9);
+          double t = sv->now();
+          double cost = (t - sv->win_t0) / std::max<long long>(sv->win_steps, 1);
           if (!sv->queue.empty()) {  // demand above the cap: the cap is what limits
-            if (thr > 1.03 * sv->best_thr) {
-              sv->best_thr = thr;
-              sv->best_cap = sv->max_slots;
-              sv->max_slots = std::min(1024, sv->max_slots + std::max(1, sv->max_slots / 2));
-            } else {
+            if (sv->best_cost > 0.0 && cost > 1.5 * sv->best_cost) {
               sv->max_slots = sv->best_cap;
               sv->settled = true;
+            } else {
+              if (sv->best_cost == 0.0 || cost < sv->best_cost) {
+                sv->best_cost = cost;
+                sv->best_cap = sv->max_slots;
+              }
+              sv->max_slots = std::min(1024, sv->max_slots + std::max(1, sv->max_slots / 2));
             }
           }
           sv->win_ticks = 0;
@@ -1809,6 +1830,8 @@ int ipc_set_tuning(int32_t key, int64_t value) {
       w.set_fused(value != 0);
     else if (key == IPC_TUNE_FOLD_DIR)
       w.fold_dir = value != 0;
+    else if (key == IPC_TUNE_NARROW)
+      w.narrow = value != 0;
     else
       throw ApiError(IPC_E_ARG, "unknown tuning key");
     return IPC_OK;
@@ -1826,6 +1849,8 @@ int ipc_get_tuning(int32_t key, int64_t *value) {
       *value = w.fused_pcg;
     else if (key == IPC_TUNE_FOLD_DIR)
       *value = w.fold_dir;
+    else if (key == IPC_TUNE_NARROW)
+      *value = w.narrow;
     else
       throw ApiError(IPC_E_ARG, "unknown tuning key");
     return IPC_OK;

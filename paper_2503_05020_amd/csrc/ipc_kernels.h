@@ -63,8 +63,6 @@ void env_dbc(hipStream_t s, const EnvState &S, const Batch &B);
 // broad phase over the state positions x (+ p if swept)
 void boxes(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, const double *x,
            const double *p);
-void bp_count(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L);
-void bp_write(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L);
 void scan_int(hipStream_t s, const int *in, int *out, int n, int *tmp);  // out[n+1] exclusive
 void grid_count(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L);
 void grid_fill(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L,

@@ -247,91 +247,6 @@ __global__ void k_boxes(WorldDev W, const EnvDev *envs, EnvState S, const Tile *
   }
 }
 
-// Count (WRITE = false) or emit (WRITE = true) the candidate pairs of each
-// work item.  PT items are surface vertices tested against every surface
-// triangle of the environment; EE items are surface edges tested against the
-// environment's edges with a larger index.  The B primitives are staged
-// through LDS 256 at a time.
-template <bool WRITE>
-__global__ void __launch_bounds__(256) k_bp(WorldDev W, const EnvDev *envs, EnvState S, const Tile *tiles, int *counts,
-                                            const int *offs, int2 *out) {
-  __shared__ double sb[6][TB];
-  __shared__ int4 sid[TB];
-  Tile t = tiles[blockIdx.x];
-  const EnvDev &E = envs[t.env];
-  int kind = t.rel;
-  int li = threadIdx.x;
-  bool valid = li < t.count;
-  int a = t.start + li;
-  int item = E.item_off + (kind == 0 ? (a - E.sv_off) : (E.nsv + a - E.e_off));
-  if (!active_env(S, t.env)) {
-    if (!WRITE && valid) counts[item] = 0;
-    return;
-  }
-  double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
-  int va0 = -1, va1 = -1;
-  bool akin = false;
-  if (valid) {
-    const double *bx = (kind == 0 ? W.box_sv : W.box_edge) + 6 * a;
-    for (int k = 0; k < 3; ++k) {
-      lo[k] = bx[k];
-      hi[k] = bx[3 + k];
-    }
-    if (kind == 0) {
-      va0 = W.sv[a];
-      akin = W.kin[va0] >= 0;
-    } else {
-      int4 q = W.edge[a];
-      va0 = q.x;
-      va1 = q.y;
-      akin = W.kin[va0] >= 0 && W.kin[va1] >= 0;
-    }
-  }
-  int bbeg = (kind == 0) ? E.tri_off : t.start + 1;
-  int bend = (kind == 0) ? E.tri_off + E.ntri : E.e_off + E.ne;
-  int cnt = 0;
-  int pos = (WRITE && valid) ? offs[item] : 0;
-  for (int c0 = bbeg; c0 < bend; c0 += TB) {
-    __syncthreads();
-    int j = c0 + li;
-    if (j < bend) {
-      const double *bx = (kind == 0 ? W.box_tri : W.box_edge) + 6 * j;
-      for (int k = 0; k < 6; ++k) sb[k][li] = bx[k];
-      int4 q;
-      if (kind == 0) {
-        q = W.tri[j];
-        q.w = (W.kin[q.x] >= 0 && W.kin[q.y] >= 0 && W.kin[q.z] >= 0) ? 1 : 0;
-      } else {
-        int4 e = W.edge[j];
-        q = make_int4(e.x, e.y, -1, (W.kin[e.x] >= 0 && W.kin[e.y] >= 0) ? 1 : 0);
-      }
-      sid[li] = q;
-    }
-    __syncthreads();
-    if (!valid) continue;
-    int n = min(TB, bend - c0);
-    for (int jj = 0; jj < n; ++jj) {
-      int b = c0 + jj;
-      if (kind == 1 && b <= a) continue;
-      if (!(lo[0] <= sb[3][jj] && sb[0][jj] <= hi[0])) continue;
-      if (!(lo[1] <= sb[4][jj] && sb[1][jj] <= hi[1])) continue;
-      if (!(lo[2] <= sb[5][jj] && sb[2][jj] <= hi[2])) continue;
-      int4 q = sid[jj];
-      if (kind == 0) {
-        if (va0 == q.x || va0 == q.y || va0 == q.z) continue;
-        if (akin && q.w) continue;
-        if (WRITE) out[pos++] = make_int2(a, b);
-      } else {
-        if (va0 == q.x || va0 == q.y || va1 == q.x || va1 == q.y) continue;
-        if (akin && q.w) continue;
-        if (WRITE) out[pos++] = make_int2(~a, b);
-      }
-      ++cnt;
-    }
-  }
-  if (!WRITE && valid) counts[item] = cnt;
-}
-
 // ---------------------------------------------------------------------------
 // hash-grid broad phase.  Each environment's triangles and edges are binned
 // into cubic cells of size E.cell (their dhat-widened boxes cover at most 4
@@ -965,68 +880,79 @@ struct DirVec {
   DEV double operator[](int k) const { return (double)dir_value<T>(z[k], pp[k], beta); }
 };
 
-template <typename V>
-DEV void contact_apply(int i, const V &v, const int *inc_off, const int *inc_ent, const int4 *ce_v, const double *ce_H,
-                       double y[3]) {
-  for (int j = inc_off[i]; j < inc_off[i + 1]; ++j) {
-    int ent = inc_ent[j];
-    int ce = ent >> 2, a = ent & 3;
-    int4 q = ce_v[ce];
-    int vv[4] = {q.x, q.y, q.z, q.w};
-    const double *H = ce_H + 90 * (size_t)ce;
-    for (int b = 0; b < 4; ++b) {
-      const double *B = H + 9 * (a <= b ? blk_index(a, b) : blk_index(b, a));
-      bool tr = a > b;
-      double x0 = v[3 * vv[b]], x1 = v[3 * vv[b] + 1], x2 = v[3 * vv[b] + 2];
-      for (int r = 0; r < 3; ++r) {
-        double b0 = tr ? B[r] : B[3 * r], b1 = tr ? B[3 + r] : B[3 * r + 1], b2 = tr ? B[6 + r] : B[3 * r + 2];
-        y[r] += b0 * x0 + b1 * x1 + b2 * x2;
-      }
-    }
-  }
-}
+// One row of the matrix-vector product by kLPR = 4 lanes: lane l takes the
+// sliced-ELL slots l, l+4, ... and the row's contact entries l, l+4, ...
+// (the four lanes' loads are in flight together); the four lane sums
+// are combined by two xor exchanges, which leaves the same bits in all four
+// lanes.  Every lane of the group must call it (invalid rows pass valid =
+// false and contribute zeros).
+constexpr int kLPR = 4;
 
-// Sliced-ELL row product, four slots per round so that their column loads,
-// block loads and vector gathers are in flight together.
 template <typename T, typename V>
-DEV void sell_apply(const WorldDev &W, int i, const V &v, const T *val, double y[3]) {
-  const int sl = i / kSlice, lane = i % kSlice;
-  const int base = W.slice_pos[sl], wdt = W.slice_w[sl];
-  const int *colp = W.col + base + lane;
-  const T *vp = val + (size_t)(base / kSlice) * (9 * kSlice) + lane;
+DEV void row_product(const WorldDev &W, int i, bool valid, int l, const V &v, const T *val, const int *inc_off,
+                     const int *inc_ent, const int4 *ce_v, const double *ce_H, double y[3]) {
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-  int k = 0;
-  for (; k + 4 <= wdt; k += 4) {
-    int c[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) c[u] = colp[(k + u) * kSlice];
-    double m[4][9], x[4][3];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const T *b = vp + (size_t)(k + u) * (9 * kSlice);
-#pragma unroll
-      for (int r = 0; r < 9; ++r) m[u][r] = (double)b[r * kSlice];
-#pragma unroll
-      for (int r = 0; r < 3; ++r) x[u][r] = v[3 * c[u] + r];
+  if (valid) {
+    const int sl = i / kSlice, lane = i % kSlice;
+    const int base = W.slice_pos[sl], wdt = W.slice_w[sl];
+    const int *colp = W.col + base + lane;
+    const T *vp = val + (size_t)(base / kSlice) * (9 * kSlice) + lane;
+#pragma unroll 1
+    for (int k = l; k < wdt; k += kLPR) {
+      const int c = colp[k * kSlice];
+      const T *b = vp + (size_t)k * (9 * kSlice);
+      const double x0 = v[3 * c], x1 = v[3 * c + 1], x2 = v[3 * c + 2];
+      a0 += (double)b[0] * x0 + (double)b[kSlice] * x1 + (double)b[2 * kSlice] * x2;
+      a1 += (double)b[3 * kSlice] * x0 + (double)b[4 * kSlice] * x1 + (double)b[5 * kSlice] * x2;
+      a2 += (double)b[6 * kSlice] * x0 + (double)b[7 * kSlice] * x1 + (double)b[8 * kSlice] * x2;
     }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      a0 += m[u][0] * x[u][0] + m[u][1] * x[u][1] + m[u][2] * x[u][2];
-      a1 += m[u][3] * x[u][0] + m[u][4] * x[u][1] + m[u][5] * x[u][2];
-      a2 += m[u][6] * x[u][0] + m[u][7] * x[u][1] + m[u][8] * x[u][2];
+    // contact elements: 10 unique 3x3 blocks per element (upper triangle)
+#pragma unroll 1
+    for (int j = inc_off[i] + l; j < inc_off[i + 1]; j += kLPR) {
+      const int ent = inc_ent[j];
+      const int ce = ent >> 2, a = ent & 3;
+      const int4 q = ce_v[ce];
+      const int vv[4] = {q.x, q.y, q.z, q.w};
+      const double *H = ce_H + 90 * (size_t)ce;
+      double acc[3] = {0.0, 0.0, 0.0};
+#pragma unroll 1
+      for (int bb = 0; bb < 4; ++bb) {
+        const double *B = H + 9 * (a <= bb ? blk_index(a, bb) : blk_index(bb, a));
+        const bool tr = a > bb;
+        const double x0 = v[3 * vv[bb]], x1 = v[3 * vv[bb] + 1], x2 = v[3 * vv[bb] + 2];
+        for (int r = 0; r < 3; ++r) {
+          const double e0 = tr ? B[r] : B[3 * r], e1 = tr ? B[3 + r] : B[3 * r + 1], e2 = tr ? B[6 + r] : B[3 * r + 2];
+          acc[r] += e0 * x0 + e1 * x1 + e2 * x2;
+        }
+      }
+      a0 += acc[0];
+      a1 += acc[1];
+      a2 += acc[2];
     }
   }
-  for (; k < wdt; ++k) {
-    int c = colp[k * kSlice];
-    const T *b = vp + (size_t)k * (9 * kSlice);
-    double x0 = v[3 * c], x1 = v[3 * c + 1], x2 = v[3 * c + 2];
-    a0 += (double)b[0] * x0 + (double)b[kSlice] * x1 + (double)b[2 * kSlice] * x2;
-    a1 += (double)b[3 * kSlice] * x0 + (double)b[4 * kSlice] * x1 + (double)b[5 * kSlice] * x2;
-    a2 += (double)b[6 * kSlice] * x0 + (double)b[7 * kSlice] * x1 + (double)b[8 * kSlice] * x2;
-  }
+  a0 += __shfl_xor(a0, 1, 64);
+  a1 += __shfl_xor(a1, 1, 64);
+  a2 += __shfl_xor(a2, 1, 64);
+  a0 += __shfl_xor(a0, 2, 64);
+  a1 += __shfl_xor(a1, 2, 64);
+  a2 += __shfl_xor(a2, 2, 64);
   y[0] = a0;
   y[1] = a1;
   y[2] = a2;
+}
+
+// sum of the 256 per-row values of a tile (written by lane 0 of each row's
+// group, row < 256) in the order of block_sum's tree; every thread gets it
+DEV double rows_tree(double v, bool writer, int row, double *sh) {
+  if (writer) sh[row] = v;
+  __syncthreads();
+  for (int s = TB / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  double r = sh[0];
+  __syncthreads();
+  return r;
 }
 
 DEV bool pcg_env_live(const EnvState &S, int env) { return S.status[env] == ST_ACTIVE && !S.pcg_done[env]; }
@@ -1061,17 +987,21 @@ DEV void row_init(const WorldDev &W, bool fr, int i, T *p, T *r, T *z, T *pp, co
   }
 }
 
-// q_i = (H v)_i; returns v_i . q_i.  With pp_out, v_i is also stored there.
+// q_i = (H v)_i by the row's 4 lanes; returns v_i . q_i (same in all four
+// lanes, 0 for an invalid row).  With pp_out, v_i is also stored there.
 template <typename T, typename V>
-DEV double row_spmv(const WorldDev &W, int i, const int *inc_off, const int *inc_ent, const int4 *ce_v,
-                    const double *ce_H, const V &v, T *q, const T *val, T *pp_out) {
-  double y[3], pq = 0.0;
-  sell_apply<T>(W, i, v, val, y);
-  contact_apply(i, v, inc_off, inc_ent, ce_v, ce_H, y);
+DEV double row_spmv(const WorldDev &W, int i, bool valid, int l, const int *inc_off, const int *inc_ent,
+                    const int4 *ce_v, const double *ce_H, const V &v, T *q, const T *val, T *pp_out) {
+  double y[3];
+  row_product<T>(W, i, valid, l, v, val, inc_off, inc_ent, ce_v, ce_H, y);
+  if (!valid) return 0.0;
+  double pq = 0.0;
   for (int c = 0; c < 3; ++c) {
     double vi = v[3 * i + c];
-    if (pp_out) pp_out[3 * i + c] = (T)vi;
-    q[3 * i + c] = (T)y[c];
+    if (l == c) {
+      if (pp_out) pp_out[3 * i + c] = (T)vi;
+      q[3 * i + c] = (T)y[c];
+    }
     pq += vi * (double)(T)y[c];
   }
   return pq;
@@ -1166,12 +1096,12 @@ DEV int pcg_check(const EnvDev &E, EnvState &S, const Tile &t, const double *par
 // (stored direction).  DIR = true: first the stopping test of the last
 // update, then v = z + beta pp formed on the fly and stored in pp_out.
 template <typename T, bool DIR>
-__global__ void __launch_bounds__(256) k_spmv(WorldDev W, const EnvDev *envs, EnvState S, const Tile *tiles,
-                                              const int *inc_off, const int *inc_ent, const int4 *ce_v,
-                                              const double *ce_H, const T *pp, const T *z, T *pp_out, T *q,
-                                              const T *val, double *part_pq, const double *part_rz_old,
-                                              const double *part_rz_new, const double *part_rr_new, int *pending,
-                                              unsigned long long *prof) {
+__global__ void __launch_bounds__(1024) k_spmv(WorldDev W, const EnvDev *envs, EnvState S, const Tile *tiles,
+                                               const int *inc_off, const int *inc_ent, const int4 *ce_v,
+                                               const double *ce_H, const T *pp, const T *z, T *pp_out, T *q,
+                                               const T *val, double *part_pq, const double *part_rz_old,
+                                               const double *part_rz_new, const double *part_rr_new, int *pending,
+                                               unsigned long long *prof) {
   __shared__ double sh[TB];
   __shared__ double s_beta;
   __shared__ int s_done;
@@ -1186,27 +1116,27 @@ __global__ void __launch_bounds__(256) k_spmv(WorldDev W, const EnvDev *envs, En
     __syncthreads();
     if (s_done) return;
   }
-  int i = t.start + threadIdx.x;
-  double pq = 0.0;
-  if ((int)threadIdx.x < t.count) {
-    if (DIR)
-      pq = row_spmv<T>(W, i, inc_off, inc_ent, ce_v, ce_H, DirVec<T>{z, pp, s_beta}, q, val, pp_out);
-    else
-      pq = row_spmv<T>(W, i, inc_off, inc_ent, ce_v, ce_H, StoredVec<T>{pp}, q, val, (T *)nullptr);
-  }
-  pq = block_sum(pq, sh);
+  const int row = threadIdx.x / kLPR, l = threadIdx.x % kLPR;
+  const int i = t.start + row;
+  const bool valid = row < t.count;
+  double pq;
+  if (DIR)
+    pq = row_spmv<T>(W, i, valid, l, inc_off, inc_ent, ce_v, ce_H, DirVec<T>{z, pp, s_beta}, q, val, pp_out);
+  else
+    pq = row_spmv<T>(W, i, valid, l, inc_off, inc_ent, ce_v, ce_H, StoredVec<T>{pp}, q, val, (T *)nullptr);
+  pq = rows_tree(pq, l == 0, row, sh);
   if (threadIdx.x == 0) part_pq[tile_slot(envs, t)] = pq;
   if (prof) {
     // algorithmic bytes of this tile: stored blocks + column indices, the
     // vector rows read and written (v and q; with DIR also z, pp and pp_out),
     // and the contact blocks it applies
     double b = 0.0;
-    if ((int)threadIdx.x < t.count) {
+    if (valid) {
       int nnz = W.row_nnz[i];
       int ninc = inc_off[i + 1] - inc_off[i];
       b = (double)nnz * (9.0 * sizeof(T) + 4.0) + (DIR ? 12.0 : 6.0) * sizeof(T) + ninc * (4.0 * 72.0 + 16.0);
     }
-    b = block_sum(b, sh);
+    b = rows_tree(b, l == 0, row, sh);
     if (threadIdx.x == 0) atomicAdd(prof, (unsigned long long)b);
   }
 }
@@ -1297,17 +1227,19 @@ DEV int env_iterate(const WorldDev &W, const EnvDev &E, const int *inc_off, cons
                     double (*sh)[FB]) {
   const int r0 = E.v_off, r1 = E.v_off + E.nv_pad;
   for (;;) {
-    for (int base = r0; base < r1; base += FB) {
-      int i = base + threadIdx.x;
-      double pq = 0.0;
-      if (i < r1) {
-        pq = row_spmv<T>(W, i, inc_off, inc_ent, ce_v, ce_H, StoredVec<T>{pp}, q, val, (T *)nullptr);
-        if (prof)
-          bytes += (double)W.row_nnz[i] * (9.0 * sizeof(T) + 4.0) + 6.0 * sizeof(T) +
-                   (inc_off[i + 1] - inc_off[i]) * (4.0 * 72.0 + 16.0);
-      }
-      tile_sums2(pq, 0.0, sh, E, (base - r0) / TB, part_pq, nullptr);
+    // the product: one 256-row tile per pass, 4 lanes per row (as k_spmv)
+    for (int base = r0; base < r1; base += TB) {
+      const int row = threadIdx.x / kLPR, l = threadIdx.x % kLPR;
+      const int i = base + row;
+      const bool valid = i < r1;
+      double pq = row_spmv<T>(W, i, valid, l, inc_off, inc_ent, ce_v, ce_H, StoredVec<T>{pp}, q, val, (T *)nullptr);
+      if (prof && valid && l == 0)
+        bytes += (double)W.row_nnz[i] * (9.0 * sizeof(T) + 4.0) + 6.0 * sizeof(T) +
+                 (inc_off[i + 1] - inc_off[i]) * (4.0 * 72.0 + 16.0);
+      pq = rows_tree(pq, l == 0, row, sh[0]);
+      if (threadIdx.x == 0) part_pq[E.vtile_first + (base - r0) / TB] = pq;
     }
+    __syncthreads();
     double pq = env_tiles_sum(part_pq, E);
     double alpha = (pq > 0.0) ? rz / pq : 0.0;
     for (int base = r0; base < r1; base += FB) {
@@ -1417,17 +1349,19 @@ __global__ void k_p32_to_p(WorldDev W, EnvState S, const Tile *tiles) {
   for (int c = 0; c < 3; ++c) W.p[3 * i + c] = (double)W.p32[3 * i + c];
 }
 
-// debug: out = H in over the batch (all vertices of ACTIVE envs)
-__global__ void k_spmv_dbg(WorldDev W, EnvState S, const Tile *tiles, const int *inc_off, const int *inc_ent,
-                           const int4 *ce_v, const double *ce_H, const double *in, double *out) {
+// debug: out = H in over the batch (all vertices of ACTIVE envs), one
+// 256-row tile per 1024-thread workgroup as in k_spmv
+__global__ void __launch_bounds__(1024) k_spmv_dbg(WorldDev W, EnvState S, const Tile *tiles, const int *inc_off,
+                                                   const int *inc_ent, const int4 *ce_v, const double *ce_H,
+                                                   const double *in, double *out) {
   Tile t = tiles[blockIdx.x];
-  if ((int)threadIdx.x >= t.count || !active_env(S, t.env)) return;
-  int i = t.start + threadIdx.x;
+  if (!active_env(S, t.env)) return;
+  const int row = threadIdx.x / kLPR, l = threadIdx.x % kLPR;
+  const int i = t.start + row;
+  const bool valid = row < t.count;
   double y[3];
-  StoredVec<double> v{in};
-  sell_apply<double>(W, i, v, W.val, y);
-  contact_apply(i, v, inc_off, inc_ent, ce_v, ce_H, y);
-  for (int c = 0; c < 3; ++c) out[3 * i + c] = y[c];
+  row_product<double>(W, i, valid, l, StoredVec<double>{in}, W.val, inc_off, inc_ent, ce_v, ce_H, y);
+  if (valid && l < 3) out[3 * i + l] = y[l];
 }
 
 // ---------------------------------------------------------------------------
@@ -1854,13 +1788,6 @@ void boxes(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S,
   if (B.n_et) IPC_LAUNCH(k_boxes, B.n_et, TB, s)(W, E, S, B.etiles, 2, x, p);
 }
 
-void bp_count(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L) {
-  if (B.n_it) IPC_LAUNCH(k_bp<false>, B.n_it, TB, s)(W, E, S, B.itiles, L.counts, nullptr, nullptr);
-}
-void bp_write(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L) {
-  if (B.n_it) IPC_LAUNCH(k_bp<true>, B.n_it, TB, s)(W, E, S, B.itiles, nullptr, L.offs, L.cand);
-}
-
 void grid_count(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L) {
   if (B.n_bt) IPC_LAUNCH(k_grid_count, B.n_bt, TB, s)(W, E, S, B.btiles, L.g_ncell, L.g_big);
 }
@@ -1985,11 +1912,11 @@ void pcg_iter(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState 
     double *ppi = cur ? W.pp2 : W.pp, *ppo = nxt ? W.pp2 : W.pp;
     if (ev0) hipEventRecord(ev0, s);
     if (dir)
-      IPC_LAUNCH((k_spmv<double, true>), n_tiles, TB, s)(W, E, S, tiles, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, ppi,
+      IPC_LAUNCH((k_spmv<double, true>), n_tiles, kLPR * TB, s)(W, E, S, tiles, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, ppi,
                                                         W.z, ppo, W.q, W.val, L.part_a, rz_prev, rz_cur, rr_cur,
                                                         pending, prof);
     else
-      IPC_LAUNCH((k_spmv<double, false>), n_tiles, TB, s)(W, E, S, tiles, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, ppi,
+      IPC_LAUNCH((k_spmv<double, false>), n_tiles, kLPR * TB, s)(W, E, S, tiles, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, ppi,
                                                          W.z, nullptr, W.q, W.val, L.part_a, nullptr, nullptr,
                                                          nullptr, pending, prof);
     if (ev1) hipEventRecord(ev1, s);
@@ -2001,11 +1928,11 @@ void pcg_iter(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState 
     float *ppi = cur ? W.pp2_32 : W.pp32, *ppo = nxt ? W.pp2_32 : W.pp32;
     if (ev0) hipEventRecord(ev0, s);
     if (dir)
-      IPC_LAUNCH((k_spmv<float, true>), n_tiles, TB, s)(W, E, S, tiles, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, ppi,
+      IPC_LAUNCH((k_spmv<float, true>), n_tiles, kLPR * TB, s)(W, E, S, tiles, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, ppi,
                                                        W.z32, ppo, W.q32, W.val32, L.part_a, rz_prev, rz_cur, rr_cur,
                                                        pending, prof);
     else
-      IPC_LAUNCH((k_spmv<float, false>), n_tiles, TB, s)(W, E, S, tiles, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, ppi,
+      IPC_LAUNCH((k_spmv<float, false>), n_tiles, kLPR * TB, s)(W, E, S, tiles, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, ppi,
                                                         W.z32, nullptr, W.q32, W.val32, L.part_a, nullptr, nullptr,
                                                         nullptr, pending, prof);
     if (ev1) hipEventRecord(ev1, s);
@@ -2052,7 +1979,7 @@ void pcg_finish(hipStream_t s, const WorldDev &W, const EnvState &S, const Batch
 
 void spmv_debug(hipStream_t s, const WorldDev &W, const EnvDev *, const EnvState &S, const Batch &B, Lists &L,
                 const double *in, double *out) {
-  if (B.n_vt) IPC_LAUNCH(k_spmv_dbg, B.n_vt, TB, s)(W, S, B.vtiles, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, in, out);
+  if (B.n_vt) IPC_LAUNCH(k_spmv_dbg, B.n_vt, kLPR * TB, s)(W, S, B.vtiles, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, in, out);
 }
 
 void conv_check(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L,

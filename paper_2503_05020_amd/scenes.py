@@ -393,6 +393,115 @@ def serving_scene(req):
     return parallel_jaw_sphere(seed=req["seed"], tet_target=req["tet_target"])
 
 
+def capsule_mesh(length: float, radius: float, around: int = 16):
+    """Closed capsule surface: 8 rings of `around` vertices plus two poles.
+
+    Rings: three on each hemisphere (polar angles 30, 60, 90 deg) and two on
+    the cylinder at 1/3 and 2/3 of `length`; the axis runs from (0,0,0) to
+    (0,0,length).  16 around gives 130 vertices and 256 triangles.
+    """
+    rings = []
+    for phi in (30.0, 60.0, 90.0):  # bottom hemisphere, pole at z = -radius
+        t = math.radians(phi)
+        rings.append((-radius * math.cos(t), radius * math.sin(t)))
+    rings += [(length / 3.0, radius), (2.0 * length / 3.0, radius)]
+    for phi in (90.0, 120.0, 150.0):  # top hemisphere
+        t = math.radians(phi)
+        rings.append((length - radius * math.cos(t), radius * math.sin(t)))
+    ang = 2.0 * math.pi * np.arange(around) / around
+    v = [[0.0, 0.0, -radius]]
+    for z, r in rings:
+        v += [[r * math.cos(a), r * math.sin(a), z] for a in ang]
+    v.append([0.0, 0.0, length + radius])
+    v = np.array(v)
+    top = len(v) - 1
+    t = []
+    for j in range(around):  # bottom cap, outward normals
+        t.append([0, 1 + (j + 1) % around, 1 + j])
+    for k in range(len(rings) - 1):
+        a0, a1 = 1 + k * around, 1 + (k + 1) * around
+        for j in range(around):
+            j1 = (j + 1) % around
+            t.append([a0 + j, a0 + j1, a1 + j1])
+            t.append([a0 + j, a1 + j1, a1 + j])
+    last = 1 + (len(rings) - 1) * around
+    for j in range(around):
+        t.append([top, last + j, last + (j + 1) % around])
+    return v, np.array(t, np.int64)
+
+
+def _rot_x(theta: float) -> np.ndarray:
+    c, s = math.cos(theta), math.sin(theta)
+    return np.array([[1.0, 0.0, 0.0], [0.0, c, -s], [0.0, s, c]])
+
+
+def rigid_hand_grasp(seed: int = 0, h: float = 2.08e-3, axes=(0.06, 0.04, 0.03), close_steps: int = 80,
+                     lift_steps: int = 40, lift_speed: float = 0.05, **params):
+    """A kinematic four-finger hand of 16 capsule links grasps a soft ellipsoid on the ground.
+
+    Ellipsoid half-axes 6 x 4 x 3 cm (201k tets at h = 2.08 mm), E = 1e5,
+    nu = 0.4, rho = 1000.  Fingers: two on each side of the y extent, at
+    x = +-2.2 cm, hanging from 4.5 cm above the centre; links 45/35/25/20 mm
+    long, radius 8 mm.  Joint angles (rotation about x, inward positive) go
+    linearly from a seeded open pose (joint 0 at -15 deg, others 0, each
+    +-10 deg) to the closed pose (35, 25, 20, 15 deg) over `close_steps`
+    steps, then the hand rises at `lift_speed` for `lift_steps` steps.
+    dt = 5 ms, dhat = 0.5 mm, mu = 0.6.  Every link is its own kinematic group
+    (0..15), the ground is group 16.  Links press into the object, so the
+    prescribed moves need the augmented-Lagrangian mode.
+    """
+    p = dict(dt=0.005, dhat=5e-4, mu=0.6)
+    p.update(params)
+    dhat = p["dhat"]
+    rng = np.random.default_rng(seed)
+    m, origin = ellipsoid_mask(axes, h)
+    ev, et = voxel_tet_mesh(m, h, origin)
+    ev[:, 2] += -ev[:, 2].min() + 1.2 * dhat
+    cz = 0.5 * (ev[:, 2].min() + ev[:, 2].max())
+    b = _Builder()
+    b.add_body(ev, et, 1e5, 0.4, 1000.0)
+    lengths, radius = (0.045, 0.035, 0.025, 0.020), 0.008
+    open_pose = np.array([-15.0, 0.0, 0.0, 0.0])
+    closed_pose = np.array([20, 14, 10, 8])
+    n_rows = close_steps + lift_steps + 1
+    motion = np.tile(IDENTITY12, (n_rows, 17, 1))
+    group = 0
+    for side in (-1.0, 1.0):
+        for xf in (-0.022, 0.022):
+            th_open = np.radians(open_pose + rng.uniform(-10.0, 10.0, 4))
+            th_closed = np.radians(closed_pose)
+            base = np.array([xf, side * (axes[1] + radius + 0.004), cz + 0.045])
+
+            def chain(th):
+                # joint positions and link rotations; a link's local +z maps to
+                # (0, -side sin T, -cos T), T = the cumulative joint angle
+                P, Rs, T = [base.copy()], [], 0.0
+                for k in range(4):
+                    T += th[k]
+                    R = _rot_x(-side * T) @ np.diag([1.0, -1.0, -1.0])  # local +z -> straight down at T = 0
+                    Rs.append(R)
+                    P.append(P[-1] + lengths[k] * R[:, 2])
+                return P, Rs
+
+            P0, R0 = chain(th_open)
+            for k in range(4):
+                cv, ct = capsule_mesh(lengths[k], radius)
+                world = cv @ R0[k].T + P0[k]
+                b.add_kinematic_mesh(world, ct, group + k)
+            for n in range(n_rows):
+                f = min(n, close_steps) / close_steps
+                Pn, Rn = chain(th_open + (th_closed - th_open) * f)
+                lift = np.array([0.0, 0.0, lift_speed * p["dt"] * max(0, n - close_steps)])
+                for k in range(4):
+                    R = Rn[k] @ R0[k].T
+                    t = Pn[k] + lift - R @ P0[k]
+                    motion[n, group + k] = np.concatenate([np.c_[R, t]]).reshape(-1)
+            group += 4
+    gv, gt = ground_plane()
+    b.add_kinematic_mesh(gv, gt, 16)
+    return b.build(motion, [[0.0, 0.0, -9.81]], **p)
+
+
 # --------------------------------------------------------------------------
 # tiny fixtures
 # --------------------------------------------------------------------------

@@ -102,3 +102,58 @@ def test_superquadric_batch_sampled_against_oracle():
         assert _min_pair_distance(scs[j], final[j]) > 0
     for g in gs:
         G.ipc_destroy_scene(g)
+
+
+def _hand_targets(sc, row):
+    """Prescribed positions of every kinematic vertex at motion row `row`."""
+    X, kin, M = sc["rest_pos"], sc["kin_group"], sc["motion"]
+    out = np.empty((int((kin >= 0).sum()), 3))
+    idx = np.flatnonzero(kin >= 0)
+    for j, i in enumerate(idx):
+        R = M[row, kin[i]].reshape(3, 4)
+        out[j] = R[:, :3] @ X[i] + R[:, 3]
+    return idx, out
+
+
+def test_rigid_hand_reduced_trajectory():
+    """The 16-capsule hand closing on the ellipsoid, at 8 mm voxels (3.6k tets) so the oracle can run
+    it: through finger contact, positions within 1e-6 of the bbox diagonal, links on target."""
+    sc = S.rigid_hand_grasp(h=8e-3, close_steps=40)
+    g = G.ipc_create_scene(sc, pcg_rel_tol=1e-8)
+    o = O.Scene(sc, pcg_rel_tol=1e-8)
+    L = sc["env_bbox_diag"]
+    worst = 0.0
+    for k in range(18):  # fingers reach the object at step ~14
+        rg, ig = G.ipc_step(g, 1)
+        ro, io = o.step(1)
+        assert rg == 0 and ro == 0, (k, ig, io)
+        pg, _ = G.ipc_get_state(g)
+        po, _ = o.state()
+        err = np.abs(pg - po).max() / L
+        worst = max(worst, err)
+        idx, tgt = _hand_targets(sc, k + 1)
+        assert np.array_equal(pg[idx], tgt)
+        say(f"step {k}: err {err:.2e} newton {ig['newton_iters']}/{io['newton_iters']} active {io['n_active_last']}")
+    say("worst", worst)
+    assert worst <= 1e-6
+    assert _dets(pg, sc["tets"]).min() > 0
+
+
+@pytest.mark.parametrize("precision", [G.IPC_FP64, G.IPC_MIXED])
+def test_rigid_hand_full_size(precision):
+    """201k-tet ellipsoid and 4096 link triangles: through finger contact the links are on target,
+    no tet inverts and every pair distance stays positive (checked by the oracle's own pair search)."""
+    sc = S.rigid_hand_grasp(close_steps=40)
+    g = G.ipc_create_scene(sc, precision=precision, pcg_rel_tol=1e-4)
+    for k in range(18):
+        rg, ig = G.ipc_step(g, 1)
+        assert rg == 0, (k, ig)
+        say(f"step {k}: newton {ig['newton_iters']} pcg {ig['pcg_iters']}")
+    pg, _ = G.ipc_get_state(g)
+    idx, tgt = _hand_targets(sc, 18)
+    assert np.array_equal(pg[idx], tgt)
+    assert _dets(pg, sc["tets"]).min() > 0
+    d = _min_pair_distance(sc, pg)
+    say("min pair distance", d)
+    assert d > 0
+    G.ipc_destroy_scene(g)
