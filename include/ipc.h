@@ -159,11 +159,19 @@ int ipc_prof_read(double *out);
  *   IPC_TUNE_NARROW: 1 = once at most half of a batch still iterates its
  *     Newton loop, the batch is laid out again with those environments only
  *     (default), 0 = never (IPC_NARROW).
+ *   IPC_TUNE_LANES: number of lanes per device (1..16, default 4; IPC_LANES).
+ *     A lane is an independent set of device buffers with its own stream;
+ *     ipc_create_scene places a scene in the lane with the fewest tets, and
+ *     ipc_step_batch steps the scenes of each lane together, the lanes
+ *     concurrently from one host thread each, so that one lane's
+ *     latency-bound tail overlaps with the others' work.  Applies to scenes
+ *     created afterwards.
  * Returns IPC_OK, or IPC_E_ARG for an unknown key or a negative value. */
 #define IPC_TUNE_TAIL_TILES 1
 #define IPC_TUNE_FUSED_PCG 2
 #define IPC_TUNE_FOLD_DIR 3
 #define IPC_TUNE_NARROW 4
+#define IPC_TUNE_LANES 5
 int ipc_set_tuning(int32_t key, int64_t value);
 int ipc_get_tuning(int32_t key, int64_t *value);
 

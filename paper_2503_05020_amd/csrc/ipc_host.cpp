@@ -19,6 +19,7 @@
 #include <memory>
 #include <condition_variable>
 #include <deque>
+#include <exception>
 #include <mutex>
 #include <thread>
 #include <stdexcept>
@@ -728,6 +729,7 @@ struct World {
     ensure_envs(recs.size());
     EnvRec &R = recs[slot];
     R.used = true;
+    live_tets += H.nt;
     R.v_n = H.nv_pad;
     R.t_n = H.nt;
     R.tri_n = H.ntri;
@@ -876,6 +878,7 @@ struct World {
     aContrib.release(R.contrib_off, R.contrib_n);
     aVT.release(R.vt_off, R.vt_n);
     aMo.release(R.mo_off, R.mo_n);
+    live_tets -= (long long)R.t_n;
     R.used = false;
     batch_envs.clear();
   }
@@ -1135,6 +1138,7 @@ struct World {
   // those swept boxes, so the list holds every pair a static pass would find,
   // and the exact d² < d̂² test picks the same active set.  -1: none.
   int swept_n = -1;
+  long long live_tets = 0;  // tets of the scenes living here (lane placement)
 
   // gradient, contact elements, incidence, assembled Hessian at W.x
   int assemble_system(int mixed) {
@@ -1156,6 +1160,7 @@ struct World {
   }
 
   // execution knobs (ipc_set_tuning); initial values from the environment
+public:
   static int env_knob(const char *name, int dflt) {
     const char *e = std::getenv(name);
     return (e && e[0]) ? std::max(0, std::atoi(e)) : dflt;
@@ -1178,6 +1183,13 @@ struct World {
     if ((on != 0) == use_fused()) return;
     fused_pcg = on ? 1 : 0;
     batch_envs.clear();  // E.fused is decided when a batch is laid out
+  }
+  void copy_knobs(const World &o) {
+    set_fused(o.fused_pcg);
+    tail_tiles = o.tail_tiles;
+    fold_dir = o.fold_dir;
+    narrow = o.narrow;
+    set_prof(o.prof_on);
   }
 
   long long solve(int mixed) {
@@ -1344,16 +1356,48 @@ struct World {
   }
 };
 
+// Each device holds up to `g_lanes` worlds ("lanes"), each with its own
+// stream, buffers and host thread while stepping.  A batch whose scenes live
+// in several lanes is stepped lane by lane concurrently, so the tail of one
+// lane's Newton and PCG loops (few environments, latency-bound launches)
+// overlaps with the other lanes' work on the same GPU.
 std::mutex g_worlds_mu;
-std::map<int, std::unique_ptr<World>> g_worlds;
+std::map<int, std::vector<std::unique_ptr<World>>> g_worlds;
+int g_lanes = -1;
 
-World &world_for_current_device() {
+int lanes_setting() {
+  if (g_lanes < 0) g_lanes = std::max(1, std::min(16, World::env_knob("IPC_LANES", 4)));
+  return g_lanes;
+}
+
+// every lane of the current device, creating them up to the lane count
+std::vector<World *> worlds_for_current_device() {
   int dev = 0;
   HC(hipGetDevice(&dev));
   std::lock_guard<std::mutex> lk(g_worlds_mu);
-  auto &w = g_worlds[dev];
-  if (!w) w = std::make_unique<World>(dev);
-  return *w;
+  auto &v = g_worlds[dev];
+  int n = lanes_setting();
+  while ((int)v.size() < n) {
+    v.push_back(std::make_unique<World>(dev));
+    if (v.size() > 1) v.back()->copy_knobs(*v.front());
+  }
+  std::vector<World *> out;
+  for (auto &w : v) out.push_back(w.get());
+  return out;
+}
+
+World &world_for_current_device() { return *worlds_for_current_device().front(); }
+
+// lane for a new scene: the one with the fewest live tets (first on ties)
+World &world_for_new_scene() {
+  auto ws = worlds_for_current_device();
+  int n = std::min<int>(lanes_setting(), (int)ws.size());
+  World *best = ws[0];
+  for (int i = 1; i < n; ++i) {
+    std::lock_guard<std::mutex> lk(ws[i]->mu);
+    if (ws[i]->live_tets < best->live_tets) best = ws[i];
+  }
+  return *best;
 }
 
 }  // namespace
@@ -1450,15 +1494,13 @@ void get_x(World &w, ipc_scene s, const double *dev_arr, double *host) {
   HC(hipStreamSynchronize(w.stream));
 }
 
-void run_steps(std::vector<ipc_scene> scenes, int n_steps, ipc_step_info *infos) {
+// steps scenes that all live in one lane
+void run_steps_lane(std::vector<ipc_scene> scenes, int n_steps, ipc_step_info *infos) {
   if (scenes.empty()) return;
   World &w = *scenes[0]->world;
   std::lock_guard<std::mutex> lk(w.mu);
   std::vector<int> slots;
-  for (auto s : scenes) {
-    if (s->world != &w) throw ApiError(IPC_E_ARG, "scenes of one batch must live on the same device");
-    slots.push_back(s->slot);
-  }
+  for (auto s : scenes) slots.push_back(s->slot);
   {
     std::vector<int> sorted = slots;
     std::sort(sorted.begin(), sorted.end());
@@ -1511,6 +1553,51 @@ void run_steps(std::vector<ipc_scene> scenes, int n_steps, ipc_step_info *infos)
     HC(hipMemcpyAsync(w.S.status, snap.status.data(), 4 * w.env_cap, hipMemcpyHostToDevice, w.stream));
     HC(hipStreamSynchronize(w.stream));
   }
+}
+
+// steps a batch: the scenes of each lane are stepped together, lanes
+// concurrently (one host thread per extra lane)
+void run_steps(const std::vector<ipc_scene> &scenes, int n_steps, ipc_step_info *infos) {
+  if (scenes.empty()) return;
+  int dev = scenes[0]->world->device;
+  std::vector<World *> lanes;
+  std::vector<std::vector<size_t>> idx;
+  for (size_t i = 0; i < scenes.size(); ++i) {
+    World *w = scenes[i]->world;
+    if (w->device != dev) throw ApiError(IPC_E_ARG, "scenes of one batch must live on the same device");
+    size_t k = std::find(lanes.begin(), lanes.end(), w) - lanes.begin();
+    if (k == lanes.size()) {
+      lanes.push_back(w);
+      idx.emplace_back();
+    }
+    idx[k].push_back(i);
+  }
+  if (lanes.size() == 1) {
+    run_steps_lane(scenes, n_steps, infos);
+    return;
+  }
+  std::vector<std::vector<ipc_step_info>> part(lanes.size());
+  std::vector<std::exception_ptr> err(lanes.size());
+  auto work = [&](size_t k) {
+    try {
+      HC(hipSetDevice(dev));
+      std::vector<ipc_scene> sub;
+      for (size_t i : idx[k]) sub.push_back(scenes[i]);
+      part[k].assign(sub.size(), ipc_step_info{});
+      run_steps_lane(sub, n_steps, infos ? part[k].data() : nullptr);
+    } catch (...) {
+      err[k] = std::current_exception();
+    }
+  };
+  std::vector<std::thread> th;
+  for (size_t k = 1; k < lanes.size(); ++k) th.emplace_back(work, k);
+  work(0);
+  for (auto &t : th) t.join();
+  for (auto &e : err)
+    if (e) std::rethrow_exception(e);
+  if (infos)
+    for (size_t k = 0; k < lanes.size(); ++k)
+      for (size_t j = 0; j < idx[k].size(); ++j) infos[idx[k][j]] = part[k][j];
 }
 
 // ---------------------------------------------------------------------------
@@ -1592,11 +1679,11 @@ void server_loop(ipc_server_s *sv) {
       }
       for (Request *r : admit) {
         auto *sc = new ipc_scene_s();
-        sc->world = sv->w;
+        sc->world = &world_for_new_scene();
         {
-          std::lock_guard<std::mutex> lk(sv->w->mu);
+          std::lock_guard<std::mutex> lk(sc->world->mu);
           try {
-            sc->slot = sv->w->add_scene(*r->host);
+            sc->slot = sc->world->add_scene(*r->host);
           } catch (...) {
             delete sc;
             throw;
@@ -1626,10 +1713,11 @@ void server_loop(ipc_server_s *sv) {
         if (fin) {
           r->pos.resize(3 * (size_t)r->nv);
           r->vel.resize(3 * (size_t)r->nv);
-          std::lock_guard<std::mutex> lk(sv->w->mu);
-          get_x(*sv->w, r->scene, sv->w->W.x, r->pos.data());
-          get_x(*sv->w, r->scene, sv->w->W.v, r->vel.data());
-          sv->w->remove_scene(r->scene->slot);
+          World &w = *r->scene->world;
+          std::lock_guard<std::mutex> lk(w.mu);
+          get_x(w, r->scene, w.W.x, r->pos.data());
+          get_x(w, r->scene, w.W.v, r->vel.data());
+          w.remove_scene(r->scene->slot);
           done.push_back(r);
         }
       }
@@ -1726,7 +1814,7 @@ int ipc_create_scene(const ipc_scene_desc *desc, ipc_scene *out) {
   return guarded([&]() {
     if (!out) throw ApiError(IPC_E_ARG, "null output handle");
     auto host = preprocess(desc);
-    World &w = world_for_current_device();
+    World &w = world_for_new_scene();
     std::lock_guard<std::mutex> lk(w.mu);
     int slot = w.add_scene(*host);
     auto *s = new ipc_scene_s();
@@ -1812,9 +1900,10 @@ int ipc_set_state(ipc_scene s, const double *pos, const double *vel, int32_t ste
 
 int ipc_prof_enable(int32_t on) {
   return guarded([&]() {
-    World &w = world_for_current_device();
-    std::lock_guard<std::mutex> lk(w.mu);
-    w.set_prof(on != 0);
+    for (World *w : worlds_for_current_device()) {
+      std::lock_guard<std::mutex> lk(w->mu);
+      w->set_prof(on != 0);
+    }
     return IPC_OK;
   });
 }
@@ -1822,18 +1911,26 @@ int ipc_prof_enable(int32_t on) {
 int ipc_set_tuning(int32_t key, int64_t value) {
   return guarded([&]() {
     if (value < 0) throw ApiError(IPC_E_ARG, "tuning value must be >= 0");
-    World &w = world_for_current_device();
-    std::lock_guard<std::mutex> lk(w.mu);
-    if (key == IPC_TUNE_TAIL_TILES)
-      w.tail_tiles = (int)std::min<int64_t>(value, 1 << 30);
-    else if (key == IPC_TUNE_FUSED_PCG)
-      w.set_fused(value != 0);
-    else if (key == IPC_TUNE_FOLD_DIR)
-      w.fold_dir = value != 0;
-    else if (key == IPC_TUNE_NARROW)
-      w.narrow = value != 0;
-    else
+    if (key == IPC_TUNE_LANES) {
+      if (value < 1 || value > 16) throw ApiError(IPC_E_ARG, "lanes must be in [1, 16]");
+      std::lock_guard<std::mutex> lk(g_worlds_mu);
+      g_lanes = (int)value;
+      return IPC_OK;
+    }
+    if (key != IPC_TUNE_TAIL_TILES && key != IPC_TUNE_FUSED_PCG && key != IPC_TUNE_FOLD_DIR && key != IPC_TUNE_NARROW)
       throw ApiError(IPC_E_ARG, "unknown tuning key");
+    for (World *pw : worlds_for_current_device()) {
+      World &w = *pw;
+      std::lock_guard<std::mutex> lk(w.mu);
+      if (key == IPC_TUNE_TAIL_TILES)
+        w.tail_tiles = (int)std::min<int64_t>(value, 1 << 30);
+      else if (key == IPC_TUNE_FUSED_PCG)
+        w.set_fused(value != 0);
+      else if (key == IPC_TUNE_FOLD_DIR)
+        w.fold_dir = value != 0;
+      else
+        w.narrow = value != 0;
+    }
     return IPC_OK;
   });
 }
@@ -1841,6 +1938,10 @@ int ipc_set_tuning(int32_t key, int64_t value) {
 int ipc_get_tuning(int32_t key, int64_t *value) {
   return guarded([&]() {
     if (!value) throw ApiError(IPC_E_ARG, "null output");
+    if (key == IPC_TUNE_LANES) {
+      *value = lanes_setting();
+      return IPC_OK;
+    }
     World &w = world_for_current_device();
     std::lock_guard<std::mutex> lk(w.mu);
     if (key == IPC_TUNE_TAIL_TILES)
@@ -1859,9 +1960,10 @@ int ipc_get_tuning(int32_t key, int64_t *value) {
 
 int ipc_prof_reset(void) {
   return guarded([&]() {
-    World &w = world_for_current_device();
-    std::lock_guard<std::mutex> lk(w.mu);
-    w.prof_reset();
+    for (World *w : worlds_for_current_device()) {
+      std::lock_guard<std::mutex> lk(w->mu);
+      w->prof_reset();
+    }
     return IPC_OK;
   });
 }
@@ -1869,17 +1971,19 @@ int ipc_prof_reset(void) {
 int ipc_prof_read(double *out) {
   return guarded([&]() {
     if (!out) throw ApiError(IPC_E_ARG, "null output");
-    World &w = world_for_current_device();
-    std::lock_guard<std::mutex> lk(w.mu);
-    unsigned long long b = 0;
-    if (w.prof_bytes.p) {
-      HC(hipMemcpyAsync(&b, w.prof_bytes.p, 8, hipMemcpyDeviceToHost, w.stream));
-      HC(hipStreamSynchronize(w.stream));
+    out[0] = out[1] = out[2] = out[3] = 0.0;
+    for (World *pw : worlds_for_current_device()) {
+      World &w = *pw;
+      std::lock_guard<std::mutex> lk(w.mu);
+      unsigned long long b = 0;
+      if (w.prof_bytes.p) {
+        HC(hipMemcpyAsync(&b, w.prof_bytes.p, 8, hipMemcpyDeviceToHost, w.stream));
+        HC(hipStreamSynchronize(w.stream));
+      }
+      out[0] += w.prof_ms;
+      out[1] += (double)w.prof_launches;
+      out[2] += (double)b;
     }
-    out[0] = w.prof_ms;
-    out[1] = (double)w.prof_launches;
-    out[2] = (double)b;
-    out[3] = 0.0;
     return IPC_OK;
   });
 }
@@ -2329,10 +2433,10 @@ void ipc_server_destroy(ipc_server srv) {
   srv->cv_work.notify_all();
   if (srv->worker.joinable()) srv->worker.join();
   try {
-    std::lock_guard<std::mutex> lk(srv->w->mu);
     for (Request *r : srv->running)
       if (r->scene) {
-        srv->w->remove_scene(r->scene->slot);
+        std::lock_guard<std::mutex> lk(r->scene->world->mu);
+        r->scene->world->remove_scene(r->scene->slot);
         delete r->scene;
         r->scene = nullptr;
       }
