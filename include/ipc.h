@@ -159,7 +159,9 @@ int ipc_prof_read(double *out);
  *   IPC_TUNE_NARROW: 1 = once at most half of a batch still iterates its
  *     Newton loop, the batch is laid out again with those environments only
  *     (default), 0 = never (IPC_NARROW).
- *   IPC_TUNE_LANES: number of lanes per device (1..16, default 4; IPC_LANES).
+ *   IPC_TUNE_LANES: number of lanes per device (1..16, default 3: with the
+ *     runtime's null stream that fills the 4 hardware queues a process gets
+ *     by default; IPC_LANES).
  *     A lane is an independent set of device buffers with its own stream;
  *     ipc_create_scene places a scene in the lane with the fewest tets, and
  *     ipc_step_batch steps the scenes of each lane together, the lanes
@@ -223,18 +225,20 @@ int64_t ipc_debug_accd(int32_t kind, int64_t n, const double *x12, const double 
 /* ===========================================================================
  * Serving: continuous batching of simulation requests on one device.
  *
- * A server owns a worker thread.  Each tick it (1) admits queued requests, in
- * submission order, while fewer than max_slots are running and the device
- * bytes of their resident state (positions and velocities, meshes, sparsity
+ * A server owns one worker thread per lane of the device (IPC_TUNE_LANES).
+ * Each worker, tick after tick: (1) admits queued requests into its lane, in
+ * submission order, while fewer than max_slots requests run in all, its lane
+ * holds less than its share (max_slots / lanes, rounded up) and the device
+ * bytes of the resident state (positions and velocities, meshes, sparsity
  * pattern, PCG vectors: ipc_request_info.bytes) fit in budget_bytes; (2)
- * advances every running request by one time step, all of them in one batch
- * through the same kernels as ipc_step_batch; (3) retires the requests that
- * completed their steps or failed, keeping their final state for
- * ipc_server_result and freeing their slot and memory.  Requests thus join and
- * leave the batch between time steps while the others keep running, and a
- * request's result is bitwise the same as when it runs alone.  Per-step
- * contact and candidate lists are shared work buffers of the device and are
- * not counted in the budget.
+ * advances every request running in its lane by one time step, all of them in
+ * one batch through the same kernels as ipc_step_batch; (3) retires the
+ * requests that completed their steps or failed, keeping their final state
+ * for ipc_server_result and freeing their slot and memory.  Requests thus join
+ * and leave a batch between time steps while the others keep running, lanes
+ * run concurrently, and a request's result is bitwise the same as when it
+ * runs alone.  Per-step contact and candidate lists are work buffers of the
+ * lanes and are not counted in the budget.
  *
  * The paper (Sec. IV) runs its grasp pipeline as many independent
  * environments; this interface serves such environments as they arrive.
@@ -264,7 +268,7 @@ typedef struct {
 /* Creates a server on the current device.  budget_bytes > 0; max_slots >= 1
  * fixes the slot cap, max_slots = 0 lets the server tune it: starting at 8,
  * while requests are waiting it raises the cap by half after every window of
- * 16 ticks, unless that window's seconds per converged step exceed 1.5x the
+ * 16 ticks per lane, unless that window's seconds per converged step exceed 1.5x the
  * best window's, in which case it settles on the best window's cap. */
 int ipc_server_create(int64_t budget_bytes, int32_t max_slots, ipc_server *out);
 /* Validates and copies the scene (as ipc_create_scene; same error codes, and

@@ -1356,7 +1356,7 @@ public:
   }
 };
 
-// Each device holds up to `g_lanes` worlds ("lanes"), each with its own
+// Each device holds `g_lanes` worlds ("lanes"), each with its own
 // stream, buffers and host thread while stepping.  A batch whose scenes live
 // in several lanes is stepped lane by lane concurrently, so the tail of one
 // lane's Newton and PCG loops (few environments, latency-bound launches)
@@ -1366,7 +1366,9 @@ std::map<int, std::vector<std::unique_ptr<World>>> g_worlds;
 int g_lanes = -1;
 
 int lanes_setting() {
-  if (g_lanes < 0) g_lanes = std::max(1, std::min(16, World::env_knob("IPC_LANES", 4)));
+  // 3 by default: a device exposes 4 hardware queues per process and the
+  // runtime's null stream holds one; a fourth lane would share a queue
+  if (g_lanes < 0) g_lanes = std::max(1, std::min(16, World::env_knob("IPC_LANES", 3)));
   return g_lanes;
 }
 
@@ -1619,29 +1621,31 @@ struct Request {
 }  // namespace
 
 struct ipc_server_s {
-  World *w = nullptr;
+  std::vector<World *> lanes;  // one worker thread per lane
   int64_t budget = 0;
   int32_t max_slots = 1;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::deque<Request *> queue;
-  std::vector<Request *> running;
+  std::vector<std::vector<Request *>> running;  // per lane
   std::map<int64_t, std::unique_ptr<Request>> reqs;
   int64_t next_id = 1, used = 0;
+  int n_running = 0;  // over all lanes, admitted requests included
   bool stop = false, dead = false;
   std::string error;
   long long finished = 0, failed = 0, conv_steps = 0, ticks = 0;
   // slot-cap autotuner (max_slots = 0 at creation): while requests wait,
-  // grow the cap by half after every window of 16 ticks, unless the window's
-  // seconds per converged step exceed 1.5x the best window's: then settle on
-  // the best window's cap.  A tick costs about its slowest environment's
-  // step, so more slots raise throughput until the device saturates.
+  // grow the cap by half after every window of 16 ticks per lane, unless the
+  // window's seconds per converged step exceed 1.5x the best window's: then
+  // settle on the best window's cap.  A tick costs about its slowest
+  // environment's step, so more slots raise throughput until the device
+  // saturates.
   bool auto_slots = false, settled = false;
   int32_t best_cap = 0;
   double best_cost = 0.0, win_t0 = 0.0;
   long long win_ticks = 0, win_steps = 0;
   std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
-  std::thread worker;
+  std::vector<std::thread> workers;
   double now() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
 };
 
@@ -1659,31 +1663,68 @@ void retire(ipc_server_s *sv, Request *r, bool failed, int reason) {
     ++sv->finished;
 }
 
-void server_loop(ipc_server_s *sv) {
+// caller holds sv->mu; `mine` = requests the asking lane runs or is admitting
+// (each lane takes at most its share of the slot cap)
+bool can_admit(const ipc_server_s *sv, size_t mine) {
+  const size_t share = (sv->max_slots + sv->lanes.size() - 1) / sv->lanes.size();
+  return !sv->queue.empty() && sv->n_running < sv->max_slots && mine < share &&
+         sv->used + sv->queue.front()->bytes <= sv->budget;
+}
+
+void autotune_tick(ipc_server_s *sv, long long tick_steps) {
+  // caller holds sv->mu
+  if (!sv->auto_slots || sv->settled) return;
+  sv->win_steps += tick_steps;
+  if (++sv->win_ticks < 16 * (long long)sv->lanes.size()) return;
+  double t = sv->now();
+  double cost = (t - sv->win_t0) / std::max<long long>(sv->win_steps, 1);
+  if (!sv->queue.empty()) {  // demand above the cap: the cap is what limits
+    if (sv->best_cost > 0.0 && cost > 1.5 * sv->best_cost) {
+      sv->max_slots = sv->best_cap;
+      sv->settled = true;
+    } else {
+      if (sv->best_cost == 0.0 || cost < sv->best_cost) {
+        sv->best_cost = cost;
+        sv->best_cap = sv->max_slots;
+      }
+      sv->max_slots = std::min(1024, sv->max_slots + std::max(1, sv->max_slots / 2));
+      sv->cv_work.notify_all();
+    }
+  }
+  sv->win_ticks = 0;
+  sv->win_steps = 0;
+  sv->win_t0 = t;
+}
+
+// the worker of lane k: admit into this lane, step its running requests one
+// time step per tick, retire the finished ones
+void server_loop(ipc_server_s *sv, size_t k) {
+  World *w = sv->lanes[k];
+  std::vector<Request *> &mine = sv->running[k];
   std::vector<ipc_step_info> infos;
   try {
-    HC(hipSetDevice(sv->w->device));
+    HC(hipSetDevice(w->device));
     while (true) {
       std::vector<Request *> admit;
       {
         std::unique_lock<std::mutex> lk(sv->mu);
-        sv->cv_work.wait(lk, [&]() { return sv->stop || !sv->queue.empty() || !sv->running.empty(); });
-        if (sv->stop) return;
-        while (!sv->queue.empty() && (int)(sv->running.size() + admit.size()) < sv->max_slots &&
-               sv->used + sv->queue.front()->bytes <= sv->budget) {
+        sv->cv_work.wait(lk, [&]() { return sv->stop || sv->dead || !mine.empty() || can_admit(sv, mine.size()); });
+        if (sv->stop || sv->dead) return;
+        while (can_admit(sv, mine.size() + admit.size())) {
           Request *r = sv->queue.front();
           sv->queue.pop_front();
           sv->used += r->bytes;
+          ++sv->n_running;
           admit.push_back(r);
         }
       }
       for (Request *r : admit) {
         auto *sc = new ipc_scene_s();
-        sc->world = &world_for_new_scene();
+        sc->world = w;
         {
-          std::lock_guard<std::mutex> lk(sc->world->mu);
+          std::lock_guard<std::mutex> lk(w->mu);
           try {
-            sc->slot = sc->world->add_scene(*r->host);
+            sc->slot = w->add_scene(*r->host);
           } catch (...) {
             delete sc;
             throw;
@@ -1694,18 +1735,18 @@ void server_loop(ipc_server_s *sv) {
         r->scene = sc;
         r->status = IPC_REQ_RUNNING;
         r->t_admit = sv->now();
-        sv->running.push_back(r);
+        mine.push_back(r);
       }
       std::vector<Request *> run;
       {
         std::lock_guard<std::mutex> lk(sv->mu);
-        run = sv->running;
+        run = mine;
       }
       if (run.empty()) continue;
       std::vector<ipc_scene> scenes;
       for (Request *r : run) scenes.push_back(r->scene);
       infos.assign(run.size(), ipc_step_info{});
-      run_steps(scenes, 1, infos.data());
+      run_steps_lane(scenes, 1, infos.data());
       std::vector<Request *> done;
       for (size_t i = 0; i < run.size(); ++i) {
         Request *r = run[i];
@@ -1713,11 +1754,10 @@ void server_loop(ipc_server_s *sv) {
         if (fin) {
           r->pos.resize(3 * (size_t)r->nv);
           r->vel.resize(3 * (size_t)r->nv);
-          World &w = *r->scene->world;
-          std::lock_guard<std::mutex> lk(w.mu);
-          get_x(w, r->scene, w.W.x, r->pos.data());
-          get_x(w, r->scene, w.W.v, r->vel.data());
-          w.remove_scene(r->scene->slot);
+          std::lock_guard<std::mutex> lk(w->mu);
+          get_x(*w, r->scene, w->W.x, r->pos.data());
+          get_x(*w, r->scene, w->W.v, r->vel.data());
+          w->remove_scene(r->scene->slot);
           done.push_back(r);
         }
       }
@@ -1731,52 +1771,37 @@ void server_loop(ipc_server_s *sv) {
         tick_steps += infos[i].steps_done;
       }
       sv->conv_steps += tick_steps;
-      if (sv->auto_slots && !sv->settled) {
-        sv->win_steps += tick_steps;
-        if (++sv->win_ticks >= 16) {
-          double t = sv->now();
-          double cost = (t - sv->win_t0) / std::max<long long>(sv->win_steps, 1);
-          if (!sv->queue.empty()) {  // demand above the cap: the cap is what limits
-            if (sv->best_cost > 0.0 && cost > 1.5 * sv->best_cost) {
-              sv->max_slots = sv->best_cap;
-              sv->settled = true;
-            } else {
-              if (sv->best_cost == 0.0 || cost < sv->best_cost) {
-                sv->best_cost = cost;
-                sv->best_cap = sv->max_slots;
-              }
-              sv->max_slots = std::min(1024, sv->max_slots + std::max(1, sv->max_slots / 2));
-            }
-          }
-          sv->win_ticks = 0;
-          sv->win_steps = 0;
-          sv->win_t0 = t;
-        }
-      }
+      autotune_tick(sv, tick_steps);
       for (Request *r : done) {
         retire(sv, r, r->scene->failed, r->scene->fail_reason);
         delete r->scene;
         r->scene = nullptr;
-        sv->running.erase(std::find(sv->running.begin(), sv->running.end(), r));
+        mine.erase(std::find(mine.begin(), mine.end(), r));
+        --sv->n_running;
       }
       ++sv->ticks;
       sv->cv_done.notify_all();
+      if (!done.empty()) sv->cv_work.notify_all();  // freed slots and memory
     }
   } catch (const std::exception &e) {
     std::lock_guard<std::mutex> lk(sv->mu);
     sv->dead = true;
     sv->error = e.what();
-    for (Request *r : sv->running) {
-      retire(sv, r, true, IPC_FAIL_DEVICE);
-      r->scene = nullptr;  // left with the device's world
+    for (auto &lane : sv->running) {
+      for (Request *r : lane) {
+        retire(sv, r, true, IPC_FAIL_DEVICE);
+        r->scene = nullptr;  // left with the device's world
+      }
+      lane.clear();
     }
     for (Request *r : sv->queue) {
       sv->used += r->bytes;  // retire() subtracts it again
       retire(sv, r, true, IPC_FAIL_DEVICE);
     }
-    sv->running.clear();
     sv->queue.clear();
+    sv->n_running = 0;
     sv->cv_done.notify_all();
+    sv->cv_work.notify_all();
   }
 }
 
@@ -2318,12 +2343,14 @@ int ipc_server_create(int64_t budget_bytes, int32_t max_slots, ipc_server *out) 
   return guarded([&]() {
     if (!out || budget_bytes <= 0 || max_slots < 0) throw ApiError(IPC_E_ARG, "bad server arguments");
     auto sv = std::make_unique<ipc_server_s>();
-    sv->w = &world_for_current_device();
+    sv->lanes = worlds_for_current_device();
+    sv->lanes.resize(std::min<size_t>(sv->lanes.size(), (size_t)lanes_setting()));
+    sv->running.resize(sv->lanes.size());
     sv->budget = budget_bytes;
     sv->auto_slots = max_slots == 0;
     sv->max_slots = sv->auto_slots ? 8 : max_slots;
     sv->best_cap = sv->max_slots;
-    sv->worker = std::thread(server_loop, sv.get());
+    for (size_t k = 0; k < sv->lanes.size(); ++k) sv->workers.emplace_back(server_loop, sv.get(), k);
     *out = sv.release();
     return IPC_OK;
   });
@@ -2335,7 +2362,7 @@ int ipc_server_submit(ipc_server srv, const ipc_scene_desc *desc, int32_t n_step
     const double t_arrival = srv->now();  // validation and copying count toward latency
     auto host = preprocess(desc);
     auto r = std::make_unique<Request>();
-    r->bytes = (int64_t)srv->w->scene_bytes(*host);
+    r->bytes = (int64_t)srv->lanes[0]->scene_bytes(*host);
     if (r->bytes > srv->budget) throw ApiError(IPC_E_NOMEM, "scene exceeds the server's memory budget");
     r->nv = host->nv;
     r->n_steps = n_steps;
@@ -2347,7 +2374,7 @@ int ipc_server_submit(ipc_server srv, const ipc_scene_desc *desc, int32_t n_step
     *id = r->id;
     srv->queue.push_back(r.get());
     srv->reqs[r->id] = std::move(r);
-    srv->cv_work.notify_one();
+    srv->cv_work.notify_all();
     return IPC_OK;
   });
 }
@@ -2402,7 +2429,7 @@ int ipc_server_set_slots(ipc_server srv, int32_t max_slots) {
     std::lock_guard<std::mutex> lk(srv->mu);
     srv->max_slots = max_slots;
     srv->auto_slots = false;
-    srv->cv_work.notify_one();
+    srv->cv_work.notify_all();
     return IPC_OK;
   });
 }
@@ -2415,7 +2442,7 @@ int ipc_server_stats(ipc_server srv, double *out) {
     out[1] = (double)srv->failed;
     out[2] = (double)srv->conv_steps;
     out[3] = (double)srv->ticks;
-    out[4] = (double)srv->running.size();
+    out[4] = (double)srv->n_running;
     out[5] = (double)srv->queue.size();
     out[6] = (double)srv->used;
     out[7] = srv->now();
@@ -2431,15 +2458,17 @@ void ipc_server_destroy(ipc_server srv) {
     srv->stop = true;
   }
   srv->cv_work.notify_all();
-  if (srv->worker.joinable()) srv->worker.join();
+  for (auto &t : srv->workers)
+    if (t.joinable()) t.join();
   try {
-    for (Request *r : srv->running)
-      if (r->scene) {
-        std::lock_guard<std::mutex> lk(r->scene->world->mu);
-        r->scene->world->remove_scene(r->scene->slot);
-        delete r->scene;
-        r->scene = nullptr;
-      }
+    for (auto &lane : srv->running)
+      for (Request *r : lane)
+        if (r->scene) {
+          std::lock_guard<std::mutex> lk(r->scene->world->mu);
+          r->scene->world->remove_scene(r->scene->slot);
+          delete r->scene;
+          r->scene = nullptr;
+        }
   } catch (...) {
   }
   delete srv;

@@ -888,7 +888,20 @@ struct DirVec {
 // false and contribute zeros).
 constexpr int kLPR = 4;
 
+// one slot of a row: a += B x_c (B = the 3x3 block at b, components kSlice apart)
 template <typename T, typename V>
+DEV void slot_acc(const T *b, const V &v, int c, double &a0, double &a1, double &a2) {
+  const double x0 = v[3 * c], x1 = v[3 * c + 1], x2 = v[3 * c + 2];
+  a0 += (double)b[0] * x0 + (double)b[kSlice] * x1 + (double)b[2 * kSlice] * x2;
+  a1 += (double)b[3 * kSlice] * x0 + (double)b[4 * kSlice] * x1 + (double)b[5 * kSlice] * x2;
+  a2 += (double)b[6 * kSlice] * x0 + (double)b[7 * kSlice] * x1 + (double)b[8 * kSlice] * x2;
+}
+
+// WIDE: the lane's slots are processed four per round (their loads in
+// flight together: fewer round trips, for launches of a few tiles where
+// latency dominates); otherwise one per round (fewer registers, more waves
+// for launches over the whole batch).  Same additions in the same order.
+template <typename T, typename V, bool WIDE>
 DEV void row_product(const WorldDev &W, int i, bool valid, int l, const V &v, const T *val, const int *inc_off,
                      const int *inc_ent, const int4 *ce_v, const double *ce_H, double y[3]) {
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
@@ -897,15 +910,18 @@ DEV void row_product(const WorldDev &W, int i, bool valid, int l, const V &v, co
     const int base = W.slice_pos[sl], wdt = W.slice_w[sl];
     const int *colp = W.col + base + lane;
     const T *vp = val + (size_t)(base / kSlice) * (9 * kSlice) + lane;
-#pragma unroll 1
-    for (int k = l; k < wdt; k += kLPR) {
-      const int c = colp[k * kSlice];
-      const T *b = vp + (size_t)k * (9 * kSlice);
-      const double x0 = v[3 * c], x1 = v[3 * c + 1], x2 = v[3 * c + 2];
-      a0 += (double)b[0] * x0 + (double)b[kSlice] * x1 + (double)b[2 * kSlice] * x2;
-      a1 += (double)b[3 * kSlice] * x0 + (double)b[4 * kSlice] * x1 + (double)b[5 * kSlice] * x2;
-      a2 += (double)b[6 * kSlice] * x0 + (double)b[7 * kSlice] * x1 + (double)b[8 * kSlice] * x2;
+    int k = l;
+    if (WIDE) {
+      for (; k + 3 * kLPR < wdt; k += 4 * kLPR) {
+        int c[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) c[u] = colp[(k + u * kLPR) * kSlice];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) slot_acc<T>(vp + (size_t)(k + u * kLPR) * (9 * kSlice), v, c[u], a0, a1, a2);
+      }
     }
+#pragma unroll 1
+    for (; k < wdt; k += kLPR) slot_acc<T>(vp + (size_t)k * (9 * kSlice), v, colp[k * kSlice], a0, a1, a2);
     // contact elements: 10 unique 3x3 blocks per element (upper triangle)
 #pragma unroll 1
     for (int j = inc_off[i] + l; j < inc_off[i + 1]; j += kLPR) {
@@ -989,11 +1005,11 @@ DEV void row_init(const WorldDev &W, bool fr, int i, T *p, T *r, T *z, T *pp, co
 
 // q_i = (H v)_i by the row's 4 lanes; returns v_i . q_i (same in all four
 // lanes, 0 for an invalid row).  With pp_out, v_i is also stored there.
-template <typename T, typename V>
+template <typename T, bool WIDE, typename V>
 DEV double row_spmv(const WorldDev &W, int i, bool valid, int l, const int *inc_off, const int *inc_ent,
                     const int4 *ce_v, const double *ce_H, const V &v, T *q, const T *val, T *pp_out) {
   double y[3];
-  row_product<T>(W, i, valid, l, v, val, inc_off, inc_ent, ce_v, ce_H, y);
+  row_product<T, V, WIDE>(W, i, valid, l, v, val, inc_off, inc_ent, ce_v, ce_H, y);
   if (!valid) return 0.0;
   double pq = 0.0;
   for (int c = 0; c < 3; ++c) {
@@ -1095,7 +1111,7 @@ DEV int pcg_check(const EnvDev &E, EnvState &S, const Tile &t, const double *par
 // q = H v for live environments, partial v.q per tile.  DIR = false: v = pp
 // (stored direction).  DIR = true: first the stopping test of the last
 // update, then v = z + beta pp formed on the fly and stored in pp_out.
-template <typename T, bool DIR>
+template <typename T, bool DIR, bool WIDE>
 __global__ void __launch_bounds__(1024) k_spmv(WorldDev W, const EnvDev *envs, EnvState S, const Tile *tiles,
                                                const int *inc_off, const int *inc_ent, const int4 *ce_v,
                                                const double *ce_H, const T *pp, const T *z, T *pp_out, T *q,
@@ -1121,9 +1137,9 @@ __global__ void __launch_bounds__(1024) k_spmv(WorldDev W, const EnvDev *envs, E
   const bool valid = row < t.count;
   double pq;
   if (DIR)
-    pq = row_spmv<T>(W, i, valid, l, inc_off, inc_ent, ce_v, ce_H, DirVec<T>{z, pp, s_beta}, q, val, pp_out);
+    pq = row_spmv<T, WIDE>(W, i, valid, l, inc_off, inc_ent, ce_v, ce_H, DirVec<T>{z, pp, s_beta}, q, val, pp_out);
   else
-    pq = row_spmv<T>(W, i, valid, l, inc_off, inc_ent, ce_v, ce_H, StoredVec<T>{pp}, q, val, (T *)nullptr);
+    pq = row_spmv<T, WIDE>(W, i, valid, l, inc_off, inc_ent, ce_v, ce_H, StoredVec<T>{pp}, q, val, (T *)nullptr);
   pq = rows_tree(pq, l == 0, row, sh);
   if (threadIdx.x == 0) part_pq[tile_slot(envs, t)] = pq;
   if (prof) {
@@ -1232,7 +1248,8 @@ DEV int env_iterate(const WorldDev &W, const EnvDev &E, const int *inc_off, cons
       const int row = threadIdx.x / kLPR, l = threadIdx.x % kLPR;
       const int i = base + row;
       const bool valid = i < r1;
-      double pq = row_spmv<T>(W, i, valid, l, inc_off, inc_ent, ce_v, ce_H, StoredVec<T>{pp}, q, val, (T *)nullptr);
+      double pq =
+          row_spmv<T, true>(W, i, valid, l, inc_off, inc_ent, ce_v, ce_H, StoredVec<T>{pp}, q, val, (T *)nullptr);
       if (prof && valid && l == 0)
         bytes += (double)W.row_nnz[i] * (9.0 * sizeof(T) + 4.0) + 6.0 * sizeof(T) +
                  (inc_off[i + 1] - inc_off[i]) * (4.0 * 72.0 + 16.0);
@@ -1360,7 +1377,8 @@ __global__ void __launch_bounds__(1024) k_spmv_dbg(WorldDev W, EnvState S, const
   const int i = t.start + row;
   const bool valid = row < t.count;
   double y[3];
-  row_product<double>(W, i, valid, l, StoredVec<double>{in}, W.val, inc_off, inc_ent, ce_v, ce_H, y);
+  row_product<double, StoredVec<double>, false>(W, i, valid, l, StoredVec<double>{in}, W.val, inc_off, inc_ent, ce_v,
+                                                ce_H, y);
   if (valid && l < 3) out[3 * i + l] = y[l];
 }
 
@@ -1894,6 +1912,30 @@ void live_tiles(hipStream_t s, const EnvState &S, const Batch &B, Lists &L, Tile
   IPC_LAUNCH(k_live_compact, nblk(B.n_vt, TB), TB, s)(B.vtiles, B.n_vt, flag, offs, out);
 }
 
+constexpr int kWideTiles = 64;
+
+template <typename T>
+void launch_spmv(hipStream_t s, bool dir, bool wide, const WorldDev &W, const EnvDev *E, const EnvState &S,
+                 const Tile *tiles, int n_tiles, Lists &L, const T *ppi, const T *z, T *ppo, T *q, const T *val,
+                 const double *rz_prev, const double *rz_cur, const double *rr_cur, int *pending,
+                 unsigned long long *prof) {
+  const int nt = kLPR * TB;
+  if (dir && wide)
+    IPC_LAUNCH((k_spmv<T, true, true>), n_tiles, nt, s)(W, E, S, tiles, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, ppi, z,
+                                                        ppo, q, val, L.part_a, rz_prev, rz_cur, rr_cur, pending, prof);
+  else if (dir)
+    IPC_LAUNCH((k_spmv<T, true, false>), n_tiles, nt, s)(W, E, S, tiles, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, ppi, z,
+                                                         ppo, q, val, L.part_a, rz_prev, rz_cur, rr_cur, pending, prof);
+  else if (wide)
+    IPC_LAUNCH((k_spmv<T, false, true>), n_tiles, nt, s)(W, E, S, tiles, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, ppi, z,
+                                                         (T *)nullptr, q, val, L.part_a, nullptr, nullptr, nullptr,
+                                                         pending, prof);
+  else
+    IPC_LAUNCH((k_spmv<T, false, false>), n_tiles, nt, s)(W, E, S, tiles, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, ppi, z,
+                                                          (T *)nullptr, q, val, L.part_a, nullptr, nullptr, nullptr,
+                                                          pending, prof);
+}
+
 void pcg_iter(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, Lists &L, int it, int *pending,
               int mixed, bool dir, int cur, bool last, hipEvent_t ev0, hipEvent_t ev1, const Tile *tiles,
               int n_tiles) {
@@ -1908,17 +1950,13 @@ void pcg_iter(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState 
   double *rr_cur = (it & 1) ? L.part_c1 : L.part_c0;
   double *rz_new = rz_prev, *rr_new = (it & 1) ? L.part_c0 : L.part_c1;
   const int nxt = dir ? 1 - cur : cur;
+  // launches of a few tiles are latency-bound: issue each lane's slots four at a time
+  const bool wide = n_tiles <= kWideTiles;
   if (!mixed) {
     double *ppi = cur ? W.pp2 : W.pp, *ppo = nxt ? W.pp2 : W.pp;
     if (ev0) hipEventRecord(ev0, s);
-    if (dir)
-      IPC_LAUNCH((k_spmv<double, true>), n_tiles, kLPR * TB, s)(W, E, S, tiles, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, ppi,
-                                                        W.z, ppo, W.q, W.val, L.part_a, rz_prev, rz_cur, rr_cur,
-                                                        pending, prof);
-    else
-      IPC_LAUNCH((k_spmv<double, false>), n_tiles, kLPR * TB, s)(W, E, S, tiles, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, ppi,
-                                                         W.z, nullptr, W.q, W.val, L.part_a, nullptr, nullptr,
-                                                         nullptr, pending, prof);
+    launch_spmv<double>(s, dir, wide, W, E, S, tiles, n_tiles, L, ppi, W.z, ppo, W.q, W.val, rz_prev, rz_cur, rr_cur,
+                        pending, prof);
     if (ev1) hipEventRecord(ev1, s);
     IPC_LAUNCH(k_pcg_update<double>, n_tiles, TB, s)(W, E, S, tiles, L.part_a, rz_cur, rz_new, rr_new, W.p, W.r, W.z,
                                                      ppo, W.q, W.Minv);
@@ -1927,14 +1965,8 @@ void pcg_iter(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState 
   } else {
     float *ppi = cur ? W.pp2_32 : W.pp32, *ppo = nxt ? W.pp2_32 : W.pp32;
     if (ev0) hipEventRecord(ev0, s);
-    if (dir)
-      IPC_LAUNCH((k_spmv<float, true>), n_tiles, kLPR * TB, s)(W, E, S, tiles, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, ppi,
-                                                       W.z32, ppo, W.q32, W.val32, L.part_a, rz_prev, rz_cur, rr_cur,
-                                                       pending, prof);
-    else
-      IPC_LAUNCH((k_spmv<float, false>), n_tiles, kLPR * TB, s)(W, E, S, tiles, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, ppi,
-                                                        W.z32, nullptr, W.q32, W.val32, L.part_a, nullptr, nullptr,
-                                                        nullptr, pending, prof);
+    launch_spmv<float>(s, dir, wide, W, E, S, tiles, n_tiles, L, ppi, W.z32, ppo, W.q32, W.val32, rz_prev, rz_cur,
+                       rr_cur, pending, prof);
     if (ev1) hipEventRecord(ev1, s);
     IPC_LAUNCH(k_pcg_update<float>, n_tiles, TB, s)(W, E, S, tiles, L.part_a, rz_cur, rz_new, rr_new, W.p32, W.r32,
                                                     W.z32, ppo, W.q32, W.Minv32);
