@@ -153,15 +153,97 @@ def serving(n_req, rate, budget, slots, precision, n_steps=100):
             "tets_total": int(sum(len(sc["tets"]) for sc in scs))}
 
 
-def roofline(prof):
+def measured_traffic(precision):
+    """HBM bytes per k_spmv launch from the committed rocprofv3 counter runs (FETCH_SIZE + WRITE_SIZE,
+    scaled by the same counters on a plain copy of known size), or None when the kernel source has
+    changed since they were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "spmv_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    src = os.path.join(ROOT, "paper_2503_05020_amd", "csrc", "ipc_kernels.hip")
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != d.get("kernel_source_sha256"):
+            return None
+    v = d.get("bytes_per_launch", {}).get(precision)
+    return None if v is None else int(v)
+
+
+def pmc_summary(d, copy_mib):
+    """Write profiles/spmv_traffic.json from rocprofv3 --pmc csv runs under directory d:
+    pmc_copy_<C> (this script with --copy-probe copy_mib) and pmc_spmv_<prec>_<C> (this script with
+    --precision <prec>), for C in FETCH_SIZE, WRITE_SIZE (KiB per dispatch)."""
+    import csv
+    import glob
+    import hashlib
+
+    def rows(sub):
+        out = []
+        for f in glob.glob(os.path.join(d, sub, "**", "*counter_collection.csv"), recursive=True):
+            with open(f) as fh:
+                out += list(csv.DictReader(fh))
+        return out
+
+    def per_dispatch(rs, counter, pick):
+        v = {}
+        for r in rs:
+            if r["Counter_Name"] == counter and pick(r["Kernel_Name"]):
+                k = r.get("Dispatch_Id") or r.get("Correlation_Id")
+                v[k] = v.get(k, 0.0) + float(r["Counter_Value"])
+        return list(v.values())
+
+    res = {"copy_probe_bytes": copy_mib << 20}
+    factor = {}
+    for c in ("FETCH_SIZE", "WRITE_SIZE"):
+        rs = rows(f"pmc_copy_{c}")
+        vals = per_dispatch(rs, c, lambda n: "copy" in n.lower())
+        kib = max(vals)  # the copy dispatches (the fill before them reads nothing)
+        factor[c] = (copy_mib << 20) / (kib * 1024.0)
+        res[f"copy_{c}_kib_per_dispatch"] = kib
+        res[f"factor_{c}"] = round(factor[c], 4)
+    res["bytes_per_launch"] = {}
+    for prec in ("fp64", "mixed"):
+        tot = 0.0
+        for c in ("FETCH_SIZE", "WRITE_SIZE"):
+            vals = per_dispatch(rows(f"pmc_spmv_{prec}_{c}"), c, lambda n: "k_spmv" in n)
+            if not vals:
+                tot = None
+                break
+            mean = sum(vals) / len(vals)
+            res[f"spmv_{prec}_{c}_kib_mean"] = round(mean, 1)
+            res[f"spmv_{prec}_{c}_dispatches"] = len(vals)
+            tot += mean * 1024.0 * factor[c]
+        if tot is not None:
+            res["bytes_per_launch"][prec] = int(tot)
+    with open(os.path.join(ROOT, "paper_2503_05020_amd", "csrc", "ipc_kernels.hip"), "rb") as f:
+        res["kernel_source_sha256"] = hashlib.sha256(f.read()).hexdigest()
+    out = os.path.join(ROOT, "profiles", "spmv_traffic.json")
+    with open(out, "w") as f:
+        json.dump(res, f, indent=1)
+    print(json.dumps(res))
+
+
+def roofline(prof, precision):
     if prof["spmv_launches"] <= 0 or prof["spmv_ms"] <= 0:
         return None
     avg_ms = prof["spmv_ms"] / prof["spmv_launches"]
     bytes_per_launch = prof["spmv_bytes"] / prof["spmv_launches"]
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_spmv",
-            "avg_launch_us": round(avg_ms * 1e3, 2), "bytes_per_launch": int(bytes_per_launch)}
+    out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(precision), "kernel": "k_spmv",
+           "avg_launch_us": round(avg_ms * 1e3, 2), "bytes_per_launch": int(bytes_per_launch),
+           "launches_timed": int(prof["spmv_launches"])}
+    if prof["big_launches"] > 0 and prof["big_ms"] > 0:
+        # the same, restricted to the launches over more than 64 tiles (the
+        # rest are the latency-bound tails of the last environments' solves)
+        bms = prof["big_ms"] / prof["big_launches"]
+        bb = prof["big_bytes"] / prof["big_launches"]
+        out["large_launches"] = {"achieved": round(bb / (bms * 1e-3) / 1e9, 1), "frac": round(bb / (bms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                 "avg_launch_us": round(bms * 1e3, 2), "bytes_per_launch": int(bb),
+                                 "launches_timed": int(prof["big_launches"])}
+    return out
 
 
 def main():
@@ -179,7 +261,12 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=0, help="0 = slot cap tuned by the server")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device copy of this many MiB, 5 times (calibrates HBM counters)")
+    ap.add_argument("--pmc-summary", default="",
+                    help="only summarise rocprofv3 --pmc csv runs under this directory into profiles/spmv_traffic.json")
     args = ap.parse_args()
+    if args.pmc_summary:
+        pmc_summary(args.pmc_summary, args.copy_probe or 512)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: environments are independent and would be sharded across GPUs "
               "without any collective; only --gpus 1 is supported on this box.", file=sys.stderr)
@@ -236,14 +323,14 @@ def main():
         "newton_iters": r["newton"],
         "pcg_iters": r["pcg"],
         "failed_envs": r["failed"],
-        "roofline": roofline(r["prof"]),
+        "roofline": roofline(r["prof"], main_p),
         "cpu_baseline": cpu,
         "serving": serve,
     }
     if "fp64" in results and main_p != "fp64":
         f = results["fp64"]
         out["fp64"] = {"value": round(f["value"], 2), "ms_per_step": round(f["ms_per_step"], 2),
-                       "failed_envs": f["failed"], "roofline": roofline(f["prof"])}
+                       "failed_envs": f["failed"], "roofline": roofline(f["prof"], "fp64")}
     if seq:
         out["sequential_single_env"] = {"value": round(seq["value"], 3), "envs": seq["envs"],
                                         "speedup_batched_vs_sequential": round(r["value"] / seq["value"], 2)}

@@ -136,7 +136,8 @@ int ipc_scene_sizes(ipc_scene s, int64_t out[7]);
  * column indices, one read and one write of a vector row, contact blocks
  * applied) to a device counter.  ipc_prof_read writes out[0] total
  * event-timed milliseconds, out[1] number of timed launches, out[2] their
- * bytes, out[3] reserved. */
+ * bytes, and out[3..5] the same three for the timed launches over more than
+ * 64 tiles (out has 6 entries).  Sums over the lanes of the device. */
 int ipc_prof_enable(int32_t on);
 int ipc_prof_reset(void);
 int ipc_prof_read(double *out);

@@ -590,8 +590,8 @@ struct World {
   bool prof_on = false;
   DBuf<unsigned long long> prof_bytes;
   std::vector<hipEvent_t> ev_pool;
-  double prof_ms = 0.0;
-  long long prof_launches = 0;
+  double prof_ms = 0.0, prof_ms_big = 0.0;  // big: launches over more than kWideTiles tiles
+  long long prof_launches = 0, prof_launches_big = 0;
   int n_fric = 0;
   std::mutex mu;
 
@@ -1030,10 +1030,10 @@ struct World {
   }
 
   void prof_reset() {
-    prof_ms = 0.0;
-    prof_launches = 0;
+    prof_ms = prof_ms_big = 0.0;
+    prof_launches = prof_launches_big = 0;
     if (prof_bytes.p) {
-      HC(hipMemsetAsync(prof_bytes.p, 0, 8, stream));
+      HC(hipMemsetAsync(prof_bytes.p, 0, 16, stream));
       HC(hipStreamSynchronize(stream));
     }
   }
@@ -1216,6 +1216,7 @@ public:
     const Tile *tl = B.vtiles;
     int ntl = B.n_vt, last_pending = -1;
     int cur = 0;  // pp buffer holding the current direction
+    std::vector<char> ev_big;  // per timed launch: over more than kWideTiles tiles
     const bool tr = tracing();
     double t_launch = 0.0, t_wait = 0.0;
     auto now = []() { return std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now().time_since_epoch()).count(); };
@@ -1231,6 +1232,7 @@ public:
         if (prof_on && (it & 15) == 5) {
           e0 = pool_event(nev++);
           e1 = pool_event(nev++);
+          ev_big.push_back(ntl > ipck::kWideTiles ? 1 : 0);
         }
         const bool dir = fold_dir && j > 0;
         ipck::pcg_iter(stream, W, envs_d, S, L, it++, pending, mixed, dir, cur, !fold_dir || j == 7, e0, e1, tl, ntl);
@@ -1266,6 +1268,10 @@ public:
         HC(hipEventElapsedTime(&ms, ev_pool[k], ev_pool[k + 1]));
         prof_ms += ms;
         prof_launches += 1;
+        if (ev_big[k / 2]) {
+          prof_ms_big += ms;
+          prof_launches_big += 1;
+        }
       }
     }
     return it;
@@ -1996,18 +2002,21 @@ int ipc_prof_reset(void) {
 int ipc_prof_read(double *out) {
   return guarded([&]() {
     if (!out) throw ApiError(IPC_E_ARG, "null output");
-    out[0] = out[1] = out[2] = out[3] = 0.0;
+    for (int k = 0; k < 6; ++k) out[k] = 0.0;
     for (World *pw : worlds_for_current_device()) {
       World &w = *pw;
       std::lock_guard<std::mutex> lk(w.mu);
-      unsigned long long b = 0;
+      unsigned long long b[2] = {0, 0};
       if (w.prof_bytes.p) {
-        HC(hipMemcpyAsync(&b, w.prof_bytes.p, 8, hipMemcpyDeviceToHost, w.stream));
+        HC(hipMemcpyAsync(b, w.prof_bytes.p, 16, hipMemcpyDeviceToHost, w.stream));
         HC(hipStreamSynchronize(w.stream));
       }
       out[0] += w.prof_ms;
       out[1] += (double)w.prof_launches;
-      out[2] += (double)b;
+      out[2] += (double)(b[0] + b[1]);
+      out[3] += w.prof_ms_big;
+      out[4] += (double)w.prof_launches_big;
+      out[5] += (double)b[1];
     }
     return IPC_OK;
   });

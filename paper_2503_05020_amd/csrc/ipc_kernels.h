@@ -29,6 +29,9 @@ struct GridEnt {
   int env, pad;
 };
 
+// PCG products over at most this many tiles use the latency variant
+constexpr int kWideTiles = 64;
+
 struct Lists {
   int *counts, *offs, *scan_tmp;  // item counts, exclusive scan (n_items+1)
   int2 *cand;                     // candidate pairs: PT (sv, tri) or EE (~ea, eb)

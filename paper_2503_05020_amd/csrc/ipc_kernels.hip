@@ -1912,8 +1912,6 @@ void live_tiles(hipStream_t s, const EnvState &S, const Batch &B, Lists &L, Tile
   IPC_LAUNCH(k_live_compact, nblk(B.n_vt, TB), TB, s)(B.vtiles, B.n_vt, flag, offs, out);
 }
 
-constexpr int kWideTiles = 64;
-
 template <typename T>
 void launch_spmv(hipStream_t s, bool dir, bool wide, const WorldDev &W, const EnvDev *E, const EnvState &S,
                  const Tile *tiles, int n_tiles, Lists &L, const T *ppi, const T *z, T *ppo, T *q, const T *val,
@@ -1940,8 +1938,9 @@ void pcg_iter(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState 
               int mixed, bool dir, int cur, bool last, hipEvent_t ev0, hipEvent_t ev1, const Tile *tiles,
               int n_tiles) {
   if (!n_tiles) return;
-  // bytes are counted only for the launches that are timed
-  unsigned long long *prof = ev0 ? L.prof : nullptr;
+  // bytes are counted only for the launches that are timed: counter 0 for
+  // launches of at most kWideTiles tiles, counter 1 for larger ones
+  unsigned long long *prof = ev0 ? L.prof + (n_tiles > kWideTiles ? 1 : 0) : nullptr;
   // per-tile partials, two slots each used alternately: rz_cur / rr_cur from
   // the last update (rz_cur gives alpha), rz_prev from the one before it;
   // this iteration's update writes rz_new (over rz_prev) and rr_new

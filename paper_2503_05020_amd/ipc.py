@@ -273,9 +273,10 @@ def ipc_prof_reset():
 
 
 def ipc_prof_read():
-    out = np.zeros(4)
+    out = np.zeros(6)
     _check(lib().ipc_prof_read(_d(out)))
-    return {"spmv_ms": float(out[0]), "spmv_launches": int(out[1]), "spmv_bytes": float(out[2])}
+    return {"spmv_ms": float(out[0]), "spmv_launches": int(out[1]), "spmv_bytes": float(out[2]),
+            "big_ms": float(out[3]), "big_launches": int(out[4]), "big_bytes": float(out[5])}
 
 
 def ipc_set_tuning(key: int, value: int):
