@@ -579,7 +579,9 @@ struct World {
   ipck::Batch B{};
   ipck::Lists L{};
   DBuf<int> counts, offs, scan_tmp, cand_type, cand_flag, cand_offs, act_type, fenv, inc_cnt, inc_off, inc_cur,
-      inc_ent, counter;
+      inc_ent, counter, cr_col, cr_src, cr_cnt;
+  DBuf<double> cr_val;
+  DBuf<float> cr_val32;
   DBuf<int2> cand, act;
   DBuf<int> g_ncell, g_big, g_eoff, g_bigoff, g_ebucket, g_bcnt, g_boff, g_bcur, g_bigl;
   DBuf<ipck::GridEnt> g_ent, g_sorted;
@@ -961,6 +963,7 @@ struct World {
     inc_cnt.ensure(nvw);
     inc_off.ensure(nvw);
     inc_cur.ensure(nvw);
+    cr_cnt.ensure(nvw);
     size_t nvt = vt.size() + 1;
     part_a.ensure(nvt);
     part_b0.ensure(nvt);
@@ -999,6 +1002,11 @@ struct World {
     L.inc_off = inc_off.p;
     L.inc_cur = inc_cur.p;
     L.inc_ent = inc_ent.p;
+    L.cr_col = cr_col.p;
+    L.cr_src = cr_src.p;
+    L.cr_cnt = cr_cnt.p;
+    L.cr_val = cr_val.p;
+    L.cr_val32 = cr_val32.p;
     L.part_a = part_a.p;
     L.part_b0 = part_b0.p;
     L.part_b1 = part_b1.p;
@@ -1152,8 +1160,14 @@ struct World {
     int nvw = (int)aV.cap;
     ipck::incidence(stream, W, S, L, nce, nvw);
     int ntot = read_int(L.inc_off + nvw);
-    if (inc_ent.ensure(ntot + 1)) refresh_lists();
+    bool moved = inc_ent.ensure(ntot + 1);
+    moved |= cr_col.ensure(4L * ntot + 1);
+    moved |= cr_src.ensure(4L * ntot + 1);
+    moved |= cr_val.ensure(36L * ntot + 1);
+    moved |= cr_val32.ensure(36L * ntot + 1);
+    if (moved) refresh_lists();
     ipck::incidence_fill(stream, W, S, L, nce, nvw);
+    ipck::contact_rows(stream, L, nvw, mixed);
     ipck::elastic(stream, W, envs_d, S, B);
     ipck::assemble(stream, W, envs_d, S, B, L, mixed);
     return na;

@@ -48,6 +48,10 @@ struct Lists {
   double *ce_g, *ce_H;
   // incidence
   int *inc_cnt, *inc_off, *inc_cur, *inc_ent;
+  // contact blocks per row merged by column: from 4 * inc_off[i], cr_cnt[i] of them
+  int *cr_col, *cr_src, *cr_cnt;
+  double *cr_val;
+  float *cr_val32;
   // reduction partials per vertex tile
   double *part_a, *part_b0, *part_b1, *part_c0, *part_c1;
   int *counter;  // device scratch counters [4]
@@ -86,6 +90,8 @@ void friction_elems(hipStream_t s, const WorldDev &W, const EnvDev *E, const Env
 void incidence(hipStream_t s, const WorldDev &W, const EnvState &S, Lists &L, int n_ce, int nv_world);
 void incidence_fill(hipStream_t s, const WorldDev &W, const EnvState &S, Lists &L, int n_ce, int nv_world);
 
+// merged contact blocks of every row (after incidence_fill)
+void contact_rows(hipStream_t s, Lists &L, int nv_world, int mixed);
 void elastic(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B);
 void assemble(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, const Lists &L,
               int mixed);

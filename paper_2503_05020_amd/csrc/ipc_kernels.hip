@@ -751,6 +751,56 @@ __global__ void k_inc_sort(const int *off, int *ent, int nv) {
   }
 }
 
+// Contact blocks per row, merged by column: row i's incidence entries (element,
+// local vertex a, in element order) give the blocks (a, b), b = 0..3, at
+// column v_b.  The (column, source) pairs are sorted by column with the
+// source order kept, and the blocks of one column are summed in that order
+// (FP64, plus an FP32 copy for mixed precision).  Output starts at
+// 4 * inc_off[i]; cr_cnt[i] = number of distinct columns.
+__global__ void k_contact_rows(const int *inc_off, const int *inc_ent, const int4 *ce_v, const double *ce_H, int nv,
+                               int *cr_col, int *cr_src, int *cr_cnt, double *cr_val, float *cr_val32, int mixed) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nv) return;
+  const int b0 = inc_off[i], n = 4 * (inc_off[i + 1] - b0), base = 4 * b0;
+  for (int k = 0; k < n; ++k) {
+    const int ent = inc_ent[b0 + k / 4];
+    const int4 q = ce_v[ent >> 2];
+    const int vv[4] = {q.x, q.y, q.z, q.w};
+    cr_col[base + k] = vv[k & 3];
+    cr_src[base + k] = k;
+  }
+  for (int k = 1; k < n; ++k) {  // stable insertion sort by column
+    const int c = cr_col[base + k], sv = cr_src[base + k];
+    int m = k - 1;
+    while (m >= 0 && cr_col[base + m] > c) {
+      cr_col[base + m + 1] = cr_col[base + m];
+      cr_src[base + m + 1] = cr_src[base + m];
+      --m;
+    }
+    cr_col[base + m + 1] = c;
+    cr_src[base + m + 1] = sv;
+  }
+  int out = 0;
+  for (int k = 0; k < n;) {
+    const int c = cr_col[base + k];
+    double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (; k < n && cr_col[base + k] == c; ++k) {
+      const int src = cr_src[base + k];
+      const int ent = inc_ent[b0 + src / 4];
+      const int a = ent & 3, bb = src & 3;
+      const double *B = ce_H + 90 * (size_t)(ent >> 2) + 9 * (a <= bb ? blk_index(a, bb) : blk_index(bb, a));
+      for (int r = 0; r < 3; ++r)
+        for (int cc = 0; cc < 3; ++cc) acc[3 * r + cc] += (a <= bb) ? B[3 * r + cc] : B[3 * cc + r];
+    }
+    cr_col[base + out] = c;  // k > out: this slot has been read
+    for (int r = 0; r < 9; ++r) cr_val[9 * (size_t)(base + out) + r] = acc[r];
+    if (mixed)
+      for (int r = 0; r < 9; ++r) cr_val32[9 * (size_t)(base + out) + r] = (float)acc[r];
+    ++out;
+  }
+  cr_cnt[i] = out;
+}
+
 // ---------------------------------------------------------------------------
 // elasticity per tet: gradient (12) and projected Hessian blocks (10 x 9)
 // ---------------------------------------------------------------------------
@@ -881,7 +931,7 @@ struct DirVec {
 };
 
 // One row of the matrix-vector product by kLPR = 4 lanes: lane l takes the
-// sliced-ELL slots l, l+4, ... and the row's contact entries l, l+4, ...
+// sliced-ELL slots l, l+4, ... and the row's merged contact blocks l, l+4, ...
 // (the four lanes' loads are in flight together); the four lane sums
 // are combined by two xor exchanges, which leaves the same bits in all four
 // lanes.  Every lane of the group must call it (invalid rows pass valid =
@@ -897,13 +947,22 @@ DEV void slot_acc(const T *b, const V &v, int c, double &a0, double &a1, double 
   a2 += (double)b[6 * kSlice] * x0 + (double)b[7 * kSlice] * x1 + (double)b[8 * kSlice] * x2;
 }
 
+// one contact block of a row: a += B x_c (B row-major, 9 contiguous values)
+template <typename T, typename V>
+DEV void block_acc(const T *b, const V &v, int c, double &a0, double &a1, double &a2) {
+  const double x0 = v[3 * c], x1 = v[3 * c + 1], x2 = v[3 * c + 2];
+  a0 += (double)b[0] * x0 + (double)b[1] * x1 + (double)b[2] * x2;
+  a1 += (double)b[3] * x0 + (double)b[4] * x1 + (double)b[5] * x2;
+  a2 += (double)b[6] * x0 + (double)b[7] * x1 + (double)b[8] * x2;
+}
+
 // WIDE: the lane's slots are processed four per round (their loads in
 // flight together: fewer round trips, for launches of a few tiles where
 // latency dominates); otherwise one per round (fewer registers, more waves
 // for launches over the whole batch).  Same additions in the same order.
 template <typename T, typename V, bool WIDE>
 DEV void row_product(const WorldDev &W, int i, bool valid, int l, const V &v, const T *val, const int *inc_off,
-                     const int *inc_ent, const int4 *ce_v, const double *ce_H, double y[3]) {
+                     const int *cr_cnt, const int *cr_col, const T *cr_val, double y[3]) {
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
   if (valid) {
     const int sl = i / kSlice, lane = i % kSlice;
@@ -922,29 +981,20 @@ DEV void row_product(const WorldDev &W, int i, bool valid, int l, const V &v, co
     }
 #pragma unroll 1
     for (; k < wdt; k += kLPR) slot_acc<T>(vp + (size_t)k * (9 * kSlice), v, colp[k * kSlice], a0, a1, a2);
-    // contact elements: 10 unique 3x3 blocks per element (upper triangle)
-#pragma unroll 1
-    for (int j = inc_off[i] + l; j < inc_off[i + 1]; j += kLPR) {
-      const int ent = inc_ent[j];
-      const int ce = ent >> 2, a = ent & 3;
-      const int4 q = ce_v[ce];
-      const int vv[4] = {q.x, q.y, q.z, q.w};
-      const double *H = ce_H + 90 * (size_t)ce;
-      double acc[3] = {0.0, 0.0, 0.0};
-#pragma unroll 1
-      for (int bb = 0; bb < 4; ++bb) {
-        const double *B = H + 9 * (a <= bb ? blk_index(a, bb) : blk_index(bb, a));
-        const bool tr = a > bb;
-        const double x0 = v[3 * vv[bb]], x1 = v[3 * vv[bb] + 1], x2 = v[3 * vv[bb] + 2];
-        for (int r = 0; r < 3; ++r) {
-          const double e0 = tr ? B[r] : B[3 * r], e1 = tr ? B[3 + r] : B[3 * r + 1], e2 = tr ? B[6 + r] : B[3 * r + 2];
-          acc[r] += e0 * x0 + e1 * x1 + e2 * x2;
-        }
+    // contact blocks of the row, merged by column (k_contact_rows)
+    const int cb = 4 * inc_off[i], cn = cr_cnt[i];
+    int j = l;
+    if (WIDE) {
+      for (; j + 3 * kLPR < cn; j += 4 * kLPR) {
+        int c[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) c[u] = cr_col[cb + j + u * kLPR];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) block_acc<T>(cr_val + 9 * (size_t)(cb + j + u * kLPR), v, c[u], a0, a1, a2);
       }
-      a0 += acc[0];
-      a1 += acc[1];
-      a2 += acc[2];
     }
+#pragma unroll 1
+    for (; j < cn; j += kLPR) block_acc<T>(cr_val + 9 * (size_t)(cb + j), v, cr_col[cb + j], a0, a1, a2);
   }
   a0 += __shfl_xor(a0, 1, 64);
   a1 += __shfl_xor(a1, 1, 64);
@@ -1006,10 +1056,10 @@ DEV void row_init(const WorldDev &W, bool fr, int i, T *p, T *r, T *z, T *pp, co
 // q_i = (H v)_i by the row's 4 lanes; returns v_i . q_i (same in all four
 // lanes, 0 for an invalid row).  With pp_out, v_i is also stored there.
 template <typename T, bool WIDE, typename V>
-DEV double row_spmv(const WorldDev &W, int i, bool valid, int l, const int *inc_off, const int *inc_ent,
-                    const int4 *ce_v, const double *ce_H, const V &v, T *q, const T *val, T *pp_out) {
+DEV double row_spmv(const WorldDev &W, int i, bool valid, int l, const int *inc_off, const int *cr_cnt,
+                    const int *cr_col, const T *cr_val, const V &v, T *q, const T *val, T *pp_out) {
   double y[3];
-  row_product<T, V, WIDE>(W, i, valid, l, v, val, inc_off, inc_ent, ce_v, ce_H, y);
+  row_product<T, V, WIDE>(W, i, valid, l, v, val, inc_off, cr_cnt, cr_col, cr_val, y);
   if (!valid) return 0.0;
   double pq = 0.0;
   for (int c = 0; c < 3; ++c) {
@@ -1113,8 +1163,8 @@ DEV int pcg_check(const EnvDev &E, EnvState &S, const Tile &t, const double *par
 // update, then v = z + beta pp formed on the fly and stored in pp_out.
 template <typename T, bool DIR, bool WIDE>
 __global__ void __launch_bounds__(1024) k_spmv(WorldDev W, const EnvDev *envs, EnvState S, const Tile *tiles,
-                                               const int *inc_off, const int *inc_ent, const int4 *ce_v,
-                                               const double *ce_H, const T *pp, const T *z, T *pp_out, T *q,
+                                               const int *inc_off, const int *cr_cnt, const int *cr_col,
+                                               const T *cr_val, const T *pp, const T *z, T *pp_out, T *q,
                                                const T *val, double *part_pq, const double *part_rz_old,
                                                const double *part_rz_new, const double *part_rr_new, int *pending,
                                                unsigned long long *prof) {
@@ -1137,20 +1187,19 @@ __global__ void __launch_bounds__(1024) k_spmv(WorldDev W, const EnvDev *envs, E
   const bool valid = row < t.count;
   double pq;
   if (DIR)
-    pq = row_spmv<T, WIDE>(W, i, valid, l, inc_off, inc_ent, ce_v, ce_H, DirVec<T>{z, pp, s_beta}, q, val, pp_out);
+    pq = row_spmv<T, WIDE>(W, i, valid, l, inc_off, cr_cnt, cr_col, cr_val, DirVec<T>{z, pp, s_beta}, q, val, pp_out);
   else
-    pq = row_spmv<T, WIDE>(W, i, valid, l, inc_off, inc_ent, ce_v, ce_H, StoredVec<T>{pp}, q, val, (T *)nullptr);
+    pq = row_spmv<T, WIDE>(W, i, valid, l, inc_off, cr_cnt, cr_col, cr_val, StoredVec<T>{pp}, q, val, (T *)nullptr);
   pq = rows_tree(pq, l == 0, row, sh);
   if (threadIdx.x == 0) part_pq[tile_slot(envs, t)] = pq;
   if (prof) {
-    // algorithmic bytes of this tile: stored blocks + column indices, the
-    // vector rows read and written (v and q; with DIR also z, pp and pp_out),
-    // and the contact blocks it applies
+    // algorithmic bytes of this tile: stored blocks + column indices (sliced
+    // ELL and merged contact blocks), the vector rows read and written (v and
+    // q; with DIR also z, pp and pp_out)
     double b = 0.0;
     if (valid) {
-      int nnz = W.row_nnz[i];
-      int ninc = inc_off[i + 1] - inc_off[i];
-      b = (double)nnz * (9.0 * sizeof(T) + 4.0) + (DIR ? 12.0 : 6.0) * sizeof(T) + ninc * (4.0 * 72.0 + 16.0);
+      int nnz = W.row_nnz[i] + cr_cnt[i];
+      b = (double)nnz * (9.0 * sizeof(T) + 4.0) + (DIR ? 12.0 : 6.0) * sizeof(T);
     }
     b = rows_tree(b, l == 0, row, sh);
     if (threadIdx.x == 0) atomicAdd(prof, (unsigned long long)b);
@@ -1237,8 +1286,8 @@ DEV void tile_sums2(double a, double b, double (*sh)[FB], const EnvDev &E, int t
 // PCG iterations of one environment from the state (p, r, z, pp, rz) until
 // pcg_stop; returns the iteration count
 template <typename T>
-DEV int env_iterate(const WorldDev &W, const EnvDev &E, const int *inc_off, const int *inc_ent, const int4 *ce_v,
-                    const double *ce_H, T *p, T *r, T *z, T *pp, T *q, const T *val, const T *Minv, double rz,
+DEV int env_iterate(const WorldDev &W, const EnvDev &E, const int *inc_off, const int *cr_cnt, const int *cr_col,
+                    const T *cr_val, T *p, T *r, T *z, T *pp, T *q, const T *val, const T *Minv, double rz,
                     double bb, int it, double *part_pq, double *part_rz, double *part_rr, double &bytes, bool prof,
                     double (*sh)[FB]) {
   const int r0 = E.v_off, r1 = E.v_off + E.nv_pad;
@@ -1249,10 +1298,9 @@ DEV int env_iterate(const WorldDev &W, const EnvDev &E, const int *inc_off, cons
       const int i = base + row;
       const bool valid = i < r1;
       double pq =
-          row_spmv<T, true>(W, i, valid, l, inc_off, inc_ent, ce_v, ce_H, StoredVec<T>{pp}, q, val, (T *)nullptr);
+          row_spmv<T, true>(W, i, valid, l, inc_off, cr_cnt, cr_col, cr_val, StoredVec<T>{pp}, q, val, (T *)nullptr);
       if (prof && valid && l == 0)
-        bytes += (double)W.row_nnz[i] * (9.0 * sizeof(T) + 4.0) + 6.0 * sizeof(T) +
-                 (inc_off[i + 1] - inc_off[i]) * (4.0 * 72.0 + 16.0);
+        bytes += (double)(W.row_nnz[i] + cr_cnt[i]) * (9.0 * sizeof(T) + 4.0) + 6.0 * sizeof(T);
       pq = rows_tree(pq, l == 0, row, sh[0]);
       if (threadIdx.x == 0) part_pq[E.vtile_first + (base - r0) / TB] = pq;
     }
@@ -1290,8 +1338,8 @@ DEV double block_total(double v, double (*sh)[FB]) {
 
 template <typename T>
 __global__ void __launch_bounds__(1024) k_pcg_fused(WorldDev W, const EnvDev *envs, EnvState S, const int *fenv,
-                                                    const int *inc_off, const int *inc_ent, const int4 *ce_v,
-                                                    const double *ce_H, T *p, T *r, T *z, T *pp, T *q, const T *val,
+                                                    const int *inc_off, const int *cr_cnt, const int *cr_col,
+                                                    const T *cr_val, T *p, T *r, T *z, T *pp, T *q, const T *val,
                                                     const T *Minv, double *part_pq, double *part_rz, double *part_rr,
                                                     unsigned long long *prof) {
   __shared__ double sh[2][FB];
@@ -1309,7 +1357,7 @@ __global__ void __launch_bounds__(1024) k_pcg_fused(WorldDev W, const EnvDev *en
   int it = 0;
   double bytes = 0.0;
   if (!(bb == 0.0 || !(bb == bb)))
-    it = env_iterate<T>(W, E, inc_off, inc_ent, ce_v, ce_H, p, r, z, pp, q, val, Minv, rz, bb, 0, part_pq, part_rz,
+    it = env_iterate<T>(W, E, inc_off, cr_cnt, cr_col, cr_val, p, r, z, pp, q, val, Minv, rz, bb, 0, part_pq, part_rz,
                         part_rr, bytes, prof != nullptr, sh);
   if (prof) bytes = block_total(bytes, sh);
   if (threadIdx.x == 0) {
@@ -1326,7 +1374,7 @@ __global__ void __launch_bounds__(1024) k_pcg_fused(WorldDev W, const EnvDev *en
 template <typename T>
 __global__ void __launch_bounds__(1024) k_pcg_resume(WorldDev W, const EnvDev *envs, EnvState S, const Tile *tiles,
                                                      const double *part_rz_cur, const int *inc_off,
-                                                     const int *inc_ent, const int4 *ce_v, const double *ce_H, T *p,
+                                                     const int *cr_cnt, const int *cr_col, const T *cr_val, T *p,
                                                      T *r, T *z, T *pp, T *q, const T *val, const T *Minv,
                                                      double *part_pq, double *part_rz, double *part_rr,
                                                      unsigned long long *prof) {
@@ -1337,7 +1385,7 @@ __global__ void __launch_bounds__(1024) k_pcg_resume(WorldDev W, const EnvDev *e
   const EnvDev &E = envs[e];
   double rz = env_tiles_sum(part_rz_cur, E);
   double bytes = 0.0;
-  int it = env_iterate<T>(W, E, inc_off, inc_ent, ce_v, ce_H, p, r, z, pp, q, val, Minv, rz, S.pcg_bb[e],
+  int it = env_iterate<T>(W, E, inc_off, cr_cnt, cr_col, cr_val, p, r, z, pp, q, val, Minv, rz, S.pcg_bb[e],
                           S.pcg_it[e], part_pq, part_rz, part_rr, bytes, prof != nullptr, sh);
   if (prof) bytes = block_total(bytes, sh);
   if (threadIdx.x == 0) {
@@ -1369,7 +1417,7 @@ __global__ void k_p32_to_p(WorldDev W, EnvState S, const Tile *tiles) {
 // debug: out = H in over the batch (all vertices of ACTIVE envs), one
 // 256-row tile per 1024-thread workgroup as in k_spmv
 __global__ void __launch_bounds__(1024) k_spmv_dbg(WorldDev W, EnvState S, const Tile *tiles, const int *inc_off,
-                                                   const int *inc_ent, const int4 *ce_v, const double *ce_H,
+                                                   const int *cr_cnt, const int *cr_col, const double *cr_val,
                                                    const double *in, double *out) {
   Tile t = tiles[blockIdx.x];
   if (!active_env(S, t.env)) return;
@@ -1377,8 +1425,8 @@ __global__ void __launch_bounds__(1024) k_spmv_dbg(WorldDev W, EnvState S, const
   const int i = t.start + row;
   const bool valid = row < t.count;
   double y[3];
-  row_product<double, StoredVec<double>, false>(W, i, valid, l, StoredVec<double>{in}, W.val, inc_off, inc_ent, ce_v,
-                                                ce_H, y);
+  row_product<double, StoredVec<double>, false>(W, i, valid, l, StoredVec<double>{in}, W.val, inc_off, cr_cnt,
+                                                cr_col, cr_val, y);
   if (valid && l < 3) out[3 * i + l] = y[l];
 }
 
@@ -1882,6 +1930,11 @@ void incidence_fill(hipStream_t s, const WorldDev &W, const EnvState &S, Lists &
   }
 }
 
+void contact_rows(hipStream_t s, Lists &L, int nv_world, int mixed) {
+  IPC_LAUNCH(k_contact_rows, nblk(nv_world, TB), TB, s)(L.inc_off, L.inc_ent, L.ce_v, L.ce_H, nv_world, L.cr_col,
+                                                        L.cr_src, L.cr_cnt, L.cr_val, L.cr_val32, mixed);
+}
+
 void elastic(hipStream_t s, const WorldDev &W, const EnvDev *, const EnvState &S, const Batch &B) {
   if (B.n_tt) IPC_LAUNCH(k_elastic, B.n_tt, TB, s)(W, S, B.ttiles);
 }
@@ -1913,23 +1966,34 @@ void live_tiles(hipStream_t s, const EnvState &S, const Batch &B, Lists &L, Tile
 }
 
 template <typename T>
+const T *cr_vals(const Lists &L);
+template <>
+const double *cr_vals<double>(const Lists &L) {
+  return L.cr_val;
+}
+template <>
+const float *cr_vals<float>(const Lists &L) {
+  return L.cr_val32;
+}
+
+template <typename T>
 void launch_spmv(hipStream_t s, bool dir, bool wide, const WorldDev &W, const EnvDev *E, const EnvState &S,
                  const Tile *tiles, int n_tiles, Lists &L, const T *ppi, const T *z, T *ppo, T *q, const T *val,
                  const double *rz_prev, const double *rz_cur, const double *rr_cur, int *pending,
                  unsigned long long *prof) {
   const int nt = kLPR * TB;
   if (dir && wide)
-    IPC_LAUNCH((k_spmv<T, true, true>), n_tiles, nt, s)(W, E, S, tiles, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, ppi, z,
+    IPC_LAUNCH((k_spmv<T, true, true>), n_tiles, nt, s)(W, E, S, tiles, L.inc_off, L.cr_cnt, L.cr_col, cr_vals<T>(L), ppi, z,
                                                         ppo, q, val, L.part_a, rz_prev, rz_cur, rr_cur, pending, prof);
   else if (dir)
-    IPC_LAUNCH((k_spmv<T, true, false>), n_tiles, nt, s)(W, E, S, tiles, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, ppi, z,
+    IPC_LAUNCH((k_spmv<T, true, false>), n_tiles, nt, s)(W, E, S, tiles, L.inc_off, L.cr_cnt, L.cr_col, cr_vals<T>(L), ppi, z,
                                                          ppo, q, val, L.part_a, rz_prev, rz_cur, rr_cur, pending, prof);
   else if (wide)
-    IPC_LAUNCH((k_spmv<T, false, true>), n_tiles, nt, s)(W, E, S, tiles, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, ppi, z,
+    IPC_LAUNCH((k_spmv<T, false, true>), n_tiles, nt, s)(W, E, S, tiles, L.inc_off, L.cr_cnt, L.cr_col, cr_vals<T>(L), ppi, z,
                                                          (T *)nullptr, q, val, L.part_a, nullptr, nullptr, nullptr,
                                                          pending, prof);
   else
-    IPC_LAUNCH((k_spmv<T, false, false>), n_tiles, nt, s)(W, E, S, tiles, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, ppi, z,
+    IPC_LAUNCH((k_spmv<T, false, false>), n_tiles, nt, s)(W, E, S, tiles, L.inc_off, L.cr_cnt, L.cr_col, cr_vals<T>(L), ppi, z,
                                                           (T *)nullptr, q, val, L.part_a, nullptr, nullptr, nullptr,
                                                           pending, prof);
 }
@@ -1978,10 +2042,10 @@ void pcg_fused(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState
                Lists &L, int mixed) {
   if (!n_fenv) return;
   if (!mixed)
-    IPC_LAUNCH(k_pcg_fused<double>, n_fenv, FB, s)(W, E, S, fenv, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, W.p, W.r, W.z,
+    IPC_LAUNCH(k_pcg_fused<double>, n_fenv, FB, s)(W, E, S, fenv, L.inc_off, L.cr_cnt, L.cr_col, L.cr_val, W.p, W.r, W.z,
                                                   W.pp, W.q, W.val, W.Minv, L.part_a, L.part_b0, L.part_c0, nullptr);
   else
-    IPC_LAUNCH(k_pcg_fused<float>, n_fenv, FB, s)(W, E, S, fenv, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, W.p32, W.r32,
+    IPC_LAUNCH(k_pcg_fused<float>, n_fenv, FB, s)(W, E, S, fenv, L.inc_off, L.cr_cnt, L.cr_col, L.cr_val32, W.p32, W.r32,
                                                  W.z32, W.pp32, W.q32, W.val32, W.Minv32, L.part_a, L.part_b0,
                                                  L.part_c0, nullptr);
 }
@@ -1995,11 +2059,11 @@ void pcg_resume(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvStat
   double *rz_tmp = (it & 1) ? L.part_b0 : L.part_b1;
   double *rr_tmp = (it & 1) ? L.part_c0 : L.part_c1;
   if (!mixed)
-    IPC_LAUNCH(k_pcg_resume<double>, n_tiles, FB, s)(W, E, S, tiles, rz, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, W.p,
+    IPC_LAUNCH(k_pcg_resume<double>, n_tiles, FB, s)(W, E, S, tiles, rz, L.inc_off, L.cr_cnt, L.cr_col, L.cr_val, W.p,
                                                      W.r, W.z, cur ? W.pp2 : W.pp, W.q, W.val, W.Minv, L.part_a, rz_tmp, rr_tmp,
                                                      nullptr);
   else
-    IPC_LAUNCH(k_pcg_resume<float>, n_tiles, FB, s)(W, E, S, tiles, rz, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, W.p32,
+    IPC_LAUNCH(k_pcg_resume<float>, n_tiles, FB, s)(W, E, S, tiles, rz, L.inc_off, L.cr_cnt, L.cr_col, L.cr_val32, W.p32,
                                                     W.r32, W.z32, cur ? W.pp2_32 : W.pp32, W.q32, W.val32, W.Minv32, L.part_a, rz_tmp,
                                                     rr_tmp, nullptr);
 }
@@ -2010,7 +2074,7 @@ void pcg_finish(hipStream_t s, const WorldDev &W, const EnvState &S, const Batch
 
 void spmv_debug(hipStream_t s, const WorldDev &W, const EnvDev *, const EnvState &S, const Batch &B, Lists &L,
                 const double *in, double *out) {
-  if (B.n_vt) IPC_LAUNCH(k_spmv_dbg, B.n_vt, kLPR * TB, s)(W, S, B.vtiles, L.inc_off, L.inc_ent, L.ce_v, L.ce_H, in, out);
+  if (B.n_vt) IPC_LAUNCH(k_spmv_dbg, B.n_vt, kLPR * TB, s)(W, S, B.vtiles, L.inc_off, L.cr_cnt, L.cr_col, L.cr_val, in, out);
 }
 
 void conv_check(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L,
