@@ -585,6 +585,7 @@ struct World {
   DBuf<int2> cand, act;
   DBuf<int> g_ncell, g_big, g_eoff, g_bigoff, g_ebucket, g_bcnt, g_boff, g_bcur, g_bigl;
   DBuf<ipck::GridEnt> g_ent, g_sorted;
+  DBuf<int2> bp_stash;
   DBuf<double> cand_d2, e_c, fw, fn, flam, e_f, ce_g, ce_H, part_a, part_b0, part_b1, part_c0, part_c1;
   DBuf<int4> fv, ce_v;
   int *pinned = nullptr;  // host mirror of counters
@@ -954,6 +955,7 @@ struct World {
     B.n_items = item_off;
     counts.ensure(item_off + 1);
     offs.ensure(item_off + 2);
+    bp_stash.ensure((size_t)ipck::kStash * item_off + 1);
     g_ncell.ensure(bitem_off + 1);
     g_big.ensure(bitem_off + 1);
     g_eoff.ensure(bitem_off + 2);
@@ -1025,6 +1027,7 @@ struct World {
     L.g_bigl = g_bigl.p;
     L.g_ent = g_ent.p;
     L.g_sorted = g_sorted.p;
+    L.bp_stash = bp_stash.p;
   }
 
   void set_prof(bool on) {
@@ -1084,6 +1087,7 @@ struct World {
     ipck::bp_grid_count(stream, W, envs_d, S, B, L, nb);
     ipck::scan_int(stream, L.counts, L.offs, B.n_items, L.scan_tmp);
     int n = read_int(L.offs + B.n_items);
+    const bool overflow = read_int(L.counter + 4) > 0;
     // each list is sized on its own: capacities are rounded independently
     moved = cand.ensure(n + 1);
     moved |= cand_type.ensure(n + 1);
@@ -1092,7 +1096,7 @@ struct World {
     moved |= cand_d2.ensure(n + 1);
     moved |= e_c.ensure(n + 1);
     if (moved) refresh_lists();
-    ipck::bp_grid_write(stream, W, envs_d, S, B, L, nb);
+    ipck::bp_grid_write(stream, W, envs_d, S, B, L, nb, overflow);
     ipck::cand_segments(stream, envs_d, S, B, L);
     return n;
   }

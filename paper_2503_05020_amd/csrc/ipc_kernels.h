@@ -31,6 +31,8 @@ struct GridEnt {
 
 // PCG products over at most this many tiles use the latency variant
 constexpr int kWideTiles = 64;
+// broad phase: pairs per query kept by the counting pass
+constexpr int kStash = 12;
 
 struct Lists {
   int *counts, *offs, *scan_tmp;  // item counts, exclusive scan (n_items+1)
@@ -58,6 +60,7 @@ struct Lists {
   // hash grid
   int *g_ncell, *g_big, *g_eoff, *g_bigoff, *g_ebucket, *g_bcnt, *g_boff, *g_bcur, *g_bigl;
   GridEnt *g_ent, *g_sorted;
+  int2 *bp_stash;  // first pairs of each query, from the counting pass
   unsigned long long *prof;  // algorithmic bytes moved by profiled kernels (nullptr = off)
 };
 
@@ -77,7 +80,7 @@ void grid_fill(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState
 void bp_grid_count(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L,
                    unsigned nbuckets);
 void bp_grid_write(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L,
-                   unsigned nbuckets);
+                   unsigned nbuckets, bool overflow);
 void cand_segments(hipStream_t s, const EnvDev *E, const EnvState &S, const Batch &B, const Lists &L);
 
 void classify_cands(hipStream_t s, const WorldDev &W, const EnvDev *E, const Lists &L, int n, const double *x);
