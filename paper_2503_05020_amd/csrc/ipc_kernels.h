@@ -51,7 +51,9 @@ struct Lists {
   // incidence
   int *inc_cnt, *inc_off, *inc_cur, *inc_ent;
   // contact blocks per row merged by column: from 4 * inc_off[i], cr_cnt[i] of them
-  int *cr_col, *cr_src, *cr_cnt;
+  int *cr_col, *cr_cnt;
+  int *cr_key, *cr_scol, *cr_ssrc;           // expanded pairs: columns, sorted columns, sorted sources
+  int *cr_flag, *cr_pos, *cr_rows;           // rows with contact: flags, scan, list
   double *cr_val;
   float *cr_val32;
   // reduction partials per vertex tile
@@ -94,7 +96,7 @@ void incidence(hipStream_t s, const WorldDev &W, const EnvState &S, Lists &L, in
 void incidence_fill(hipStream_t s, const WorldDev &W, const EnvState &S, Lists &L, int n_ce, int nv_world);
 
 // merged contact blocks of every row (after incidence_fill)
-void contact_rows(hipStream_t s, Lists &L, int nv_world, int mixed);
+void contact_rows(hipStream_t s, Lists &L, int nv_world, int n_inc, int mixed);
 void elastic(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B);
 void assemble(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, const Lists &L,
               int mixed);

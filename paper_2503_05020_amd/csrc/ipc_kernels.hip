@@ -786,52 +786,76 @@ __global__ void k_inc_sort(const int *off, int *ent, int nv) {
 
 // Contact blocks per row, merged by column: row i's incidence entries (element,
 // local vertex a, in element order) give the blocks (a, b), b = 0..3, at
-// column v_b.  The (column, source) pairs are sorted by column with the
-// source order kept, and the blocks of one column are summed in that order
-// (FP64, plus an FP32 copy for mixed precision).  Output starts at
-// 4 * inc_off[i]; cr_cnt[i] = number of distinct columns.
-__global__ void k_contact_rows(const int *inc_off, const int *inc_ent, const int4 *ce_v, const double *ce_H, int nv,
-                               int *cr_col, int *cr_src, int *cr_cnt, double *cr_val, float *cr_val32, int mixed) {
+// column v_b, numbered k = 4 * entry + b.  They are ordered by (column, k) and
+// the blocks of one column are summed in that order (FP64, plus an FP32 copy
+// for mixed precision).  Output starts at 4 * inc_off[i]; cr_cnt[i] = number
+// of distinct columns.  One 64-lane wavefront per row with contact; the rows
+// are listed by k_contact_row_list.
+__global__ void k_contact_row_flags(const int *inc_off, int nv, int *flag, int *cr_cnt) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nv) return;
+  flag[i] = inc_off[i + 1] > inc_off[i] ? 1 : 0;
+  cr_cnt[i] = 0;
+}
+
+__global__ void k_contact_row_list(const int *flag, const int *pos, int nv, int *rows) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nv && flag[i]) rows[pos[i]] = i;
+}
+
+__global__ void __launch_bounds__(64) k_contact_rows(const int *rows, const int *n_rows, const int *inc_off,
+                                                     const int *inc_ent, const int4 *ce_v, const double *ce_H,
+                                                     int *cr_key, int *cr_scol, int *cr_ssrc, int *cr_col, int *cr_cnt,
+                                                     double *cr_val, float *cr_val32, int mixed) {
+  if ((int)blockIdx.x >= *n_rows) return;
+  const int i = rows[blockIdx.x];
+  const int lane = threadIdx.x;
   const int b0 = inc_off[i], n = 4 * (inc_off[i + 1] - b0), base = 4 * b0;
-  for (int k = 0; k < n; ++k) {
-    const int ent = inc_ent[b0 + k / 4];
-    const int4 q = ce_v[ent >> 2];
+  // columns of the expanded pairs
+  for (int k = lane; k < n; k += 64) {
+    const int4 q = ce_v[inc_ent[b0 + k / 4] >> 2];
     const int vv[4] = {q.x, q.y, q.z, q.w};
-    cr_col[base + k] = vv[k & 3];
-    cr_src[base + k] = k;
+    cr_key[base + k] = vv[k & 3];
   }
-  for (int k = 1; k < n; ++k) {  // stable insertion sort by column
-    const int c = cr_col[base + k], sv = cr_src[base + k];
-    int m = k - 1;
-    while (m >= 0 && cr_col[base + m] > c) {
-      cr_col[base + m + 1] = cr_col[base + m];
-      cr_src[base + m + 1] = cr_src[base + m];
-      --m;
+  __syncthreads();
+  // stable order by column: the rank of pair k
+  for (int k = lane; k < n; k += 64) {
+    const int c = cr_key[base + k];
+    int r = 0;
+    for (int m = 0; m < n; ++m) {
+      const int cm = cr_key[base + m];
+      r += (cm < c || (cm == c && m < k)) ? 1 : 0;
     }
-    cr_col[base + m + 1] = c;
-    cr_src[base + m + 1] = sv;
+    cr_scol[base + r] = c;
+    cr_ssrc[base + r] = k;
   }
-  int out = 0;
-  for (int k = 0; k < n;) {
-    const int c = cr_col[base + k];
-    double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (; k < n && cr_col[base + k] == c; ++k) {
-      const int src = cr_src[base + k];
-      const int ent = inc_ent[b0 + src / 4];
-      const int a = ent & 3, bb = src & 3;
-      const double *B = ce_H + 90 * (size_t)(ent >> 2) + 9 * (a <= bb ? blk_index(a, bb) : blk_index(bb, a));
-      for (int r = 0; r < 3; ++r)
-        for (int cc = 0; cc < 3; ++cc) acc[3 * r + cc] += (a <= bb) ? B[3 * r + cc] : B[3 * cc + r];
+  __syncthreads();
+  // runs of equal columns: the first pair of each run sums the run's blocks
+  int heads = 0;
+  for (int k0 = 0; k0 < n; k0 += 64) {  // same trip count in every lane
+    const int k = k0 + lane;
+    const bool head = k < n && (k == 0 || cr_scol[base + k] != cr_scol[base + k - 1]);
+    const unsigned long long mask = __ballot(head);
+    if (head) {
+      const int out = heads + __builtin_popcountll(mask & ((1ull << lane) - 1ull));
+      const int c = cr_scol[base + k];
+      double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+      for (int m = k; m < n && cr_scol[base + m] == c; ++m) {
+        const int src = cr_ssrc[base + m];
+        const int ent = inc_ent[b0 + src / 4];
+        const int a = ent & 3, bb = src & 3;
+        const double *B = ce_H + 90 * (size_t)(ent >> 2) + 9 * (a <= bb ? blk_index(a, bb) : blk_index(bb, a));
+        for (int r = 0; r < 3; ++r)
+          for (int cc = 0; cc < 3; ++cc) acc[3 * r + cc] += (a <= bb) ? B[3 * r + cc] : B[3 * cc + r];
+      }
+      cr_col[base + out] = c;
+      for (int r = 0; r < 9; ++r) cr_val[9 * (size_t)(base + out) + r] = acc[r];
+      if (mixed)
+        for (int r = 0; r < 9; ++r) cr_val32[9 * (size_t)(base + out) + r] = (float)acc[r];
     }
-    cr_col[base + out] = c;  // k > out: this slot has been read
-    for (int r = 0; r < 9; ++r) cr_val[9 * (size_t)(base + out) + r] = acc[r];
-    if (mixed)
-      for (int r = 0; r < 9; ++r) cr_val32[9 * (size_t)(base + out) + r] = (float)acc[r];
-    ++out;
+    heads += __builtin_popcountll(mask);
   }
-  cr_cnt[i] = out;
+  if (lane == 0) cr_cnt[i] = heads;
 }
 
 // ---------------------------------------------------------------------------
@@ -1965,9 +1989,16 @@ void incidence_fill(hipStream_t s, const WorldDev &W, const EnvState &S, Lists &
   }
 }
 
-void contact_rows(hipStream_t s, Lists &L, int nv_world, int mixed) {
-  IPC_LAUNCH(k_contact_rows, nblk(nv_world, TB), TB, s)(L.inc_off, L.inc_ent, L.ce_v, L.ce_H, nv_world, L.cr_col,
-                                                        L.cr_src, L.cr_cnt, L.cr_val, L.cr_val32, mixed);
+void contact_rows(hipStream_t s, Lists &L, int nv_world, int n_inc, int mixed) {
+  IPC_LAUNCH(k_contact_row_flags, nblk(nv_world, TB), TB, s)(L.inc_off, nv_world, L.cr_flag, L.cr_cnt);
+  scan_int(s, L.cr_flag, L.cr_pos, nv_world, L.scan_tmp);
+  IPC_LAUNCH(k_contact_row_list, nblk(nv_world, TB), TB, s)(L.cr_flag, L.cr_pos, nv_world, L.cr_rows);
+  // at most one listed row per incidence entry; blocks past the list's length exit
+  const int grid = std::min(n_inc, nv_world);
+  if (grid > 0)
+    IPC_LAUNCH(k_contact_rows, grid, 64, s)(L.cr_rows, L.cr_pos + nv_world, L.inc_off, L.inc_ent, L.ce_v, L.ce_H,
+                                           L.cr_key, L.cr_scol, L.cr_ssrc, L.cr_col, L.cr_cnt, L.cr_val, L.cr_val32,
+                                           mixed);
 }
 
 void elastic(hipStream_t s, const WorldDev &W, const EnvDev *, const EnvState &S, const Batch &B) {
