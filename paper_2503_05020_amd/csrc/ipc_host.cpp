@@ -579,7 +579,7 @@ struct World {
   ipck::Batch B{};
   ipck::Lists L{};
   DBuf<int> counts, offs, scan_tmp, cand_type, cand_flag, cand_offs, act_type, fenv, inc_cnt, inc_off, inc_cur,
-      inc_ent, counter, cr_col, cr_src, cr_cnt;
+      inc_ent, counter, cr_col, cr_cnt, cr_key, cr_scol, cr_ssrc, cr_flag, cr_pos, cr_rows;
   DBuf<double> cr_val;
   DBuf<float> cr_val32;
   DBuf<int2> cand, act;
@@ -966,6 +966,9 @@ struct World {
     inc_off.ensure(nvw);
     inc_cur.ensure(nvw);
     cr_cnt.ensure(nvw);
+    cr_flag.ensure(nvw);
+    cr_pos.ensure(nvw + 1);
+    cr_rows.ensure(nvw);
     size_t nvt = vt.size() + 1;
     part_a.ensure(nvt);
     part_b0.ensure(nvt);
@@ -1005,8 +1008,13 @@ struct World {
     L.inc_cur = inc_cur.p;
     L.inc_ent = inc_ent.p;
     L.cr_col = cr_col.p;
-    L.cr_src = cr_src.p;
     L.cr_cnt = cr_cnt.p;
+    L.cr_key = cr_key.p;
+    L.cr_scol = cr_scol.p;
+    L.cr_ssrc = cr_ssrc.p;
+    L.cr_flag = cr_flag.p;
+    L.cr_pos = cr_pos.p;
+    L.cr_rows = cr_rows.p;
     L.cr_val = cr_val.p;
     L.cr_val32 = cr_val32.p;
     L.part_a = part_a.p;
@@ -1123,8 +1131,9 @@ struct World {
   }
 
   // friction pairs = active pairs at x^n (positions in W.x)
-  void friction_setup() {
-    int nc = broad_phase(W.x, nullptr);
+  // lagged friction set from the active pairs at W.x (= xn at step start),
+  // classified from a candidate list of nc pairs whose boxes contain W.x
+  void friction_setup(int nc) {
     int na = active_pairs(nc, W.x);
     bool moved = fv.ensure(na + 1);
     moved |= fw.ensure(4L * (na + 1));
@@ -1166,12 +1175,15 @@ struct World {
     int ntot = read_int(L.inc_off + nvw);
     bool moved = inc_ent.ensure(ntot + 1);
     moved |= cr_col.ensure(4L * ntot + 1);
-    moved |= cr_src.ensure(4L * ntot + 1);
+    moved |= cr_key.ensure(4L * ntot + 1);
+    moved |= cr_scol.ensure(4L * ntot + 1);
+    moved |= cr_ssrc.ensure(4L * ntot + 1);
+    moved |= scan_tmp.ensure(nvw / 1024 + 64);
     moved |= cr_val.ensure(36L * ntot + 1);
     moved |= cr_val32.ensure(36L * ntot + 1);
     if (moved) refresh_lists();
     ipck::incidence_fill(stream, W, S, L, nce, nvw);
-    ipck::contact_rows(stream, L, nvw, mixed);
+    ipck::contact_rows(stream, L, nvw, ntot, mixed);
     ipck::elastic(stream, W, envs_d, S, B);
     ipck::assemble(stream, W, envs_d, S, B, L, mixed);
     return na;
@@ -1314,9 +1326,10 @@ public:
     swept_n = -1;
     ipck::env_begin(stream, S, B);
     ipck::begin_step(stream, W, envs_d, S, B);
-    friction_setup();
-    // Dirichlet move: CCD-safe and inversion-free, else the env fails
+    // one swept pass over the Dirichlet move (free vertices stay at xn): its
+    // boxes contain xn, so it also yields the friction set's pairs at xn
     int nc = broad_phase(W.xn, W.p);
+    friction_setup(nc);
     ipck::ccd_init(stream, S, B);
     ipck::accd(stream, W, envs_d, S, L, nc, W.xn, W.p);
     ipck::dbc_check_J(stream, W, envs_d, S, B);
@@ -2177,8 +2190,8 @@ int ipc_debug_begin_step(ipc_scene s, double *x_start) {
       w.upload_env(s->slot);
       ipck::env_begin(w.stream, w.S, w.B);
       ipck::begin_step(w.stream, w.W, w.envs_d, w.S, w.B);
-      w.friction_setup();
       int nc = w.broad_phase(w.W.xn, w.W.p);
+      w.friction_setup(nc);
       ipck::ccd_init(w.stream, w.S, w.B);
       ipck::accd(w.stream, w.W, w.envs_d, w.S, w.L, nc, w.W.xn, w.W.p);
       ipck::dbc_check_J(w.stream, w.W, w.envs_d, w.S, w.B);
