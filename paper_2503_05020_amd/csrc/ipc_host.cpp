@@ -1784,21 +1784,28 @@ void server_loop(ipc_server_s *sv, size_t k) {
       for (Request *r : run) scenes.push_back(r->scene);
       infos.assign(run.size(), ipc_step_info{});
       run_steps_lane(scenes, 1, infos.data());
+      {
+        // another lane's device error retires every request: leave them alone
+        std::lock_guard<std::mutex> lk(sv->mu);
+        if (sv->dead) return;
+      }
       std::vector<Request *> done;
       for (size_t i = 0; i < run.size(); ++i) {
         Request *r = run[i];
-        bool fin = r->scene->failed || r->steps_done + infos[i].steps_done >= r->n_steps;
+        ipc_scene sc = scenes[i];
+        bool fin = sc->failed || r->steps_done + infos[i].steps_done >= r->n_steps;
         if (fin) {
           r->pos.resize(3 * (size_t)r->nv);
           r->vel.resize(3 * (size_t)r->nv);
           std::lock_guard<std::mutex> lk(w->mu);
-          get_x(*w, r->scene, w->W.x, r->pos.data());
-          get_x(*w, r->scene, w->W.v, r->vel.data());
-          w->remove_scene(r->scene->slot);
+          get_x(*w, sc, w->W.x, r->pos.data());
+          get_x(*w, sc, w->W.v, r->vel.data());
+          w->remove_scene(sc->slot);
           done.push_back(r);
         }
       }
       std::lock_guard<std::mutex> lk(sv->mu);
+      if (sv->dead) return;
       long long tick_steps = 0;
       for (size_t i = 0; i < run.size(); ++i) {
         Request *r = run[i];
