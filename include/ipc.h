@@ -153,10 +153,6 @@ int ipc_prof_read(double *out);
  *     variable IPC_TAIL_TILES).
  *   IPC_TUNE_FUSED_PCG: 1 = every environment of up to 8192 rows runs its
  *     whole PCG in one workgroup from the start (default 0; IPC_FUSED_PCG).
- *   IPC_TUNE_FOLD_DIR: 1 = the tiled PCG forms the next search direction
- *     inside the following matrix-vector product (two launches per
- *     iteration), 0 = a separate direction kernel (default; the extra
- *     vector gathers cost more than the launch they save; IPC_FOLD_DIR).
  *   IPC_TUNE_NARROW: 1 = once at most half of a batch still iterates its
  *     Newton loop, the batch is laid out again with those environments only
  *     (default), 0 = never (IPC_NARROW).
@@ -172,7 +168,6 @@ int ipc_prof_read(double *out);
  * Returns IPC_OK, or IPC_E_ARG for an unknown key or a negative value. */
 #define IPC_TUNE_TAIL_TILES 1
 #define IPC_TUNE_FUSED_PCG 2
-#define IPC_TUNE_FOLD_DIR 3
 #define IPC_TUNE_NARROW 4
 #define IPC_TUNE_LANES 5
 int ipc_set_tuning(int32_t key, int64_t value);

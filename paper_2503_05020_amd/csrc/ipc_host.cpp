@@ -615,7 +615,7 @@ struct World {
     reg(aV, (void **)&W.r, 24);
     reg(aV, (void **)&W.z, 24);
     reg(aV, (void **)&W.pp, 24);
-    reg(aV, (void **)&W.pp2, 24);
+    reg(aV, (void **)&W.w, 24);
     reg(aV, (void **)&W.q, 24);
     reg(aV, (void **)&W.mass, 8);
     reg(aV, (void **)&W.Minv, 72);
@@ -624,7 +624,7 @@ struct World {
     reg(aV, (void **)&W.r32, 12);
     reg(aV, (void **)&W.z32, 12);
     reg(aV, (void **)&W.pp32, 12);
-    reg(aV, (void **)&W.pp2_32, 12);
+    reg(aV, (void **)&W.w32, 12);
     reg(aV, (void **)&W.q32, 12);
     reg(aV, (void **)&W.p32, 12);
     reg(aV, (void **)&W.Minv32, 36);
@@ -668,7 +668,8 @@ struct World {
                  (void **)&S.snap_bad};
     state_ll = {(void **)&S.pcg_total, (void **)&S.amax_bits};
     state_dbl = {(void **)&S.alpha, (void **)&S.E0,  (void **)&S.E1,       (void **)&S.pinf,
-                 (void **)&S.pcg_bb, (void **)&S.kA, (void **)&S.viol, (void **)&S.viol_prev};
+                 (void **)&S.pcg_bb, (void **)&S.kA, (void **)&S.viol, (void **)&S.viol_prev,
+                 (void **)&S.cg_a0,  (void **)&S.cg_a1, (void **)&S.cg_g0, (void **)&S.cg_g1};
   }
 
   void ensure_envs(size_t n) {
@@ -783,8 +784,6 @@ struct World {
     HC(hipMemsetAsync(W.p + 3 * vo, 0, 24 * R.v_n, stream));
     HC(hipMemsetAsync(W.pp + 3 * vo, 0, 24 * R.v_n, stream));
     HC(hipMemsetAsync(W.pp32 + 3 * vo, 0, 12 * R.v_n, stream));
-    HC(hipMemsetAsync(W.pp2 + 3 * vo, 0, 24 * R.v_n, stream));
-    HC(hipMemsetAsync(W.pp2_32 + 3 * vo, 0, 12 * R.v_n, stream));
     HC(hipMemsetAsync(W.lam + 3 * vo, 0, 24 * R.v_n, stream));
     std::vector<int> vt(H.vt_ent.size());
     for (size_t i = 0; i < vt.size(); ++i) vt[i] = (H.vt_ent[i] >> 2) * 4 + (int)to * 4 + (H.vt_ent[i] & 3);
@@ -1202,9 +1201,6 @@ public:
   // live vertex tiles at or below which the tiled PCG hands the remaining
   // environments to one workgroup each (0 = never)
   int tail_tiles = env_knob("IPC_TAIL_TILES", 0);
-  // 1: the direction update is folded into the next product (two launches
-  // per PCG iteration); 0: a separate direction kernel every iteration
-  int fold_dir = env_knob("IPC_FOLD_DIR", 0) ? 1 : 0;
   // 1: re-lay the batch out with the still-iterating environments once at
   // most half of it iterates (narrow_batch)
   int narrow = env_knob("IPC_NARROW", 1) ? 1 : 0;
@@ -1217,7 +1213,6 @@ public:
   void copy_knobs(const World &o) {
     set_fused(o.fused_pcg);
     tail_tiles = o.tail_tiles;
-    fold_dir = o.fold_dir;
     narrow = o.narrow;
     set_prof(o.prof_on);
   }
@@ -1237,24 +1232,23 @@ public:
       return mx;
     }
     ipck::pcg_init(stream, W, envs_d, S, B, L, pending, mixed);
+    // an environment's solve stops at the latest in the iteration whose index
+    // reaches its cap of 30 n_v + 10 (that iteration only takes the test)
     int cap = 0;
-    for (int e : batch_envs) cap = std::max(cap, 30 * envs_h[e].nv + 10);
+    for (int e : batch_envs) cap = std::max(cap, 30 * envs_h[e].nv + 11);
     int it = 0;
     size_t nev = 0;
     // iterate over the tiles of environments still solving; the list is
     // compacted whenever an environment has converged since the last poll
     const Tile *tl = B.vtiles;
     int ntl = B.n_vt, last_pending = -1;
-    int cur = 0;  // pp buffer holding the current direction
     std::vector<char> ev_big;  // per timed launch: over more than kWideTiles tiles
     const bool tr = tracing();
     double t_launch = 0.0, t_wait = 0.0;
     auto now = []() { return std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now().time_since_epoch()).count(); };
     while (true) {
       double t0 = tr ? now() : 0.0;
-      // a block of 8 iterations: the first product reads the stored
-      // direction, the next 7 form it on the fly, the last update is
-      // followed by the stopping test + direction kernel before the poll
+      // a block of 8 iterations between polls of the pending count
       for (int j = 0; j < 8; ++j) {
         hipEvent_t e0 = nullptr, e1 = nullptr;
         // every 16th iteration is timed (an event pair costs a few us of
@@ -1264,9 +1258,7 @@ public:
           e1 = pool_event(nev++);
           ev_big.push_back(ntl > ipck::kWideTiles ? 1 : 0);
         }
-        const bool dir = fold_dir && j > 0;
-        ipck::pcg_iter(stream, W, envs_d, S, L, it++, pending, mixed, dir, cur, !fold_dir || j == 7, e0, e1, tl, ntl);
-        if (dir) cur = 1 - cur;
+        ipck::pcg_iter(stream, W, envs_d, S, L, it++, pending, mixed, e0, e1, tl, ntl);
       }
       double t1 = tr ? now() : 0.0;
       int pend = read_int(pending);
@@ -1283,7 +1275,7 @@ public:
         if (ntl <= tail_tiles) {
           // few tiles left: their launches would be latency-bound, so one
           // workgroup per environment finishes the solves in one launch
-          ipck::pcg_resume(stream, W, envs_d, S, L, tl, ntl, it, cur, mixed);
+          ipck::pcg_resume(stream, W, envs_d, S, L, tl, ntl, it, mixed);
           break;
         }
       }
@@ -1986,7 +1978,7 @@ int ipc_set_tuning(int32_t key, int64_t value) {
       g_lanes = (int)value;
       return IPC_OK;
     }
-    if (key != IPC_TUNE_TAIL_TILES && key != IPC_TUNE_FUSED_PCG && key != IPC_TUNE_FOLD_DIR && key != IPC_TUNE_NARROW)
+    if (key != IPC_TUNE_TAIL_TILES && key != IPC_TUNE_FUSED_PCG && key != IPC_TUNE_NARROW)
       throw ApiError(IPC_E_ARG, "unknown tuning key");
     for (World *pw : worlds_for_current_device()) {
       World &w = *pw;
@@ -1995,8 +1987,6 @@ int ipc_set_tuning(int32_t key, int64_t value) {
         w.tail_tiles = (int)std::min<int64_t>(value, 1 << 30);
       else if (key == IPC_TUNE_FUSED_PCG)
         w.set_fused(value != 0);
-      else if (key == IPC_TUNE_FOLD_DIR)
-        w.fold_dir = value != 0;
       else
         w.narrow = value != 0;
     }
@@ -2017,8 +2007,6 @@ int ipc_get_tuning(int32_t key, int64_t *value) {
       *value = w.tail_tiles;
     else if (key == IPC_TUNE_FUSED_PCG)
       *value = w.fused_pcg;
-    else if (key == IPC_TUNE_FOLD_DIR)
-      *value = w.fold_dir;
     else if (key == IPC_TUNE_NARROW)
       *value = w.narrow;
     else

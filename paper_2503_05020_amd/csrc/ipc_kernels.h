@@ -56,7 +56,7 @@ struct Lists {
   int *cr_flag, *cr_pos, *cr_rows;           // rows with contact: flags, scan, list
   double *cr_val;
   float *cr_val32;
-  // reduction partials per vertex tile
+  // reduction partials per vertex tile (PCG: a = u.Hu, b0/b1 = r.u, c0/c1 = r.r)
   double *part_a, *part_b0, *part_b1, *part_c0, *part_c1;
   int *counter;  // device scratch counters [4]
   // hash grid
@@ -103,18 +103,16 @@ void assemble(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState 
 
 void pcg_init(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L,
               int *pending, int mixed);
-// one tiled PCG iteration: product (dir: with the stopping test of the last
-// update and the next direction formed from pp buffer `cur` into the other
-// one), update, and with `last` the stopping test + direction in place
+// one tiled PCG iteration (product with its dot product, then the update with
+// the stopping test) over the listed tiles; `it` = iterations done so far
 void pcg_iter(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, Lists &L, int it, int *pending,
-              int mixed, bool dir, int cur, bool last, hipEvent_t ev0, hipEvent_t ev1, const Tile *tiles,
-              int n_tiles);
+              int mixed, hipEvent_t ev0, hipEvent_t ev1, const Tile *tiles, int n_tiles);
 // tiles of environments whose PCG still iterates -> out (count at offs[B.n_vt])
 void live_tiles(hipStream_t s, const EnvState &S, const Batch &B, Lists &L, Tile *out, int *flag, int *offs);
 // continues the PCG of the environments whose tiles are listed (one workgroup
 // each) to convergence; `it` = tiled iterations done so far
 void pcg_resume(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, Lists &L, const Tile *tiles,
-                int n_tiles, int it, int cur, int mixed);
+                int n_tiles, int it, int mixed);
 void pcg_finish(hipStream_t s, const WorldDev &W, const EnvState &S, const Batch &B, int mixed);
 // one workgroup per environment for the environments flagged `fused`
 void pcg_fused(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const int *fenv, int n_fenv,

@@ -8,6 +8,8 @@
 // (iii) and (iv)).  Reductions use fixed shared-memory trees over tiles and a
 // fixed order over an environment's tiles, so no floating-point atomics are
 // used anywhere.
+#include <type_traits>
+
 #include "device_math.h"
 #include "ipc_kernels.h"
 
@@ -967,24 +969,11 @@ __global__ void k_assemble_sell(WorldDev W, const EnvDev *envs, EnvState S, cons
 // ---------------------------------------------------------------------------
 // block-Jacobi PCG, one independent solve per environment
 // ---------------------------------------------------------------------------
-// new search direction z + beta pp, rounded once (fma) so that every kernel
-// that forms it gets the same bits
-template <typename T>
-DEV T dir_value(T z, T pp, double beta) {
-  return (T)fma(beta, (double)pp, (double)z);
-}
-
 // the vector a product reads: stored, or the next direction formed on the fly
 template <typename T>
 struct StoredVec {
   const T *v;
   DEV double operator[](int k) const { return (double)v[k]; }
-};
-template <typename T>
-struct DirVec {
-  const T *z, *pp;
-  double beta;
-  DEV double operator[](int k) const { return (double)dir_value<T>(z[k], pp[k], beta); }
 };
 
 // One row of the matrix-vector product by kLPR = 4 lanes: lane l takes the
@@ -1085,92 +1074,107 @@ DEV bool pcg_env_live(const EnvState &S, int env) { return S.status[env] == ST_A
 DEV int tile_slot(const EnvDev *envs, const Tile &t) { return envs[t.env].vtile_first + t.rel; }
 
 // ---------------------------------------------------------------------------
-// Block-Jacobi PCG.  The per-row pieces below are shared by the tiled kernels
-// (one 256-row tile per workgroup, three launches per iteration) and the
-// per-environment kernels (one 1024-thread workgroup iterating a whole
-// environment), and both reduce dot products per 256-row tile with the same
-// tree and then over the environment's tiles in order: the two paths produce
-// the same bits, so where the tiled solve hands over to the per-environment
-// kernel does not change any result.
+// Block-Jacobi PCG in the Chronopoulos-Gear form: alongside the direction p
+// it updates s = H p, so that both dot products of an iteration (gamma = r.u
+// and delta = w.u, with u = M r and w = H u) come from one product launch and
+// one update launch.  Per iteration i:
+//   beta = gamma_i / gamma_{i-1},  alpha = gamma_i / (delta_i - beta gamma_i / alpha_{i-1})
+//   (beta = 0, alpha = gamma/delta at i = 0)
+//   p = u + beta p,  s = w + beta s,  x += alpha p,  r -= alpha s,  u = M r
+// Vectors: x in p (the solution), r, u in z, p in pp, s in q, w in w.
+// The per-row pieces are shared by the tiled kernels (one 256-row tile per
+// workgroup, two launches per iteration) and the per-environment kernels
+// (one 1024-thread workgroup iterating a whole environment); both reduce dot
+// products per 256-row tile with the same tree and then over the
+// environment's tiles in order, and take the same scalar steps, so the two
+// paths produce the same bits and where the tiled solve hands over to the
+// per-environment kernel changes no result.
 // ---------------------------------------------------------------------------
 template <typename T>
-DEV void row_init(const WorldDev &W, bool fr, int i, T *p, T *r, T *z, T *pp, const T *Minv, double &rz,
+DEV void row_init(const WorldDev &W, bool fr, int i, T *x, T *r, T *u, T *pp, T *q, const T *Minv, double &g,
                   double &rr) {
-  T rv[3], zv[3];
+  T rv[3], uv[3];
   for (int c = 0; c < 3; ++c) rv[c] = fr ? (T)(-W.g[3 * i + c]) : (T)0;
   const T *M = Minv + 9 * (size_t)i;
-  for (int c = 0; c < 3; ++c) zv[c] = fr ? M[3 * c] * rv[0] + M[3 * c + 1] * rv[1] + M[3 * c + 2] * rv[2] : (T)0;
+  for (int c = 0; c < 3; ++c) uv[c] = fr ? M[3 * c] * rv[0] + M[3 * c + 1] * rv[1] + M[3 * c + 2] * rv[2] : (T)0;
   for (int c = 0; c < 3; ++c) {
     r[3 * i + c] = rv[c];
-    z[3 * i + c] = zv[c];
-    pp[3 * i + c] = zv[c];
-    p[3 * i + c] = (T)0;
-    rz += (double)rv[c] * (double)zv[c];
+    u[3 * i + c] = uv[c];
+    pp[3 * i + c] = (T)0;
+    q[3 * i + c] = (T)0;
+    x[3 * i + c] = (T)0;
+    g += (double)rv[c] * (double)uv[c];
     rr += (double)rv[c] * (double)rv[c];
   }
 }
 
-// q_i = (H v)_i by the row's 4 lanes; returns v_i . q_i (same in all four
-// lanes, 0 for an invalid row).  With pp_out, v_i is also stored there.
-template <typename T, bool WIDE, typename V>
+// w_i = (H u)_i by the row's 4 lanes; returns u_i . w_i (same in all four
+// lanes, 0 for an invalid row)
+template <typename T, bool WIDE>
 DEV double row_spmv(const WorldDev &W, int i, bool valid, int l, const int *inc_off, const int *cr_cnt,
-                    const int *cr_col, const T *cr_val, const V &v, T *q, const T *val, T *pp_out) {
+                    const int *cr_col, const T *cr_val, const T *u, T *w, const T *val) {
   double y[3];
-  row_product<T, V, WIDE>(W, i, valid, l, v, val, inc_off, cr_cnt, cr_col, cr_val, y);
+  const StoredVec<T> v{u};
+  row_product<T, StoredVec<T>, WIDE>(W, i, valid, l, v, val, inc_off, cr_cnt, cr_col, cr_val, y);
   if (!valid) return 0.0;
-  double pq = 0.0;
+  double d = 0.0;
   for (int c = 0; c < 3; ++c) {
-    double vi = v[3 * i + c];
-    if (l == c) {
-      if (pp_out) pp_out[3 * i + c] = (T)vi;
-      q[3 * i + c] = (T)y[c];
-    }
-    pq += vi * (double)(T)y[c];
+    if (l == c) w[3 * i + c] = (T)y[c];
+    d += v[3 * i + c] * (double)(T)y[c];
   }
-  return pq;
+  return d;
 }
 
+// the update of one row; adds r.u and r.r of the new residual
 template <typename T>
-DEV void row_update(int i, double alpha, T *p, T *r, T *z, const T *pp, const T *q, const T *Minv, double &rz,
-                    double &rr) {
-  T rv[3], zv[3];
+DEV void row_update(int i, double alpha, double beta, T *x, T *r, T *u, T *pp, T *q, const T *w, const T *Minv,
+                    double &g, double &rr) {
+  T rv[3], uv[3];
   for (int c = 0; c < 3; ++c) {
-    p[3 * i + c] = (T)((double)p[3 * i + c] + alpha * (double)pp[3 * i + c]);
-    rv[c] = (T)((double)r[3 * i + c] - alpha * (double)q[3 * i + c]);
+    const T pn = (T)fma(beta, (double)pp[3 * i + c], (double)u[3 * i + c]);
+    const T sn = (T)fma(beta, (double)q[3 * i + c], (double)w[3 * i + c]);
+    pp[3 * i + c] = pn;
+    q[3 * i + c] = sn;
+    x[3 * i + c] = (T)((double)x[3 * i + c] + alpha * (double)pn);
+    rv[c] = (T)((double)r[3 * i + c] - alpha * (double)sn);
     r[3 * i + c] = rv[c];
   }
   const T *M = Minv + 9 * (size_t)i;
-  for (int c = 0; c < 3; ++c) zv[c] = M[3 * c] * rv[0] + M[3 * c + 1] * rv[1] + M[3 * c + 2] * rv[2];
+  for (int c = 0; c < 3; ++c) uv[c] = M[3 * c] * rv[0] + M[3 * c + 1] * rv[1] + M[3 * c + 2] * rv[2];
   for (int c = 0; c < 3; ++c) {
-    z[3 * i + c] = zv[c];
-    rz += (double)rv[c] * (double)zv[c];
+    u[3 * i + c] = uv[c];
+    g += (double)rv[c] * (double)uv[c];
     rr += (double)rv[c] * (double)rv[c];
   }
 }
 
-template <typename T>
-DEV void row_dir(int i, double beta, T *pp, const T *z) {
-  for (int c = 0; c < 3; ++c) pp[3 * i + c] = dir_value<T>(z[3 * i + c], pp[3 * i + c], beta);
+// Scalars of iteration `it` from the environment's sums (gamma, delta, r.r)
+// and the previous iteration's alpha and gamma; returns 1 if the solve stops:
+// relative residual reached, non-finite values, the cap of 30 n_v + 10
+// iterations, or a non-positive curvature.
+DEV int cg_step(const EnvDev &E, double bb, int it, double gam, double del, double rr, double a_prev, double g_prev,
+                double &alpha, double &beta) {
+  if (rr <= E.pcg_tol * E.pcg_tol * bb || !(rr == rr) || it >= 30 * E.nv + 10 || !(gam > 0.0)) return 1;
+  beta = it == 0 ? 0.0 : gam / g_prev;
+  const double den = it == 0 ? del : del - beta * gam / a_prev;
+  if (!(den > 0.0)) return 1;
+  alpha = gam / den;
+  return 0;
 }
 
-// stopping rule of one environment after `it` iterations
-DEV bool pcg_stop(const EnvDev &E, double rr, double bb, double rz_old, int it) {
-  return (rr <= E.pcg_tol * E.pcg_tol * bb) || !(rr == rr) || it >= 30 * E.nv + 10 || !(rz_old > 0.0);
-}
-
 template <typename T>
-__global__ void k_pcg_init(WorldDev W, const EnvDev *envs, EnvState S, const Tile *tiles, T *p, T *r, T *z, T *pp,
-                           const T *Minv, double *part_rz, double *part_rr) {
+__global__ void k_pcg_init(WorldDev W, const EnvDev *envs, EnvState S, const Tile *tiles, T *x, T *r, T *u, T *pp,
+                           T *q, const T *Minv, double *part_g, double *part_rr) {
   __shared__ double sh[TB];
   Tile t = tiles[blockIdx.x];
   if (!active_env(S, t.env) || envs[t.env].fused) return;
   int i = t.start + threadIdx.x;
-  double rz = 0.0, rr = 0.0;
-  if ((int)threadIdx.x < t.count) row_init<T>(W, is_dof(W, S, i, t.env), i, p, r, z, pp, Minv, rz, rr);
-  rz = block_sum(rz, sh);
+  double g = 0.0, rr = 0.0;
+  if ((int)threadIdx.x < t.count) row_init<T>(W, is_dof(W, S, i, t.env), i, x, r, u, pp, q, Minv, g, rr);
+  g = block_sum(g, sh);
   rr = block_sum(rr, sh);
   if (threadIdx.x == 0) {
-    part_rz[tile_slot(envs, t)] = rz;
+    part_g[tile_slot(envs, t)] = g;
     part_rr[tile_slot(envs, t)] = rr;
   }
 }
@@ -1196,125 +1200,89 @@ __global__ void k_pcg_env_init(const EnvDev *envs, EnvState S, const int *benv, 
   atomicAdd(pending, 1);
 }
 
-// Stopping test of a live environment after an update (thread 0 of a tile):
-// returns 1 if it stops, else sets beta.  Only the environment's first tile
-// writes the bookkeeping; the iteration counter is advanced by the update
-// kernel, so every tile of this launch reads the same count.
-DEV int pcg_check(const EnvDev &E, EnvState &S, const Tile &t, const double *part_rz_old, const double *part_rz_new,
-                  const double *part_rr_new, int *pending, double &beta) {
-  double rzn = env_tiles_sum(part_rz_new, E), rzo = env_tiles_sum(part_rz_old, E);
-  double rr = env_tiles_sum(part_rr_new, E);
-  int it = S.pcg_it[t.env];
-  int done = pcg_stop(E, rr, S.pcg_bb[t.env], rzo, it);
-  beta = done ? 0.0 : rzn / rzo;
-  if (done && t.rel == 0) {
-    S.pcg_done[t.env] = 1;
-    S.pcg_total[t.env] += it;
-    atomicSub(pending, 1);
-  }
-  return done;
-}
-
-// q = H v for live environments, partial v.q per tile.  DIR = false: v = pp
-// (stored direction).  DIR = true: first the stopping test of the last
-// update, then v = z + beta pp formed on the fly and stored in pp_out.
-template <typename T, bool DIR, bool WIDE>
+// w = H u for live environments, partial u.w (delta) per tile
+template <typename T, bool WIDE>
 __global__ void __launch_bounds__(1024) k_spmv(WorldDev W, const EnvDev *envs, EnvState S, const Tile *tiles,
                                                const int *inc_off, const int *cr_cnt, const int *cr_col,
-                                               const T *cr_val, const T *pp, const T *z, T *pp_out, T *q,
-                                               const T *val, double *part_pq, const double *part_rz_old,
-                                               const double *part_rz_new, const double *part_rr_new, int *pending,
+                                               const T *cr_val, const T *u, T *w, const T *val, double *part_d,
                                                unsigned long long *prof) {
   __shared__ double sh[TB];
-  __shared__ double s_beta;
-  __shared__ int s_done;
   Tile t = tiles[blockIdx.x];
   if (!pcg_env_live(S, t.env)) return;
-  if (DIR) {
-    if (threadIdx.x == 0) {
-      double beta;
-      s_done = pcg_check(envs[t.env], S, t, part_rz_old, part_rz_new, part_rr_new, pending, beta);
-      s_beta = beta;
-    }
-    __syncthreads();
-    if (s_done) return;
-  }
   const int row = threadIdx.x / kLPR, l = threadIdx.x % kLPR;
   const int i = t.start + row;
   const bool valid = row < t.count;
-  double pq;
-  if (DIR)
-    pq = row_spmv<T, WIDE>(W, i, valid, l, inc_off, cr_cnt, cr_col, cr_val, DirVec<T>{z, pp, s_beta}, q, val, pp_out);
-  else
-    pq = row_spmv<T, WIDE>(W, i, valid, l, inc_off, cr_cnt, cr_col, cr_val, StoredVec<T>{pp}, q, val, (T *)nullptr);
-  pq = rows_tree(pq, l == 0, row, sh);
-  if (threadIdx.x == 0) part_pq[tile_slot(envs, t)] = pq;
+  double d = row_spmv<T, WIDE>(W, i, valid, l, inc_off, cr_cnt, cr_col, cr_val, u, w, val);
+  d = rows_tree(d, l == 0, row, sh);
+  if (threadIdx.x == 0) part_d[tile_slot(envs, t)] = d;
   if (prof) {
     // algorithmic bytes of this tile: stored blocks + column indices (sliced
-    // ELL and merged contact blocks), the vector rows read and written (v and
-    // q; with DIR also z, pp and pp_out)
+    // ELL and merged contact blocks), one read of u and one write of w per row
     double b = 0.0;
-    if (valid) {
-      int nnz = W.row_nnz[i] + cr_cnt[i];
-      b = (double)nnz * (9.0 * sizeof(T) + 4.0) + (DIR ? 12.0 : 6.0) * sizeof(T);
-    }
+    if (valid) b = (double)(W.row_nnz[i] + cr_cnt[i]) * (9.0 * sizeof(T) + 4.0) + 6.0 * sizeof(T);
     b = rows_tree(b, l == 0, row, sh);
     if (threadIdx.x == 0) atomicAdd(prof, (unsigned long long)b);
   }
 }
 
+// Stopping test, scalars and the update of iteration `it` (the host's count:
+// every live environment started its solve with the others).  The first tile
+// of an environment keeps alpha and gamma for the next iteration (slot it&1;
+// this launch reads slot (it-1)&1 only) and, when the solve stops, the
+// bookkeeping.
 template <typename T>
-__global__ void k_pcg_update(WorldDev W, const EnvDev *envs, EnvState S, const Tile *tiles, const double *part_pq,
-                             const double *part_rz_old, double *part_rz_new, double *part_rr_new, T *p, T *r, T *z,
-                             const T *pp, const T *q, const T *Minv) {
+__global__ void k_pcg_update(WorldDev W, const EnvDev *envs, EnvState S, const Tile *tiles, int it,
+                             const double *part_d, const double *part_g, const double *part_rr, double *part_g_new,
+                             double *part_rr_new, T *x, T *r, T *u, T *pp, T *q, const T *w, const T *Minv,
+                             int *pending) {
   __shared__ double sh[TB];
-  __shared__ double s_alpha;
+  __shared__ double s_ab[2];
+  __shared__ int s_done;
   Tile t = tiles[blockIdx.x];
   if (!pcg_env_live(S, t.env)) return;
   const EnvDev &E = envs[t.env];
   if (threadIdx.x == 0) {
-    double pq = env_tiles_sum(part_pq, E), rz = env_tiles_sum(part_rz_old, E);
-    s_alpha = (pq > 0.0) ? rz / pq : 0.0;
-  }
-  __syncthreads();
-  double alpha = s_alpha;
-  int i = t.start + threadIdx.x;
-  double rz = 0.0, rr = 0.0;
-  if ((int)threadIdx.x < t.count) row_update<T>(i, alpha, p, r, z, pp, q, Minv, rz, rr);
-  rz = block_sum(rz, sh);
-  rr = block_sum(rr, sh);
-  if (threadIdx.x == 0) {
-    part_rz_new[tile_slot(envs, t)] = rz;
-    part_rr_new[tile_slot(envs, t)] = rr;
-    if (t.rel == 0) S.pcg_it[t.env] += 1;
-  }
-}
-
-// stopping test and pp = z + beta pp in place (last iteration of a block)
-template <typename T>
-__global__ void k_pcg_dir(WorldDev W, const EnvDev *envs, EnvState S, const Tile *tiles, const double *part_rz_old,
-                          const double *part_rz_new, const double *part_rr_new, T *pp, const T *z, int *pending) {
-  __shared__ double s_beta;
-  __shared__ int s_done;
-  Tile t = tiles[blockIdx.x];
-  if (!pcg_env_live(S, t.env)) return;
-  if (threadIdx.x == 0) {
-    double beta;
-    s_done = pcg_check(envs[t.env], S, t, part_rz_old, part_rz_new, part_rr_new, pending, beta);
-    s_beta = beta;
+    const int e = t.env, k = (it + 1) & 1;  // slot of iteration it - 1
+    double alpha = 0.0, beta = 0.0;
+    const double gam = env_tiles_sum(part_g, E), del = env_tiles_sum(part_d, E), rr = env_tiles_sum(part_rr, E);
+    s_done = cg_step(E, S.pcg_bb[e], it, gam, del, rr, k ? S.cg_a1[e] : S.cg_a0[e], k ? S.cg_g1[e] : S.cg_g0[e],
+                     alpha, beta);
+    s_ab[0] = alpha;
+    s_ab[1] = beta;
+    if (t.rel == 0) {
+      if (s_done) {
+        S.pcg_done[e] = 1;
+        S.pcg_it[e] = it;
+        S.pcg_total[e] += it;
+        atomicSub(pending, 1);
+      } else if (it & 1) {
+        S.cg_a1[e] = alpha;
+        S.cg_g1[e] = gam;
+      } else {
+        S.cg_a0[e] = alpha;
+        S.cg_g0[e] = gam;
+      }
+    }
   }
   __syncthreads();
   if (s_done) return;
   int i = t.start + threadIdx.x;
-  if ((int)threadIdx.x < t.count) row_dir<T>(i, s_beta, pp, z);
+  double g = 0.0, rr = 0.0;
+  if ((int)threadIdx.x < t.count) row_update<T>(i, s_ab[0], s_ab[1], x, r, u, pp, q, w, Minv, g, rr);
+  g = block_sum(g, sh);
+  rr = block_sum(rr, sh);
+  if (threadIdx.x == 0) {
+    part_g_new[tile_slot(envs, t)] = g;
+    part_rr_new[tile_slot(envs, t)] = rr;
+  }
 }
 
 // ---------------------------------------------------------------------------
 // Per-environment PCG: one 1024-thread workgroup iterates a whole
-// environment inside one launch.  Thread t handles rows t, t+1024, ...; each
-// 256-thread quarter therefore covers one vertex tile per pass and reduces it
-// with the tiled kernels' tree; tile partials go to the same per-tile arrays
-// and are summed in tile order.
+// environment inside one launch.  The product runs one 256-row tile per pass
+// (4 lanes per row, as k_spmv); the update runs four tiles per pass, each
+// 256-thread quarter reducing its tile with the tiled kernels' tree.  Tile
+// partials go to the same per-tile arrays and are summed in tile order.
 // ---------------------------------------------------------------------------
 constexpr int FB = 1024;
 
@@ -1322,7 +1290,7 @@ constexpr int FB = 1024;
 // thread 0 of each quarter stores them for tile `tile0 + quarter` if that
 // tile exists
 DEV void tile_sums2(double a, double b, double (*sh)[FB], const EnvDev &E, int tile0, double *pa, double *pb) {
-  const int q = threadIdx.x / TB, l = threadIdx.x % TB;
+  const int qd = threadIdx.x / TB, l = threadIdx.x % TB;
   sh[0][threadIdx.x] = a;
   sh[1][threadIdx.x] = b;
   __syncthreads();
@@ -1333,123 +1301,102 @@ DEV void tile_sums2(double a, double b, double (*sh)[FB], const EnvDev &E, int t
     }
     __syncthreads();
   }
-  if (l == 0 && tile0 + q < E.vtile_count) {
-    if (pa) pa[E.vtile_first + tile0 + q] = sh[0][q * TB];
-    if (pb) pb[E.vtile_first + tile0 + q] = sh[1][q * TB];
+  if (l == 0 && tile0 + qd < E.vtile_count) {
+    if (pa) pa[E.vtile_first + tile0 + qd] = sh[0][qd * TB];
+    if (pb) pb[E.vtile_first + tile0 + qd] = sh[1][qd * TB];
   }
   __syncthreads();
 }
 
-// PCG iterations of one environment from the state (p, r, z, pp, rz) until
-// pcg_stop; returns the iteration count
+// Iterations of one environment from iteration `it` (u, r, x, p, s current;
+// gamma and r.r partials in part_g[it&1], part_rr[it&1]; alpha, gamma of
+// iteration it-1 in a_prev, g_prev) until the stopping rule; returns the
+// iteration count
 template <typename T>
-DEV int env_iterate(const WorldDev &W, const EnvDev &E, const int *inc_off, const int *cr_cnt, const int *cr_col,
-                    const T *cr_val, T *p, T *r, T *z, T *pp, T *q, const T *val, const T *Minv, double rz,
-                    double bb, int it, double *part_pq, double *part_rz, double *part_rr, double &bytes, bool prof,
-                    double (*sh)[FB]) {
+DEV int env_iterate(const WorldDev &W, const EnvDev &E, double bb, int it, double a_prev, double g_prev,
+                    const int *inc_off, const int *cr_cnt, const int *cr_col, const T *cr_val, T *x, T *r, T *u, T *pp,
+                    T *q, T *w, const T *val, const T *Minv, double *part_d, double *const part_g[2],
+                    double *const part_rr[2], double (*sh)[FB]) {
   const int r0 = E.v_off, r1 = E.v_off + E.nv_pad;
   for (;;) {
-    // the product: one 256-row tile per pass, 4 lanes per row (as k_spmv)
     for (int base = r0; base < r1; base += TB) {
       const int row = threadIdx.x / kLPR, l = threadIdx.x % kLPR;
       const int i = base + row;
       const bool valid = i < r1;
-      double pq =
-          row_spmv<T, true>(W, i, valid, l, inc_off, cr_cnt, cr_col, cr_val, StoredVec<T>{pp}, q, val, (T *)nullptr);
-      if (prof && valid && l == 0)
-        bytes += (double)(W.row_nnz[i] + cr_cnt[i]) * (9.0 * sizeof(T) + 4.0) + 6.0 * sizeof(T);
-      pq = rows_tree(pq, l == 0, row, sh[0]);
-      if (threadIdx.x == 0) part_pq[E.vtile_first + (base - r0) / TB] = pq;
+      double d = row_spmv<T, true>(W, i, valid, l, inc_off, cr_cnt, cr_col, cr_val, u, w, val);
+      d = rows_tree(d, l == 0, row, sh[0]);
+      if (threadIdx.x == 0) part_d[E.vtile_first + (base - r0) / TB] = d;
     }
     __syncthreads();
-    double pq = env_tiles_sum(part_pq, E);
-    double alpha = (pq > 0.0) ? rz / pq : 0.0;
+    const double gam = env_tiles_sum(part_g[it & 1], E), del = env_tiles_sum(part_d, E);
+    const double rr = env_tiles_sum(part_rr[it & 1], E);
+    double alpha = 0.0, beta = 0.0;
+    if (cg_step(E, bb, it, gam, del, rr, a_prev, g_prev, alpha, beta)) break;
     for (int base = r0; base < r1; base += FB) {
       int i = base + threadIdx.x;
-      double rzi = 0.0, rri = 0.0;
-      if (i < r1) row_update<T>(i, alpha, p, r, z, pp, q, Minv, rzi, rri);
-      tile_sums2(rzi, rri, sh, E, (base - r0) / TB, part_rz, part_rr);
+      double g = 0.0, rri = 0.0;
+      if (i < r1) row_update<T>(i, alpha, beta, x, r, u, pp, q, w, Minv, g, rri);
+      tile_sums2(g, rri, sh, E, (base - r0) / TB, part_g[(it + 1) & 1], part_rr[(it + 1) & 1]);
     }
-    double rzn = env_tiles_sum(part_rz, E), rrn = env_tiles_sum(part_rr, E);
+    a_prev = alpha;
+    g_prev = gam;
     ++it;
-    if (pcg_stop(E, rrn, bb, rz, it)) break;
-    double beta = rzn / rz;
-    rz = rzn;
-    for (int i = r0 + threadIdx.x; i < r1; i += FB) row_dir<T>(i, beta, pp, z);
-    __syncthreads();
   }
   return it;
-}
-
-DEV double block_total(double v, double (*sh)[FB]) {
-  sh[0][threadIdx.x] = v;
-  __syncthreads();
-  for (int s = FB / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) sh[0][threadIdx.x] += sh[0][threadIdx.x + s];
-    __syncthreads();
-  }
-  double t = sh[0][0];
-  __syncthreads();
-  return t;
 }
 
 template <typename T>
 __global__ void __launch_bounds__(1024) k_pcg_fused(WorldDev W, const EnvDev *envs, EnvState S, const int *fenv,
                                                     const int *inc_off, const int *cr_cnt, const int *cr_col,
-                                                    const T *cr_val, T *p, T *r, T *z, T *pp, T *q, const T *val,
-                                                    const T *Minv, double *part_pq, double *part_rz, double *part_rr,
-                                                    unsigned long long *prof) {
+                                                    const T *cr_val, T *x, T *r, T *u, T *pp, T *q, T *w,
+                                                    const T *val, const T *Minv, double *part_d, double *part_g0,
+                                                    double *part_g1, double *part_rr0, double *part_rr1) {
   __shared__ double sh[2][FB];
   int e = fenv[blockIdx.x];
   if (S.status[e] != ST_ACTIVE) return;
   const EnvDev &E = envs[e];
   const int r0 = E.v_off, r1 = E.v_off + E.nv_pad;
+  double *const pg[2] = {part_g0, part_g1}, *const prr[2] = {part_rr0, part_rr1};
   for (int base = r0; base < r1; base += FB) {
     int i = base + threadIdx.x;
-    double rzi = 0.0, rri = 0.0;
-    if (i < r1) row_init<T>(W, is_dof(W, S, i, e), i, p, r, z, pp, Minv, rzi, rri);
-    tile_sums2(rzi, rri, sh, E, (base - r0) / TB, part_rz, part_rr);
+    double g = 0.0, rr = 0.0;
+    if (i < r1) row_init<T>(W, is_dof(W, S, i, e), i, x, r, u, pp, q, Minv, g, rr);
+    tile_sums2(g, rr, sh, E, (base - r0) / TB, part_g0, part_rr0);
   }
-  double rz = env_tiles_sum(part_rz, E), bb = env_tiles_sum(part_rr, E);
+  const double bb = env_tiles_sum(part_rr0, E);
   int it = 0;
-  double bytes = 0.0;
   if (!(bb == 0.0 || !(bb == bb)))
-    it = env_iterate<T>(W, E, inc_off, cr_cnt, cr_col, cr_val, p, r, z, pp, q, val, Minv, rz, bb, 0, part_pq, part_rz,
-                        part_rr, bytes, prof != nullptr, sh);
-  if (prof) bytes = block_total(bytes, sh);
+    it = env_iterate<T>(W, E, bb, 0, 0.0, 0.0, inc_off, cr_cnt, cr_col, cr_val, x, r, u, pp, q, w, val, Minv, part_d,
+                        pg, prr, sh);
   if (threadIdx.x == 0) {
     S.pcg_it[e] = it;
     S.pcg_total[e] += it;
     S.pcg_done[e] = 1;
-    if (prof) atomicAdd(prof, (unsigned long long)bytes);
   }
 }
 
 // Tail of the tiled PCG: once few tiles are still iterating, the first tile
 // of each live environment continues its solve in one workgroup from the
-// state the tiled kernels left (direction already updated, rz in part_rz_cur).
+// state the tiled kernels left after `it` iterations.
 template <typename T>
 __global__ void __launch_bounds__(1024) k_pcg_resume(WorldDev W, const EnvDev *envs, EnvState S, const Tile *tiles,
-                                                     const double *part_rz_cur, const int *inc_off,
-                                                     const int *cr_cnt, const int *cr_col, const T *cr_val, T *p,
-                                                     T *r, T *z, T *pp, T *q, const T *val, const T *Minv,
-                                                     double *part_pq, double *part_rz, double *part_rr,
-                                                     unsigned long long *prof) {
+                                                     int it, const int *inc_off, const int *cr_cnt, const int *cr_col,
+                                                     const T *cr_val, T *x, T *r, T *u, T *pp, T *q, T *w,
+                                                     const T *val, const T *Minv, double *part_d, double *part_g0,
+                                                     double *part_g1, double *part_rr0, double *part_rr1) {
   __shared__ double sh[2][FB];
   Tile t = tiles[blockIdx.x];
   if (t.rel != 0 || !pcg_env_live(S, t.env)) return;
   const int e = t.env;
   const EnvDev &E = envs[e];
-  double rz = env_tiles_sum(part_rz_cur, E);
-  double bytes = 0.0;
-  int it = env_iterate<T>(W, E, inc_off, cr_cnt, cr_col, cr_val, p, r, z, pp, q, val, Minv, rz, S.pcg_bb[e],
-                          S.pcg_it[e], part_pq, part_rz, part_rr, bytes, prof != nullptr, sh);
-  if (prof) bytes = block_total(bytes, sh);
+  double *const pg[2] = {part_g0, part_g1}, *const prr[2] = {part_rr0, part_rr1};
+  const int k = (it + 1) & 1;  // slot of iteration it - 1
+  const int n = env_iterate<T>(W, E, S.pcg_bb[e], it, k ? S.cg_a1[e] : S.cg_a0[e], k ? S.cg_g1[e] : S.cg_g0[e],
+                               inc_off, cr_cnt, cr_col, cr_val, x, r, u, pp, q, w, val, Minv, part_d, pg, prr, sh);
   if (threadIdx.x == 0) {
-    S.pcg_it[e] = it;
-    S.pcg_total[e] += it;
+    S.pcg_it[e] = n;
+    S.pcg_total[e] += n;
     S.pcg_done[e] = 1;
-    if (prof) atomicAdd(prof, (unsigned long long)bytes);
   }
 }
 
@@ -2016,10 +1963,10 @@ void pcg_init(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState 
               int *pending, int mixed) {
   IPC_LAUNCH(k_fill_int, 1, 64, s)(pending, 1, 0);
   if (B.n_vt && !mixed)
-    IPC_LAUNCH(k_pcg_init<double>, B.n_vt, TB, s)(W, E, S, B.vtiles, W.p, W.r, W.z, W.pp, W.Minv, L.part_b0,
+    IPC_LAUNCH(k_pcg_init<double>, B.n_vt, TB, s)(W, E, S, B.vtiles, W.p, W.r, W.z, W.pp, W.q, W.Minv, L.part_b0,
                                                   L.part_c0);
   if (B.n_vt && mixed)
-    IPC_LAUNCH(k_pcg_init<float>, B.n_vt, TB, s)(W, E, S, B.vtiles, W.p32, W.r32, W.z32, W.pp32, W.Minv32,
+    IPC_LAUNCH(k_pcg_init<float>, B.n_vt, TB, s)(W, E, S, B.vtiles, W.p32, W.r32, W.z32, W.pp32, W.q32, W.Minv32,
                                                  L.part_b0, L.part_c0);
   IPC_LAUNCH(k_pcg_env_init, nblk(B.n_envs, 64), 64, s)(E, S, B.envs, B.n_envs, L.part_c0, pending);
 }
@@ -2042,96 +1989,81 @@ const float *cr_vals<float>(const Lists &L) {
   return L.cr_val32;
 }
 
+// the vectors of one precision: solution, residual, preconditioned residual,
+// direction, H times direction, H times preconditioned residual
 template <typename T>
-void launch_spmv(hipStream_t s, bool dir, bool wide, const WorldDev &W, const EnvDev *E, const EnvState &S,
-                 const Tile *tiles, int n_tiles, Lists &L, const T *ppi, const T *z, T *ppo, T *q, const T *val,
-                 const double *rz_prev, const double *rz_cur, const double *rr_cur, int *pending,
-                 unsigned long long *prof) {
-  const int nt = kLPR * TB;
-  if (dir && wide)
-    IPC_LAUNCH((k_spmv<T, true, true>), n_tiles, nt, s)(W, E, S, tiles, L.inc_off, L.cr_cnt, L.cr_col, cr_vals<T>(L), ppi, z,
-                                                        ppo, q, val, L.part_a, rz_prev, rz_cur, rr_cur, pending, prof);
-  else if (dir)
-    IPC_LAUNCH((k_spmv<T, true, false>), n_tiles, nt, s)(W, E, S, tiles, L.inc_off, L.cr_cnt, L.cr_col, cr_vals<T>(L), ppi, z,
-                                                         ppo, q, val, L.part_a, rz_prev, rz_cur, rr_cur, pending, prof);
-  else if (wide)
-    IPC_LAUNCH((k_spmv<T, false, true>), n_tiles, nt, s)(W, E, S, tiles, L.inc_off, L.cr_cnt, L.cr_col, cr_vals<T>(L), ppi, z,
-                                                         (T *)nullptr, q, val, L.part_a, nullptr, nullptr, nullptr,
-                                                         pending, prof);
-  else
-    IPC_LAUNCH((k_spmv<T, false, false>), n_tiles, nt, s)(W, E, S, tiles, L.inc_off, L.cr_cnt, L.cr_col, cr_vals<T>(L), ppi, z,
-                                                          (T *)nullptr, q, val, L.part_a, nullptr, nullptr, nullptr,
-                                                          pending, prof);
+struct PcgVecs {
+  T *x, *r, *u, *pp, *q, *w;
+  const T *val, *Minv, *cr_val;
+};
+PcgVecs<double> vecs64(const WorldDev &W, const Lists &L) {
+  return {W.p, W.r, W.z, W.pp, W.q, W.w, W.val, W.Minv, L.cr_val};
+}
+PcgVecs<float> vecs32(const WorldDev &W, const Lists &L) {
+  return {W.p32, W.r32, W.z32, W.pp32, W.q32, W.w32, W.val32, W.Minv32, L.cr_val32};
 }
 
-void pcg_iter(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, Lists &L, int it, int *pending,
-              int mixed, bool dir, int cur, bool last, hipEvent_t ev0, hipEvent_t ev1, const Tile *tiles,
-              int n_tiles) {
-  if (!n_tiles) return;
+template <typename T>
+void pcg_iter_t(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, Lists &L, int it, int *pending,
+                hipEvent_t ev0, hipEvent_t ev1, const Tile *tiles, int n_tiles, const PcgVecs<T> &v) {
   // bytes are counted only for the launches that are timed: counter 0 for
   // launches of at most kWideTiles tiles, counter 1 for larger ones
   unsigned long long *prof = ev0 ? L.prof + (n_tiles > kWideTiles ? 1 : 0) : nullptr;
-  // per-tile partials, two slots each used alternately: rz_cur / rr_cur from
-  // the last update (rz_cur gives alpha), rz_prev from the one before it;
-  // this iteration's update writes rz_new (over rz_prev) and rr_new
-  double *rz_prev = (it & 1) ? L.part_b0 : L.part_b1;
-  double *rz_cur = (it & 1) ? L.part_b1 : L.part_b0;
-  double *rr_cur = (it & 1) ? L.part_c1 : L.part_c0;
-  double *rz_new = rz_prev, *rr_new = (it & 1) ? L.part_c0 : L.part_c1;
-  const int nxt = dir ? 1 - cur : cur;
+  // per-tile partials of gamma and r.r: slot it & 1 holds this iteration's,
+  // the update writes the next iteration's into the other slot
+  double *g_cur = (it & 1) ? L.part_b1 : L.part_b0, *g_new = (it & 1) ? L.part_b0 : L.part_b1;
+  double *rr_cur = (it & 1) ? L.part_c1 : L.part_c0, *rr_new = (it & 1) ? L.part_c0 : L.part_c1;
+  const int nt = kLPR * TB;
+  if (ev0) hipEventRecord(ev0, s);
   // launches of a few tiles are latency-bound: issue each lane's slots four at a time
-  const bool wide = n_tiles <= kWideTiles;
-  if (!mixed) {
-    double *ppi = cur ? W.pp2 : W.pp, *ppo = nxt ? W.pp2 : W.pp;
-    if (ev0) hipEventRecord(ev0, s);
-    launch_spmv<double>(s, dir, wide, W, E, S, tiles, n_tiles, L, ppi, W.z, ppo, W.q, W.val, rz_prev, rz_cur, rr_cur,
-                        pending, prof);
-    if (ev1) hipEventRecord(ev1, s);
-    IPC_LAUNCH(k_pcg_update<double>, n_tiles, TB, s)(W, E, S, tiles, L.part_a, rz_cur, rz_new, rr_new, W.p, W.r, W.z,
-                                                     ppo, W.q, W.Minv);
-    if (last)
-      IPC_LAUNCH(k_pcg_dir<double>, n_tiles, TB, s)(W, E, S, tiles, rz_cur, rz_new, rr_new, ppo, W.z, pending);
-  } else {
-    float *ppi = cur ? W.pp2_32 : W.pp32, *ppo = nxt ? W.pp2_32 : W.pp32;
-    if (ev0) hipEventRecord(ev0, s);
-    launch_spmv<float>(s, dir, wide, W, E, S, tiles, n_tiles, L, ppi, W.z32, ppo, W.q32, W.val32, rz_prev, rz_cur,
-                       rr_cur, pending, prof);
-    if (ev1) hipEventRecord(ev1, s);
-    IPC_LAUNCH(k_pcg_update<float>, n_tiles, TB, s)(W, E, S, tiles, L.part_a, rz_cur, rz_new, rr_new, W.p32, W.r32,
-                                                    W.z32, ppo, W.q32, W.Minv32);
-    if (last)
-      IPC_LAUNCH(k_pcg_dir<float>, n_tiles, TB, s)(W, E, S, tiles, rz_cur, rz_new, rr_new, ppo, W.z32, pending);
-  }
+  if (n_tiles <= kWideTiles)
+    IPC_LAUNCH((k_spmv<T, true>), n_tiles, nt, s)(W, E, S, tiles, L.inc_off, L.cr_cnt, L.cr_col, v.cr_val, v.u, v.w,
+                                                  v.val, L.part_a, prof);
+  else
+    IPC_LAUNCH((k_spmv<T, false>), n_tiles, nt, s)(W, E, S, tiles, L.inc_off, L.cr_cnt, L.cr_col, v.cr_val, v.u, v.w,
+                                                   v.val, L.part_a, prof);
+  if (ev1) hipEventRecord(ev1, s);
+  IPC_LAUNCH(k_pcg_update<T>, n_tiles, TB, s)(W, E, S, tiles, it, L.part_a, g_cur, rr_cur, g_new, rr_new, v.x, v.r,
+                                              v.u, v.pp, v.q, v.w, v.Minv, pending);
+}
+
+void pcg_iter(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, Lists &L, int it, int *pending,
+              int mixed, hipEvent_t ev0, hipEvent_t ev1, const Tile *tiles, int n_tiles) {
+  if (!n_tiles) return;
+  if (!mixed)
+    pcg_iter_t<double>(s, W, E, S, L, it, pending, ev0, ev1, tiles, n_tiles, vecs64(W, L));
+  else
+    pcg_iter_t<float>(s, W, E, S, L, it, pending, ev0, ev1, tiles, n_tiles, vecs32(W, L));
 }
 
 void pcg_fused(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const int *fenv, int n_fenv,
                Lists &L, int mixed) {
   if (!n_fenv) return;
+  auto go = [&](auto v) {
+    using T = std::remove_pointer_t<decltype(v.x)>;
+    IPC_LAUNCH(k_pcg_fused<T>, n_fenv, FB, s)(W, E, S, fenv, L.inc_off, L.cr_cnt, L.cr_col, v.cr_val, v.x, v.r, v.u,
+                                              v.pp, v.q, v.w, v.val, v.Minv, L.part_a, L.part_b0, L.part_b1,
+                                              L.part_c0, L.part_c1);
+  };
   if (!mixed)
-    IPC_LAUNCH(k_pcg_fused<double>, n_fenv, FB, s)(W, E, S, fenv, L.inc_off, L.cr_cnt, L.cr_col, L.cr_val, W.p, W.r, W.z,
-                                                  W.pp, W.q, W.val, W.Minv, L.part_a, L.part_b0, L.part_c0, nullptr);
+    go(vecs64(W, L));
   else
-    IPC_LAUNCH(k_pcg_fused<float>, n_fenv, FB, s)(W, E, S, fenv, L.inc_off, L.cr_cnt, L.cr_col, L.cr_val32, W.p32, W.r32,
-                                                 W.z32, W.pp32, W.q32, W.val32, W.Minv32, L.part_a, L.part_b0,
-                                                 L.part_c0, nullptr);
+    go(vecs32(W, L));
 }
 
 void pcg_resume(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, Lists &L, const Tile *tiles,
-                int n_tiles, int it, int cur, int mixed) {
+                int n_tiles, int it, int mixed) {
   if (!n_tiles) return;
-  // after `it` tiled iterations the current rz partials are in part_b1 (odd)
-  // or part_b0 (even); the per-environment loop then uses the other pair
-  const double *rz = (it & 1) ? L.part_b1 : L.part_b0;
-  double *rz_tmp = (it & 1) ? L.part_b0 : L.part_b1;
-  double *rr_tmp = (it & 1) ? L.part_c0 : L.part_c1;
+  auto go = [&](auto v) {
+    using T = std::remove_pointer_t<decltype(v.x)>;
+    IPC_LAUNCH(k_pcg_resume<T>, n_tiles, FB, s)(W, E, S, tiles, it, L.inc_off, L.cr_cnt, L.cr_col, v.cr_val, v.x, v.r,
+                                                v.u, v.pp, v.q, v.w, v.val, v.Minv, L.part_a, L.part_b0, L.part_b1,
+                                                L.part_c0, L.part_c1);
+  };
   if (!mixed)
-    IPC_LAUNCH(k_pcg_resume<double>, n_tiles, FB, s)(W, E, S, tiles, rz, L.inc_off, L.cr_cnt, L.cr_col, L.cr_val, W.p,
-                                                     W.r, W.z, cur ? W.pp2 : W.pp, W.q, W.val, W.Minv, L.part_a, rz_tmp, rr_tmp,
-                                                     nullptr);
+    go(vecs64(W, L));
   else
-    IPC_LAUNCH(k_pcg_resume<float>, n_tiles, FB, s)(W, E, S, tiles, rz, L.inc_off, L.cr_cnt, L.cr_col, L.cr_val32, W.p32,
-                                                    W.r32, W.z32, cur ? W.pp2_32 : W.pp32, W.q32, W.val32, W.Minv32, L.part_a, rz_tmp,
-                                                    rr_tmp, nullptr);
+    go(vecs32(W, L));
 }
 
 void pcg_finish(hipStream_t s, const WorldDev &W, const EnvState &S, const Batch &B, int mixed) {

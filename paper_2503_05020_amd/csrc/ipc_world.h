@@ -65,13 +65,15 @@ struct EnvState {
   int *al, *al_action, *snap_bad;
   double *kA, *viol, *viol_prev;
   double *pcg_bb;                 // |g|^2 of the current solve
+  // PCG step length and r.u of the last two iterations (slot = iteration & 1)
+  double *cg_a0, *cg_a1, *cg_g0, *cg_g1;
 };
 
 // Flat device arrays of the world (element-indexed).
 struct WorldDev {
   // per vertex
-  double *X, *x, *v, *xn, *xh, *p, *g, *r, *z, *pp, *pp2, *q, *mass, *Minv, *e_v, *lam;
-  float *r32, *z32, *pp32, *pp2_32, *q32, *p32, *Minv32;
+  double *X, *x, *v, *xn, *xh, *p, *g, *r, *z, *pp, *w, *q, *mass, *Minv, *e_v, *lam;
+  float *r32, *z32, *pp32, *w32, *q32, *p32, *Minv32;
   int *kin, *venv, *vt_beg, *vt_end, *row_nnz;
   // per slice (vertex / 64)
   int *slice_pos, *slice_w;

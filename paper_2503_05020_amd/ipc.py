@@ -25,7 +25,6 @@ IPC_FP64 = 0
 IPC_MIXED = 1
 IPC_TUNE_TAIL_TILES = 1
 IPC_TUNE_FUSED_PCG = 2
-IPC_TUNE_FOLD_DIR = 3
 IPC_TUNE_NARROW = 4
 IPC_TUNE_LANES = 5
 FAIL_REASONS = {0: "none", 1: "maxit", 2: "nonfinite", 3: "line-search", 4: "dirichlet"}

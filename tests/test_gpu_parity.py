@@ -256,15 +256,13 @@ def test_augmented_lagrangian_press_parity():
 
 @pytest.mark.parametrize("precision", [G.IPC_FP64, G.IPC_MIXED])
 def test_pcg_paths_same_bits(precision):
-    """Tiled PCG (direction folded into the product, or a separate direction kernel), tiled with the
-    per-environment tail hand-off at the first poll, and the fully per-environment PCG reduce in the
-    same order: the trajectories must be bitwise identical."""
+    """Tiled PCG, tiled with the per-environment tail hand-off at the first poll, and the fully
+    per-environment PCG reduce in the same order: the trajectories must be bitwise identical."""
     scs = [S.soft_cube_drop(cells=3, edge=0.05, height=0.003 + 0.001 * i, seed=i) for i in range(3)]
     runs = []
-    for tail, fused, fold in ((0, 0, 1), (1 << 30, 0, 1), (0, 1, 1), (0, 0, 0)):
+    for tail, fused in ((0, 0), (1 << 30, 0), (0, 1)):
         G.ipc_set_tuning(G.IPC_TUNE_TAIL_TILES, tail)
         G.ipc_set_tuning(G.IPC_TUNE_FUSED_PCG, fused)
-        G.ipc_set_tuning(G.IPC_TUNE_FOLD_DIR, fold)
         gs = [G.ipc_create_scene(sc, precision=precision) for sc in scs]
         for _ in range(8):
             rc, _ = G.ipc_step_batch(gs, 1)
@@ -274,8 +272,7 @@ def test_pcg_paths_same_bits(precision):
             G.ipc_destroy_scene(g)
     G.ipc_set_tuning(G.IPC_TUNE_TAIL_TILES, 0)
     G.ipc_set_tuning(G.IPC_TUNE_FUSED_PCG, 0)
-    G.ipc_set_tuning(G.IPC_TUNE_FOLD_DIR, 1)
-    for k in (1, 2, 3):
+    for k in (1, 2):
         for a, b in zip(runs[0], runs[k]):
             assert np.array_equal(a, b), k
 
