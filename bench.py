@@ -269,7 +269,7 @@ def main():
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: environments are independent and would be sharded across GPUs "
-              "without any collective; only --gpus 1 is supported on this box.", file=sys.stderr)
+              "without any collective; only --gpus 1 is supported.", file=sys.stderr)
         sys.exit(2)
     import torch  # device selection only
     assert torch.cuda.is_available(), "no GPU"

@@ -954,7 +954,7 @@ struct World {
     B.n_items = item_off;
     counts.ensure(item_off + 1);
     offs.ensure(item_off + 2);
-    bp_stash.ensure((size_t)ipck::kStash * item_off + 1);
+    bp_stash.ensure((size_t)stash_n * item_off + 1);
     g_ncell.ensure(bitem_off + 1);
     g_big.ensure(bitem_off + 1);
     g_eoff.ensure(bitem_off + 2);
@@ -1035,6 +1035,7 @@ struct World {
     L.g_ent = g_ent.p;
     L.g_sorted = g_sorted.p;
     L.bp_stash = bp_stash.p;
+    L.stash_n = stash_n;
   }
 
   void set_prof(bool on) {
@@ -1094,7 +1095,11 @@ struct World {
     ipck::bp_grid_count(stream, W, envs_d, S, B, L, nb);
     ipck::scan_int(stream, L.counts, L.offs, B.n_items, L.scan_tmp);
     int n = read_int(L.offs + B.n_items);
-    const bool overflow = read_int(L.counter + 4) > 0;
+    const int n_over = read_int(L.counter + 4);
+    const bool overflow = n_over > 0;
+    if (tracing())
+      std::fprintf(stderr, "[ipc]   broad phase: %d queries, %d pairs, %d queries over the stash of %d\n", B.n_items, n,
+                   n_over, stash_n);
     // each list is sized on its own: capacities are rounded independently
     moved = cand.ensure(n + 1);
     moved |= cand_type.ensure(n + 1);
@@ -1201,6 +1206,9 @@ public:
   // live vertex tiles at or below which the tiled PCG hands the remaining
   // environments to one workgroup each (0 = never)
   int tail_tiles = env_knob("IPC_TAIL_TILES", 0);
+  // broad phase: pairs per query that the counting pass keeps (queries with
+  // more are traversed a second time to write them)
+  const int stash_n = std::max(1, env_knob("IPC_BP_STASH", 64));
   // 1: re-lay the batch out with the still-iterating environments once at
   // most half of it iterates (narrow_batch)
   int narrow = env_knob("IPC_NARROW", 1) ? 1 : 0;

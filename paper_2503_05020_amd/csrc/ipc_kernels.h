@@ -31,8 +31,6 @@ struct GridEnt {
 
 // PCG products over at most this many tiles use the latency variant
 constexpr int kWideTiles = 64;
-// broad phase: pairs per query kept by the counting pass
-constexpr int kStash = 12;
 
 struct Lists {
   int *counts, *offs, *scan_tmp;  // item counts, exclusive scan (n_items+1)
@@ -63,6 +61,7 @@ struct Lists {
   int *g_ncell, *g_big, *g_eoff, *g_bigoff, *g_ebucket, *g_bcnt, *g_boff, *g_bcur, *g_bigl;
   GridEnt *g_ent, *g_sorted;
   int2 *bp_stash;  // first pairs of each query, from the counting pass
+  int stash_n;     // pairs per query the stash holds
   unsigned long long *prof;  // algorithmic bytes moved by profiled kernels (nullptr = off)
 };
 

@@ -20,7 +20,6 @@
 using namespace ipcw;
 using namespace ipcdev;
 using ipck::GridEnt;
-using ipck::kStash;
 
 namespace {
 
@@ -400,15 +399,15 @@ DEV bool boxes_overlap(const QueryPrim &A, const double *bx) {
          bx[2] <= A.hi[2];
 }
 
-// WRITE = false: count each query's pairs and keep the first kStash of them,
-// in their final order, in stash[item * kStash ...]; queries with more are
+// WRITE = false: count each query's pairs and keep the first stash_n of them,
+// in their final order, in stash[item * stash_n ...]; queries with more are
 // counted in *n_over.  WRITE = true: write the pairs of those queries only
 // (the others are copied from the stash by k_bp_gather).
 template <bool WRITE>
 __global__ void __launch_bounds__(256) k_bp_grid(WorldDev W, const EnvDev *envs, EnvState S, const Tile *tiles,
                                                  int *counts, const int *offs, int2 *out, const GridEnt *sorted,
                                                  const int *boff, const int *bigl, unsigned mask, int2 *stash,
-                                                 int *n_over) {
+                                                 int stash_n, int *n_over) {
   Tile t = tiles[blockIdx.x];
   if ((int)threadIdx.x >= t.count) return;
   const EnvDev &E = envs[t.env];
@@ -419,8 +418,8 @@ __global__ void __launch_bounds__(256) k_bp_grid(WorldDev W, const EnvDev *envs,
     if (!WRITE) counts[item] = 0;
     return;
   }
-  if (WRITE && counts[item] <= kStash) return;
-  int2 *st = stash + (size_t)item * kStash;
+  if (WRITE && counts[item] <= stash_n) return;
+  int2 *st = stash + (size_t)item * stash_n;
   QueryPrim A;
   const double *bx = (kind == 0 ? W.box_sv : W.box_edge) + 6 * a;
   for (int k = 0; k < 3; ++k) {
@@ -454,7 +453,7 @@ __global__ void __launch_bounds__(256) k_bp_grid(WorldDev W, const EnvDev *envs,
       const int2 hit = kind == 0 ? make_int2(a, b) : make_int2(~a, b);
       if (WRITE)
         out[pos++] = hit;
-      else if (cnt < kStash)
+      else if (cnt < stash_n)
         st[cnt] = hit;
       ++cnt;
     }
@@ -483,7 +482,7 @@ __global__ void __launch_bounds__(256) k_bp_grid(WorldDev W, const EnvDev *envs,
             const int2 hit = kind == 0 ? make_int2(a, b) : make_int2(~a, b);
             if (WRITE)
               out[pos++] = hit;
-            else if (cnt < kStash)
+            else if (cnt < stash_n)
               st[cnt] = hit;
             ++cnt;
           }
@@ -491,7 +490,7 @@ __global__ void __launch_bounds__(256) k_bp_grid(WorldDev W, const EnvDev *envs,
     // bucket order depends on atomics: put this query's cell hits in
     // candidate-index order so the output is deterministic
     int2 *o = WRITE ? out + offs[item] : st;
-    const int nc = WRITE ? pos - offs[item] : (cnt <= kStash ? cnt : 0);
+    const int nc = WRITE ? pos - offs[item] : (cnt <= stash_n ? cnt : 0);
     for (int j = 1; j < nc; ++j) {
       int2 key = o[j];
       int m = j - 1;
@@ -511,24 +510,25 @@ __global__ void __launch_bounds__(256) k_bp_grid(WorldDev W, const EnvDev *envs,
       const int2 hit = kind == 0 ? make_int2(a, b) : make_int2(~a, b);
       if (WRITE)
         out[pos++] = hit;
-      else if (cnt < kStash)
+      else if (cnt < stash_n)
         st[cnt] = hit;
       ++cnt;
     }
   }
   if (!WRITE) {
     counts[item] = cnt;
-    if (cnt > kStash) atomicAdd(n_over, 1);
+    if (cnt > stash_n) atomicAdd(n_over, 1);
   }
 }
 
 // pairs of the queries that fit the stash, copied to their place in the list
-__global__ void k_bp_gather(const int *counts, const int *offs, const int2 *stash, int n_items, int2 *out) {
+__global__ void k_bp_gather(const int *counts, const int *offs, const int2 *stash, int stash_n, int n_items,
+                            int2 *out) {
   int item = blockIdx.x * blockDim.x + threadIdx.x;
   if (item >= n_items) return;
   const int c = counts[item];
-  if (c > kStash) return;
-  const int2 *st = stash + (size_t)item * kStash;
+  if (c > stash_n) return;
+  const int2 *st = stash + (size_t)item * stash_n;
   int2 *o = out + offs[item];
   for (int j = 0; j < c; ++j) o[j] = st[j];
 }
@@ -1877,14 +1877,15 @@ void bp_grid_count(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvS
   IPC_LAUNCH(k_fill_int, 1, 64, s)(L.counter + 4, 1, 0);
   if (B.n_it)
     IPC_LAUNCH(k_bp_grid<false>, B.n_it, TB, s)(W, E, S, B.itiles, L.counts, nullptr, nullptr, L.g_sorted, L.g_boff,
-                                               L.g_bigl, nbuckets - 1, L.bp_stash, L.counter + 4);
+                                               L.g_bigl, nbuckets - 1, L.bp_stash, L.stash_n, L.counter + 4);
 }
 void bp_grid_write(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L,
                    unsigned nbuckets, bool overflow) {
-  if (B.n_items) IPC_LAUNCH(k_bp_gather, nblk(B.n_items, TB), TB, s)(L.counts, L.offs, L.bp_stash, B.n_items, L.cand);
+  if (B.n_items) IPC_LAUNCH(k_bp_gather, nblk(B.n_items, TB), TB, s)(L.counts, L.offs, L.bp_stash, L.stash_n, B.n_items,
+                                                                   L.cand);
   if (overflow && B.n_it)
     IPC_LAUNCH(k_bp_grid<true>, B.n_it, TB, s)(W, E, S, B.itiles, L.counts, L.offs, L.cand, L.g_sorted, L.g_boff,
-                                              L.g_bigl, nbuckets - 1, L.bp_stash, nullptr);
+                                              L.g_bigl, nbuckets - 1, L.bp_stash, L.stash_n, nullptr);
 }
 
 void scan_int(hipStream_t s, const int *in, int *out, int n, int *tmp) {
