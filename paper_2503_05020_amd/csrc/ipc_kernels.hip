@@ -1053,18 +1053,73 @@ DEV void row_product(const WorldDev &W, int i, bool valid, int l, const V &v, co
   y[2] = a2;
 }
 
-// sum of the 256 per-row values of a tile (written by lane 0 of each row's
-// group, row < 256) in the order of block_sum's tree; every thread gets it
-DEV double rows_tree(double v, bool writer, int row, double *sh) {
-  if (writer) sh[row] = v;
-  __syncthreads();
-  for (int s = TB / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
-    __syncthreads();
+// Fixed-order sums of the PCG (the tiled and the per-environment kernels use
+// the same ones, so both give the same bits).  A butterfly over the lanes of
+// a wavefront leaves the same bits in every lane: each step adds the same two
+// operands, only their order differs.
+//
+// quarter_sum2: a and b summed over each 256-thread quarter of the block (a
+// whole 256-thread block, or one tile's quarter of a 1024-thread block): the
+// butterfly over each wavefront, then the quarter's four wavefront sums as
+// (w0 + w1) + (w2 + w3); every thread gets its quarter's sums.  sh: 32 doubles.
+DEV void quarter_sum2(double &a, double &b, double *sh) {
+  for (int m = 32; m > 0; m >>= 1) {
+    a += __shfl_xor(a, m, 64);
+    b += __shfl_xor(b, m, 64);
   }
-  double r = sh[0];
+  const int wv = threadIdx.x / 64;
+  if ((threadIdx.x & 63) == 0) {
+    sh[wv] = a;
+    sh[16 + wv] = b;
+  }
+  __syncthreads();
+  const int q = wv & ~3;
+  a = (sh[q] + sh[q + 1]) + (sh[q + 2] + sh[q + 3]);
+  b = (sh[16 + q] + sh[17 + q]) + (sh[18 + q] + sh[19 + q]);
+  __syncthreads();
+}
+
+// rows_sum: the sum over the 256 rows of a tile in a 1024-thread block with
+// kLPR lanes per row, every lane of a row holding the row's value: the
+// butterfly over the 16 rows of each wavefront, then the 16 wavefront sums
+// pairwise; every thread gets it.  sh: 16 doubles.
+DEV double rows_sum(double v, double *sh) {
+  for (int m = 32; m >= kLPR; m >>= 1) v += __shfl_xor(v, m, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x / 64] = v;
+  __syncthreads();
+  double t[8];
+  for (int k = 0; k < 8; ++k) t[k] = sh[2 * k] + sh[2 * k + 1];
+  for (int k = 0; k < 4; ++k) t[k] = t[2 * k] + t[2 * k + 1];
+  const double r = (t[0] + t[1]) + (t[2] + t[3]);
   __syncthreads();
   return r;
+}
+
+// env_sums3: the per-tile partials pa, pb, pc of one environment summed in
+// tile order (the additions of env_tiles_sum), with up to 256 partials of
+// each loaded at once by the block's first 256 threads and added up from LDS
+// by every thread.  sh: 768 doubles; every thread of the block calls it.
+DEV void env_sums3(const double *pa, const double *pb, const double *pc, const EnvDev &E, double *sh, double &a,
+                   double &b, double &c) {
+  a = 0.0;
+  b = 0.0;
+  c = 0.0;
+  for (int base = 0; base < E.vtile_count; base += TB) {
+    const int j = base + (int)threadIdx.x;
+    if ((int)threadIdx.x < TB && j < E.vtile_count) {
+      sh[threadIdx.x] = pa[E.vtile_first + j];
+      sh[TB + threadIdx.x] = pb[E.vtile_first + j];
+      sh[2 * TB + threadIdx.x] = pc[E.vtile_first + j];
+    }
+    __syncthreads();
+    const int n = min(TB, E.vtile_count - base);
+    for (int k = 0; k < n; ++k) {
+      a += sh[k];
+      b += sh[TB + k];
+      c += sh[2 * TB + k];
+    }
+    __syncthreads();
+  }
 }
 
 DEV bool pcg_env_live(const EnvState &S, int env) { return S.status[env] == ST_ACTIVE && !S.pcg_done[env]; }
@@ -1125,22 +1180,40 @@ DEV double row_spmv(const WorldDev &W, int i, bool valid, int l, const int *inc_
   return d;
 }
 
+// one row's vectors and preconditioner block, loaded ahead of the scalars
+template <typename T>
+struct RowVals {
+  T x[3], r[3], u[3], p[3], s[3], w[3], M[9];
+};
+template <typename T>
+DEV void row_load(int i, const T *x, const T *r, const T *u, const T *pp, const T *q, const T *w, const T *Minv,
+                  RowVals<T> &v) {
+  for (int c = 0; c < 3; ++c) {
+    v.x[c] = x[3 * i + c];
+    v.r[c] = r[3 * i + c];
+    v.u[c] = u[3 * i + c];
+    v.p[c] = pp[3 * i + c];
+    v.s[c] = q[3 * i + c];
+    v.w[c] = w[3 * i + c];
+  }
+  for (int k = 0; k < 9; ++k) v.M[k] = Minv[9 * (size_t)i + k];
+}
+
 // the update of one row; adds r.u and r.r of the new residual
 template <typename T>
-DEV void row_update(int i, double alpha, double beta, T *x, T *r, T *u, T *pp, T *q, const T *w, const T *Minv,
-                    double &g, double &rr) {
+DEV void row_step(int i, double alpha, double beta, const RowVals<T> &v, T *x, T *r, T *u, T *pp, T *q, double &g,
+                  double &rr) {
   T rv[3], uv[3];
   for (int c = 0; c < 3; ++c) {
-    const T pn = (T)fma(beta, (double)pp[3 * i + c], (double)u[3 * i + c]);
-    const T sn = (T)fma(beta, (double)q[3 * i + c], (double)w[3 * i + c]);
+    const T pn = (T)fma(beta, (double)v.p[c], (double)v.u[c]);
+    const T sn = (T)fma(beta, (double)v.s[c], (double)v.w[c]);
     pp[3 * i + c] = pn;
     q[3 * i + c] = sn;
-    x[3 * i + c] = (T)((double)x[3 * i + c] + alpha * (double)pn);
-    rv[c] = (T)((double)r[3 * i + c] - alpha * (double)sn);
+    x[3 * i + c] = (T)((double)v.x[c] + alpha * (double)pn);
+    rv[c] = (T)((double)v.r[c] - alpha * (double)sn);
     r[3 * i + c] = rv[c];
   }
-  const T *M = Minv + 9 * (size_t)i;
-  for (int c = 0; c < 3; ++c) uv[c] = M[3 * c] * rv[0] + M[3 * c + 1] * rv[1] + M[3 * c + 2] * rv[2];
+  for (int c = 0; c < 3; ++c) uv[c] = v.M[3 * c] * rv[0] + v.M[3 * c + 1] * rv[1] + v.M[3 * c + 2] * rv[2];
   for (int c = 0; c < 3; ++c) {
     u[3 * i + c] = uv[c];
     g += (double)rv[c] * (double)uv[c];
@@ -1165,14 +1238,13 @@ DEV int cg_step(const EnvDev &E, double bb, int it, double gam, double del, doub
 template <typename T>
 __global__ void k_pcg_init(WorldDev W, const EnvDev *envs, EnvState S, const Tile *tiles, T *x, T *r, T *u, T *pp,
                            T *q, const T *Minv, double *part_g, double *part_rr) {
-  __shared__ double sh[TB];
+  __shared__ double sh[32];
   Tile t = tiles[blockIdx.x];
   if (!active_env(S, t.env) || envs[t.env].fused) return;
   int i = t.start + threadIdx.x;
   double g = 0.0, rr = 0.0;
   if ((int)threadIdx.x < t.count) row_init<T>(W, is_dof(W, S, i, t.env), i, x, r, u, pp, q, Minv, g, rr);
-  g = block_sum(g, sh);
-  rr = block_sum(rr, sh);
+  quarter_sum2(g, rr, sh);
   if (threadIdx.x == 0) {
     part_g[tile_slot(envs, t)] = g;
     part_rr[tile_slot(envs, t)] = rr;
@@ -1206,21 +1278,21 @@ __global__ void __launch_bounds__(1024) k_spmv(WorldDev W, const EnvDev *envs, E
                                                const int *inc_off, const int *cr_cnt, const int *cr_col,
                                                const T *cr_val, const T *u, T *w, const T *val, double *part_d,
                                                unsigned long long *prof) {
-  __shared__ double sh[TB];
+  __shared__ double sh[16];
   Tile t = tiles[blockIdx.x];
   if (!pcg_env_live(S, t.env)) return;
   const int row = threadIdx.x / kLPR, l = threadIdx.x % kLPR;
   const int i = t.start + row;
   const bool valid = row < t.count;
   double d = row_spmv<T, WIDE>(W, i, valid, l, inc_off, cr_cnt, cr_col, cr_val, u, w, val);
-  d = rows_tree(d, l == 0, row, sh);
+  d = rows_sum(d, sh);
   if (threadIdx.x == 0) part_d[tile_slot(envs, t)] = d;
   if (prof) {
     // algorithmic bytes of this tile: stored blocks + column indices (sliced
     // ELL and merged contact blocks), one read of u and one write of w per row
     double b = 0.0;
     if (valid) b = (double)(W.row_nnz[i] + cr_cnt[i]) * (9.0 * sizeof(T) + 4.0) + 6.0 * sizeof(T);
-    b = rows_tree(b, l == 0, row, sh);
+    b = rows_sum(b, sh);
     if (threadIdx.x == 0) atomicAdd(prof, (unsigned long long)b);
   }
 }
@@ -1235,16 +1307,22 @@ __global__ void k_pcg_update(WorldDev W, const EnvDev *envs, EnvState S, const T
                              const double *part_d, const double *part_g, const double *part_rr, double *part_g_new,
                              double *part_rr_new, T *x, T *r, T *u, T *pp, T *q, const T *w, const T *Minv,
                              int *pending) {
-  __shared__ double sh[TB];
+  __shared__ double sh[3 * TB];
   __shared__ double s_ab[2];
   __shared__ int s_done;
   Tile t = tiles[blockIdx.x];
   if (!pcg_env_live(S, t.env)) return;
   const EnvDev &E = envs[t.env];
+  // the row's vectors are loaded while the environment's sums are formed
+  const int i = t.start + threadIdx.x;
+  const bool mine = (int)threadIdx.x < t.count;
+  RowVals<T> v;
+  if (mine) row_load<T>(i, x, r, u, pp, q, w, Minv, v);
+  double gam, del, rr;
+  env_sums3(part_g, part_d, part_rr, E, sh, gam, del, rr);
   if (threadIdx.x == 0) {
     const int e = t.env, k = (it + 1) & 1;  // slot of iteration it - 1
     double alpha = 0.0, beta = 0.0;
-    const double gam = env_tiles_sum(part_g, E), del = env_tiles_sum(part_d, E), rr = env_tiles_sum(part_rr, E);
     s_done = cg_step(E, S.pcg_bb[e], it, gam, del, rr, k ? S.cg_a1[e] : S.cg_a0[e], k ? S.cg_g1[e] : S.cg_g0[e],
                      alpha, beta);
     s_ab[0] = alpha;
@@ -1266,14 +1344,12 @@ __global__ void k_pcg_update(WorldDev W, const EnvDev *envs, EnvState S, const T
   }
   __syncthreads();
   if (s_done) return;
-  int i = t.start + threadIdx.x;
-  double g = 0.0, rr = 0.0;
-  if ((int)threadIdx.x < t.count) row_update<T>(i, s_ab[0], s_ab[1], x, r, u, pp, q, w, Minv, g, rr);
-  g = block_sum(g, sh);
-  rr = block_sum(rr, sh);
+  double g = 0.0, rr2 = 0.0;
+  if (mine) row_step<T>(i, s_ab[0], s_ab[1], v, x, r, u, pp, q, g, rr2);
+  quarter_sum2(g, rr2, sh);
   if (threadIdx.x == 0) {
     part_g_new[tile_slot(envs, t)] = g;
-    part_rr_new[tile_slot(envs, t)] = rr;
+    part_rr_new[tile_slot(envs, t)] = rr2;
   }
 }
 
@@ -1286,24 +1362,14 @@ __global__ void k_pcg_update(WorldDev W, const EnvDev *envs, EnvState S, const T
 // ---------------------------------------------------------------------------
 constexpr int FB = 1024;
 
-// tree sums of a and b over each 256-thread quarter (the block_sum tree);
-// thread 0 of each quarter stores them for tile `tile0 + quarter` if that
-// tile exists
-DEV void tile_sums2(double a, double b, double (*sh)[FB], const EnvDev &E, int tile0, double *pa, double *pb) {
-  const int qd = threadIdx.x / TB, l = threadIdx.x % TB;
-  sh[0][threadIdx.x] = a;
-  sh[1][threadIdx.x] = b;
-  __syncthreads();
-  for (int s = TB / 2; s > 0; s >>= 1) {
-    if (l < s) {
-      sh[0][threadIdx.x] += sh[0][threadIdx.x + s];
-      sh[1][threadIdx.x] += sh[1][threadIdx.x + s];
-    }
-    __syncthreads();
-  }
-  if (l == 0 && tile0 + qd < E.vtile_count) {
-    if (pa) pa[E.vtile_first + tile0 + qd] = sh[0][qd * TB];
-    if (pb) pb[E.vtile_first + tile0 + qd] = sh[1][qd * TB];
+// sums of a and b over each 256-thread quarter (quarter_sum2); thread 0 of
+// each quarter stores them for tile `tile0 + quarter` if that tile exists
+DEV void tile_sums2(double a, double b, double *sh, const EnvDev &E, int tile0, double *pa, double *pb) {
+  quarter_sum2(a, b, sh);
+  const int qd = threadIdx.x / TB;
+  if (threadIdx.x % TB == 0 && tile0 + qd < E.vtile_count) {
+    if (pa) pa[E.vtile_first + tile0 + qd] = a;
+    if (pb) pb[E.vtile_first + tile0 + qd] = b;
   }
   __syncthreads();
 }
@@ -1324,19 +1390,23 @@ DEV int env_iterate(const WorldDev &W, const EnvDev &E, double bb, int it, doubl
       const int i = base + row;
       const bool valid = i < r1;
       double d = row_spmv<T, true>(W, i, valid, l, inc_off, cr_cnt, cr_col, cr_val, u, w, val);
-      d = rows_tree(d, l == 0, row, sh[0]);
+      d = rows_sum(d, sh[0]);
       if (threadIdx.x == 0) part_d[E.vtile_first + (base - r0) / TB] = d;
     }
-    __syncthreads();
-    const double gam = env_tiles_sum(part_g[it & 1], E), del = env_tiles_sum(part_d, E);
-    const double rr = env_tiles_sum(part_rr[it & 1], E);
+    __syncthreads();  // the last tile's partial
+    double gam, del, rr;
+    env_sums3(part_g[it & 1], part_d, part_rr[it & 1], E, sh[0], gam, del, rr);
     double alpha = 0.0, beta = 0.0;
     if (cg_step(E, bb, it, gam, del, rr, a_prev, g_prev, alpha, beta)) break;
     for (int base = r0; base < r1; base += FB) {
       int i = base + threadIdx.x;
       double g = 0.0, rri = 0.0;
-      if (i < r1) row_update<T>(i, alpha, beta, x, r, u, pp, q, w, Minv, g, rri);
-      tile_sums2(g, rri, sh, E, (base - r0) / TB, part_g[(it + 1) & 1], part_rr[(it + 1) & 1]);
+      if (i < r1) {
+        RowVals<T> v;
+        row_load<T>(i, x, r, u, pp, q, w, Minv, v);
+        row_step<T>(i, alpha, beta, v, x, r, u, pp, q, g, rri);
+      }
+      tile_sums2(g, rri, sh[1], E, (base - r0) / TB, part_g[(it + 1) & 1], part_rr[(it + 1) & 1]);
     }
     a_prev = alpha;
     g_prev = gam;
@@ -1361,7 +1431,7 @@ __global__ void __launch_bounds__(1024) k_pcg_fused(WorldDev W, const EnvDev *en
     int i = base + threadIdx.x;
     double g = 0.0, rr = 0.0;
     if (i < r1) row_init<T>(W, is_dof(W, S, i, e), i, x, r, u, pp, q, Minv, g, rr);
-    tile_sums2(g, rr, sh, E, (base - r0) / TB, part_g0, part_rr0);
+    tile_sums2(g, rr, sh[1], E, (base - r0) / TB, part_g0, part_rr0);
   }
   const double bb = env_tiles_sum(part_rr0, E);
   int it = 0;
