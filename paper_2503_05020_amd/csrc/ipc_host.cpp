@@ -589,6 +589,7 @@ struct World {
   DBuf<double> cand_d2, e_c, fw, fn, flam, e_f, ce_g, ce_H, part_a, part_b0, part_b1, part_c0, part_c1;
   DBuf<int4> fv, ce_v;
   int *pinned = nullptr;  // host mirror of counters
+  hipEvent_t poll_ev[2] = {nullptr, nullptr};  // PCG polls in flight (copies into pinned[8], pinned[9])
   // profiling of the PCG matrix product (HIP events on this stream)
   bool prof_on = false;
   DBuf<unsigned long long> prof_bytes;
@@ -602,6 +603,7 @@ struct World {
     HC(hipSetDevice(dev));
     HC(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
     HC(hipHostMalloc((void **)&pinned, 64 * sizeof(int), hipHostMallocDefault));
+    for (hipEvent_t &e : poll_ev) HC(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     aV.align = ipcw::kSlice;
     aPos.align = ipcw::kSlice;
     auto reg = [](Arena &a, void **slot, size_t elem) { a.bufs.push_back({slot, elem}); };
@@ -1206,6 +1208,9 @@ public:
   // live vertex tiles at or below which the tiled PCG hands the remaining
   // environments to one workgroup each (0 = never)
   int tail_tiles = env_knob("IPC_TAIL_TILES", 0);
+  // 1: the next block of PCG iterations is queued before the host polls the
+  // previous one (0: after it)
+  const int pipeline = env_knob("IPC_PIPELINE", 1) ? 1 : 0;
   // broad phase: pairs per query that the counting pass keeps (queries with
   // more are traversed a second time to write them)
   const int stash_n = std::max(1, env_knob("IPC_BP_STASH", 64));
@@ -1254,9 +1259,11 @@ public:
     const bool tr = tracing();
     double t_launch = 0.0, t_wait = 0.0;
     auto now = []() { return std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now().time_since_epoch()).count(); };
-    while (true) {
-      double t0 = tr ? now() : 0.0;
-      // a block of 8 iterations between polls of the pending count
+    // Blocks of 8 iterations, pipelined: block k+1 is queued before the host
+    // waits for the count of environments still iterating after block k, so
+    // the device does not idle while the host polls.  A block queued after
+    // every solve has stopped costs only launches whose tiles exit at once.
+    auto launch_block = [&](int slot) {
       for (int j = 0; j < 8; ++j) {
         hipEvent_t e0 = nullptr, e1 = nullptr;
         // every 16th iteration is timed (an event pair costs a few us of
@@ -1268,8 +1275,18 @@ public:
         }
         ipck::pcg_iter(stream, W, envs_d, S, L, it++, pending, mixed, e0, e1, tl, ntl);
       }
+      HC(hipMemcpyAsync(pinned + 8 + slot, pending, sizeof(int), hipMemcpyDeviceToHost, stream));
+      HC(hipEventRecord(poll_ev[slot], stream));
+    };
+    int slot = 0;
+    launch_block(slot);
+    while (true) {
+      double t0 = tr ? now() : 0.0;
+      const bool queued = pipeline && it < cap;
+      if (queued) launch_block(1 - slot);
       double t1 = tr ? now() : 0.0;
-      int pend = read_int(pending);
+      HC(hipEventSynchronize(poll_ev[slot]));
+      const int pend = pinned[8 + slot];
       if (tr) {
         t_launch += t1 - t0;
         t_wait += now() - t1;
@@ -1287,6 +1304,8 @@ public:
           break;
         }
       }
+      if (!queued) launch_block(1 - slot);
+      slot = 1 - slot;
     }
     ipck::pcg_finish(stream, W, S, B, mixed);
     if (tr)
