@@ -1002,45 +1002,66 @@ DEV void block_acc(const T *b, const V &v, int c, double &a0, double &a1, double
   a2 += (double)b[6] * x0 + (double)b[7] * x1 + (double)b[8] * x2;
 }
 
+// Where a row's stored blocks are: its slice's offset and width in the
+// sliced-ELL arrays, and the offset and count of its merged contact blocks.
+// Loaded apart from the product so that kernels can issue these loads with
+// their other first loads.
+struct RowHead {
+  int base, wdt, cb, cn;
+};
+DEV RowHead row_head(const WorldDev &W, int i, const int *inc_off, const int *cr_cnt) {
+  const int sl = i / kSlice;
+  return {W.slice_pos[sl], W.slice_w[sl], 4 * inc_off[i], cr_cnt[i]};
+}
+
 // WIDE: the lane's slots are processed four per round (their loads in
 // flight together: fewer round trips, for launches of a few tiles where
-// latency dominates); otherwise one per round (fewer registers, more waves
-// for launches over the whole batch).  Same additions in the same order.
+// latency dominates), and the columns of its first four contact blocks are
+// loaded with the first slots; otherwise one per round (fewer registers,
+// more waves for launches over the whole batch).  Same additions in the
+// same order.
 template <typename T, typename V, bool WIDE>
-DEV void row_product(const WorldDev &W, int i, bool valid, int l, const V &v, const T *val, const int *inc_off,
-                     const int *cr_cnt, const int *cr_col, const T *cr_val, double y[3]) {
+DEV void row_product(const WorldDev &W, int i, bool valid, int l, const RowHead &h, const V &v, const T *val,
+                     const int *cr_col, const T *cr_val, double y[3]) {
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
   if (valid) {
-    const int sl = i / kSlice, lane = i % kSlice;
-    const int base = W.slice_pos[sl], wdt = W.slice_w[sl];
-    const int *colp = W.col + base + lane;
-    const T *vp = val + (size_t)(base / kSlice) * (9 * kSlice) + lane;
-    int k = l;
+    const int lane = i % kSlice;
+    const int *colp = W.col + h.base + lane;
+    const T *vp = val + (size_t)(h.base / kSlice) * (9 * kSlice) + lane;
+    int k = l, j = l;
     if (WIDE) {
-      for (; k + 3 * kLPR < wdt; k += 4 * kLPR) {
+      int cc[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) cc[u] = l + u * kLPR < h.cn ? cr_col[h.cb + l + u * kLPR] : 0;
+      for (; k + 3 * kLPR < h.wdt; k += 4 * kLPR) {
         int c[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) c[u] = colp[(k + u * kLPR) * kSlice];
 #pragma unroll
         for (int u = 0; u < 4; ++u) slot_acc<T>(vp + (size_t)(k + u * kLPR) * (9 * kSlice), v, c[u], a0, a1, a2);
       }
-    }
 #pragma unroll 1
-    for (; k < wdt; k += kLPR) slot_acc<T>(vp + (size_t)k * (9 * kSlice), v, colp[k * kSlice], a0, a1, a2);
-    // contact blocks of the row, merged by column (k_contact_rows)
-    const int cb = 4 * inc_off[i], cn = cr_cnt[i];
-    int j = l;
-    if (WIDE) {
-      for (; j + 3 * kLPR < cn; j += 4 * kLPR) {
+      for (; k < h.wdt; k += kLPR) slot_acc<T>(vp + (size_t)k * (9 * kSlice), v, colp[k * kSlice], a0, a1, a2);
+      // contact blocks of the row, merged by column (k_contact_rows): the
+      // first four from the columns loaded above, then four per round
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (j + u * kLPR < h.cn) block_acc<T>(cr_val + 9 * (size_t)(h.cb + j + u * kLPR), v, cc[u], a0, a1, a2);
+      j += 4 * kLPR;
+      for (; j + 3 * kLPR < h.cn; j += 4 * kLPR) {
         int c[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) c[u] = cr_col[cb + j + u * kLPR];
+        for (int u = 0; u < 4; ++u) c[u] = cr_col[h.cb + j + u * kLPR];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) block_acc<T>(cr_val + 9 * (size_t)(cb + j + u * kLPR), v, c[u], a0, a1, a2);
+        for (int u = 0; u < 4; ++u) block_acc<T>(cr_val + 9 * (size_t)(h.cb + j + u * kLPR), v, c[u], a0, a1, a2);
       }
-    }
+    } else {
 #pragma unroll 1
-    for (; j < cn; j += kLPR) block_acc<T>(cr_val + 9 * (size_t)(cb + j), v, cr_col[cb + j], a0, a1, a2);
+      for (; k < h.wdt; k += kLPR) slot_acc<T>(vp + (size_t)k * (9 * kSlice), v, colp[k * kSlice], a0, a1, a2);
+    }
+    // contact blocks of the row, merged by column (k_contact_rows)
+#pragma unroll 1
+    for (; j < h.cn; j += kLPR) block_acc<T>(cr_val + 9 * (size_t)(h.cb + j), v, cr_col[h.cb + j], a0, a1, a2);
   }
   a0 += __shfl_xor(a0, 1, 64);
   a1 += __shfl_xor(a1, 1, 64);
@@ -1166,11 +1187,11 @@ DEV void row_init(const WorldDev &W, bool fr, int i, T *x, T *r, T *u, T *pp, T 
 // w_i = (H u)_i by the row's 4 lanes; returns u_i . w_i (same in all four
 // lanes, 0 for an invalid row)
 template <typename T, bool WIDE>
-DEV double row_spmv(const WorldDev &W, int i, bool valid, int l, const int *inc_off, const int *cr_cnt,
-                    const int *cr_col, const T *cr_val, const T *u, T *w, const T *val) {
+DEV double row_spmv(const WorldDev &W, int i, bool valid, int l, const RowHead &h, const int *cr_col,
+                    const T *cr_val, const T *u, T *w, const T *val) {
   double y[3];
   const StoredVec<T> v{u};
-  row_product<T, StoredVec<T>, WIDE>(W, i, valid, l, v, val, inc_off, cr_cnt, cr_col, cr_val, y);
+  row_product<T, StoredVec<T>, WIDE>(W, i, valid, l, h, v, val, cr_col, cr_val, y);
   if (!valid) return 0.0;
   double d = 0.0;
   for (int c = 0; c < 3; ++c) {
@@ -1280,11 +1301,17 @@ __global__ void __launch_bounds__(1024) k_spmv(WorldDev W, const EnvDev *envs, E
                                                unsigned long long *prof) {
   __shared__ double sh[16];
   Tile t = tiles[blockIdx.x];
-  if (!pcg_env_live(S, t.env)) return;
   const int row = threadIdx.x / kLPR, l = threadIdx.x % kLPR;
   const int i = t.start + row;
   const bool valid = row < t.count;
-  double d = row_spmv<T, WIDE>(W, i, valid, l, inc_off, cr_cnt, cr_col, cr_val, u, w, val);
+  // the row's head (row t.start for lanes past the tile's rows) is loaded
+  // together with the environment's state; the empty asm keeps the compiler
+  // from moving these loads after the test
+  int st = S.status[t.env], dn = S.pcg_done[t.env];
+  RowHead h = row_head(W, valid ? i : t.start, inc_off, cr_cnt);
+  asm volatile("" : "+v"(h.base), "+v"(h.wdt), "+v"(h.cb), "+v"(h.cn), "+v"(st), "+v"(dn));
+  if (st != ST_ACTIVE || dn) return;
+  double d = row_spmv<T, WIDE>(W, i, valid, l, h, cr_col, cr_val, u, w, val);
   d = rows_sum(d, sh);
   if (threadIdx.x == 0) part_d[tile_slot(envs, t)] = d;
   if (prof) {
@@ -1311,16 +1338,22 @@ __global__ void k_pcg_update(WorldDev W, const EnvDev *envs, EnvState S, const T
   __shared__ double s_ab[2];
   __shared__ int s_done;
   Tile t = tiles[blockIdx.x];
-  if (!pcg_env_live(S, t.env)) return;
-  const EnvDev &E = envs[t.env];
-  // the row's vectors are loaded while the environment's sums are formed
+  // The row's vectors (row t.start for threads past the tile's rows) are
+  // loaded together with the environment's state and are in flight while the
+  // environment's sums are formed; an environment no longer iterating takes
+  // the same path and stops at the test below, so that no branch stands
+  // between these loads.
   const int i = t.start + threadIdx.x;
   const bool mine = (int)threadIdx.x < t.count;
   RowVals<T> v;
-  if (mine) row_load<T>(i, x, r, u, pp, q, w, Minv, v);
+  row_load<T>(mine ? i : t.start, x, r, u, pp, q, w, Minv, v);
+  const int st = S.status[t.env], dn = S.pcg_done[t.env];
+  const bool live = st == ST_ACTIVE && !dn;
+  const EnvDev &E = envs[t.env];
   double gam, del, rr;
   env_sums3(part_g, part_d, part_rr, E, sh, gam, del, rr);
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0 && !live) s_done = 1;
+  if (threadIdx.x == 0 && live) {
     const int e = t.env, k = (it + 1) & 1;  // slot of iteration it - 1
     double alpha = 0.0, beta = 0.0;
     s_done = cg_step(E, S.pcg_bb[e], it, gam, del, rr, k ? S.cg_a1[e] : S.cg_a0[e], k ? S.cg_g1[e] : S.cg_g0[e],
@@ -1389,7 +1422,9 @@ DEV int env_iterate(const WorldDev &W, const EnvDev &E, double bb, int it, doubl
       const int row = threadIdx.x / kLPR, l = threadIdx.x % kLPR;
       const int i = base + row;
       const bool valid = i < r1;
-      double d = row_spmv<T, true>(W, i, valid, l, inc_off, cr_cnt, cr_col, cr_val, u, w, val);
+      RowHead h{0, 0, 0, 0};
+      if (valid) h = row_head(W, i, inc_off, cr_cnt);
+      double d = row_spmv<T, true>(W, i, valid, l, h, cr_col, cr_val, u, w, val);
       d = rows_sum(d, sh[0]);
       if (threadIdx.x == 0) part_d[E.vtile_first + (base - r0) / TB] = d;
     }
@@ -1499,8 +1534,9 @@ __global__ void __launch_bounds__(1024) k_spmv_dbg(WorldDev W, EnvState S, const
   const int i = t.start + row;
   const bool valid = row < t.count;
   double y[3];
-  row_product<double, StoredVec<double>, false>(W, i, valid, l, StoredVec<double>{in}, W.val, inc_off, cr_cnt,
-                                                cr_col, cr_val, y);
+  RowHead h{0, 0, 0, 0};
+  if (valid) h = row_head(W, i, inc_off, cr_cnt);
+  row_product<double, StoredVec<double>, false>(W, i, valid, l, h, StoredVec<double>{in}, W.val, cr_col, cr_val, y);
   if (valid && l < 3) out[3 * i + l] = y[l];
 }
 
