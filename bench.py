@@ -54,7 +54,7 @@ def make_scenes(workload: str, n_envs: int):
     raise SystemExit(f"unknown workload {workload}")
 
 
-def run_gpu(scs, precision, warmup, steps, pcg_tol, label):
+def run_gpu(scs, precision, warmup, steps, pcg_tol, label, count_all=False):
     import torch
     t0 = time.time()
     gs = [G.ipc_create_scene(sc, precision=precision, pcg_rel_tol=pcg_tol) for sc in scs]
@@ -63,7 +63,8 @@ def run_gpu(scs, precision, warmup, steps, pcg_tol, label):
         rc, infos = G.ipc_step_batch(gs, 1)
         log(f"[{label}] warmup step {k}: newton(max)={max(i['max_newton_iters'] for i in infos)}")
     torch.cuda.synchronize()
-    G.ipc_prof_reset()
+    if not count_all:
+        G.ipc_prof_reset()
     # the timed steps in one call: each lane of the library then runs through
     # them at its own pace instead of waiting for the slowest lane every step
     t0 = time.perf_counter()
@@ -174,7 +175,8 @@ def measured_traffic(precision):
 def pmc_summary(d, copy_mib):
     """Write profiles/spmv_traffic.json from rocprofv3 --pmc csv runs under directory d:
     pmc_copy_<C> (this script with --copy-probe copy_mib) and pmc_spmv_<prec>_<C> (this script with
-    --precision <prec>), for C in FETCH_SIZE, WRITE_SIZE (KiB per dispatch)."""
+    --precision <prec> --count-all-bytes, its output in pmc_spmv_<prec>_<C>.log), for C in FETCH_SIZE,
+    WRITE_SIZE (KiB per dispatch)."""
     import csv
     import glob
     import hashlib
@@ -217,6 +219,16 @@ def pmc_summary(d, copy_mib):
             tot += mean * 1024.0 * factor[c]
         if tot is not None:
             res["bytes_per_launch"][prec] = int(tot)
+        # the algorithmic bytes of the same launches (the counter runs use --count-all-bytes)
+        log_path = os.path.join(d, f"pmc_spmv_{prec}_FETCH_SIZE.log")
+        if os.path.exists(log_path):
+            with open(log_path) as fh:
+                for line in fh:
+                    if line.startswith("{") and "algorithmic_bytes_per_launch" in line:
+                        alg = json.loads(line)["algorithmic_bytes_per_launch"][prec]
+                        res.setdefault("algorithmic_bytes_per_launch", {})[prec] = alg
+                        if tot:
+                            res.setdefault("traffic_over_algorithmic", {})[prec] = round(tot / alg, 3)
     with open(os.path.join(ROOT, "paper_2503_05020_amd", "csrc", "ipc_kernels.hip"), "rb") as f:
         res["kernel_source_sha256"] = hashlib.sha256(f.read()).hexdigest()
     out = os.path.join(ROOT, "profiles", "spmv_traffic.json")
@@ -259,6 +271,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=48, help="0 skips the serving run")
     ap.add_argument("--serve-slots", type=int, default=0, help="0 = slot cap tuned by the server")
+    ap.add_argument("--count-all-bytes", action="store_true",
+                    help="count the algorithmic bytes of every PCG product launch (warm-up included), time none")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device copy of this many MiB, 5 times (calibrates HBM counters)")
     ap.add_argument("--pmc-summary", default="",
@@ -286,12 +300,18 @@ def main():
     scs = make_scenes(args.workload, args.envs)
     ntets = sum(len(sc["E"]) for sc in scs)
     log(f"workload {args.workload}: {len(scs)} envs, {ntets} tets")
-    G.ipc_prof_enable(1)
+    G.ipc_prof_enable(2 if args.count_all_bytes else 1)
     results = {}
     precs = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
     for p in precs:
         results[p] = run_gpu(scs, G.IPC_MIXED if p == "mixed" else G.IPC_FP64, args.warmup, args.steps,
-                             args.pcg_tol, p)
+                             args.pcg_tol, p, args.count_all_bytes)
+        if args.count_all_bytes:
+            pr = results[p]["prof"]
+            # algorithmic bytes per product launch over the whole run, the
+            # launches a counter run of the same command sees
+            print(json.dumps({"algorithmic_bytes_per_launch": {p: int(pr["spmv_bytes"] / max(1, pr["spmv_launches"]))},
+                              "launches": pr["spmv_launches"]}), flush=True)
         log(f"[{p}] {results[p]['value']:.1f} converged env-steps/s, {results[p]['ms_per_step']:.1f} ms/step")
     main_p = "mixed" if "mixed" in results else precs[0]
     r = results[main_p]

@@ -137,7 +137,11 @@ int ipc_scene_sizes(ipc_scene s, int64_t out[7]);
  * applied) to a device counter.  ipc_prof_read writes out[0] total
  * event-timed milliseconds, out[1] number of timed launches, out[2] their
  * bytes, and out[3..5] the same three for the timed launches over more than
- * 64 tiles (out has 6 entries).  Sums over the lanes of the device. */
+ * 64 tiles (out has 6 entries).  Sums over the lanes of the device.
+ * ipc_prof_enable(2) instead counts the bytes of every launch of the kernel
+ * and times none of them (out[0] stays 0, out[1] counts every launch): the
+ * algorithmic bytes of the same launches that a hardware counter run over
+ * the whole program sees.  ipc_prof_enable(0) turns measurement off. */
 int ipc_prof_enable(int32_t on);
 int ipc_prof_reset(void);
 int ipc_prof_read(double *out);

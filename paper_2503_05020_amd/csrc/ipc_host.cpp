@@ -592,6 +592,7 @@ struct World {
   hipEvent_t poll_ev[2] = {nullptr, nullptr};  // PCG polls in flight (copies into pinned[8], pinned[9])
   // profiling of the PCG matrix product (HIP events on this stream)
   bool prof_on = false;
+  bool prof_all = false;  // bytes of every product launch, none timed
   DBuf<unsigned long long> prof_bytes;
   std::vector<hipEvent_t> ev_pool;
   double prof_ms = 0.0, prof_ms_big = 0.0;  // big: launches over more than kWideTiles tiles
@@ -1040,8 +1041,10 @@ struct World {
     L.stash_n = stash_n;
   }
 
-  void set_prof(bool on) {
-    prof_on = on;
+  void set_prof(int mode) {
+    prof_on = mode != 0;
+    prof_all = mode == 2;
+    const bool on = prof_on;
     if (on && !prof_bytes.p) {
       prof_bytes.ensure(4);
       HC(hipMemsetAsync(prof_bytes.p, 0, 8 * prof_bytes.cap, stream));
@@ -1227,7 +1230,7 @@ public:
     set_fused(o.fused_pcg);
     tail_tiles = o.tail_tiles;
     narrow = o.narrow;
-    set_prof(o.prof_on);
+    set_prof(o.prof_all ? 2 : o.prof_on ? 1 : 0);
   }
 
   long long solve(int mixed) {
@@ -1267,8 +1270,13 @@ public:
       for (int j = 0; j < 8; ++j) {
         hipEvent_t e0 = nullptr, e1 = nullptr;
         // every 16th iteration is timed (an event pair costs a few us of
-        // dispatch gap, which would slow the solve it measures)
-        if (prof_on && (it & 15) == 5) {
+        // dispatch gap, which would slow the solve it measures); with
+        // prof_all every launch counts its bytes and none is timed
+        if (prof_all) {
+          e0 = pool_event(0);
+          e1 = pool_event(1);
+          prof_launches += 1;
+        } else if (prof_on && (it & 15) == 5) {
           e0 = pool_event(nev++);
           e1 = pool_event(nev++);
           ev_big.push_back(ntl > ipck::kWideTiles ? 1 : 0);
@@ -1990,7 +1998,7 @@ int ipc_prof_enable(int32_t on) {
   return guarded([&]() {
     for (World *w : worlds_for_current_device()) {
       std::lock_guard<std::mutex> lk(w->mu);
-      w->set_prof(on != 0);
+      w->set_prof(on == 2 ? 2 : on != 0 ? 1 : 0);
     }
     return IPC_OK;
   });
