@@ -608,10 +608,179 @@ DEV double nh_energy(const double *x, const double *Dinv, double vol, double mu,
 // (0,0),(0,1),(0,2),(0,3),(1,1),(1,2),(1,3),(2,2),(2,3),(3,3).
 HD int blk_index(int a, int b) { return a * 4 - (a * (a - 1)) / 2 + (b - a); }
 
-// Returns false if J <= 0.  g[12]; blocks[90] (10 blocks x 9, row-major).
-// HF and V are scratch arrays of 81 doubles each.
+// One Jacobi rotation of a symmetric 3x3 A (row-major) in the (p, q) plane,
+// accumulated into the columns of V (the rotation of psd_project).
+template <int p, int q>
+DEV void jacobi3_rot(double A[9], double V[9]) {
+  const double apq = A[3 * p + q];
+  if (apq == 0.0) return;
+  const double theta = (A[3 * q + q] - A[3 * p + p]) / (2.0 * apq);
+  const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+  const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double akp = A[3 * k + p], akq = A[3 * k + q];
+    A[3 * k + p] = c * akp - s * akq;
+    A[3 * k + q] = s * akp + c * akq;
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double apk = A[3 * p + k], aqk = A[3 * q + k];
+    A[3 * p + k] = c * apk - s * aqk;
+    A[3 * q + k] = s * apk + c * aqk;
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double vkp = V[3 * k + p], vkq = V[3 * k + q];
+    V[3 * k + p] = c * vkp - s * vkq;
+    V[3 * k + q] = s * vkp + c * vkq;
+  }
+}
+
+// Eigen-decomposition of a symmetric 3x3 by cyclic Jacobi (fixed indices, so
+// everything stays in registers): A ends diagonal with the eigenvalues, the
+// columns of V are the eigenvectors.
+DEV void jacobi3(double A[9], double V[9]) {
+#pragma unroll
+  for (int k = 0; k < 9; ++k) V[k] = (k % 4 == 0) ? 1.0 : 0.0;
+  for (int sweep = 0; sweep < 32; ++sweep) {
+    const double off = A[1] * A[1] + A[2] * A[2] + A[5] * A[5];
+    const double dia = A[0] * A[0] + A[4] * A[4] + A[8] * A[8];
+    if (!(off > 1e-34 * dia)) break;
+    jacobi3_rot<0, 1>(A, V);
+    jacobi3_rot<0, 2>(A, V);
+    jacobi3_rot<1, 2>(A, V);
+  }
+}
+
+// index of (r, c), r <= c, in the packed upper triangle of a symmetric 9x9
+HD int tri9(int r, int c) { return r * 9 - (r * (r - 1)) / 2 + (c - r); }
+
+// PSD projection of the Neo-Hookean dP/dF in closed form, packed upper
+// triangle of the 9x9 (row-major (i,j),(k,l) indexing as in nh_element).
+// dP/dF maps a 3x3 X to mu X + c1 G X^T G + la (G:X) G with G = F^-T and
+// c1 = mu - la ln J.  With the singular value decomposition F = U diag(sig) V^T
+// (U, V orthogonal, sig > 0 as J > 0), G = U diag(s) V^T with s = 1/sig, and for
+// X = U Y V^T the image is U (mu Y + c1 S Y^T S + la (s . diag Y) S) V^T.  Hence
+// the nine eigenpairs, all in closed form but one 3x3 block:
+//   Y = (E_ab + E_ba)/sqrt2, a < b:  mu + c1 s_a s_b
+//   Y = (E_ab - E_ba)/sqrt2, a < b:  mu - c1 s_a s_b
+//   Y diagonal: the symmetric 3x3 block  mu I + c1 diag(s_a^2) + la s s^T.
+// The projection sums the modes with their eigenvalues clamped at 0.
+DEV void nh_dPdF_projected(const double F[9], double lJ, double mu, double la, double Hs[45]) {
+  // right singular vectors and singular values from F^T F
+  double C[9], V[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) C[3 * i + j] = F[i] * F[j] + F[3 + i] * F[3 + j] + F[6 + i] * F[6 + j];
+  jacobi3(C, V);
+  // left singular vectors: u_a = F v_a / |F v_a| for the two largest singular
+  // values (the second orthogonalised against the first), the third
+  // completing an orthonormal basis with the sign of F v_3
+  double ev[3] = {C[0], C[4], C[8]}, v[3][3], u[3][3], sg[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) v[a][i] = V[3 * i + a];
+  // descending order (fixed indices: the swaps stay in registers)
+  auto order = [&](int p, int q) {
+    if (ev[p] < ev[q]) {
+      const double t = ev[p];
+      ev[p] = ev[q];
+      ev[q] = t;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const double w = v[p][i];
+        v[p][i] = v[q][i];
+        v[q][i] = w;
+      }
+    }
+  };
+  order(0, 1);
+  order(1, 2);
+  order(0, 1);
+  double Fv[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) Fv[a][i] = F[3 * i] * v[a][0] + F[3 * i + 1] * v[a][1] + F[3 * i + 2] * v[a][2];
+  {
+    double n0 = sqrt(Fv[0][0] * Fv[0][0] + Fv[0][1] * Fv[0][1] + Fv[0][2] * Fv[0][2]);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) u[0][i] = Fv[0][i] / n0;
+    double d = u[0][0] * Fv[1][0] + u[0][1] * Fv[1][1] + u[0][2] * Fv[1][2];
+    double w[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) w[i] = Fv[1][i] - d * u[0][i];
+    double n1 = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) u[1][i] = w[i] / n1;
+    double c3[3] = {u[0][1] * u[1][2] - u[0][2] * u[1][1], u[0][2] * u[1][0] - u[0][0] * u[1][2],
+                    u[0][0] * u[1][1] - u[0][1] * u[1][0]};
+    const double sgn = (c3[0] * Fv[2][0] + c3[1] * Fv[2][1] + c3[2] * Fv[2][2]) >= 0.0 ? 1.0 : -1.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) u[2][i] = sgn * c3[i];
+    // singular values as u_a . F v_a (more accurate for the small ones than
+    // the square roots of the eigenvalues of F^T F)
+    sg[0] = n0;
+    sg[1] = n1;
+    sg[2] = u[2][0] * Fv[2][0] + u[2][1] * Fv[2][1] + u[2][2] * Fv[2][2];
+  }
+  double sv[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) sv[a] = 1.0 / sg[a];
+  const double c1 = mu - la * lJ;
+#pragma unroll
+  for (int k = 0; k < 45; ++k) Hs[k] = 0.0;
+  // adds lam+ vec(Q) vec(Q)^T for Q = sum_m coef_m u_{a_m} v_{b_m}^T
+  auto add_mode = [&](double lam, const double Q[9]) {
+    if (!(lam > 0.0)) return;
+#pragma unroll
+    for (int r = 0; r < 9; ++r)
+#pragma unroll
+      for (int c = r; c < 9; ++c) Hs[tri9(r, c)] += lam * Q[r] * Q[c];
+  };
+  // the diagonal block
+  double A[9], Wd[9];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) A[3 * a + b] = (a == b ? mu + c1 * sv[a] * sv[a] : 0.0) + la * sv[a] * sv[b];
+  jacobi3(A, Wd);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    double Q[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        Q[3 * i + j] = Wd[k] * u[0][i] * v[0][j] + Wd[3 + k] * u[1][i] * v[1][j] + Wd[6 + k] * u[2][i] * v[2][j];
+    add_mode(A[4 * k], Q);
+  }
+  // twist and flip pairs
+  const double r2 = 0.70710678118654752440;
+#pragma unroll
+  for (int pr = 0; pr < 3; ++pr) {
+    const int a = pr == 2 ? 1 : 0, b = pr == 0 ? 1 : 2;
+    double Qp[9], Qm[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const double x1 = u[a][i] * v[b][j], x2 = u[b][i] * v[a][j];
+        Qp[3 * i + j] = r2 * (x1 + x2);
+        Qm[3 * i + j] = r2 * (x1 - x2);
+      }
+    add_mode(mu + c1 * sv[a] * sv[b], Qp);
+    add_mode(mu - c1 * sv[a] * sv[b], Qm);
+  }
+}
+
+// Returns false if J <= 0.  g[12]; blocks[90] (10 blocks x 9, row-major),
+// from the projected dP/dF (nh_dPdF_projected).
 DEV bool nh_element(const double *x, const double *Dinv, double vol, double mu, double la, double *energy, double *g,
-                    double *blocks, double *HF, double *V) {
+                    double *blocks) {
   double F[9], FiT[9];
   nh_F(x, Dinv, F);
   double J = inv_T33(F, FiT);
@@ -633,23 +802,27 @@ DEV bool nh_element(const double *x, const double *Dinv, double vol, double mu, 
     for (int k = 0; k < 3; ++k)
       g[3 * a + k] = vol * (P[k * 3] * dvec[a][0] + P[k * 3 + 1] * dvec[a][1] + P[k * 3 + 2] * dvec[a][2]);
   if (!blocks) return true;
-  double c1 = mu - la * lJ;
-  for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j)
-      for (int k = 0; k < 3; ++k)
-        for (int l = 0; l < 3; ++l)
-          HF[(i * 3 + j) * 9 + k * 3 + l] = ((i == k && j == l) ? mu : 0.0) + c1 * FiT[i * 3 + l] * FiT[k * 3 + j] +
-                                            la * FiT[i * 3 + j] * FiT[k * 3 + l];
-  psd_project(9, HF, 9, V);
+  double Hs[45];
+  nh_dPdF_projected(F, lJ, mu, la, Hs);
+  // block (a,b)_{k,m} = vol sum_{j,l} d_a[j] H[(k,j),(m,l)] d_b[l]
+#pragma unroll
   for (int a = 0; a < 4; ++a)
+#pragma unroll
     for (int b = a; b < 4; ++b) {
       double *B = blocks + 9 * blk_index(a, b);
+#pragma unroll
       for (int k = 0; k < 3; ++k)
+#pragma unroll
         for (int m = 0; m < 3; ++m) {
           double s = 0.0;
+#pragma unroll
           for (int j = 0; j < 3; ++j) {
             double t = 0.0;
-            for (int l = 0; l < 3; ++l) t += HF[(k * 3 + j) * 9 + m * 3 + l] * dvec[b][l];
+#pragma unroll
+            for (int l = 0; l < 3; ++l) {
+              const int r = k * 3 + j, c = m * 3 + l;
+              t += Hs[r <= c ? tri9(r, c) : tri9(c, r)] * dvec[b][l];
+            }
             s += dvec[a][j] * t;
           }
           B[k * 3 + m] = vol * s;

@@ -869,15 +869,16 @@ __global__ void __launch_bounds__(256) k_elastic(WorldDev W, EnvState S, const T
   int e = t.start + threadIdx.x;
   int4 q = W.tet[e];
   int v[4] = {q.x, q.y, q.z, q.w};
-  double x[12], g[12], blocks[90], HF[81], V[81], en;
+  double x[12], g[12], en;
   gather12(W.x, v, x);
-  bool ok = nh_element(x, W.Dinv + 9 * e, W.vol[e], W.mu[e], W.la[e], &en, g, blocks, HF, V);
+  // the Hessian blocks are written straight to their place
+  double *blocks = W.tH + 90 * (size_t)e;
+  const bool ok = nh_element(x, W.Dinv + 9 * e, W.vol[e], W.mu[e], W.la[e], &en, g, blocks);
   if (!ok) {
     for (int i = 0; i < 12; ++i) g[i] = __builtin_nan("");
     for (int i = 0; i < 90; ++i) blocks[i] = 0.0;
   }
   for (int i = 0; i < 12; ++i) W.tg[12 * (size_t)e + i] = g[i];
-  for (int i = 0; i < 90; ++i) W.tH[90 * (size_t)e + i] = blocks[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -1904,9 +1905,9 @@ __global__ void k_dbg_tet(const double *X12, const double *x12, double mu, doubl
     for (int a = 0; a < 3; ++a) Dm[i * 3 + a] = X12[3 * (a + 1) + i] - X12[i];
   inv33(Dm, Dinv);
   double vol = det33(Dm) / 6.0;
-  double x[12], g[12], blocks[90], HF[81], V[81], en;
+  double x[12], g[12], blocks[90], en;
   for (int i = 0; i < 12; ++i) x[i] = x12[i];
-  if (!nh_element(x, Dinv, vol, mu, la, &en, g, blocks, HF, V)) {
+  if (!nh_element(x, Dinv, vol, mu, la, &en, g, blocks)) {
     out[0] = kInf;
     return;
   }
