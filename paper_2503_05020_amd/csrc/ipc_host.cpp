@@ -1039,6 +1039,7 @@ struct World {
     L.g_sorted = g_sorted.p;
     L.bp_stash = bp_stash.p;
     L.stash_n = stash_n;
+    L.wide_tiles = wide_tiles;
   }
 
   void set_prof(int mode) {
@@ -1217,6 +1218,11 @@ public:
   // broad phase: pairs per query that the counting pass keeps (queries with
   // more are traversed a second time to write them)
   const int stash_n = std::max(1, env_knob("IPC_BP_STASH", 64));
+  // PCG product launches over at most this many tiles issue each lane's
+  // slots four at a time, larger ones one at a time (default 0: the one-slot
+  // variant everywhere, at 44 VGPRs against 86, measured faster on the
+  // batched grasp workload also in its latency-bound tails)
+  const int wide_tiles = env_knob("IPC_WIDE_TILES", 0);
   // 1: re-lay the batch out with the still-iterating environments once at
   // most half of it iterates (narrow_batch)
   int narrow = env_knob("IPC_NARROW", 1) ? 1 : 0;

@@ -29,7 +29,8 @@ struct GridEnt {
   int env, pad;
 };
 
-// PCG products over at most this many tiles use the latency variant
+// PCG product launches over more than this many tiles are measured as a
+// class of their own (the rest are the latency-bound tails)
 constexpr int kWideTiles = 64;
 
 struct Lists {
@@ -62,6 +63,7 @@ struct Lists {
   GridEnt *g_ent, *g_sorted;
   int2 *bp_stash;  // first pairs of each query, from the counting pass
   int stash_n;     // pairs per query the stash holds
+  int wide_tiles;  // PCG products over at most this many tiles use the latency variant
   unsigned long long *prof;  // algorithmic bytes moved by profiled kernels (nullptr = off)
 };
 

@@ -2124,7 +2124,7 @@ void pcg_iter_t(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvStat
   const int nt = kLPR * TB;
   if (ev0) hipEventRecord(ev0, s);
   // launches of a few tiles are latency-bound: issue each lane's slots four at a time
-  if (n_tiles <= kWideTiles)
+  if (n_tiles <= L.wide_tiles)
     IPC_LAUNCH((k_spmv<T, true>), n_tiles, nt, s)(W, E, S, tiles, L.inc_off, L.cr_cnt, L.cr_col, v.cr_val, v.u, v.w,
                                                   v.val, L.part_a, prof);
   else
