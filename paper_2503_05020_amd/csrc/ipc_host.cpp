@@ -1039,7 +1039,6 @@ struct World {
     L.g_sorted = g_sorted.p;
     L.bp_stash = bp_stash.p;
     L.stash_n = stash_n;
-    L.wide_tiles = wide_tiles;
   }
 
   void set_prof(int mode) {
@@ -1219,10 +1218,13 @@ public:
   // more are traversed a second time to write them)
   const int stash_n = std::max(1, env_knob("IPC_BP_STASH", 64));
   // PCG product launches over at most this many tiles issue each lane's
-  // slots four at a time, larger ones one at a time (default 0: the one-slot
-  // variant everywhere, at 44 VGPRs against 86, measured faster on the
-  // batched grasp workload also in its latency-bound tails)
-  const int wide_tiles = env_knob("IPC_WIDE_TILES", 0);
+  // slots four at a time, larger ones one at a time.  Default (-1): 64 tiles
+  // in FP64 and none in the mixed path, where the one-slot variant (44 VGPRs
+  // against 86) measured faster also in the latency-bound tails.
+  const int wide_tiles = [] {
+    const char *e = std::getenv("IPC_WIDE_TILES");
+    return (e && e[0]) ? std::max(0, std::atoi(e)) : -1;
+  }();
   // 1: re-lay the batch out with the still-iterating environments once at
   // most half of it iterates (narrow_batch)
   int narrow = env_knob("IPC_NARROW", 1) ? 1 : 0;
@@ -1253,6 +1255,7 @@ public:
       for (int e : fused_h) mx = std::max(mx, its[e]);
       return mx;
     }
+    L.wide_tiles = wide_tiles >= 0 ? wide_tiles : mixed ? 0 : 64;
     ipck::pcg_init(stream, W, envs_d, S, B, L, pending, mixed);
     // an environment's solve stops at the latest in the iteration whose index
     // reaches its cap of 30 n_v + 10 (that iteration only takes the test)
