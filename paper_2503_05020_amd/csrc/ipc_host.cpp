@@ -1039,6 +1039,7 @@ struct World {
     L.g_sorted = g_sorted.p;
     L.bp_stash = bp_stash.p;
     L.stash_n = stash_n;
+    L.bp_coop = bp_coop;
   }
 
   void set_prof(int mode) {
@@ -1217,6 +1218,9 @@ public:
   // broad phase: pairs per query that the counting pass keeps (queries with
   // more are traversed a second time to write them)
   const int stash_n = std::max(1, env_knob("IPC_BP_STASH", 64));
+  // 1: the counting pass walks each query's cells with a group of 8 lanes
+  // (adjacent loads), 0: one lane per query
+  const int bp_coop = env_knob("IPC_BP_COOP", 1) ? 1 : 0;
   // PCG product launches over at most this many tiles issue each lane's
   // slots four at a time, larger ones one at a time.  Default (-1): 64 tiles
   // in FP64 and none in the mixed path, where the one-slot variant (44 VGPRs

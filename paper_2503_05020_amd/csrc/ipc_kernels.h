@@ -63,6 +63,7 @@ struct Lists {
   GridEnt *g_ent, *g_sorted;
   int2 *bp_stash;  // first pairs of each query, from the counting pass
   int stash_n;     // pairs per query the stash holds
+  int bp_coop;     // 1: the counting pass walks each query's cells with a group of lanes
   int wide_tiles;  // PCG products over at most this many tiles use the latency variant
   unsigned long long *prof;  // algorithmic bytes moved by profiled kernels (nullptr = off)
 };

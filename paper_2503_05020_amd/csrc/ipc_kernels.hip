@@ -521,6 +521,139 @@ __global__ void __launch_bounds__(256) k_bp_grid(WorldDev W, const EnvDev *envs,
   }
 }
 
+// Counting pass with kBpGroup lanes per query (launch: kBpGroup blocks per
+// query tile).  The lanes of a group take every kBpGroup-th entry of each
+// bucket (and of the big list or the all-pairs range), so that a group's loads
+// are adjacent; each round's hits are placed by a ballot prefix count in the
+// order one lane walking the entries would find them, and the group's first
+// lane sorts the cell hits.  Same output as k_bp_grid<false>.
+constexpr int kBpGroup = 8;
+__global__ void __launch_bounds__(256) k_bp_coop(WorldDev W, const EnvDev *envs, EnvState S, const Tile *tiles,
+                                                 int *counts, const GridEnt *sorted, const int *boff,
+                                                 const int *bigl, unsigned mask, int2 *stash, int stash_n,
+                                                 int *n_over) {
+  constexpr int G = kBpGroup, QPB = TB / G;
+  Tile t = tiles[blockIdx.x / G];
+  const int qi = (int)(blockIdx.x % G) * QPB + (int)threadIdx.x / G;  // query within the tile
+  if (qi >= t.count) return;  // the whole group
+  const int gl = threadIdx.x % G, gbase = (threadIdx.x & 63) & ~(G - 1);
+  const unsigned long long below = (1ull << gl) - 1;
+  const EnvDev &E = envs[t.env];
+  const int kind = t.rel;
+  const int a = t.start + qi;
+  const int item = E.item_off + (kind == 0 ? (a - E.sv_off) : (E.nsv + a - E.e_off));
+  if (!active_env(S, t.env)) {
+    if (gl == 0) counts[item] = 0;
+    return;
+  }
+  int2 *st = stash + (size_t)item * stash_n;
+  QueryPrim A;
+  const double *bx = (kind == 0 ? W.box_sv : W.box_edge) + 6 * a;
+  for (int k = 0; k < 3; ++k) {
+    A.lo[k] = bx[k];
+    A.hi[k] = bx[3 + k];
+    A.flo[k] = f_down(bx[k]);
+    A.fhi[k] = f_up(bx[3 + k]);
+  }
+  if (kind == 0) {
+    A.v0 = W.sv[a];
+    A.v1 = -1;
+    A.akin = W.kin[A.v0] >= 0;
+  } else {
+    int4 q = W.edge[a];
+    A.v0 = q.x;
+    A.v1 = q.y;
+    A.akin = W.kin[q.x] >= 0 && W.kin[q.y] >= 0;
+  }
+  const double h = E.cell;
+  int cnt = 0;
+  // one round of the group: every lane with a hit stores it at its place
+  auto emit = [&](bool hit, int b) {
+    const unsigned long long m = (__ballot(hit) >> gbase) & ((1ull << G) - 1);
+    if (hit) {
+      const int pos = cnt + __popcll(m & below);
+      if (pos < stash_n) st[pos] = kind == 0 ? make_int2(a, b) : make_int2(~a, b);
+    }
+    cnt += __popcll(m);
+  };
+  int lo[3], hi[3];
+  if (cell_range(bx, h, lo, hi)) {
+    // every candidate of the environment, like an all-pairs test
+    const int bbeg = (kind == 0) ? E.tri_off : a + 1;
+    const int bend = (kind == 0) ? E.tri_off + E.ntri : E.e_off + E.ne;
+    for (int b0 = bbeg; b0 < bend; b0 += G) {
+      const int b = b0 + gl;
+      bool hit = false;
+      if (b < bend) {
+        const double *bb = (kind == 0 ? W.box_tri : W.box_edge) + 6 * b;
+        hit = boxes_overlap(A, bb) && accept_pair(W, kind, A, b);
+      }
+      emit(hit, b);
+    }
+  } else {
+    for (int cx = lo[0]; cx <= hi[0]; ++cx)
+      for (int cy = lo[1]; cy <= hi[1]; ++cy)
+        for (int cz = lo[2]; cz <= hi[2]; ++cz) {
+          const unsigned hh = cell_hash(kind, t.env, cx, cy, cz, mask);
+          const int e0 = boff[hh], e1 = boff[hh + 1];
+          for (int eb = e0; eb < e1; eb += G) {
+            const int e = eb + gl;
+            bool hit = false;
+            int b = 0;
+            if (e < e1) {
+              const GridEnt &en = sorted[e];
+              b = (kind == 0) ? en.code : ~en.code;
+              // outward-rounded float boxes: no overlap here means none in FP64
+              hit = en.cx == cx && en.cy == cy && en.cz == cz && en.env == t.env && (kind == 0) == (en.code >= 0) &&
+                    !(A.flo[0] > en.hi[0] || en.lo[0] > A.fhi[0] || A.flo[1] > en.hi[1] || en.lo[1] > A.fhi[1] ||
+                      A.flo[2] > en.hi[2] || en.lo[2] > A.fhi[2]) &&
+                    !(kind == 1 && b <= a);
+              if (hit) {
+                const double *bb = (kind == 0 ? W.box_tri : W.box_edge) + 6 * b;
+                // owner cell: the one holding the lower corner of the intersection
+                hit = boxes_overlap(A, bb) && (int)floor(fmax(A.lo[0], bb[0]) / h) == cx &&
+                      (int)floor(fmax(A.lo[1], bb[1]) / h) == cy && (int)floor(fmax(A.lo[2], bb[2]) / h) == cz &&
+                      accept_pair(W, kind, A, b);
+              }
+            }
+            emit(hit, b);
+          }
+        }
+    // bucket order depends on atomics: the first lane puts the query's cell
+    // hits in candidate-index order so the output is deterministic
+    if (gl == 0 && cnt <= stash_n)
+      for (int j = 1; j < cnt; ++j) {
+        int2 key = st[j];
+        int m = j - 1;
+        while (m >= 0 && st[m].y > key.y) {
+          st[m + 1] = st[m];
+          --m;
+        }
+        st[m + 1] = key;
+      }
+    const int jb = S.big_beg[t.env], je = S.big_end[t.env];
+    for (int j0 = jb; j0 < je; j0 += G) {
+      const int j = j0 + gl;
+      bool hit = false;
+      int b = 0;
+      if (j < je) {
+        const int code = bigl[j];
+        b = (kind == 0) ? code : ~code;
+        hit = (kind == 0) == (code >= 0) && !(kind == 1 && b <= a);
+        if (hit) {
+          const double *bb = (kind == 0 ? W.box_tri : W.box_edge) + 6 * b;
+          hit = boxes_overlap(A, bb) && accept_pair(W, kind, A, b);
+        }
+      }
+      emit(hit, b);
+    }
+  }
+  if (gl == 0) {
+    counts[item] = cnt;
+    if (cnt > stash_n) atomicAdd(n_over, 1);
+  }
+}
+
 // pairs of the queries that fit the stash, copied to their place in the list
 __global__ void k_bp_gather(const int *counts, const int *offs, const int2 *stash, int stash_n, int n_items,
                             int2 *out) {
@@ -1982,7 +2115,10 @@ void grid_fill(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState
 void bp_grid_count(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L,
                    unsigned nbuckets) {
   IPC_LAUNCH(k_fill_int, 1, 64, s)(L.counter + 4, 1, 0);
-  if (B.n_it)
+  if (B.n_it && L.bp_coop)
+    IPC_LAUNCH(k_bp_coop, B.n_it * kBpGroup, TB, s)(W, E, S, B.itiles, L.counts, L.g_sorted, L.g_boff, L.g_bigl,
+                                                    nbuckets - 1, L.bp_stash, L.stash_n, L.counter + 4);
+  else if (B.n_it)
     IPC_LAUNCH(k_bp_grid<false>, B.n_it, TB, s)(W, E, S, B.itiles, L.counts, nullptr, nullptr, L.g_sorted, L.g_boff,
                                                L.g_bigl, nbuckets - 1, L.bp_stash, L.stash_n, L.counter + 4);
 }
