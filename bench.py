@@ -31,6 +31,12 @@ import os
 import sys
 import time
 
+# At least five hardware queues for this process (read by the HIP runtime
+# when it starts, so before any GPU call): four library lanes plus the null
+# stream; the library's lane count defaults to the queues minus one, at most 4.
+if int(os.environ.get("GPU_MAX_HW_QUEUES", "4") or 4) < 5:
+    os.environ["GPU_MAX_HW_QUEUES"] = "5"
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 

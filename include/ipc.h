@@ -160,9 +160,9 @@ int ipc_prof_read(double *out);
  *   IPC_TUNE_NARROW: 1 = once at most half of a batch still iterates its
  *     Newton loop, the batch is laid out again with those environments only
  *     (default), 0 = never (IPC_NARROW).
- *   IPC_TUNE_LANES: number of lanes per device (1..16, default 3: with the
- *     runtime's null stream that fills the 4 hardware queues a process gets
- *     by default; IPC_LANES).
+ *   IPC_TUNE_LANES: number of lanes per device (1..16; default: the
+ *     process's hardware queues minus the one the runtime's null stream
+ *     holds, at most 4 -- GPU_MAX_HW_QUEUES, 4 unless set, gives 3; IPC_LANES).
  *     A lane is an independent set of device buffers with its own stream;
  *     ipc_create_scene places a scene in the lane with the fewest tets, and
  *     ipc_step_batch steps the scenes of each lane together, the lanes
