@@ -277,6 +277,27 @@ def test_pcg_paths_same_bits(precision):
             assert np.array_equal(a, b), k
 
 
+def test_lane_count_changes_no_result():
+    """The same batch placed on one lane and spread over four lanes (one stream and one host
+    thread each) gives bitwise identical trajectories: every reduction is environment-local."""
+    scs = [S.soft_cube_drop(cells=2, edge=0.04, height=0.002 + 0.001 * i, seed=i) for i in range(6)]
+    before = G.ipc_get_tuning(G.IPC_TUNE_LANES)
+    runs = []
+    try:
+        for lanes in (1, 4):
+            G.ipc_set_tuning(G.IPC_TUNE_LANES, lanes)
+            gs = [G.ipc_create_scene(sc) for sc in scs]
+            rc, infos = G.ipc_step_batch(gs, 5)
+            assert rc == 0, infos
+            runs.append([G.ipc_get_state(g)[0] for g in gs])
+            for g in gs:
+                G.ipc_destroy_scene(g)
+    finally:
+        G.ipc_set_tuning(G.IPC_TUNE_LANES, before)
+    for a, b in zip(runs[0], runs[1]):
+        assert np.array_equal(a, b)
+
+
 def test_alone_equals_batch_bitwise():
     say("alone vs batch")
     scs = [S.soft_cube_drop(cells=2, edge=0.04, height=0.002 + 0.001 * i, seed=i) for i in range(3)]
