@@ -266,10 +266,10 @@ typedef struct {
 #define IPC_FAIL_DEVICE 5 /* the server's worker hit a device error and stopped */
 
 /* Creates a server on the current device.  budget_bytes > 0; max_slots >= 1
- * fixes the slot cap, max_slots = 0 lets the server tune it: starting at 8,
- * while requests are waiting it raises the cap by half after every window of
- * 16 ticks per lane, unless that window's seconds per converged step exceed 1.5x the
- * best window's, in which case it settles on the best window's cap. */
+ * fixes the slot cap, max_slots = 0 lets the server tune it: starting at 8
+ * per lane, while requests are waiting it doubles the cap after every window
+ * of 8 ticks per lane, unless that window's seconds per converged step exceed
+ * 1.5x the best window's, in which case it settles on the best window's cap. */
 int ipc_server_create(int64_t budget_bytes, int32_t max_slots, ipc_server *out);
 /* Validates and copies the scene (as ipc_create_scene; same error codes, and
  * IPC_E_NOMEM if it alone exceeds the budget) and queues it for n_steps >= 1

@@ -1716,12 +1716,12 @@ struct ipc_server_s {
   bool stop = false, dead = false;
   std::string error;
   long long finished = 0, failed = 0, conv_steps = 0, ticks = 0;
-  // slot-cap autotuner (max_slots = 0 at creation): while requests wait,
-  // grow the cap by half after every window of 16 ticks per lane, unless the
-  // window's seconds per converged step exceed 1.5x the best window's: then
-  // settle on the best window's cap.  A tick costs about its slowest
-  // environment's step, so more slots raise throughput until the device
-  // saturates.
+  // slot-cap autotuner (max_slots = 0 at creation): starting from 8 slots per
+  // lane, while requests wait, double the cap after every window of 8 ticks
+  // per lane, unless the window's seconds per converged step exceed 1.5x the
+  // best window's: then settle on the best window's cap.  A tick costs about
+  // its slowest environment's step, so more slots raise throughput until the
+  // device saturates.
   bool auto_slots = false, settled = false;
   int32_t best_cap = 0;
   double best_cost = 0.0, win_t0 = 0.0;
@@ -1757,7 +1757,7 @@ void autotune_tick(ipc_server_s *sv, long long tick_steps) {
   // caller holds sv->mu
   if (!sv->auto_slots || sv->settled) return;
   sv->win_steps += tick_steps;
-  if (++sv->win_ticks < 16 * (long long)sv->lanes.size()) return;
+  if (++sv->win_ticks < 8 * (long long)sv->lanes.size()) return;
   double t = sv->now();
   double cost = (t - sv->win_t0) / std::max<long long>(sv->win_steps, 1);
   if (!sv->queue.empty()) {  // demand above the cap: the cap is what limits
@@ -1769,7 +1769,7 @@ void autotune_tick(ipc_server_s *sv, long long tick_steps) {
         sv->best_cost = cost;
         sv->best_cap = sv->max_slots;
       }
-      sv->max_slots = std::min(1024, sv->max_slots + std::max(1, sv->max_slots / 2));
+      sv->max_slots = std::min(1024, 2 * sv->max_slots);
       sv->cv_work.notify_all();
     }
   }
@@ -2436,7 +2436,7 @@ int ipc_server_create(int64_t budget_bytes, int32_t max_slots, ipc_server *out) 
     sv->running.resize(sv->lanes.size());
     sv->budget = budget_bytes;
     sv->auto_slots = max_slots == 0;
-    sv->max_slots = sv->auto_slots ? 8 : max_slots;
+    sv->max_slots = sv->auto_slots ? 8 * (int32_t)std::max<size_t>(1, sv->lanes.size()) : max_slots;
     sv->best_cap = sv->max_slots;
     for (size_t k = 0; k < sv->lanes.size(); ++k) sv->workers.emplace_back(server_loop, sv.get(), k);
     *out = sv.release();
