@@ -17,10 +17,11 @@
 // cyclic Jacobi.  The linear solve is textbook block-Jacobi PCG (or a dense
 // Cholesky factorisation for tiny systems).
 //
-// Parity status of each routine is listed in the repository's design notes;
-// the whole-trajectory result has no closed form and is pinned only through
-// the invariants (no intersection, J > 0, energy decrease) and the physics
-// cases checked in the tests.
+// Every per-element routine is pinned by the CPU tests (closed forms, finite
+// differences, brute force, special cases).  Parity unpinned: the
+// whole-trajectory result, which has no closed form; it is checked only
+// through the invariants (no intersection, J > 0, energy decrease) and the
+// physics cases in the tests.
 #include "ipc_oracle.h"
 
 #include <algorithm>
