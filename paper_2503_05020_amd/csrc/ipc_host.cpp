@@ -1215,6 +1215,11 @@ public:
   // 1: the next block of PCG iterations is queued before the host polls the
   // previous one (0: after it)
   const int pipeline = env_knob("IPC_PIPELINE", 1) ? 1 : 0;
+  // PCG iterations per block between polls of the pending count
+  const int poll_block = std::max(1, env_knob("IPC_POLL_BLOCK", 8));
+  // the batch is laid out again once at most this percentage of it still
+  // iterates its Newton loop
+  const int narrow_pct = std::min(100, env_knob("IPC_NARROW_PCT", 50));
   // broad phase: pairs per query that the counting pass keeps (queries with
   // more are traversed a second time to write them)
   const int stash_n = std::max(1, env_knob("IPC_BP_STASH", 64));
@@ -1280,7 +1285,7 @@ public:
     // the device does not idle while the host polls.  A block queued after
     // every solve has stopped costs only launches whose tiles exit at once.
     auto launch_block = [&](int slot) {
-      for (int j = 0; j < 8; ++j) {
+      for (int j = 0; j < poll_block; ++j) {
         hipEvent_t e0 = nullptr, e1 = nullptr;
         // every 16th iteration is timed (an event pair costs a few us of
         // dispatch gap, which would slow the solve it measures); with
@@ -1390,7 +1395,7 @@ public:
         std::fprintf(stderr, "[ipc] newton %d: active pairs %d friction %d pcg %lld envs-left %d  %.1f ms\n", it, na,
                      n_fric, pit, still, ms());
       if (still == 0) break;
-      if (narrow && 2 * still <= (int)batch_envs.size()) narrow_batch();
+      if (narrow && 100 * still <= narrow_pct * (int)batch_envs.size()) narrow_batch();
       ipck::al_prepare(stream, W, S, B);
       int ns = broad_phase(W.x, W.p);
       ipck::ccd_init(stream, S, B);
