@@ -1077,6 +1077,14 @@ struct World {
     HC(hipStreamSynchronize(stream));
     return pinned[0];
   }
+  // two device ints read with one synchronisation
+  void read_int2(const int *a, const int *b, int &va, int &vb) {
+    HC(hipMemcpyAsync(pinned, a, sizeof(int), hipMemcpyDeviceToHost, stream));
+    HC(hipMemcpyAsync(pinned + 1, b, sizeof(int), hipMemcpyDeviceToHost, stream));
+    HC(hipStreamSynchronize(stream));
+    va = pinned[0];
+    vb = pinned[1];
+  }
 
   // ---- broad phase: candidate list at x (p == nullptr) or over x -> x+p ----
   int broad_phase(const double *x, const double *p) {
@@ -1100,8 +1108,8 @@ struct World {
     // query: count, scan, write
     ipck::bp_grid_count(stream, W, envs_d, S, B, L, nb);
     ipck::scan_int(stream, L.counts, L.offs, B.n_items, L.scan_tmp);
-    int n = read_int(L.offs + B.n_items);
-    const int n_over = read_int(L.counter + 4);
+    int n = 0, n_over = 0;
+    read_int2(L.offs + B.n_items, L.counter + 4, n, n_over);
     const bool overflow = n_over > 0;
     if (tracing())
       std::fprintf(stderr, "[ipc]   broad phase: %d queries, %d pairs, %d queries over the stash of %d\n", B.n_items, n,
