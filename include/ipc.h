@@ -170,6 +170,20 @@ int ipc_prof_read(double *out);
  *     latency-bound tail overlaps with the others' work.  Applies to scenes
  *     created afterwards.
  * Returns IPC_OK, or IPC_E_ARG for an unknown key or a negative value. */
+/* Further execution settings, read from the environment when a device's
+ * first lane is created (none changes a result):
+ *   IPC_BP_STASH    broad phase: pairs per query kept by the counting pass
+ *                   (default 64); queries with more are traversed again
+ *   IPC_BP_COOP     1 (default): the counting pass walks each query's cells
+ *                   with a group of 8 lanes; 0: one lane per query
+ *   IPC_PIPELINE    1 (default): the next block of PCG iterations is queued
+ *                   before the host polls the previous one
+ *   IPC_POLL_BLOCK  PCG iterations per poll (default 8)
+ *   IPC_NARROW_PCT  the batch is laid out again once at most this percentage
+ *                   of it still iterates its Newton loop (default 50)
+ *   IPC_WIDE_TILES  PCG product launches over at most this many tiles issue
+ *                   four slots per lane and round (default: 64 in FP64, none
+ *                   in the mixed path) */
 #define IPC_TUNE_TAIL_TILES 1
 #define IPC_TUNE_FUSED_PCG 2
 #define IPC_TUNE_NARROW 4
