@@ -115,3 +115,24 @@ def test_server_failure_is_isolated():
             G.ipc_server_poll(srv, ok1)
     finally:
         G.ipc_server_destroy(srv)
+
+
+def test_server_autotuned_slots():
+    """max_slots = 0: the server tunes its slot cap (from 8 per lane); every request still
+    completes with the result of its alone run."""
+    scs = [_cube(i) for i in range(6)]
+    steps = [5, 3, 6, 4, 5, 3]
+    srv = G.ipc_server_create(1 << 30, 0)
+    try:
+        ids = [G.ipc_server_submit(srv, sc, n) for sc, n in zip(scs, steps)]
+        infos = [G.ipc_server_wait(srv, i, 300.0) for i in ids]
+        assert all(inf["status"] == G.IPC_REQ_DONE for inf in infos), infos
+        assert [inf["steps_done"] for inf in infos] == steps
+        for sc, n, i in zip(scs, steps, ids):
+            _, _, p_alone, _ = _run_alone(sc, n)
+            assert np.array_equal(G.ipc_server_result(srv, i)[0], p_alone)
+        st = G.ipc_server_stats(srv)
+        say(st)
+        assert st["slot_cap"] >= 8 and st["finished"] == len(scs)
+    finally:
+        G.ipc_server_destroy(srv)
