@@ -178,7 +178,7 @@ int ipc_prof_read(double *out);
  *                   with a group of 8 lanes; 0: one lane per query
  *   IPC_PIPELINE    1 (default): the next block of PCG iterations is queued
  *                   before the host polls the previous one
- *   IPC_POLL_BLOCK  PCG iterations per poll (default 8)
+ *   IPC_POLL_BLOCK  PCG iterations per poll (default 16)
  *   IPC_NARROW_PCT  the batch is laid out again once at most this percentage
  *                   of it still iterates its Newton loop (default 50)
  *   IPC_WIDE_TILES  PCG product launches over at most this many tiles issue

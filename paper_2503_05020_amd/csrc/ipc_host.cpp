@@ -1224,7 +1224,7 @@ public:
   // previous one (0: after it)
   const int pipeline = env_knob("IPC_PIPELINE", 1) ? 1 : 0;
   // PCG iterations per block between polls of the pending count
-  const int poll_block = std::max(1, env_knob("IPC_POLL_BLOCK", 8));
+  const int poll_block = std::max(1, env_knob("IPC_POLL_BLOCK", 16));
   // the batch is laid out again once at most this percentage of it still
   // iterates its Newton loop
   const int narrow_pct = std::min(100, env_knob("IPC_NARROW_PCT", 50));
@@ -1288,7 +1288,7 @@ public:
     const bool tr = tracing();
     double t_launch = 0.0, t_wait = 0.0;
     auto now = []() { return std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now().time_since_epoch()).count(); };
-    // Blocks of 8 iterations, pipelined: block k+1 is queued before the host
+    // Blocks of poll_block iterations, pipelined: block k+1 is queued before the host
     // waits for the count of environments still iterating after block k, so
     // the device does not idle while the host polls.  A block queued after
     // every solve has stopped costs only launches whose tiles exit at once.
