@@ -182,8 +182,8 @@ int ipc_prof_read(double *out);
  *   IPC_NARROW_PCT  the batch is laid out again once at most this percentage
  *                   of it still iterates its Newton loop (default 50)
  *   IPC_WIDE_TILES  PCG product launches over at most this many tiles issue
- *                   four slots per lane and round (default: 64 in FP64, none
- *                   in the mixed path) */
+ *                   four slots per lane and round (default: every launch in
+ *                   FP64, none in the mixed path) */
 #define IPC_TUNE_TAIL_TILES 1
 #define IPC_TUNE_FUSED_PCG 2
 #define IPC_TUNE_NARROW 4

@@ -1235,9 +1235,9 @@ public:
   // (adjacent loads), 0: one lane per query
   const int bp_coop = env_knob("IPC_BP_COOP", 1) ? 1 : 0;
   // PCG product launches over at most this many tiles issue each lane's
-  // slots four at a time, larger ones one at a time.  Default (-1): 64 tiles
-  // in FP64 and none in the mixed path, where the one-slot variant (44 VGPRs
-  // against 86) measured faster also in the latency-bound tails.
+  // slots four at a time, larger ones one at a time.  Default (-1): every
+  // launch in FP64 and none in the mixed path, where the one-slot variant (44
+  // VGPRs against 86) measured faster also in the latency-bound tails.
   const int wide_tiles = [] {
     const char *e = std::getenv("IPC_WIDE_TILES");
     return (e && e[0]) ? std::max(0, std::atoi(e)) : -1;
@@ -1272,7 +1272,7 @@ public:
       for (int e : fused_h) mx = std::max(mx, its[e]);
       return mx;
     }
-    L.wide_tiles = wide_tiles >= 0 ? wide_tiles : mixed ? 0 : 64;
+    L.wide_tiles = wide_tiles >= 0 ? wide_tiles : mixed ? 0 : 1 << 30;
     ipck::pcg_init(stream, W, envs_d, S, B, L, pending, mixed);
     // an environment's solve stops at the latest in the iteration whose index
     // reaches its cap of 30 n_v + 10 (that iteration only takes the test)
