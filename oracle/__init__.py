@@ -97,6 +97,10 @@ def lib():
         L.ipco_accd.argtypes = [C.c_int, _dp, _dp, C.c_double]
         L.ipco_accd.restype = C.c_double
         L.ipco_friction_f0.argtypes = [C.c_double, C.c_double, _dp]
+        L.ipco_friction_elem.argtypes = [_dp, _dp, _dp, _dp, C.c_double, C.c_double, C.c_double, _dp, _dp, _dp]
+        L.ipco_iter_log.argtypes = [C.c_void_p, _dp, C.c_int64]
+        L.ipco_iter_log.restype = C.c_int64
+        L.ipco_debug_ls_offset.argtypes = [C.c_void_p, C.c_double]
         _lib = L
     return _lib
 
@@ -242,6 +246,17 @@ class Scene:
     def ccd_bound(self, x, p):
         return lib().ipco_ccd_bound(self.h, _d(_f64(x)), _d(_f64(p)))
 
+    def iter_log(self):
+        """Rows (Phi before, Phi accepted, step size, halvings), one per accepted Newton iterate of the last step."""
+        n = lib().ipco_iter_log(self.h, None, 0)
+        out = np.zeros((max(n, 1), 4))
+        lib().ipco_iter_log(self.h, _d(out), n)
+        return out[:n]
+
+    def debug_ls_offset(self, delta):
+        """Test-only planted fault: delta is added to every line-search trial energy."""
+        lib().ipco_debug_ls_offset(self.h, float(delta))
+
     def friction_pairs(self):
         n = lib().ipco_friction_pairs(self.h, None, None, None, None, 0)
         v = np.zeros((max(n, 1), 4), np.int32)
@@ -304,3 +319,12 @@ def friction_f0(y, eps):
     out = np.zeros(3)
     lib().ipco_friction_f0(y, eps, _d(out))
     return out
+
+
+def friction_elem(x12, xn12, w4, n3, lam, mu, eps):
+    e = C.c_double()
+    g = np.zeros(12)
+    H = np.zeros(144)
+    lib().ipco_friction_elem(_d(_f64(x12).reshape(-1)), _d(_f64(xn12).reshape(-1)), _d(_f64(w4)), _d(_f64(n3)),
+                             lam, mu, eps, C.byref(e), _d(g), _d(H))
+    return e.value, g, H.reshape(12, 12)

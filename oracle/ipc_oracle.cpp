@@ -599,6 +599,52 @@ struct FricPair {
   double lambda;
 };
 
+// One lagged friction element: energy mu*lambda*f0(|u|) with
+// u = (I - n n^T) sum_i w_i (x_i - x^n_i), its gradient and its Hessian.
+// With y = |u|, the gradient is mu*lambda*w_i*(f1(y)/y)*u for vertex i and the
+// Hessian block (i, j) is mu*lambda*w_i*w_j*[a (I - n n^T) + c u u^T]:
+//   y < eps:  a = f1/y = 2/eps - y/eps^2,  c = (d/dy)(f1/y)/y = -1/(eps^2 y)  (c = 0 at y = 0)
+//   y >= eps: a = 1/y,                     c = -1/y^3
+// (the exact second derivatives of f0(|u|); a + c y^2 >= 0 in both branches,
+// so the matrix is PSD without projection).
+double friction_elem(const double x12[12], const double xn12[12], const double w[4], const double n[3],
+                     double lambda, double mu, double eps, double *g, double *H) {
+  double u[3] = {0, 0, 0};
+  for (int i = 0; i < 4; ++i)
+    for (int k = 0; k < 3; ++k) u[k] += w[i] * (x12[3 * i + k] - xn12[3 * i + k]);
+  double un = u[0] * n[0] + u[1] * n[1] + u[2] * n[2];
+  for (int k = 0; k < 3; ++k) u[k] -= un * n[k];
+  double y = std::sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+  double f0[3];
+  friction_f0(y, eps, f0);
+  double E = mu * lambda * f0[0];
+  if (!g && !H) return E;
+  double f1y, a, c;
+  if (y < eps) {
+    f1y = 2.0 / eps - y / (eps * eps);
+    a = f1y;
+    c = (y > 0.0) ? -1.0 / (eps * eps * y) : 0.0;
+  } else {
+    f1y = 1.0 / y;
+    a = 1.0 / y;
+    c = -1.0 / (y * y * y);
+  }
+  double sc = mu * lambda;
+  if (g)
+    for (int i = 0; i < 4; ++i)
+      for (int k = 0; k < 3; ++k) g[3 * i + k] = sc * w[i] * f1y * u[k];
+  if (H) {
+    double K[9];
+    for (int r = 0; r < 3; ++r)
+      for (int q = 0; q < 3; ++q) K[r * 3 + q] = a * ((r == q ? 1.0 : 0.0) - n[r] * n[q]) + c * u[r] * u[q];
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j)
+        for (int r = 0; r < 3; ++r)
+          for (int q = 0; q < 3; ++q) H[(3 * i + r) * 12 + 3 * j + q] = sc * w[i] * w[j] * K[r * 3 + q];
+  }
+  return E;
+}
+
 // Closest-point weights of a classified pair: sum_i w_i x_i is the vector
 // from the closest point of the second primitive to that of the first.
 void closest_weights(int kind, int type, const double *x, double w[4]) {
@@ -721,6 +767,11 @@ struct Scene {
   bool al = false;
   double kA = 0.0, w_al = 0.0, viol_prev = 0.0;
   std::vector<double> Lam;
+  // Newton record of the last step: per accepted iterate (Phi before, Phi
+  // after, step size, halvings)
+  std::vector<double> iter_log;
+  // test-only planted fault: added to every line-search trial energy
+  double debug_ls_offset = 0.0;
 };
 
 bool is_kin(const Scene &s, int i) { return s.kin[i] >= 0; }
@@ -1069,15 +1120,10 @@ double energy(const Scene &s, const std::vector<double> &x) {
   }
   double Ef = 0.0, eps = s.eps_v * s.dt;
   for (const FricPair &f : s.fric) {
-    double u[3] = {0, 0, 0};
-    for (int i = 0; i < 4; ++i)
-      for (int k = 0; k < 3; ++k) u[k] += f.w[i] * (x[3 * f.v[i] + k] - s.xn[3 * f.v[i] + k]);
-    double un = u[0] * f.n[0] + u[1] * f.n[1] + u[2] * f.n[2];
-    for (int k = 0; k < 3; ++k) u[k] -= un * f.n[k];
-    double y = std::sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-    double f0[3];
-    friction_f0(y, eps, f0);
-    Ef += s.mu * f.lambda * f0[0];
+    double xx[12], xxn[12];
+    gather12(x, f.v, xx);
+    gather12(s.xn, f.v, xxn);
+    Ef += friction_elem(xx, xxn, f.w, f.n, f.lambda, s.mu, eps, nullptr, nullptr);
   }
   double E = Ein + Eel + Eb + Ef;
   return std::isfinite(E) ? E : kInf;
@@ -1160,35 +1206,10 @@ bool grad_hess(const Scene &s, const std::vector<double> &x, std::vector<double>
   }
   double eps = s.eps_v * s.dt;
   for (const FricPair &f : s.fric) {
-    double u[3] = {0, 0, 0};
-    for (int i = 0; i < 4; ++i)
-      for (int k = 0; k < 3; ++k) u[k] += f.w[i] * (x[3 * f.v[i] + k] - s.xn[3 * f.v[i] + k]);
-    double un = u[0] * f.n[0] + u[1] * f.n[1] + u[2] * f.n[2];
-    for (int k = 0; k < 3; ++k) u[k] -= un * f.n[k];
-    double y = std::sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-    // f1(y)/y and the Hessian coefficients a (on the tangent projector) and
-    // c (on u u^T); both branches are the exact derivatives of f0.
-    double f1y, a, c;
-    if (y < eps) {
-      f1y = 2.0 / eps - y / (eps * eps);
-      a = f1y;
-      c = (y > 0.0) ? -1.0 / (eps * eps * y) : 0.0;
-    } else {
-      f1y = 1.0 / y;
-      a = 1.0 / y;
-      c = -1.0 / (y * y * y);
-    }
-    double sc = s.mu * f.lambda;
-    double K[9];
-    for (int r = 0; r < 3; ++r)
-      for (int q = 0; q < 3; ++q) K[r * 3 + q] = a * ((r == q ? 1.0 : 0.0) - f.n[r] * f.n[q]) + c * u[r] * u[q];
-    double g[12], H[144];
-    for (int i = 0; i < 4; ++i)
-      for (int k = 0; k < 3; ++k) g[3 * i + k] = sc * f.w[i] * f1y * u[k];
-    for (int i = 0; i < 4; ++i)
-      for (int j = 0; j < 4; ++j)
-        for (int r = 0; r < 3; ++r)
-          for (int q = 0; q < 3; ++q) H[(3 * i + r) * 12 + 3 * j + q] = sc * f.w[i] * f.w[j] * K[r * 3 + q];
+    double xx[12], xxn[12], g[12], H[144];
+    gather12(x, f.v, xx);
+    gather12(s.xn, f.v, xxn);
+    friction_elem(xx, xxn, f.w, f.n, f.lambda, s.mu, eps, g, H);
     add_element(s, f.v, g, H, G, Gabs, M);
   }
   for (double gv : G)
@@ -1483,6 +1504,7 @@ int step_one(Scene &s, ipco_info *info) {
   double tolh = s.tol * s.dt;
   bool converged = false;
   int it = 0;
+  s.iter_log.clear();
   std::vector<double> p, xt(3 * s.nv);
   for (; it < s.maxit; ++it) {
     long pit = 0;
@@ -1530,8 +1552,11 @@ int step_one(Scene &s, ipco_info *info) {
     int halvings = 0;
     for (;;) {
       for (int i = 0; i < 3 * s.nv; ++i) xt[i] = x[i] + alpha * p[i];
-      double E1 = energy(s, xt);
-      if (E1 <= E0) break;
+      double E1 = energy(s, xt) + s.debug_ls_offset;
+      if (E1 <= E0) {
+        s.iter_log.insert(s.iter_log.end(), {E0, E1, alpha, (double)halvings});
+        break;
+      }
       alpha *= 0.5;
       if (++halvings > 40) {
         s.failed = true;
@@ -1836,6 +1861,25 @@ int ipco_psd_project(int n, double *A) {
 }
 
 double ipco_accd(int kind, const double *x12, const double *p12, double s) { return accd(kind, x12, p12, s); }
+
+int64_t ipco_iter_log(void *h, double *out, int64_t cap) {
+  Scene *s = static_cast<Scene *>(h);
+  int64_t n = (int64_t)s->iter_log.size() / 4;
+  for (int64_t i = 0; i < 4 * std::min(n, cap); ++i) out[i] = s->iter_log[i];
+  return n;
+}
+
+int ipco_debug_ls_offset(void *h, double delta) {
+  static_cast<Scene *>(h)->debug_ls_offset = delta;
+  return OK;
+}
+
+int ipco_friction_elem(const double *x12, const double *xn12, const double *w4, const double *n3, double lambda,
+                       double mu, double eps, double *energy, double *g12, double *H144) {
+  double e = friction_elem(x12, xn12, w4, n3, lambda, mu, eps, g12, H144);
+  if (energy) *energy = e;
+  return OK;
+}
 
 int ipco_friction_f0(double y, double eps, double *out3) {
   friction_f0(y, eps, out3);

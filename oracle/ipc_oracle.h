@@ -83,6 +83,13 @@ int ipco_tet_elastic(const double *X12, const double *x12, double E, double nu, 
 int ipco_psd_project(int n, double *A);
 double ipco_accd(int kind, const double *x12, const double *p12, double s);
 int ipco_friction_f0(double y, double eps, double *out3);
+/* One lagged friction element (energy mu*lambda*f0(|u|), gradient, Hessian). */
+int ipco_friction_elem(const double *x12, const double *xn12, const double *w4, const double *n3, double lambda,
+                       double mu, double eps, double *energy, double *g12, double *H144);
+/* Newton record of the last step: rows (Phi before, Phi accepted, alpha, halvings). */
+int64_t ipco_iter_log(void *s, double *out, int64_t cap);
+/* Test-only planted fault: delta added to every line-search trial energy. */
+int ipco_debug_ls_offset(void *s, double delta);
 
 #ifdef __cplusplus
 }

@@ -408,7 +408,7 @@ def test_candidates_match_brute_force_on_tiny_scene():
     act, d2 = s.active(x)
     assert len(act) > 0 and np.all(d2 < sc["dhat"] ** 2)
     for row in act:
-        assert tuple(row[:5]) in got or True
+        assert tuple(row[:5]) in got
 
 
 def test_active_set_is_exactly_pairs_within_dhat():
