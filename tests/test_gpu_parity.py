@@ -231,7 +231,7 @@ def test_cube_drop_trajectory_parity():
 
 def test_augmented_lagrangian_press_parity():
     """Plate pressed onto a block faster than the gap allows: the augmented-Lagrangian Dirichlet mode
-    (Sec. III-B) must end each step with the plate on target and match the oracle's trajectory."""
+    (the reading taken for enforcing prescribed finger motion, Sec. III-D; the paper names no method) must end each step with the plate on target and match the oracle's trajectory."""
     sc = S.press_block(steps=4)
     g = G.ipc_create_scene(sc, pcg_rel_tol=1e-8)
     o = O.Scene(sc, pcg_rel_tol=1e-8)
