@@ -29,6 +29,8 @@ class Desc(C.Structure):
         ("dt", C.c_double), ("dhat", C.c_double), ("kappa", C.c_double), ("mu", C.c_double),
         ("eps_v", C.c_double), ("newton_tol", C.c_double), ("newton_max_iter", C.c_int32),
         ("pcg_rel_tol", C.c_double), ("linear_solver", C.c_int32),
+        ("newton_rel_tol", C.c_double), ("friction_iters", C.c_int32), ("inversion_filter", C.c_int32),
+        ("adaptive_kappa", C.c_int32),
     ]
 
 
@@ -37,7 +39,7 @@ class Info(C.Structure):
         ("steps_done", C.c_int32), ("status", C.c_int32), ("fail_reason", C.c_int32),
         ("newton_iters", C.c_int32), ("max_newton_iters", C.c_int32), ("ls_halvings", C.c_int32),
         ("pcg_iters", C.c_int64), ("n_active_last", C.c_int64), ("min_dist_last", C.c_double),
-        ("energy_last", C.c_double),
+        ("energy_last", C.c_double), ("kappa_last", C.c_double),
     ]
 
     def as_dict(self):
@@ -101,6 +103,12 @@ def lib():
         L.ipco_iter_log.argtypes = [C.c_void_p, _dp, C.c_int64]
         L.ipco_iter_log.restype = C.c_int64
         L.ipco_debug_ls_offset.argtypes = [C.c_void_p, C.c_double]
+        L.ipco_tet_first_root.argtypes = [_dp, _dp, C.c_double, _dp]
+        L.ipco_tet_first_root.restype = C.c_double
+        L.ipco_inversion_bound.argtypes = [C.c_void_p, _dp, _dp]
+        L.ipco_inversion_bound.restype = C.c_double
+        L.ipco_kappa.argtypes = [C.c_void_p]
+        L.ipco_kappa.restype = C.c_double
         _lib = L
     return _lib
 
@@ -157,7 +165,8 @@ class Scene:
                  _d(k["nu"]), _d(k["rho"]), len(k["tris"]) // 3, _i(k["tris"]), _i(k["kin"]),
                  motion.shape[1], motion.shape[0], _d(k["motion"]), _d(k["gravity"]),
                  p["dt"], p["dhat"], p["kappa"], p["mu"], p["eps_v"], p["newton_tol"], int(p["newton_max_iter"]),
-                 pcg_rel_tol, linear_solver)
+                 pcg_rel_tol, linear_solver, float(p.get("newton_rel_tol", 0.0)), int(p.get("friction_iters", 1)),
+                 int(p.get("inversion_filter", 0)), int(p.get("adaptive_kappa", 0)))
         h = C.c_void_p()
         _check(lib().ipco_create(C.byref(d), C.byref(h)))
         self.h = h
@@ -253,6 +262,13 @@ class Scene:
         lib().ipco_iter_log(self.h, _d(out), n)
         return out[:n]
 
+    def inversion_bound(self, x, p):
+        return lib().ipco_inversion_bound(self.h, _d(_f64(x)), _d(_f64(p)))
+
+    @property
+    def kappa(self):
+        return lib().ipco_kappa(self.h)
+
     def debug_ls_offset(self, delta):
         """Test-only planted fault: delta is added to every line-search trial energy."""
         lib().ipco_debug_ls_offset(self.h, float(delta))
@@ -328,3 +344,10 @@ def friction_elem(x12, xn12, w4, n3, lam, mu, eps):
     lib().ipco_friction_elem(_d(_f64(x12).reshape(-1)), _d(_f64(xn12).reshape(-1)), _d(_f64(w4)), _d(_f64(n3)),
                              lam, mu, eps, C.byref(e), _d(g), _d(H))
     return e.value, g, H.reshape(12, 12)
+
+
+def tet_first_root(x12, p12, tmax=1.25):
+    """First t in (0, tmax] with det(Ds(x + t p)) <= 0 (inf if none), and the cubic's coefficients."""
+    k = np.zeros(4)
+    t = lib().ipco_tet_first_root(_d(_f64(x12).reshape(-1)), _d(_f64(p12).reshape(-1)), tmax, _d(k))
+    return t, k

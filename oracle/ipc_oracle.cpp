@@ -751,6 +751,12 @@ struct Scene {
   std::vector<double> motion, gravity;
   double dt, dhat, kappa, mu, eps_v, tol, pcg_tol;
   int maxit, solver;
+  // solver variants (off by default)
+  int friction_iters = 1;     // lagged friction updates per step
+  bool inv_filter = false;    // per-tet det F root bounds the line search
+  bool adaptive_kappa = false;
+  double kappa0 = 0.0;        // kappa as given (adaptive kappa stays in [kappa0, 100 kappa0])
+  double dmin_prev = 0.0;     // least active-pair distance at the previous Newton iterate
   std::vector<std::array<int, 3>> stri;
   std::vector<std::array<int, 2>> sedge;
   std::vector<int> svert;
@@ -934,9 +940,18 @@ int build_scene(const ipco_desc *d, Scene **out) {
     delete s;
     return fail(E_ARG, "non-finite motion");
   }
+  if (d->newton_rel_tol < 0 || d->friction_iters < 0 || d->inversion_filter < 0 || d->adaptive_kappa < 0) {
+    delete s;
+    return fail(E_ARG, "bad solver variant");
+  }
   s->dt = d->dt;
   s->dhat = d->dhat;
   s->kappa = d->kappa;
+  s->kappa0 = d->kappa;
+  s->dmin_prev = kInf;
+  s->friction_iters = std::max(1, (int)d->friction_iters);
+  s->inv_filter = d->inversion_filter != 0;
+  s->adaptive_kappa = d->adaptive_kappa != 0;
   s->mu = d->mu;
   s->eps_v = d->eps_v;
   s->tol = d->newton_tol;
@@ -985,6 +1000,20 @@ int build_scene(const ipco_desc *d, Scene **out) {
     }
   }
   s->mbar = nfree > 0 ? s->mbar / nfree : 1.0;
+  if (d->newton_rel_tol > 0) {
+    // the paper's relative Newton tolerance (Sec. III-D), read as a fraction
+    // of the free vertices' bounding-box diagonal per time step
+    double lo[3] = {kInf, kInf, kInf}, hi[3] = {-kInf, -kInf, -kInf};
+    for (int i = 0; i < s->nv; ++i)
+      if (!is_kin(*s, i))
+        for (int k = 0; k < 3; ++k) {
+          lo[k] = std::min(lo[k], s->x[3 * i + k]);
+          hi[k] = std::max(hi[k], s->x[3 * i + k]);
+        }
+    double L2 = 0.0;
+    for (int k = 0; k < 3; ++k) L2 += nfree > 0 ? (hi[k] - lo[k]) * (hi[k] - lo[k]) : 0.0;
+    s->tol = d->newton_rel_tol * std::sqrt(L2);
+  }
   // Surface: tet faces used by exactly one tet, plus the kinematic triangles.
   // Canonical form: triangle vertices ascending, list sorted; edges (min,max).
   std::map<std::array<int, 3>, int> faces;
@@ -1381,6 +1410,91 @@ double ccd_bound(const Scene &s, const std::vector<double> &x, const std::vector
   return alpha;
 }
 
+// ---------------------------------------------------------------------------
+// Inversion filter (a step-size filter that keeps every tet inversion-free
+// along the search line, Sec. II-C).  Along x + t p the volume factor of a
+// tet, J(t) = det(Ds(x) + t Ds(p)), is a cubic in t with J(0) > 0: expanding
+// the determinant column by column,
+//   J(t) = k0 + k1 t + k2 t^2 + k3 t^3,
+//   k0 = |a0 a1 a2|,  k1 = |b0 a1 a2| + |a0 b1 a2| + |a0 a1 b2|,
+//   k2 = |a0 b1 b2| + |b0 a1 b2| + |b0 b1 a2|,  k3 = |b0 b1 b2|,
+// with a_c, b_c the columns of Ds(x), Ds(p).  Its first positive root t*
+// bounds the step: every tet keeps J > 0 on [0, 0.8 t*] (the factor 0.8 is
+// a reading; the paper gives no constant).
+// ---------------------------------------------------------------------------
+double det_cols(const double *c0, const double *c1, const double *c2) {
+  return c0[0] * (c1[1] * c2[2] - c1[2] * c2[1]) - c1[0] * (c0[1] * c2[2] - c0[2] * c2[1]) +
+         c2[0] * (c0[1] * c1[2] - c0[2] * c1[1]);
+}
+
+void det_cubic(const double *x12, const double *p12, double k[4]) {
+  double a[3][3], b[3][3];
+  for (int c = 0; c < 3; ++c)
+    for (int r = 0; r < 3; ++r) {
+      a[c][r] = x12[3 * (c + 1) + r] - x12[r];
+      b[c][r] = p12[3 * (c + 1) + r] - p12[r];
+    }
+  k[0] = det_cols(a[0], a[1], a[2]);
+  k[1] = det_cols(b[0], a[1], a[2]) + det_cols(a[0], b[1], a[2]) + det_cols(a[0], a[1], b[2]);
+  k[2] = det_cols(a[0], b[1], b[2]) + det_cols(b[0], a[1], b[2]) + det_cols(b[0], b[1], a[2]);
+  k[3] = det_cols(b[0], b[1], b[2]);
+}
+
+double cubic_at(const double k[4], double t) { return ((k[3] * t + k[2]) * t + k[1]) * t + k[0]; }
+
+// First t in (0, tmax] with J(t) <= 0 (+inf if J stays positive there).  The
+// stationary points of J (roots of J' = k1 + 2 k2 t + 3 k3 t^2) split
+// [0, tmax] into pieces on which J is monotone; the first piece whose right
+// end has J <= 0 holds the root, found by bisection.
+double first_root(const double k[4], double tmax) {
+  if (!(k[0] > 0.0)) return 0.0;
+  std::vector<double> cut = {0.0};
+  double A = 3.0 * k[3], B = 2.0 * k[2], C = k[1];
+  if (A != 0.0) {
+    double disc = B * B - 4.0 * A * C;
+    if (disc >= 0.0) {
+      double sq = std::sqrt(disc);
+      double r1 = (-B - sq) / (2.0 * A), r2 = (-B + sq) / (2.0 * A);
+      for (double r : {std::min(r1, r2), std::max(r1, r2)})
+        if (r > 0.0 && r < tmax) cut.push_back(r);
+    }
+  } else if (B != 0.0) {
+    double r = -C / B;
+    if (r > 0.0 && r < tmax) cut.push_back(r);
+  }
+  cut.push_back(tmax);
+  for (size_t i = 0; i + 1 < cut.size(); ++i) {
+    double lo = cut[i], hi = cut[i + 1];
+    if (cubic_at(k, hi) > 0.0) continue;
+    // J(lo) > 0 >= J(hi): bisect to the interval's resolution
+    for (int it = 0; it < 200 && hi - lo > 1e-15 * hi; ++it) {
+      double mid = 0.5 * (lo + hi);
+      if (cubic_at(k, mid) > 0.0)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    return hi;
+  }
+  return kInf;
+}
+
+constexpr double kInvSafety = 0.8;
+
+// min over tets of 0.8 t* (capped at 1), the inversion filter's step bound
+double inversion_bound(const Scene &s, const std::vector<double> &x, const std::vector<double> &p) {
+  double alpha = 1.0;
+  for (int e = 0; e < s.nt; ++e) {
+    double xe[12], pe[12], k[4];
+    gather12(x, &s.tet[4 * e], xe);
+    gather12(p, &s.tet[4 * e], pe);
+    det_cubic(xe, pe, k);
+    double t = first_root(k, 1.0 / kInvSafety);
+    alpha = std::min(alpha, kInvSafety * t);
+  }
+  return alpha;
+}
+
 bool all_tets_positive(const Scene &s, const std::vector<double> &x) {
   for (int e = 0; e < s.nt; ++e) {
     double xe[12], Ds[9], F[9];
@@ -1390,6 +1504,38 @@ bool all_tets_positive(const Scene &s, const std::vector<double> &x) {
     if (!(det3<double>(F) > 0.0)) return false;
   }
   return true;
+}
+
+// Lagged friction data (lambda, n, closest-point weights) of the active
+// pairs at xl; the tangential displacement is always measured from x^n.
+// The first lag of a step is taken at x^n; with friction_iters > 1 it is
+// taken again at each converged iterate and the step is solved again.
+void lag_friction(Scene &s, const std::vector<double> &xl) {
+  s.fric.clear();
+  std::vector<Pair> cand = candidates(s, xl, nullptr);
+  for (const ActivePair &a : active_set(s, xl, cand)) {
+    double xx[12];
+    gather12(xl, a.p.v, xx);
+    FricPair f;
+    std::copy(a.p.v, a.p.v + 4, f.v);
+    closest_weights(a.p.kind, a.type, xx, f.w);
+    double dv[3] = {0, 0, 0};
+    for (int i = 0; i < 4; ++i)
+      for (int k = 0; k < 3; ++k) dv[k] += f.w[i] * xx[3 * i + k];
+    double dn = std::sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+    for (int k = 0; k < 3; ++k) f.n[k] = dv[k] / dn;
+    double d = std::sqrt(a.d2), b[3];
+    barrier_scalar(d, s.dhat, b);
+    double e = 1.0;
+    if (a.p.kind == 1) {
+      V3 ea = sub(ld(xx + 3), ld(xx)), eb = sub(ld(xx + 9), ld(xx + 6));
+      V3 c3 = cross(ea, eb);
+      double c = dot(c3, c3), ex = eps_cross(s, a.p);
+      if (c < ex) e = (c / ex) * (2.0 - c / ex);
+    }
+    f.lambda = -s.kappa * e * b[1];
+    if (f.lambda > 0.0 && s.mu > 0.0) s.fric.push_back(f);
+  }
 }
 
 // Kinematic targets, predicted positions, lagged friction and the direct
@@ -1414,31 +1560,7 @@ int begin_step(Scene &s, std::vector<double> &x0) {
     }
   }
   // lagged friction set at x^n
-  s.fric.clear();
-  std::vector<Pair> cand = candidates(s, s.xn, nullptr);
-  for (const ActivePair &a : active_set(s, s.xn, cand)) {
-    double xx[12];
-    gather12(s.xn, a.p.v, xx);
-    FricPair f;
-    std::copy(a.p.v, a.p.v + 4, f.v);
-    closest_weights(a.p.kind, a.type, xx, f.w);
-    double dv[3] = {0, 0, 0};
-    for (int i = 0; i < 4; ++i)
-      for (int k = 0; k < 3; ++k) dv[k] += f.w[i] * xx[3 * i + k];
-    double dn = std::sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
-    for (int k = 0; k < 3; ++k) f.n[k] = dv[k] / dn;
-    double d = std::sqrt(a.d2), b[3];
-    barrier_scalar(d, s.dhat, b);
-    double e = 1.0;
-    if (a.p.kind == 1) {
-      V3 ea = sub(ld(xx + 3), ld(xx)), eb = sub(ld(xx + 9), ld(xx + 6));
-      V3 c3 = cross(ea, eb);
-      double c = dot(c3, c3), ex = eps_cross(s, a.p);
-      if (c < ex) e = (c / ex) * (2.0 - c / ex);
-    }
-    f.lambda = -s.kappa * e * b[1];
-    if (f.lambda > 0.0 && s.mu > 0.0) s.fric.push_back(f);
-  }
+  lag_friction(s, s.xn);
   // direct Dirichlet move if CCD-safe and inversion-free
   std::vector<double> y = s.xn, dp(3 * s.nv, 0.0);
   bool any = false;
@@ -1475,6 +1597,8 @@ double dbc_violation(const Scene &s, const std::vector<double> &x) {
   return v;
 }
 
+// Contact statistics of an accepted iterate: the number of active pairs
+// (d^2 < dhat^2) and the least distance among them (+inf if there are none).
 void min_dist(const Scene &s, const std::vector<double> &x, double *dmin, long *nact) {
   std::vector<Pair> cand = candidates(s, x, nullptr);
   double m = kInf;
@@ -1486,41 +1610,46 @@ void min_dist(const Scene &s, const std::vector<double> &x, double *dmin, long *
       pt_classify(xx, &d2);
     else
       ee_classify(xx, &d2);
-    m = std::min(m, d2);
-    if (d2 < s.dhat * s.dhat) ++na;
+    if (d2 < s.dhat * s.dhat) {
+      m = std::min(m, d2);
+      ++na;
+    }
   }
   *dmin = std::sqrt(m);
   *nact = na;
 }
 
-int step_one(Scene &s, ipco_info *info) {
-  std::vector<double> x;
-  int fr = begin_step(s, x);
-  if (fr != FAIL_NONE) {
-    s.failed = true;
-    s.fail_reason = fr;
-    return E_FAILED;
-  }
+// Adaptive barrier stiffness (variant): at each Newton iterate, if the least
+// active-pair distance is below 1e-2 dhat and smaller than at the previous
+// iterate, kappa doubles, up to 100 times its given value (a reading of IPC's
+// adaptive stiffness; the paper fixes kappa = 3e6, Sec. III-D).
+void adapt_kappa(Scene &s, const std::vector<double> &x) {
+  double d;
+  long na;
+  min_dist(s, x, &d, &na);
+  if (d < 1e-2 * s.dhat && d < s.dmin_prev) s.kappa = std::min(2.0 * s.kappa, 100.0 * s.kappa0);
+  s.dmin_prev = d;
+}
+
+// One projected-Newton solve from x (Sec. II-C): direction from the
+// PSD-projected Hessian, stop on |p|_inf <= tol dt, CCD (and optionally
+// inversion) step bound, backtracking line search on Phi.  Returns FAIL_NONE
+// when converged, else the failure reason; *n_dirs counts the directions.
+int newton_solve(Scene &s, std::vector<double> &x, ipco_info *info, int *n_dirs) {
   double tolh = s.tol * s.dt;
-  bool converged = false;
-  int it = 0;
-  s.iter_log.clear();
   std::vector<double> p, xt(3 * s.nv);
+  int it = 0;
+  *n_dirs = 0;
   for (; it < s.maxit; ++it) {
+    if (s.adaptive_kappa) adapt_kappa(s, x);
     long pit = 0;
-    if (!newton_dir(s, x, p, &pit)) {
-      s.failed = true;
-      s.fail_reason = FAIL_NONFINITE;
-      return E_FAILED;
-    }
+    if (!newton_dir(s, x, p, &pit)) return FAIL_NONFINITE;
+    *n_dirs = it + 1;
     if (info) info->pcg_iters += pit;
     double pinf = 0.0;
     for (double v : p) pinf = std::max(pinf, std::fabs(v));
     if (pinf <= tolh) {
-      if (!s.al) {
-        converged = true;
-        break;
-      }
+      if (!s.al) return FAIL_NONE;
       // AL mode: the inner problem converged.  Snap to the targets once they
       // are within 1e-2 dhat and the move is CCD-safe; otherwise update the
       // multipliers (and double kA unless the violation fell tenfold).
@@ -1548,6 +1677,7 @@ int step_one(Scene &s, ipco_info *info) {
       continue;
     }
     double alpha = ccd_bound(s, x, p);
+    if (s.inv_filter) alpha = std::min(alpha, inversion_bound(s, x, p));
     double E0 = energy(s, x);
     int halvings = 0;
     for (;;) {
@@ -1558,22 +1688,34 @@ int step_one(Scene &s, ipco_info *info) {
         break;
       }
       alpha *= 0.5;
-      if (++halvings > 40) {
-        s.failed = true;
-        s.fail_reason = FAIL_LS;
-        return E_FAILED;
-      }
+      if (++halvings > 40) return FAIL_LS;
     }
     if (info) info->ls_halvings += halvings;
     x = xt;
   }
-  if (info) {
-    info->newton_iters += it + (converged ? 1 : 0);
-    info->max_newton_iters = std::max(info->max_newton_iters, it + (converged ? 1 : 0));
+  return FAIL_MAXIT;
+}
+
+int step_one(Scene &s, ipco_info *info) {
+  std::vector<double> x;
+  int fr = begin_step(s, x);
+  s.iter_log.clear();
+  int dirs_total = 0;
+  // friction lagged at x^n, then (variant) re-lagged at each converged iterate
+  for (int lag = 0; fr == FAIL_NONE && lag < s.friction_iters; ++lag) {
+    if (lag > 0) lag_friction(s, x);
+    int dirs = 0;
+    fr = newton_solve(s, x, info, &dirs);
+    dirs_total += dirs;
   }
-  if (!converged) {
+  if (info) {
+    info->newton_iters += dirs_total;
+    info->max_newton_iters = std::max(info->max_newton_iters, dirs_total);
+    info->kappa_last = s.kappa;
+  }
+  if (fr != FAIL_NONE) {
     s.failed = true;
-    s.fail_reason = FAIL_MAXIT;
+    s.fail_reason = fr;
     return E_FAILED;
   }
   for (int i = 0; i < 3 * s.nv; ++i) s.v[i] = (x[i] - s.xn[i]) / s.dt;
@@ -1868,6 +2010,21 @@ int64_t ipco_iter_log(void *h, double *out, int64_t cap) {
   for (int64_t i = 0; i < 4 * std::min(n, cap); ++i) out[i] = s->iter_log[i];
   return n;
 }
+
+double ipco_tet_first_root(const double *x12, const double *p12, double tmax, double *k4) {
+  double k[4];
+  det_cubic(x12, p12, k);
+  if (k4)
+    for (int i = 0; i < 4; ++i) k4[i] = k[i];
+  return first_root(k, tmax);
+}
+
+double ipco_inversion_bound(void *h, const double *x, const double *p) {
+  Scene *s = static_cast<Scene *>(h);
+  return inversion_bound(*s, std::vector<double>(x, x + 3 * s->nv), std::vector<double>(p, p + 3 * s->nv));
+}
+
+double ipco_kappa(void *h) { return static_cast<Scene *>(h)->kappa; }
 
 int ipco_debug_ls_offset(void *h, double delta) {
   static_cast<Scene *>(h)->debug_ls_offset = delta;

@@ -35,6 +35,14 @@ typedef struct {
   int32_t newton_max_iter;
   double pcg_rel_tol;       /* relative residual for the linear solve */
   int32_t linear_solver;    /* 0 = block-Jacobi PCG, 1 = dense Cholesky */
+  /* solver variants (0 = off; see the step-by-step description in ipc_oracle.cpp) */
+  double newton_rel_tol;    /* > 0: stop at |p|_inf <= newton_rel_tol * L * dt, L = bbox diagonal
+                               of the free vertices at creation (replaces newton_tol)          */
+  int32_t friction_iters;   /* lagged friction updates per step (0 or 1: one, at x^n)        */
+  int32_t inversion_filter; /* 1: the line search starts at most at 0.8 x the first root of
+                               det F(alpha) = 0 over all tets                                 */
+  int32_t adaptive_kappa;   /* 1: kappa doubles (up to 100 kappa) when the least active-pair
+                               distance falls below 1e-2 dhat and keeps decreasing            */
 } ipco_desc;
 
 typedef struct {
@@ -48,6 +56,7 @@ typedef struct {
   int64_t n_active_last;
   double min_dist_last;
   double energy_last;
+  double kappa_last;        /* barrier stiffness after the last step */
 } ipco_info;
 
 int ipco_create(const ipco_desc *d, void **out);
@@ -88,6 +97,13 @@ int ipco_friction_elem(const double *x12, const double *xn12, const double *w4, 
                        double mu, double eps, double *energy, double *g12, double *H144);
 /* Newton record of the last step: rows (Phi before, Phi accepted, alpha, halvings). */
 int64_t ipco_iter_log(void *s, double *out, int64_t cap);
+/* Inversion filter of one tet: the first t in (0, tmax] with det(Ds(x + t p)) <= 0, or +inf
+ * (x12, p12: the four vertices and their displacements).  Also the cubic's coefficients k[4]. */
+double ipco_tet_first_root(const double *x12, const double *p12, double tmax, double *k4);
+/* Step bound of the inversion filter over a scene's tets at x along p. */
+double ipco_inversion_bound(void *s, const double *x, const double *p);
+/* Current barrier stiffness of a scene. */
+double ipco_kappa(void *s);
 /* Test-only planted fault: delta added to every line-search trial energy. */
 int ipco_debug_ls_offset(void *s, double delta);
 
