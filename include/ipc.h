@@ -80,6 +80,24 @@ typedef struct {
   int32_t newton_max_iter;  /* 100 (Sec. III-D)                                             */
   double pcg_rel_tol;       /* PCG stops at |r|_2 <= pcg_rel_tol |g|_2 (1e-4 default, 1e-8 for parity) */
   int32_t precision;        /* IPC_FP64 or IPC_MIXED                                        */
+  /* Solver variants (0 = off).  Each follows a passage of the paper that
+   * leaves the exact rule open; the rule taken is stated here. */
+  double newton_rel_tol;    /* > 0: the paper's relative Newton tolerance eps_r (Sec. III-D, 1e-3):
+                               converged when |p|_inf <= eps_r * L * dt, L = diagonal of the
+                               bounding box of the free vertices at creation; replaces newton_tol */
+  int32_t friction_iters;   /* lagged friction updates per time step (0 or 1: one, at x^n; the
+                               paper leaves the count open, Sec. III-D).  With k > 1, once an
+                               environment's Newton solve converges its friction data are taken
+                               again at the converged iterate (the tangential displacement is still
+                               measured from x^n) and the solve is repeated, k solves in all, each
+                               with its own newton_max_iter budget                           */
+  int32_t inversion_filter; /* 1: step-size filter against inversion (Sec. II-C): the line search
+                               starts at most at 0.8 t*, t* the first root in (0, 1.25] of
+                               det(Ds(x + t p)) over every tet (a cubic in t), besides the CCD bound */
+  int32_t adaptive_kappa;   /* 1: at each Newton iterate, if the least active-pair distance is below
+                               1e-2 dhat and smaller than at the previous iterate, kappa doubles, up
+                               to 100 times its given value (the paper fixes kappa = 3e6, Sec.
+                               III-D; this is the variant that adapts it)                     */
 } ipc_scene_desc;
 
 typedef struct {
@@ -90,9 +108,11 @@ typedef struct {
   int32_t max_newton_iters; /* largest per-step count                                        */
   int32_t ls_halvings;      /* total line-search halvings                                    */
   int64_t pcg_iters;        /* total PCG iterations                                          */
-  int64_t n_active_last;    /* active contact pairs at the last accepted iterate             */
-  double min_dist_last;     /* unused by the GPU path (0)                                     */
+  int64_t n_active_last;    /* active contact pairs (d^2 < dhat^2) at the last accepted iterate */
+  double min_dist_last;     /* least distance among those pairs (+inf if none): the contact
+                               gap of Table I's D2, zero penetration when > 0               */
   double energy_last;       /* Phi at the last accepted iterate                              */
+  double kappa_last;        /* barrier stiffness after the last step (kappa unless adaptive)  */
 } ipc_step_info;
 
 /* Create a scene from host data (copied).  Validates sizes, finiteness,
@@ -117,8 +137,13 @@ int ipc_step_batch(ipc_scene *scenes, int32_t n, int32_t n_steps, ipc_step_info 
  * [n_tets] or NULL (per-tet stress output, Sec. IV-D). */
 int ipc_get_state(ipc_scene s, double *pos, double *vel, double *cauchy, double *von_mises);
 
-/* Overwrite positions/velocities (vel NULL = 0) and the step index; clears a
- * failed flag.  Used for checkpoint / resume. */
+/* Utility, not a step of the method: overwrite positions/velocities (vel
+ * NULL = 0) and the step index, and clear a failed flag, for checkpoint /
+ * resume.  The caller vouches for the state: it is not checked for
+ * intersection or inversion here (the next step's line search would reject
+ * an infeasible iterate).  The barrier stiffness and augmented-Lagrangian
+ * state are kept.  IPC_E_ARG for a NULL pos, a negative step or non-finite
+ * values. */
 int ipc_set_state(ipc_scene s, const double *pos, const double *vel, int32_t step);
 
 void ipc_destroy_scene(ipc_scene s);
@@ -191,6 +216,17 @@ int ipc_prof_read(double *out);
 int ipc_set_tuning(int32_t key, int64_t value);
 int ipc_get_tuning(int32_t key, int64_t *value);
 
+/* CCD step bound over a caller's list of contact pairs (Sec. II-C: the
+ * projected-Newton step is filtered by continuous collision detection; the
+ * bound is the additive-CCD time of impact, mean displacement removed,
+ * conservative rescaling s).  n pairs of one kind (0 point-triangle: point,
+ * then the triangle's three vertices; 1 edge-edge: the two vertices of each
+ * edge), positions x12 [n*12] and displacements p12 [n*12], host pointers.
+ * *alpha = min(1, min over the pairs of the time of impact), 1 for n = 0.
+ * IPC_E_ARG for a bad kind, n < 0, NULL pointers, non-finite data or s
+ * outside (0, 1).  Uses a per-call device buffer of per-block minima. */
+int ipc_ccd_bound_pairs(int32_t kind, int64_t n, const double *x12, const double *p12, double s, double *alpha);
+
 /* ---------------------------------------------------------------------------
  * Inspection entry points.  Each runs the same device kernels the step uses,
  * on host-supplied positions, so callers can check individual stages.
@@ -228,6 +264,11 @@ int ipc_debug_newton_dir(ipc_scene s, const double *x, double *p, int64_t *pcg_i
 /* CCD step bound min(1, additive-CCD time of impact) over the sweep x -> x+p. */
 double ipc_debug_ccd_bound(ipc_scene s, const double *x, const double *p);
 
+/* Inversion filter's step bound min(1, min over tets of 0.8 t*) along x + t p
+ * (t* the first root of det(Ds(x + t p)), Sec. II-C step-size filter),
+ * whether or not the scene enables the filter. */
+double ipc_debug_inversion_bound(ipc_scene s, const double *x, const double *p);
+
 /* Element routines evaluated by device code (one element per call). */
 int ipc_debug_classify(int32_t kind, int64_t n, const double *x12, int32_t *types, double *d2);
 int ipc_debug_pair_barrier(int32_t kind, int32_t type, const double *x12, double dhat, double kappa,
@@ -235,6 +276,10 @@ int ipc_debug_pair_barrier(int32_t kind, int32_t type, const double *x12, double
 int ipc_debug_tet_elastic(const double *X12, const double *x12, double E, double nu, int32_t project,
                           double *energy, double *g12, double *H144);
 int64_t ipc_debug_accd(int32_t kind, int64_t n, const double *x12, const double *p12, double s, double *t);
+/* Per tet (x12, p12: its four vertices and their displacements): the
+ * coefficients k4 [n*4] of det(Ds(x + t p)) = k0 + k1 t + k2 t^2 + k3 t^3 and
+ * its first root t [n] in (0, tmax] (+inf if none, 0 if det <= 0 at t = 0). */
+int64_t ipc_debug_tet_first_root(int64_t n, const double *x12, const double *p12, double tmax, double *t, double *k4);
 
 /* ===========================================================================
  * Serving: continuous batching of simulation requests on one device.

@@ -872,6 +872,83 @@ DEV double accd(int kind, const double *x, const double *p, double s) {
   return t;
 }
 
+// -- inversion filter (the step-size filter of Sec. II-C that keeps every tet
+//    inversion-free along the search line) ---------------------------------------
+// Along x + t p the edge matrix of a tet is Ds(x) + t Ds(p), with columns
+// a_c + t b_c (a_c = x_{c+1} - x_0, b_c = p_{c+1} - p_0).  Its determinant is
+// multilinear in the columns, so det = c0 + c1 t + c2 t^2 + c3 t^3 with
+//   c0 = [a0 a1 a2],  c1 = [b0 a1 a2] + [a0 b1 a2] + [a0 a1 b2],
+//   c2 = [a0 b1 b2] + [b0 a1 b2] + [b0 b1 a2],  c3 = [b0 b1 b2],
+// [u v w] = u . (v x w).  J = det Ds / det Dm has the same sign (det Dm > 0).
+DEV void det_line_cubic(const double *x, const double *p, double c[4]) {
+  d3 a[3], b[3];
+  for (int k = 0; k < 3; ++k) {
+    a[k] = sub3(ld3(x + 3 * (k + 1)), ld3(x));
+    b[k] = sub3(ld3(p + 3 * (k + 1)), ld3(p));
+  }
+  c[0] = dot3(a[0], cross3(a[1], a[2]));
+  c[1] = dot3(b[0], cross3(a[1], a[2])) + dot3(a[0], cross3(b[1], a[2])) + dot3(a[0], cross3(a[1], b[2]));
+  c[2] = dot3(a[0], cross3(b[1], b[2])) + dot3(b[0], cross3(a[1], b[2])) + dot3(b[0], cross3(b[1], a[2]));
+  c[3] = dot3(b[0], cross3(b[1], b[2]));
+}
+
+DEV double cubic_eval(const double c[4], double t) { return c[0] + t * (c[1] + t * (c[2] + t * c[3])); }
+
+// Smallest t in (0, tmax] with det <= 0, +inf if there is none (0 if det <= 0
+// already at t = 0).  The real roots of the derivative c1 + 2 c2 t + 3 c3 t^2
+// cut [0, tmax] into pieces on which the cubic is monotone; the first piece
+// whose right end is not positive holds the root, which bisection brackets
+// down to adjacent doubles (the returned end has det <= 0).
+DEV double cubic_first_root(const double c[4], double tmax) {
+  if (!(c[0] > 0.0)) return 0.0;
+  double cut[4];
+  int nc = 0;
+  cut[nc++] = 0.0;
+  const double qa = 3.0 * c[3], qb = 2.0 * c[2], qc = c[1];
+  double r0 = -1.0, r1 = -1.0;
+  if (qa != 0.0) {
+    const double disc = qb * qb - 4.0 * qa * qc;
+    if (disc >= 0.0) {
+      const double sq = sqrt(disc);
+      r0 = (-qb - sq) / (2.0 * qa);
+      r1 = (-qb + sq) / (2.0 * qa);
+      if (r1 < r0) {
+        const double t = r0;
+        r0 = r1;
+        r1 = t;
+      }
+    }
+  } else if (qb != 0.0) {
+    r0 = -qc / qb;
+  }
+  if (r0 > 0.0 && r0 < tmax) cut[nc++] = r0;
+  if (r1 > 0.0 && r1 < tmax && r1 > cut[nc - 1]) cut[nc++] = r1;
+  cut[nc++] = tmax;
+  for (int i = 0; i + 1 < nc; ++i) {
+    double lo = cut[i], hi = cut[i + 1];
+    if (cubic_eval(c, hi) > 0.0) continue;
+    for (int it = 0; it < 128; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if (!(mid > lo && mid < hi)) break;
+      if (cubic_eval(c, mid) > 0.0)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    return hi;
+  }
+  return kInf;
+}
+
+// the filter's step bound for one tet: min(1, 0.8 t*) (0.8: safety factor)
+constexpr double kInvSafety = 0.8;
+DEV double tet_inversion_bound(const double *x, const double *p) {
+  double c[4];
+  det_line_cubic(x, p, c);
+  const double t = cubic_first_root(c, 1.0 / kInvSafety);
+  return fmin(1.0, kInvSafety * t);
+}
+
 DEV void inv33(const double *M, double *R) {
   double det = det33(M);
   double id = 1.0 / det;

@@ -160,6 +160,7 @@ struct HostScene {
   double mbar = 1.0;  // mean free-vertex mass
   double dt, dhat, kappa, mu_f, eps_v, tol, pcg_tol;
   int maxit, precision;
+  int fric_iters = 1, inv_filter = 0, adapt_kappa = 0;
 };
 
 bool finite_all(const double *p, long n) {
@@ -287,6 +288,9 @@ std::unique_ptr<HostScene> preprocess(const ipc_scene_desc *d) {
       !std::isfinite(d->dhat) || !std::isfinite(d->kappa) || !std::isfinite(d->mu))
     throw ApiError(IPC_E_ARG, "bad solver parameter");
   if (d->precision != IPC_FP64 && d->precision != IPC_MIXED) throw ApiError(IPC_E_ARG, "bad precision flag");
+  if (!(d->newton_rel_tol >= 0) || !std::isfinite(d->newton_rel_tol) || d->friction_iters < 0 ||
+      d->inversion_filter < 0 || d->adaptive_kappa < 0)
+    throw ApiError(IPC_E_ARG, "bad solver variant");
   if ((long)d->n_tets * 32 >= (1L << 31)) throw ApiError(IPC_E_ARG, "too many tets for one scene");
   auto S = std::make_unique<HostScene>();
   HostScene &H = *S;
@@ -358,6 +362,24 @@ std::unique_ptr<HostScene> preprocess(const ipc_scene_desc *d) {
     }
   }
   H.mbar = H.n_free > 0 ? msum / H.n_free : 1.0;
+  H.fric_iters = std::max(1, (int)d->friction_iters);
+  H.inv_filter = d->inversion_filter != 0;
+  H.adapt_kappa = d->adaptive_kappa != 0;
+  if (d->newton_rel_tol > 0) {
+    // the paper's relative Newton tolerance (Sec. III-D): eps_r times the
+    // diagonal of the free vertices' bounding box at creation
+    double lo[3] = {HUGE_VAL, HUGE_VAL, HUGE_VAL}, hi[3] = {-HUGE_VAL, -HUGE_VAL, -HUGE_VAL};
+    for (int i = 0; i < H.nv; ++i)
+      if (H.kin[i] < 0)
+        for (int k = 0; k < 3; ++k) {
+          lo[k] = std::min(lo[k], H.x0[3 * i + k]);
+          hi[k] = std::max(hi[k], H.x0[3 * i + k]);
+        }
+    double diag2 = 0.0;
+    if (H.n_free > 0)
+      for (int k = 0; k < 3; ++k) diag2 += (hi[k] - lo[k]) * (hi[k] - lo[k]);
+    H.tol = d->newton_rel_tol * std::sqrt(diag2);
+  }
   // surface: boundary faces (used by one tet) + kinematic triangles, each with
   // ascending vertex ids, list sorted lexicographically; edges (min,max) sorted
   {
@@ -586,7 +608,7 @@ struct World {
   DBuf<int> g_ncell, g_big, g_eoff, g_bigoff, g_ebucket, g_bcnt, g_boff, g_bcur, g_bigl;
   DBuf<ipck::GridEnt> g_ent, g_sorted;
   DBuf<int2> bp_stash;
-  DBuf<double> cand_d2, e_c, fw, fn, flam, e_f, ce_g, ce_H, part_a, part_b0, part_b1, part_c0, part_c1;
+  DBuf<double> act_d2, cand_d2, e_c, fw, fn, flam, e_f, ce_g, ce_H, part_a, part_b0, part_b1, part_c0, part_c1;
   DBuf<int4> fv, ce_v;
   int *pinned = nullptr;  // host mirror of counters
   hipEvent_t poll_ev[2] = {nullptr, nullptr};  // PCG polls in flight (copies into pinned[8], pinned[9])
@@ -668,11 +690,12 @@ struct World {
                  (void **)&S.dbc_bad,  (void **)&S.cand_beg, (void **)&S.cand_end, (void **)&S.act_beg,
                  (void **)&S.act_end,  (void **)&S.fric_beg, (void **)&S.fric_end, (void **)&S.in_step,
                  (void **)&S.big_beg,  (void **)&S.big_end,  (void **)&S.al,       (void **)&S.al_action,
-                 (void **)&S.snap_bad};
+                 (void **)&S.snap_bad, (void **)&S.nact,     (void **)&S.lag,      (void **)&S.iter_cap};
     state_ll = {(void **)&S.pcg_total, (void **)&S.amax_bits};
     state_dbl = {(void **)&S.alpha, (void **)&S.E0,  (void **)&S.E1,       (void **)&S.pinf,
                  (void **)&S.pcg_bb, (void **)&S.kA, (void **)&S.viol, (void **)&S.viol_prev,
-                 (void **)&S.cg_a0,  (void **)&S.cg_a1, (void **)&S.cg_g0, (void **)&S.cg_g1};
+                 (void **)&S.cg_a0,  (void **)&S.cg_a1, (void **)&S.cg_g0, (void **)&S.cg_g1,
+                 (void **)&S.kappa,  (void **)&S.kappa0, (void **)&S.dmin_prev, (void **)&S.dmin2};
   }
 
   void ensure_envs(size_t n) {
@@ -863,9 +886,17 @@ struct World {
     E.pcg_tol = H.pcg_tol;
     E.cell = H.cell;
     E.mbar = H.mbar;
+    E.fric_iters = H.fric_iters;
+    E.inv_filter = H.inv_filter;
+    E.adapt_kappa = H.adapt_kappa;
     upload_env(slot);
     int zero = 0;
     HC(hipMemcpyAsync(S.status + slot, &zero, 4, hipMemcpyHostToDevice, stream));
+    // barrier stiffness as given; no previous iterate yet
+    const double kap = H.kappa, inf = HUGE_VAL;
+    HC(hipMemcpyAsync(S.kappa + slot, &kap, 8, hipMemcpyHostToDevice, stream));
+    HC(hipMemcpyAsync(S.kappa0 + slot, &kap, 8, hipMemcpyHostToDevice, stream));
+    HC(hipMemcpyAsync(S.dmin_prev + slot, &inf, 8, hipMemcpyHostToDevice, stream));
     HC(hipStreamSynchronize(stream));
     batch_envs.clear();  // tile lists must be rebuilt
     return slot;
@@ -996,6 +1027,7 @@ struct World {
     L.e_c = e_c.p;
     L.act = act.p;
     L.act_type = act_type.p;
+    L.act_d2 = act_d2.p;
     L.fv = fv.p;
     L.fw = fw.p;
     L.fn = fn.p;
@@ -1128,16 +1160,19 @@ struct World {
   }
 
   // classify + compact the active pairs of the current candidate list
-  int active_pairs(int n_cand, const double *x) {
+  // adapt = 1 at a Newton iterate: the adaptive barrier stiffness update
+  int active_pairs(int n_cand, const double *x, int adapt = 0) {
     if (scan_tmp.ensure(n_cand / 1024 + 64)) refresh_lists();
     ipck::classify_cands(stream, W, envs_d, L, n_cand, x);
     ipck::scan_int(stream, L.cand_flag, L.cand_offs, n_cand, L.scan_tmp);
     int n = read_int(L.cand_offs + n_cand);
     bool moved = act.ensure(n + 1);
     moved |= act_type.ensure(n + 1);
+    moved |= act_d2.ensure(n + 1);
     if (moved) refresh_lists();
     ipck::compact_active(stream, L, n_cand);
     ipck::act_segments(stream, S, B, L);
+    ipck::act_stats(stream, envs_d, S, B, L, adapt);
     return n;
   }
 
@@ -1160,7 +1195,7 @@ struct World {
     moved |= e_f.ensure(na + 1);
     moved |= fenv.ensure(na + 1);
     if (moved) refresh_lists();
-    ipck::friction_setup(stream, W, envs_d, L, na);
+    ipck::friction_setup(stream, W, envs_d, S, L, na);
     // the friction segments are the active segments of this list
     copy_state_int(S.fric_beg, S.act_beg);
     copy_state_int(S.fric_end, S.act_end);
@@ -1183,9 +1218,9 @@ struct World {
   int assemble_system(int mixed) {
     int nc = swept_n >= 0 ? swept_n : broad_phase(W.x, nullptr);
     swept_n = -1;
-    int na = active_pairs(nc, W.x);
+    int na = active_pairs(nc, W.x, 1);
     ensure_ce(na + n_fric);
-    ipck::barrier_elems(stream, W, envs_d, L, na, W.x);
+    ipck::barrier_elems(stream, W, envs_d, S, L, na, W.x);
     ipck::friction_elems(stream, W, envs_d, S, L, n_fric, na, W.x);
     int nce = na + n_fric;
     int nvw = (int)aV.cap;
@@ -1371,29 +1406,10 @@ public:
     return t == 1;
   }
 
-  void step_batch() {
-    auto t0 = std::chrono::steady_clock::now();
-    auto ms = [&]() {
-      return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    };
-    swept_n = -1;
-    ipck::env_begin(stream, S, B);
-    ipck::begin_step(stream, W, envs_d, S, B);
-    // one swept pass over the Dirichlet move (free vertices stay at xn): its
-    // boxes contain xn, so it also yields the friction set's pairs at xn
-    int nc = broad_phase(W.xn, W.p);
-    friction_setup(nc);
-    ipck::ccd_init(stream, S, B);
-    ipck::accd(stream, W, envs_d, S, L, nc, W.xn, W.p);
-    ipck::dbc_check_J(stream, W, envs_d, S, B);
-    ipck::env_dbc(stream, S, B);
-    ipck::apply_dbc(stream, W, envs_d, S, B);
-    swept_n = nc;  // x is xn, or the targets on kinematic rows: inside these boxes
-    int maxit = 0;
-    for (int e : batch_envs) maxit = std::max(maxit, envs_h[e].maxit);
-    int mixed = 0;
-    for (int e : batch_envs) mixed |= envs_h[e].precision == IPC_MIXED;
-    const std::vector<int> step_envs = batch_envs;
+  // Newton iterations of the current batch until every environment has
+  // converged or failed (at most maxit iterations per environment and round)
+  template <class Clock>
+  void newton_loop(int maxit, int mixed, bool inv, Clock &ms) {
     for (int it = 0; it < maxit; ++it) {
       int na = assemble_system(mixed);
       long long pit = solve(mixed);
@@ -1408,6 +1424,7 @@ public:
       int ns = broad_phase(W.x, W.p);
       ipck::ccd_init(stream, S, B);
       ipck::accd(stream, W, envs_d, S, L, ns, W.x, W.p);
+      if (inv) ipck::inv_bound(stream, W, envs_d, S, B, 0);
       ipck::snap_J(stream, W, S, B);
       ipck::ls_init(stream, S, B);
       ipck::energy(stream, W, envs_d, S, B, L, ns, n_fric, 1, S.E0);
@@ -1424,6 +1441,49 @@ public:
       swept_n = ns;  // x moved by a p with a <= 1, snapped inside the swept boxes, or stayed
       ipck::iter_end(stream, envs_d, S, B, L.counter + 3);
       if (read_int(L.counter + 3) == 0) break;
+    }
+  }
+
+  void step_batch() {
+    auto t0 = std::chrono::steady_clock::now();
+    auto ms = [&]() {
+      return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    };
+    swept_n = -1;
+    ipck::env_begin(stream, envs_d, S, B);
+    ipck::begin_step(stream, W, envs_d, S, B);
+    // one swept pass over the Dirichlet move (free vertices stay at xn): its
+    // boxes contain xn, so it also yields the friction set's pairs at xn
+    int nc = broad_phase(W.xn, W.p);
+    friction_setup(nc);
+    ipck::ccd_init(stream, S, B);
+    ipck::accd(stream, W, envs_d, S, L, nc, W.xn, W.p);
+    ipck::dbc_check_J(stream, W, envs_d, S, B);
+    ipck::env_dbc(stream, S, B);
+    ipck::apply_dbc(stream, W, envs_d, S, B);
+    swept_n = nc;  // x is xn, or the targets on kinematic rows: inside these boxes
+    int maxit = 0, rounds = 1;
+    bool inv = false;
+    int mixed = 0;
+    for (int e : batch_envs) {
+      maxit = std::max(maxit, envs_h[e].maxit);
+      rounds = std::max(rounds, envs_h[e].fric_iters);
+      inv |= envs_h[e].inv_filter != 0;
+      mixed |= envs_h[e].precision == IPC_MIXED;
+    }
+    const std::vector<int> step_envs = batch_envs;
+    for (int lag = 0; lag < rounds; ++lag) {
+      if (lag > 0) {
+        // another lagged friction update: environments that converged and
+        // take one solve again, with friction data taken at their iterate
+        set_batch(step_envs);
+        ipck::relag(stream, envs_d, S, B, L.counter + 5);
+        if (read_int(L.counter + 5) == 0) break;
+        int nc = broad_phase(W.x, nullptr);
+        friction_setup(nc);
+        swept_n = nc;  // the static list at x serves the first iteration
+      }
+      newton_loop(maxit, mixed, inv, ms);
     }
     swept_n = -1;
     set_batch(step_envs);
@@ -1542,17 +1602,23 @@ struct EnvSnapshot {
 
 // all env slots at once (one copy per field)
 struct EnvSnapshots {
-  std::vector<int> status, reason, iters, halvings;
+  std::vector<int> status, reason, iters, halvings, nact;
   std::vector<long long> pcg_total;
-  std::vector<double> E0;
+  std::vector<double> E0, dmin2, kappa;
   void fetch(World &w) {
     size_t n = w.env_cap;
     status.resize(n);
     reason.resize(n);
     iters.resize(n);
     halvings.resize(n);
+    nact.resize(n);
     pcg_total.resize(n);
     E0.resize(n);
+    dmin2.resize(n);
+    kappa.resize(n);
+    HC(hipMemcpyAsync(nact.data(), w.S.nact, 4 * n, hipMemcpyDeviceToHost, w.stream));
+    HC(hipMemcpyAsync(dmin2.data(), w.S.dmin2, 8 * n, hipMemcpyDeviceToHost, w.stream));
+    HC(hipMemcpyAsync(kappa.data(), w.S.kappa, 8 * n, hipMemcpyDeviceToHost, w.stream));
     HC(hipMemcpyAsync(status.data(), w.S.status, 4 * n, hipMemcpyDeviceToHost, w.stream));
     HC(hipMemcpyAsync(reason.data(), w.S.reason, 4 * n, hipMemcpyDeviceToHost, w.stream));
     HC(hipMemcpyAsync(iters.data(), w.S.iters, 4 * n, hipMemcpyDeviceToHost, w.stream));
@@ -1632,10 +1698,16 @@ void run_steps_lane(std::vector<ipc_scene> scenes, int n_steps, ipc_step_info *i
         infos[i].ls_halvings += snap.halvings[e];
         infos[i].pcg_iters += snap.pcg_total[e];
         infos[i].energy_last = snap.E0[e];
+        infos[i].kappa_last = snap.kappa[e];
       }
       if (snap.status[e] == ipcw::ST_CONVERGED) {
         s->step += 1;
-        if (infos) infos[i].steps_done += 1;
+        if (infos) {
+          infos[i].steps_done += 1;
+          // contact statistics of the accepted iterate (its last classification)
+          infos[i].n_active_last = snap.nact[e];
+          infos[i].min_dist_last = std::sqrt(snap.dmin2[e]);
+        }
         snap.status[e] = ipcw::ST_IDLE;
       } else {
         s->failed = true;
@@ -2249,7 +2321,7 @@ int ipc_debug_begin_step(ipc_scene s, double *x_start) {
       DebugScope D(s);
       w.envs_h[s->slot].step = s->step;
       w.upload_env(s->slot);
-      ipck::env_begin(w.stream, w.S, w.B);
+      ipck::env_begin(w.stream, w.envs_d, w.S, w.B);
       ipck::begin_step(w.stream, w.W, w.envs_d, w.S, w.B);
       int nc = w.broad_phase(w.W.xn, w.W.p);
       w.friction_setup(nc);
@@ -2354,7 +2426,73 @@ double ipc_debug_ccd_bound(ipc_scene s, const double *x, const double *p) {
   }
 }
 
+double ipc_debug_inversion_bound(ipc_scene s, const double *x, const double *p) {
+  try {
+    if (!s || !x || !p) throw ApiError(IPC_E_ARG, "bad arguments");
+    DebugScope D(s);
+    World &w = D.w;
+    put_x(w, s, w.W.x, x);
+    put_x(w, s, w.W.p, p);
+    ipck::ccd_init(w.stream, w.S, w.B);
+    ipck::inv_bound(w.stream, w.W, w.envs_d, w.S, w.B, 1);
+    unsigned long long bits;
+    down(w, &bits, w.S.amax_bits + s->slot, 1);
+    HC(hipStreamSynchronize(w.stream));
+    double a;
+    std::memcpy(&a, &bits, 8);
+    return a;
+  } catch (const std::exception &e) {
+    api_error(e);
+    return std::nan("");
+  }
+}
+
+int ipc_ccd_bound_pairs(int32_t kind, int64_t n, const double *x12, const double *p12, double s, double *alpha) {
+  return guarded([&]() {
+    if ((kind != 0 && kind != 1) || n < 0 || n > INT32_MAX || (n > 0 && (!x12 || !p12)) || !alpha ||
+        !(s > 0.0 && s < 1.0))
+      throw ApiError(IPC_E_ARG, "bad arguments");
+    if (!finite_all(x12, 12 * n) || !finite_all(p12, 12 * n)) throw ApiError(IPC_E_ARG, "non-finite pair data");
+    World &w = world_for_current_device();
+    std::lock_guard<std::mutex> lk(w.mu);
+    DBuf<double> X, P, part, out;
+    X.ensure(12 * n + 1);
+    P.ensure(12 * n + 1);
+    part.ensure(ipck::pairs_ccd_parts(n) + 1);
+    out.ensure(1);
+    w.up(X.p, x12, 12 * n);
+    w.up(P.p, p12, 12 * n);
+    ipck::pairs_ccd_bound(w.stream, kind, (int)n, X.p, P.p, s, part.p, out.p);
+    HC(hipGetLastError());
+    down(w, alpha, out.p, 1);
+    HC(hipStreamSynchronize(w.stream));
+    return IPC_OK;
+  });
+}
+
 // element-level routines on the device
+int64_t ipc_debug_tet_first_root(int64_t n, const double *x12, const double *p12, double tmax, double *t, double *k4) {
+  try {
+    if (n < 0 || (n > 0 && (!x12 || !p12 || !t || !k4)) || !(tmax > 0)) throw ApiError(IPC_E_ARG, "bad arguments");
+    World &w = world_for_current_device();
+    std::lock_guard<std::mutex> lk(w.mu);
+    DBuf<double> X, P, T, K;
+    X.ensure(12 * n + 1);
+    P.ensure(12 * n + 1);
+    T.ensure(n + 1);
+    K.ensure(4 * n + 1);
+    w.up(X.p, x12, 12 * n);
+    w.up(P.p, p12, 12 * n);
+    ipck::dbg_tet_root(w.stream, (int)n, X.p, P.p, tmax, T.p, K.p);
+    down(w, t, T.p, n);
+    down(w, k4, K.p, 4 * n);
+    HC(hipStreamSynchronize(w.stream));
+    return n;
+  } catch (const std::exception &e) {
+    return api_error(e);
+  }
+}
+
 int ipc_debug_classify(int32_t kind, int64_t n, const double *x12, int32_t *types, double *d2) {
   return guarded([&]() {
     if (n < 0 || (n > 0 && (!x12 || !types || !d2))) throw ApiError(IPC_E_ARG, "bad arguments");

@@ -40,6 +40,7 @@ struct Lists {
   double *cand_d2, *e_c;
   int2 *act;                      // active pairs (same encoding)
   int *act_type;
+  double *act_d2;                 // their squared distances
   // friction (lagged at x^n)
   int4 *fv;
   double *fw, *fn, *flam, *e_f;
@@ -71,7 +72,7 @@ struct Lists {
 void begin_step(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B);
 void apply_dbc(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B);
 void dbc_check_J(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B);
-void env_begin(hipStream_t s, const EnvState &S, const Batch &B);
+void env_begin(hipStream_t s, const EnvDev *E, const EnvState &S, const Batch &B);
 void env_dbc(hipStream_t s, const EnvState &S, const Batch &B);
 
 // broad phase over the state positions x (+ p if swept)
@@ -90,8 +91,12 @@ void cand_segments(hipStream_t s, const EnvDev *E, const EnvState &S, const Batc
 void classify_cands(hipStream_t s, const WorldDev &W, const EnvDev *E, const Lists &L, int n, const double *x);
 void compact_active(hipStream_t s, const Lists &L, int n);
 void act_segments(hipStream_t s, const EnvState &S, const Batch &B, const Lists &L);
-void barrier_elems(hipStream_t s, const WorldDev &W, const EnvDev *E, const Lists &L, int n_act, const double *x);
-void friction_setup(hipStream_t s, const WorldDev &W, const EnvDev *E, const Lists &L, int n_act);
+// per environment: active-pair count, least squared distance; with adapt = 1
+// (a Newton iterate) the adaptive barrier stiffness update
+void act_stats(hipStream_t s, const EnvDev *E, const EnvState &S, const Batch &B, const Lists &L, int adapt);
+void barrier_elems(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Lists &L, int n_act,
+                   const double *x);
+void friction_setup(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Lists &L, int n_act);
 void friction_elems(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Lists &L, int n_fric,
                     int ce_off, const double *x);
 void incidence(hipStream_t s, const WorldDev &W, const EnvState &S, Lists &L, int n_ce, int nv_world);
@@ -133,6 +138,13 @@ void al_finish(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState
 void ccd_init(hipStream_t s, const EnvState &S, const Batch &B);
 void accd(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Lists &L, int n,
           const double *x, const double *p);
+// inversion filter: lowers each line-searching environment's step bound to
+// 0.8 x the first root of det F along the direction, over its tets
+// (force = 1: every listed environment, whatever its variant flag and AL action)
+void inv_bound(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, int force);
+// friction lag rounds: reactivates converged environments that take another
+// lagged friction update this step; *n_relag = their number
+void relag(hipStream_t s, const EnvDev *E, const EnvState &S, const Batch &B, int *n_relag);
 void ls_init(hipStream_t s, const EnvState &S, const Batch &B);
 void energy(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L, int n_cand,
             int n_fric, int zero_alpha, double *E_out);
@@ -149,5 +161,11 @@ void dbg_pair(hipStream_t s, int kind, int type, const double *x12, double dhat,
               int project, double *out /*1+12+144*/);
 void dbg_tet(hipStream_t s, const double *X12, const double *x12, double mu, double la, double *out /*1+12+144*/);
 void dbg_accd(hipStream_t s, int kind, int n, const double *x12, const double *p12, double sfac, double *t);
+// CCD bound over n pairs of one kind: out[0] = min(1, min_k ACCD_k); part
+// holds pairs_ccd_parts(n) per-block minima (no clearing needed)
+int pairs_ccd_parts(int64_t n);
+void pairs_ccd_bound(hipStream_t s, int kind, int n, const double *x12, const double *p12, double sfac, double *part,
+                     double *out);
+void dbg_tet_root(hipStream_t s, int n, const double *x12, const double *p12, double tmax, double *t, double *k4);
 
 }  // namespace ipck

@@ -168,16 +168,18 @@ __global__ void k_apply_dbc(WorldDev W, EnvState S, const Tile *tiles) {
   for (int c = 0; c < 3; ++c) W.x[3 * i + c] = W.xh[3 * i + c];
 }
 
-__global__ void k_env_begin(EnvState S, const int *envs, int n) {
+__global__ void k_env_begin(const EnvDev *envs, EnvState S, const int *benv, int n) {
   int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
-  int e = envs[j];
+  int e = benv[j];
   S.in_step[e] = 0;
   if (S.status[e] == ST_FAILED) return;
   S.in_step[e] = 1;
   S.status[e] = ST_ACTIVE;
   S.reason[e] = FAIL_NONE;
   S.iters[e] = 0;
+  S.iter_cap[e] = envs[e].maxit;
+  S.lag[e] = 0;
   S.halvings[e] = 0;
   S.pcg_total[e] = 0;
   S.dbc_bad[e] = 0;
@@ -754,13 +756,14 @@ __global__ void k_classify(WorldDev W, const EnvDev *envs, const int2 *cand, int
   flag[k] = (d2 < dh * dh) ? 1 : 0;
 }
 
-__global__ void k_compact(const int2 *cand, const int *type, const int *flag, const int *offs, int n, int2 *act,
-                          int *act_type) {
+__global__ void k_compact(const int2 *cand, const int *type, const double *d2, const int *flag, const int *offs,
+                          int n, int2 *act, int *act_type, double *act_d2) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n || !flag[k]) return;
   int o = offs[k];
   act[o] = cand[k];
   act_type[o] = type[k];
+  act_d2[o] = d2[k];
 }
 
 __global__ void k_act_seg(EnvState S, const int *benv, int n, const int *offs) {
@@ -769,6 +772,37 @@ __global__ void k_act_seg(EnvState S, const int *benv, int n, const int *offs) {
   int e = benv[j];
   S.act_beg[e] = offs[S.cand_beg[e]];
   S.act_end[e] = offs[S.cand_end[e]];
+}
+
+// Contact statistics of the iterate just classified, one block per
+// environment still iterating: the number of active pairs and the least
+// squared distance among them.  With `adapt` (a Newton iterate) and the
+// adaptive-stiffness variant, kappa doubles, up to 100 times its given value,
+// when the least distance is below 1e-2 dhat and smaller than at the
+// previous iterate.
+__global__ void k_act_stats(const EnvDev *envs, EnvState S, const int *benv, const double *act_d2, int adapt) {
+  __shared__ double sh[TB];
+  int e = benv[blockIdx.x];
+  if (S.status[e] != ST_ACTIVE) return;
+  const int b = S.act_beg[e], n = S.act_end[e] - b;
+  double m = kInf;
+  for (int i = threadIdx.x; i < n; i += TB) m = fmin(m, act_d2[b + i]);
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = TB / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] = fmin(sh[threadIdx.x], sh[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  m = sh[0];
+  S.nact[e] = n;
+  S.dmin2[e] = m;
+  const EnvDev &E = envs[e];
+  if (adapt && E.adapt_kappa) {
+    const double d = sqrt(m);
+    if (d < 1e-2 * E.dhat && d < S.dmin_prev[e]) S.kappa[e] = fmin(2.0 * S.kappa[e], 100.0 * S.kappa0[e]);
+    S.dmin_prev[e] = d;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -783,9 +817,9 @@ DEV void store_blocks(const double *H, double *out) {
     }
 }
 
-__global__ void __launch_bounds__(128) k_barrier_elems(WorldDev W, const EnvDev *envs, const int2 *act,
-                                                       const int *act_type, int n, const double *x, int4 *ce_v,
-                                                       double *ce_g, double *ce_H) {
+__global__ void __launch_bounds__(128) k_barrier_elems(WorldDev W, const EnvDev *envs, const double *kap,
+                                                       const int2 *act, const int *act_type, int n, const double *x,
+                                                       int4 *ce_v, double *ce_g, double *ce_H) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   int kind, v[4], env;
@@ -794,15 +828,16 @@ __global__ void __launch_bounds__(128) k_barrier_elems(WorldDev W, const EnvDev 
   const EnvDev &E = envs[env];
   double xx[12], g[12], H[144], scr[168];
   gather12(x, v, xx);
-  pair_barrier_full(kind, act_type[k], xx, E.dhat, E.kappa, ex, true, g, H, scr);
+  pair_barrier_full(kind, act_type[k], xx, E.dhat, kap[env], ex, true, g, H, scr);
   ce_v[k] = make_int4(v[0], v[1], v[2], v[3]);
   for (int i = 0; i < 12; ++i) ce_g[12 * k + i] = g[i];
   store_blocks(H, ce_H + 90 * (size_t)k);
 }
 
 // lagged friction data at x^n (positions in W.x at set-up time)
-__global__ void k_friction_setup(WorldDev W, const EnvDev *envs, const int2 *act, const int *act_type, int n,
-                                 int4 *fv, double *fw, double *fn, double *flam, int *fenv) {
+__global__ void k_friction_setup(WorldDev W, const EnvDev *envs, const double *kap, const int2 *act,
+                                 const int *act_type, int n, int4 *fv, double *fw, double *fn, double *flam,
+                                 int *fenv) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   int kind, v[4], env;
@@ -830,7 +865,7 @@ __global__ void k_friction_setup(WorldDev W, const EnvDev *envs, const int2 *act
   fv[k] = make_int4(v[0], v[1], v[2], v[3]);
   for (int i = 0; i < 4; ++i) fw[4 * k + i] = w[i];
   for (int c = 0; c < 3; ++c) fn[3 * k + c] = dv[c] / dn;
-  flam[k] = -E.kappa * e * b1;
+  flam[k] = -kap[env] * e * b1;
   fenv[k] = env;
 }
 
@@ -1820,6 +1855,38 @@ __global__ void __launch_bounds__(128) k_accd(WorldDev W, EnvState S, const int2
   if (tt < 1.0) atomicMin(&S.amax_bits[env], (unsigned long long)__double_as_longlong(tt));
 }
 
+// inversion filter: every tet of an environment in its line search lowers the
+// environment's step bound to min(1, 0.8 t*), t* the first root of
+// det(Ds(x + t p)) (ordered-bit atomicMin, as for the CCD bound)
+__global__ void k_inv_bound(WorldDev W, const EnvDev *envs, EnvState S, const Tile *tiles, int force) {
+  Tile t = tiles[blockIdx.x];
+  if ((int)threadIdx.x >= t.count || !active_env(S, t.env)) return;
+  if (!force && (S.al_action[t.env] != 0 || !envs[t.env].inv_filter)) return;
+  int e = t.start + threadIdx.x;
+  int4 q = W.tet[e];
+  int v[4] = {q.x, q.y, q.z, q.w};
+  double xx[12], pp[12];
+  gather12(W.x, v, xx);
+  gather12(W.p, v, pp);
+  double a = tet_inversion_bound(xx, pp);
+  if (a < 1.0) atomicMin(&S.amax_bits[t.env], (unsigned long long)__double_as_longlong(a));
+}
+
+// friction lag round: an environment whose Newton solve converged and that
+// takes more lagged friction updates this step solves again (friction data
+// are then taken at its converged iterate), with a fresh iteration budget
+__global__ void k_relag(const EnvDev *envs, EnvState S, const int *benv, int n, int *n_relag) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  int e = benv[j];
+  if (!S.in_step[e] || S.status[e] != ST_CONVERGED || S.lag[e] + 1 >= envs[e].fric_iters) return;
+  S.lag[e] += 1;
+  S.status[e] = ST_ACTIVE;
+  S.iter_cap[e] = S.iters[e] + envs[e].maxit;
+  S.al_action[e] = 0;
+  atomicAdd(n_relag, 1);
+}
+
 __global__ void k_ls_init(EnvState S, const int *benv, int n) {
   int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
@@ -1889,7 +1956,7 @@ __global__ void k_energy_c(WorldDev W, const EnvDev *envs, EnvState S, const int
   if (!(d2 > 0.0))
     e = kInf;
   else if (d2 < E.dhat * E.dhat)
-    e = pair_barrier_energy(kind, xx, d2, E.dhat, E.kappa, ex);
+    e = pair_barrier_energy(kind, xx, d2, E.dhat, S.kappa[env], ex);
   e_c[k] = e;
 }
 
@@ -1961,7 +2028,7 @@ __global__ void k_iter_end(const EnvDev *envs, EnvState S, const int *benv, int 
   if (j >= n) return;
   int e = benv[j];
   if (S.status[e] != ST_ACTIVE) return;
-  if (S.iters[e] >= envs[e].maxit) {
+  if (S.iters[e] >= S.iter_cap[e]) {
     S.status[e] = ST_FAILED;
     S.reason[e] = FAIL_MAXIT;
     return;
@@ -2055,10 +2122,52 @@ __global__ void k_dbg_tet(const double *X12, const double *x12, double mu, doubl
         }
 }
 
+__global__ void k_dbg_tet_root(int n, const double *x12, const double *p12, double tmax, double *t, double *k4) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  double c[4];
+  det_line_cubic(x12 + 12 * k, p12 + 12 * k, c);
+  t[k] = cubic_first_root(c, tmax);
+  for (int i = 0; i < 4; ++i) k4[4 * k + i] = c[i];
+}
+
 __global__ void k_dbg_accd(int kind, int n, const double *x12, const double *p12, double sfac, double *t) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   t[k] = accd(kind, x12 + 12 * (size_t)k, p12 + 12 * (size_t)k, sfac);
+}
+
+// CCD step bound over a list of pairs of one kind (Sec. II-C: CCD bounds the
+// Newton step): min(1, min_k ACCD_k).  Pass 1 writes each block's minimum to
+// part[block]; pass 2 (one block) takes the minimum over the partials.  Both
+// minima are exact, so the result does not depend on the block count.
+constexpr int kCcdBlock = 128;
+__global__ void __launch_bounds__(kCcdBlock) k_pairs_ccd_min(int kind, int n, const double *x12, const double *p12,
+                                                            double sfac, double *part) {
+  __shared__ double sh[kCcdBlock];
+  const int k = blockIdx.x * kCcdBlock + threadIdx.x;
+  double t = 1.0;
+  if (k < n) t = fmin(1.0, accd(kind, x12 + 12 * (size_t)k, p12 + 12 * (size_t)k, sfac));
+  sh[threadIdx.x] = t;
+  __syncthreads();
+  for (int w = kCcdBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] = fmin(sh[threadIdx.x], sh[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void __launch_bounds__(TB) k_min_reduce(const double *part, int n_part, double *out) {
+  __shared__ double sh[TB];
+  double m = 1.0;
+  for (int i = threadIdx.x; i < n_part; i += TB) m = fmin(m, part[i]);
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = TB / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] = fmin(sh[threadIdx.x], sh[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sh[0];
 }
 
 __global__ void k_fill_int(int *p, int n, int v) {
@@ -2084,8 +2193,8 @@ void dbc_check_J(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvSta
 void apply_dbc(hipStream_t s, const WorldDev &W, const EnvDev *, const EnvState &S, const Batch &B) {
   if (B.n_vt) IPC_LAUNCH(k_apply_dbc, B.n_vt, TB, s)(W, S, B.vtiles);
 }
-void env_begin(hipStream_t s, const EnvState &S, const Batch &B) {
-  IPC_LAUNCH(k_env_begin, nblk(B.n_envs, 64), 64, s)(S, B.envs, B.n_envs);
+void env_begin(hipStream_t s, const EnvDev *E, const EnvState &S, const Batch &B) {
+  IPC_LAUNCH(k_env_begin, nblk(B.n_envs, 64), 64, s)(E, S, B.envs, B.n_envs);
 }
 void env_dbc(hipStream_t s, const EnvState &S, const Batch &B) {
   IPC_LAUNCH(k_env_dbc, nblk(B.n_envs, 64), 64, s)(S, B.envs, B.n_envs);
@@ -2146,18 +2255,26 @@ void classify_cands(hipStream_t s, const WorldDev &W, const EnvDev *E, const Lis
   if (n) IPC_LAUNCH(k_classify, nblk(n, TB), TB, s)(W, E, L.cand, n, x, L.cand_type, L.cand_d2, L.cand_flag);
 }
 void compact_active(hipStream_t s, const Lists &L, int n) {
-  if (n) IPC_LAUNCH(k_compact, nblk(n, TB), TB, s)(L.cand, L.cand_type, L.cand_flag, L.cand_offs, n, L.act, L.act_type);
+  if (n)
+    IPC_LAUNCH(k_compact, nblk(n, TB), TB, s)(L.cand, L.cand_type, L.cand_d2, L.cand_flag, L.cand_offs, n, L.act,
+                                              L.act_type, L.act_d2);
 }
 void act_segments(hipStream_t s, const EnvState &S, const Batch &B, const Lists &L) {
   IPC_LAUNCH(k_act_seg, nblk(B.n_envs, 64), 64, s)(S, B.envs, B.n_envs, L.cand_offs);
 }
-void barrier_elems(hipStream_t s, const WorldDev &W, const EnvDev *E, const Lists &L, int n_act, const double *x) {
-  if (n_act)
-    IPC_LAUNCH(k_barrier_elems, nblk(n_act, 128), 128, s)(W, E, L.act, L.act_type, n_act, x, L.ce_v, L.ce_g, L.ce_H);
+void act_stats(hipStream_t s, const EnvDev *E, const EnvState &S, const Batch &B, const Lists &L, int adapt) {
+  if (B.n_envs) IPC_LAUNCH(k_act_stats, B.n_envs, TB, s)(E, S, B.envs, L.act_d2, adapt);
 }
-void friction_setup(hipStream_t s, const WorldDev &W, const EnvDev *E, const Lists &L, int n_act) {
+void barrier_elems(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Lists &L, int n_act,
+                   const double *x) {
   if (n_act)
-    IPC_LAUNCH(k_friction_setup, nblk(n_act, TB), TB, s)(W, E, L.act, L.act_type, n_act, L.fv, L.fw, L.fn, L.flam, L.fenv);
+    IPC_LAUNCH(k_barrier_elems, nblk(n_act, 128), 128, s)(W, E, S.kappa, L.act, L.act_type, n_act, x, L.ce_v, L.ce_g,
+                                                          L.ce_H);
+}
+void friction_setup(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Lists &L, int n_act) {
+  if (n_act)
+    IPC_LAUNCH(k_friction_setup, nblk(n_act, TB), TB, s)(W, E, S.kappa, L.act, L.act_type, n_act, L.fv, L.fw, L.fn,
+                                                         L.flam, L.fenv);
 }
 void friction_elems(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Lists &L, int n_fric,
                     int ce_off, const double *x) {
@@ -2345,6 +2462,13 @@ void accd(hipStream_t s, const WorldDev &W, const EnvDev *, const EnvState &S, c
           const double *p) {
   if (n) IPC_LAUNCH(k_accd, nblk(n, 128), 128, s)(W, S, L.cand, n, x, p);
 }
+void inv_bound(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, int force) {
+  if (B.n_tt) IPC_LAUNCH(k_inv_bound, B.n_tt, TB, s)(W, E, S, B.ttiles, force);
+}
+void relag(hipStream_t s, const EnvDev *E, const EnvState &S, const Batch &B, int *n_relag) {
+  IPC_LAUNCH(k_fill_int, 1, 64, s)(n_relag, 1, 0);
+  IPC_LAUNCH(k_relag, nblk(B.n_envs, 64), 64, s)(E, S, B.envs, B.n_envs, n_relag);
+}
 void ls_init(hipStream_t s, const EnvState &S, const Batch &B) {
   IPC_LAUNCH(k_ls_init, nblk(B.n_envs, 64), 64, s)(S, B.envs, B.n_envs);
 }
@@ -2387,6 +2511,16 @@ void dbg_pair(hipStream_t s, int kind, int type, const double *x12, double dhat,
 }
 void dbg_tet(hipStream_t s, const double *X12, const double *x12, double mu, double la, double *out) {
   IPC_LAUNCH(k_dbg_tet, 1, 64, s)(X12, x12, mu, la, out);
+}
+int pairs_ccd_parts(int64_t n) { return (int)((n + kCcdBlock - 1) / kCcdBlock); }
+void pairs_ccd_bound(hipStream_t s, int kind, int n, const double *x12, const double *p12, double sfac, double *part,
+                     double *out) {
+  const int nb = pairs_ccd_parts(n);
+  if (nb) IPC_LAUNCH(k_pairs_ccd_min, nb, kCcdBlock, s)(kind, n, x12, p12, sfac, part);
+  IPC_LAUNCH(k_min_reduce, 1, TB, s)(part, nb, out);
+}
+void dbg_tet_root(hipStream_t s, int n, const double *x12, const double *p12, double tmax, double *t, double *k4) {
+  if (n) IPC_LAUNCH(k_dbg_tet_root, nblk(n, 64), 64, s)(n, x12, p12, tmax, t, k4);
 }
 void dbg_accd(hipStream_t s, int kind, int n, const double *x12, const double *p12, double sfac, double *t) {
   if (n) IPC_LAUNCH(k_dbg_accd, nblk(n, 128), 128, s)(kind, n, x12, p12, sfac, t);

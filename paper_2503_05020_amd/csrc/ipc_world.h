@@ -49,6 +49,11 @@ struct EnvDev {
   double dt, dhat, kappa, mu, eps_v, tol, pcg_tol;
   double cell;                   // hash-grid cell size of this environment
   double mbar;                   // mean free-vertex mass (augmented-Lagrangian weight mbar / dt^2)
+  // solver variants
+  int fric_iters;                // lagged friction updates per step (>= 1)
+  int inv_filter;                // 1: the inversion filter bounds the line search
+  int adapt_kappa;               // 1: kappa adapts to the least active-pair distance
+  int pad_v;
 };
 
 // Per-environment solver state (device arrays indexed by slot).
@@ -65,6 +70,14 @@ struct EnvState {
   int *al, *al_action, *snap_bad;
   double *kA, *viol, *viol_prev;
   double *pcg_bb;                 // |g|^2 of the current solve
+  // barrier stiffness (adapted per iterate with adapt_kappa), its given value,
+  // and the least active-pair distance at the previous Newton iterate
+  double *kappa, *kappa0, *dmin_prev;
+  // active pairs and least squared distance among them at the last
+  // classified iterate; friction lag rounds done this step; the Newton
+  // iteration count at which the current round fails
+  int *nact, *lag, *iter_cap;
+  double *dmin2;
   // PCG step length and r.u of the last two iterations (slot = iteration & 1)
   double *cg_a0, *cg_a1, *cg_g0, *cg_g1;
 };

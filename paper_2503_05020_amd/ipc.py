@@ -42,6 +42,8 @@ class ipc_scene_desc(C.Structure):
         ("dt", C.c_double), ("dhat", C.c_double), ("kappa", C.c_double), ("mu", C.c_double),
         ("eps_v", C.c_double), ("newton_tol", C.c_double), ("newton_max_iter", C.c_int32),
         ("pcg_rel_tol", C.c_double), ("precision", C.c_int32),
+        ("newton_rel_tol", C.c_double), ("friction_iters", C.c_int32), ("inversion_filter", C.c_int32),
+        ("adaptive_kappa", C.c_int32),
     ]
 
 
@@ -50,7 +52,7 @@ class ipc_step_info(C.Structure):
         ("steps_done", C.c_int32), ("status", C.c_int32), ("fail_reason", C.c_int32),
         ("newton_iters", C.c_int32), ("max_newton_iters", C.c_int32), ("ls_halvings", C.c_int32),
         ("pcg_iters", C.c_int64), ("n_active_last", C.c_int64), ("min_dist_last", C.c_double),
-        ("energy_last", C.c_double),
+        ("energy_last", C.c_double), ("kappa_last", C.c_double),
     ]
 
     def as_dict(self):
@@ -62,7 +64,8 @@ EXPORTS = [
     "ipc_last_error", "ipc_scene_sizes", "ipc_debug_candidates", "ipc_debug_active", "ipc_debug_begin_step",
     "ipc_debug_gradient", "ipc_debug_energy", "ipc_debug_hessian_apply", "ipc_debug_newton_dir",
     "ipc_debug_ccd_bound", "ipc_debug_classify", "ipc_debug_pair_barrier", "ipc_debug_tet_elastic",
-    "ipc_debug_accd", "ipc_prof_enable", "ipc_prof_reset", "ipc_prof_read", "ipc_set_tuning", "ipc_get_tuning",
+    "ipc_debug_accd", "ipc_debug_inversion_bound", "ipc_debug_tet_first_root", "ipc_ccd_bound_pairs",
+    "ipc_prof_enable", "ipc_prof_reset", "ipc_prof_read", "ipc_set_tuning", "ipc_get_tuning",
     "ipc_server_create", "ipc_server_submit", "ipc_server_poll", "ipc_server_wait", "ipc_server_result",
     "ipc_server_release", "ipc_server_set_slots", "ipc_server_stats", "ipc_server_destroy",
 ]
@@ -119,6 +122,11 @@ def lib():
     L.ipc_debug_tet_elastic.argtypes = [_dp, _dp, C.c_double, C.c_double, C.c_int32, _dp, _dp, _dp]
     L.ipc_debug_accd.argtypes = [C.c_int32, C.c_int64, _dp, _dp, C.c_double, _dp]
     L.ipc_debug_accd.restype = C.c_int64
+    L.ipc_ccd_bound_pairs.argtypes = [C.c_int32, C.c_int64, _dp, _dp, C.c_double, _dp]
+    L.ipc_debug_inversion_bound.argtypes = [vp, _dp, _dp]
+    L.ipc_debug_inversion_bound.restype = C.c_double
+    L.ipc_debug_tet_first_root.argtypes = [C.c_int64, _dp, _dp, C.c_double, _dp, _dp]
+    L.ipc_debug_tet_first_root.restype = C.c_int64
     L.ipc_prof_enable.argtypes = [C.c_int32]
     L.ipc_prof_read.argtypes = [_dp]
     L.ipc_set_tuning.argtypes = [C.c_int32, C.c_int64]
@@ -188,7 +196,8 @@ def make_desc(sc: dict, precision: int = IPC_FP64, pcg_rel_tol: float = 1e-4, **
         len(keep["tris"]) // 3, _i(keep["tris"]), _i(keep["kin"]),
         motion.shape[1], motion.shape[0], _d(keep["motion"]), _d(keep["gravity"]),
         p["dt"], p["dhat"], p["kappa"], p["mu"], p["eps_v"], p["newton_tol"], int(p["newton_max_iter"]),
-        pcg_rel_tol, precision)
+        pcg_rel_tol, precision, float(p.get("newton_rel_tol", 0.0)), int(p.get("friction_iters", 1)),
+        int(p.get("inversion_filter", 0)), int(p.get("adaptive_kappa", 0)))
     return d, keep
 
 
@@ -405,6 +414,30 @@ def ipc_debug_newton_dir(scene, x):
 
 def ipc_debug_ccd_bound(scene, x, p):
     return lib().ipc_debug_ccd_bound(scene.h, _d(_f64(x)), _d(_f64(p)))
+
+
+def ipc_ccd_bound_pairs(kind, x12, p12, s=0.1):
+    """min(1, min over the pairs of the additive-CCD time of impact) for pairs of one kind."""
+    x12 = _f64(x12).reshape(-1, 12)
+    p12 = _f64(p12).reshape(-1, 12)
+    a = C.c_double()
+    _check(lib().ipc_ccd_bound_pairs(kind, len(x12), _d(x12), _d(p12), s, C.byref(a)))
+    return a.value
+
+
+def ipc_debug_inversion_bound(scene, x, p):
+    return lib().ipc_debug_inversion_bound(scene.h, _d(_f64(x)), _d(_f64(p)))
+
+
+def ipc_debug_tet_first_root(x12, p12, tmax=1.25):
+    """Per tet: first root of det(Ds(x + t p)) in (0, tmax] and the cubic's coefficients [n, 4]."""
+    x12 = _f64(x12).reshape(-1, 12)
+    p12 = _f64(p12).reshape(-1, 12)
+    n = len(x12)
+    t = np.zeros(n)
+    k = np.zeros((n, 4))
+    _check(lib().ipc_debug_tet_first_root(n, _d(x12), _d(p12), tmax, _d(t), _d(k)))
+    return t, k
 
 
 def ipc_debug_classify(kind, x12):

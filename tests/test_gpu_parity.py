@@ -106,6 +106,25 @@ def test_accd_matches_oracle(kind):
     assert np.allclose(tg, to, rtol=1e-9, atol=1e-12)
 
 
+@pytest.mark.parametrize("kind", [0, 1])
+def test_ccd_bound_over_pairs_matches_oracle(kind):
+    """min(1, min_k ACCD_k) over pair lists of several sizes (one block, several blocks with a ragged tail,
+    empty): equal to the minimum of the oracle's per-pair times (ties broken by the exact minimum)."""
+    rng = np.random.default_rng(91 + kind)
+    for n in (1, 127, 128, 1000, 4097):
+        x = rng.uniform(-1, 1, (n, 4, 3))
+        p = rng.uniform(-0.3, 0.3, (n, 4, 3))
+        ag = G.ipc_ccd_bound_pairs(kind, x.reshape(-1, 12), p.reshape(-1, 12))
+        ao = min(1.0, min(O.accd(kind, x[i], p[i]) for i in range(n)))
+        say(f"kind {kind} n {n}: gpu {ag:.17g} oracle {ao:.17g}")
+        assert ag == pytest.approx(ao, rel=1e-9, abs=1e-15)
+        # the pair holding the minimum gives the same time alone
+        if ao < 1.0:
+            i = int(np.argmin([O.accd(kind, x[j], p[j]) for j in range(n)]))
+            assert G.ipc_ccd_bound_pairs(kind, x[i:i + 1].reshape(-1, 12), p[i:i + 1].reshape(-1, 12)) == ag
+    assert G.ipc_ccd_bound_pairs(kind, np.zeros((0, 12)), np.zeros((0, 12))) == 1.0
+
+
 # ---------------------------------------------------------------------------
 # scene level
 # ---------------------------------------------------------------------------
