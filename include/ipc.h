@@ -213,6 +213,12 @@ int ipc_prof_read(double *out);
 #define IPC_TUNE_FUSED_PCG 2
 #define IPC_TUNE_NARROW 4
 #define IPC_TUNE_LANES 5
+/* Test hook, not an execution knob: the next `value` scene placements on
+ * each lane of the current device fail as if the device were out of memory
+ * (ipc_create_scene returns IPC_E_NOMEM; a server retires the request with
+ * IPC_FAIL_ADMIT and goes on).  Lets the failure path be tested without
+ * exhausting the GPU. */
+#define IPC_TUNE_ADMIT_FAULTS 6
 int ipc_set_tuning(int32_t key, int64_t value);
 int ipc_get_tuning(int32_t key, int64_t *value);
 
@@ -323,6 +329,8 @@ typedef struct {
 } ipc_request_info;
 
 #define IPC_FAIL_DEVICE 5 /* the server's worker hit a device error and stopped */
+#define IPC_FAIL_ADMIT 6  /* the request could not be placed on the device (out of memory);
+                             the server goes on with the others                          */
 
 /* Creates a server on the current device.  budget_bytes > 0; max_slots >= 1
  * fixes the slot cap, max_slots = 0 lets the server tune it: starting at 8

@@ -38,7 +38,12 @@ using ipcw::WorldDev;
 
 namespace {
 
-thread_local std::string g_err;
+// message of the last error on this thread (fixed storage: setting it never allocates)
+thread_local char g_err[512];
+void set_err(const char *m) {
+  std::strncpy(g_err, m ? m : "", sizeof g_err - 1);
+  g_err[sizeof g_err - 1] = 0;
+}
 
 struct ApiError : std::runtime_error {
   int code;
@@ -733,7 +738,7 @@ struct World {
 
   // device bytes of a scene's resident state (every array registered with
   // the arenas, at the scene's element counts)
-  size_t scene_bytes(const HostScene &H) const {
+  size_t resident_bytes(const HostScene &H) const {
     auto ab = [](const Arena &a, size_t n) {
       size_t e = 0;
       for (const RawBuf &b : a.bufs) e += b.elem;
@@ -743,6 +748,26 @@ struct World {
            ab(aContrib, H.contrib.size()) + ab(aVT, H.vt_ent.size()) + ab(aMo, H.motion.size()) +
            ab(aSlice, (H.nv_pad + ipcw::kSlice - 1) / ipcw::kSlice);
   }
+  // The serving admission charge of a scene: its resident bytes, half again
+  // for the arenas' growth slack (they grow by 1.5x), and an estimate of its
+  // share of the lane's per-step work buffers, which scale with the scene's
+  // surface: per broad-phase query the counts, offsets and pair stash; per
+  // grid item its entries (a box spans at most 8 cells before it goes to the
+  // per-environment list, 2 on average); 16 candidate pairs per query with
+  // their type, flags, squared distance and energy; one contact element per
+  // surface vertex (4 blocks per row in the merged contact rows); the
+  // vertex-tile partials.  Lists longer than that grow the lane's buffers
+  // beyond the charge.
+  size_t work_bytes(const HostScene &H) const {
+    const size_t items = (size_t)H.nsv + H.ne, grid = (size_t)H.ntri + H.ne;
+    size_t b = items * (8 + 8 * (size_t)stash_n);
+    b += grid * (2 * 2 * sizeof(ipck::GridEnt) + 6 * 4);
+    b += items * 16 * (8 + 4 + 4 + 4 + 8 + 8 + 8 + 4 + 8);
+    b += (size_t)H.nsv * ((16 + 96 + 720) + 4 * 4 * (4 * 4 + 36 + 72));
+    b += (size_t)H.nv_pad * 4 * 7 + (H.nv_pad / ipcw::kTile + 1) * 40;
+    return b;
+  }
+  size_t scene_bytes(const HostScene &H) const { return resident_bytes(H) * 3 / 2 + work_bytes(H); }
 
   int add_scene(const HostScene &H) {
     int slot = -1;
@@ -778,9 +803,29 @@ struct World {
     R.contrib_off = aContrib.alloc(R.contrib_n);
     R.vt_off = aVT.alloc(R.vt_n);
     R.mo_off = aMo.alloc(R.mo_n);
+    const size_t slice_top = aSlice.top;
     aSlice.top = std::max(aSlice.top, aV.top / ipcw::kSlice);
-    if ((aT.top + 1) * 32 >= (size_t)1 << 31) throw ApiError(IPC_E_NOMEM, "world tet index space exhausted");
-    for (Arena *a : {&aV, &aT, &aTri, &aE, &aSV, &aPos, &aContrib, &aVT, &aMo, &aSlice}) a->reserve(stream);
+    try {
+      if (admit_faults > 0) {
+        --admit_faults;
+        throw ApiError(IPC_E_NOMEM, "admission fault planted by IPC_TUNE_ADMIT_FAULTS");
+      }
+      if ((aT.top + 1) * 32 >= (size_t)1 << 31) throw ApiError(IPC_E_NOMEM, "world tet index space exhausted");
+      for (Arena *a : {&aV, &aT, &aTri, &aE, &aSV, &aPos, &aContrib, &aVT, &aMo, &aSlice}) a->reserve(stream);
+      upload_scene(H, slot);
+    } catch (...) {
+      // leave the world as it was: ranges released, slot free
+      remove_scene(slot);
+      aSlice.top = std::max(slice_top, aV.top / ipcw::kSlice);
+      throw;
+    }
+    batch_envs.clear();  // tile lists must be rebuilt
+    return slot;
+  }
+
+  // copies a scene into its allocated ranges (slot's record filled in)
+  void upload_scene(const HostScene &H, int slot) {
+    EnvRec &R = recs[slot];
     size_t vo = R.v_off, to = R.t_off;
     // vertices (padded rows: zero position, kin = PAD)
     std::vector<double> X(3 * R.v_n, 0.0), x(3 * R.v_n, 0.0), v(3 * R.v_n, 0.0), m(R.v_n, 0.0);
@@ -898,8 +943,6 @@ struct World {
     HC(hipMemcpyAsync(S.kappa0 + slot, &kap, 8, hipMemcpyHostToDevice, stream));
     HC(hipMemcpyAsync(S.dmin_prev + slot, &inf, 8, hipMemcpyHostToDevice, stream));
     HC(hipStreamSynchronize(stream));
-    batch_envs.clear();  // tile lists must be rebuilt
-    return slot;
   }
 
   void remove_scene(int slot) {
@@ -1213,6 +1256,7 @@ struct World {
   // and the exact d² < d̂² test picks the same active set.  -1: none.
   int swept_n = -1;
   long long live_tets = 0;  // tets of the scenes living here (lane placement)
+  int admit_faults = 0;     // test hook: the next add_scene calls fail as out of memory
 
   // gradient, contact elements, incidence, assembled Hessian at W.x
   int assemble_system(int mixed) {
@@ -1572,10 +1616,10 @@ namespace {
 
 int api_error(const std::exception &e) {
   if (auto *a = dynamic_cast<const ApiError *>(&e)) {
-    g_err = a->what();
+    set_err(a->what());
     return a->code;
   }
-  g_err = e.what();
+  set_err(e.what());
   return IPC_E_DEVICE;
 }
 
@@ -1795,6 +1839,10 @@ struct ipc_server_s {
   std::condition_variable cv_work, cv_done;
   std::deque<Request *> queue;
   std::vector<std::vector<Request *>> running;  // per lane
+  // per lane: requests taken off the queue and being placed on the device
+  // (their bytes and slot are already counted); a device error retires them
+  // with the running ones
+  std::vector<std::vector<Request *>> admitting;
   std::map<int64_t, std::unique_ptr<Request>> reqs;
   int64_t next_id = 1, used = 0;
   int n_running = 0;  // over all lanes, admitted requests included
@@ -1868,6 +1916,7 @@ void autotune_tick(ipc_server_s *sv, long long tick_steps) {
 void server_loop(ipc_server_s *sv, size_t k) {
   World *w = sv->lanes[k];
   std::vector<Request *> &mine = sv->running[k];
+  std::vector<Request *> &admitting = sv->admitting[k];
   std::vector<ipc_step_info> infos;
   try {
     HC(hipSetDevice(w->device));
@@ -1877,32 +1926,67 @@ void server_loop(ipc_server_s *sv, size_t k) {
         std::unique_lock<std::mutex> lk(sv->mu);
         sv->cv_work.wait(lk, [&]() { return sv->stop || sv->dead || !mine.empty() || can_admit(sv, mine.size()); });
         if (sv->stop || sv->dead) return;
-        while (can_admit(sv, mine.size() + admit.size())) {
+        while (can_admit(sv, mine.size() + admitting.size())) {
           Request *r = sv->queue.front();
           sv->queue.pop_front();
           sv->used += r->bytes;
           ++sv->n_running;
-          admit.push_back(r);
+          admitting.push_back(r);
         }
+        admit = admitting;
       }
+      bool freed = false;
       for (Request *r : admit) {
         auto *sc = new ipc_scene_s();
         sc->world = w;
+        bool placed = false;
         {
           std::lock_guard<std::mutex> lk(w->mu);
           try {
             sc->slot = w->add_scene(*r->host);
+            placed = true;
+          } catch (const ApiError &e) {
+            // out of device memory for this request alone: it fails, the
+            // others go on (add_scene left the lane as it was)
+            if (e.code != IPC_E_NOMEM) {
+              delete sc;
+              throw;
+            }
           } catch (...) {
             delete sc;
             throw;
           }
         }
-        sc->host = std::move(r->host);
         std::lock_guard<std::mutex> lk(sv->mu);
+        auto at = std::find(admitting.begin(), admitting.end(), r);
+        if (at != admitting.end()) admitting.erase(at);
+        if (sv->dead) {
+          // another lane's device error retired every request meanwhile
+          if (placed) {
+            std::lock_guard<std::mutex> wl(w->mu);
+            w->remove_scene(sc->slot);
+          }
+          delete sc;
+          return;
+        }
+        if (!placed) {
+          delete sc;
+          r->t_admit = sv->now();
+          retire(sv, r, true, IPC_FAIL_ADMIT);
+          --sv->n_running;
+          freed = true;
+          continue;
+        }
+        sc->host = std::move(r->host);
         r->scene = sc;
         r->status = IPC_REQ_RUNNING;
         r->t_admit = sv->now();
         mine.push_back(r);
+      }
+      if (freed) {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->cv_done.notify_all();
+        sv->cv_work.notify_all();
       }
       std::vector<Request *> run;
       {
@@ -1968,6 +2052,10 @@ void server_loop(ipc_server_s *sv, size_t k) {
       }
       lane.clear();
     }
+    for (auto &lane : sv->admitting) {
+      for (Request *r : lane) retire(sv, r, true, IPC_FAIL_DEVICE);
+      lane.clear();
+    }
     for (Request *r : sv->queue) {
       sv->used += r->bytes;  // retire() subtracts it again
       retire(sv, r, true, IPC_FAIL_DEVICE);
@@ -2007,7 +2095,7 @@ bool finished(const Request &r) { return r.status == IPC_REQ_DONE || r.status ==
 // ===========================================================================
 extern "C" {
 
-const char *ipc_last_error(void) { return g_err.c_str(); }
+const char *ipc_last_error(void) { return g_err; }
 
 int ipc_create_scene(const ipc_scene_desc *desc, ipc_scene *out) {
   return guarded([&]() {
@@ -2048,7 +2136,7 @@ int ipc_step_batch(ipc_scene *scenes, int32_t n, int32_t n_steps, ipc_step_info 
     run_steps(v, n_steps, infos);
     for (auto s : v)
       if (s->failed) {
-        g_err = failed_before ? "scene already failed" : "environment failed";
+        set_err(failed_before ? "scene already failed" : "environment failed");
         return IPC_E_FAILED;
       }
     return IPC_OK;
@@ -2116,7 +2204,8 @@ int ipc_set_tuning(int32_t key, int64_t value) {
       g_lanes = (int)value;
       return IPC_OK;
     }
-    if (key != IPC_TUNE_TAIL_TILES && key != IPC_TUNE_FUSED_PCG && key != IPC_TUNE_NARROW)
+    if (key != IPC_TUNE_TAIL_TILES && key != IPC_TUNE_FUSED_PCG && key != IPC_TUNE_NARROW &&
+        key != IPC_TUNE_ADMIT_FAULTS)
       throw ApiError(IPC_E_ARG, "unknown tuning key");
     for (World *pw : worlds_for_current_device()) {
       World &w = *pw;
@@ -2125,6 +2214,8 @@ int ipc_set_tuning(int32_t key, int64_t value) {
         w.tail_tiles = (int)std::min<int64_t>(value, 1 << 30);
       else if (key == IPC_TUNE_FUSED_PCG)
         w.set_fused(value != 0);
+      else if (key == IPC_TUNE_ADMIT_FAULTS)
+        w.admit_faults = (int)std::min<int64_t>(value, 1 << 30);
       else
         w.narrow = value != 0;
     }
@@ -2147,6 +2238,8 @@ int ipc_get_tuning(int32_t key, int64_t *value) {
       *value = w.fused_pcg;
     else if (key == IPC_TUNE_NARROW)
       *value = w.narrow;
+    else if (key == IPC_TUNE_ADMIT_FAULTS)
+      *value = w.admit_faults;
     else
       throw ApiError(IPC_E_ARG, "unknown tuning key");
     return IPC_OK;
@@ -2585,6 +2678,7 @@ int ipc_server_create(int64_t budget_bytes, int32_t max_slots, ipc_server *out) 
     sv->lanes = worlds_for_current_device();
     sv->lanes.resize(std::min<size_t>(sv->lanes.size(), (size_t)lanes_setting()));
     sv->running.resize(sv->lanes.size());
+    sv->admitting.resize(sv->lanes.size());
     sv->budget = budget_bytes;
     sv->auto_slots = max_slots == 0;
     sv->max_slots = sv->auto_slots ? 8 * (int32_t)std::max<size_t>(1, sv->lanes.size()) : max_slots;

@@ -15,28 +15,45 @@ def say(*a):
     print(*a, flush=True)
 
 
-def _cube(i, steps_height=0.002):
-    return S.soft_cube_drop(cells=2, edge=0.04, height=steps_height + 0.001 * i, seed=i)
+def _cube(i, steps_height=0.002, precision=G.IPC_FP64):
+    sc = S.soft_cube_drop(cells=2, edge=0.04, height=steps_height + 0.001 * i, seed=i)
+    sc["precision"] = precision
+    return sc
+
+
+def _sphere(precision):
+    """A small soft sphere resting on the ground between the two finger slabs: contact from the first
+    step (the configuration served by the benchmark is the sphere grasp in mixed precision)."""
+    sc = S.parallel_jaw_sphere(seed=3, radius=0.021, h=0.006)
+    sc["precision"] = precision
+    return sc
 
 
 def _run_alone(sc, n_steps):
-    g = G.ipc_create_scene(sc)
+    g = G.ipc_create_scene(sc, precision=sc.get("precision", G.IPC_FP64))
     rc, info = G.ipc_step(g, n_steps)
     pos, vel = G.ipc_get_state(g)
     G.ipc_destroy_scene(g)
     return rc, info, pos, vel
 
 
-def test_server_result_same_alone_and_in_mix():
-    say("server alone vs mix")
-    scs = [_cube(i) for i in range(5)]
+def _submit(srv, sc, n, **kw):
+    return G.ipc_server_submit(srv, sc, n, precision=sc.get("precision", G.IPC_FP64), **kw)
+
+
+@pytest.mark.parametrize("precision", [G.IPC_FP64, G.IPC_MIXED])
+def test_server_result_same_alone_and_in_mix(precision):
+    say("server alone vs mix", precision)
+    scs = [_cube(i, precision=precision) for i in range(4)]
+    scs.insert(2, _sphere(precision))
     steps = [6, 9, 4, 7, 5]
-    # request 2 through the plain API and through a server on its own
+    # request 2 (the sphere, in contact) through the plain API and through a server on its own
     rc, info, ref_pos, ref_vel = _run_alone(scs[2], steps[2])
     assert rc == 0 and info["steps_done"] == steps[2]
+    assert info["n_active_last"] > 0
     srv = G.ipc_server_create(1 << 30, 4)
     try:
-        rid = G.ipc_server_submit(srv, scs[2], steps[2])
+        rid = _submit(srv, scs[2], steps[2])
         inf = G.ipc_server_wait(srv, rid, 120.0)
         assert inf["status"] == G.IPC_REQ_DONE and inf["steps_done"] == steps[2], inf
         pos, vel = G.ipc_server_result(srv, rid)
@@ -49,7 +66,7 @@ def test_server_result_same_alone_and_in_mix():
     try:
         ids = []
         for k, (sc, n) in enumerate(zip(scs, steps)):
-            ids.append(G.ipc_server_submit(srv, sc, n))
+            ids.append(_submit(srv, sc, n))
             time.sleep(0.02 * k)
         infos = [G.ipc_server_wait(srv, i, 300.0) for i in ids]
         for i, inf in zip(ids, infos):
@@ -135,4 +152,37 @@ def test_server_autotuned_slots():
         say(st)
         assert st["slot_cap"] >= 8 and st["finished"] == len(scs)
     finally:
+        G.ipc_server_destroy(srv)
+
+
+def test_server_admission_failure_fails_only_that_request():
+    """A placement that runs out of device memory (planted from the host with the IPC_TUNE_ADMIT_FAULTS
+    hook) fails that request with IPC_FAIL_ADMIT; the server keeps serving, every other request completes
+    with its alone result, and the budget accounting returns to zero."""
+    scs = [_cube(i) for i in range(4)]
+    srv = G.ipc_server_create(1 << 30, 8)
+    try:
+        G.ipc_set_tuning(G.IPC_TUNE_ADMIT_FAULTS, 1)
+        ids = [G.ipc_server_submit(srv, sc, 3) for sc in scs]
+        infos = [G.ipc_server_wait(srv, i, 120.0) for i in ids]
+        G.ipc_set_tuning(G.IPC_TUNE_ADMIT_FAULTS, 0)  # lanes that admitted nothing keep theirs
+        failed = [k for k, inf in enumerate(infos) if inf["status"] == G.IPC_REQ_FAILED]
+        say("admission failures", failed, [inf["fail_reason"] for inf in infos])
+        assert 1 <= len(failed) <= G.ipc_get_tuning(G.IPC_TUNE_LANES)
+        for k, inf in enumerate(infos):
+            if k in failed:
+                assert inf["fail_reason"] == G.IPC_FAIL_ADMIT
+            else:
+                assert inf["status"] == G.IPC_REQ_DONE and inf["steps_done"] == 3, inf
+                _, _, p_alone, _ = _run_alone(scs[k], 3)
+                assert np.array_equal(G.ipc_server_result(srv, ids[k])[0], p_alone)
+        # the server still admits and runs new requests
+        again = G.ipc_server_submit(srv, scs[failed[0]], 3)
+        inf = G.ipc_server_wait(srv, again, 120.0)
+        assert inf["status"] == G.IPC_REQ_DONE, inf
+        st = G.ipc_server_stats(srv)
+        assert st["running"] == 0 and st["queued"] == 0 and st["bytes_in_use"] == 0
+        assert st["finished"] + st["failed"] == len(scs) + 1 and st["failed"] == len(failed)
+    finally:
+        G.ipc_set_tuning(G.IPC_TUNE_ADMIT_FAULTS, 0)
         G.ipc_server_destroy(srv)
