@@ -50,14 +50,18 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def make_scenes(workload: str, n_envs: int):
+def make_scene(workload: str, i: int):
     if workload == "superquadric_batch":
-        return [S.superquadric_grasp(i) for i in range(n_envs)]
+        return S.superquadric_grasp(i)
     if workload == "sphere_grasp":
-        return [S.parallel_jaw_sphere(seed=i) for i in range(n_envs)]
+        return S.parallel_jaw_sphere(seed=i)
     if workload == "cube_drop":
-        return [S.soft_cube_drop(seed=i) for i in range(n_envs)]
+        return S.soft_cube_drop(seed=i)
     raise SystemExit(f"unknown workload {workload}")
+
+
+def make_scenes(workload: str, n_envs: int):
+    return [make_scene(workload, i) for i in range(n_envs)]
 
 
 def run_gpu(scs, precision, warmup, steps, pcg_tol, label, count_all=False):
@@ -104,24 +108,67 @@ def sequential_gpu(scs, precision, warmup, steps, pcg_tol, n):
     return dict(value=done / wall, envs=n)
 
 
-def cpu_baseline(scs, budget_s=20.0):
-    """The oracle (single thread) on the first environments of the same workload."""
+def _oracle_worker(args):
+    """One host process: the oracle on environments envs, each stepped `warmup` steps untimed and then
+    through the timed window (at most `steps` steps) until `budget_s` of timed stepping is spent."""
+    workload, n_envs, envs, warmup, steps, budget_s = args
     import oracle as O
-    t_start = time.perf_counter()
-    done = 0
-    env = 0
-    while time.perf_counter() - t_start < budget_s and env < len(scs):
-        o = O.Scene(scs[env], pcg_rel_tol=1e-4)
-        while time.perf_counter() - t_start < budget_s:
-            rc, info = o.step(1)
+    done, timed = 0, 0.0
+    used = []
+    for e in envs:
+        if timed >= budget_s:
+            break
+        o = O.Scene(make_scene(workload, e), pcg_rel_tol=1e-4)
+        rc, _ = o.step(warmup)
+        if rc != 0:
+            continue
+        used.append(e)
+        for _ in range(steps):
+            t0 = time.perf_counter()
+            rc, _ = o.step(1)
+            timed += time.perf_counter() - t0
             if rc != 0:
                 break
             done += 1
-        env += 1
-    wall = time.perf_counter() - t_start
-    return dict(value=round(done / wall, 3), unit="converged env-steps/s", cores=1, kind="oracle",
-                sample=f"{done} env-steps of environment(s) 0..{env - 1} from step 0 (contact from step ~12), "
-                       f"one thread, {wall:.1f}s")
+            if timed >= budget_s:
+                break
+    return done, timed, used
+
+
+def cpu_baseline(workload, n_envs, warmup, steps, budget_s=15.0):
+    """The oracle (single-threaded per environment, FP64, PCG tolerance 1e-4 as the GPU run) timed on the
+    host cores: one process per core, each taking environments spread over the whole batch, every
+    environment stepped to the GPU's first timed step untimed and then timed through the GPU's window;
+    throughput = timed converged env-steps over the timed seconds per process, summed over processes."""
+    import multiprocessing as mp
+    import platform
+    import subprocess
+    ncpu = os.cpu_count() or 1
+    try:
+        aff = len(os.sched_getaffinity(0))
+    except AttributeError:
+        aff = ncpu
+    procs = max(1, min(16, aff))
+    stride = max(1, n_envs // (procs * 4))
+    order = list(range(0, n_envs, stride))
+    jobs = [(workload, n_envs, order[k::procs], warmup, steps, budget_s) for k in range(procs)]
+    with mp.get_context("spawn").Pool(procs) as pool:
+        res = pool.map(_oracle_worker, jobs)
+    per_proc = [d / t for d, t, _ in res if t > 0]
+    done = sum(d for d, _, _ in res)
+    envs = sorted(e for _, _, u in res for e in u)
+    model = ""
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        model = next((ln.split(":", 1)[1].strip() for ln in out.splitlines() if ln.startswith("Model name")), "")
+    except Exception:
+        pass
+    return dict(value=round(sum(per_proc), 3), unit="converged env-steps/s", cores=procs, kind="oracle",
+                single_core=round(sum(d for d, _, _ in res) / max(1e-9, sum(t for _, t, _ in res)), 3),
+                nproc=ncpu, cpus_allowed=aff, lscpu_model=model or platform.processor(),
+                sample=f"{done} timed env-steps of {len(envs)} environments spread over the batch "
+                       f"({envs[:6]}...), each from step {warmup} (untimed before) through at most {steps} steps, "
+                       f"{procs} processes of one thread, about {budget_s:.0f} s of timed stepping each")
 
 
 def serving(n_req, rate, budget, slots, precision, n_steps=100):
@@ -243,7 +290,14 @@ def pmc_summary(d, copy_mib):
     print(json.dumps(res))
 
 
+def _bw(bytes_, ms):
+    return bytes_ / (ms * 1e-3) / 1e9
+
+
 def roofline(prof, precision):
+    """k_spmv (the dominant kernel): the event-timed launches' algorithmic bytes over their time (the bytes
+    are counted by a separate launch, so no counting runs inside the timed kernel); beside it the whole PCG
+    iteration (product + update) and the assembly pass against the same HBM peak."""
     if prof["spmv_launches"] <= 0 or prof["spmv_ms"] <= 0:
         return None
     avg_ms = prof["spmv_ms"] / prof["spmv_launches"]
@@ -261,6 +315,19 @@ def roofline(prof, precision):
         out["large_launches"] = {"achieved": round(bb / (bms * 1e-3) / 1e9, 1), "frac": round(bb / (bms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                                  "avg_launch_us": round(bms * 1e3, 2), "bytes_per_launch": int(bb),
                                  "launches_timed": int(prof["big_launches"])}
+    if prof["iters"] > 0 and prof["iter_ms"] > 0:
+        a = _bw(prof["iter_bytes"], prof["iter_ms"])
+        out["pcg_iteration"] = {"achieved": round(a, 1), "frac": round(a / HBM_PEAK_GBS, 4),
+                                "avg_us": round(1e3 * prof["iter_ms"] / prof["iters"], 2),
+                                "bytes_per_iteration": int(prof["iter_bytes"] / prof["iters"]),
+                                "kernels": ["k_spmv", "k_pcg_update"], "iterations_timed": prof["iters"]}
+    if prof["asm_passes"] > 0 and prof["asm_ms"] > 0:
+        a = _bw(prof["asm_bytes"], prof["asm_ms"])
+        out["assembly"] = {"achieved": round(a, 1), "frac": round(a / HBM_PEAK_GBS, 4),
+                           "avg_us": round(1e3 * prof["asm_ms"] / prof["asm_passes"], 2),
+                           "bytes_per_pass": int(prof["asm_bytes"] / prof["asm_passes"]),
+                           "kernels": ["k_elastic", "k_assemble_rows", "k_assemble_sell"],
+                           "passes_timed": prof["asm_passes"]}
     return out
 
 
@@ -274,6 +341,8 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "mixed", "both"], default="both")
     ap.add_argument("--pcg-tol", type=float, default=1e-4)
     ap.add_argument("--sequential-envs", type=int, default=8)
+    ap.add_argument("--full-horizon", type=int, default=100,
+                    help="also time this many steps from step 0 (the whole grasp) per precision; 0 skips")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=48, help="0 skips the serving run")
     ap.add_argument("--serve-slots", type=int, default=0, help="0 = slot cap tuned by the server")
@@ -330,7 +399,17 @@ def main():
     if args.serve_requests > 0:
         serve = serving(args.serve_requests, 50.0, 200 << 30, args.serve_slots, G.IPC_MIXED)
         log(f"[serving] {serve}")
-    cpu = None if args.no_cpu_baseline else cpu_baseline(scs)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(args.workload, len(scs), args.warmup, args.steps)
+    horizon = None
+    if args.full_horizon > 0:
+        # the whole grasp (closing with gravity off, gravity from step 60), both precisions
+        horizon = {}
+        for p in precs:
+            h = run_gpu(scs, G.IPC_MIXED if p == "mixed" else G.IPC_FP64, 0, args.full_horizon, args.pcg_tol,
+                        f"{p} horizon")
+            horizon[p] = {"value": round(h["value"], 2), "steps": args.full_horizon, "failed_envs": h["failed"],
+                          "wall_s": round(h["wall"], 2)}
+            log(f"[{p}] full horizon: {h['value']:.1f} converged env-steps/s over steps 0..{args.full_horizon - 1}")
     out = {
         "metric": "converged sim steps/s over batched scenes",
         "value": round(r["value"], 2),
@@ -357,6 +436,8 @@ def main():
         f = results["fp64"]
         out["fp64"] = {"value": round(f["value"], 2), "ms_per_step": round(f["ms_per_step"], 2),
                        "failed_envs": f["failed"], "roofline": roofline(f["prof"], "fp64")}
+    if horizon:
+        out["full_horizon"] = horizon
     if seq:
         out["sequential_single_env"] = {"value": round(seq["value"], 3), "envs": seq["envs"],
                                         "speedup_batched_vs_sequential": round(r["value"] / seq["value"], 2)}

@@ -154,19 +154,27 @@ const char *ipc_last_error(void);
  * out[6] failed flag. */
 int ipc_scene_sizes(ipc_scene s, int64_t out[7]);
 
-/* Measurement of the tiled PCG matrix-vector product on the current device:
- * when enabled, every 16th launch of that kernel (iterations 5, 21, 37, ...
- * of each solve) is bracketed by HIP events on the library's stream, and
- * those launches add the algorithmic bytes they move (stored blocks and
- * column indices, one read and one write of a vector row, contact blocks
- * applied) to a device counter.  ipc_prof_read writes out[0] total
- * event-timed milliseconds, out[1] number of timed launches, out[2] their
- * bytes, and out[3..5] the same three for the timed launches over more than
- * 64 tiles (out has 6 entries).  Sums over the lanes of the device.
- * ipc_prof_enable(2) instead counts the bytes of every launch of the kernel
- * and times none of them (out[0] stays 0, out[1] counts every launch): the
- * algorithmic bytes of the same launches that a hardware counter run over
- * the whole program sees.  ipc_prof_enable(0) turns measurement off. */
+/* Measurement on the current device (sums over its lanes).  When enabled,
+ * every 16th PCG iteration of each solve (iterations 5, 21, 37, ...) has its
+ * matrix-vector product and its update each bracketed by HIP events on the
+ * library's stream, and a separate launch between the two kernels (outside
+ * both timings) adds the iteration's algorithmic bytes to device counters:
+ * for the product the stored 3x3 blocks and column indices (sliced ELL and
+ * merged contact blocks) plus one read of u and one write of w per row; for
+ * the whole iteration the same blocks plus per row the preconditioner block
+ * and eight vector accesses of three values (N (9 s + 4) + n 9 s + 24 n s).
+ * Every assembly pass (elasticity, inertia, gradient and stored blocks) is
+ * bracketed too, its algorithmic bytes (per tet 208 B of inputs, per row
+ * 80 B, 9 s per stored block) counted the same way.  ipc_prof_read writes
+ * out[12]: out[0] product milliseconds, out[1] timed iterations, out[2] their
+ * product bytes; out[3..5] the same three for the timed products over more
+ * than 64 tiles; out[6] milliseconds of product + update of the timed
+ * iterations, out[7] their count, out[8] their whole-iteration bytes;
+ * out[9] assembly milliseconds, out[10] assembly passes, out[11] their bytes.
+ * ipc_prof_enable(2) instead counts the bytes of every iteration and times
+ * none (out[0] stays 0, out[1] counts every iteration): the algorithmic
+ * bytes of the same launches that a hardware counter run over the whole
+ * program sees.  ipc_prof_enable(0) turns measurement off. */
 int ipc_prof_enable(int32_t on);
 int ipc_prof_reset(void);
 int ipc_prof_read(double *out);
@@ -232,6 +240,91 @@ int ipc_get_tuning(int32_t key, int64_t *value);
  * IPC_E_ARG for a bad kind, n < 0, NULL pointers, non-finite data or s
  * outside (0, 1).  Uses a per-call device buffer of per-block minima. */
 int ipc_ccd_bound_pairs(int32_t kind, int64_t n, const double *x12, const double *p12, double s, double *alpha);
+
+/* Grasp-quality metrics of Sec. IV-C, Eq. (2)-(3), at the scene's current
+ * positions.  The manipuland is given by its closed boundary triangle mesh
+ * obj_tris [n_obj_tris*3] (scene vertex ids, outward oriented); its signed
+ * distance field d_o(p) is the distance from p to the nearest of those
+ * triangles, positive inside (generalised winding number above 1/2),
+ * negative outside.  The sample set S_h on the gripper's surface is given as
+ * n_samples points on the triangles hand_tris [n_hand_tris*3]: point k lies
+ * on triangle sample_tri[k] at barycentric (u, v) = sample_uv[2k..2k+1],
+ * p = (1-u-v) x0 + u x1 + v x2 (the paper samples 50,000 points; the caller
+ * draws them).  D[0] = D1 = max(0, max_p d_o(p)) (penetration depth), D[1] =
+ * D2 = |max_p d_o(p)| (gripper-manipuland gap, or the depth when they
+ * interpenetrate).  sdf [n_samples] receives every d_o(p) (may be NULL).
+ * IPC_E_ARG for indices out of range, u or v negative or u + v > 1, empty
+ * sets.  Host pointers; per-call device buffers. */
+int ipc_grasp_metrics(ipc_scene s, int32_t n_obj_tris, const int32_t *obj_tris, int32_t n_hand_tris,
+                      const int32_t *hand_tris, int32_t n_samples, const int32_t *sample_tri, const double *sample_uv,
+                      double *D, double *sdf);
+
+/* ---------------------------------------------------------------------------
+ * Grasp validation (Sec. III-D): gravity is off while the fingers close, a
+ * finger's motion is halted once its contact force exceeds 50 N, then gravity
+ * of 9.8 m/s^2 is applied along the six axis directions for 0.1 s each; the
+ * grasp is stable if the manipuland is still in contact with the gripper at
+ * the end and its centre of mass moves less than a threshold proportional to
+ * eps_v dt.  The controls below act on the following time steps.
+ * ------------------------------------------------------------------------- */
+
+/* Holds kinematic group `group` at motion row `row`: from the next step on
+ * its targets are those of row min(scheduled row, row); row = -1 releases it.
+ * IPC_E_ARG for a bad group or row < -1. */
+int ipc_hold_group(ipc_scene s, int32_t group, int32_t row);
+
+/* Overrides the gravity schedule with g [3] (m/s^2) for the following steps;
+ * g = NULL returns to the schedule. */
+int ipc_set_gravity(ipc_scene s, const double *g);
+
+/* Contact forces between tagged bodies at the scene's current positions:
+ * tags [n_verts] gives each vertex a body tag in [0, ntags) (others: ignored),
+ * out [ntags*ntags*3]: out[(a*ntags + b)*3 + k] is the force on the vertices
+ * tagged a exerted by those tagged b through the barrier: every active pair
+ * pushes its first side (the point, or the first edge) with lambda n and its
+ * second side with -lambda n, lambda = -kappa e b'(d), n the unit normal of
+ * the closest-point difference.  1 <= ntags <= 64. */
+int ipc_contact_forces(ipc_scene s, const int32_t *tags, int32_t ntags, double *out);
+
+#define IPC_MAX_FINGERS 8
+typedef struct {
+  const int32_t *vertex_tag;      /* [n_verts]: 0 the manipuland, f = 1..n_fingers finger f, -1 other */
+  int32_t n_fingers;              /* 1..IPC_MAX_FINGERS                                             */
+  const int32_t *finger_of_group; /* [n_groups]: the finger (1..n_fingers) a kinematic group drives,
+                                     0 none (ground, ...)                                          */
+  double force_limit;             /* 50 N: a finger halts once |force on it from the manipuland|
+                                     exceeds this                                                  */
+  int32_t max_close_steps;        /* closing steps at most (the motion schedule's rows drive them)   */
+  int32_t settle_steps;           /* steps with gravity off after closing                           */
+  int32_t phase_steps;            /* steps per gravity direction (0.1 s / dt = 10)                   */
+  double gravity;                 /* 9.8 m/s^2                                                      */
+  double com_factor;              /* threshold = com_factor * eps_v * dt on the centre-of-mass
+                                     displacement in each phase's last step                         */
+} ipc_grasp_protocol;
+
+typedef struct {
+  int32_t stable;                          /* in contact at the end and every phase below threshold */
+  int32_t in_contact;                      /* a finger touches the manipuland at the final step     */
+  int32_t failed, fail_reason;             /* the simulation failed (IPC_FAIL_*); stable = 0        */
+  int32_t steps_run;
+  int32_t halt_step[IPC_MAX_FINGERS];      /* step index at which finger f+1 halted, -1 never       */
+  double finger_force[IPC_MAX_FINGERS];    /* its contact force then (N)                            */
+  double com_shift[6];                     /* |COM displacement| over each gravity phase (m):
+                                              +x, -x, +y, -y, +z, -z                               */
+  double com_drift[6];                     /* |COM displacement| in each phase's last step (m)       */
+} ipc_grasp_result;
+
+/* Runs the protocol on a scene from its current state (the reading taken
+ * where the paper is brief): gravity off; up to max_close_steps steps of the
+ * motion schedule, after each the contact force of every finger from the
+ * manipuland, a finger whose force exceeds force_limit holding its groups at
+ * the row just reached; every finger still moving is then held where it is;
+ * settle_steps steps; then for +x, -x, +y, -y, +z, -z in turn gravity of that
+ * magnitude for phase_steps steps.  The scene is left at the final state with
+ * its holds and the last gravity override in place (release with
+ * ipc_hold_group(.., -1) / ipc_set_gravity(s, NULL)).  A simulation failure
+ * ends the protocol with r->failed set and IPC_OK returned. */
+int ipc_validate_grasp(ipc_scene s, const ipc_grasp_protocol *p, ipc_grasp_result *r);
 
 /* ---------------------------------------------------------------------------
  * Inspection entry points.  Each runs the same device kernels the step uses,

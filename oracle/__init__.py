@@ -109,6 +109,9 @@ def lib():
         L.ipco_inversion_bound.restype = C.c_double
         L.ipco_kappa.argtypes = [C.c_void_p]
         L.ipco_kappa.restype = C.c_double
+        L.ipco_contact_forces.argtypes = [C.c_void_p, _dp, _ip, C.c_int32, _dp]
+        L.ipco_hold_group.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
+        L.ipco_set_gravity.argtypes = [C.c_void_p, _dp]
         _lib = L
     return _lib
 
@@ -268,6 +271,18 @@ class Scene:
     @property
     def kappa(self):
         return lib().ipco_kappa(self.h)
+
+    def contact_forces(self, x, tags, ntags):
+        """[ntags, ntags, 3]: force on the vertices tagged a exerted by those tagged b, at x."""
+        out = np.zeros((ntags, ntags, 3))
+        _check(lib().ipco_contact_forces(self.h, _d(_f64(x)), _i(_i32(tags)), ntags, _d(out)))
+        return out
+
+    def hold_group(self, group, row):
+        _check(lib().ipco_hold_group(self.h, int(group), int(row)))
+
+    def set_gravity(self, g):
+        _check(lib().ipco_set_gravity(self.h, None if g is None else _d(_f64(g))))
 
     def debug_ls_offset(self, delta):
         """Test-only planted fault: delta is added to every line-search trial energy."""

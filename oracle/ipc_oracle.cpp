@@ -778,6 +778,12 @@ struct Scene {
   std::vector<double> iter_log;
   // test-only planted fault: added to every line-search trial energy
   double debug_ls_offset = 0.0;
+  // grasp-validation controls (Sec. III-D): a held kinematic group keeps the
+  // target of motion row hold[g] from then on (-1: follows its schedule); a
+  // gravity override replaces the schedule's gravity rows
+  std::vector<int> hold;
+  bool g_over = false;
+  double g_ovr[3] = {0, 0, 0};
 };
 
 bool is_kin(const Scene &s, int i) { return s.kin[i] >= 0; }
@@ -1544,14 +1550,16 @@ int begin_step(Scene &s, std::vector<double> &x0) {
   int n = s.step;
   int mrow = std::min(n + 1, s.nmotion - 1);
   int grow = std::min(n, s.nmotion - 1);
-  const double *g = &s.gravity[3 * grow];
+  const double *g = s.g_over ? s.g_ovr : &s.gravity[3 * grow];
   double h = s.dt;
   s.xn = s.x;
   s.xhat = s.x;
   s.xbar = s.x;
   for (int i = 0; i < s.nv; ++i) {
     if (is_kin(s, i)) {
-      const double *T = &s.motion[12L * (mrow * s.ngroups + s.kin[i])];
+      int row = mrow;
+      if (!s.hold.empty() && s.hold[s.kin[i]] >= 0) row = std::min(row, s.hold[s.kin[i]]);
+      const double *T = &s.motion[12L * (row * s.ngroups + s.kin[i])];
       const double *X = &s.X[3 * i];
       for (int r = 0; r < 3; ++r)
         s.xbar[3 * i + r] = T[4 * r] * X[0] + T[4 * r + 1] * X[1] + T[4 * r + 2] * X[2] + T[4 * r + 3];
@@ -2025,6 +2033,66 @@ double ipco_inversion_bound(void *h, const double *x, const double *p) {
 }
 
 double ipco_kappa(void *h) { return static_cast<Scene *>(h)->kappa; }
+
+// Contact force between tagged bodies at x (Sec. III-D halts a finger once its
+// contact force exceeds 50 N).  For every active pair the barrier pushes its
+// two sides apart along the unit normal n of the closest-point difference
+// (from the triangle / second edge toward the point / first edge) with
+// magnitude lambda = -kappa e b'(d): the first side receives +lambda n, the
+// second -lambda n.  out[(a ntags + b) 3 + k] sums, over the pairs whose first
+// side is tagged a and second side b (and the reverse, with the sign
+// flipped), the force exerted on a by b.  Vertices tagged outside [0, ntags)
+// are ignored.
+int ipco_contact_forces(void *h, const double *x, const int32_t *tags, int32_t ntags, double *out) {
+  Scene *s = static_cast<Scene *>(h);
+  if (!s || !x || !tags || ntags < 1 || !out) return fail(E_ARG, "bad arguments");
+  std::vector<double> xv(x, x + 3 * s->nv);
+  for (int k = 0; k < 3 * ntags * ntags; ++k) out[k] = 0.0;
+  std::vector<Pair> cand = candidates(*s, xv, nullptr);
+  for (const ActivePair &a : active_set(*s, xv, cand)) {
+    double xx[12], w[4];
+    gather12(xv, a.p.v, xx);
+    closest_weights(a.p.kind, a.type, xx, w);
+    double dv[3] = {0, 0, 0};
+    for (int i = 0; i < 4; ++i)
+      for (int k = 0; k < 3; ++k) dv[k] += w[i] * xx[3 * i + k];
+    double dn = std::sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+    double d = std::sqrt(a.d2), b[3];
+    barrier_scalar(d, s->dhat, b);
+    double e = 1.0;
+    if (a.p.kind == 1) {
+      V3 ea = sub(ld(xx + 3), ld(xx)), eb = sub(ld(xx + 9), ld(xx + 6));
+      V3 c3 = cross(ea, eb);
+      double c = dot(c3, c3), ex = eps_cross(*s, a.p);
+      if (c < ex) e = (c / ex) * (2.0 - c / ex);
+    }
+    double lambda = -s->kappa * e * b[1];
+    int ta = tags[a.p.v[0]], tb = tags[a.p.v[a.p.kind == 0 ? 1 : 2]];
+    if (ta < 0 || ta >= ntags || tb < 0 || tb >= ntags) continue;
+    for (int k = 0; k < 3; ++k) {
+      out[(ta * ntags + tb) * 3 + k] += lambda * dv[k] / dn;
+      out[(tb * ntags + ta) * 3 + k] -= lambda * dv[k] / dn;
+    }
+  }
+  return OK;
+}
+
+int ipco_hold_group(void *h, int32_t group, int32_t row) {
+  Scene *s = static_cast<Scene *>(h);
+  if (!s || group < 0 || group >= s->ngroups || row < -1) return fail(E_ARG, "bad arguments");
+  if (s->hold.empty()) s->hold.assign(s->ngroups, -1);
+  s->hold[group] = row;
+  return OK;
+}
+
+int ipco_set_gravity(void *h, const double *g) {
+  Scene *s = static_cast<Scene *>(h);
+  if (!s) return fail(E_ARG, "bad arguments");
+  s->g_over = g != nullptr;
+  if (g)
+    for (int k = 0; k < 3; ++k) s->g_ovr[k] = g[k];
+  return OK;
+}
 
 int ipco_debug_ls_offset(void *h, double delta) {
   static_cast<Scene *>(h)->debug_ls_offset = delta;

@@ -104,6 +104,13 @@ double ipco_tet_first_root(const double *x12, const double *p12, double tmax, do
 double ipco_inversion_bound(void *s, const double *x, const double *p);
 /* Current barrier stiffness of a scene. */
 double ipco_kappa(void *s);
+/* Grasp-validation controls (Sec. III-D).  Contact force between tagged bodies at x:
+ * out[(a*ntags + b)*3 + k] = force on the vertices tagged a exerted by those tagged b. */
+int ipco_contact_forces(void *s, const double *x, const int32_t *tags, int32_t ntags, double *out);
+/* Hold kinematic group `group` at motion row `row` from the next step on (-1 releases it). */
+int ipco_hold_group(void *s, int32_t group, int32_t row);
+/* Gravity override for the following steps (NULL: back to the schedule). */
+int ipco_set_gravity(void *s, const double *g);
 /* Test-only planted fault: delta added to every line-search trial energy. */
 int ipco_debug_ls_offset(void *s, double delta);
 

@@ -949,6 +949,56 @@ DEV double tet_inversion_bound(const double *x, const double *p) {
   return fmin(1.0, kInvSafety * t);
 }
 
+// -- grasp-quality metrics (Sec. IV-C): distance and solid angle of a triangle
+//    seen from a point -----------------------------------------------------------
+// Squared distance from p to the triangle (a, b, c) by the region of the
+// closest point: the barycentric coordinates of p's projection decide whether
+// the closest point is a vertex, a point on an edge, or interior.
+DEV double point_tri_dist2(d3 p, d3 a, d3 b, d3 c) {
+  const d3 ab = sub3(b, a), ac = sub3(c, a), ap = sub3(p, a);
+  const double d1 = dot3(ab, ap), d2 = dot3(ac, ap);
+  auto n2 = [](d3 v) { return v.x * v.x + v.y * v.y + v.z * v.z; };
+  auto at = [](d3 o, d3 e, double t) { return d3{o.x + t * e.x, o.y + t * e.y, o.z + t * e.z}; };
+  if (d1 <= 0.0 && d2 <= 0.0) return n2(ap);  // vertex a
+  const d3 bp = sub3(p, b);
+  const double d3_ = dot3(ab, bp), d4 = dot3(ac, bp);
+  if (d3_ >= 0.0 && d4 <= d3_) return n2(bp);  // vertex b
+  const double vc = d1 * d4 - d3_ * d2;
+  if (vc <= 0.0 && d1 >= 0.0 && d3_ <= 0.0) {  // edge ab
+    const double t = d1 / (d1 - d3_);
+    return n2(sub3(p, at(a, ab, t)));
+  }
+  const d3 cp = sub3(p, c);
+  const double d5 = dot3(ab, cp), d6 = dot3(ac, cp);
+  if (d6 >= 0.0 && d5 <= d6) return n2(cp);  // vertex c
+  const double vb = d5 * d2 - d1 * d6;
+  if (vb <= 0.0 && d2 >= 0.0 && d6 <= 0.0) {  // edge ac
+    const double t = d2 / (d2 - d6);
+    return n2(sub3(p, at(a, ac, t)));
+  }
+  const double va = d3_ * d6 - d5 * d4;
+  if (va <= 0.0 && (d4 - d3_) >= 0.0 && (d5 - d6) >= 0.0) {  // edge bc
+    const d3 bc = sub3(c, b);
+    const double t = (d4 - d3_) / ((d4 - d3_) + (d5 - d6));
+    return n2(sub3(p, at(b, bc, t)));
+  }
+  const double den = 1.0 / (va + vb + vc);  // interior: project onto the plane
+  const double v = vb * den, w = vc * den;
+  const d3 q = {a.x + ab.x * v + ac.x * w, a.y + ab.y * v + ac.y * w, a.z + ab.z * v + ac.z * w};
+  return n2(sub3(p, q));
+}
+
+// Signed solid angle of the oriented triangle (a, b, c) seen from p
+// (Van Oosterom and Strackee, 1983); the sum over a closed outward surface is
+// 4 pi inside and 0 outside.
+DEV double tri_solid_angle(d3 p, d3 a, d3 b, d3 c) {
+  const d3 u = sub3(a, p), v = sub3(b, p), w = sub3(c, p);
+  const double lu = sqrt(dot3(u, u)), lv = sqrt(dot3(v, v)), lw = sqrt(dot3(w, w));
+  const double num = dot3(u, cross3(v, w));
+  const double den = lu * lv * lw + dot3(u, v) * lw + dot3(u, w) * lv + dot3(v, w) * lu;
+  return 2.0 * atan2(num, den);
+}
+
 DEV void inv33(const double *M, double *R) {
   double det = det33(M);
   double id = 1.0 / det;

@@ -316,6 +316,11 @@ std::unique_ptr<HostScene> preprocess(const ipc_scene_desc *d) {
   if (H.n_groups > 0) H.motion.assign(d->motion, d->motion + 12L * H.n_groups * H.n_motion);
   H.motion.insert(H.motion.end(), d->gravity, d->gravity + 3L * H.n_motion);
   if (!finite_all(H.motion.data(), (long)H.motion.size())) throw ApiError(IPC_E_ARG, "non-finite motion");
+  // controls of the grasp-validation protocol after the schedule: per group
+  // the motion row it is held at (-1: none), then the gravity override
+  // (flag, g); see ipc_hold_group / ipc_set_gravity
+  H.motion.insert(H.motion.end(), (size_t)H.n_groups, -1.0);
+  H.motion.insert(H.motion.end(), 4, 0.0);
   H.dt = d->dt;
   H.dhat = d->dhat;
   H.kappa = d->kappa;
@@ -624,6 +629,9 @@ struct World {
   std::vector<hipEvent_t> ev_pool;
   double prof_ms = 0.0, prof_ms_big = 0.0;  // big: launches over more than kWideTiles tiles
   long long prof_launches = 0, prof_launches_big = 0;
+  double prof_ms_iter = 0.0, prof_ms_asm = 0.0;  // whole PCG iterations (product + update); assembly passes
+  long long prof_asm = 0;
+  std::vector<hipEvent_t> asm_ev;  // event pairs around the assembly passes of the current step
   int n_fric = 0;
   std::mutex mu;
 
@@ -932,6 +940,8 @@ struct World {
     E.cell = H.cell;
     E.mbar = H.mbar;
     E.fric_iters = H.fric_iters;
+    E.nnzb = 0;
+    for (int r : H.row_nnz) E.nnzb += r;
     E.inv_filter = H.inv_filter;
     E.adapt_kappa = H.adapt_kappa;
     upload_env(slot);
@@ -1122,7 +1132,7 @@ struct World {
     prof_all = mode == 2;
     const bool on = prof_on;
     if (on && !prof_bytes.p) {
-      prof_bytes.ensure(4);
+      prof_bytes.ensure(8);
       HC(hipMemsetAsync(prof_bytes.p, 0, 8 * prof_bytes.cap, stream));
       HC(hipStreamSynchronize(stream));
     }
@@ -1130,12 +1140,32 @@ struct World {
   }
 
   void prof_reset() {
-    prof_ms = prof_ms_big = 0.0;
-    prof_launches = prof_launches_big = 0;
+    prof_ms = prof_ms_big = prof_ms_iter = prof_ms_asm = 0.0;
+    prof_launches = prof_launches_big = prof_asm = 0;
     if (prof_bytes.p) {
-      HC(hipMemsetAsync(prof_bytes.p, 0, 16, stream));
+      HC(hipMemsetAsync(prof_bytes.p, 0, 32, stream));
       HC(hipStreamSynchronize(stream));
     }
+  }
+
+  std::vector<hipEvent_t> asm_pool;
+  hipEvent_t asm_event(size_t i) {
+    while (asm_pool.size() <= i) {
+      hipEvent_t e;
+      HC(hipEventCreate(&e));
+      asm_pool.push_back(e);
+    }
+    return asm_pool[i];
+  }
+  // adds the assembly passes timed since the last call (stream idle)
+  void collect_asm() {
+    for (size_t k = 0; k + 1 < asm_ev.size(); k += 2) {
+      float ms = 0.f;
+      HC(hipEventElapsedTime(&ms, asm_ev[k], asm_ev[k + 1]));
+      prof_ms_asm += ms;
+      prof_asm += 1;
+    }
+    asm_ev.clear();
   }
 
   hipEvent_t pool_event(size_t i) {
@@ -1281,8 +1311,20 @@ struct World {
     if (moved) refresh_lists();
     ipck::incidence_fill(stream, W, S, L, nce, nvw);
     ipck::contact_rows(stream, L, nvw, ntot, mixed);
+    // measurement: the assembly pass (elasticity, inertia, gradient, stored
+    // blocks) between two events, its algorithmic bytes counted after it
+    hipEvent_t a0 = nullptr, a1 = nullptr;
+    if (prof_on && !prof_all) {
+      a0 = asm_event(asm_ev.size());
+      a1 = asm_event(asm_ev.size() + 1);
+      asm_ev.push_back(a0);
+      asm_ev.push_back(a1);
+      HC(hipEventRecord(a0, stream));
+    }
     ipck::elastic(stream, W, envs_d, S, B);
     ipck::assemble(stream, W, envs_d, S, B, L, mixed);
+    if (a1) HC(hipEventRecord(a1, stream));
+    if (prof_on) ipck::asm_bytes(stream, envs_d, S, B, mixed, prof_bytes.p + 3);
     return na;
   }
 
@@ -1373,20 +1415,24 @@ public:
     // every solve has stopped costs only launches whose tiles exit at once.
     auto launch_block = [&](int slot) {
       for (int j = 0; j < poll_block; ++j) {
-        hipEvent_t e0 = nullptr, e1 = nullptr;
-        // every 16th iteration is timed (an event pair costs a few us of
-        // dispatch gap, which would slow the solve it measures); with
-        // prof_all every launch counts its bytes and none is timed
+        // every 16th iteration is timed (events before and after the product
+        // and the update: each costs a few us of dispatch gap, which would
+        // slow the solve it measures) and counts its algorithmic bytes in a
+        // launch of its own between the two kernels; with prof_all every
+        // iteration counts its bytes and none is timed
+        const hipEvent_t *ev = nullptr;
+        bool count = false;
         if (prof_all) {
-          e0 = pool_event(0);
-          e1 = pool_event(1);
+          count = true;
           prof_launches += 1;
         } else if (prof_on && (it & 15) == 5) {
-          e0 = pool_event(nev++);
-          e1 = pool_event(nev++);
+          for (int q = 0; q < 4; ++q) pool_event(nev + q);
+          ev = &ev_pool[nev];
+          nev += 4;
+          count = true;
           ev_big.push_back(ntl > ipck::kWideTiles ? 1 : 0);
         }
-        ipck::pcg_iter(stream, W, envs_d, S, L, it++, pending, mixed, e0, e1, tl, ntl);
+        ipck::pcg_iter(stream, W, envs_d, S, L, it++, pending, mixed, ev, count, tl, ntl);
       }
       HC(hipMemcpyAsync(pinned + 8 + slot, pending, sizeof(int), hipMemcpyDeviceToHost, stream));
       HC(hipEventRecord(poll_ev[slot], stream));
@@ -1425,16 +1471,19 @@ public:
       std::fprintf(stderr, "[ipc]   pcg %d iterations: host launching %.0f us, waiting %.0f us\n", it, t_launch, t_wait);
     if (prof_on) {
       HC(hipStreamSynchronize(stream));
-      for (size_t k = 0; k + 1 < nev; k += 2) {
-        float ms = 0.f;
+      for (size_t k = 0; k + 3 < nev; k += 4) {
+        float ms = 0.f, mu = 0.f;
         HC(hipEventElapsedTime(&ms, ev_pool[k], ev_pool[k + 1]));
+        HC(hipEventElapsedTime(&mu, ev_pool[k + 2], ev_pool[k + 3]));
         prof_ms += ms;
+        prof_ms_iter += ms + mu;
         prof_launches += 1;
-        if (ev_big[k / 2]) {
+        if (ev_big[k / 4]) {
           prof_ms_big += ms;
           prof_launches_big += 1;
         }
       }
+      collect_asm();
     }
     return it;
   }
@@ -1533,6 +1582,7 @@ public:
     set_batch(step_envs);
     ipck::step_end(stream, W, envs_d, S, B);
     HC(hipStreamSynchronize(stream));
+    if (prof_on) collect_asm();
   }
 
   // Once at most half of the batch is still iterating, lay the batch out
@@ -2259,13 +2309,13 @@ int ipc_prof_reset(void) {
 int ipc_prof_read(double *out) {
   return guarded([&]() {
     if (!out) throw ApiError(IPC_E_ARG, "null output");
-    for (int k = 0; k < 6; ++k) out[k] = 0.0;
+    for (int k = 0; k < 12; ++k) out[k] = 0.0;
     for (World *pw : worlds_for_current_device()) {
       World &w = *pw;
       std::lock_guard<std::mutex> lk(w.mu);
-      unsigned long long b[2] = {0, 0};
+      unsigned long long b[4] = {0, 0, 0, 0};
       if (w.prof_bytes.p) {
-        HC(hipMemcpyAsync(b, w.prof_bytes.p, 16, hipMemcpyDeviceToHost, w.stream));
+        HC(hipMemcpyAsync(b, w.prof_bytes.p, 32, hipMemcpyDeviceToHost, w.stream));
         HC(hipStreamSynchronize(w.stream));
       }
       out[0] += w.prof_ms;
@@ -2274,6 +2324,12 @@ int ipc_prof_read(double *out) {
       out[3] += w.prof_ms_big;
       out[4] += (double)w.prof_launches_big;
       out[5] += (double)b[1];
+      out[6] += w.prof_ms_iter;
+      out[7] += (double)w.prof_launches;
+      out[8] += (double)b[2];
+      out[9] += w.prof_ms_asm;
+      out[10] += (double)w.prof_asm;
+      out[11] += (double)b[3];
     }
     return IPC_OK;
   });
@@ -2559,6 +2615,238 @@ int ipc_ccd_bound_pairs(int32_t kind, int64_t n, const double *x12, const double
     HC(hipGetLastError());
     down(w, alpha, out.p, 1);
     HC(hipStreamSynchronize(w.stream));
+    return IPC_OK;
+  });
+}
+
+int ipc_grasp_metrics(ipc_scene s, int32_t n_obj_tris, const int32_t *obj_tris, int32_t n_hand_tris,
+                      const int32_t *hand_tris, int32_t n_samples, const int32_t *sample_tri, const double *sample_uv,
+                      double *D, double *sdf) {
+  return guarded([&]() {
+    if (!s || n_obj_tris < 1 || !obj_tris || n_hand_tris < 1 || !hand_tris || n_samples < 1 || !sample_tri ||
+        !sample_uv || !D)
+      throw ApiError(IPC_E_ARG, "bad arguments");
+    const int nv = s->host->nv;
+    for (int64_t k = 0; k < 3L * n_obj_tris; ++k)
+      if (obj_tris[k] < 0 || obj_tris[k] >= nv) throw ApiError(IPC_E_ARG, "manipuland triangle index out of range");
+    for (int64_t k = 0; k < 3L * n_hand_tris; ++k)
+      if (hand_tris[k] < 0 || hand_tris[k] >= nv) throw ApiError(IPC_E_ARG, "gripper triangle index out of range");
+    for (int k = 0; k < n_samples; ++k) {
+      const double u = sample_uv[2 * k], v = sample_uv[2 * k + 1];
+      if (sample_tri[k] < 0 || sample_tri[k] >= n_hand_tris || !(u >= 0.0) || !(v >= 0.0) || !(u + v <= 1.0 + 1e-12))
+        throw ApiError(IPC_E_ARG, "bad sample (triangle index or barycentric coordinates)");
+    }
+    World &w = *s->world;
+    std::lock_guard<std::mutex> lk(w.mu);
+    HC(hipSetDevice(w.device));
+    const int vo = w.envs_h[s->slot].v_off;
+    std::vector<int> ot(obj_tris, obj_tris + 3L * n_obj_tris), ht(hand_tris, hand_tris + 3L * n_hand_tris);
+    for (int &v : ot) v += vo;
+    for (int &v : ht) v += vo;
+    DBuf<int> OT, HT, ST;
+    DBuf<double> UV, SDF, part, out;
+    OT.ensure(ot.size());
+    HT.ensure(ht.size());
+    ST.ensure(n_samples);
+    UV.ensure(2L * n_samples);
+    SDF.ensure(n_samples);
+    part.ensure(ipck::sdf_parts(n_samples) + 1);
+    out.ensure(2);
+    w.up(OT.p, ot.data(), ot.size());
+    w.up(HT.p, ht.data(), ht.size());
+    w.up(ST.p, sample_tri, n_samples);
+    w.up(UV.p, sample_uv, 2L * n_samples);
+    ipck::grasp_metrics(w.stream, w.W.x, OT.p, n_obj_tris, HT.p, ST.p, UV.p, n_samples, SDF.p, part.p, out.p);
+    HC(hipGetLastError());
+    down(w, D, out.p, 2);
+    if (sdf) down(w, sdf, SDF.p, n_samples);
+    HC(hipStreamSynchronize(w.stream));
+    return IPC_OK;
+  });
+}
+
+// ---- grasp validation (Sec. III-D) -------------------------------------------
+namespace {
+// where a scene's protocol controls sit in the world's motion array
+size_t ctl_offset(World &w, ipc_scene s) {
+  const EnvDev &E = w.envs_h[s->slot];
+  return w.recs[s->slot].mo_off + (12L * E.n_groups + 3) * E.n_motion;
+}
+
+// force on every tag from every tag at the scene's positions (caller holds w.mu)
+void contact_forces_locked(World &w, ipc_scene s, const int32_t *tags, int ntags, double *out) {
+  DBuf<int> T, fab;
+  DBuf<double> f, o;
+  const int nv = s->host->nv;
+  T.ensure(nv);
+  o.ensure(3L * ntags * ntags);
+  w.up(T.p, tags, nv);
+  w.set_batch({s->slot});
+  set_status(w, s->slot, ipcw::ST_ACTIVE);
+  try {
+    int nc = w.broad_phase(w.W.x, nullptr);
+    int na = w.active_pairs(nc, w.W.x);
+    f.ensure(3L * na + 3);
+    fab.ensure(na + 1);
+    ipck::contact_forces(w.stream, w.W, w.envs_d, w.S, w.L, na, T.p, w.envs_h[s->slot].v_off, ntags, f.p, fab.p, o.p);
+    HC(hipGetLastError());
+    down(w, out, o.p, 3L * ntags * ntags);
+    HC(hipStreamSynchronize(w.stream));
+  } catch (...) {
+    set_status(w, s->slot, s->failed ? ipcw::ST_FAILED : ipcw::ST_IDLE);
+    throw;
+  }
+  set_status(w, s->slot, s->failed ? ipcw::ST_FAILED : ipcw::ST_IDLE);
+}
+
+double com_of(const std::vector<double> &pos, const HostScene &H, const int32_t *tags, int k) {
+  double m = 0.0, c = 0.0;
+  for (int i = 0; i < H.nv; ++i)
+    if (tags[i] == 0) {
+      m += H.mass[i];
+      c += H.mass[i] * pos[3 * i + k];
+    }
+  return m > 0 ? c / m : 0.0;
+}
+}  // namespace
+
+int ipc_hold_group(ipc_scene s, int32_t group, int32_t row) {
+  return guarded([&]() {
+    if (!s || group < 0 || group >= s->host->n_groups || row < -1) throw ApiError(IPC_E_ARG, "bad arguments");
+    World &w = *s->world;
+    std::lock_guard<std::mutex> lk(w.mu);
+    HC(hipSetDevice(w.device));
+    const double v = row;
+    HC(hipMemcpyAsync(w.W.motion + ctl_offset(w, s) + group, &v, 8, hipMemcpyHostToDevice, w.stream));
+    HC(hipStreamSynchronize(w.stream));
+    return IPC_OK;
+  });
+}
+
+int ipc_set_gravity(ipc_scene s, const double *g) {
+  return guarded([&]() {
+    if (!s || (g && !finite_all(g, 3))) throw ApiError(IPC_E_ARG, "bad arguments");
+    World &w = *s->world;
+    std::lock_guard<std::mutex> lk(w.mu);
+    HC(hipSetDevice(w.device));
+    const double v[4] = {g ? 1.0 : 0.0, g ? g[0] : 0.0, g ? g[1] : 0.0, g ? g[2] : 0.0};
+    HC(hipMemcpyAsync(w.W.motion + ctl_offset(w, s) + s->host->n_groups, v, 32, hipMemcpyHostToDevice, w.stream));
+    HC(hipStreamSynchronize(w.stream));
+    return IPC_OK;
+  });
+}
+
+int ipc_contact_forces(ipc_scene s, const int32_t *tags, int32_t ntags, double *out) {
+  return guarded([&]() {
+    if (!s || !tags || ntags < 1 || ntags > 64 || !out) throw ApiError(IPC_E_ARG, "bad arguments");
+    World &w = *s->world;
+    std::lock_guard<std::mutex> lk(w.mu);
+    HC(hipSetDevice(w.device));
+    contact_forces_locked(w, s, tags, ntags, out);
+    return IPC_OK;
+  });
+}
+
+int ipc_validate_grasp(ipc_scene s, const ipc_grasp_protocol *p, ipc_grasp_result *r) {
+  return guarded([&]() {
+    if (!s || !p || !r || !p->vertex_tag || p->n_fingers < 1 || p->n_fingers > IPC_MAX_FINGERS ||
+        !p->finger_of_group || !(p->force_limit > 0) || p->max_close_steps < 0 || p->settle_steps < 0 ||
+        p->phase_steps < 1 || !(p->gravity >= 0) || !(p->com_factor > 0))
+      throw ApiError(IPC_E_ARG, "bad protocol");
+    const HostScene &H = *s->host;
+    for (int g = 0; g < H.n_groups; ++g)
+      if (p->finger_of_group[g] < 0 || p->finger_of_group[g] > p->n_fingers)
+        throw ApiError(IPC_E_ARG, "finger_of_group out of range");
+    const int nt = p->n_fingers + 1;
+    std::memset(r, 0, sizeof(*r));
+    for (int f = 0; f < IPC_MAX_FINGERS; ++f) r->halt_step[f] = -1;
+    World &w = *s->world;
+    std::vector<double> F(3L * nt * nt), pos(3L * H.nv);
+    auto step1 = [&]() {
+      if (s->failed) return false;
+      ipc_step_info info{};
+      run_steps_lane({s}, 1, &info);
+      r->steps_run += 1;
+      if (s->failed) {
+        r->failed = 1;
+        r->fail_reason = s->fail_reason;
+        return false;
+      }
+      return true;
+    };
+    auto forces = [&]() {
+      std::lock_guard<std::mutex> lk(w.mu);
+      contact_forces_locked(w, s, p->vertex_tag, nt, F.data());
+    };
+    auto finger_force = [&](int f) {  // |force on finger f from the manipuland|
+      const double *v = &F[3L * (f * nt + 0)];
+      return std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    };
+    auto com = [&](double c[3]) {
+      {
+        std::lock_guard<std::mutex> lk(w.mu);
+        get_x(w, s, w.W.x, pos.data());
+      }
+      for (int k = 0; k < 3; ++k) c[k] = com_of(pos, H, p->vertex_tag, k);
+    };
+    HC(hipSetDevice(w.device));
+    const double zero[3] = {0, 0, 0};
+    int rc = ipc_set_gravity(s, zero);  // gravity off while the fingers close
+    if (rc != IPC_OK) return rc;
+    // closing: each finger is halted once its contact force exceeds the limit
+    int halted = 0;
+    for (int n = 0; n < p->max_close_steps && halted < p->n_fingers; ++n) {
+      if (!step1()) return IPC_OK;
+      forces();
+      for (int f = 1; f <= p->n_fingers; ++f) {
+        if (r->halt_step[f - 1] >= 0 || !(finger_force(f) > p->force_limit)) continue;
+        r->halt_step[f - 1] = s->step;
+        r->finger_force[f - 1] = finger_force(f);
+        ++halted;
+        // the finger's groups keep the targets they have now reached
+        const int row = std::min(s->step, H.n_motion - 1);
+        for (int g = 0; g < H.n_groups; ++g)
+          if (p->finger_of_group[g] == f && (rc = ipc_hold_group(s, g, row)) != IPC_OK) return rc;
+      }
+    }
+    // fingers still moving stop where they are after the closing phase
+    {
+      const int row = std::min(s->step, H.n_motion - 1);
+      for (int g = 0; g < H.n_groups; ++g)
+        if (p->finger_of_group[g] > 0 && r->halt_step[p->finger_of_group[g] - 1] < 0 &&
+            (rc = ipc_hold_group(s, g, row)) != IPC_OK)
+          return rc;
+    }
+    for (int n = 0; n < p->settle_steps; ++n)
+      if (!step1()) return IPC_OK;
+    // six axis-aligned gravity phases
+    for (int ph = 0; ph < 6; ++ph) {
+      double g[3] = {0, 0, 0};
+      g[ph / 2] = (ph % 2 == 0 ? 1.0 : -1.0) * p->gravity;
+      if ((rc = ipc_set_gravity(s, g)) != IPC_OK) return rc;
+      double c0[3], cp[3], c1[3];
+      com(c0);
+      for (int n = 0; n < p->phase_steps; ++n) {
+        if (n == p->phase_steps - 1) com(cp);
+        if (!step1()) return IPC_OK;
+      }
+      com(c1);
+      double sh = 0.0, dr = 0.0;
+      for (int k = 0; k < 3; ++k) {
+        sh += (c1[k] - c0[k]) * (c1[k] - c0[k]);
+        dr += (c1[k] - cp[k]) * (c1[k] - cp[k]);
+      }
+      r->com_shift[ph] = std::sqrt(sh);
+      r->com_drift[ph] = std::sqrt(dr);
+    }
+    forces();
+    double fsum = 0.0;
+    for (int f = 1; f <= p->n_fingers; ++f) fsum += finger_force(f);
+    r->in_contact = fsum > 0.0;
+    const double limit = p->com_factor * H.eps_v * H.dt;
+    bool still = true;
+    for (int ph = 0; ph < 6; ++ph) still &= r->com_drift[ph] <= limit;
+    r->stable = (r->in_contact && still) ? 1 : 0;
     return IPC_OK;
   });
 }

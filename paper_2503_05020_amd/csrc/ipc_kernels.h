@@ -112,8 +112,14 @@ void pcg_init(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState 
               int *pending, int mixed);
 // one tiled PCG iteration (product with its dot product, then the update with
 // the stopping test) over the listed tiles; `it` = iterations done so far
+// ev (nullable): four events recorded before and after the product and
+// before and after the update; count: add the iteration's algorithmic bytes
+// to L.prof[0 or 1] (product, by launch size) and L.prof[2] (whole iteration)
 void pcg_iter(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, Lists &L, int it, int *pending,
-              int mixed, hipEvent_t ev0, hipEvent_t ev1, const Tile *tiles, int n_tiles);
+              int mixed, const hipEvent_t *ev, bool count, const Tile *tiles, int n_tiles);
+// algorithmic bytes of one assembly pass over the environments still iterating -> *prof
+void asm_bytes(hipStream_t s, const EnvDev *E, const EnvState &S, const Batch &B, int mixed,
+               unsigned long long *prof);
 // tiles of environments whose PCG still iterates -> out (count at offs[B.n_vt])
 void live_tiles(hipStream_t s, const EnvState &S, const Batch &B, Lists &L, Tile *out, int *flag, int *offs);
 // continues the PCG of the environments whose tiles are listed (one workgroup
@@ -166,6 +172,18 @@ void dbg_accd(hipStream_t s, int kind, int n, const double *x12, const double *p
 int pairs_ccd_parts(int64_t n);
 void pairs_ccd_bound(hipStream_t s, int kind, int n, const double *x12, const double *p12, double sfac, double *part,
                      double *out);
+// grasp-quality metrics over n_samples points on the gripper (triangle index +
+// barycentric (u, v) into hand_tris) against the manipuland's triangles, at
+// positions x (world vertex ids): sdf [n_samples], part [sdf_parts(n)] block
+// maxima, out[0] = D1, out[1] = D2
+// contact forces between tagged bodies over the active pairs in L (positions
+// W.x): out [ntags*ntags*3]; f [n_act*3], fab [n_act] scratch
+void contact_forces(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Lists &L, int n_act,
+                    const int *tag, int v_off, int ntags, double *f, int *fab, double *out);
+int sdf_parts(int n_samples);
+void grasp_metrics(hipStream_t s, const double *x, const int *obj_tris, int n_obj, const int *hand_tris,
+                   const int *sample_tri, const double *sample_uv, int n_samples, double *sdf, double *part,
+                   double *out);
 void dbg_tet_root(hipStream_t s, int n, const double *x12, const double *p12, double tmax, double *t, double *k4);
 
 }  // namespace ipck

@@ -8,6 +8,7 @@
 // (iii) and (iv)).  Reductions use fixed shared-memory trees over tiles and a
 // fixed order over an environment's tiles, so no floating-point atomics are
 // used anywhere.
+#include <mutex>
 #include <type_traits>
 
 #include "device_math.h"
@@ -123,8 +124,12 @@ __global__ void k_begin_step(WorldDev W, const EnvDev *envs, EnvState S, const T
     }
     return;
   }
+  // after the schedule's motion and gravity rows: per group its hold row
+  // (-1: none), then the gravity override (flag, g)
+  const double *ctl = W.motion + E.mo_off + (12 * E.n_groups + 3) * E.n_motion;
   if (k >= 0) {
     int row = min(E.step + 1, E.n_motion - 1);
+    if (ctl[k] >= 0.0) row = min(row, (int)ctl[k]);
     const double *T = W.motion + E.mo_off + 12 * (row * E.n_groups + k);
     const double *X = W.X + 3 * i;
     for (int r = 0; r < 3; ++r) {
@@ -135,6 +140,7 @@ __global__ void k_begin_step(WorldDev W, const EnvDev *envs, EnvState S, const T
   } else {
     int grow = min(E.step, E.n_motion - 1);
     const double *g = W.motion + E.mo_off + 12 * E.n_motion * E.n_groups + 3 * grow;
+    if (ctl[E.n_groups] != 0.0) g = ctl + E.n_groups + 1;
     double h = E.dt;
     for (int c = 0; c < 3; ++c) {
       W.xh[3 * i + c] = xi[c] + h * W.v[3 * i + c] + h * h * g[c];
@@ -869,6 +875,66 @@ __global__ void k_friction_setup(WorldDev W, const EnvDev *envs, const double *k
   fenv[k] = env;
 }
 
+// Contact force of every active pair (grasp validation, Sec. III-D): the
+// barrier pushes the pair's first side (the point / first edge) along the unit
+// normal n of the closest-point difference with lambda = -kappa e b'(d), the
+// second side with the opposite force.  f[k] = lambda n; fab[k] = the tag pair
+// (first side's tag) * ntags + (second side's tag), -1 if either is untagged.
+__global__ void k_pair_force(WorldDev W, const EnvDev *envs, const double *kap, const int2 *act, const int *act_type,
+                             int n, const int *tag, int v_off, int ntags, double *f, int *fab) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  int kind, v[4], env;
+  double ex;
+  pair_info(W, act[k], kind, v, env, ex);
+  const EnvDev &E = envs[env];
+  double xx[12], w[4];
+  gather12(W.x, v, xx);
+  closest_weights(kind, act_type[k], xx, w);
+  double dv[3] = {0, 0, 0};
+  for (int i = 0; i < 4; ++i)
+    for (int c = 0; c < 3; ++c) dv[c] += w[i] * xx[3 * i + c];
+  const double dn = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+  double d2;
+  classify(kind, xx, &d2);
+  double b0, b1, b2;
+  barrier_b(sqrt(d2), E.dhat, &b0, &b1, &b2);
+  double e = 1.0;
+  if (kind == 1) {
+    d3 nn = cross3(sub3(ld3(xx + 3), ld3(xx)), sub3(ld3(xx + 9), ld3(xx + 6)));
+    double c = dot3(nn, nn);
+    if (c < ex) e = (c / ex) * (2.0 - c / ex);
+  }
+  const double lam = -kap[env] * e * b1;
+  for (int c = 0; c < 3; ++c) f[3 * k + c] = lam * dv[c] / dn;
+  const int ta = tag[v[0] - v_off], tb = tag[v[kind == 0 ? 1 : 2] - v_off];
+  fab[k] = (ta >= 0 && ta < ntags && tb >= 0 && tb < ntags) ? ta * ntags + tb : -1;
+}
+
+// out[(a ntags + b) 3 + c]: force on the vertices tagged a from those tagged b,
+// one block per (a, b): the pairs of tag pair (a, b) add their force, those of
+// (b, a) subtract it; each thread sums a fixed stride, then a fixed tree
+__global__ void k_tag_force_sum(const double *f, const int *fab, int n, int ntags, double *out) {
+  __shared__ double sh[3 * TB];
+  const int a = blockIdx.x / ntags, b = blockIdx.x % ntags;
+  const int ab = a * ntags + b, ba = b * ntags + a;
+  double s[3] = {0, 0, 0};
+  for (int k = threadIdx.x; k < n; k += TB) {
+    const double sg = fab[k] == ab ? 1.0 : (fab[k] == ba ? -1.0 : 0.0);
+    if (sg != 0.0 && ab != ba)
+      for (int c = 0; c < 3; ++c) s[c] += sg * f[3 * k + c];
+  }
+  for (int c = 0; c < 3; ++c) sh[c * TB + threadIdx.x] = s[c];
+  __syncthreads();
+  for (int w = TB / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int c = 0; c < 3; ++c) sh[c * TB + threadIdx.x] += sh[c * TB + threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int c = 0; c < 3; ++c) out[3 * ab + c] = sh[c * TB];
+}
+
 // friction potential mu lambda f0(|u|), u = (I - n n^T) sum_i w_i (x_i - x^n_i):
 // grad_i = mu lambda w_i (f1(y)/y) u,  hess_ij = mu lambda w_i w_j [a (I - n n^T) + c u u^T]
 // with a = f1/y, c = (f1' - f1/y) / y^2 (closed form, PSD).
@@ -1466,8 +1532,7 @@ __global__ void k_pcg_env_init(const EnvDev *envs, EnvState S, const int *benv, 
 template <typename T, bool WIDE>
 __global__ void __launch_bounds__(1024) k_spmv(WorldDev W, const EnvDev *envs, EnvState S, const Tile *tiles,
                                                const int *inc_off, const int *cr_cnt, const int *cr_col,
-                                               const T *cr_val, const T *u, T *w, const T *val, double *part_d,
-                                               unsigned long long *prof) {
+                                               const T *cr_val, const T *u, T *w, const T *val, double *part_d) {
   __shared__ double sh[16];
   Tile t = tiles[blockIdx.x];
   const int row = threadIdx.x / kLPR, l = threadIdx.x % kLPR;
@@ -1483,14 +1548,59 @@ __global__ void __launch_bounds__(1024) k_spmv(WorldDev W, const EnvDev *envs, E
   double d = row_spmv<T, WIDE>(W, i, valid, l, h, cr_col, cr_val, u, w, val);
   d = rows_sum(d, sh);
   if (threadIdx.x == 0) part_d[tile_slot(envs, t)] = d;
-  if (prof) {
-    // algorithmic bytes of this tile: stored blocks + column indices (sliced
-    // ELL and merged contact blocks), one read of u and one write of w per row
-    double b = 0.0;
-    if (valid) b = (double)(W.row_nnz[i] + cr_cnt[i]) * (9.0 * sizeof(T) + 4.0) + 6.0 * sizeof(T);
-    b = rows_sum(b, sh);
-    if (threadIdx.x == 0) atomicAdd(prof, (unsigned long long)b);
+}
+
+// Algorithmic bytes of a PCG iteration over the listed tiles, counted by a
+// launch of its own right after the product (outside its timing, before the
+// update changes which environments iterate): *spmv += the product's
+// (stored 3x3 blocks and column indices of the sliced ELL and the merged
+// contact blocks, one read of u and one write of w per row), *iter += the
+// whole iteration's: the product's blocks plus per row the preconditioner
+// block and eight vector accesses of three values, N (9 s + 4) + n 9 s +
+// 24 n s for N blocks, n rows, s bytes per value.
+template <typename T>
+__global__ void k_pcg_bytes(WorldDev W, EnvState S, const Tile *tiles, const int *cr_cnt, unsigned long long *spmv,
+                            unsigned long long *iter) {
+  __shared__ double sh[2 * TB];
+  Tile t = tiles[blockIdx.x];
+  if (S.status[t.env] != ST_ACTIVE || S.pcg_done[t.env]) return;
+  double b = 0.0, c = 0.0;
+  if ((int)threadIdx.x < t.count) {
+    const int i = t.start + threadIdx.x;
+    const double blk = (double)(W.row_nnz[i] + cr_cnt[i]) * (9.0 * sizeof(T) + 4.0);
+    b = blk + 6.0 * sizeof(T);
+    c = blk + 9.0 * sizeof(T) + 24.0 * sizeof(T);
   }
+  sh[threadIdx.x] = b;
+  sh[TB + threadIdx.x] = c;
+  __syncthreads();
+  for (int w = TB / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      sh[threadIdx.x] += sh[threadIdx.x + w];
+      sh[TB + threadIdx.x] += sh[TB + threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    atomicAdd(spmv, (unsigned long long)sh[0]);
+    atomicAdd(iter, (unsigned long long)sh[TB]);
+  }
+}
+
+// Algorithmic bytes of one assembly pass (elasticity, inertia, gradient and
+// the stored 3x3 blocks) over the environments still iterating: per tet its
+// vertex ids, gathered positions, inverse rest shape, volume and Lame
+// parameters (208 B); per row mass, position, predicted position and the
+// gradient written (80 B); the N stored blocks written once (9 s each).
+__global__ void k_asm_bytes(const EnvDev *envs, EnvState S, const int *benv, int n, int mixed,
+                            unsigned long long *prof) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  int e = benv[j];
+  if (S.status[e] != ST_ACTIVE) return;
+  const EnvDev &E = envs[e];
+  const double b = 208.0 * E.nt + 80.0 * E.nv + 9.0 * (mixed ? 4.0 : 8.0) * E.nnzb;
+  atomicAdd(prof, (unsigned long long)b);
 }
 
 // Stopping test, scalars and the update of iteration `it` (the host's count:
@@ -2170,6 +2280,75 @@ __global__ void __launch_bounds__(TB) k_min_reduce(const double *part, int n_par
   if (threadIdx.x == 0) out[0] = sh[0];
 }
 
+// Grasp-quality metrics (Sec. IV-C, Eq. (2)-(3)): one thread per sample point
+// on the gripper's surface, the manipuland's boundary triangles streamed
+// through LDS in tiles of 256; each thread keeps its least squared distance
+// and its winding sum (solid angles / 4 pi).  d_o(p) = +distance inside
+// (winding > 1/2), -distance outside.  part[block] = the block's largest d_o.
+constexpr int kSdfTile = 256;
+__global__ void __launch_bounds__(kSdfTile) k_sdf_samples(const double *x, const int *obj_tris, int n_obj,
+                                                          const int *hand_tris, const int *sample_tri,
+                                                          const double *sample_uv, int n_samples, double *sdf,
+                                                          double *part) {
+  __shared__ double tv[kSdfTile * 9];
+  __shared__ double red[kSdfTile];
+  const int i = blockIdx.x * kSdfTile + threadIdx.x;
+  d3 p = {0.0, 0.0, 0.0};
+  if (i < n_samples) {
+    const int t = sample_tri[i];
+    const double u = sample_uv[2 * i], v = sample_uv[2 * i + 1], w = 1.0 - u - v;
+    const int a = hand_tris[3 * t], b = hand_tris[3 * t + 1], c = hand_tris[3 * t + 2];
+    p = {w * x[3 * a] + u * x[3 * b] + v * x[3 * c], w * x[3 * a + 1] + u * x[3 * b + 1] + v * x[3 * c + 1],
+         w * x[3 * a + 2] + u * x[3 * b + 2] + v * x[3 * c + 2]};
+  }
+  double best = kInf, wind = 0.0;
+  for (int base = 0; base < n_obj; base += kSdfTile) {
+    const int m = min(kSdfTile, n_obj - base);
+    __syncthreads();
+    for (int k = threadIdx.x; k < 9 * m; k += kSdfTile) {
+      const int tri = k / 9, r = k % 9;
+      tv[k] = x[3 * obj_tris[3 * (base + tri) + r / 3] + r % 3];
+    }
+    __syncthreads();
+    if (i < n_samples)
+      for (int j = 0; j < m; ++j) {
+        const double *q = tv + 9 * j;
+        const d3 A = {q[0], q[1], q[2]}, B = {q[3], q[4], q[5]}, C = {q[6], q[7], q[8]};
+        best = fmin(best, point_tri_dist2(p, A, B, C));
+        wind += tri_solid_angle(p, A, B, C);
+      }
+  }
+  double d = -kInf;
+  if (i < n_samples) {
+    d = sqrt(best);
+    if (!(wind > 2.0 * M_PI)) d = -d;  // winding number wind / 4 pi <= 1/2: outside
+    sdf[i] = d;
+  }
+  red[threadIdx.x] = d;
+  __syncthreads();
+  for (int s = kSdfTile / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void k_max_reduce(const double *part, int n, double *out) {
+  __shared__ double red[TB];
+  double m = -kInf;
+  for (int k = threadIdx.x; k < n; k += TB) m = fmax(m, part[k]);
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = TB / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = fmax(0.0, red[0]);  // D1
+    out[1] = fabs(red[0]);       // D2
+  }
+}
+
 __global__ void k_fill_int(int *p, int n, int v) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -2366,35 +2545,44 @@ PcgVecs<float> vecs32(const WorldDev &W, const Lists &L) {
 
 template <typename T>
 void pcg_iter_t(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, Lists &L, int it, int *pending,
-                hipEvent_t ev0, hipEvent_t ev1, const Tile *tiles, int n_tiles, const PcgVecs<T> &v) {
-  // bytes are counted only for the launches that are timed: counter 0 for
-  // launches of at most kWideTiles tiles, counter 1 for larger ones
-  unsigned long long *prof = ev0 ? L.prof + (n_tiles > kWideTiles ? 1 : 0) : nullptr;
+                const hipEvent_t *ev, bool count, const Tile *tiles, int n_tiles, const PcgVecs<T> &v) {
   // per-tile partials of gamma and r.r: slot it & 1 holds this iteration's,
   // the update writes the next iteration's into the other slot
   double *g_cur = (it & 1) ? L.part_b1 : L.part_b0, *g_new = (it & 1) ? L.part_b0 : L.part_b1;
   double *rr_cur = (it & 1) ? L.part_c1 : L.part_c0, *rr_new = (it & 1) ? L.part_c0 : L.part_c1;
   const int nt = kLPR * TB;
-  if (ev0) hipEventRecord(ev0, s);
+  if (ev) hipEventRecord(ev[0], s);
   // launches of a few tiles are latency-bound: issue each lane's slots four at a time
   if (n_tiles <= L.wide_tiles)
     IPC_LAUNCH((k_spmv<T, true>), n_tiles, nt, s)(W, E, S, tiles, L.inc_off, L.cr_cnt, L.cr_col, v.cr_val, v.u, v.w,
-                                                  v.val, L.part_a, prof);
+                                                  v.val, L.part_a);
   else
     IPC_LAUNCH((k_spmv<T, false>), n_tiles, nt, s)(W, E, S, tiles, L.inc_off, L.cr_cnt, L.cr_col, v.cr_val, v.u, v.w,
-                                                   v.val, L.part_a, prof);
-  if (ev1) hipEventRecord(ev1, s);
+                                                   v.val, L.part_a);
+  if (ev) hipEventRecord(ev[1], s);
+  // the iteration's algorithmic bytes (product: counter 0 for launches of at
+  // most kWideTiles tiles, 1 for larger ones; whole iteration: counter 2),
+  // counted between the two kernels, outside both timings
+  if (count)
+    IPC_LAUNCH(k_pcg_bytes<T>, n_tiles, TB, s)(W, S, tiles, L.cr_cnt, L.prof + (n_tiles > kWideTiles ? 1 : 0),
+                                               L.prof + 2);
+  if (ev) hipEventRecord(ev[2], s);
   IPC_LAUNCH(k_pcg_update<T>, n_tiles, TB, s)(W, E, S, tiles, it, L.part_a, g_cur, rr_cur, g_new, rr_new, v.x, v.r,
                                               v.u, v.pp, v.q, v.w, v.Minv, pending);
+  if (ev) hipEventRecord(ev[3], s);
 }
 
 void pcg_iter(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, Lists &L, int it, int *pending,
-              int mixed, hipEvent_t ev0, hipEvent_t ev1, const Tile *tiles, int n_tiles) {
+              int mixed, const hipEvent_t *ev, bool count, const Tile *tiles, int n_tiles) {
   if (!n_tiles) return;
   if (!mixed)
-    pcg_iter_t<double>(s, W, E, S, L, it, pending, ev0, ev1, tiles, n_tiles, vecs64(W, L));
+    pcg_iter_t<double>(s, W, E, S, L, it, pending, ev, count, tiles, n_tiles, vecs64(W, L));
   else
-    pcg_iter_t<float>(s, W, E, S, L, it, pending, ev0, ev1, tiles, n_tiles, vecs32(W, L));
+    pcg_iter_t<float>(s, W, E, S, L, it, pending, ev, count, tiles, n_tiles, vecs32(W, L));
+}
+void asm_bytes(hipStream_t s, const EnvDev *E, const EnvState &S, const Batch &B, int mixed,
+               unsigned long long *prof) {
+  IPC_LAUNCH(k_asm_bytes, nblk(B.n_envs, 64), 64, s)(E, S, B.envs, B.n_envs, mixed, prof);
 }
 
 void pcg_fused(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const int *fenv, int n_fenv,
@@ -2513,11 +2701,29 @@ void dbg_tet(hipStream_t s, const double *X12, const double *x12, double mu, dou
   IPC_LAUNCH(k_dbg_tet, 1, 64, s)(X12, x12, mu, la, out);
 }
 int pairs_ccd_parts(int64_t n) { return (int)((n + kCcdBlock - 1) / kCcdBlock); }
+
 void pairs_ccd_bound(hipStream_t s, int kind, int n, const double *x12, const double *p12, double sfac, double *part,
                      double *out) {
   const int nb = pairs_ccd_parts(n);
   if (nb) IPC_LAUNCH(k_pairs_ccd_min, nb, kCcdBlock, s)(kind, n, x12, p12, sfac, part);
   IPC_LAUNCH(k_min_reduce, 1, TB, s)(part, nb, out);
+}
+void contact_forces(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Lists &L, int n_act,
+                    const int *tag, int v_off, int ntags, double *f, int *fab, double *out) {
+  if (n_act)
+    IPC_LAUNCH(k_pair_force, nblk(n_act, TB), TB, s)(W, E, S.kappa, L.act, L.act_type, n_act, tag, v_off, ntags, f,
+                                                     fab);
+  IPC_LAUNCH(k_tag_force_sum, ntags * ntags, TB, s)(f, fab, n_act, ntags, out);
+}
+int sdf_parts(int n_samples) { return (n_samples + kSdfTile - 1) / kSdfTile; }
+void grasp_metrics(hipStream_t s, const double *x, const int *obj_tris, int n_obj, const int *hand_tris,
+                   const int *sample_tri, const double *sample_uv, int n_samples, double *sdf, double *part,
+                   double *out) {
+  const int nb = sdf_parts(n_samples);
+  if (nb)
+    IPC_LAUNCH(k_sdf_samples, nb, kSdfTile, s)(x, obj_tris, n_obj, hand_tris, sample_tri, sample_uv, n_samples, sdf,
+                                               part);
+  IPC_LAUNCH(k_max_reduce, 1, TB, s)(part, nb, out);
 }
 void dbg_tet_root(hipStream_t s, int n, const double *x12, const double *p12, double tmax, double *t, double *k4) {
   if (n) IPC_LAUNCH(k_dbg_tet_root, nblk(n, 64), 64, s)(n, x12, p12, tmax, t, k4);

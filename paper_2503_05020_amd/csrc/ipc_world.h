@@ -53,7 +53,7 @@ struct EnvDev {
   int fric_iters;                // lagged friction updates per step (>= 1)
   int inv_filter;                // 1: the inversion filter bounds the line search
   int adapt_kappa;               // 1: kappa adapts to the least active-pair distance
-  int pad_v;
+  int nnzb;                      // stored 3x3 blocks of the elastic pattern (measurement)
 };
 
 // Per-environment solver state (device arrays indexed by slot).

@@ -67,12 +67,30 @@ EXPORTS = [
     "ipc_debug_gradient", "ipc_debug_energy", "ipc_debug_hessian_apply", "ipc_debug_newton_dir",
     "ipc_debug_ccd_bound", "ipc_debug_classify", "ipc_debug_pair_barrier", "ipc_debug_tet_elastic",
     "ipc_debug_accd", "ipc_debug_inversion_bound", "ipc_debug_tet_first_root", "ipc_ccd_bound_pairs",
-    "ipc_prof_enable", "ipc_prof_reset", "ipc_prof_read", "ipc_set_tuning", "ipc_get_tuning",
+    "ipc_grasp_metrics", "ipc_hold_group", "ipc_set_gravity", "ipc_contact_forces",
+    "ipc_validate_grasp", "ipc_prof_enable", "ipc_prof_reset", "ipc_prof_read", "ipc_set_tuning", "ipc_get_tuning",
     "ipc_server_create", "ipc_server_submit", "ipc_server_poll", "ipc_server_wait", "ipc_server_result",
     "ipc_server_release", "ipc_server_set_slots", "ipc_server_stats", "ipc_server_destroy",
 ]
 
 IPC_REQ_QUEUED, IPC_REQ_RUNNING, IPC_REQ_DONE, IPC_REQ_FAILED = 0, 1, 2, 3
+IPC_MAX_FINGERS = 8
+
+
+class ipc_grasp_protocol(C.Structure):
+    _fields_ = [
+        ("vertex_tag", _ip), ("n_fingers", C.c_int32), ("finger_of_group", _ip), ("force_limit", C.c_double),
+        ("max_close_steps", C.c_int32), ("settle_steps", C.c_int32), ("phase_steps", C.c_int32),
+        ("gravity", C.c_double), ("com_factor", C.c_double),
+    ]
+
+
+class ipc_grasp_result(C.Structure):
+    _fields_ = [
+        ("stable", C.c_int32), ("in_contact", C.c_int32), ("failed", C.c_int32), ("fail_reason", C.c_int32),
+        ("steps_run", C.c_int32), ("halt_step", C.c_int32 * IPC_MAX_FINGERS),
+        ("finger_force", C.c_double * IPC_MAX_FINGERS), ("com_shift", C.c_double * 6), ("com_drift", C.c_double * 6),
+    ]
 
 
 class ipc_request_info(C.Structure):
@@ -125,6 +143,11 @@ def lib():
     L.ipc_debug_accd.argtypes = [C.c_int32, C.c_int64, _dp, _dp, C.c_double, _dp]
     L.ipc_debug_accd.restype = C.c_int64
     L.ipc_ccd_bound_pairs.argtypes = [C.c_int32, C.c_int64, _dp, _dp, C.c_double, _dp]
+    L.ipc_grasp_metrics.argtypes = [vp, C.c_int32, _ip, C.c_int32, _ip, C.c_int32, _ip, _dp, _dp, _dp]
+    L.ipc_hold_group.argtypes = [vp, C.c_int32, C.c_int32]
+    L.ipc_set_gravity.argtypes = [vp, _dp]
+    L.ipc_contact_forces.argtypes = [vp, _ip, C.c_int32, _dp]
+    L.ipc_validate_grasp.argtypes = [vp, C.POINTER(ipc_grasp_protocol), C.POINTER(ipc_grasp_result)]
     L.ipc_debug_inversion_bound.argtypes = [vp, _dp, _dp]
     L.ipc_debug_inversion_bound.restype = C.c_double
     L.ipc_debug_tet_first_root.argtypes = [C.c_int64, _dp, _dp, C.c_double, _dp, _dp]
@@ -283,10 +306,12 @@ def ipc_prof_reset():
 
 
 def ipc_prof_read():
-    out = np.zeros(6)
+    out = np.zeros(12)
     _check(lib().ipc_prof_read(_d(out)))
     return {"spmv_ms": float(out[0]), "spmv_launches": int(out[1]), "spmv_bytes": float(out[2]),
-            "big_ms": float(out[3]), "big_launches": int(out[4]), "big_bytes": float(out[5])}
+            "big_ms": float(out[3]), "big_launches": int(out[4]), "big_bytes": float(out[5]),
+            "iter_ms": float(out[6]), "iters": int(out[7]), "iter_bytes": float(out[8]),
+            "asm_ms": float(out[9]), "asm_passes": int(out[10]), "asm_bytes": float(out[11])}
 
 
 def ipc_set_tuning(key: int, value: int):
@@ -425,6 +450,49 @@ def ipc_ccd_bound_pairs(kind, x12, p12, s=0.1):
     a = C.c_double()
     _check(lib().ipc_ccd_bound_pairs(kind, len(x12), _d(x12), _d(p12), s, C.byref(a)))
     return a.value
+
+
+def ipc_grasp_metrics(scene, obj_tris, hand_tris, sample_tri, sample_uv, want_sdf=False):
+    """D1, D2 (Sec. IV-C Eq. (2)-(3)) at the scene's current positions; with want_sdf also d_o at every sample."""
+    ot = np.ascontiguousarray(obj_tris, np.int32).reshape(-1, 3)
+    ht = np.ascontiguousarray(hand_tris, np.int32).reshape(-1, 3)
+    st = np.ascontiguousarray(sample_tri, np.int32).reshape(-1)
+    uv = _f64(sample_uv).reshape(-1, 2)
+    D = np.zeros(2)
+    sdf = np.zeros(len(st)) if want_sdf else None
+    _check(lib().ipc_grasp_metrics(scene.h, len(ot), _i(ot), len(ht), _i(ht), len(st), _i(st), _d(uv), _d(D),
+                                   _d(sdf)))
+    return (D[0], D[1], sdf) if want_sdf else (D[0], D[1])
+
+
+def ipc_hold_group(scene, group, row):
+    _check(lib().ipc_hold_group(scene.h, int(group), int(row)))
+
+
+def ipc_set_gravity(scene, g):
+    _check(lib().ipc_set_gravity(scene.h, None if g is None else _d(_f64(g).reshape(3))))
+
+
+def ipc_contact_forces(scene, tags, ntags):
+    """[ntags, ntags, 3]: force on the vertices tagged a exerted by those tagged b."""
+    t = np.ascontiguousarray(tags, np.int32)
+    out = np.zeros((ntags, ntags, 3))
+    _check(lib().ipc_contact_forces(scene.h, _i(t), int(ntags), _d(out)))
+    return out
+
+
+def ipc_validate_grasp(scene, vertex_tag, n_fingers, finger_of_group, force_limit=50.0, max_close_steps=60,
+                       settle_steps=10, phase_steps=10, gravity=9.8, com_factor=10.0):
+    vt = np.ascontiguousarray(vertex_tag, np.int32)
+    fg = np.ascontiguousarray(finger_of_group, np.int32)
+    p = ipc_grasp_protocol(_i(vt), int(n_fingers), _i(fg), float(force_limit), int(max_close_steps),
+                           int(settle_steps), int(phase_steps), float(gravity), float(com_factor))
+    r = ipc_grasp_result()
+    _check(lib().ipc_validate_grasp(scene.h, C.byref(p), C.byref(r)))
+    return {"stable": r.stable, "in_contact": r.in_contact, "failed": r.failed, "fail_reason": r.fail_reason,
+            "steps_run": r.steps_run, "halt_step": list(r.halt_step)[:n_fingers],
+            "finger_force": list(r.finger_force)[:n_fingers], "com_shift": list(r.com_shift),
+            "com_drift": list(r.com_drift)}
 
 
 def ipc_debug_inversion_bound(scene, x, p):

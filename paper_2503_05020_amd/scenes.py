@@ -164,7 +164,7 @@ def h_for_tet_target(mask_fn, target: int, h_lo: float, h_hi: float, rel: float 
 class _Builder:
     def __init__(self):
         self.verts, self.tets, self.E, self.nu, self.rho = [], [], [], [], []
-        self.tris, self.kin = [], []
+        self.tris, self.kin, self.body = [], [], []
         self.nv = 0
 
     def add_body(self, verts, tets, E, nu, rho, kin=None):
@@ -177,6 +177,7 @@ class _Builder:
         self.rho.append(np.broadcast_to(np.asarray(rho, np.float64), (nt,)).copy())
         k = np.full(len(verts), -1, np.int32) if kin is None else np.asarray(kin, np.int32)
         self.kin.append(k)
+        self.body.append(np.full(len(verts), len(self.body), np.int32))
         self.nv += len(verts)
         return off
 
@@ -185,6 +186,7 @@ class _Builder:
         self.verts.append(np.asarray(verts, np.float64))
         self.tris.append(np.asarray(tris, np.int64) + off)
         self.kin.append(np.full(len(verts), group, np.int32))
+        self.body.append(np.full(len(verts), len(self.body), np.int32))
         self.nv += len(verts)
         return off
 
@@ -212,9 +214,54 @@ class _Builder:
             motion=np.ascontiguousarray(np.asarray(motion, np.float64)),
             gravity=np.ascontiguousarray(np.asarray(gravity, np.float64)),
             env_bbox_diag=float(np.linalg.norm(hi - lo)),
+            body=np.concatenate(self.body, 0),  # per vertex: the add_body / add_kinematic_mesh call it came from
         )
         sc.update(p)
         return sc
+
+
+def body_surface(sc: dict, body: int) -> np.ndarray:
+    """Boundary triangles [m,3] of one body of a scene (vertex ids of the scene), oriented outward at
+    the rest positions: for a tet body its faces used by one tet only, each ordered so that the tet's
+    fourth vertex lies behind it; for a kinematic mesh its own triangles."""
+    vb = sc["body"]
+    tets = np.asarray(sc["tets"])
+    tets = tets[vb[tets[:, 0]] == body]
+    if len(tets) == 0:
+        tris = np.asarray(sc["tris"])
+        return tris[vb[tris[:, 0]] == body].astype(np.int32)
+    X = sc["rest_pos"]
+    faces = {}
+    for t in tets:
+        for k in range(4):
+            f = [t[j] for j in range(4) if j != k]
+            key = tuple(sorted(f))
+            if key in faces:
+                faces[key] = None
+            else:
+                faces[key] = (f, t[k])
+    out = []
+    for v in faces.values():
+        if v is None:
+            continue
+        f, opp = v
+        n = np.cross(X[f[1]] - X[f[0]], X[f[2]] - X[f[0]])
+        if np.dot(n, X[opp] - X[f[0]]) > 0:
+            f = [f[0], f[2], f[1]]
+        out.append(f)
+    return np.array(out, np.int32)
+
+
+def surface_samples(sc: dict, tris: np.ndarray, n: int, seed: int = 0):
+    """n points on the triangles, uniform by rest area: (triangle index [n], barycentric (u, v) [n,2])."""
+    rng = np.random.default_rng(seed)
+    X = sc["rest_pos"]
+    a = 0.5 * np.linalg.norm(np.cross(X[tris[:, 1]] - X[tris[:, 0]], X[tris[:, 2]] - X[tris[:, 0]]), axis=1)
+    tri = rng.choice(len(tris), size=n, p=a / a.sum()).astype(np.int32)
+    u, v = rng.uniform(size=n), rng.uniform(size=n)
+    flip = u + v > 1.0
+    u[flip], v[flip] = 1.0 - u[flip], 1.0 - v[flip]
+    return tri, np.stack([u, v], 1)
 
 
 def ground_plane(half: float = 0.5, z: float = 0.0):
