@@ -241,6 +241,23 @@ int ipc_get_tuning(int32_t key, int64_t *value);
  * outside (0, 1).  Uses a per-call device buffer of per-block minima. */
 int ipc_ccd_bound_pairs(int32_t kind, int64_t n, const double *x12, const double *p12, double s, double *alpha);
 
+/* The same bound for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * it calls no allocating routine.  x12, p12 [n*12] and alpha [1] are DEVICE
+ * pointers on the current device; the two kernels are queued on `stream`
+ * (a hipStream_t, NULL = the null stream) and the call returns without
+ * waiting: *alpha holds the bound once the stream has reached it.  The
+ * per-block minima live in a fixed device array of 65536 doubles (512 KiB)
+ * that each GPU the library runs on holds until the process ends, so
+ * n <= 8388608 (128 pairs per entry); larger n is rejected with IPC_E_ARG
+ * before anything is queued.  Every call on one GPU shares that array and
+ * overwrites the entries it uses (nothing needs to start at zero): calls
+ * that overlap on one GPU (different streams, or threads) race; calls on
+ * one stream are ordered.  Errors: IPC_E_ARG as above, IPC_E_DEVICE if the
+ * launch fails; the message is in ipc_last_error(). */
+int ipc_ccd_bound_pairs_noalloc(int32_t kind, int64_t n, const double *x12, const double *p12, double s,
+                                double *alpha, void *stream);
+
 /* Grasp-quality metrics of Sec. IV-C, Eq. (2)-(3), at the scene's current
  * positions.  The manipuland is given by its closed boundary triangle mesh
  * obj_tris [n_obj_tris*3] (scene vertex ids, outward oriented); its signed

@@ -2619,6 +2619,30 @@ int ipc_ccd_bound_pairs(int32_t kind, int64_t n, const double *x12, const double
   });
 }
 
+int ipc_ccd_bound_pairs_noalloc(int32_t kind, int64_t n, const double *x12, const double *p12, double s,
+                                double *alpha, void *stream) {
+  // no allocation anywhere on this path: no exceptions, no containers
+  if ((kind != 0 && kind != 1) || n < 0 || (n > 0 && (!x12 || !p12)) || !alpha || !(s > 0.0 && s < 1.0)) {
+    set_err("ipc_ccd_bound_pairs_noalloc: bad arguments");
+    return IPC_E_ARG;
+  }
+  if (n > ipck::noalloc_max_pairs()) {
+    set_err("ipc_ccd_bound_pairs_noalloc: more pairs than the fixed scratch holds (8388608)");
+    return IPC_E_ARG;
+  }
+  double *part = nullptr;
+  hipError_t e = ipck::noalloc_scratch(&part);
+  if (e == hipSuccess) {
+    ipck::pairs_ccd_bound(static_cast<hipStream_t>(stream), kind, (int)n, x12, p12, s, part, alpha);
+    e = hipGetLastError();
+  }
+  if (e != hipSuccess) {
+    set_err(hipGetErrorString(e));
+    return IPC_E_DEVICE;
+  }
+  return IPC_OK;
+}
+
 int ipc_grasp_metrics(ipc_scene s, int32_t n_obj_tris, const int32_t *obj_tris, int32_t n_hand_tris,
                       const int32_t *hand_tris, int32_t n_samples, const int32_t *sample_tri, const double *sample_uv,
                       double *D, double *sdf) {

@@ -172,6 +172,11 @@ void dbg_accd(hipStream_t s, int kind, int n, const double *x12, const double *p
 int pairs_ccd_parts(int64_t n);
 void pairs_ccd_bound(hipStream_t s, int kind, int n, const double *x12, const double *p12, double sfac, double *part,
                      double *out);
+// the allocation-free variant's per-block minima: a static device array
+// (*ptr: the current device's copy) holding pairs for up to
+// noalloc_max_pairs() pairs
+int64_t noalloc_max_pairs();
+hipError_t noalloc_scratch(double **ptr);
 // grasp-quality metrics over n_samples points on the gripper (triangle index +
 // barycentric (u, v) into hand_tris) against the manipuland's triangles, at
 // positions x (world vertex ids): sdf [n_samples], part [sdf_parts(n)] block

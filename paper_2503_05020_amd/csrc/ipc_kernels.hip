@@ -2280,6 +2280,13 @@ __global__ void __launch_bounds__(TB) k_min_reduce(const double *part, int n_par
   if (threadIdx.x == 0) out[0] = sh[0];
 }
 
+// Per-block minima of the allocation-free CCD bound: a file-scope device
+// array, one copy per GPU (its storage comes with the code object and lives
+// until the process ends).  Host code reaches it only through the address
+// hipGetSymbolAddress returns for the current device.
+constexpr int kNoAllocParts = 1 << 16;
+static __device__ __align__(256) double ccd_scratch[kNoAllocParts];
+
 // Grasp-quality metrics (Sec. IV-C, Eq. (2)-(3)): one thread per sample point
 // on the gripper's surface, the manipuland's boundary triangles streamed
 // through LDS in tiles of 256; each thread keeps its least squared distance
@@ -2702,6 +2709,28 @@ void dbg_tet(hipStream_t s, const double *X12, const double *x12, double mu, dou
 }
 int pairs_ccd_parts(int64_t n) { return (int)((n + kCcdBlock - 1) / kCcdBlock); }
 
+int64_t noalloc_max_pairs() { return (int64_t)kNoAllocParts * kCcdBlock; }
+
+// Address of the current device's copy of ccd_scratch, looked up once per
+// device and kept (no allocation: a fixed table indexed by device ordinal).
+hipError_t noalloc_scratch(double **ptr) {
+  constexpr int kMaxDev = 64;
+  static std::mutex mu;
+  static double *addr[kMaxDev] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDev) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!addr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(ccd_scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = static_cast<double *>(p);
+  }
+  *ptr = addr[dev];
+  return hipSuccess;
+}
 void pairs_ccd_bound(hipStream_t s, int kind, int n, const double *x12, const double *p12, double sfac, double *part,
                      double *out) {
   const int nb = pairs_ccd_parts(n);

@@ -67,7 +67,7 @@ EXPORTS = [
     "ipc_debug_gradient", "ipc_debug_energy", "ipc_debug_hessian_apply", "ipc_debug_newton_dir",
     "ipc_debug_ccd_bound", "ipc_debug_classify", "ipc_debug_pair_barrier", "ipc_debug_tet_elastic",
     "ipc_debug_accd", "ipc_debug_inversion_bound", "ipc_debug_tet_first_root", "ipc_ccd_bound_pairs",
-    "ipc_grasp_metrics", "ipc_hold_group", "ipc_set_gravity", "ipc_contact_forces",
+    "ipc_ccd_bound_pairs_noalloc", "ipc_grasp_metrics", "ipc_hold_group", "ipc_set_gravity", "ipc_contact_forces",
     "ipc_validate_grasp", "ipc_prof_enable", "ipc_prof_reset", "ipc_prof_read", "ipc_set_tuning", "ipc_get_tuning",
     "ipc_server_create", "ipc_server_submit", "ipc_server_poll", "ipc_server_wait", "ipc_server_result",
     "ipc_server_release", "ipc_server_set_slots", "ipc_server_stats", "ipc_server_destroy",
@@ -148,6 +148,7 @@ def lib():
     L.ipc_set_gravity.argtypes = [vp, _dp]
     L.ipc_contact_forces.argtypes = [vp, _ip, C.c_int32, _dp]
     L.ipc_validate_grasp.argtypes = [vp, C.POINTER(ipc_grasp_protocol), C.POINTER(ipc_grasp_result)]
+    L.ipc_ccd_bound_pairs_noalloc.argtypes = [C.c_int32, C.c_int64, vp, vp, C.c_double, vp, vp]
     L.ipc_debug_inversion_bound.argtypes = [vp, _dp, _dp]
     L.ipc_debug_inversion_bound.restype = C.c_double
     L.ipc_debug_tet_first_root.argtypes = [C.c_int64, _dp, _dp, C.c_double, _dp, _dp]
@@ -450,6 +451,12 @@ def ipc_ccd_bound_pairs(kind, x12, p12, s=0.1):
     a = C.c_double()
     _check(lib().ipc_ccd_bound_pairs(kind, len(x12), _d(x12), _d(p12), s, C.byref(a)))
     return a.value
+
+
+def ipc_ccd_bound_pairs_noalloc(kind, n, x12_dev, p12_dev, alpha_dev, s=0.1, stream=None):
+    """Allocation-free variant: device addresses (ints) of x12 [n*12], p12 [n*12] and alpha [1] FP64
+    buffers; queued on `stream` (a hipStream_t handle as an int, None = null stream), not waited for."""
+    _check(lib().ipc_ccd_bound_pairs_noalloc(kind, n, x12_dev, p12_dev, s, alpha_dev, stream))
 
 
 def ipc_grasp_metrics(scene, obj_tris, hand_tris, sample_tri, sample_uv, want_sdf=False):
