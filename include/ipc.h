@@ -227,6 +227,13 @@ int ipc_prof_read(double *out);
  * IPC_FAIL_ADMIT and goes on).  Lets the failure path be tested without
  * exhausting the GPU. */
 #define IPC_TUNE_ADMIT_FAULTS 6
+/* IPC_TUNE_ASYNC: 1 (default; IPC_ASYNC) = decoupled schedule: within a
+ * lane, an environment that finishes a time step begins its next one while
+ * the others are still iterating theirs, each round being one Newton
+ * iteration of every environment with work; 0 = lock-step time steps (every
+ * environment of the batch finishes step n before any begins step n+1).  The
+ * same results bit for bit (every environment runs the same sequence). */
+#define IPC_TUNE_ASYNC 7
 int ipc_set_tuning(int32_t key, int64_t value);
 int ipc_get_tuning(int32_t key, int64_t *value);
 

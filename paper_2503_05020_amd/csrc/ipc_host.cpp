@@ -620,6 +620,13 @@ struct World {
   DBuf<int2> bp_stash;
   DBuf<double> act_d2, cand_d2, e_c, fw, fn, flam, e_f, ce_g, ce_H, part_a, part_b0, part_b1, part_c0, part_c1;
   DBuf<int4> fv, ce_v;
+  // decoupled schedule: second friction buffers (merged into, then swapped),
+  // per-environment plans of the new friction ranges, host copy of the phases
+  DBuf<int4> fv2;
+  DBuf<double> fw2, fn2, flam2;
+  DBuf<int> fenv2, fplan_b, fplan_e;
+  int *phase_h = nullptr;  // pinned, env_cap entries
+  size_t phase_cap = 0;
   int *pinned = nullptr;  // host mirror of counters
   hipEvent_t poll_ev[2] = {nullptr, nullptr};  // PCG polls in flight (copies into pinned[8], pinned[9])
   // profiling of the PCG matrix product (HIP events on this stream)
@@ -703,7 +710,8 @@ struct World {
                  (void **)&S.dbc_bad,  (void **)&S.cand_beg, (void **)&S.cand_end, (void **)&S.act_beg,
                  (void **)&S.act_end,  (void **)&S.fric_beg, (void **)&S.fric_end, (void **)&S.in_step,
                  (void **)&S.big_beg,  (void **)&S.big_end,  (void **)&S.al,       (void **)&S.al_action,
-                 (void **)&S.snap_bad, (void **)&S.nact,     (void **)&S.lag,      (void **)&S.iter_cap};
+                 (void **)&S.snap_bad, (void **)&S.nact,     (void **)&S.lag,      (void **)&S.iter_cap,
+                 (void **)&S.phase};
     state_ll = {(void **)&S.pcg_total, (void **)&S.amax_bits};
     state_dbl = {(void **)&S.alpha, (void **)&S.E0,  (void **)&S.E1,       (void **)&S.pinf,
                  (void **)&S.pcg_bb, (void **)&S.kA, (void **)&S.viol, (void **)&S.viol_prev,
@@ -1275,6 +1283,62 @@ struct World {
     n_fric = na;
   }
 
+  // Decoupled schedule: environments in phase PH_BEGIN / PH_RELAG take new
+  // lagged friction data from the active pairs at W.x of the current
+  // candidate list (nc pairs, whose boxes contain W.x); environments still
+  // iterating keep theirs; the others drop theirs.  Pairs stay grouped per
+  // environment in batch order and in candidate order within one, the order
+  // a full friction set-up gives.
+  void friction_merge(int nc) {
+    bool moved = scan_tmp.ensure(nc / 1024 + 64);
+    moved |= act.ensure(nc + 1);
+    moved |= act_type.ensure(nc + 1);
+    moved |= act_d2.ensure(nc + 1);
+    if (moved) refresh_lists();
+    ipck::classify_cands(stream, W, envs_d, L, nc, W.x);
+    ipck::cand_restrict(stream, W, S, L, nc);
+    ipck::scan_int(stream, L.cand_flag, L.cand_offs, nc, L.scan_tmp);
+    ipck::compact_active(stream, L, nc);
+    ipck::act_segments(stream, S, B, L);
+    fplan_b.ensure(env_cap + 1);
+    fplan_e.ensure(env_cap + 1);
+    ipck::fric_plan(stream, S, B, fplan_b.p, fplan_e.p, L.counter + 6);
+    int na = 0, total = 0;
+    read_int2(L.cand_offs + nc, L.counter + 6, na, total);
+    fv2.ensure(total + 1);
+    fw2.ensure(4L * (total + 1));
+    fn2.ensure(3L * (total + 1));
+    flam2.ensure(total + 1);
+    fenv2.ensure(total + 1);
+    ipck::fric_merge(stream, W, envs_d, S, B, L, n_fric, na, fplan_b.p, fplan_e.p, fv2.p, fw2.p, fn2.p, flam2.p,
+                     fenv2.p);
+    auto swp = [](auto &a, auto &b) {
+      std::swap(a.p, b.p);
+      std::swap(a.cap, b.cap);
+    };
+    swp(fv, fv2);
+    swp(fw, fw2);
+    swp(fn, fn2);
+    swp(flam, flam2);
+    swp(fenv, fenv2);
+    e_f.ensure(total + 1);
+    n_fric = total;
+    refresh_lists();
+  }
+
+  // host phases of every environment slot -> device (pinned staging)
+  void upload_phases(const std::vector<int> &ph) {
+    if (phase_cap < ph.size()) {
+      HC(hipStreamSynchronize(stream));
+      if (phase_h) HC(hipHostFree(phase_h));
+      phase_cap = std::max<size_t>(ph.size(), 256);
+      HC(hipHostMalloc((void **)&phase_h, phase_cap * sizeof(int), hipHostMallocDefault));
+    }
+    HC(hipStreamSynchronize(stream));  // the previous upload has been read
+    std::memcpy(phase_h, ph.data(), ph.size() * sizeof(int));
+    HC(hipMemcpyAsync(S.phase, phase_h, ph.size() * sizeof(int), hipMemcpyHostToDevice, stream));
+  }
+
   void copy_state_int(int *dst, const int *src) {
     HC(hipMemcpyAsync(dst, src, sizeof(int) * env_cap, hipMemcpyDeviceToDevice, stream));
   }
@@ -1366,6 +1430,9 @@ public:
   // 1: re-lay the batch out with the still-iterating environments once at
   // most half of it iterates (narrow_batch)
   int narrow = env_knob("IPC_NARROW", 1) ? 1 : 0;
+  // 1: the decoupled schedule (run_steps_lane_async): environments begin
+  // their next step as soon as they finish one; 0: lock-step time steps
+  int async_mode = env_knob("IPC_ASYNC", 1) ? 1 : 0;
   bool use_fused() const { return fused_pcg == 1; }
   void set_fused(int on) {
     if ((on != 0) == use_fused()) return;
@@ -1376,6 +1443,7 @@ public:
     set_fused(o.fused_pcg);
     tail_tiles = o.tail_tiles;
     narrow = o.narrow;
+    async_mode = o.async_mode;
     set_prof(o.prof_all ? 2 : o.prof_on ? 1 : 0);
   }
 
@@ -1543,6 +1611,7 @@ public:
       return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     };
     swept_n = -1;
+    ipck::set_phase(stream, S, B, ipcw::PH_BEGIN);
     ipck::env_begin(stream, envs_d, S, B);
     ipck::begin_step(stream, W, envs_d, S, B);
     // one swept pass over the Dirichlet move (free vertices stay at xn): its
@@ -1554,6 +1623,7 @@ public:
     ipck::dbc_check_J(stream, W, envs_d, S, B);
     ipck::env_dbc(stream, S, B);
     ipck::apply_dbc(stream, W, envs_d, S, B);
+    ipck::set_phase(stream, S, B, ipcw::PH_ITER);
     swept_n = nc;  // x is xn, or the targets on kinematic rows: inside these boxes
     int maxit = 0, rounds = 1;
     bool inv = false;
@@ -1570,7 +1640,7 @@ public:
         // another lagged friction update: environments that converged and
         // take one solve again, with friction data taken at their iterate
         set_batch(step_envs);
-        ipck::relag(stream, envs_d, S, B, L.counter + 5);
+        ipck::relag(stream, envs_d, S, B, 0, L.counter + 5);
         if (read_int(L.counter + 5) == 0) break;
         int nc = broad_phase(W.x, nullptr);
         friction_setup(nc);
@@ -1580,7 +1650,7 @@ public:
     }
     swept_n = -1;
     set_batch(step_envs);
-    ipck::step_end(stream, W, envs_d, S, B);
+    ipck::step_end(stream, W, envs_d, S, B, 0);
     HC(hipStreamSynchronize(stream));
     if (prof_on) collect_asm();
   }
@@ -1696,7 +1766,7 @@ struct EnvSnapshot {
 
 // all env slots at once (one copy per field)
 struct EnvSnapshots {
-  std::vector<int> status, reason, iters, halvings, nact;
+  std::vector<int> status, reason, iters, halvings, nact, lag;
   std::vector<long long> pcg_total;
   std::vector<double> E0, dmin2, kappa;
   void fetch(World &w) {
@@ -1710,6 +1780,8 @@ struct EnvSnapshots {
     E0.resize(n);
     dmin2.resize(n);
     kappa.resize(n);
+    lag.resize(n);
+    HC(hipMemcpyAsync(lag.data(), w.S.lag, 4 * n, hipMemcpyDeviceToHost, w.stream));
     HC(hipMemcpyAsync(nact.data(), w.S.nact, 4 * n, hipMemcpyDeviceToHost, w.stream));
     HC(hipMemcpyAsync(dmin2.data(), w.S.dmin2, 8 * n, hipMemcpyDeviceToHost, w.stream));
     HC(hipMemcpyAsync(kappa.data(), w.S.kappa, 8 * n, hipMemcpyDeviceToHost, w.stream));
@@ -1751,6 +1823,175 @@ void get_x(World &w, ipc_scene s, const double *dev_arr, double *host) {
   HC(hipStreamSynchronize(w.stream));
 }
 
+// Decoupled schedule of one lane: every round, the environments in the middle
+// of a time step take one Newton iteration (assembly, solve, convergence
+// test, then CCD and line search), while an environment whose step ended in
+// the round's convergence test ends it at once and begins its next step in
+// the same round (targets, predicted positions, lagged friction and the
+// Dirichlet move), or re-lags its friction.  No environment waits for the
+// others to finish a step, so a round's launches cover every environment
+// that still has work, and the lane's rounds number about the largest total
+// of Newton iterations of one environment instead of the sum over steps of
+// each step's largest.  Each environment goes through exactly the sequence of
+// the lock-step schedule (same lists, same order of every sum), so its
+// results are bitwise those of World::step_batch.
+void run_steps_lane_async(World &w, std::vector<ipc_scene> &scenes, int n_steps, ipc_step_info *infos) {
+  using namespace ipcw;
+  const int n = (int)scenes.size();
+  std::vector<int> remaining(n), stepping(n, 0);
+  for (int i = 0; i < n; ++i) remaining[i] = scenes[i]->failed ? 0 : n_steps;
+  int maxit = 0;
+  bool inv = false;
+  int mixed = 0;
+  for (auto s : scenes) {
+    const EnvDev &E = w.envs_h[s->slot];
+    maxit = std::max(maxit, E.maxit);
+    inv |= E.inv_filter != 0;
+    mixed |= E.precision == IPC_MIXED;
+  }
+  std::vector<int> ph(w.env_cap, PH_ITER);
+  std::vector<int> batch;
+  for (auto s : scenes) batch.push_back(s->slot);
+  EnvSnapshots snap;
+  w.swept_n = -1;
+  bool first = true;
+  auto t0 = std::chrono::steady_clock::now();
+  auto ms = [&]() { return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count(); };
+  for (long round = 0;; ++round) {
+    // 1. one Newton iteration of the environments in the middle of a step
+    if (!first) {
+      int na = w.assemble_system(mixed);
+      long long pit = w.solve(mixed);
+      ipck::conv_check(w.stream, w.W, w.envs_d, w.S, w.B, w.L, w.L.counter + 1);
+      if (World::tracing())
+        std::fprintf(stderr, "[ipc] round %ld: active pairs %d friction %d pcg %lld  %.1f ms\n", round, na, w.n_fric,
+                     pit, ms());
+    }
+    // 2. states; steps that ended, steps that begin, friction re-lags
+    snap.fetch(w);
+    std::fill(ph.begin(), ph.end(), (int)PH_ITER);
+    bool begin = false, relag = false, iterate = false, finish = false;
+    for (int i = 0; i < n; ++i) {
+      ipc_scene s = scenes[i];
+      const int e = s->slot;
+      if (first) {
+        if (remaining[i] > 0) {
+          ph[e] = PH_BEGIN;
+          stepping[i] = 1;
+          begin = true;
+          w.envs_h[e].step = s->step;
+          w.upload_env(e);
+        }
+        continue;
+      }
+      if (!stepping[i]) continue;
+      const int st = snap.status[e];
+      if (st == ST_ACTIVE) {
+        iterate = true;
+        continue;
+      }
+      if (st == ST_CONVERGED && snap.lag[e] + 1 < w.envs_h[e].fric_iters) {
+        ph[e] = PH_RELAG;
+        relag = true;
+        continue;
+      }
+      // the step is over
+      if (infos) {
+        infos[i].newton_iters += snap.iters[e];
+        infos[i].max_newton_iters = std::max(infos[i].max_newton_iters, snap.iters[e]);
+        infos[i].ls_halvings += snap.halvings[e];
+        infos[i].pcg_iters += snap.pcg_total[e];
+        infos[i].energy_last = snap.E0[e];
+        infos[i].kappa_last = snap.kappa[e];
+      }
+      finish = true;
+      if (st == ST_CONVERGED) {
+        s->step += 1;
+        remaining[i] -= 1;
+        if (infos) {
+          infos[i].steps_done += 1;
+          infos[i].n_active_last = snap.nact[e];
+          infos[i].min_dist_last = std::sqrt(snap.dmin2[e]);
+        }
+        if (remaining[i] > 0) {
+          ph[e] = PH_FINISH_BEGIN;
+          begin = true;
+          w.envs_h[e].step = s->step;
+          w.upload_env(e);
+        } else {
+          ph[e] = PH_FINISH;
+          stepping[i] = 0;
+        }
+      } else {
+        s->failed = true;
+        s->fail_reason = (st == ST_FAILED) ? snap.reason[e] : IPC_FAIL_MAXIT;
+        if (infos) {
+          infos[i].status = IPC_E_FAILED;
+          infos[i].fail_reason = s->fail_reason;
+        }
+        ph[e] = PH_FINISH;
+        stepping[i] = 0;
+      }
+    }
+    first = false;
+    if (!begin && !relag && !iterate && !finish) break;
+    // 3. the round's device work
+    w.upload_phases(ph);
+    if (finish) {
+      ipck::step_end(w.stream, w.W, w.envs_d, w.S, w.B, 1);
+      ipck::phase_advance(w.stream, w.S, w.B);
+    }
+    // once at most narrow_pct% of the lane's environments still have work,
+    // lay the batch out again with those alone (before the round's candidate
+    // list, which the next assembly reuses, as the lock-step schedule does)
+    if (w.narrow) {
+      std::vector<int> live;
+      for (int i = 0; i < n; ++i)
+        if (stepping[i]) live.push_back(scenes[i]->slot);
+      if (!live.empty() && live.size() < w.batch_envs.size() &&
+          100 * (int)live.size() <= w.narrow_pct * (int)batch.size())
+        w.set_batch(live);
+    }
+    if (begin) {
+      ipck::env_begin(w.stream, w.envs_d, w.S, w.B);
+      ipck::begin_step(w.stream, w.W, w.envs_d, w.S, w.B);
+    }
+    if (relag) ipck::relag(w.stream, w.envs_d, w.S, w.B, 1, w.L.counter + 5);
+    if (!begin && !relag && !iterate) break;  // only step ends this round
+    if (iterate) ipck::al_prepare(w.stream, w.W, w.S, w.B);
+    // one swept pass: the Newton directions of the iterating environments and
+    // the Dirichlet moves of the beginning ones (their free vertices stay)
+    int ns = w.broad_phase(w.W.x, w.W.p);
+    if (begin || relag) w.friction_merge(ns);
+    ipck::ccd_init(w.stream, w.S, w.B);
+    ipck::accd(w.stream, w.W, w.envs_d, w.S, w.L, ns, w.W.x, w.W.p);
+    if (begin) {
+      ipck::dbc_check_J(w.stream, w.W, w.envs_d, w.S, w.B);
+      ipck::env_dbc(w.stream, w.S, w.B);
+      ipck::apply_dbc(w.stream, w.W, w.envs_d, w.S, w.B);
+    }
+    if (iterate) {
+      if (inv) ipck::inv_bound(w.stream, w.W, w.envs_d, w.S, w.B, 0);
+      ipck::snap_J(w.stream, w.W, w.S, w.B);
+      ipck::ls_init(w.stream, w.S, w.B);
+      ipck::energy(w.stream, w.W, w.envs_d, w.S, w.B, w.L, ns, w.n_fric, 1, w.S.E0);
+      for (int trial = 0; trial < 64; ++trial) {
+        ipck::energy(w.stream, w.W, w.envs_d, w.S, w.B, w.L, ns, w.n_fric, 0, w.S.E1);
+        ipck::ls_decide(w.stream, w.S, w.B, w.L.counter + 2);
+        if (w.read_int(w.L.counter + 2) == 0) break;
+      }
+      ipck::al_finish(w.stream, w.W, w.envs_d, w.S, w.B);
+      ipck::update_x(w.stream, w.W, w.S, w.B);
+    }
+    ipck::iter_end(w.stream, w.envs_d, w.S, w.B, w.L.counter + 3);
+    w.swept_n = ns;
+  }
+  w.swept_n = -1;
+  w.set_batch(batch);
+  HC(hipStreamSynchronize(w.stream));
+  if (w.prof_on) w.collect_asm();
+}
+
 // steps scenes that all live in one lane
 void run_steps_lane(std::vector<ipc_scene> scenes, int n_steps, ipc_step_info *infos) {
   if (scenes.empty()) return;
@@ -1772,6 +2013,10 @@ void run_steps_lane(std::vector<ipc_scene> scenes, int n_steps, ipc_step_info *i
       infos[i].status = scenes[i]->failed ? IPC_E_FAILED : IPC_OK;
       infos[i].fail_reason = scenes[i]->fail_reason;
     }
+  if (w.async_mode) {
+    run_steps_lane_async(w, scenes, n_steps, infos);
+    return;
+  }
   EnvSnapshots snap;
   for (int st = 0; st < n_steps; ++st) {
     bool any = false;
@@ -2255,7 +2500,7 @@ int ipc_set_tuning(int32_t key, int64_t value) {
       return IPC_OK;
     }
     if (key != IPC_TUNE_TAIL_TILES && key != IPC_TUNE_FUSED_PCG && key != IPC_TUNE_NARROW &&
-        key != IPC_TUNE_ADMIT_FAULTS)
+        key != IPC_TUNE_ADMIT_FAULTS && key != IPC_TUNE_ASYNC)
       throw ApiError(IPC_E_ARG, "unknown tuning key");
     for (World *pw : worlds_for_current_device()) {
       World &w = *pw;
@@ -2266,6 +2511,8 @@ int ipc_set_tuning(int32_t key, int64_t value) {
         w.set_fused(value != 0);
       else if (key == IPC_TUNE_ADMIT_FAULTS)
         w.admit_faults = (int)std::min<int64_t>(value, 1 << 30);
+      else if (key == IPC_TUNE_ASYNC)
+        w.async_mode = value != 0;
       else
         w.narrow = value != 0;
     }
@@ -2290,6 +2537,8 @@ int ipc_get_tuning(int32_t key, int64_t *value) {
       *value = w.narrow;
     else if (key == IPC_TUNE_ADMIT_FAULTS)
       *value = w.admit_faults;
+    else if (key == IPC_TUNE_ASYNC)
+      *value = w.async_mode;
     else
       throw ApiError(IPC_E_ARG, "unknown tuning key");
     return IPC_OK;
@@ -2470,6 +2719,7 @@ int ipc_debug_begin_step(ipc_scene s, double *x_start) {
       DebugScope D(s);
       w.envs_h[s->slot].step = s->step;
       w.upload_env(s->slot);
+      ipck::set_phase(w.stream, w.S, w.B, ipcw::PH_BEGIN);
       ipck::env_begin(w.stream, w.envs_d, w.S, w.B);
       ipck::begin_step(w.stream, w.W, w.envs_d, w.S, w.B);
       int nc = w.broad_phase(w.W.xn, w.W.p);
@@ -2479,6 +2729,7 @@ int ipc_debug_begin_step(ipc_scene s, double *x_start) {
       ipck::dbc_check_J(w.stream, w.W, w.envs_d, w.S, w.B);
       ipck::env_dbc(w.stream, w.S, w.B);
       ipck::apply_dbc(w.stream, w.W, w.envs_d, w.S, w.B);
+      ipck::set_phase(w.stream, w.S, w.B, ipcw::PH_ITER);
       if (x_start) get_x(w, s, w.W.x, x_start);
     }
     return IPC_OK;

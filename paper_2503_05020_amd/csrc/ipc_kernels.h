@@ -150,14 +150,28 @@ void accd(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, 
 void inv_bound(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, int force);
 // friction lag rounds: reactivates converged environments that take another
 // lagged friction update this step; *n_relag = their number
-void relag(hipStream_t s, const EnvDev *E, const EnvState &S, const Batch &B, int *n_relag);
+// sel = 0: every converged environment with lag rounds left; sel = 1: those
+// in phase PH_RELAG (decoupled schedule)
+void relag(hipStream_t s, const EnvDev *E, const EnvState &S, const Batch &B, int sel, int *n_relag);
+// decoupled schedule: phase of every batch environment; the phase step after k_step_end
+void set_phase(hipStream_t s, const EnvState &S, const Batch &B, int ph);
+void phase_advance(hipStream_t s, const EnvState &S, const Batch &B);
+// friction merge: clear the active flags of candidates whose environment keeps
+// its friction; plan the new per-environment ranges (total -> *total); copy
+// the kept pairs and set up the new ones into the second buffers
+void cand_restrict(hipStream_t s, const WorldDev &W, const EnvState &S, const Lists &L, int n);
+void fric_plan(hipStream_t s, const EnvState &S, const Batch &B, int *nb, int *ne, int *total);
+void fric_merge(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, const Lists &L,
+                int n_old, int n_act, const int *nb, const int *ne, int4 *fv2, double *fw2, double *fn2, double *flam2,
+                int *fenv2);
 void ls_init(hipStream_t s, const EnvState &S, const Batch &B);
 void energy(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L, int n_cand,
             int n_fric, int zero_alpha, double *E_out);
 void ls_decide(hipStream_t s, const EnvState &S, const Batch &B, int *pending);
 void update_x(hipStream_t s, const WorldDev &W, const EnvState &S, const Batch &B);
 void iter_end(hipStream_t s, const EnvDev *E, const EnvState &S, const Batch &B, int *n_active);
-void step_end(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B);
+// sel = 0: every environment in the step; sel = 1: those whose phase ends it
+void step_end(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, int sel);
 
 void stress(hipStream_t s, const WorldDev &W, int t_off, int nt, double *cauchy, double *vm);
 

@@ -109,9 +109,11 @@ DEV bool is_dof(const WorldDev &W, const EnvState &S, int i, int env) {
 // ---------------------------------------------------------------------------
 // step set-up: kinematic targets, predicted positions, Dirichlet displacement
 // ---------------------------------------------------------------------------
+DEV bool begins(const EnvState &S, int env) { return S.status[env] == ST_ACTIVE && S.phase[env] == PH_BEGIN; }
+
 __global__ void k_begin_step(WorldDev W, const EnvDev *envs, EnvState S, const Tile *tiles) {
   Tile t = tiles[blockIdx.x];
-  if ((int)threadIdx.x >= t.count || !active_env(S, t.env)) return;
+  if ((int)threadIdx.x >= t.count || !begins(S, t.env)) return;
   const EnvDev &E = envs[t.env];
   int i = t.start + threadIdx.x;
   int k = W.kin[i];
@@ -151,7 +153,7 @@ __global__ void k_begin_step(WorldDev W, const EnvDev *envs, EnvState S, const T
 
 __global__ void k_dbc_J(WorldDev W, const EnvDev *envs, EnvState S, const Tile *tiles) {
   Tile t = tiles[blockIdx.x];
-  if ((int)threadIdx.x >= t.count || !active_env(S, t.env)) return;
+  if ((int)threadIdx.x >= t.count || !begins(S, t.env)) return;
   int e = t.start + threadIdx.x;
   int4 q = W.tet[e];
   int v[4] = {q.x, q.y, q.z, q.w};
@@ -164,7 +166,7 @@ __global__ void k_dbc_J(WorldDev W, const EnvDev *envs, EnvState S, const Tile *
 
 __global__ void k_apply_dbc(WorldDev W, EnvState S, const Tile *tiles) {
   Tile t = tiles[blockIdx.x];
-  if ((int)threadIdx.x >= t.count || !active_env(S, t.env)) return;
+  if ((int)threadIdx.x >= t.count || !begins(S, t.env)) return;
   int i = t.start + threadIdx.x;
   if (W.kin[i] < 0) return;
   if (S.al[t.env]) {
@@ -178,6 +180,7 @@ __global__ void k_env_begin(const EnvDev *envs, EnvState S, const int *benv, int
   int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
   int e = benv[j];
+  if (S.phase[e] != PH_BEGIN) return;
   S.in_step[e] = 0;
   if (S.status[e] == ST_FAILED) return;
   S.in_step[e] = 1;
@@ -198,7 +201,7 @@ __global__ void k_env_dbc(EnvState S, const int *envs, int n) {
   int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
   int e = envs[j];
-  if (S.status[e] != ST_ACTIVE) return;
+  if (!begins(S, e)) return;
   double a = __longlong_as_double((long long)S.amax_bits[e]);
   if (a < 1.0 || S.dbc_bad[e]) {
     // the prescribed move is not feasible in one go: the kinematic vertices
@@ -841,18 +844,21 @@ __global__ void __launch_bounds__(128) k_barrier_elems(WorldDev W, const EnvDev 
 }
 
 // lagged friction data at x^n (positions in W.x at set-up time)
+// (nb != nullptr: the pair of environment env goes to position nb[env] + its
+// index within the environment's active pairs, act_beg the first of those)
 __global__ void k_friction_setup(WorldDev W, const EnvDev *envs, const double *kap, const int2 *act,
                                  const int *act_type, int n, int4 *fv, double *fw, double *fn, double *flam,
-                                 int *fenv) {
-  int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n) return;
+                                 int *fenv, const int *nb, const int *act_beg) {
+  int kk = blockIdx.x * blockDim.x + threadIdx.x;
+  if (kk >= n) return;
   int kind, v[4], env;
   double ex;
-  pair_info(W, act[k], kind, v, env, ex);
+  pair_info(W, act[kk], kind, v, env, ex);
+  const int k = nb ? nb[env] + (kk - act_beg[env]) : kk;
   const EnvDev &E = envs[env];
   double xx[12], w[4];
   gather12(W.x, v, xx);
-  int ty = act_type[k];
+  int ty = act_type[kk];
   closest_weights(kind, ty, xx, w);
   double dv[3] = {0, 0, 0};
   for (int i = 0; i < 4; ++i)
@@ -891,9 +897,14 @@ __global__ void k_pair_force(WorldDev W, const EnvDev *envs, const double *kap, 
   double xx[12], w[4];
   gather12(W.x, v, xx);
   closest_weights(kind, act_type[k], xx, w);
+  // closest_weights gives the closest-point difference up to orientation:
+  // make it point from the second side to the first (the first side's
+  // weights sum to +1)
+  const double first = kind == 0 ? w[0] : w[0] + w[1];
+  const double sg = first < 0.0 ? -1.0 : 1.0;
   double dv[3] = {0, 0, 0};
   for (int i = 0; i < 4; ++i)
-    for (int c = 0; c < 3; ++c) dv[c] += w[i] * xx[3 * i + c];
+    for (int c = 0; c < 3; ++c) dv[c] += sg * w[i] * xx[3 * i + c];
   const double dn = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
   double d2;
   classify(kind, xx, &d2);
@@ -1971,7 +1982,7 @@ __global__ void __launch_bounds__(128) k_accd(WorldDev W, EnvState S, const int2
 __global__ void k_inv_bound(WorldDev W, const EnvDev *envs, EnvState S, const Tile *tiles, int force) {
   Tile t = tiles[blockIdx.x];
   if ((int)threadIdx.x >= t.count || !active_env(S, t.env)) return;
-  if (!force && (S.al_action[t.env] != 0 || !envs[t.env].inv_filter)) return;
+  if (!force && (S.al_action[t.env] != 0 || !envs[t.env].inv_filter || S.phase[t.env] != PH_ITER)) return;
   int e = t.start + threadIdx.x;
   int4 q = W.tet[e];
   int v[4] = {q.x, q.y, q.z, q.w};
@@ -1985,11 +1996,13 @@ __global__ void k_inv_bound(WorldDev W, const EnvDev *envs, EnvState S, const Ti
 // friction lag round: an environment whose Newton solve converged and that
 // takes more lagged friction updates this step solves again (friction data
 // are then taken at its converged iterate), with a fresh iteration budget
-__global__ void k_relag(const EnvDev *envs, EnvState S, const int *benv, int n, int *n_relag) {
+__global__ void k_relag(const EnvDev *envs, EnvState S, const int *benv, int n, int sel, int *n_relag) {
   int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
   int e = benv[j];
-  if (!S.in_step[e] || S.status[e] != ST_CONVERGED || S.lag[e] + 1 >= envs[e].fric_iters) return;
+  if (sel ? S.phase[e] != PH_RELAG
+          : (!S.in_step[e] || S.status[e] != ST_CONVERGED || S.lag[e] + 1 >= envs[e].fric_iters))
+    return;
   S.lag[e] += 1;
   S.status[e] = ST_ACTIVE;
   S.iter_cap[e] = S.iters[e] + envs[e].maxit;
@@ -2002,7 +2015,7 @@ __global__ void k_ls_init(EnvState S, const int *benv, int n) {
   if (j >= n) return;
   int e = benv[j];
   S.alpha[e] = __longlong_as_double((long long)S.amax_bits[e]);
-  S.ls_done[e] = (S.status[e] == ST_ACTIVE && S.al_action[e] == 0) ? 0 : 1;
+  S.ls_done[e] = (S.status[e] == ST_ACTIVE && S.al_action[e] == 0 && S.phase[e] == PH_ITER) ? 0 : 1;
   S.ls_cnt[e] = 0;
 }
 
@@ -2127,7 +2140,9 @@ __global__ void k_ls_decide(EnvState S, const int *benv, int n, int *pending) {
 
 __global__ void k_update_x(WorldDev W, EnvState S, const Tile *tiles) {
   Tile t = tiles[blockIdx.x];
-  if ((int)threadIdx.x >= t.count || S.status[t.env] != ST_ACTIVE || S.al_action[t.env] != 0) return;
+  if ((int)threadIdx.x >= t.count || S.status[t.env] != ST_ACTIVE || S.al_action[t.env] != 0 ||
+      S.phase[t.env] != PH_ITER)
+    return;
   int i = t.start + threadIdx.x;
   double a = S.alpha[t.env];
   for (int c = 0; c < 3; ++c) W.x[3 * i + c] += a * W.p[3 * i + c];
@@ -2146,9 +2161,12 @@ __global__ void k_iter_end(const EnvDev *envs, EnvState S, const int *benv, int 
   atomicAdd(n_active, 1);
 }
 
-__global__ void k_step_end(WorldDev W, const EnvDev *envs, EnvState S, const Tile *tiles) {
+// sel = 0: every environment that took part in the step; sel = 1: those
+// whose phase ends a step (the decoupled schedule)
+__global__ void k_step_end(WorldDev W, const EnvDev *envs, EnvState S, const Tile *tiles, int sel) {
   Tile t = tiles[blockIdx.x];
   if ((int)threadIdx.x >= t.count || !S.in_step[t.env]) return;
+  if (sel && S.phase[t.env] != PH_FINISH && S.phase[t.env] != PH_FINISH_BEGIN) return;
   int st = S.status[t.env];
   int i = t.start + threadIdx.x;
   if (st == ST_CONVERGED) {
@@ -2157,6 +2175,86 @@ __global__ void k_step_end(WorldDev W, const EnvDev *envs, EnvState S, const Til
   } else if (st == ST_FAILED) {
     for (int c = 0; c < 3; ++c) W.x[3 * i + c] = W.xn[3 * i + c];
   }
+}
+
+// after k_step_end of the decoupled schedule: an environment that ended its
+// step rests (converged) or stays failed, and one that goes on begins
+__global__ void k_phase_advance(EnvState S, const int *benv, int n) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  int e = benv[j];
+  const int ph = S.phase[e];
+  if (ph == PH_FINISH || ph == PH_FINISH_BEGIN) {
+    if (S.status[e] == ST_CONVERGED) S.status[e] = ST_IDLE;
+    S.phase[e] = ph == PH_FINISH_BEGIN ? PH_BEGIN : PH_ITER;
+  }
+}
+
+__global__ void k_set_phase(EnvState S, const int *benv, int n, int ph) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < n) S.phase[benv[j]] = ph;
+}
+
+// ---------------------------------------------------------------------------
+// friction merge of the decoupled schedule: environments that begin a step or
+// re-lag take new friction data from the active pairs of this round's list;
+// the others keep theirs.  Pairs are stored per environment in batch order.
+// ---------------------------------------------------------------------------
+DEV bool new_friction(const EnvState &S, int env) {
+  return S.status[env] == ST_ACTIVE && (S.phase[env] == PH_BEGIN || S.phase[env] == PH_RELAG);
+}
+DEV bool keeps_friction(const EnvState &S, int env) { return S.status[env] == ST_ACTIVE && S.phase[env] == PH_ITER; }
+
+// candidates of environments that keep their friction are not active here
+__global__ void k_cand_restrict(WorldDev W, EnvState S, const int2 *cand, int n, int *flag) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  int kind, v[4], env;
+  double ex;
+  pair_info(W, cand[k], kind, v, env, ex);
+  if (!new_friction(S, env)) flag[k] = 0;
+}
+
+// new friction ranges in batch order (one thread: a few hundred environments);
+// nb[e] = -1 for environments whose friction is dropped
+__global__ void k_fric_plan(EnvState S, const int *benv, int n, int *nb, int *ne, int *total) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  int off = 0;
+  for (int j = 0; j < n; ++j) {
+    const int e = benv[j];
+    int c = -1;
+    if (new_friction(S, e))
+      c = S.act_end[e] - S.act_beg[e];
+    else if (keeps_friction(S, e))
+      c = S.fric_end[e] - S.fric_beg[e];
+    nb[e] = c < 0 ? -1 : off;
+    ne[e] = c < 0 ? -1 : off + c;
+    off += c < 0 ? 0 : c;
+  }
+  *total = off;
+}
+
+__global__ void k_fric_copy(EnvState S, int n_old, const int4 *fv, const double *fw, const double *fn,
+                            const double *flam, const int *fenv, const int *nb, int4 *fv2, double *fw2, double *fn2,
+                            double *flam2, int *fenv2) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_old) return;
+  const int e = fenv[k];
+  if (!keeps_friction(S, e) || nb[e] < 0) return;
+  const int o = nb[e] + (k - S.fric_beg[e]);
+  fv2[o] = fv[k];
+  for (int i = 0; i < 4; ++i) fw2[4 * o + i] = fw[4 * k + i];
+  for (int c = 0; c < 3; ++c) fn2[3 * o + c] = fn[3 * k + c];
+  flam2[o] = flam[k];
+  fenv2[o] = e;
+}
+
+__global__ void k_fric_commit(EnvState S, const int *benv, int n, const int *nb, const int *ne) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const int e = benv[j];
+  S.fric_beg[e] = nb[e] < 0 ? 0 : nb[e];
+  S.fric_end[e] = nb[e] < 0 ? 0 : ne[e];
 }
 
 // ---------------------------------------------------------------------------
@@ -2460,7 +2558,30 @@ void barrier_elems(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvS
 void friction_setup(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Lists &L, int n_act) {
   if (n_act)
     IPC_LAUNCH(k_friction_setup, nblk(n_act, TB), TB, s)(W, E, S.kappa, L.act, L.act_type, n_act, L.fv, L.fw, L.fn,
-                                                         L.flam, L.fenv);
+                                                         L.flam, L.fenv, nullptr, nullptr);
+}
+void cand_restrict(hipStream_t s, const WorldDev &W, const EnvState &S, const Lists &L, int n) {
+  if (n) IPC_LAUNCH(k_cand_restrict, nblk(n, TB), TB, s)(W, S, L.cand, n, L.cand_flag);
+}
+void fric_plan(hipStream_t s, const EnvState &S, const Batch &B, int *nb, int *ne, int *total) {
+  IPC_LAUNCH(k_fric_plan, 1, 64, s)(S, B.envs, B.n_envs, nb, ne, total);
+}
+void fric_merge(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, const Lists &L,
+                int n_old, int n_act, const int *nb, const int *ne, int4 *fv2, double *fw2, double *fn2, double *flam2,
+                int *fenv2) {
+  if (n_old)
+    IPC_LAUNCH(k_fric_copy, nblk(n_old, TB), TB, s)(S, n_old, L.fv, L.fw, L.fn, L.flam, L.fenv, nb, fv2, fw2, fn2,
+                                                    flam2, fenv2);
+  if (n_act)
+    IPC_LAUNCH(k_friction_setup, nblk(n_act, TB), TB, s)(W, E, S.kappa, L.act, L.act_type, n_act, fv2, fw2, fn2,
+                                                         flam2, fenv2, nb, S.act_beg);
+  IPC_LAUNCH(k_fric_commit, nblk(B.n_envs, 64), 64, s)(S, B.envs, B.n_envs, nb, ne);
+}
+void set_phase(hipStream_t s, const EnvState &S, const Batch &B, int ph) {
+  IPC_LAUNCH(k_set_phase, nblk(B.n_envs, 64), 64, s)(S, B.envs, B.n_envs, ph);
+}
+void phase_advance(hipStream_t s, const EnvState &S, const Batch &B) {
+  IPC_LAUNCH(k_phase_advance, nblk(B.n_envs, 64), 64, s)(S, B.envs, B.n_envs);
 }
 void friction_elems(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Lists &L, int n_fric,
                     int ce_off, const double *x) {
@@ -2660,9 +2781,9 @@ void accd(hipStream_t s, const WorldDev &W, const EnvDev *, const EnvState &S, c
 void inv_bound(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, int force) {
   if (B.n_tt) IPC_LAUNCH(k_inv_bound, B.n_tt, TB, s)(W, E, S, B.ttiles, force);
 }
-void relag(hipStream_t s, const EnvDev *E, const EnvState &S, const Batch &B, int *n_relag) {
+void relag(hipStream_t s, const EnvDev *E, const EnvState &S, const Batch &B, int sel, int *n_relag) {
   IPC_LAUNCH(k_fill_int, 1, 64, s)(n_relag, 1, 0);
-  IPC_LAUNCH(k_relag, nblk(B.n_envs, 64), 64, s)(E, S, B.envs, B.n_envs, n_relag);
+  IPC_LAUNCH(k_relag, nblk(B.n_envs, 64), 64, s)(E, S, B.envs, B.n_envs, sel, n_relag);
 }
 void ls_init(hipStream_t s, const EnvState &S, const Batch &B) {
   IPC_LAUNCH(k_ls_init, nblk(B.n_envs, 64), 64, s)(S, B.envs, B.n_envs);
@@ -2689,8 +2810,8 @@ void iter_end(hipStream_t s, const EnvDev *E, const EnvState &S, const Batch &B,
   IPC_LAUNCH(k_fill_int, 1, 64, s)(n_active, 1, 0);
   IPC_LAUNCH(k_iter_end, nblk(B.n_envs, 64), 64, s)(E, S, B.envs, B.n_envs, n_active);
 }
-void step_end(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B) {
-  if (B.n_vt) IPC_LAUNCH(k_step_end, B.n_vt, TB, s)(W, E, S, B.vtiles);
+void step_end(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, int sel) {
+  if (B.n_vt) IPC_LAUNCH(k_step_end, B.n_vt, TB, s)(W, E, S, B.vtiles, sel);
 }
 
 void stress(hipStream_t s, const WorldDev &W, int t_off, int nt, double *cauchy, double *vm) {

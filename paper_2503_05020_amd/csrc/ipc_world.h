@@ -18,6 +18,12 @@ constexpr int kSlice = 64;     // rows per sliced-ELL slice (one wavefront)
 constexpr int kFusedRows = 8192;  // environments up to this many rows solve in one workgroup
 
 enum Status { ST_IDLE = 0, ST_ACTIVE = 1, ST_CONVERGED = 2, ST_FAILED = 3 };
+// Phase of an environment in one round of the decoupled schedule: PH_ITER
+// (iterating, or not in the round), PH_BEGIN (starts a time step: targets,
+// predicted positions, lagged friction, Dirichlet move), PH_RELAG (takes its
+// friction data again at its converged iterate), PH_FINISH (ends its step),
+// PH_FINISH_BEGIN (ends its step and starts the next).
+enum Phase { PH_ITER = 0, PH_BEGIN = 1, PH_RELAG = 2, PH_FINISH = 3, PH_FINISH_BEGIN = 4 };
 enum Fail { FAIL_NONE = 0, FAIL_MAXIT = 1, FAIL_NONFINITE = 2, FAIL_LS = 3, FAIL_DBC = 4 };
 
 // vertex kind codes in kin[]: >= 0 kinematic group, -1 free, -2 padding row
@@ -78,6 +84,8 @@ struct EnvState {
   // iteration count at which the current round fails
   int *nact, *lag, *iter_cap;
   double *dmin2;
+  // what the environment does in the current round of work (PH_*)
+  int *phase;
   // PCG step length and r.u of the last two iterations (slot = iteration & 1)
   double *cg_a0, *cg_a1, *cg_g0, *cg_g1;
 };

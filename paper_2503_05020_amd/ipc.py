@@ -28,6 +28,7 @@ IPC_TUNE_FUSED_PCG = 2
 IPC_TUNE_NARROW = 4
 IPC_TUNE_LANES = 5
 IPC_TUNE_ADMIT_FAULTS = 6
+IPC_TUNE_ASYNC = 7
 IPC_FAIL_ADMIT = 6
 FAIL_REASONS = {0: "none", 1: "maxit", 2: "nonfinite", 3: "line-search", 4: "dirichlet"}
 

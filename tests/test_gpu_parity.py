@@ -317,6 +317,83 @@ def test_lane_count_changes_no_result():
         assert np.array_equal(a, b)
 
 
+def _async_batch(precision):
+    """Environments whose steps take different Newton iteration counts: cube drops at different heights
+    (impact at different steps), a plate pressed faster than the gap allows (augmented-Lagrangian
+    Dirichlet mode), a block sliding on an incline with two lagged friction updates per step, a cube
+    with the inversion filter and adaptive kappa, and one that fails (one Newton iteration allowed)."""
+    scs = [S.soft_cube_drop(cells=2, edge=0.04, height=0.002 + 0.002 * i, seed=i) for i in range(4)]
+    scs.append(S.press_block(steps=4))
+    inc = S.block_on_incline(45.0)
+    inc["friction_iters"] = 2
+    scs.append(inc)
+    var = S.soft_cube_drop(cells=2, edge=0.02, height=0.0015, kappa=0.005, seed=7)
+    var["inversion_filter"] = 1
+    var["adaptive_kappa"] = 1
+    scs.append(var)
+    bad = S.soft_cube_drop(cells=2, edge=0.04, height=0.001, seed=9)
+    bad["newton_max_iter"] = 1
+    scs.append(bad)
+    return scs
+
+
+@pytest.mark.parametrize("precision", [G.IPC_FP64, G.IPC_MIXED])
+def test_decoupled_schedule_same_bits_as_lock_step(precision):
+    """Within a lane, environments that finish a step begin the next while the others still iterate
+    (IPC_TUNE_ASYNC = 1): every environment runs the same sequence as under lock-step time steps, so
+    positions, velocities and per-step records are bitwise equal, failure included."""
+    scs = _async_batch(precision)
+    before = G.ipc_get_tuning(G.IPC_TUNE_ASYNC)
+    runs = []
+    try:
+        for mode in (0, 1):
+            G.ipc_set_tuning(G.IPC_TUNE_ASYNC, mode)
+            gs = [G.ipc_create_scene(sc, precision=precision, pcg_rel_tol=1e-6) for sc in scs]
+            recs = []
+            for chunk in (3, 5):  # two calls: the second starts from the state the first left
+                rc, infos = G.ipc_step_batch(gs, chunk)
+                recs.append(infos)
+            say(f"mode {mode}:", [i["steps_done"] for i in recs[0]], [i["newton_iters"] for i in recs[1]])
+            runs.append(([G.ipc_get_state(g) for g in gs], recs))
+            for g in gs:
+                G.ipc_destroy_scene(g)
+    finally:
+        G.ipc_set_tuning(G.IPC_TUNE_ASYNC, before)
+    (st0, rec0), (st1, rec1) = runs
+    assert rec0[0][-1]["status"] != 0 and rec0[0][-1]["fail_reason"] == 1  # the failing one
+    for (p0, v0), (p1, v1) in zip(st0, st1):
+        assert np.array_equal(p0, p1) and np.array_equal(v0, v1)
+    for a, b in zip(rec0, rec1):
+        for i0, i1 in zip(a, b):
+            for k in ("steps_done", "status", "fail_reason", "newton_iters", "max_newton_iters", "ls_halvings",
+                      "pcg_iters", "n_active_last", "kappa_last"):
+                assert i0[k] == i1[k], (k, i0, i1)
+            assert i0["min_dist_last"] == i1["min_dist_last"] or (np.isinf(i0["min_dist_last"])
+                                                                  and np.isinf(i1["min_dist_last"]))
+
+
+def test_decoupled_schedule_superquadric_batch_same_bits():
+    """The benchmark's workload (first 32 environments, mixed precision) over 8 steps through first contact:
+    decoupled and lock-step schedules give the same bits."""
+    scs = [S.superquadric_grasp(i) for i in range(32)]
+    before = G.ipc_get_tuning(G.IPC_TUNE_ASYNC)
+    runs = []
+    try:
+        for mode in (0, 1):
+            G.ipc_set_tuning(G.IPC_TUNE_ASYNC, mode)
+            gs = [G.ipc_create_scene(sc, precision=G.IPC_MIXED, pcg_rel_tol=1e-4) for sc in scs]
+            G.ipc_step_batch(gs, 6)
+            rc, infos = G.ipc_step_batch(gs, 8)
+            runs.append(([G.ipc_get_state(g)[0] for g in gs], [i["newton_iters"] for i in infos]))
+            for g in gs:
+                G.ipc_destroy_scene(g)
+    finally:
+        G.ipc_set_tuning(G.IPC_TUNE_ASYNC, before)
+    assert runs[0][1] == runs[1][1]
+    for a, b in zip(runs[0][0], runs[1][0]):
+        assert np.array_equal(a, b)
+
+
 def test_alone_equals_batch_bitwise():
     say("alone vs batch")
     scs = [S.soft_cube_drop(cells=2, edge=0.04, height=0.002 + 0.001 * i, seed=i) for i in range(3)]
