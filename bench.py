@@ -346,6 +346,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=48, help="0 skips the serving run")
     ap.add_argument("--serve-slots", type=int, default=0, help="0 = slot cap tuned by the server")
+    ap.add_argument("--serve-rate", type=float, default=50.0, help="request arrivals per second")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="only run the serving sample (--serve-requests at --serve-rate) and print its JSON object")
     ap.add_argument("--count-all-bytes", action="store_true",
                     help="count the algorithmic bytes of every PCG product launch (warm-up included), time none")
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -372,6 +375,10 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_read": n, "copy_probe_bytes_written": n, "launches": 5}), flush=True)
         return
+    if args.serve_only:
+        serve = serving(args.serve_requests, args.serve_rate, 200 << 30, args.serve_slots, G.IPC_MIXED)
+        print(json.dumps({"serving": serve}), flush=True)
+        return
     scs = make_scenes(args.workload, args.envs)
     ntets = sum(len(sc["E"]) for sc in scs)
     log(f"workload {args.workload}: {len(scs)} envs, {ntets} tets")
@@ -397,7 +404,7 @@ def main():
         log(f"sequential single-env: {seq['value']:.2f} env-steps/s")
     serve = None
     if args.serve_requests > 0:
-        serve = serving(args.serve_requests, 50.0, 200 << 30, args.serve_slots, G.IPC_MIXED)
+        serve = serving(args.serve_requests, args.serve_rate, 200 << 30, args.serve_slots, G.IPC_MIXED)
         log(f"[serving] {serve}")
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.workload, len(scs), args.warmup, args.steps)
     horizon = None

@@ -410,17 +410,22 @@ int64_t ipc_debug_tet_first_root(int64_t n, const double *x12, const double *p12
  * A server owns one worker thread per lane of the device (IPC_TUNE_LANES).
  * Each worker, tick after tick: (1) admits queued requests into its lane, in
  * submission order, while fewer than max_slots requests run in all, its lane
- * holds less than its share (max_slots / lanes, rounded up) and the device
- * bytes of the resident state (positions and velocities, meshes, sparsity
- * pattern, PCG vectors: ipc_request_info.bytes) fit in budget_bytes; (2)
- * advances every request running in its lane by one time step, all of them in
- * one batch through the same kernels as ipc_step_batch; (3) retires the
- * requests that completed their steps or failed, keeping their final state
- * for ipc_server_result and freeing their slot and memory.  Requests thus join
- * and leave a batch between time steps while the others keep running, lanes
- * run concurrently, and a request's result is bitwise the same as when it
- * runs alone.  Per-step contact and candidate lists are work buffers of the
- * lanes and are not counted in the budget.
+ * holds less than its share (max_slots / lanes, rounded up) and the request's
+ * admission charge fits in budget_bytes; (2) advances the requests running in
+ * its lane, all of them in one batch through the same kernels as
+ * ipc_step_batch; (3) retires the requests that completed their steps or
+ * failed, keeping their final state for ipc_server_result and freeing their
+ * slot and memory.  Under the decoupled schedule (IPC_TUNE_ASYNC = 1, the
+ * default) a tick is one round of it: every running request takes one Newton
+ * iteration, or ends its step and begins the next, so requests join and leave
+ * between Newton iterations; with IPC_TUNE_ASYNC = 0 a tick is one time step
+ * of every running request.  Lanes run concurrently, and a request's result
+ * is bitwise the same as when it runs alone.  The admission charge
+ * (ipc_request_info.bytes) is the resident state (positions and velocities,
+ * meshes, sparsity pattern, PCG vectors) plus half again for the arenas'
+ * growth, plus an estimate of the request's share of the lane's per-step
+ * contact and candidate lists, which scales with its surface; denser contact
+ * than the estimate grows those lists beyond the charge.
  *
  * The paper (Sec. IV) runs its grasp pipeline as many independent
  * environments; this interface serves such environments as they arrive.
@@ -452,7 +457,7 @@ typedef struct {
 /* Creates a server on the current device.  budget_bytes > 0; max_slots >= 1
  * fixes the slot cap, max_slots = 0 lets the server tune it: starting at 8
  * per lane, while requests are waiting it doubles the cap after every window
- * of 8 ticks per lane, unless that window's seconds per converged step exceed
+ * of 8 ticks per lane (64 under the decoupled schedule), unless that window's seconds per converged step exceed
  * 1.5x the best window's, in which case it settles on the best window's cap. */
 int ipc_server_create(int64_t budget_bytes, int32_t max_slots, ipc_server *out);
 /* Validates and copies the scene (as ipc_create_scene; same error codes, and

@@ -1835,56 +1835,117 @@ void get_x(World &w, ipc_scene s, const double *dev_arr, double *host) {
 // each step's largest.  Each environment goes through exactly the sequence of
 // the lock-step schedule (same lists, same order of every sum), so its
 // results are bitwise those of World::step_batch.
-void run_steps_lane_async(World &w, std::vector<ipc_scene> &scenes, int n_steps, ipc_step_info *infos) {
-  using namespace ipcw;
-  const int n = (int)scenes.size();
-  std::vector<int> remaining(n), stepping(n, 0);
-  for (int i = 0; i < n; ++i) remaining[i] = scenes[i]->failed ? 0 : n_steps;
-  int maxit = 0;
-  bool inv = false;
-  int mixed = 0;
-  for (auto s : scenes) {
-    const EnvDev &E = w.envs_h[s->slot];
-    maxit = std::max(maxit, E.maxit);
-    inv |= E.inv_filter != 0;
-    mixed |= E.precision == IPC_MIXED;
-  }
-  std::vector<int> ph(w.env_cap, PH_ITER);
-  std::vector<int> batch;
-  for (auto s : scenes) batch.push_back(s->slot);
+//
+// LaneRounds holds the schedule's state so that environments can join between
+// rounds (the server admits requests there) and leave once their steps are
+// done or they fail.  A batch layout change between rounds only makes the
+// next assembly search its candidates afresh: an environment's active pairs,
+// their order and every sum over them are the same either way.
+struct LaneRounds {
+  struct Item {
+    ipc_scene s = nullptr;
+    int remaining = 0;
+    bool stepping = false;  // in the middle of a time step
+    bool fresh = true;      // added, not begun yet
+    ipc_step_info info{};
+  };
+  World &w;
+  std::vector<Item> items;
+  std::vector<int> ph;
   EnvSnapshots snap;
-  w.swept_n = -1;
-  bool first = true;
-  auto t0 = std::chrono::steady_clock::now();
-  auto ms = [&]() { return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count(); };
-  for (long round = 0;; ++round) {
+  std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+  double t_asm = 0, t_pcg = 0, t_state = 0, t_begin = 0, t_ls = 0;
+  long rounds = 0;
+  long long steps_converged = 0;  // over all items, since creation
+  explicit LaneRounds(World &lane) : w(lane) {}
+  double ms() const {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  void add(ipc_scene s, int n_steps, const ipc_step_info &init) {
+    Item it;
+    it.s = s;
+    it.remaining = s->failed ? 0 : n_steps;
+    it.info = init;
+    items.push_back(it);
+  }
+  bool has_work() const {
+    for (const Item &it : items)
+      if (it.stepping || (it.fresh && it.remaining > 0)) return true;
+    return false;
+  }
+  // items with no steps left (done or failed), removed from the schedule
+  std::vector<Item> take_done() {
+    std::vector<Item> done, keep;
+    for (Item &it : items) (it.stepping || (it.fresh && it.remaining > 0) ? keep : done).push_back(it);
+    items.swap(keep);
+    return done;
+  }
+
+  // One round.  Returns false when no item had work.
+  bool round() {
+    using namespace ipcw;
+    // batch: the items with work; laid out again when items joined or left
+    // it, or once at most narrow_pct% of it still has work
+    std::vector<int> live;
+    bool joined = false;
+    for (const Item &it : items)
+      if (it.stepping || (it.fresh && it.remaining > 0)) {
+        live.push_back(it.s->slot);
+        joined |= it.fresh;
+      }
+    if (live.empty()) return false;
+    {
+      std::vector<int> have = w.batch_envs;
+      std::sort(have.begin(), have.end());
+      bool covered = true;
+      for (int e : live) covered &= std::binary_search(have.begin(), have.end(), e);
+      const bool shrink = w.narrow && 100 * (int)live.size() <= w.narrow_pct * (int)w.batch_envs.size();
+      if (!covered || joined || shrink) w.set_batch(live);
+    }
+    if (ph.size() < w.env_cap) ph.assign(w.env_cap, PH_ITER);
+    int mixed = 0;
+    bool inv = false, any_stepping = false;
+    for (const Item &it : items) {
+      const EnvDev &E = w.envs_h[it.s->slot];
+      inv |= E.inv_filter != 0;
+      mixed |= E.precision == IPC_MIXED;
+      any_stepping |= it.stepping;
+    }
     // 1. one Newton iteration of the environments in the middle of a step
-    if (!first) {
+    double t = ms();
+    if (any_stepping) {
       int na = w.assemble_system(mixed);
+      double t1 = ms();
+      t_asm += t1 - t;
       long long pit = w.solve(mixed);
       ipck::conv_check(w.stream, w.W, w.envs_d, w.S, w.B, w.L, w.L.counter + 1);
+      t_pcg += ms() - t1;
       if (World::tracing())
-        std::fprintf(stderr, "[ipc] round %ld: active pairs %d friction %d pcg %lld  %.1f ms\n", round, na, w.n_fric,
-                     pit, ms());
+        std::fprintf(stderr, "[ipc] round %ld: active pairs %d friction %d pcg %lld  %.1f ms\n", rounds, na,
+                     w.n_fric, pit, ms());
     }
     // 2. states; steps that ended, steps that begin, friction re-lags
+    t = ms();
     snap.fetch(w);
+    t_state += ms() - t;
+    ++rounds;
     std::fill(ph.begin(), ph.end(), (int)PH_ITER);
     bool begin = false, relag = false, iterate = false, finish = false;
-    for (int i = 0; i < n; ++i) {
-      ipc_scene s = scenes[i];
+    for (Item &it : items) {
+      ipc_scene s = it.s;
       const int e = s->slot;
-      if (first) {
-        if (remaining[i] > 0) {
+      if (it.fresh) {
+        if (it.remaining > 0) {
           ph[e] = PH_BEGIN;
-          stepping[i] = 1;
+          it.stepping = true;
           begin = true;
           w.envs_h[e].step = s->step;
           w.upload_env(e);
         }
+        it.fresh = false;
         continue;
       }
-      if (!stepping[i]) continue;
+      if (!it.stepping) continue;
       const int st = snap.status[e];
       if (st == ST_ACTIVE) {
         iterate = true;
@@ -1896,68 +1957,58 @@ void run_steps_lane_async(World &w, std::vector<ipc_scene> &scenes, int n_steps,
         continue;
       }
       // the step is over
-      if (infos) {
-        infos[i].newton_iters += snap.iters[e];
-        infos[i].max_newton_iters = std::max(infos[i].max_newton_iters, snap.iters[e]);
-        infos[i].ls_halvings += snap.halvings[e];
-        infos[i].pcg_iters += snap.pcg_total[e];
-        infos[i].energy_last = snap.E0[e];
-        infos[i].kappa_last = snap.kappa[e];
-      }
+      ipc_step_info &inf = it.info;
+      inf.newton_iters += snap.iters[e];
+      inf.max_newton_iters = std::max(inf.max_newton_iters, snap.iters[e]);
+      inf.ls_halvings += snap.halvings[e];
+      inf.pcg_iters += snap.pcg_total[e];
+      inf.energy_last = snap.E0[e];
+      inf.kappa_last = snap.kappa[e];
       finish = true;
       if (st == ST_CONVERGED) {
         s->step += 1;
-        remaining[i] -= 1;
-        if (infos) {
-          infos[i].steps_done += 1;
-          infos[i].n_active_last = snap.nact[e];
-          infos[i].min_dist_last = std::sqrt(snap.dmin2[e]);
-        }
-        if (remaining[i] > 0) {
+        it.remaining -= 1;
+        inf.steps_done += 1;
+        ++steps_converged;
+        inf.n_active_last = snap.nact[e];
+        inf.min_dist_last = std::sqrt(snap.dmin2[e]);
+        if (it.remaining > 0) {
           ph[e] = PH_FINISH_BEGIN;
           begin = true;
           w.envs_h[e].step = s->step;
           w.upload_env(e);
         } else {
           ph[e] = PH_FINISH;
-          stepping[i] = 0;
+          it.stepping = false;
         }
       } else {
         s->failed = true;
         s->fail_reason = (st == ST_FAILED) ? snap.reason[e] : IPC_FAIL_MAXIT;
-        if (infos) {
-          infos[i].status = IPC_E_FAILED;
-          infos[i].fail_reason = s->fail_reason;
-        }
+        inf.status = IPC_E_FAILED;
+        inf.fail_reason = s->fail_reason;
         ph[e] = PH_FINISH;
-        stepping[i] = 0;
+        it.stepping = false;
+        it.remaining = 0;
       }
     }
-    first = false;
-    if (!begin && !relag && !iterate && !finish) break;
+    if (!begin && !relag && !iterate && !finish) return false;
     // 3. the round's device work
     w.upload_phases(ph);
     if (finish) {
       ipck::step_end(w.stream, w.W, w.envs_d, w.S, w.B, 1);
       ipck::phase_advance(w.stream, w.S, w.B);
     }
-    // once at most narrow_pct% of the lane's environments still have work,
-    // lay the batch out again with those alone (before the round's candidate
-    // list, which the next assembly reuses, as the lock-step schedule does)
-    if (w.narrow) {
-      std::vector<int> live;
-      for (int i = 0; i < n; ++i)
-        if (stepping[i]) live.push_back(scenes[i]->slot);
-      if (!live.empty() && live.size() < w.batch_envs.size() &&
-          100 * (int)live.size() <= w.narrow_pct * (int)batch.size())
-        w.set_batch(live);
-    }
     if (begin) {
       ipck::env_begin(w.stream, w.envs_d, w.S, w.B);
       ipck::begin_step(w.stream, w.W, w.envs_d, w.S, w.B);
     }
     if (relag) ipck::relag(w.stream, w.envs_d, w.S, w.B, 1, w.L.counter + 5);
-    if (!begin && !relag && !iterate) break;  // only step ends this round
+    if (!begin && !relag && !iterate) {  // only step ends this round
+      w.swept_n = -1;
+      HC(hipStreamSynchronize(w.stream));
+      return true;
+    }
+    t = ms();
     if (iterate) ipck::al_prepare(w.stream, w.W, w.S, w.B);
     // one swept pass: the Newton directions of the iterating environments and
     // the Dirichlet moves of the beginning ones (their free vertices stay)
@@ -1970,6 +2021,8 @@ void run_steps_lane_async(World &w, std::vector<ipc_scene> &scenes, int n_steps,
       ipck::env_dbc(w.stream, w.S, w.B);
       ipck::apply_dbc(w.stream, w.W, w.envs_d, w.S, w.B);
     }
+    t_begin += ms() - t;
+    t = ms();
     if (iterate) {
       if (inv) ipck::inv_bound(w.stream, w.W, w.envs_d, w.S, w.B, 0);
       ipck::snap_J(w.stream, w.W, w.S, w.B);
@@ -1985,7 +2038,35 @@ void run_steps_lane_async(World &w, std::vector<ipc_scene> &scenes, int n_steps,
     }
     ipck::iter_end(w.stream, w.envs_d, w.S, w.B, w.L.counter + 3);
     w.swept_n = ns;
+    t_ls += ms() - t;
+    return true;
   }
+
+  void trace_summary() const {
+    if (World::tracing())
+      std::fprintf(stderr,
+                   "[ipc] lane %p: %zu envs, %ld rounds, %.1f ms: assembly %.1f, pcg %.1f, states %.1f, "
+                   "begin+broad phase+ccd %.1f, line search %.1f\n",
+                   (void *)&w, items.size(), rounds, ms(), t_asm, t_pcg, t_state, t_begin, t_ls);
+  }
+};
+
+void run_steps_lane_async(World &w, std::vector<ipc_scene> &scenes, int n_steps, ipc_step_info *infos) {
+  LaneRounds R(w);
+  std::vector<int> batch;
+  for (size_t i = 0; i < scenes.size(); ++i) {
+    R.add(scenes[i], n_steps, infos ? infos[i] : ipc_step_info{});
+    batch.push_back(scenes[i]->slot);
+  }
+  std::vector<LaneRounds::Item> all = R.items;  // item order = scene order
+  w.swept_n = -1;
+  while (R.round()) {
+  }
+  R.trace_summary();
+  if (infos)
+    for (size_t i = 0; i < scenes.size(); ++i)
+      for (const LaneRounds::Item &it : R.items)
+        if (it.s == scenes[i]) infos[i] = it.info;
   w.swept_n = -1;
   w.set_batch(batch);
   HC(hipStreamSynchronize(w.stream));
@@ -2109,9 +2190,10 @@ void run_steps(const std::vector<ipc_scene> &scenes, int n_steps, ipc_step_info 
 }
 
 // ---------------------------------------------------------------------------
-// serving: a worker thread admits queued requests by slot count and memory,
-// steps all running ones together one time step per tick, retires finished
-// ones between ticks
+// serving: a worker thread per lane admits queued requests by slot count and
+// memory, advances all running ones together one tick at a time (a round of
+// the decoupled schedule, or a time step under the lock-step one), retires
+// finished ones between ticks
 // ---------------------------------------------------------------------------
 struct Request {
   int64_t id = 0;
@@ -2146,7 +2228,8 @@ struct ipc_server_s {
   long long finished = 0, failed = 0, conv_steps = 0, ticks = 0;
   // slot-cap autotuner (max_slots = 0 at creation): starting from 8 slots per
   // lane, while requests wait, double the cap after every window of 8 ticks
-  // per lane, unless the window's seconds per converged step exceed 1.5x the
+  // per lane (64 rounds per lane under the decoupled schedule, where a round
+  // is one Newton iteration), unless the window's seconds per converged step exceed 1.5x the
   // best window's: then settle on the best window's cap.  A tick costs about
   // its slowest environment's step, so more slots raise throughput until the
   // device saturates.
@@ -2185,7 +2268,8 @@ void autotune_tick(ipc_server_s *sv, long long tick_steps) {
   // caller holds sv->mu
   if (!sv->auto_slots || sv->settled) return;
   sv->win_steps += tick_steps;
-  if (++sv->win_ticks < 8 * (long long)sv->lanes.size()) return;
+  const long long window = sv->lanes[0]->async_mode ? 64 : 8;
+  if (++sv->win_ticks < window * (long long)sv->lanes.size()) return;
   double t = sv->now();
   double cost = (t - sv->win_t0) / std::max<long long>(sv->win_steps, 1);
   if (!sv->queue.empty()) {  // demand above the cap: the cap is what limits
@@ -2206,13 +2290,14 @@ void autotune_tick(ipc_server_s *sv, long long tick_steps) {
   sv->win_t0 = t;
 }
 
-// the worker of lane k: admit into this lane, step its running requests one
-// time step per tick, retire the finished ones
+// the worker of lane k: admit into this lane, advance its running requests
+// one tick, retire the finished ones
 void server_loop(ipc_server_s *sv, size_t k) {
   World *w = sv->lanes[k];
   std::vector<Request *> &mine = sv->running[k];
   std::vector<Request *> &admitting = sv->admitting[k];
   std::vector<ipc_step_info> infos;
+  LaneRounds R(*w);  // the lane's decoupled schedule (w->async_mode)
   try {
     HC(hipSetDevice(w->device));
     while (true) {
@@ -2289,40 +2374,85 @@ void server_loop(ipc_server_s *sv, size_t k) {
         run = mine;
       }
       if (run.empty()) continue;
-      std::vector<ipc_scene> scenes;
-      for (Request *r : run) scenes.push_back(r->scene);
-      infos.assign(run.size(), ipc_step_info{});
-      run_steps_lane(scenes, 1, infos.data());
-      {
-        // another lane's device error retires every request: leave them alone
-        std::lock_guard<std::mutex> lk(sv->mu);
-        if (sv->dead) return;
-      }
       std::vector<Request *> done;
-      for (size_t i = 0; i < run.size(); ++i) {
-        Request *r = run[i];
-        ipc_scene sc = scenes[i];
-        bool fin = sc->failed || r->steps_done + infos[i].steps_done >= r->n_steps;
-        if (fin) {
+      long long tick_steps = 0;
+      if (w->async_mode) {
+        // one round of the decoupled schedule: the admitted requests begin
+        // their first step in it, the others take a Newton iteration or move
+        // on to their next step
+        for (Request *r : run)
+          if (std::none_of(R.items.begin(), R.items.end(),
+                           [&](const LaneRounds::Item &it) { return it.s == r->scene; })) {
+            ipc_step_info init{};
+            init.status = r->scene->failed ? IPC_E_FAILED : IPC_OK;
+            R.add(r->scene, r->n_steps - r->steps_done, init);
+          }
+        const long long before = R.steps_converged;
+        {
+          std::lock_guard<std::mutex> wl(w->mu);
+          R.round();
+        }
+        tick_steps = R.steps_converged - before;
+        std::vector<LaneRounds::Item> fin = R.take_done();
+        for (const LaneRounds::Item &it : fin) {
+          Request *r = *std::find_if(run.begin(), run.end(), [&](Request *q) { return q->scene == it.s; });
           r->pos.resize(3 * (size_t)r->nv);
           r->vel.resize(3 * (size_t)r->nv);
-          std::lock_guard<std::mutex> lk(w->mu);
-          get_x(*w, sc, w->W.x, r->pos.data());
-          get_x(*w, sc, w->W.v, r->vel.data());
-          w->remove_scene(sc->slot);
+          std::lock_guard<std::mutex> wl(w->mu);
+          get_x(*w, it.s, w->W.x, r->pos.data());
+          get_x(*w, it.s, w->W.v, r->vel.data());
+          w->remove_scene(it.s->slot);
           done.push_back(r);
+        }
+        std::lock_guard<std::mutex> lk(sv->mu);
+        if (sv->dead) return;
+        // progress of the lane's requests (counts since admission)
+        auto progress = [&](const LaneRounds::Item &it) {
+          auto at = std::find_if(run.begin(), run.end(), [&](Request *q) { return q->scene == it.s; });
+          if (at == run.end()) return;
+          Request *r = *at;
+          r->steps_done = it.info.steps_done;
+          r->newton = it.info.newton_iters;
+          r->pcg = it.info.pcg_iters;
+        };
+        for (const LaneRounds::Item &it : R.items) progress(it);
+        for (const LaneRounds::Item &it : fin) progress(it);
+      } else {
+        std::vector<ipc_scene> scenes;
+        for (Request *r : run) scenes.push_back(r->scene);
+        infos.assign(run.size(), ipc_step_info{});
+        run_steps_lane(scenes, 1, infos.data());
+        {
+          // another lane's device error retires every request: leave them alone
+          std::lock_guard<std::mutex> lk(sv->mu);
+          if (sv->dead) return;
+        }
+        for (size_t i = 0; i < run.size(); ++i) {
+          Request *r = run[i];
+          ipc_scene sc = scenes[i];
+          bool fin = sc->failed || r->steps_done + infos[i].steps_done >= r->n_steps;
+          if (fin) {
+            r->pos.resize(3 * (size_t)r->nv);
+            r->vel.resize(3 * (size_t)r->nv);
+            std::lock_guard<std::mutex> lk(w->mu);
+            get_x(*w, sc, w->W.x, r->pos.data());
+            get_x(*w, sc, w->W.v, r->vel.data());
+            w->remove_scene(sc->slot);
+            done.push_back(r);
+          }
+        }
+        std::lock_guard<std::mutex> lk(sv->mu);
+        if (sv->dead) return;
+        for (size_t i = 0; i < run.size(); ++i) {
+          Request *r = run[i];
+          r->steps_done += infos[i].steps_done;
+          r->newton += infos[i].newton_iters;
+          r->pcg += infos[i].pcg_iters;
+          tick_steps += infos[i].steps_done;
         }
       }
       std::lock_guard<std::mutex> lk(sv->mu);
       if (sv->dead) return;
-      long long tick_steps = 0;
-      for (size_t i = 0; i < run.size(); ++i) {
-        Request *r = run[i];
-        r->steps_done += infos[i].steps_done;
-        r->newton += infos[i].newton_iters;
-        r->pcg += infos[i].pcg_iters;
-        tick_steps += infos[i].steps_done;
-      }
       sv->conv_steps += tick_steps;
       autotune_tick(sv, tick_steps);
       for (Request *r : done) {
