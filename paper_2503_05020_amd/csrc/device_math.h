@@ -187,51 +187,66 @@ DEV void type_geometry(int kind, int type, const double *x, TypeGeo &T) {
     }
     return;
   }
-  // sub-types: point-edge (point, a, b) or point-point (point, other)
+  // sub-types: point-edge (point, a, b) or point-point (point, other); the
+  // slots are picked with selects, not by indexing, so that the arrays stay
+  // in registers
   int sp, sa, sb = -1;
   if (kind == 0) {
+    sp = 0;
     if (type <= 3) {
-      sp = 0;
       sa = type;
       sb = (type == 3) ? 1 : type + 1;
     } else {
-      sp = 0;
       sa = type - 3;
     }
-  } else {
-    const int pe[4][3] = {{0, 2, 3}, {1, 2, 3}, {2, 0, 1}, {3, 0, 1}};
-    const int pp[4][2] = {{0, 2}, {0, 3}, {1, 2}, {1, 3}};
-    if (type <= 4) {
-      sp = pe[type - 1][0];
-      sa = pe[type - 1][1];
-      sb = pe[type - 1][2];
-    } else {
-      sp = pp[type - 5][0];
-      sa = pp[type - 5][1];
-    }
+  } else if (type <= 4) {  // point-edge: (0; 2, 3), (1; 2, 3), (2; 0, 1), (3; 0, 1)
+    sp = type - 1;
+    sa = (type <= 2) ? 2 : 0;
+    sb = sa + 1;
+  } else {  // point-point: (0, 2), (0, 3), (1, 2), (1, 3)
+    sp = (type <= 6) ? 0 : 1;
+    sa = (type == 5 || type == 7) ? 2 : 3;
   }
   if (sb < 0) {  // r = p - q
     T.nb = 0;
     T.n_involved = 2;
     T.involved[0] = sp;
     T.involved[1] = sa;
-    T.c[sp] = 1.0;
-    T.c[sa] = -1.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) T.c[i] = (i == sp) ? 1.0 : (i == sa) ? -1.0 : 0.0;
     return;
   }
-  // r = p - a - s (b - a)
-  d3 e = sub3(P[sb], P[sa]), w = sub3(P[sp], P[sa]);
+  // r = p - a - s (b - a).  e = b - a and w = p - a are formed as sums with
+  // coefficients in {-1, 0, 1} (exact products, zeros added exactly: the
+  // same bits as the differences) rather than by picking points with a
+  // run-time index, which would put the points in scratch memory.
+  double ce[4], cw[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    ce[i] = (i == sb) ? 1.0 : (i == sa) ? -1.0 : 0.0;
+    cw[i] = (i == sp) ? 1.0 : (i == sa) ? -1.0 : 0.0;
+  }
+  d3 e = {0.0, 0.0, 0.0}, w = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    e.x += ce[i] * P[i].x;
+    e.y += ce[i] * P[i].y;
+    e.z += ce[i] * P[i].z;
+    w.x += cw[i] * P[i].x;
+    w.y += cw[i] * P[i].y;
+    w.z += cw[i] * P[i].z;
+  }
   double s = dot3(w, e) / dot3(e, e);
   T.nb = 1;
   T.n_involved = 3;
   T.involved[0] = sp;
   T.involved[1] = sa;
   T.involved[2] = sb;
-  T.c[sp] = 1.0;
-  T.c[sa] = -(1.0 - s);
-  T.c[sb] = -s;
-  T.dc[0][sa] = 1.0;
-  T.dc[0][sb] = -1.0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    T.c[i] = (i == sp) ? 1.0 : (i == sa) ? -(1.0 - s) : (i == sb) ? -s : 0.0;
+    T.dc[0][i] = (i == sa) ? 1.0 : (i == sb) ? -1.0 : 0.0;
+  }
 }
 
 // z = d^2, gz[12], Hz[144] (row-major, zero outside the involved slots).
@@ -529,6 +544,217 @@ DEV double pair_barrier_full(int kind, int type, const double *x, double dhat, d
     }
   }
   return kappa * e * b0;
+}
+
+// -- PSD projection of a fixed-size symmetric matrix ----------------------------
+// The cyclic Jacobi of psd_project with the size known at compile time, so
+// that A and V stay in registers (no per-lane scratch memory).
+template <int N>
+DEV void psd_project_n(double A[N * N], double V[N * N]) {
+  double fro = 0.0;
+#pragma unroll
+  for (int i = 0; i < N * N; ++i) fro += A[i] * A[i];
+  if (fro == 0.0) return;
+  fro = sqrt(fro);
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) V[i * N + j] = (i == j) ? 1.0 : 0.0;
+  for (int sweep = 0; sweep < 50; ++sweep) {
+    double off = 0.0;
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int j = i + 1; j < N; ++j) off += 2.0 * A[i * N + j] * A[i * N + j];
+    if (sqrt(off) <= 1e-15 * fro) break;
+#pragma unroll
+    for (int p = 0; p < N - 1; ++p)
+#pragma unroll
+      for (int q = p + 1; q < N; ++q) {
+        const double apq = A[p * N + q];
+        if (apq == 0.0) continue;
+        const double theta = (A[q * N + q] - A[p * N + p]) / (2.0 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+        const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+          const double akp = A[k * N + p], akq = A[k * N + q];
+          A[k * N + p] = c * akp - s * akq;
+          A[k * N + q] = s * akp + c * akq;
+        }
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+          const double apk = A[p * N + k], aqk = A[q * N + k];
+          A[p * N + k] = c * apk - s * aqk;
+          A[q * N + k] = s * apk + c * aqk;
+        }
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+          const double vkp = V[k * N + p], vkq = V[k * N + q];
+          V[k * N + p] = c * vkp - s * vkq;
+          V[k * N + q] = s * vkp + c * vkq;
+        }
+      }
+  }
+  double lam[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) lam[k] = fmax(A[k * N + k], 0.0);
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = i; j < N; ++j) {
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < N; ++k) acc += V[i * N + k] * lam[k] * V[j * N + k];
+      A[i * N + j] = acc;
+      A[j * N + i] = acc;
+    }
+}
+
+// -- pair barrier element without the 12x12 matrix ---------------------------------
+// The unmollified element (e = 1): H = kappa (B2 gz gz^T + B1 Hz) lies in the
+// span of the orthonormal Q_m = c (x) e_m / |c| (m < 3) and
+// Q_{3+j} = om_j (x) r / |r| (subspace_project), so its projection is
+// Q Proj(M) Q^T with M = Q^T H Q, formed here from coordinates in that basis
+// instead of from H:
+//   c (x) v -> |c| v in coordinates 0..2;  w (x) r -> |r| (w . om_j) in
+//   coordinate 3 + j, for w orthogonal to c;
+//   gz = 2 c (x) r;  u_k = c (x) (q_k + (c . dc_k) / |c|^2 r) + w_k (x) r with
+//   w_k = dc_k - c (c . dc_k) / |c|^2;
+//   Hz = 2 sum_m (c (x) e_m)(c (x) e_m)^T - 2 sum_kl Ginv_kl u_k u_l^T.
+// M is padded to 5 x 5 with zero rows and columns, which the Jacobi rotations
+// leave alone.  The projected blocks are then
+//   H[3a + r][3b + s] = sum_ij phi_a(r, i) P_ij phi_b(s, j),
+//   phi_a(r, m) = c_a [r = m] / |c|,  phi_a(r, 3 + j) = om_j[a] r_r / |r|.
+// Writes the gradient g[12] and the ten 3x3 blocks (a <= b, blk_index order)
+// of the projected Hessian to blocks[90] and returns the energy; returns -1
+// with nothing written for an edge-edge pair in its mollified range
+// (|ea x eb|^2 < eps_x) or a degenerate pair (|c| or |r| zero), which
+// pair_barrier_full handles.
+DEV double pair_barrier_fast(int kind, int type, const double *x, double dhat, double kappa, double eps_x,
+                             double *g, double *blocks) {
+  if (kind == 1) {
+    d3 n = cross3(sub3(ld3(x + 3), ld3(x)), sub3(ld3(x + 9), ld3(x + 6)));
+    if (dot3(n, n) < eps_x) return -1.0;
+  }
+  TypeGeo T;
+  type_geometry(kind, type, x, T);
+  double r[3] = {0, 0, 0}, q[2][3] = {{0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      r[k] += T.c[i] * x[3 * i + k];
+      q[0][k] += T.dc[0][i] * x[3 * i + k];
+      q[1][k] += T.dc[1][i] * x[3 * i + k];
+    }
+  const double z = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+  const double cn2 = T.c[0] * T.c[0] + T.c[1] * T.c[1] + T.c[2] * T.c[2] + T.c[3] * T.c[3];
+  if (!(cn2 > 0.0) || !(z > 0.0)) return -1.0;
+  const double d = sqrt(z), cn = sqrt(cn2);
+  double b0, b1, b2;
+  barrier_b(d, dhat, &b0, &b1, &b2);
+  const double B1 = b1 / (2.0 * d), B2 = (b2 - b1 / d) / (4.0 * z);
+  double Gi[2][2] = {{0, 0}, {0, 0}};
+  if (T.nb == 1) {
+    Gi[0][0] = 1.0 / (q[0][0] * q[0][0] + q[0][1] * q[0][1] + q[0][2] * q[0][2]);
+  } else if (T.nb == 2) {
+    const double g00 = q[0][0] * q[0][0] + q[0][1] * q[0][1] + q[0][2] * q[0][2];
+    const double g01 = q[0][0] * q[1][0] + q[0][1] * q[1][1] + q[0][2] * q[1][2];
+    const double g11 = q[1][0] * q[1][0] + q[1][1] * q[1][1] + q[1][2] * q[1][2];
+    const double id = 1.0 / (g00 * g11 - g01 * g01);
+    Gi[0][0] = g11 * id;
+    Gi[1][1] = g00 * id;
+    Gi[0][1] = Gi[1][0] = -g01 * id;
+  }
+  // w_k and their orthonormalisation om_j (Gram-Schmidt, as subspace_project)
+  double w[2][4], om[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}}, cd[2] = {0, 0};
+  int nw = 0;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    double dn = 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      cd[k] += T.c[i] * T.dc[k][i];
+      dn += T.dc[k][i] * T.dc[k][i];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) w[k][i] = T.dc[k][i] - T.c[i] * cd[k] / cn2;
+    if (k >= T.nb) continue;
+    double o[4] = {w[k][0], w[k][1], w[k][2], w[k][3]};
+    if (nw == 1) {
+      const double pr = o[0] * om[0][0] + o[1] * om[0][1] + o[2] * om[0][2] + o[3] * om[0][3];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) o[i] -= pr * om[0][i];
+    }
+    const double on = sqrt(o[0] * o[0] + o[1] * o[1] + o[2] * o[2] + o[3] * o[3]);
+    if (!(on > 1e-12 * sqrt(dn))) continue;
+    if (nw == 0) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) om[0][i] = o[i] / on;
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) om[1][i] = o[i] / on;
+    }
+    ++nw;
+  }
+  // coordinates of gz and u_k
+  double G5[5] = {2.0 * cn * r[0], 2.0 * cn * r[1], 2.0 * cn * r[2], 0.0, 0.0};
+  double U[2][5];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+#pragma unroll
+    for (int m = 0; m < 3; ++m) U[k][m] = cn * (q[k][m] + cd[k] / cn2 * r[m]);
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      U[k][3 + j] = d * (w[k][0] * om[j][0] + w[k][1] * om[j][1] + w[k][2] * om[j][2] + w[k][3] * om[j][3]);
+  }
+  double M[25], V[25];
+#pragma unroll
+  for (int i = 0; i < 5; ++i)
+#pragma unroll
+    for (int j = i; j < 5; ++j) {
+      double h = B2 * G5[i] * G5[j] + ((i == j && i < 3) ? B1 * 2.0 * cn2 : 0.0);
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int l = 0; l < 2; ++l) h -= B1 * 2.0 * Gi[k][l] * U[k][i] * U[l][j];
+      M[i * 5 + j] = M[j * 5 + i] = kappa * h;
+    }
+  psd_project_n<5>(M, V);
+  // blocks: for each b, T_b = P phi_b^T (5 x 3), then block (a, b) = phi_a T_b
+  double ca[4], oa[2][4], rh[3];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    ca[a] = T.c[a] / cn;
+    oa[0][a] = om[0][a];
+    oa[1][a] = om[1][a];
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) rh[k] = r[k] / d;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    double Tb[5][3];
+#pragma unroll
+    for (int i = 0; i < 5; ++i)
+#pragma unroll
+      for (int s2 = 0; s2 < 3; ++s2)
+        Tb[i][s2] = M[i * 5 + s2] * ca[b] + (M[i * 5 + 3] * oa[0][b] + M[i * 5 + 4] * oa[1][b]) * rh[s2];
+#pragma unroll
+    for (int a = 0; a <= b; ++a) {
+      double *B = blocks + 9 * (a * 4 - (a * (a - 1)) / 2 + (b - a));  // blk_index(a, b)
+#pragma unroll
+      for (int r2 = 0; r2 < 3; ++r2)
+#pragma unroll
+        for (int s2 = 0; s2 < 3; ++s2)
+          B[3 * r2 + s2] = ca[a] * Tb[r2][s2] + (oa[0][a] * Tb[3][s2] + oa[1][a] * Tb[4][s2]) * rh[r2];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) g[3 * i + k] = kappa * (B1 * (2.0 * T.c[i] * r[k]));
+  return kappa * b0;
 }
 
 // Energy only, from the classified squared distance.

@@ -625,6 +625,7 @@ struct World {
   DBuf<int4> fv2;
   DBuf<double> fw2, fn2, flam2;
   DBuf<int> fenv2, fplan_b, fplan_e;
+  DBuf<int> bar_slow;  // barrier pairs for the full element kernel
   int *phase_h = nullptr;  // pinned, env_cap entries
   size_t phase_cap = 0;
   int *pinned = nullptr;  // host mirror of counters
@@ -1118,6 +1119,7 @@ struct World {
     L.part_c0 = part_c0.p;
     L.part_c1 = part_c1.p;
     L.counter = counter.p;
+    L.bar_slow = bar_slow.p;
     L.prof = prof_on ? prof_bytes.p : nullptr;
     L.g_ncell = g_ncell.p;
     L.g_big = g_big.p;
@@ -1358,6 +1360,7 @@ struct World {
     swept_n = -1;
     int na = active_pairs(nc, W.x, 1);
     ensure_ce(na + n_fric);
+    if (bar_slow.ensure(na + 1)) L.bar_slow = bar_slow.p;
     ipck::barrier_elems(stream, W, envs_d, S, L, na, W.x);
     ipck::friction_elems(stream, W, envs_d, S, L, n_fric, na, W.x);
     int nce = na + n_fric;

@@ -58,7 +58,8 @@ struct Lists {
   float *cr_val32;
   // reduction partials per vertex tile (PCG: a = u.Hu, b0/b1 = r.u, c0/c1 = r.r)
   double *part_a, *part_b0, *part_b1, *part_c0, *part_c1;
-  int *counter;  // device scratch counters [4]
+  int *counter;  // device scratch counters [16]
+  int *bar_slow;  // barrier pairs that take the full 12x12 element (k_barrier_elems_full)
   // hash grid
   int *g_ncell, *g_big, *g_eoff, *g_bigoff, *g_ebucket, *g_bcnt, *g_boff, *g_bcur, *g_bigl;
   GridEnt *g_ent, *g_sorted;

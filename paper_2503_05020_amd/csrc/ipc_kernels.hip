@@ -826,21 +826,52 @@ DEV void store_blocks(const double *H, double *out) {
     }
 }
 
+// Barrier contact elements.  The unmollified, non-degenerate pairs (nearly
+// all) are formed without the 12x12 matrix (pair_barrier_fast: no per-lane
+// scratch memory); the others are listed in slow (count in *n_slow) for
+// k_barrier_elems_full.  Each pair writes only its own slot, so the split
+// changes no result.
 __global__ void __launch_bounds__(128) k_barrier_elems(WorldDev W, const EnvDev *envs, const double *kap,
                                                        const int2 *act, const int *act_type, int n, const double *x,
-                                                       int4 *ce_v, double *ce_g, double *ce_H) {
+                                                       int4 *ce_v, double *ce_g, double *ce_H, int *n_slow,
+                                                       int *slow) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   int kind, v[4], env;
   double ex;
   pair_info(W, act[k], kind, v, env, ex);
   const EnvDev &E = envs[env];
-  double xx[12], g[12], H[144], scr[168];
+  double xx[12], g[12];
   gather12(x, v, xx);
-  pair_barrier_full(kind, act_type[k], xx, E.dhat, kap[env], ex, true, g, H, scr);
+  if (pair_barrier_fast(kind, act_type[k], xx, E.dhat, kap[env], ex, g, ce_H + 90 * (size_t)k) < 0.0) {
+    slow[atomicAdd(n_slow, 1)] = k;
+    return;
+  }
   ce_v[k] = make_int4(v[0], v[1], v[2], v[3]);
   for (int i = 0; i < 12; ++i) ce_g[12 * k + i] = g[i];
-  store_blocks(H, ce_H + 90 * (size_t)k);
+}
+
+// the listed pairs: mollified edge-edge pairs and degenerate ones, through
+// the full 12x12 element and its Jacobi projection (grid-stride over the
+// list, whose length only the device knows)
+__global__ void __launch_bounds__(128) k_barrier_elems_full(WorldDev W, const EnvDev *envs, const double *kap,
+                                                            const int2 *act, const int *act_type, const double *x,
+                                                            int4 *ce_v, double *ce_g, double *ce_H,
+                                                            const int *n_slow, const int *slow) {
+  const int m = *n_slow;
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < m; j += gridDim.x * blockDim.x) {
+    const int k = slow[j];
+    int kind, v[4], env;
+    double ex;
+    pair_info(W, act[k], kind, v, env, ex);
+    const EnvDev &E = envs[env];
+    double xx[12], g[12], H[144], scr[168];
+    gather12(x, v, xx);
+    pair_barrier_full(kind, act_type[k], xx, E.dhat, kap[env], ex, true, g, H, scr);
+    ce_v[k] = make_int4(v[0], v[1], v[2], v[3]);
+    for (int i = 0; i < 12; ++i) ce_g[12 * k + i] = g[i];
+    store_blocks(H, ce_H + 90 * (size_t)k);
+  }
 }
 
 // lagged friction data at x^n (positions in W.x at set-up time)
@@ -2551,9 +2582,14 @@ void act_stats(hipStream_t s, const EnvDev *E, const EnvState &S, const Batch &B
 }
 void barrier_elems(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Lists &L, int n_act,
                    const double *x) {
-  if (n_act)
-    IPC_LAUNCH(k_barrier_elems, nblk(n_act, 128), 128, s)(W, E, S.kappa, L.act, L.act_type, n_act, x, L.ce_v, L.ce_g,
-                                                          L.ce_H);
+  if (!n_act) return;
+  int *n_slow = L.counter + 8;
+  IPC_LAUNCH(k_fill_int, 1, 64, s)(n_slow, 1, 0);
+  IPC_LAUNCH(k_barrier_elems, nblk(n_act, 128), 128, s)(W, E, S.kappa, L.act, L.act_type, n_act, x, L.ce_v, L.ce_g,
+                                                        L.ce_H, n_slow, L.bar_slow);
+  // few pairs take the full path: a small grid strides over them
+  IPC_LAUNCH(k_barrier_elems_full, std::min(nblk(n_act, 128), 64), 128, s)(W, E, S.kappa, L.act, L.act_type, x,
+                                                                          L.ce_v, L.ce_g, L.ce_H, n_slow, L.bar_slow);
 }
 void friction_setup(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Lists &L, int n_act) {
   if (n_act)

@@ -483,7 +483,7 @@ def _rot_x(theta: float) -> np.ndarray:
 
 
 def rigid_hand_grasp(seed: int = 0, h: float = 2.08e-3, axes=(0.06, 0.04, 0.03), close_steps: int = 80,
-                     lift_steps: int = 40, lift_speed: float = 0.05, **params):
+                     lift_steps: int = 40, lift_speed: float = 0.05, closed_pose=(12.0, 8.0, 6.0, 4.0), **params):
     """A kinematic four-finger hand of 16 capsule links grasps a soft ellipsoid on the ground.
 
     Ellipsoid half-axes 6 x 4 x 3 cm (201k tets at h = 2.08 mm), E = 1e5,
@@ -491,8 +491,8 @@ def rigid_hand_grasp(seed: int = 0, h: float = 2.08e-3, axes=(0.06, 0.04, 0.03),
     x = +-2.2 cm, hanging from 4.5 cm above the centre; links 45/35/25/20 mm
     long, radius 8 mm.  Joint angles (rotation about x, inward positive) go
     linearly from a seeded open pose (joint 0 at -15 deg, others 0, each
-    +-10 deg) to the closed pose (12, 8, 6, 4 deg: the links press about 3 mm
-    into the ellipsoid's rest shape) over `close_steps`
+    +-10 deg) to the closed pose (default 12, 8, 6, 4 deg: the links press
+    about 3 mm into the ellipsoid's rest shape) over `close_steps`
     steps, then the hand rises at `lift_speed` for `lift_steps` steps.
     dt = 5 ms, dhat = 0.5 mm, mu = 0.6.  Every link is its own kinematic group
     (0..15), the ground is group 16.  Links press into the object, so the
@@ -510,7 +510,7 @@ def rigid_hand_grasp(seed: int = 0, h: float = 2.08e-3, axes=(0.06, 0.04, 0.03),
     b.add_body(ev, et, 1e5, 0.4, 1000.0)
     lengths, radius = (0.045, 0.035, 0.025, 0.020), 0.008
     open_pose = np.array([-15.0, 0.0, 0.0, 0.0])
-    closed_pose = np.array([12.0, 8.0, 6.0, 4.0])
+    closed_pose = np.array(closed_pose, dtype=float)
     n_rows = close_steps + lift_steps + 1
     motion = np.tile(IDENTITY12, (n_rows, 17, 1))
     group = 0
