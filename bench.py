@@ -64,10 +64,10 @@ def make_scenes(workload: str, n_envs: int):
     return [make_scene(workload, i) for i in range(n_envs)]
 
 
-def run_gpu(scs, precision, warmup, steps, pcg_tol, label, count_all=False):
+def run_gpu(scs, precision, warmup, steps, pcg_tol, label, count_all=False, **overrides):
     import torch
     t0 = time.time()
-    gs = [G.ipc_create_scene(sc, precision=precision, pcg_rel_tol=pcg_tol) for sc in scs]
+    gs = [G.ipc_create_scene(sc, precision=precision, pcg_rel_tol=pcg_tol, **overrides) for sc in scs]
     log(f"[{label}] created {len(gs)} scenes in {time.time() - t0:.1f}s")
     for k in range(warmup):
         rc, infos = G.ipc_step_batch(gs, 1)
@@ -344,6 +344,8 @@ def main():
     ap.add_argument("--full-horizon", type=int, default=100,
                     help="also time this many steps from step 0 (the whole grasp) per precision; 0 skips")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--relative-stop", type=float, default=1e-3,
+                    help="also time the mixed window with the paper's relative Newton stop (eps_r; 0 skips)")
     ap.add_argument("--serve-requests", type=int, default=48, help="0 skips the serving run")
     ap.add_argument("--serve-slots", type=int, default=0, help="0 = slot cap tuned by the server")
     ap.add_argument("--serve-rate", type=float, default=50.0, help="request arrivals per second")
@@ -406,6 +408,14 @@ def main():
     if args.serve_requests > 0:
         serve = serving(args.serve_requests, args.serve_rate, 200 << 30, args.serve_slots, G.IPC_MIXED)
         log(f"[serving] {serve}")
+    rel = None
+    if args.relative_stop > 0 and "mixed" in results:
+        # the same window under the relative reading of the Newton stop (eps_r L h)
+        h = run_gpu(scs, G.IPC_MIXED, args.warmup, args.steps, args.pcg_tol, "mixed relative stop",
+                    newton_rel_tol=args.relative_stop)
+        rel = {"eps_r": args.relative_stop, "value": round(h["value"], 2), "ms_per_step": round(h["ms_per_step"], 2),
+               "failed_envs": h["failed"], "newton_iters": h["newton"], "pcg_iters": h["pcg"]}
+        log(f"[mixed relative stop] {h['value']:.1f} converged env-steps/s, {h['failed']} failed")
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.workload, len(scs), args.warmup, args.steps)
     horizon = None
     if args.full_horizon > 0:
@@ -445,6 +455,8 @@ def main():
                        "failed_envs": f["failed"], "roofline": roofline(f["prof"], "fp64")}
     if horizon:
         out["full_horizon"] = horizon
+    if rel:
+        out["relative_newton_stop"] = rel
     if seq:
         out["sequential_single_env"] = {"value": round(seq["value"], 3), "envs": seq["envs"],
                                         "speedup_batched_vs_sequential": round(r["value"] / seq["value"], 2)}

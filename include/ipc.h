@@ -156,15 +156,17 @@ int ipc_scene_sizes(ipc_scene s, int64_t out[7]);
 
 /* Measurement on the current device (sums over its lanes).  When enabled,
  * every 16th PCG iteration of each solve (iterations 5, 21, 37, ...) has its
- * matrix-vector product and its update each bracketed by HIP events on the
- * library's stream, and a separate launch between the two kernels (outside
- * both timings) adds the iteration's algorithmic bytes to device counters:
+ * matrix-vector product and its update each timed from kernel start to
+ * kernel end by HIP events carried in their dispatches (hipExtLaunchKernel),
+ * and a separate launch between the two kernels (outside both timings) adds
+ * the iteration's algorithmic bytes to device counters:
  * for the product the stored 3x3 blocks and column indices (sliced ELL and
  * merged contact blocks) plus one read of u and one write of w per row; for
  * the whole iteration the same blocks plus per row the preconditioner block
  * and eight vector accesses of three values (N (9 s + 4) + n 9 s + 24 n s).
  * Every assembly pass (elasticity, inertia, gradient and stored blocks) is
- * bracketed too, its algorithmic bytes (per tet 208 B of inputs, per row
+ * timed too, from the start of its first kernel to the end of its last, its
+ * algorithmic bytes (per tet 208 B of inputs, per row
  * 80 B, 9 s per stored block) counted the same way.  ipc_prof_read writes
  * out[12]: out[0] product milliseconds, out[1] timed iterations, out[2] their
  * product bytes; out[3..5] the same three for the timed products over more

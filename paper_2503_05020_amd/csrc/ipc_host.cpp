@@ -1379,18 +1379,18 @@ struct World {
     ipck::incidence_fill(stream, W, S, L, nce, nvw);
     ipck::contact_rows(stream, L, nvw, ntot, mixed);
     // measurement: the assembly pass (elasticity, inertia, gradient, stored
-    // blocks) between two events, its algorithmic bytes counted after it
+    // blocks) from the start of its first kernel to the end of its last
+    // (events carried by the two dispatches), its algorithmic bytes counted
+    // after it
     hipEvent_t a0 = nullptr, a1 = nullptr;
     if (prof_on && !prof_all) {
       a0 = asm_event(asm_ev.size());
       a1 = asm_event(asm_ev.size() + 1);
       asm_ev.push_back(a0);
       asm_ev.push_back(a1);
-      HC(hipEventRecord(a0, stream));
     }
-    ipck::elastic(stream, W, envs_d, S, B);
-    ipck::assemble(stream, W, envs_d, S, B, L, mixed);
-    if (a1) HC(hipEventRecord(a1, stream));
+    ipck::elastic(stream, W, envs_d, S, B, a0);
+    ipck::assemble(stream, W, envs_d, S, B, L, mixed, a1);
     if (prof_on) ipck::asm_bytes(stream, envs_d, S, B, mixed, prof_bytes.p + 3);
     return na;
   }
@@ -1486,11 +1486,10 @@ public:
     // every solve has stopped costs only launches whose tiles exit at once.
     auto launch_block = [&](int slot) {
       for (int j = 0; j < poll_block; ++j) {
-        // every 16th iteration is timed (events before and after the product
-        // and the update: each costs a few us of dispatch gap, which would
-        // slow the solve it measures) and counts its algorithmic bytes in a
-        // launch of its own between the two kernels; with prof_all every
-        // iteration counts its bytes and none is timed
+        // every 16th iteration is timed (the product and the update carry
+        // start and end events in their dispatches) and counts its
+        // algorithmic bytes in a launch of its own between the two kernels;
+        // with prof_all every iteration counts its bytes and none is timed
         const hipEvent_t *ev = nullptr;
         bool count = false;
         if (prof_all) {

@@ -105,9 +105,12 @@ void incidence_fill(hipStream_t s, const WorldDev &W, const EnvState &S, Lists &
 
 // merged contact blocks of every row (after incidence_fill)
 void contact_rows(hipStream_t s, Lists &L, int nv_world, int n_inc, int mixed);
-void elastic(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B);
+// start / stop (nullable): events recorded by the dispatches themselves at the
+// start of k_elastic and the end of k_assemble_sell (the assembly pass timing)
+void elastic(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B,
+             hipEvent_t start = nullptr);
 void assemble(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, const Lists &L,
-              int mixed);
+              int mixed, hipEvent_t stop = nullptr);
 
 void pcg_init(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L,
               int *pending, int mixed);
