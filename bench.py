@@ -64,7 +64,7 @@ def make_scenes(workload: str, n_envs: int):
     return [make_scene(workload, i) for i in range(n_envs)]
 
 
-def run_gpu(scs, precision, warmup, steps, pcg_tol, label, count_all=False, **overrides):
+def run_gpu(scs, precision, warmup, steps, pcg_tol, label, count_all=False, autotune=None, **overrides):
     import torch
     t0 = time.time()
     gs = [G.ipc_create_scene(sc, precision=precision, pcg_rel_tol=pcg_tol, **overrides) for sc in scs]
@@ -72,6 +72,10 @@ def run_gpu(scs, precision, warmup, steps, pcg_tol, label, count_all=False, **ov
     for k in range(warmup):
         rc, infos = G.ipc_step_batch(gs, 1)
         log(f"[{label}] warmup step {k}: newton(max)={max(i['max_newton_iters'] for i in infos)}")
+    if autotune:
+        # per-workload choice of the scheduling knobs (untimed; changes no result)
+        t1 = time.time()
+        log(f"[{label}] autotune: {G.ipc_autotune(gs, 3, autotune)} in {time.time() - t1:.1f}s")
     torch.cuda.synchronize()
     if not count_all:
         G.ipc_prof_reset()
@@ -344,6 +348,8 @@ def main():
     ap.add_argument("--full-horizon", type=int, default=100,
                     help="also time this many steps from step 0 (the whole grasp) per precision; 0 skips")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--autotune", default="",
+                    help="tune the scheduling knobs per workload before timing, caching the choice in this file")
     ap.add_argument("--relative-stop", type=float, default=1e-3,
                     help="also time the mixed window with the paper's relative Newton stop (eps_r; 0 skips)")
     ap.add_argument("--serve-requests", type=int, default=48, help="0 skips the serving run")
@@ -389,7 +395,7 @@ def main():
     precs = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
     for p in precs:
         results[p] = run_gpu(scs, G.IPC_MIXED if p == "mixed" else G.IPC_FP64, args.warmup, args.steps,
-                             args.pcg_tol, p, args.count_all_bytes)
+                             args.pcg_tol, p, args.count_all_bytes, autotune=args.autotune or None)
         if args.count_all_bytes:
             pr = results[p]["prof"]
             # algorithmic bytes per product launch over the whole run, the

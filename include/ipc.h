@@ -204,7 +204,8 @@ int ipc_prof_read(double *out);
  *     concurrently from one host thread each, so that one lane's
  *     latency-bound tail overlaps with the others' work.  Applies to scenes
  *     created afterwards.
- * Returns IPC_OK, or IPC_E_ARG for an unknown key or a negative value. */
+ * Returns IPC_OK, or IPC_E_ARG for an unknown key or a negative value (other
+ * than -1 for IPC_TUNE_WIDE_TILES). */
 /* Further execution settings, read from the environment when a device's
  * first lane is created (none changes a result):
  *   IPC_BP_STASH    broad phase: pairs per query kept by the counting pass
@@ -236,8 +237,31 @@ int ipc_prof_read(double *out);
  * environment of the batch finishes step n before any begins step n+1).  The
  * same results bit for bit (every environment runs the same sequence). */
 #define IPC_TUNE_ASYNC 7
+/* IPC_TUNE_WIDE_TILES: PCG product launches over at most this many tiles
+ * issue each lane's slots four at a time (0 = none; -1 = the default: every
+ * FP64 launch and no mixed one; initial value from IPC_WIDE_TILES, else -1).
+ * IPC_TUNE_POLL_BLOCK: PCG iterations queued per host poll, 1..1024 (initial
+ * value IPC_POLL_BLOCK, else 16).  Neither changes a result. */
+#define IPC_TUNE_WIDE_TILES 8
+#define IPC_TUNE_POLL_BLOCK 9
 int ipc_set_tuning(int32_t key, int64_t value);
 int ipc_get_tuning(int32_t key, int64_t *value);
+
+/* Per-workload tuning of IPC_TUNE_WIDE_TILES and IPC_TUNE_POLL_BLOCK on the
+ * current device.  With cache_path (nullable) naming a text file that holds
+ * a line for this workload (key: scene count, total tets to three significant
+ * digits, precisions, lane count), its values are applied and out[2] = 1.
+ * Otherwise the current setting and each of the candidates {0, 64, all
+ * tiles} x {8, 16, 32} are timed (twice each, the faster run counting) over
+ * `steps` (1..64) time steps of copies of the n scenes set to their current
+ * state (the copies take device memory alongside the scenes while the call
+ * runs; the scenes themselves are not stepped); the fastest candidate
+ * replaces the current setting only if it is at least 3% faster; the result
+ * is applied, out[2] = 0, and a line "key<TAB>wide poll ms_per_step" is
+ * appended to the file.  out[0], out[1] = the values applied.  The knobs change no result,
+ * so results stay bitwise those of any other setting.  IPC_E_ARG for bad
+ * arguments or an unwritable cache file; a device error as any stepping call. */
+int ipc_autotune(const ipc_scene *scenes, int32_t n, int32_t steps, const char *cache_path, int64_t out[3]);
 
 /* CCD step bound over a caller's list of contact pairs (Sec. II-C: the
  * projected-Newton step is filtered by continuous collision detection; the

@@ -14,6 +14,7 @@
 #include <cstdlib>
 #include <cmath>
 #include <cstdio>
+#include <fstream>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -1412,7 +1413,7 @@ public:
   // previous one (0: after it)
   const int pipeline = env_knob("IPC_PIPELINE", 1) ? 1 : 0;
   // PCG iterations per block between polls of the pending count
-  const int poll_block = std::max(1, env_knob("IPC_POLL_BLOCK", 16));
+  int poll_block = std::max(1, env_knob("IPC_POLL_BLOCK", 16));
   // the batch is laid out again once at most this percentage of it still
   // iterates its Newton loop
   const int narrow_pct = std::min(100, env_knob("IPC_NARROW_PCT", 50));
@@ -1426,7 +1427,7 @@ public:
   // slots four at a time, larger ones one at a time.  Default (-1): every
   // launch in FP64 and none in the mixed path, where the one-slot variant (44
   // VGPRs against 86) measured faster also in the latency-bound tails.
-  const int wide_tiles = [] {
+  int wide_tiles = [] {
     const char *e = std::getenv("IPC_WIDE_TILES");
     return (e && e[0]) ? std::max(0, std::atoi(e)) : -1;
   }();
@@ -2624,7 +2625,8 @@ int ipc_prof_enable(int32_t on) {
 
 int ipc_set_tuning(int32_t key, int64_t value) {
   return guarded([&]() {
-    if (value < 0) throw ApiError(IPC_E_ARG, "tuning value must be >= 0");
+    if (value < 0 && !(key == IPC_TUNE_WIDE_TILES && value == -1))
+      throw ApiError(IPC_E_ARG, "tuning value must be >= 0");
     if (key == IPC_TUNE_LANES) {
       if (value < 1 || value > 16) throw ApiError(IPC_E_ARG, "lanes must be in [1, 16]");
       std::lock_guard<std::mutex> lk(g_worlds_mu);
@@ -2632,8 +2634,11 @@ int ipc_set_tuning(int32_t key, int64_t value) {
       return IPC_OK;
     }
     if (key != IPC_TUNE_TAIL_TILES && key != IPC_TUNE_FUSED_PCG && key != IPC_TUNE_NARROW &&
-        key != IPC_TUNE_ADMIT_FAULTS && key != IPC_TUNE_ASYNC)
+        key != IPC_TUNE_ADMIT_FAULTS && key != IPC_TUNE_ASYNC && key != IPC_TUNE_WIDE_TILES &&
+        key != IPC_TUNE_POLL_BLOCK)
       throw ApiError(IPC_E_ARG, "unknown tuning key");
+    if (key == IPC_TUNE_POLL_BLOCK && (value < 1 || value > 1024))
+      throw ApiError(IPC_E_ARG, "poll block must be in [1, 1024]");
     for (World *pw : worlds_for_current_device()) {
       World &w = *pw;
       std::lock_guard<std::mutex> lk(w.mu);
@@ -2645,6 +2650,10 @@ int ipc_set_tuning(int32_t key, int64_t value) {
         w.admit_faults = (int)std::min<int64_t>(value, 1 << 30);
       else if (key == IPC_TUNE_ASYNC)
         w.async_mode = value != 0;
+      else if (key == IPC_TUNE_WIDE_TILES)
+        w.wide_tiles = (int)std::min<int64_t>(value, 1 << 30);  // -1: the default
+      else if (key == IPC_TUNE_POLL_BLOCK)
+        w.poll_block = (int)value;
       else
         w.narrow = value != 0;
     }
@@ -2671,8 +2680,139 @@ int ipc_get_tuning(int32_t key, int64_t *value) {
       *value = w.admit_faults;
     else if (key == IPC_TUNE_ASYNC)
       *value = w.async_mode;
+    else if (key == IPC_TUNE_WIDE_TILES)
+      *value = w.wide_tiles;  // -1: the default (every FP64 launch, no mixed one)
+    else if (key == IPC_TUNE_POLL_BLOCK)
+      *value = w.poll_block;
     else
       throw ApiError(IPC_E_ARG, "unknown tuning key");
+    return IPC_OK;
+  });
+}
+
+// an entry point of this library called from another one: its error code
+// and message are passed on
+#define HC_API(call)                                       \
+  do {                                                     \
+    const int rc_ = (call);                                \
+    if (rc_ != IPC_OK) throw ApiError(rc_, ipc_last_error()); \
+  } while (0)
+
+// Per-workload tuning of the scheduling knobs that change no result (the
+// four-slot product variant's tile threshold and the PCG poll block): every
+// candidate pair is timed on copies of the caller's scenes set to their
+// current state, the fastest is applied to the device and recorded in the
+// cache file under the workload's key (scene count, total tets to three
+// significant digits, precisions, lane count), so a later call with the same
+// key applies it without timing.
+int ipc_autotune(const ipc_scene *scenes, int32_t n, int32_t steps, const char *cache_path, int64_t out[3]) {
+  return guarded([&]() {
+    if (!scenes || n <= 0 || steps <= 0 || steps > 64 || !out) throw ApiError(IPC_E_ARG, "bad arguments");
+    std::vector<ipc_scene> orig(scenes, scenes + n);
+    long long tets = 0;
+    int prec_mask = 0;
+    for (ipc_scene s : orig) {
+      if (!s) throw ApiError(IPC_E_ARG, "null scene");
+      tets += s->host->nt;
+      prec_mask |= 1 << (s->host->precision == IPC_MIXED ? 1 : 0);
+    }
+    long long mag = 1;
+    while (tets / mag >= 1000) mag *= 10;
+    char key[160];
+    std::snprintf(key, sizeof key, "envs=%d tets=%lld prec=%d lanes=%d", n, (tets + mag / 2) / mag * mag, prec_mask,
+                  lanes_setting());
+    auto apply = [&](int64_t wide, int64_t poll) {
+      for (World *pw : worlds_for_current_device()) {
+        std::lock_guard<std::mutex> lk(pw->mu);
+        pw->wide_tiles = (int)wide;
+        pw->poll_block = (int)poll;
+      }
+    };
+    if (cache_path) {
+      std::ifstream in(cache_path);
+      std::string line;
+      while (std::getline(in, line)) {
+        const size_t tab = line.find('\t');
+        if (tab == std::string::npos || line.compare(0, tab, key) != 0 || tab != std::strlen(key)) continue;
+        long long wide = 0, poll = 0;
+        double ms = 0.0;
+        if (std::sscanf(line.c_str() + tab + 1, "%lld %lld %lf", &wide, &poll, &ms) == 3 && poll >= 1) {
+          apply(wide, poll);
+          out[0] = wide;
+          out[1] = poll;
+          out[2] = 1;
+          return IPC_OK;
+        }
+      }
+    }
+    // copies of the scenes at their current state
+    std::vector<ipc_scene> copies;
+    std::vector<std::vector<double>> pos(n), vel(n);
+    auto destroy = [&]() {
+      for (ipc_scene c : copies) ipc_destroy_scene(c);
+      copies.clear();
+    };
+    try {
+      for (int i = 0; i < n; ++i) {
+        ipc_scene s = orig[i];
+        pos[i].resize(3L * s->host->nv);
+        vel[i].resize(3L * s->host->nv);
+        HC_API(ipc_get_state(s, pos[i].data(), vel[i].data(), nullptr, nullptr));
+        World &w = world_for_new_scene();
+        std::lock_guard<std::mutex> lk(w.mu);
+        int slot = w.add_scene(*s->host);
+        auto *c = new ipc_scene_s();
+        c->world = &w;
+        c->slot = slot;
+        c->host = std::make_unique<HostScene>(*s->host);
+        copies.push_back(c);
+      }
+      auto reset = [&]() {
+        for (int i = 0; i < n; ++i) HC_API(ipc_set_state(copies[i], pos[i].data(), vel[i].data(), orig[i]->step));
+      };
+      // the current setting first: a candidate replaces it only when it is
+      // at least 3% faster (each timed twice, the faster run counts)
+      World &w0 = world_for_current_device();
+      std::vector<std::pair<int64_t, int64_t>> cand = {{w0.wide_tiles, w0.poll_block}};
+      for (int64_t wd : {int64_t(0), int64_t(64), int64_t(1) << 30})
+        for (int64_t pl : {int64_t(8), int64_t(16), int64_t(32)})
+          if (!(wd == cand[0].first && pl == cand[0].second)) cand.push_back({wd, pl});
+      double best = HUGE_VAL, current = HUGE_VAL;
+      int64_t bw = cand[0].first, bp = cand[0].second;
+      for (size_t k = 0; k < cand.size(); ++k) {
+        apply(cand[k].first, cand[k].second);
+        if (k == 0) {  // buffers grow to this workload's sizes once, untimed
+          reset();
+          run_steps(copies, steps, nullptr);
+        }
+        double ms = HUGE_VAL;
+        for (int rep = 0; rep < 2; ++rep) {
+          reset();
+          const auto t0 = std::chrono::steady_clock::now();
+          run_steps(copies, steps, nullptr);
+          ms = std::min(ms, std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
+        }
+        if (k == 0) current = ms;
+        if (ms < best && (k == 0 || ms < 0.97 * current)) {
+          best = ms;
+          bw = cand[k].first;
+          bp = cand[k].second;
+        }
+      }
+      destroy();
+      apply(bw, bp);
+      out[0] = bw;
+      out[1] = bp;
+      out[2] = 0;
+      if (cache_path) {
+        std::ofstream o(cache_path, std::ios::app);
+        if (!o) throw ApiError(IPC_E_ARG, "cannot write the tuning cache file");
+        o << key << '\t' << bw << ' ' << bp << ' ' << best / steps << '\n';
+      }
+    } catch (...) {
+      destroy();
+      throw;
+    }
     return IPC_OK;
   });
 }

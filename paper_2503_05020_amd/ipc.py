@@ -29,6 +29,8 @@ IPC_TUNE_NARROW = 4
 IPC_TUNE_LANES = 5
 IPC_TUNE_ADMIT_FAULTS = 6
 IPC_TUNE_ASYNC = 7
+IPC_TUNE_WIDE_TILES = 8
+IPC_TUNE_POLL_BLOCK = 9
 IPC_FAIL_ADMIT = 6
 FAIL_REASONS = {0: "none", 1: "maxit", 2: "nonfinite", 3: "line-search", 4: "dirichlet"}
 
@@ -69,7 +71,7 @@ EXPORTS = [
     "ipc_debug_ccd_bound", "ipc_debug_classify", "ipc_debug_pair_barrier", "ipc_debug_tet_elastic",
     "ipc_debug_accd", "ipc_debug_inversion_bound", "ipc_debug_tet_first_root", "ipc_ccd_bound_pairs",
     "ipc_ccd_bound_pairs_noalloc", "ipc_grasp_metrics", "ipc_hold_group", "ipc_set_gravity", "ipc_contact_forces",
-    "ipc_validate_grasp", "ipc_prof_enable", "ipc_prof_reset", "ipc_prof_read", "ipc_set_tuning", "ipc_get_tuning",
+    "ipc_validate_grasp", "ipc_prof_enable", "ipc_prof_reset", "ipc_prof_read", "ipc_set_tuning", "ipc_get_tuning", "ipc_autotune",
     "ipc_server_create", "ipc_server_submit", "ipc_server_poll", "ipc_server_wait", "ipc_server_result",
     "ipc_server_release", "ipc_server_set_slots", "ipc_server_stats", "ipc_server_destroy",
 ]
@@ -158,6 +160,7 @@ def lib():
     L.ipc_prof_read.argtypes = [_dp]
     L.ipc_set_tuning.argtypes = [C.c_int32, C.c_int64]
     L.ipc_get_tuning.argtypes = [C.c_int32, C.POINTER(C.c_int64)]
+    L.ipc_autotune.argtypes = [C.POINTER(vp), C.c_int32, C.c_int32, C.c_char_p, C.POINTER(C.c_int64)]
     L.ipc_server_create.argtypes = [C.c_int64, C.c_int32, C.POINTER(vp)]
     L.ipc_server_submit.argtypes = [vp, C.POINTER(ipc_scene_desc), C.c_int32, C.POINTER(C.c_int64)]
     L.ipc_server_poll.argtypes = [vp, C.c_int64, C.POINTER(ipc_request_info)]
@@ -324,6 +327,16 @@ def ipc_get_tuning(key: int) -> int:
     out = C.c_int64()
     _check(lib().ipc_get_tuning(key, C.byref(out)))
     return int(out.value)
+
+
+def ipc_autotune(scenes, steps: int = 2, cache_path=None):
+    """Per-workload choice of IPC_TUNE_WIDE_TILES and IPC_TUNE_POLL_BLOCK (applied to the device);
+    returns (wide_tiles, poll_block, from_cache)."""
+    arr = (C.c_void_p * max(1, len(scenes)))(*[s.h.value for s in scenes])
+    out = (C.c_int64 * 3)()
+    path = None if cache_path is None else os.fsencode(cache_path)
+    _check(lib().ipc_autotune(arr, len(scenes), int(steps), path, out))
+    return int(out[0]), int(out[1]), bool(out[2])
 
 
 # --- serving -----------------------------------------------------------------
