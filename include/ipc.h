@@ -244,6 +244,15 @@ int ipc_prof_read(double *out);
  * value IPC_POLL_BLOCK, else 16).  Neither changes a result. */
 #define IPC_TUNE_WIDE_TILES 8
 #define IPC_TUNE_POLL_BLOCK 9
+/* IPC_TUNE_COARSE: 1 (default; IPC_COARSE) = two-level PCG: block Jacobi plus
+ * an exact solve on the rigid motions (3 translations, 3 rotations) of each
+ * body of an environment (its connected sets of free vertices, the 4 largest
+ * with at least 4 vertices); 0 = block Jacobi alone.  Unlike the other knobs
+ * it changes the PCG's iterates, within its stopping tolerance; results stay
+ * the same alone and in any batch.  While it is on, IPC_TUNE_FUSED_PCG and
+ * IPC_TUNE_TAIL_TILES have no effect (those kernels are block Jacobi only).
+ * Applies from the next step. */
+#define IPC_TUNE_COARSE 10
 int ipc_set_tuning(int32_t key, int64_t value);
 int ipc_get_tuning(int32_t key, int64_t *value);
 

@@ -167,6 +167,11 @@ struct HostScene {
   double dt, dhat, kappa, mu_f, eps_v, tol, pcg_tol;
   int maxit, precision;
   int fric_iters = 1, inv_filter = 0, adapt_kappa = 0;
+  // coarse space of the PCG: body of each free vertex (-1: none), bodies'
+  // reference points and lengths
+  std::vector<int> vbody;
+  int nbody = 0;
+  double cb[ipcw::kCoarseBodies][3] = {}, cscale[ipcw::kCoarseBodies] = {};
 };
 
 bool finite_all(const double *p, long n) {
@@ -580,6 +585,50 @@ std::unique_ptr<HostScene> preprocess(const ipc_scene_desc *d) {
       H.cb_end[p] = (int)H.contrib.size();
     }
   }
+  // coarse space of the two-level PCG: the connected sets of free vertices
+  // (joined through tets), the kCoarseBodies largest with at least 4
+  // vertices (ties: lowest vertex id), each with its rest centroid and the
+  // largest rest distance from it
+  {
+    std::vector<int> par(H.nv);
+    for (int i = 0; i < H.nv; ++i) par[i] = i;
+    auto find = [&](int i) {
+      while (par[i] != i) i = par[i] = par[par[i]];
+      return i;
+    };
+    for (int e = 0; e < H.nt; ++e)
+      for (int a = 1; a < 4; ++a) {
+        const int u = H.tets[4 * e], v = H.tets[4 * e + a];
+        if (H.kin[u] >= 0 || H.kin[v] >= 0) continue;
+        const int ru = find(u), rv = find(v);
+        if (ru != rv) par[std::max(ru, rv)] = std::min(ru, rv);
+      }
+    std::map<int, std::vector<int>> comp;  // root (lowest id of the set) -> free vertices, ascending
+    for (int i = 0; i < H.nv; ++i)
+      if (H.kin[i] < 0) comp[find(i)].push_back(i);
+    std::vector<const std::vector<int> *> order;
+    for (auto &c : comp)
+      if (c.second.size() >= 4) order.push_back(&c.second);
+    std::stable_sort(order.begin(), order.end(),
+                     [](const std::vector<int> *a, const std::vector<int> *b) { return a->size() > b->size(); });
+    H.vbody.assign(H.nv_pad, -1);
+    H.nbody = (int)std::min<size_t>(order.size(), ipcw::kCoarseBodies);
+    for (int b = 0; b < H.nbody; ++b) {
+      const std::vector<int> &vs = *order[b];
+      double c[3] = {0, 0, 0};
+      for (int i : vs)
+        for (int k = 0; k < 3; ++k) c[k] += H.X[3 * i + k];
+      for (int k = 0; k < 3; ++k) H.cb[b][k] = c[k] / (double)vs.size();
+      double r2 = 0.0;
+      for (int i : vs) {
+        double d2 = 0.0;
+        for (int k = 0; k < 3; ++k) d2 += (H.X[3 * i + k] - H.cb[b][k]) * (H.X[3 * i + k] - H.cb[b][k]);
+        r2 = std::max(r2, d2);
+        H.vbody[i] = b;
+      }
+      H.cscale[b] = std::max(std::sqrt(r2), 1e-12);
+    }
+  }
   return S;
 }
 
@@ -603,6 +652,7 @@ struct World {
   size_t env_cap = 0;
   EnvState S{};
   std::vector<void **> state_int, state_ll, state_dbl;
+  std::vector<std::pair<void **, size_t>> state_wide;  // per-environment arrays of several values
   // batch
   std::vector<int> batch_envs;
   DBuf<Tile> vt_d, tt_d, svt_d, trit_d, et_d, it_d, bt_d;
@@ -619,7 +669,7 @@ struct World {
   DBuf<int> g_ncell, g_big, g_eoff, g_bigoff, g_ebucket, g_bcnt, g_boff, g_bcur, g_bigl;
   DBuf<ipck::GridEnt> g_ent, g_sorted;
   DBuf<int2> bp_stash;
-  DBuf<double> act_d2, cand_d2, e_c, fw, fn, flam, e_f, ce_g, ce_H, part_a, part_b0, part_b1, part_c0, part_c1;
+  DBuf<double> act_d2, cand_d2, e_c, fw, fn, flam, e_f, ce_g, ce_H, part_a, part_z, e_tile, part_b0, part_b1, part_c0, part_c1;
   DBuf<int4> fv, ce_v;
   // decoupled schedule: second friction buffers (merged into, then swapped),
   // per-environment plans of the new friction ranges, host copy of the phases
@@ -638,7 +688,8 @@ struct World {
   std::vector<hipEvent_t> ev_pool;
   double prof_ms = 0.0, prof_ms_big = 0.0;  // big: launches over more than kWideTiles tiles
   long long prof_launches = 0, prof_launches_big = 0;
-  double prof_ms_iter = 0.0, prof_ms_asm = 0.0;  // whole PCG iterations (product + update); assembly passes
+  double prof_ms_iter = 0.0, prof_ms_asm = 0.0;
+  long long prof_skipped = 0;  // timed samples whose events were not recorded  // whole PCG iterations (product + update); assembly passes
   long long prof_asm = 0;
   std::vector<hipEvent_t> asm_ev;  // event pairs around the assembly passes of the current step
   int n_fric = 0;
@@ -680,6 +731,9 @@ struct World {
     reg(aV, (void **)&W.vt_beg, 4);
     reg(aV, (void **)&W.vt_end, 4);
     reg(aV, (void **)&W.row_nnz, 4);
+    reg(aV, (void **)&W.vbody, 4);
+    reg(aV, (void **)&W.hz, 8 * 3 * ipcw::kCoarseM);
+    reg(aV, (void **)&W.hz32, 4 * 3 * ipcw::kCoarseM);
     reg(aSlice, (void **)&W.slice_pos, 4);
     reg(aSlice, (void **)&W.slice_w, 4);
     reg(aPos, (void **)&W.col, 4);
@@ -718,7 +772,10 @@ struct World {
     state_dbl = {(void **)&S.alpha, (void **)&S.E0,  (void **)&S.E1,       (void **)&S.pinf,
                  (void **)&S.pcg_bb, (void **)&S.kA, (void **)&S.viol, (void **)&S.viol_prev,
                  (void **)&S.cg_a0,  (void **)&S.cg_a1, (void **)&S.cg_g0, (void **)&S.cg_g1,
-                 (void **)&S.kappa,  (void **)&S.kappa0, (void **)&S.dmin_prev, (void **)&S.dmin2};
+                 (void **)&S.kappa,  (void **)&S.kappa0, (void **)&S.dmin_prev, (void **)&S.dmin2,
+                 (void **)&S.cgam};
+    state_int.push_back((void **)&S.cok);
+    state_wide = {{(void **)&S.cinv, 8 * ipcw::kCoarseM * ipcw::kCoarseM}, {(void **)&S.cc, 8 * ipcw::kCoarseM}};
   }
 
   void ensure_envs(size_t n) {
@@ -737,6 +794,7 @@ struct World {
     for (void **s : state_int) grow(s, 4);
     for (void **s : state_ll) grow(s, 8);
     for (void **s : state_dbl) grow(s, 8);
+    for (auto &s : state_wide) grow(s.first, s.second);
     env_cap = nc;
   }
 
@@ -870,6 +928,7 @@ struct World {
     up(W.vt_beg + vo, vb.data(), vb.size());
     up(W.vt_end + vo, ve.data(), ve.size());
     up(W.row_nnz + vo, H.row_nnz.data(), H.row_nnz.size());
+    up(W.vbody + vo, H.vbody.data(), H.vbody.size());
     HC(hipMemsetAsync(W.p + 3 * vo, 0, 24 * R.v_n, stream));
     HC(hipMemsetAsync(W.pp + 3 * vo, 0, 24 * R.v_n, stream));
     HC(hipMemsetAsync(W.pp32 + 3 * vo, 0, 12 * R.v_n, stream));
@@ -954,6 +1013,11 @@ struct World {
     for (int r : H.row_nnz) E.nnzb += r;
     E.inv_filter = H.inv_filter;
     E.adapt_kappa = H.adapt_kappa;
+    E.nbody = H.nbody;
+    for (int b = 0; b < ipcw::kCoarseBodies; ++b) {
+      for (int k = 0; k < 3; ++k) E.cb[b][k] = H.cb[b][k];
+      E.cscale[b] = H.cscale[b] > 0.0 ? H.cscale[b] : 1.0;
+    }
     upload_env(slot);
     int zero = 0;
     HC(hipMemcpyAsync(S.status + slot, &zero, 4, hipMemcpyHostToDevice, stream));
@@ -1067,6 +1131,8 @@ struct World {
     cr_rows.ensure(nvw);
     size_t nvt = vt.size() + 1;
     part_a.ensure(nvt);
+    part_z.ensure(nvt * ipcw::kCoarseM);
+    e_tile.ensure(nvt * ipcw::kCoarseM * ipcw::kCoarseM);
     part_b0.ensure(nvt);
     part_b1.ensure(nvt);
     part_c0.ensure(nvt);
@@ -1115,6 +1181,8 @@ struct World {
     L.cr_val = cr_val.p;
     L.cr_val32 = cr_val32.p;
     L.part_a = part_a.p;
+    L.part_z = part_z.p;
+    L.e_tile = e_tile.p;
     L.part_b0 = part_b0.p;
     L.part_b1 = part_b1.p;
     L.part_c0 = part_c0.p;
@@ -1152,6 +1220,7 @@ struct World {
 
   void prof_reset() {
     prof_ms = prof_ms_big = prof_ms_iter = prof_ms_asm = 0.0;
+    prof_skipped = 0;
     prof_launches = prof_launches_big = prof_asm = 0;
     if (prof_bytes.p) {
       HC(hipMemsetAsync(prof_bytes.p, 0, 32, stream));
@@ -1392,6 +1461,7 @@ struct World {
     }
     ipck::elastic(stream, W, envs_d, S, B, a0);
     ipck::assemble(stream, W, envs_d, S, B, L, mixed, a1);
+    if (coarse) ipck::coarse_setup(stream, W, envs_d, S, B, L, mixed);
     if (prof_on) ipck::asm_bytes(stream, envs_d, S, B, mixed, prof_bytes.p + 3);
     return na;
   }
@@ -1437,14 +1507,26 @@ public:
   // 1: the decoupled schedule (run_steps_lane_async): environments begin
   // their next step as soon as they finish one; 0: lock-step time steps
   int async_mode = env_knob("IPC_ASYNC", 1) ? 1 : 0;
-  bool use_fused() const { return fused_pcg == 1; }
+  // 1: the two-level PCG (block Jacobi plus the bodies' rigid motions as a
+  // coarse space); the per-environment PCG kernels are block Jacobi only, so
+  // they are not used while it is on
+  int coarse = env_knob("IPC_COARSE", 1) ? 1 : 0;
+  bool use_fused() const { return fused_pcg == 1 && !coarse; }
   void set_fused(int on) {
-    if ((on != 0) == use_fused()) return;
+    if ((on != 0) == (fused_pcg == 1)) return;
     fused_pcg = on ? 1 : 0;
     batch_envs.clear();  // E.fused is decided when a batch is laid out
   }
+  void set_coarse(int on) {
+    if ((on != 0) == (coarse == 1)) return;
+    coarse = on ? 1 : 0;
+    batch_envs.clear();
+  }
   void copy_knobs(const World &o) {
     set_fused(o.fused_pcg);
+    set_coarse(o.coarse);
+    wide_tiles = o.wide_tiles;
+    poll_block = o.poll_block;
     tail_tiles = o.tail_tiles;
     narrow = o.narrow;
     async_mode = o.async_mode;
@@ -1466,6 +1548,7 @@ public:
       return mx;
     }
     L.wide_tiles = wide_tiles >= 0 ? wide_tiles : mixed ? 0 : 1 << 30;
+    L.coarse = coarse;
     ipck::pcg_init(stream, W, envs_d, S, B, L, pending, mixed);
     // an environment's solve stops at the latest in the iteration whose index
     // reaches its cap of 30 n_v + 10 (that iteration only takes the test)
@@ -1527,7 +1610,7 @@ public:
         ntl = read_int(live_offs.p + B.n_vt);
         tl = live_d.p;
         last_pending = pend;
-        if (ntl <= tail_tiles) {
+        if (ntl <= tail_tiles && !coarse) {
           // few tiles left: their launches would be latency-bound, so one
           // workgroup per environment finishes the solves in one launch
           ipck::pcg_resume(stream, W, envs_d, S, L, tl, ntl, it, mixed);
@@ -1544,8 +1627,13 @@ public:
       HC(hipStreamSynchronize(stream));
       for (size_t k = 0; k + 3 < nev; k += 4) {
         float ms = 0.f, mu = 0.f;
-        HC(hipEventElapsedTime(&ms, ev_pool[k], ev_pool[k + 1]));
-        HC(hipEventElapsedTime(&mu, ev_pool[k + 2], ev_pool[k + 3]));
+        // a sample whose events were not both recorded is left out (counted)
+        if (hipEventElapsedTime(&ms, ev_pool[k], ev_pool[k + 1]) != hipSuccess ||
+            hipEventElapsedTime(&mu, ev_pool[k + 2], ev_pool[k + 3]) != hipSuccess) {
+          (void)hipGetLastError();
+          ++prof_skipped;
+          continue;
+        }
         prof_ms += ms;
         prof_ms_iter += ms + mu;
         prof_launches += 1;
@@ -2635,7 +2723,7 @@ int ipc_set_tuning(int32_t key, int64_t value) {
     }
     if (key != IPC_TUNE_TAIL_TILES && key != IPC_TUNE_FUSED_PCG && key != IPC_TUNE_NARROW &&
         key != IPC_TUNE_ADMIT_FAULTS && key != IPC_TUNE_ASYNC && key != IPC_TUNE_WIDE_TILES &&
-        key != IPC_TUNE_POLL_BLOCK)
+        key != IPC_TUNE_POLL_BLOCK && key != IPC_TUNE_COARSE)
       throw ApiError(IPC_E_ARG, "unknown tuning key");
     if (key == IPC_TUNE_POLL_BLOCK && (value < 1 || value > 1024))
       throw ApiError(IPC_E_ARG, "poll block must be in [1, 1024]");
@@ -2654,6 +2742,8 @@ int ipc_set_tuning(int32_t key, int64_t value) {
         w.wide_tiles = (int)std::min<int64_t>(value, 1 << 30);  // -1: the default
       else if (key == IPC_TUNE_POLL_BLOCK)
         w.poll_block = (int)value;
+      else if (key == IPC_TUNE_COARSE)
+        w.set_coarse(value != 0);
       else
         w.narrow = value != 0;
     }
@@ -2684,6 +2774,8 @@ int ipc_get_tuning(int32_t key, int64_t *value) {
       *value = w.wide_tiles;  // -1: the default (every FP64 launch, no mixed one)
     else if (key == IPC_TUNE_POLL_BLOCK)
       *value = w.poll_block;
+    else if (key == IPC_TUNE_COARSE)
+      *value = w.coarse;
     else
       throw ApiError(IPC_E_ARG, "unknown tuning key");
     return IPC_OK;
@@ -2848,6 +2940,7 @@ int ipc_prof_read(double *out) {
       out[6] += w.prof_ms_iter;
       out[7] += (double)w.prof_launches;
       out[8] += (double)b[2];
+      if (w.prof_skipped) std::fprintf(stderr, "[ipc] %lld timed PCG samples left out: events not recorded\n", w.prof_skipped);
       out[9] += w.prof_ms_asm;
       out[10] += (double)w.prof_asm;
       out[11] += (double)b[3];

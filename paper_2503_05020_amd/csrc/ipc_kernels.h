@@ -58,6 +58,9 @@ struct Lists {
   float *cr_val32;
   // reduction partials per vertex tile (PCG: a = u.Hu, b0/b1 = r.u, c0/c1 = r.r)
   double *part_a, *part_b0, *part_b1, *part_c0, *part_c1;
+  // two-level PCG: per tile, Z^T r [kCoarseM] and the tile's part of Z^T H Z [kCoarseM^2]
+  double *part_z, *e_tile;
+  int coarse;  // 1: the PCG uses the coarse correction
   int *counter;  // device scratch counters [16]
   int *bar_slow;  // barrier pairs that take the full 12x12 element (k_barrier_elems_full)
   // hash grid
@@ -112,6 +115,10 @@ void elastic(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &
 void assemble(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, const Lists &L,
               int mixed, hipEvent_t stop = nullptr);
 
+// the coarse matrix E = Z^T H Z of the two-level PCG and E^-1, per environment
+// of the batch, at the assembled H
+void coarse_setup(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B,
+                  const Lists &L, int mixed);
 void pcg_init(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, Lists &L,
               int *pending, int mixed);
 // one tiled PCG iteration (product with its dot product, then the update with

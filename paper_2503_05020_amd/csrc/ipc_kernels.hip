@@ -11,6 +11,8 @@
 #include <hip/hip_ext.h>
 
 #include <mutex>
+#include <stdexcept>
+#include <string>
 #include <type_traits>
 
 #include "device_math.h"
@@ -1252,6 +1254,72 @@ __global__ void k_assemble_sell(WorldDev W, const EnvDev *envs, EnvState S, cons
 // ---------------------------------------------------------------------------
 // block-Jacobi PCG, one independent solve per environment
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// Two-level PCG.  The coarse space spans the rigid motions of each body of an
+// environment (its connected sets of free vertices): for a free vertex i of
+// body b, Z_i = [I | R_i] with R_i = -[d_i]x / s_b, d_i = x_i - cb_b (cb_b a
+// reference point, s_b the body's size, so that the six columns have like
+// magnitudes); Z_i = 0 for every other row.  The preconditioner is
+//   M^-1 r = D^-1 r + Z E^-1 Z^T r,  E = Z^T H Z
+// (block Jacobi plus an exact solve on the coarse space).  Z_i [t; w] =
+// t + (w x d_i) / s_b and Z_i^T r = [r; (d_i x r) / s_b].
+// ---------------------------------------------------------------------------
+// tiles whose Z^T r partials a 1024-thread product stages in LDS at once
+constexpr int kZChunk = 1024 / kCoarseM;
+// position of entry k (of 3 kCoarseM) of (H Z)_i in the sliced layout: the
+// 64 rows of a slice side by side for each entry
+DEV size_t hz_index(int i, int k) {
+  return ((size_t)(i / kSlice) * (3 * kCoarseM) + k) * kSlice + (size_t)(i % kSlice);
+}
+// coarse correction (Z c)_i of a row at position xi in body b; c holds
+// (t, w) per body.  The one routine every kernel uses for it (same bits).
+DEV void coarse_corr_x(const EnvDev &E, int b, const double xi[3], const double *c, double out[3]) {
+  const double is = 1.0 / E.cscale[b];
+  const double d0 = xi[0] - E.cb[b][0], d1 = xi[1] - E.cb[b][1], d2 = xi[2] - E.cb[b][2];
+  const double *t = c + 6 * b, *w = c + 6 * b + 3;
+  out[0] = t[0] + (w[1] * d2 - w[2] * d1) * is;
+  out[1] = t[1] + (w[2] * d0 - w[0] * d2) * is;
+  out[2] = t[2] + (w[0] * d1 - w[1] * d0) * is;
+}
+DEV void coarse_corr(const EnvDev &E, int b, const double *x, int i, const double *c, double out[3]) {
+  const double xi[3] = {x[3 * i], x[3 * i + 1], x[3 * i + 2]};
+  coarse_corr_x(E, b, xi, c, out);
+}
+// Z_i^T r of a row at position xi in body b (six values)
+DEV void coarse_zt_x(const EnvDev &E, int b, const double xi[3], const double r[3], double q[6]) {
+  const double is = 1.0 / E.cscale[b];
+  const double d0 = xi[0] - E.cb[b][0], d1 = xi[1] - E.cb[b][1], d2 = xi[2] - E.cb[b][2];
+  q[0] = r[0];
+  q[1] = r[1];
+  q[2] = r[2];
+  q[3] = (d1 * r[2] - d2 * r[1]) * is;
+  q[4] = (d2 * r[0] - d0 * r[2]) * is;
+  q[5] = (d0 * r[1] - d1 * r[0]) * is;
+}
+
+// sums of v[0..N) over the 256 threads of a tile (one row each): the
+// butterfly over each wavefront, then the four wavefront sums as
+// (w0 + w1) + (w2 + w3); thread k < N gets sum k (others 0).  Every thread of
+// the block calls it.  sh: 4 * N doubles.
+template <int N>
+DEV double tile_sums(double v[N], double *sh) {
+#pragma unroll
+  for (int k = 0; k < N; ++k)
+    for (int m = 32; m > 0; m >>= 1) v[k] += __shfl_xor(v[k], m, 64);
+  const int wv = threadIdx.x / 64;
+  if ((threadIdx.x & 63) == 0 && wv < 4)
+#pragma unroll
+    for (int k = 0; k < N; ++k) sh[wv * N + k] = v[k];
+  __syncthreads();
+  double out = 0.0;
+  if ((int)threadIdx.x < N) {
+    const int k = threadIdx.x;
+    out = (sh[k] + sh[N + k]) + (sh[2 * N + k] + sh[3 * N + k]);
+  }
+  __syncthreads();
+  return out;
+}
+
 // the vector a product reads: stored, or the next direction formed on the fly
 template <typename T>
 struct StoredVec {
@@ -1469,12 +1537,11 @@ DEV void row_init(const WorldDev &W, bool fr, int i, T *x, T *r, T *u, T *pp, T 
 
 // w_i = (H u)_i by the row's 4 lanes; returns u_i . w_i (same in all four
 // lanes, 0 for an invalid row)
-template <typename T, bool WIDE>
-DEV double row_spmv(const WorldDev &W, int i, bool valid, int l, const RowHead &h, const int *cr_col,
-                    const T *cr_val, const T *u, T *w, const T *val) {
+template <typename T, bool WIDE, typename V>
+DEV double row_spmv_v(const WorldDev &W, int i, bool valid, int l, const RowHead &h, const int *cr_col,
+                      const T *cr_val, const V &v, T *w, const T *val) {
   double y[3];
-  const StoredVec<T> v{u};
-  row_product<T, StoredVec<T>, WIDE>(W, i, valid, l, h, v, val, cr_col, cr_val, y);
+  row_product<T, V, WIDE>(W, i, valid, l, h, v, val, cr_col, cr_val, y);
   if (!valid) return 0.0;
   double d = 0.0;
   for (int c = 0; c < 3; ++c) {
@@ -1482,6 +1549,11 @@ DEV double row_spmv(const WorldDev &W, int i, bool valid, int l, const RowHead &
     d += v[3 * i + c] * (double)(T)y[c];
   }
   return d;
+}
+template <typename T, bool WIDE>
+DEV double row_spmv(const WorldDev &W, int i, bool valid, int l, const RowHead &h, const int *cr_col,
+                    const T *cr_val, const T *u, T *w, const T *val) {
+  return row_spmv_v<T, WIDE>(W, i, valid, l, h, cr_col, cr_val, StoredVec<T>{u}, w, val);
 }
 
 // one row's vectors and preconditioner block, loaded ahead of the scalars
@@ -1504,12 +1576,14 @@ DEV void row_load(int i, const T *x, const T *r, const T *u, const T *pp, const 
 }
 
 // the update of one row; adds r.u and r.r of the new residual
+// uc: the coarse correction of the row's preconditioned residual (zeros for
+// block Jacobi alone): the direction is updated with u + uc
 template <typename T>
 DEV void row_step(int i, double alpha, double beta, const RowVals<T> &v, T *x, T *r, T *u, T *pp, T *q, double &g,
-                  double &rr) {
+                  double &rr, const double uc[3], double rn[3]) {
   T rv[3], uv[3];
   for (int c = 0; c < 3; ++c) {
-    const T pn = (T)fma(beta, (double)v.p[c], (double)v.u[c]);
+    const T pn = (T)fma(beta, (double)v.p[c], (double)v.u[c] + uc[c]);
     const T sn = (T)fma(beta, (double)v.s[c], (double)v.w[c]);
     pp[3 * i + c] = pn;
     q[3 * i + c] = sn;
@@ -1522,6 +1596,7 @@ DEV void row_step(int i, double alpha, double beta, const RowVals<T> &v, T *x, T
     u[3 * i + c] = uv[c];
     g += (double)rv[c] * (double)uv[c];
     rr += (double)rv[c] * (double)rv[c];
+    rn[c] = (double)rv[c];
   }
 }
 
@@ -1539,19 +1614,56 @@ DEV int cg_step(const EnvDev &E, double bb, int it, double gam, double del, doub
   return 0;
 }
 
+// per-tile Z^T r of the rows' residual rv (row in body bi at xi; bi < 0 for
+// rows outside the bodies): per body, the butterfly of its six values over
+// each wavefront, then the four wavefront sums as (w0 + w1) + (w2 + w3):
+// part_z[slot * kCoarseM + 6 b + k].  Every thread of the 256-thread block
+// calls it.  sh: 4 * kCoarseM doubles.
+DEV void tile_zt(const EnvDev &E, int bi, const double xi[3], const double rv[3], double *sh, double *out) {
+  double q[6] = {0, 0, 0, 0, 0, 0};
+  if (bi >= 0) coarse_zt_x(E, bi, xi, rv, q);
+  const int wv = threadIdx.x / 64;
+  for (int b = 0; b < E.nbody; ++b) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      double v = (bi == b) ? q[k] : 0.0;
+      for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+      if ((threadIdx.x & 63) == 0) sh[wv * kCoarseM + 6 * b + k] = v;
+    }
+  }
+  __syncthreads();
+  const int n = 6 * E.nbody;
+  if ((int)threadIdx.x < n) {
+    const int k = threadIdx.x;
+    out[k] = (sh[k] + sh[kCoarseM + k]) + (sh[2 * kCoarseM + k] + sh[3 * kCoarseM + k]);
+  }
+}
+
 template <typename T>
 __global__ void k_pcg_init(WorldDev W, const EnvDev *envs, EnvState S, const Tile *tiles, T *x, T *r, T *u, T *pp,
-                           T *q, const T *Minv, double *part_g, double *part_rr) {
-  __shared__ double sh[32];
+                           T *q, const T *Minv, double *part_g, double *part_rr, double *part_z, int coarse) {
+  __shared__ double sh[4 * kCoarseM];
   Tile t = tiles[blockIdx.x];
   if (!active_env(S, t.env) || envs[t.env].fused) return;
   int i = t.start + threadIdx.x;
+  const bool mine = (int)threadIdx.x < t.count;
   double g = 0.0, rr = 0.0;
-  if ((int)threadIdx.x < t.count) row_init<T>(W, is_dof(W, S, i, t.env), i, x, r, u, pp, q, Minv, g, rr);
+  if (mine) row_init<T>(W, is_dof(W, S, i, t.env), i, x, r, u, pp, q, Minv, g, rr);
   quarter_sum2(g, rr, sh);
   if (threadIdx.x == 0) {
     part_g[tile_slot(envs, t)] = g;
     part_rr[tile_slot(envs, t)] = rr;
+  }
+  const EnvDev &E = envs[t.env];
+  if (coarse && E.nbody > 0) {
+    const int bi = mine ? W.vbody[i] : -1;
+    double xi[3] = {0.0, 0.0, 0.0}, rv[3] = {0.0, 0.0, 0.0};
+    if (bi >= 0)
+      for (int c = 0; c < 3; ++c) {
+        xi[c] = W.x[3 * (size_t)i + c];
+        rv[c] = (double)r[3 * (size_t)i + c];
+      }
+    tile_zt(E, bi, xi, rv, sh, part_z + (size_t)tile_slot(envs, t) * kCoarseM);
   }
 }
 
@@ -1577,11 +1689,16 @@ __global__ void k_pcg_env_init(const EnvDev *envs, EnvState S, const int *benv, 
 }
 
 // w = H u for live environments, partial u.w (delta) per tile
-template <typename T, bool WIDE>
+// CO: the two-level PCG is on (environments with a coarse factor take u + Z c)
+template <typename T, bool WIDE, bool CO>
 __global__ void __launch_bounds__(1024) k_spmv(WorldDev W, const EnvDev *envs, EnvState S, const Tile *tiles,
                                                const int *inc_off, const int *cr_cnt, const int *cr_col,
-                                               const T *cr_val, const T *u, T *w, const T *val, double *part_d) {
+                                               const T *cr_val, const T *u, T *w, const T *val, double *part_d,
+                                               const double *part_z) {
   __shared__ double sh[16];
+  // two-level PCG: the tiles' Z^T r (kZChunk tiles), E^-1, Z^T r and c
+  __shared__ double zs[CO ? kZChunk * kCoarseM : 1], es[CO ? kCoarseM * kCoarseM : 1];
+  __shared__ double zq[CO ? kCoarseM : 1], zc[CO ? kCoarseM : 1];
   Tile t = tiles[blockIdx.x];
   const int row = threadIdx.x / kLPR, l = threadIdx.x % kLPR;
   const int i = t.start + row;
@@ -1593,7 +1710,75 @@ __global__ void __launch_bounds__(1024) k_spmv(WorldDev W, const EnvDev *envs, E
   RowHead h = row_head(W, valid ? i : t.start, inc_off, cr_cnt);
   asm volatile("" : "+v"(h.base), "+v"(h.wdt), "+v"(h.cb), "+v"(h.cn), "+v"(st), "+v"(dn));
   if (st != ST_ACTIVE || dn) return;
-  double d = row_spmv<T, WIDE>(W, i, valid, l, h, cr_col, cr_val, u, w, val);
+  const EnvDev &E = envs[t.env];
+  double d;
+  if (CO && E.nbody > 0 && S.cok[t.env]) {
+    // c = E^-1 Z^T r from the tiles' Z^T r (tile order), then w = H u +
+    // (H Z) c at this row (H Z stored by k_coarse_hz; lane l < 3 takes
+    // component l, exchanged among the row's lanes) and delta with u + Z c.
+    // The tiles' Z^T r, E^-1, the row's body and its H Z entries of the
+    // first body are loaded ahead of the product and used after it.
+    const int m = 6 * E.nbody;
+    const int nz = min(E.vtile_count, kZChunk);
+    const int tz = threadIdx.x / kCoarseM, jz = threadIdx.x % kCoarseM;
+    const double pz = (tz < nz && jz < m) ? part_z[(size_t)(E.vtile_first + tz) * kCoarseM + jz] : 0.0;
+    const double pe =
+        (int)threadIdx.x < m * kCoarseM ? S.cinv[(size_t)t.env * (kCoarseM * kCoarseM) + threadIdx.x] : 0.0;
+    const int ri = valid ? i : t.start;
+    const int b = W.vbody[ri];
+    const T *hzp = (sizeof(T) == 4 ? (const T *)(const void *)W.hz32 : (const T *)(const void *)W.hz) +
+                   hz_index(ri, (l < 3 ? l : 0) * kCoarseM);
+    T hz0[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) hz0[k] = hzp[(size_t)k * kSlice];
+    double y[3];
+    row_product<T, StoredVec<T>, WIDE>(W, i, valid, l, h, StoredVec<T>{u}, val, cr_col, cr_val, y);
+    if (tz < kZChunk) zs[threadIdx.x] = pz;
+    if ((int)threadIdx.x < kCoarseM * kCoarseM) es[threadIdx.x] = pe;
+    __syncthreads();
+    if ((int)threadIdx.x < m) {
+      double q = 0.0;
+      for (int k = 0; k < nz; ++k) q += zs[k * kCoarseM + threadIdx.x];
+      for (int k = nz; k < E.vtile_count; ++k) q += part_z[(size_t)(E.vtile_first + k) * kCoarseM + threadIdx.x];
+      zq[threadIdx.x] = q;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < m) {
+      double c = 0.0;
+      for (int j = 0; j < m; ++j) c += es[threadIdx.x * kCoarseM + j] * zq[j];
+      zc[threadIdx.x] = c;
+      if (t.rel == 0) S.cc[(size_t)t.env * kCoarseM + threadIdx.x] = c;
+    }
+    __syncthreads();
+    if (t.rel == 0 && threadIdx.x == 0) {
+      double gz = 0.0;
+      for (int j = 0; j < m; ++j) gz += zq[j] * zc[j];
+      S.cgam[t.env] = gz;
+    }
+    double hc = 0.0;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) hc += (double)hz0[k] * zc[k];
+    for (int k = 6; k < m; ++k) hc += (double)hzp[(size_t)k * kSlice] * zc[k];
+    const int base = threadIdx.x & 63 & ~3;
+    const double h0 = __shfl(hc, base, 64), h1 = __shfl(hc, base + 1, 64), h2 = __shfl(hc, base + 2, 64);
+    d = 0.0;
+    if (valid) {
+      double uf[3] = {(double)u[3 * i], (double)u[3 * i + 1], (double)u[3 * i + 2]};
+      if (b >= 0) {
+        double o[3];
+        coarse_corr(E, b, W.x, i, zc, o);
+        for (int c = 0; c < 3; ++c) uf[c] = uf[c] + o[c];
+      }
+      const double hcc[3] = {h0, h1, h2};
+      for (int c = 0; c < 3; ++c) {
+        const double yc = y[c] + hcc[c];
+        if (l == c) w[3 * i + c] = (T)yc;
+        d += uf[c] * (double)(T)yc;
+      }
+    }
+  } else {
+    d = row_spmv<T, WIDE>(W, i, valid, l, h, cr_col, cr_val, u, w, val);
+  }
   d = rows_sum(d, sh);
   if (threadIdx.x == 0) part_d[tile_slot(envs, t)] = d;
 }
@@ -1660,10 +1845,11 @@ template <typename T>
 __global__ void k_pcg_update(WorldDev W, const EnvDev *envs, EnvState S, const Tile *tiles, int it,
                              const double *part_d, const double *part_g, const double *part_rr, double *part_g_new,
                              double *part_rr_new, T *x, T *r, T *u, T *pp, T *q, const T *w, const T *Minv,
-                             int *pending) {
+                             int *pending, double *part_z, int coarse) {
   __shared__ double sh[3 * TB];
   __shared__ double s_ab[2];
   __shared__ int s_done;
+  __shared__ double zc[kCoarseM];
   Tile t = tiles[blockIdx.x];
   // The row's vectors (row t.start for threads past the tile's rows) are
   // loaded together with the environment's state and are in flight while the
@@ -1677,8 +1863,24 @@ __global__ void k_pcg_update(WorldDev W, const EnvDev *envs, EnvState S, const T
   const int st = S.status[t.env], dn = S.pcg_done[t.env];
   const bool live = st == ST_ACTIVE && !dn;
   const EnvDev &E = envs[t.env];
+  // two-level PCG: the correction c of this iteration's u (stored by the
+  // product), r.u's share (Z^T r).c, the row's body and position, loaded
+  // with the rest
+  double cgam = 0.0, cpre = 0.0, xi[3] = {0.0, 0.0, 0.0};
+  int bi = -1;
+  if (coarse) {
+    cgam = S.cgam[t.env];
+    if ((int)threadIdx.x < kCoarseM) cpre = S.cc[(size_t)t.env * kCoarseM + threadIdx.x];
+    const int ri = mine ? i : t.start;
+    bi = mine ? W.vbody[ri] : -1;
+    for (int c = 0; c < 3; ++c) xi[c] = W.x[3 * (size_t)ri + c];
+  }
+  const bool co = coarse && E.nbody > 0 && S.cok[t.env];
+  if (!co) bi = -1;
   double gam, del, rr;
   env_sums3(part_g, part_d, part_rr, E, sh, gam, del, rr);
+  if (co) gam += cgam;
+  if (co && (int)threadIdx.x < kCoarseM) zc[threadIdx.x] = cpre;  // read after the barrier below
   if (threadIdx.x == 0 && !live) s_done = 1;
   if (threadIdx.x == 0 && live) {
     const int e = t.env, k = (it + 1) & 1;  // slot of iteration it - 1
@@ -1705,12 +1907,173 @@ __global__ void k_pcg_update(WorldDev W, const EnvDev *envs, EnvState S, const T
   __syncthreads();
   if (s_done) return;
   double g = 0.0, rr2 = 0.0;
-  if (mine) row_step<T>(i, s_ab[0], s_ab[1], v, x, r, u, pp, q, g, rr2);
+  double uc[3] = {0.0, 0.0, 0.0}, rn[3] = {0.0, 0.0, 0.0};
+  if (bi >= 0) coarse_corr_x(E, bi, xi, zc, uc);
+  if (mine) row_step<T>(i, s_ab[0], s_ab[1], v, x, r, u, pp, q, g, rr2, uc, rn);
   quarter_sum2(g, rr2, sh);
   if (threadIdx.x == 0) {
     part_g_new[tile_slot(envs, t)] = g;
     part_rr_new[tile_slot(envs, t)] = rr2;
   }
+  if (co) tile_zt(E, bi, xi, rn, sh, part_z + (size_t)tile_slot(envs, t) * kCoarseM);
+}
+
+// ---------------------------------------------------------------------------
+// Coarse matrix E = Z^T H Z of the two-level PCG, at the assembled H: per tile
+// (one row per thread) and per column body bb, Y = (H Z)_i restricted to the
+// columns of bb (3 x 6, over the row's sliced-ELL slots and merged contact
+// blocks, FP64), then Z_i^T Y (6 x 6) summed over the tile's rows of each body
+// b2 into e_tile[slot][6 b2 + r][6 bb + c].  Rows outside the bodies add zero.
+// ---------------------------------------------------------------------------
+DEV void coarse_block_acc(const double *B, int stride, const EnvDev &E, int b, const double *x, int j,
+                          double Y[3][6]) {
+  const double is = 1.0 / E.cscale[b];
+  const double d[3] = {x[3 * j] - E.cb[b][0], x[3 * j + 1] - E.cb[b][1], x[3 * j + 2] - E.cb[b][2]};
+  // columns of R_j = -[d]x / s: e_0 x d, e_1 x d, e_2 x d, over s
+  const double R[3][3] = {{0.0, d[2] * is, -d[1] * is}, {-d[2] * is, 0.0, d[0] * is}, {d[1] * is, -d[0] * is, 0.0}};
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const double b0 = B[(3 * r) * stride], b1 = B[(3 * r + 1) * stride], b2 = B[(3 * r + 2) * stride];
+    Y[r][0] += b0;
+    Y[r][1] += b1;
+    Y[r][2] += b2;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) Y[r][3 + c] += b0 * R[0][c] + b1 * R[1][c] + b2 * R[2][c];
+  }
+}
+
+__global__ void __launch_bounds__(256) k_coarse_hz(WorldDev W, const EnvDev *envs, EnvState S, const Tile *tiles,
+                                                   const int *inc_off, const int *cr_cnt, const int *cr_col,
+                                                   const double *cr_val, double *e_tile, int mixed) {
+  __shared__ double sh[4 * 36];
+  Tile t = tiles[blockIdx.x];
+  const EnvDev &E = envs[t.env];
+  if (!active_env(S, t.env) || E.nbody == 0) return;
+  const int i = t.start + threadIdx.x;
+  const bool mine = (int)threadIdx.x < t.count;
+  const int bi = mine ? W.vbody[i] : -1;
+  RowHead h{0, 0, 0, 0};
+  if (mine) h = row_head(W, i, inc_off, cr_cnt);
+  double di[3] = {0, 0, 0}, isi = 0.0;
+  if (bi >= 0) {
+    isi = 1.0 / E.cscale[bi];
+    for (int k = 0; k < 3; ++k) di[k] = W.x[3 * i + k] - E.cb[bi][k];
+  }
+  double *out = e_tile + (size_t)tile_slot(envs, t) * (kCoarseM * kCoarseM);
+  for (int bb = 0; bb < E.nbody; ++bb) {
+    double Y[3][6] = {{0, 0, 0, 0, 0, 0}, {0, 0, 0, 0, 0, 0}, {0, 0, 0, 0, 0, 0}};
+    if (mine) {
+      const int lane = i % kSlice;
+      const double *vp = W.val + (size_t)(h.base / kSlice) * (9 * kSlice) + lane;
+      for (int k = 0; k < h.wdt; ++k) {
+        const int j = W.col[h.base + lane + k * kSlice];
+        if (W.vbody[j] == bb) coarse_block_acc(vp + (size_t)k * (9 * kSlice), kSlice, E, bb, W.x, j, Y);
+      }
+      for (int k = 0; k < h.cn; ++k) {
+        const int j = cr_col[h.cb + k];
+        if (W.vbody[j] == bb) coarse_block_acc(cr_val + 9 * (size_t)(h.cb + k), 1, E, bb, W.x, j, Y);
+      }
+      // (H Z)_i for the update of the two-level PCG (every row: a dof row
+      // outside the bodies may neighbour them)
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 6; ++c) {
+          const size_t o = hz_index(i, r * kCoarseM + 6 * bb + c);
+          W.hz[o] = Y[r][c];
+          if (mixed) W.hz32[o] = (float)Y[r][c];
+        }
+    }
+    // C = Z_i^T Y: the rows of Y, then (d_i x Y_c) / s for each column c
+    double C[36];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const double y0 = Y[0][c], y1 = Y[1][c], y2 = Y[2][c];
+      C[c] = y0;
+      C[6 + c] = y1;
+      C[12 + c] = y2;
+      C[18 + c] = (di[1] * y2 - di[2] * y1) * isi;
+      C[24 + c] = (di[2] * y0 - di[0] * y2) * isi;
+      C[30 + c] = (di[0] * y1 - di[1] * y0) * isi;
+    }
+    for (int b2 = 0; b2 < E.nbody; ++b2) {
+      double v[36];
+#pragma unroll
+      for (int k = 0; k < 36; ++k) v[k] = (bi == b2) ? C[k] : 0.0;
+      const double sum = tile_sums<36>(v, sh);
+      if ((int)threadIdx.x < 36) {
+        const int r = threadIdx.x / 6, c = threadIdx.x % 6;
+        out[(6 * b2 + r) * kCoarseM + 6 * bb + c] = sum;
+      }
+    }
+  }
+}
+
+// E from the tiles (tile order), symmetrised, Cholesky-factored and inverted
+// (E^-1 = L^-T L^-1) in LDS by one 64-thread block per environment; cok = 0
+// when a pivot is not positive (the environment then runs block Jacobi alone)
+__global__ void __launch_bounds__(64) k_coarse_factor(const EnvDev *envs, EnvState S, const int *benv,
+                                                      const double *e_tile) {
+  constexpr int M = kCoarseM;
+  __shared__ double A[M * M], Li[M * M];
+  __shared__ int bad;
+  const int e = benv[blockIdx.x];
+  const EnvDev &E = envs[e];
+  const int m = 6 * E.nbody, tid = threadIdx.x;
+  if (S.status[e] != ST_ACTIVE || m == 0) {
+    if (tid == 0) S.cok[e] = 0;
+    return;
+  }
+  for (int qd = tid; qd < m * m; qd += 64) {
+    const int r = qd / m, c = qd % m;
+    double a = 0.0;
+    for (int k = 0; k < E.vtile_count; ++k) a += e_tile[(size_t)(E.vtile_first + k) * (M * M) + r * M + c];
+    A[r * M + c] = a;
+  }
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  for (int qd = tid; qd < m * m; qd += 64) {
+    const int r = qd / m, c = qd % m;
+    if (r < c) {
+      const double a = 0.5 * (A[r * M + c] + A[c * M + r]);
+      A[r * M + c] = a;
+      A[c * M + r] = a;
+    }
+  }
+  __syncthreads();
+  for (int k = 0; k < m; ++k) {
+    if (tid == 0) {
+      const double p = A[k * M + k];
+      if (!(p > 0.0)) bad = 1;
+      A[k * M + k] = p > 0.0 ? sqrt(p) : 1.0;
+    }
+    __syncthreads();
+    for (int r = k + 1 + tid; r < m; r += 64) A[r * M + k] /= A[k * M + k];
+    __syncthreads();
+    for (int qd = tid; qd < m * m; qd += 64) {
+      const int r = qd / m, c = qd % m;
+      if (c > k && c <= r) A[r * M + c] -= A[r * M + k] * A[c * M + k];
+    }
+    __syncthreads();
+  }
+  // L^-1 column by column (forward substitution of e_j)
+  for (int j = tid; j < m; j += 64)
+    for (int r = 0; r < m; ++r) {
+      if (r < j) {
+        Li[r * M + j] = 0.0;
+        continue;
+      }
+      double a = (r == j) ? 1.0 : 0.0;
+      for (int k = j; k < r; ++k) a -= A[r * M + k] * Li[k * M + j];
+      Li[r * M + j] = a / A[r * M + r];
+    }
+  __syncthreads();
+  double *inv = S.cinv + (size_t)e * (M * M);
+  for (int qd = tid; qd < m * m; qd += 64) {
+    const int r = qd / m, c = qd % m;
+    double a = 0.0;
+    for (int k = (r > c ? r : c); k < m; ++k) a += Li[k * M + r] * Li[k * M + c];
+    inv[r * M + c] = a;
+  }
+  if (tid == 0) S.cok[e] = bad ? 0 : 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -1766,7 +2129,9 @@ DEV int env_iterate(const WorldDev &W, const EnvDev &E, double bb, int it, doubl
       if (i < r1) {
         RowVals<T> v;
         row_load<T>(i, x, r, u, pp, q, w, Minv, v);
-        row_step<T>(i, alpha, beta, v, x, r, u, pp, q, g, rri);
+        const double zero3[3] = {0.0, 0.0, 0.0};
+        double rn[3];
+        row_step<T>(i, alpha, beta, v, x, r, u, pp, q, g, rri, zero3, rn);
       }
       tile_sums2(g, rri, sh[1], E, (base - r0) / TB, part_g[(it + 1) & 1], part_rr[(it + 1) & 1]);
     }
@@ -2662,13 +3027,13 @@ void elastic(hipStream_t s, const WorldDev &W, const EnvDev *, const EnvState &S
   if (B.n_tt)
     hipExtLaunchKernelGGL(k_elastic, dim3(B.n_tt), dim3(TB), 0, s, start, nullptr, 0, W, S, B.ttiles);
   else if (start)
-    hipEventRecord(start, s);
+    (void)hipEventRecord(start, s);
 }
 
 void assemble(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B, const Lists &L,
               int mixed, hipEvent_t stop) {
   if (!B.n_vt) {
-    if (stop) hipEventRecord(stop, s);
+    if (stop) (void)hipEventRecord(stop, s);
     return;
   }
   IPC_LAUNCH(k_assemble_rows, B.n_vt, TB, s)(W, E, S, B.vtiles, L.inc_off, L.inc_ent, L.ce_g, L.ce_H, mixed);
@@ -2681,11 +3046,19 @@ void pcg_init(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState 
   IPC_LAUNCH(k_fill_int, 1, 64, s)(pending, 1, 0);
   if (B.n_vt && !mixed)
     IPC_LAUNCH(k_pcg_init<double>, B.n_vt, TB, s)(W, E, S, B.vtiles, W.p, W.r, W.z, W.pp, W.q, W.Minv, L.part_b0,
-                                                  L.part_c0);
+                                                  L.part_c0, L.part_z, L.coarse);
   if (B.n_vt && mixed)
     IPC_LAUNCH(k_pcg_init<float>, B.n_vt, TB, s)(W, E, S, B.vtiles, W.p32, W.r32, W.z32, W.pp32, W.q32, W.Minv32,
-                                                 L.part_b0, L.part_c0);
+                                                 L.part_b0, L.part_c0, L.part_z, L.coarse);
   IPC_LAUNCH(k_pcg_env_init, nblk(B.n_envs, 64), 64, s)(E, S, B.envs, B.n_envs, L.part_c0, pending);
+}
+
+void coarse_setup(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, const Batch &B,
+                  const Lists &L, int mixed) {
+  if (!B.n_vt) return;
+  IPC_LAUNCH(k_coarse_hz, B.n_vt, TB, s)(W, E, S, B.vtiles, L.inc_off, L.cr_cnt, L.cr_col, L.cr_val, L.e_tile,
+                                         mixed);
+  IPC_LAUNCH(k_coarse_factor, B.n_envs, 64, s)(E, S, B.envs, L.e_tile);
 }
 
 void live_tiles(hipStream_t s, const EnvState &S, const Batch &B, Lists &L, Tile *out, int *flag, int *offs) {
@@ -2732,13 +3105,22 @@ void pcg_iter_t(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvStat
   // kernel itself, as a profiler sees them; no event packets around it)
   hipEvent_t e0 = ev ? ev[0] : nullptr, e1 = ev ? ev[1] : nullptr, e2 = ev ? ev[2] : nullptr,
              e3 = ev ? ev[3] : nullptr;
-  // launches of a few tiles are latency-bound: issue each lane's slots four at a time
-  if (n_tiles <= L.wide_tiles)
-    hipExtLaunchKernelGGL((k_spmv<T, true>), dim3(n_tiles), dim3(nt), 0, s, e0, e1, 0, W, E, S, tiles, L.inc_off,
-                          L.cr_cnt, L.cr_col, v.cr_val, (const T *)v.u, v.w, v.val, L.part_a);
+  // launches of a few tiles are latency-bound: issue each lane's slots four
+  // at a time (not with the two-level PCG, whose loads ahead of the product
+  // leave no registers for it)
+  const bool wide = n_tiles <= L.wide_tiles;
+  auto spmv = [&](auto kern) {
+    hipExtLaunchKernelGGL(kern, dim3(n_tiles), dim3(nt), 0, s, e0, e1, 0, W, E, S, tiles, L.inc_off, L.cr_cnt,
+                          L.cr_col, v.cr_val, (const T *)v.u, v.w, v.val, L.part_a, (const double *)L.part_z);
+  };
+  if (L.coarse)
+    spmv(k_spmv<T, false, true>);
   else
-    hipExtLaunchKernelGGL((k_spmv<T, false>), dim3(n_tiles), dim3(nt), 0, s, e0, e1, 0, W, E, S, tiles, L.inc_off,
-                          L.cr_cnt, L.cr_col, v.cr_val, (const T *)v.u, v.w, v.val, L.part_a);
+    wide ? spmv(k_spmv<T, true, false>) : spmv(k_spmv<T, false, false>);
+  if (ev) {
+    const hipError_t le = hipGetLastError();
+    if (le != hipSuccess) throw std::runtime_error(std::string("timed product launch: ") + hipGetErrorString(le));
+  }
   // the iteration's algorithmic bytes (product: counter 0 for launches of at
   // most kWideTiles tiles, 1 for larger ones; whole iteration: counter 2),
   // counted between the two kernels, outside both timings
@@ -2747,7 +3129,7 @@ void pcg_iter_t(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvStat
                                                L.prof + 2);
   hipExtLaunchKernelGGL(k_pcg_update<T>, dim3(n_tiles), dim3(TB), 0, s, e2, e3, 0, W, E, S, tiles, it,
                         (const double *)L.part_a, (const double *)g_cur, (const double *)rr_cur, g_new, rr_new, v.x,
-                        v.r, v.u, v.pp, v.q, (const T *)v.w, v.Minv, pending);
+                        v.r, v.u, v.pp, v.q, (const T *)v.w, v.Minv, pending, L.part_z, L.coarse);
 }
 
 void pcg_iter(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvState &S, Lists &L, int it, int *pending,

@@ -16,6 +16,10 @@ namespace ipcw {
 constexpr int kTile = 256;     // elements per work tile (one 256-thread block)
 constexpr int kSlice = 64;     // rows per sliced-ELL slice (one wavefront)
 constexpr int kFusedRows = 8192;  // environments up to this many rows solve in one workgroup
+// Two-level PCG: the rigid motions (3 translations, 3 rotations) of up to
+// kCoarseBodies bodies per environment span the coarse space
+constexpr int kCoarseBodies = 4;
+constexpr int kCoarseM = 6 * kCoarseBodies;
 
 enum Status { ST_IDLE = 0, ST_ACTIVE = 1, ST_CONVERGED = 2, ST_FAILED = 3 };
 // Phase of an environment in one round of the decoupled schedule: PH_ITER
@@ -60,6 +64,11 @@ struct EnvDev {
   int inv_filter;                // 1: the inversion filter bounds the line search
   int adapt_kappa;               // 1: kappa adapts to the least active-pair distance
   int nnzb;                      // stored 3x3 blocks of the elastic pattern (measurement)
+  // coarse space of the PCG: bodies (connected sets of free vertices), each
+  // with a reference point and a length that scales its rotation columns
+  int nbody;
+  double cb[kCoarseBodies][3];
+  double cscale[kCoarseBodies];
 };
 
 // Per-environment solver state (device arrays indexed by slot).
@@ -88,6 +97,11 @@ struct EnvState {
   int *phase;
   // PCG step length and r.u of the last two iterations (slot = iteration & 1)
   double *cg_a0, *cg_a1, *cg_g0, *cg_g1;
+  // two-level PCG: E^-1 of the coarse matrix Z^T H Z [kCoarseM^2 per env],
+  // the current coarse correction c = E^-1 Z^T r [kCoarseM per env], its
+  // contribution (Z^T r).c to r.u, and whether the factorisation succeeded
+  double *cinv, *cc, *cgam;
+  int *cok;
 };
 
 // Flat device arrays of the world (element-indexed).
@@ -96,6 +110,12 @@ struct WorldDev {
   double *X, *x, *v, *xn, *xh, *p, *g, *r, *z, *pp, *w, *q, *mass, *Minv, *e_v, *lam;
   float *r32, *z32, *pp32, *w32, *q32, *p32, *Minv32;
   int *kin, *venv, *vt_beg, *vt_end, *row_nnz;
+  int *vbody;  // coarse body of a free vertex within its environment, -1 for others
+  // (H Z)_i of the two-level PCG, 3 x kCoarseM per vertex, FP64 and FP32
+  // copies, sliced like the ELL values: entry (r, k) of row i at
+  // ((i / kSlice) 3 kCoarseM + r kCoarseM + k) kSlice + i % kSlice
+  double *hz;
+  float *hz32;
   // per slice (vertex / 64)
   int *slice_pos, *slice_w;
   // per sliced-ELL position

@@ -31,6 +31,7 @@ IPC_TUNE_ADMIT_FAULTS = 6
 IPC_TUNE_ASYNC = 7
 IPC_TUNE_WIDE_TILES = 8
 IPC_TUNE_POLL_BLOCK = 9
+IPC_TUNE_COARSE = 10
 IPC_FAIL_ADMIT = 6
 FAIL_REASONS = {0: "none", 1: "maxit", 2: "nonfinite", 3: "line-search", 4: "dirichlet"}
 

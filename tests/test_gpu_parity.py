@@ -279,6 +279,8 @@ def test_pcg_paths_same_bits(precision):
     per-environment PCG reduce in the same order: the trajectories must be bitwise identical."""
     scs = [S.soft_cube_drop(cells=3, edge=0.05, height=0.003 + 0.001 * i, seed=i) for i in range(3)]
     runs = []
+    # the per-environment kernels are block Jacobi only: compare with the two-level PCG off
+    G.ipc_set_tuning(G.IPC_TUNE_COARSE, 0)
     for tail, fused in ((0, 0), (1 << 30, 0), (0, 1)):
         G.ipc_set_tuning(G.IPC_TUNE_TAIL_TILES, tail)
         G.ipc_set_tuning(G.IPC_TUNE_FUSED_PCG, fused)
@@ -291,6 +293,7 @@ def test_pcg_paths_same_bits(precision):
             G.ipc_destroy_scene(g)
     G.ipc_set_tuning(G.IPC_TUNE_TAIL_TILES, 0)
     G.ipc_set_tuning(G.IPC_TUNE_FUSED_PCG, 0)
+    G.ipc_set_tuning(G.IPC_TUNE_COARSE, 1)
     for k in (1, 2):
         for a, b in zip(runs[0], runs[k]):
             assert np.array_equal(a, b), k
