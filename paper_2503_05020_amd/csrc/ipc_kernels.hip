@@ -1320,6 +1320,35 @@ DEV double tile_sums(double v[N], double *sh) {
   return out;
 }
 
+// sums of v[0..8) over the 256 threads of a tile (one row each): a
+// transposed butterfly over each wavefront (at the exchanges 32, 16 and 8
+// each lane keeps half of its values, adds its partner's copies of them and
+// hands over the other half; the one value left goes through the exchanges
+// 4, 2, 1), then the four wavefront sums as (w0 + w1) + (w2 + w3).  Thread
+// k < 8 gets sum k (others 0).  10 exchanges instead of the full butterfly's
+// 48.  Every thread of the block calls it.  sh: 32 doubles.
+DEV double tile_sums8(const double v[8], double *sh) {
+  const int ln = threadIdx.x & 63;
+  const bool h32 = ln & 32, h16 = ln & 16, h8 = ln & 8;
+  double a[4], b[2];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) a[j] = (h32 ? v[j + 4] : v[j]) + __shfl_xor(h32 ? v[j] : v[j + 4], 32, 64);
+#pragma unroll
+  for (int j = 0; j < 2; ++j) b[j] = (h16 ? a[j + 2] : a[j]) + __shfl_xor(h16 ? a[j] : a[j + 2], 16, 64);
+  double c = (h8 ? b[1] : b[0]) + __shfl_xor(h8 ? b[0] : b[1], 8, 64);
+  for (int m = 4; m > 0; m >>= 1) c += __shfl_xor(c, m, 64);
+  const int wv = threadIdx.x / 64;
+  if ((ln & 7) == 0) sh[wv * 8 + (h32 ? 4 : 0) + (h16 ? 2 : 0) + (h8 ? 1 : 0)] = c;
+  __syncthreads();
+  double out = 0.0;
+  if (threadIdx.x < 8) {
+    const int k = threadIdx.x;
+    out = (sh[k] + sh[8 + k]) + (sh[16 + k] + sh[24 + k]);
+  }
+  __syncthreads();
+  return out;
+}
+
 // the vector a product reads: stored, or the next direction formed on the fly
 template <typename T>
 struct StoredVec {
@@ -1790,19 +1819,28 @@ __global__ void __launch_bounds__(1024) k_spmv(WorldDev W, const EnvDev *envs, E
 // contact blocks, one read of u and one write of w per row), *iter += the
 // whole iteration's: the product's blocks plus per row the preconditioner
 // block and eight vector accesses of three values, N (9 s + 4) + n 9 s +
-// 24 n s for N blocks, n rows, s bytes per value.
+// 24 n s for N blocks, n rows, s bytes per value.  With the two-level PCG
+// (m = 6 bodies) the product also reads per row its 3 m entries of H Z and
+// its body (3 m s + 4) and per row of a body its position (24); the update
+// reads body and position again (4 + 24) and writes m partials per tile (8 m).
 template <typename T>
-__global__ void k_pcg_bytes(WorldDev W, EnvState S, const Tile *tiles, const int *cr_cnt, unsigned long long *spmv,
-                            unsigned long long *iter) {
+__global__ void k_pcg_bytes(WorldDev W, const EnvDev *envs, EnvState S, const Tile *tiles, const int *cr_cnt,
+                            int coarse, unsigned long long *spmv, unsigned long long *iter) {
   __shared__ double sh[2 * TB];
   Tile t = tiles[blockIdx.x];
   if (S.status[t.env] != ST_ACTIVE || S.pcg_done[t.env]) return;
-  double b = 0.0, c = 0.0;
+  const int m = coarse && S.cok[t.env] ? 6 * envs[t.env].nbody : 0;
+  double b = 0.0, c = threadIdx.x == 0 ? 8.0 * m : 0.0;
   if ((int)threadIdx.x < t.count) {
     const int i = t.start + threadIdx.x;
     const double blk = (double)(W.row_nnz[i] + cr_cnt[i]) * (9.0 * sizeof(T) + 4.0);
     b = blk + 6.0 * sizeof(T);
-    c = blk + 9.0 * sizeof(T) + 24.0 * sizeof(T);
+    c += blk + 9.0 * sizeof(T) + 24.0 * sizeof(T);
+    if (m) {
+      const double pos = W.vbody[i] >= 0 ? 24.0 : 0.0;
+      b += 3.0 * m * sizeof(T) + 4.0 + pos;
+      c += 3.0 * m * sizeof(T) + 8.0 + 2.0 * pos;
+    }
   }
   sh[threadIdx.x] = b;
   sh[TB + threadIdx.x] = c;
@@ -1910,12 +1948,30 @@ __global__ void k_pcg_update(WorldDev W, const EnvDev *envs, EnvState S, const T
   double uc[3] = {0.0, 0.0, 0.0}, rn[3] = {0.0, 0.0, 0.0};
   if (bi >= 0) coarse_corr_x(E, bi, xi, zc, uc);
   if (mine) row_step<T>(i, s_ab[0], s_ab[1], v, x, r, u, pp, q, g, rr2, uc, rn);
-  quarter_sum2(g, rr2, sh);
-  if (threadIdx.x == 0) {
-    part_g_new[tile_slot(envs, t)] = g;
-    part_rr_new[tile_slot(envs, t)] = rr2;
+  const int slot = tile_slot(envs, t);
+  if (!co) {
+    quarter_sum2(g, rr2, sh);
+    if (threadIdx.x == 0) {
+      part_g_new[slot] = g;
+      part_rr_new[slot] = rr2;
+    }
+    return;
   }
-  if (co) tile_zt(E, bi, xi, rn, sh, part_z + (size_t)tile_slot(envs, t) * kCoarseM);
+  // two-level PCG: Z^T r of the new residual per body, reduced together
+  // with r.u and r.r (with the first body)
+  double zr[6] = {0, 0, 0, 0, 0, 0};
+  if (bi >= 0) coarse_zt_x(E, bi, xi, rn, zr);
+  for (int b = 0; b < E.nbody; ++b) {
+    double vals[8];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) vals[k] = bi == b ? zr[k] : 0.0;
+    vals[6] = b == 0 ? g : 0.0;
+    vals[7] = b == 0 ? rr2 : 0.0;
+    const double sum = tile_sums8(vals, sh);
+    if ((int)threadIdx.x < 6) part_z[(size_t)slot * kCoarseM + 6 * b + threadIdx.x] = sum;
+    if (b == 0 && threadIdx.x == 6) part_g_new[slot] = sum;
+    if (b == 0 && threadIdx.x == 7) part_rr_new[slot] = sum;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -3125,8 +3181,8 @@ void pcg_iter_t(hipStream_t s, const WorldDev &W, const EnvDev *E, const EnvStat
   // most kWideTiles tiles, 1 for larger ones; whole iteration: counter 2),
   // counted between the two kernels, outside both timings
   if (count)
-    IPC_LAUNCH(k_pcg_bytes<T>, n_tiles, TB, s)(W, S, tiles, L.cr_cnt, L.prof + (n_tiles > kWideTiles ? 1 : 0),
-                                               L.prof + 2);
+    IPC_LAUNCH(k_pcg_bytes<T>, n_tiles, TB, s)(W, E, S, tiles, L.cr_cnt, L.coarse,
+                                               L.prof + (n_tiles > kWideTiles ? 1 : 0), L.prof + 2);
   hipExtLaunchKernelGGL(k_pcg_update<T>, dim3(n_tiles), dim3(TB), 0, s, e2, e3, 0, W, E, S, tiles, it,
                         (const double *)L.part_a, (const double *)g_cur, (const double *)rr_cur, g_new, rr_new, v.x,
                         v.r, v.u, v.pp, v.q, (const T *)v.w, v.Minv, pending, L.part_z, L.coarse);
