@@ -302,6 +302,21 @@ def soft_cube_drop(seed: int = 0, cells: int = 5, edge: float = 0.1, height: flo
     return b.build(static_motion(1), [[0.0, 0.0, -9.81]], **params)
 
 
+def stacked_cubes(n: int, cells: int = 2, edge: float = 0.03, gap: float = 0.004, **params):
+    """n soft cubes (cells^3 voxels each, E = 1e5 Pa, nu = 0.4, rho = 1000) stacked along z with
+    `gap` between them and above a kinematic ground plane, each shifted 2 mm along x from the one
+    below; gravity 9.81.  n separate bodies: a scene with several connected sets of free vertices."""
+    b = _Builder()
+    h = edge / cells
+    for k in range(n):
+        origin = (-edge / 2 + 0.002 * k, -edge / 2, gap + k * (edge + gap))
+        v, t = voxel_tet_mesh(np.ones((cells,) * 3, bool), h, origin)
+        b.add_body(v, t, 1e5, 0.4, 1000.0)
+    gv, gt = ground_plane()
+    b.add_kinematic_mesh(gv, gt, 0)
+    return b.build(static_motion(1), [[0.0, 0.0, -9.81]], **params)
+
+
 def _slab(h: float = 0.004, cells=(2, 4, 10)):
     """Finger slab: cells along (closing, width, length) = 8 x 16 x 40 mm at 4 mm."""
     v, t = voxel_tet_mesh(np.ones(cells, bool), h, (0.0, 0.0, 0.0))

@@ -21,18 +21,6 @@ def say(*a):
     print(*a, flush=True)
 
 
-def stacked_cubes(n, cells=2, edge=0.03, gap=0.004, **params):
-    """n soft cubes stacked along z with small gaps, over a kinematic ground."""
-    b = S._Builder()
-    h = edge / cells
-    for k in range(n):
-        v, t = S.voxel_tet_mesh(np.ones((cells,) * 3, bool), h, (-edge / 2 + 0.002 * k, -edge / 2, gap + k * (edge + gap)))
-        b.add_body(v, t, 1e5, 0.4, 1000.0)
-    gv, gt = S.ground_plane()
-    b.add_kinematic_mesh(gv, gt, 0)
-    return b.build(S.static_motion(1), [[0.0, 0.0, -9.81]], **params)
-
-
 def _set_coarse(on):
     G.ipc_set_tuning(G.IPC_TUNE_COARSE, int(on))
 
@@ -46,7 +34,7 @@ def _coarse_back_on():
 @pytest.mark.parametrize("nbodies", [1, 2, 5])
 def test_direction_matches_oracle(nbodies):
     say("two-level direction", nbodies)
-    sc = stacked_cubes(nbodies)
+    sc = S.stacked_cubes(nbodies)
     g = G.ipc_create_scene(sc, pcg_rel_tol=1e-8)
     o = O.Scene(sc, pcg_rel_tol=1e-8)
     for _ in range(4):
@@ -94,7 +82,7 @@ def test_trajectories_agree_and_iterations_drop():
 
 def test_alone_equals_batch_with_bodies():
     """Each environment's coarse space is its own: alone and in a batch give the same bits."""
-    scs = [stacked_cubes(n) for n in (1, 2, 5)]
+    scs = [S.stacked_cubes(n) for n in (1, 2, 5)]
     alone = []
     for sc in scs:
         g = G.ipc_create_scene(sc)
