@@ -416,8 +416,20 @@ double ipc_debug_energy(ipc_scene s, const double *x);
 /* y = H v with H the PSD-projected Hessian at x (kinematic rows: identity). */
 int ipc_debug_hessian_apply(ipc_scene s, const double *x, const double *v, double *y);
 
-/* Newton search direction at x (solves H p = -g with block-Jacobi PCG). */
+/* Newton search direction at x (solves H p = -g with the world's PCG: the
+ * two-level one unless IPC_TUNE_COARSE is 0, then block Jacobi alone). */
 int ipc_debug_newton_dir(ipc_scene s, const double *x, double *p, int64_t *pcg_iters);
+
+/* Coarse space of the two-level PCG as built at creation (a utility for tests;
+ * no passage of the paper defines it): vbody[n_verts] receives each vertex's
+ * body (0 .. nbody-1; -1 for kinematic vertices and free vertices outside the
+ * bodies), frame[4 * nbody] each body's reference point and size (x, y, z, s:
+ * the rest centroid of its vertices, summed in vertex order, and the largest
+ * rest distance from it).  Either pointer may be null; frame must hold
+ * 4 * IPC_COARSE_BODIES doubles.  Returns nbody (0 .. IPC_COARSE_BODIES) or
+ * a negative error code. */
+#define IPC_COARSE_BODIES 4
+int ipc_debug_bodies(ipc_scene s, int32_t *vbody, double *frame);
 
 /* CCD step bound min(1, additive-CCD time of impact) over the sweep x -> x+p. */
 double ipc_debug_ccd_bound(ipc_scene s, const double *x, const double *p);

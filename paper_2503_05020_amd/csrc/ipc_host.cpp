@@ -3075,6 +3075,22 @@ int64_t ipc_debug_active(ipc_scene s, const double *x, int32_t *out, double *d2,
   }
 }
 
+int ipc_debug_bodies(ipc_scene s, int32_t *vbody, double *frame) {
+  return guarded([&]() {
+    if (!s) throw ApiError(IPC_E_ARG, "bad arguments");
+    static_assert(ipcw::kCoarseBodies == IPC_COARSE_BODIES, "coarse body count");
+    const HostScene &H = *s->host;
+    if (vbody)
+      for (int i = 0; i < H.nv; ++i) vbody[i] = H.vbody[i];
+    if (frame)
+      for (int b = 0; b < H.nbody; ++b) {
+        for (int k = 0; k < 3; ++k) frame[4 * b + k] = H.cb[b][k];
+        frame[4 * b + 3] = H.cscale[b];
+      }
+    return H.nbody;
+  });
+}
+
 int ipc_debug_begin_step(ipc_scene s, double *x_start) {
   return guarded([&]() {
     if (!s) throw ApiError(IPC_E_ARG, "bad arguments");

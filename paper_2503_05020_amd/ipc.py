@@ -32,6 +32,7 @@ IPC_TUNE_ASYNC = 7
 IPC_TUNE_WIDE_TILES = 8
 IPC_TUNE_POLL_BLOCK = 9
 IPC_TUNE_COARSE = 10
+IPC_COARSE_BODIES = 4
 IPC_FAIL_ADMIT = 6
 FAIL_REASONS = {0: "none", 1: "maxit", 2: "nonfinite", 3: "line-search", 4: "dirichlet"}
 
@@ -68,7 +69,7 @@ class ipc_step_info(C.Structure):
 EXPORTS = [
     "ipc_create_scene", "ipc_step", "ipc_step_batch", "ipc_get_state", "ipc_set_state", "ipc_destroy_scene",
     "ipc_last_error", "ipc_scene_sizes", "ipc_debug_candidates", "ipc_debug_active", "ipc_debug_begin_step",
-    "ipc_debug_gradient", "ipc_debug_energy", "ipc_debug_hessian_apply", "ipc_debug_newton_dir",
+    "ipc_debug_gradient", "ipc_debug_energy", "ipc_debug_hessian_apply", "ipc_debug_newton_dir", "ipc_debug_bodies",
     "ipc_debug_ccd_bound", "ipc_debug_classify", "ipc_debug_pair_barrier", "ipc_debug_tet_elastic",
     "ipc_debug_accd", "ipc_debug_inversion_bound", "ipc_debug_tet_first_root", "ipc_ccd_bound_pairs",
     "ipc_ccd_bound_pairs_noalloc", "ipc_grasp_metrics", "ipc_hold_group", "ipc_set_gravity", "ipc_contact_forces",
@@ -138,6 +139,7 @@ def lib():
     L.ipc_debug_energy.restype = C.c_double
     L.ipc_debug_hessian_apply.argtypes = [vp, _dp, _dp, _dp]
     L.ipc_debug_newton_dir.argtypes = [vp, _dp, _dp, C.POINTER(C.c_int64)]
+    L.ipc_debug_bodies.argtypes = [vp, _ip, _dp]
     L.ipc_debug_ccd_bound.argtypes = [vp, _dp, _dp]
     L.ipc_debug_ccd_bound.restype = C.c_double
     L.ipc_debug_classify.argtypes = [C.c_int32, C.c_int64, _dp, _ip, _dp]
@@ -453,6 +455,15 @@ def ipc_debug_newton_dir(scene, x):
     it = C.c_int64()
     _check(lib().ipc_debug_newton_dir(scene.h, _d(_f64(x)), _d(p), C.byref(it)))
     return p, it.value
+
+
+def ipc_debug_bodies(scene):
+    """Per-vertex body of the two-level PCG's coarse space and each body's (x, y, z, size)."""
+    vbody = np.zeros(scene.nv, np.int32)
+    frame = np.zeros((IPC_COARSE_BODIES, 4))
+    n = lib().ipc_debug_bodies(scene.h, _i(vbody), _d(frame))
+    _check(n)
+    return vbody, frame[:n]
 
 
 def ipc_debug_ccd_bound(scene, x, p):

@@ -96,3 +96,48 @@ def test_alone_equals_batch_with_bodies():
     for a, g in zip(alone, gs):
         assert np.array_equal(a, G.ipc_get_state(g)[0])
         G.ipc_destroy_scene(g)
+
+
+def _expected_bodies(sc):
+    """The coarse space's bodies from scipy's connected components (an independent construction):
+    free vertices joined through tet edges, sets of at least 4, the 4 largest (ties: lowest id)."""
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import connected_components
+    kin = np.asarray(sc["kin_group"])
+    T = np.asarray(sc["tets"])
+    nv = len(kin)
+    free = kin < 0
+    r, c = [], []
+    for a in range(4):
+        for b in range(4):
+            m = free[T[:, a]] & free[T[:, b]]
+            r.append(T[m, a])
+            c.append(T[m, b])
+    A = coo_matrix((np.ones(sum(len(x) for x in r)), (np.concatenate(r), np.concatenate(c))), shape=(nv, nv))
+    _, lab = connected_components(A, directed=False)
+    sets = {}
+    for i in np.where(free)[0]:
+        sets.setdefault(lab[i], []).append(i)
+    sets = sorted((v for v in sets.values() if len(v) >= 4), key=lambda v: (-len(v), v[0]))[:4]
+    vbody = np.full(nv, -1, np.int32)
+    for b, vs in enumerate(sets):
+        vbody[vs] = b
+    return vbody, sets
+
+
+@pytest.mark.parametrize("case", ["cubes5", "cubes2", "grasp"])
+def test_bodies_are_the_largest_connected_sets(case):
+    sc = {"cubes5": lambda: S.stacked_cubes(5), "cubes2": lambda: S.stacked_cubes(2),
+          "grasp": lambda: S.superquadric_grasp(0, tet_median=1500.0)}[case]()
+    g = G.ipc_create_scene(sc)
+    vb, fr = G.ipc_debug_bodies(g)
+    G.ipc_destroy_scene(g)
+    want, sets = _expected_bodies(sc)
+    assert np.array_equal(vb, want)
+    assert len(fr) == len(sets)
+    X = np.asarray(sc["rest_pos"])
+    for b, vs in enumerate(sets):
+        c = X[vs].mean(0)
+        s = np.sqrt(((X[vs] - c) ** 2).sum(1)).max()
+        assert np.abs(fr[b, :3] - c).max() <= 1e-12 * s
+        assert fr[b, 3] == pytest.approx(s, rel=1e-12)
