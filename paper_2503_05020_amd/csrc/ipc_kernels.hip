@@ -2071,6 +2071,7 @@ __global__ void __launch_bounds__(64) k_coarse_factor(const EnvDev *envs, EnvSta
   constexpr int M = kCoarseM;
   __shared__ double A[M * M], Li[M * M];
   __shared__ int bad;
+  __shared__ double tiny;
   const int e = benv[blockIdx.x];
   const EnvDev &E = envs[e];
   const int m = 6 * E.nbody, tid = threadIdx.x;
@@ -2094,12 +2095,20 @@ __global__ void __launch_bounds__(64) k_coarse_factor(const EnvDev *envs, EnvSta
       A[c * M + r] = a;
     }
   }
+  // a pivot below 1e-10 of E's largest diagonal entry (a body whose rigid
+  // motions are not independent, e.g. collinear free vertices) counts as a
+  // failed factorisation: the environment then runs block Jacobi alone
+  if (tid == 0) {
+    double dmax = 0.0;
+    for (int k = 0; k < m; ++k) dmax = fmax(dmax, A[k * M + k]);
+    tiny = 1e-10 * dmax;
+  }
   __syncthreads();
   for (int k = 0; k < m; ++k) {
     if (tid == 0) {
       const double p = A[k * M + k];
-      if (!(p > 0.0)) bad = 1;
-      A[k * M + k] = p > 0.0 ? sqrt(p) : 1.0;
+      if (!(p > tiny)) bad = 1;
+      A[k * M + k] = p > tiny ? sqrt(p) : 1.0;
     }
     __syncthreads();
     for (int r = k + 1 + tid; r < m; r += 64) A[r * M + k] /= A[k * M + k];

@@ -317,6 +317,17 @@ def stacked_cubes(n: int, cells: int = 2, edge: float = 0.03, gap: float = 0.004
     return b.build(static_motion(1), [[0.0, 0.0, -9.81]], **params)
 
 
+def pinned_column(cells: int = 3, h: float = 0.01, **params):
+    """A soft voxel column (1 x 1 x cells cells) whose vertices are all held in place except the
+    cells + 1 on one vertical edge: the only free vertices lie on a line (a body whose rotation
+    about that line moves nothing).  Gravity 9.81."""
+    v, t = voxel_tet_mesh(np.ones((1, 1, cells), bool), h, (0.0, 0.0, 0.005))
+    line = (np.abs(v[:, 0] - v[:, 0].min()) < 1e-12) & (np.abs(v[:, 1] - v[:, 1].min()) < 1e-12)
+    b = _Builder()
+    b.add_body(v, t, 1e5, 0.4, 1000.0, kin=np.where(line, -1, 0))
+    return b.build(static_motion(1), [[0.0, 0.0, -9.81]], **params)
+
+
 def _slab(h: float = 0.004, cells=(2, 4, 10)):
     """Finger slab: cells along (closing, width, length) = 8 x 16 x 40 mm at 4 mm."""
     v, t = voxel_tet_mesh(np.ones(cells, bool), h, (0.0, 0.0, 0.0))

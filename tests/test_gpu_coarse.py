@@ -141,3 +141,35 @@ def test_bodies_are_the_largest_connected_sets(case):
         s = np.sqrt(((X[vs] - c) ** 2).sum(1)).max()
         assert np.abs(fr[b, :3] - c).max() <= 1e-12 * s
         assert fr[b, 3] == pytest.approx(s, rel=1e-12)
+
+
+def test_degenerate_body_runs_block_jacobi():
+    """Free vertices on one line (at the rest shape): E = Z^T H Z is singular (the rotation about
+    the line moves nothing), the factorisation is refused and the environment runs block Jacobi
+    alone -- the same bits as with the coarse space off -- matching the oracle; the steps that
+    follow (the line bends slightly, E is then merely ill-conditioned) still track the oracle."""
+    sc = S.pinned_column()
+    g = G.ipc_create_scene(sc, pcg_rel_tol=1e-8)
+    o = O.Scene(sc, pcg_rel_tol=1e-8)
+    vb, fr = G.ipc_debug_bodies(g)
+    assert len(fr) == 1 and int((vb == 0).sum()) == 4
+    G.ipc_debug_begin_step(g)
+    xo = o.begin_step()
+    po, _ = o.newton_dir(xo)
+    out = {}
+    for on in (1, 0):
+        _set_coarse(on)
+        out[on] = G.ipc_debug_newton_dir(g, xo)
+    _set_coarse(1)
+    assert np.array_equal(out[1][0], out[0][0]) and out[1][1] == out[0][1]
+    assert np.abs(out[1][0] - po).max() <= 1e-6 * np.abs(po).max()
+    G.ipc_destroy_scene(g)
+    g = G.ipc_create_scene(sc, pcg_rel_tol=1e-8)
+    o = O.Scene(sc, pcg_rel_tol=1e-8)
+    for _ in range(4):
+        assert G.ipc_step(g, 1)[0] == 0
+        assert o.step(1)[0] == 0
+        pg, _ = G.ipc_get_state(g)
+        po, _ = o.state()
+        assert np.abs(pg - po).max() <= 1e-6 * sc["env_bbox_diag"]
+    G.ipc_destroy_scene(g)
