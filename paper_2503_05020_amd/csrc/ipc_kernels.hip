@@ -2029,7 +2029,7 @@ __global__ void __launch_bounds__(256) k_coarse_hz(WorldDev W, const EnvDev *env
         const int j = cr_col[h.cb + k];
         if (W.vbody[j] == bb) coarse_block_acc(cr_val + 9 * (size_t)(h.cb + k), 1, E, bb, W.x, j, Y);
       }
-      // (H Z)_i for the update of the two-level PCG (every row: a dof row
+      // (H Z)_i for the product of the two-level PCG (every row: a dof row
       // outside the bodies may neighbour them)
       for (int r = 0; r < 3; ++r)
         for (int c = 0; c < 6; ++c) {
@@ -2065,7 +2065,8 @@ __global__ void __launch_bounds__(256) k_coarse_hz(WorldDev W, const EnvDev *env
 
 // E from the tiles (tile order), symmetrised, Cholesky-factored and inverted
 // (E^-1 = L^-T L^-1) in LDS by one 64-thread block per environment; cok = 0
-// when a pivot is not positive (the environment then runs block Jacobi alone)
+// when a pivot is below 1e-10 of E's largest diagonal entry (the environment
+// then runs block Jacobi alone)
 __global__ void __launch_bounds__(64) k_coarse_factor(const EnvDev *envs, EnvState S, const int *benv,
                                                       const double *e_tile) {
   constexpr int M = kCoarseM;
