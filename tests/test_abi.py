@@ -42,3 +42,14 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(ipc, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError):
         ipc.lib()
+
+
+def test_binding_constants_match_header():
+    """Every integer #define of include/ipc.h that the binding also names has the same value."""
+    from paper_2503_05020_amd import ipc
+    src = open(HEADER).read()
+    defs = dict(re.findall(r"#define\s+(IPC_\w+)\s+\(?(-?\d+)\)?\s*$", src, flags=re.M))
+    shared = [n for n in defs if hasattr(ipc, n)]
+    assert "IPC_TUNE_COARSE" in shared and "IPC_COARSE_BODIES" in shared
+    for n in shared:
+        assert getattr(ipc, n) == int(defs[n]), n
