@@ -90,11 +90,22 @@ def run_gpu(scs, precision, warmup, steps, pcg_tol, label, count_all=False, auto
     pcg = sum(i["pcg_iters"] for i in infos)
     log(f"[{label}] {steps} timed steps: converged {converged}/{len(gs) * steps} env-steps")
     prof = G.ipc_prof_read()
+    pairs = G.ipc_prof_pairs()
     failed = sum(1 for g in gs if G.ipc_scene_sizes(g)[6])
     for g in gs:
         G.ipc_destroy_scene(g)
-    return dict(wall=wall, converged=converged, newton=newton, pcg=pcg, prof=prof, failed=failed,
+    return dict(wall=wall, converged=converged, newton=newton, pcg=pcg, prof=prof, pairs=pairs, failed=failed,
                 value=converged / wall, ms_per_step=1e3 * wall / steps)
+
+
+def contact_rates(r):
+    """Contact work per second of the timed window (all lanes): candidate pairs classified and barrier /
+    friction elements evaluated (gradient + projected Hessian) by the assembly passes."""
+    w = r["wall"]
+    p = r["pairs"]
+    return {"candidates_classified_per_s": round(p["candidates"] / w), "barrier_elems_per_s": round(p["barrier_elems"] / w),
+            "friction_elems_per_s": round(p["friction_elems"] / w),
+            "contact_pair_evals_per_s": round((p["barrier_elems"] + p["friction_elems"]) / w)}
 
 
 def sequential_gpu(scs, precision, warmup, steps, pcg_tol, n):
@@ -452,13 +463,15 @@ def main():
         "pcg_iters": r["pcg"],
         "failed_envs": r["failed"],
         "roofline": roofline(r["prof"], main_p),
+        "contact": contact_rates(r),
         "cpu_baseline": cpu,
         "serving": serve,
     }
     if "fp64" in results and main_p != "fp64":
         f = results["fp64"]
         out["fp64"] = {"value": round(f["value"], 2), "ms_per_step": round(f["ms_per_step"], 2),
-                       "failed_envs": f["failed"], "roofline": roofline(f["prof"], "fp64")}
+                       "failed_envs": f["failed"], "roofline": roofline(f["prof"], "fp64"),
+                       "contact": contact_rates(f)}
     if horizon:
         out["full_horizon"] = horizon
     if rel:

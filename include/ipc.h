@@ -180,6 +180,14 @@ int ipc_scene_sizes(ipc_scene s, int64_t out[7]);
 int ipc_prof_enable(int32_t on);
 int ipc_prof_reset(void);
 int ipc_prof_read(double *out);
+/* Contact work since the last reset while measurement is enabled (sums over
+ * the device's lanes), counted per assembly pass of a Newton iteration
+ * (Sec. II-C: the barrier and friction terms of the incremental potential):
+ * out[0] candidate pairs classified (closest-point type and distance),
+ * out[1] active barrier pair elements evaluated (energy gradient and
+ * PSD-projected Hessian), out[2] lagged friction elements evaluated.
+ * Line-search energy passes are not counted. */
+int ipc_prof_pairs(double *out);
 
 /* Execution knobs of the current device's solver.  They change how work is
  * scheduled, never a result: the tiled PCG kernels and the per-environment

@@ -689,8 +689,11 @@ struct World {
   double prof_ms = 0.0, prof_ms_big = 0.0;  // big: launches over more than kWideTiles tiles
   long long prof_launches = 0, prof_launches_big = 0;
   double prof_ms_iter = 0.0, prof_ms_asm = 0.0;
-  long long prof_skipped = 0;  // timed samples whose events were not recorded  // whole PCG iterations (product + update); assembly passes
-  long long prof_asm = 0;
+  long long prof_skipped = 0;  // timed samples whose events were not recorded
+  long long prof_asm = 0;      // assembly passes
+  // contact work of the assembly passes: candidate pairs classified, barrier
+  // pair elements and friction elements evaluated (gradient and projected Hessian)
+  long long prof_cands = 0, prof_bar = 0, prof_fric = 0;
   std::vector<hipEvent_t> asm_ev;  // event pairs around the assembly passes of the current step
   int n_fric = 0;
   std::mutex mu;
@@ -1222,6 +1225,7 @@ struct World {
     prof_ms = prof_ms_big = prof_ms_iter = prof_ms_asm = 0.0;
     prof_skipped = 0;
     prof_launches = prof_launches_big = prof_asm = 0;
+    prof_cands = prof_bar = prof_fric = 0;
     if (prof_bytes.p) {
       HC(hipMemsetAsync(prof_bytes.p, 0, 32, stream));
       HC(hipStreamSynchronize(stream));
@@ -1434,6 +1438,11 @@ struct World {
     ipck::barrier_elems(stream, W, envs_d, S, L, na, W.x);
     ipck::friction_elems(stream, W, envs_d, S, L, n_fric, na, W.x);
     int nce = na + n_fric;
+    if (prof_on) {
+      prof_cands += nc;
+      prof_bar += na;
+      prof_fric += n_fric;
+    }
     int nvw = (int)aV.cap;
     ipck::incidence(stream, W, S, L, nce, nvw);
     int ntot = read_int(L.inc_off + nvw);
@@ -2944,6 +2953,20 @@ int ipc_prof_read(double *out) {
       out[9] += w.prof_ms_asm;
       out[10] += (double)w.prof_asm;
       out[11] += (double)b[3];
+    }
+    return IPC_OK;
+  });
+}
+
+int ipc_prof_pairs(double *out) {
+  return guarded([&]() {
+    if (!out) throw ApiError(IPC_E_ARG, "null output");
+    for (int k = 0; k < 3; ++k) out[k] = 0.0;
+    for (World *pw : worlds_for_current_device()) {
+      std::lock_guard<std::mutex> lk(pw->mu);
+      out[0] += (double)pw->prof_cands;
+      out[1] += (double)pw->prof_bar;
+      out[2] += (double)pw->prof_fric;
     }
     return IPC_OK;
   });

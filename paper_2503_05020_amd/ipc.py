@@ -73,7 +73,7 @@ EXPORTS = [
     "ipc_debug_ccd_bound", "ipc_debug_classify", "ipc_debug_pair_barrier", "ipc_debug_tet_elastic",
     "ipc_debug_accd", "ipc_debug_inversion_bound", "ipc_debug_tet_first_root", "ipc_ccd_bound_pairs",
     "ipc_ccd_bound_pairs_noalloc", "ipc_grasp_metrics", "ipc_hold_group", "ipc_set_gravity", "ipc_contact_forces",
-    "ipc_validate_grasp", "ipc_prof_enable", "ipc_prof_reset", "ipc_prof_read", "ipc_set_tuning", "ipc_get_tuning", "ipc_autotune",
+    "ipc_validate_grasp", "ipc_prof_enable", "ipc_prof_reset", "ipc_prof_read", "ipc_prof_pairs", "ipc_set_tuning", "ipc_get_tuning", "ipc_autotune",
     "ipc_server_create", "ipc_server_submit", "ipc_server_poll", "ipc_server_wait", "ipc_server_result",
     "ipc_server_release", "ipc_server_set_slots", "ipc_server_stats", "ipc_server_destroy",
 ]
@@ -161,6 +161,7 @@ def lib():
     L.ipc_debug_tet_first_root.restype = C.c_int64
     L.ipc_prof_enable.argtypes = [C.c_int32]
     L.ipc_prof_read.argtypes = [_dp]
+    L.ipc_prof_pairs.argtypes = [_dp]
     L.ipc_set_tuning.argtypes = [C.c_int32, C.c_int64]
     L.ipc_get_tuning.argtypes = [C.c_int32, C.POINTER(C.c_int64)]
     L.ipc_autotune.argtypes = [C.POINTER(vp), C.c_int32, C.c_int32, C.c_char_p, C.POINTER(C.c_int64)]
@@ -320,6 +321,13 @@ def ipc_prof_read():
             "big_ms": float(out[3]), "big_launches": int(out[4]), "big_bytes": float(out[5]),
             "iter_ms": float(out[6]), "iters": int(out[7]), "iter_bytes": float(out[8]),
             "asm_ms": float(out[9]), "asm_passes": int(out[10]), "asm_bytes": float(out[11])}
+
+
+def ipc_prof_pairs():
+    """Contact work since the last reset: candidates classified, barrier and friction elements evaluated."""
+    out = np.zeros(3)
+    _check(lib().ipc_prof_pairs(_d(out)))
+    return {"candidates": int(out[0]), "barrier_elems": int(out[1]), "friction_elems": int(out[2])}
 
 
 def ipc_set_tuning(key: int, value: int):

@@ -202,3 +202,31 @@ def test_contact_statistics_match_oracle():
             assert ig["min_dist_last"] == pytest.approx(io["min_dist_last"], rel=1e-6)
             assert 0 < ig["min_dist_last"] < sc["dhat"]
     assert seen > 5
+
+
+def test_contact_work_counters():
+    """ipc_prof_pairs: zero after a reset, no barrier or friction elements without contact, and with
+    resting contact at least the last iterate's active pairs per step, classified from more candidates."""
+    G.ipc_prof_enable(1)
+    try:
+        G.ipc_prof_reset()
+        assert G.ipc_prof_pairs() == {"candidates": 0, "barrier_elems": 0, "friction_elems": 0}
+        g = G.ipc_create_scene(S.free_block())
+        assert G.ipc_step(g, 3)[0] == 0
+        c = G.ipc_prof_pairs()
+        G.ipc_destroy_scene(g)
+        assert c["barrier_elems"] == 0 and c["friction_elems"] == 0
+        sc = S.soft_cube_drop()
+        g = G.ipc_create_scene(sc)
+        assert G.ipc_step(g, 14)[0] == 0
+        G.ipc_prof_reset()
+        rc, info = G.ipc_step(g, 1)
+        assert rc == 0 and info["n_active_last"] > 0
+        c = G.ipc_prof_pairs()
+        G.ipc_destroy_scene(g)
+        assert c["barrier_elems"] >= info["n_active_last"]
+        assert c["candidates"] >= c["barrier_elems"]
+        assert c["friction_elems"] > 0
+    finally:
+        G.ipc_prof_reset()
+        G.ipc_prof_enable(0)
