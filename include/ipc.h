@@ -222,7 +222,7 @@ int ipc_prof_pairs(double *out);
  *                   with a group of 8 lanes; 0: one lane per query
  *   IPC_PIPELINE    1 (default): the next block of PCG iterations is queued
  *                   before the host polls the previous one
- *   IPC_POLL_BLOCK  PCG iterations per poll (default 16)
+ *   IPC_POLL_BLOCK  PCG iterations per poll (default 8 mixed, 4 FP64)
  *   IPC_NARROW_PCT  the batch is laid out again once at most this percentage
  *                   of it still iterates its Newton loop (default 50)
  *   IPC_WIDE_TILES  PCG product launches over at most this many tiles issue
@@ -248,8 +248,9 @@ int ipc_prof_pairs(double *out);
 /* IPC_TUNE_WIDE_TILES: PCG product launches over at most this many tiles
  * issue each lane's slots four at a time (0 = none; -1 = the default: every
  * FP64 launch and no mixed one; initial value from IPC_WIDE_TILES, else -1).
- * IPC_TUNE_POLL_BLOCK: PCG iterations queued per host poll, 1..1024 (initial
- * value IPC_POLL_BLOCK, else 16).  Neither changes a result. */
+ * IPC_TUNE_POLL_BLOCK: PCG iterations queued per host poll, 1..1024, or -1 =
+ * the default: 8 in mixed precision, 4 in FP64 (initial value IPC_POLL_BLOCK,
+ * else -1).  Neither changes a result. */
 #define IPC_TUNE_WIDE_TILES 8
 #define IPC_TUNE_POLL_BLOCK 9
 /* IPC_TUNE_COARSE: 1 (default; IPC_COARSE) = two-level PCG: block Jacobi plus
@@ -269,7 +270,7 @@ int ipc_get_tuning(int32_t key, int64_t *value);
  * a line for this workload (key: scene count, total tets to three significant
  * digits, precisions, lane count), its values are applied and out[2] = 1.
  * Otherwise the current setting and each of the candidates {0, 64, all
- * tiles} x {8, 16, 32} are timed (twice each, the faster run counting) over
+ * tiles} x {4, 8, 16} are timed (twice each, the faster run counting) over
  * `steps` (1..64) time steps of copies of the n scenes set to their current
  * state (the copies take device memory alongside the scenes while the call
  * runs; the scenes themselves are not stepped); the fastest candidate

@@ -1491,8 +1491,9 @@ public:
   // 1: the next block of PCG iterations is queued before the host polls the
   // previous one (0: after it)
   const int pipeline = env_knob("IPC_PIPELINE", 1) ? 1 : 0;
-  // PCG iterations per block between polls of the pending count
-  int poll_block = std::max(1, env_knob("IPC_POLL_BLOCK", 16));
+  // PCG iterations per block between polls of the pending count (-1: 8 in
+  // mixed precision, 4 in FP64)
+  int poll_block = env_knob("IPC_POLL_BLOCK", -1) > 0 ? env_knob("IPC_POLL_BLOCK", -1) : -1;
   // the batch is laid out again once at most this percentage of it still
   // iterates its Newton loop
   const int narrow_pct = std::min(100, env_knob("IPC_NARROW_PCT", 50));
@@ -1577,8 +1578,9 @@ public:
     // waits for the count of environments still iterating after block k, so
     // the device does not idle while the host polls.  A block queued after
     // every solve has stopped costs only launches whose tiles exit at once.
+    const int pb = poll_block > 0 ? poll_block : mixed ? 8 : 4;
     auto launch_block = [&](int slot) {
-      for (int j = 0; j < poll_block; ++j) {
+      for (int j = 0; j < pb; ++j) {
         // every 16th iteration is timed (the product and the update carry
         // start and end events in their dispatches) and counts its
         // algorithmic bytes in a launch of its own between the two kernels;
@@ -2722,7 +2724,7 @@ int ipc_prof_enable(int32_t on) {
 
 int ipc_set_tuning(int32_t key, int64_t value) {
   return guarded([&]() {
-    if (value < 0 && !(key == IPC_TUNE_WIDE_TILES && value == -1))
+    if (value < 0 && !((key == IPC_TUNE_WIDE_TILES || key == IPC_TUNE_POLL_BLOCK) && value == -1))
       throw ApiError(IPC_E_ARG, "tuning value must be >= 0");
     if (key == IPC_TUNE_LANES) {
       if (value < 1 || value > 16) throw ApiError(IPC_E_ARG, "lanes must be in [1, 16]");
@@ -2734,8 +2736,8 @@ int ipc_set_tuning(int32_t key, int64_t value) {
         key != IPC_TUNE_ADMIT_FAULTS && key != IPC_TUNE_ASYNC && key != IPC_TUNE_WIDE_TILES &&
         key != IPC_TUNE_POLL_BLOCK && key != IPC_TUNE_COARSE)
       throw ApiError(IPC_E_ARG, "unknown tuning key");
-    if (key == IPC_TUNE_POLL_BLOCK && (value < 1 || value > 1024))
-      throw ApiError(IPC_E_ARG, "poll block must be in [1, 1024]");
+    if (key == IPC_TUNE_POLL_BLOCK && value != -1 && (value < 1 || value > 1024))
+      throw ApiError(IPC_E_ARG, "poll block must be -1 or in [1, 1024]");
     for (World *pw : worlds_for_current_device()) {
       World &w = *pw;
       std::lock_guard<std::mutex> lk(w.mu);
@@ -2782,7 +2784,7 @@ int ipc_get_tuning(int32_t key, int64_t *value) {
     else if (key == IPC_TUNE_WIDE_TILES)
       *value = w.wide_tiles;  // -1: the default (every FP64 launch, no mixed one)
     else if (key == IPC_TUNE_POLL_BLOCK)
-      *value = w.poll_block;
+      *value = w.poll_block;  // -1: the default (8 mixed, 4 FP64)
     else if (key == IPC_TUNE_COARSE)
       *value = w.coarse;
     else
@@ -2837,7 +2839,8 @@ int ipc_autotune(const ipc_scene *scenes, int32_t n, int32_t steps, const char *
         if (tab == std::string::npos || line.compare(0, tab, key) != 0 || tab != std::strlen(key)) continue;
         long long wide = 0, poll = 0;
         double ms = 0.0;
-        if (std::sscanf(line.c_str() + tab + 1, "%lld %lld %lf", &wide, &poll, &ms) == 3 && poll >= 1) {
+        if (std::sscanf(line.c_str() + tab + 1, "%lld %lld %lf", &wide, &poll, &ms) == 3 &&
+            (poll == -1 || (poll >= 1 && poll <= 1024))) {
           apply(wide, poll);
           out[0] = wide;
           out[1] = poll;
@@ -2876,7 +2879,7 @@ int ipc_autotune(const ipc_scene *scenes, int32_t n, int32_t steps, const char *
       World &w0 = world_for_current_device();
       std::vector<std::pair<int64_t, int64_t>> cand = {{w0.wide_tiles, w0.poll_block}};
       for (int64_t wd : {int64_t(0), int64_t(64), int64_t(1) << 30})
-        for (int64_t pl : {int64_t(8), int64_t(16), int64_t(32)})
+        for (int64_t pl : {int64_t(4), int64_t(8), int64_t(16)})
           if (!(wd == cand[0].first && pl == cand[0].second)) cand.push_back({wd, pl});
       double best = HUGE_VAL, current = HUGE_VAL;
       int64_t bw = cand[0].first, bp = cand[0].second;
