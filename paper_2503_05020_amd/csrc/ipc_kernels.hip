@@ -1349,6 +1349,41 @@ DEV double tile_sums8(const double v[8], double *sh) {
   return out;
 }
 
+// sums of v[0..P) over the 256 threads of a tile (one row each), P = 8, 16,
+// 32 or 64: the transposed butterfly of tile_sums8 with log2 P halving
+// exchanges (32, 16, ...) and the full butterfly over the exchanges left,
+// then the four wavefront sums as (w0 + w1) + (w2 + w3).  Thread k < P gets
+// sum k (others 0).  Every thread of the block calls it.  sh: 4 P doubles.
+template <int P>
+DEV double tile_sums_tr(const double v[P], double *sh) {
+  static_assert(P == 8 || P == 16 || P == 32 || P == 64, "P");
+  const int ln = threadIdx.x & 63;
+  double a[P];
+#pragma unroll
+  for (int k = 0; k < P; ++k) a[k] = v[k];
+  int idx = 0;
+#pragma unroll
+  for (int m = 32, h = P / 2; h >= 1; m >>= 1, h >>= 1) {
+    const bool hi = ln & m;
+#pragma unroll
+    for (int j = 0; j < h; ++j) a[j] = (hi ? a[j + h] : a[j]) + __shfl_xor(hi ? a[j] : a[j + h], m, 64);
+    idx += hi ? h : 0;
+  }
+  constexpr int group = 64 / P;  // lanes left holding the same value
+#pragma unroll
+  for (int m = group / 2; m > 0; m >>= 1) a[0] += __shfl_xor(a[0], m, 64);
+  const int wv = threadIdx.x / 64;
+  if (ln % group == 0) sh[wv * P + idx] = a[0];
+  __syncthreads();
+  double out = 0.0;
+  if ((int)threadIdx.x < P) {
+    const int k = threadIdx.x;
+    out = (sh[k] + sh[P + k]) + (sh[2 * P + k] + sh[3 * P + k]);
+  }
+  __syncthreads();
+  return out;
+}
+
 // the vector a product reads: stored, or the next direction formed on the fly
 template <typename T>
 struct StoredVec {
@@ -1957,21 +1992,31 @@ __global__ void k_pcg_update(WorldDev W, const EnvDev *envs, EnvState S, const T
     }
     return;
   }
-  // two-level PCG: Z^T r of the new residual per body, reduced together
-  // with r.u and r.r (with the first body)
+  // two-level PCG: Z^T r of the new residual (six values per body) reduced
+  // together with r.u and r.r in one pass of P = 8, 16 or 32 values
   double zr[6] = {0, 0, 0, 0, 0, 0};
   if (bi >= 0) coarse_zt_x(E, bi, xi, rn, zr);
-  for (int b = 0; b < E.nbody; ++b) {
-    double vals[8];
+  const int m = 6 * E.nbody;
+  auto reduce = [&](auto tag) {
+    constexpr int P = decltype(tag)::value;
+    double vals[P];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) vals[k] = bi == b ? zr[k] : 0.0;
-    vals[6] = b == 0 ? g : 0.0;
-    vals[7] = b == 0 ? rr2 : 0.0;
-    const double sum = tile_sums8(vals, sh);
-    if ((int)threadIdx.x < 6) part_z[(size_t)slot * kCoarseM + 6 * b + threadIdx.x] = sum;
-    if (b == 0 && threadIdx.x == 6) part_g_new[slot] = sum;
-    if (b == 0 && threadIdx.x == 7) part_rr_new[slot] = sum;
-  }
+    for (int k = 0; k < P; ++k) vals[k] = 0.0;
+#pragma unroll
+    for (int k = 0; k < P - 2; ++k) vals[k] = (bi >= 0 && k / 6 == bi) ? zr[k % 6] : 0.0;
+    vals[P - 2] = g;
+    vals[P - 1] = rr2;
+    const double sum = tile_sums_tr<P>(vals, sh);
+    if ((int)threadIdx.x < m) part_z[(size_t)slot * kCoarseM + threadIdx.x] = sum;
+    if (threadIdx.x == P - 2) part_g_new[slot] = sum;
+    if (threadIdx.x == P - 1) part_rr_new[slot] = sum;
+  };
+  if (m <= 6)
+    reduce(std::integral_constant<int, 8>());
+  else if (m <= 14)
+    reduce(std::integral_constant<int, 16>());
+  else
+    reduce(std::integral_constant<int, 32>());
 }
 
 // ---------------------------------------------------------------------------
