@@ -458,7 +458,9 @@ def main():
         "dtype": "f64+f32pcg" if main_p == "mixed" else "f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "envs": len(scs), "tets": ntets, "precision": main_p,
-                   "pcg_rel_tol": args.pcg_tol, "first_timed_step": args.warmup},
+                   "pcg_rel_tol": args.pcg_tol, "first_timed_step": args.warmup,
+                   "pcg_preconditioner": "two-level (block Jacobi + rigid-body coarse space)"
+                   if G.ipc_get_tuning(G.IPC_TUNE_COARSE) else "block Jacobi"},
         "newton_iters": r["newton"],
         "pcg_iters": r["pcg"],
         "failed_envs": r["failed"],
