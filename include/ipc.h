@@ -163,7 +163,11 @@ int ipc_scene_sizes(ipc_scene s, int64_t out[7]);
  * for the product the stored 3x3 blocks and column indices (sliced ELL and
  * merged contact blocks) plus one read of u and one write of w per row; for
  * the whole iteration the same blocks plus per row the preconditioner block
- * and eight vector accesses of three values (N (9 s + 4) + n 9 s + 24 n s).
+ * and eight vector accesses of three values (N (9 s + 4) + n 9 s + 24 n s);
+ * with the two-level PCG (m = 6 x bodies) the product adds per row its 3 m
+ * entries of H Z, its body index and, in a body, its position (3 m s + 4 +
+ * 24), and the iteration adds the update's body index and position reads and
+ * its m partials per tile.
  * Every assembly pass (elasticity, inertia, gradient and stored blocks) is
  * timed too, from the start of its first kernel to the end of its last, its
  * algorithmic bytes (per tet 208 B of inputs, per row
