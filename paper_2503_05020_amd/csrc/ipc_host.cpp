@@ -587,8 +587,11 @@ std::unique_ptr<HostScene> preprocess(const ipc_scene_desc *d) {
   }
   // coarse space of the two-level PCG: the connected sets of free vertices
   // (joined through tets), the kCoarseBodies largest with at least 4
-  // vertices (ties: lowest vertex id), each with its rest centroid and the
-  // largest rest distance from it
+  // vertices (ties: lowest vertex id); while a slot is left and the largest
+  // set has at least 64 vertices, that set is split in two halves at the
+  // median of its rest positions along the longest axis of their box (ties:
+  // vertex order), which then take the first two slots.  Each piece has its
+  // rest centroid and the largest rest distance from it.
   {
     std::vector<int> par(H.nv);
     for (int i = 0; i < H.nv; ++i) par[i] = i;
@@ -612,9 +615,29 @@ std::unique_ptr<HostScene> preprocess(const ipc_scene_desc *d) {
     std::stable_sort(order.begin(), order.end(),
                      [](const std::vector<int> *a, const std::vector<int> *b) { return a->size() > b->size(); });
     H.vbody.assign(H.nv_pad, -1);
-    H.nbody = (int)std::min<size_t>(order.size(), ipcw::kCoarseBodies);
+    std::vector<std::vector<int>> pieces;
+    for (size_t k = 0; k < std::min<size_t>(order.size(), ipcw::kCoarseBodies); ++k) pieces.push_back(*order[k]);
+    if (!pieces.empty() && pieces.size() < (size_t)ipcw::kCoarseBodies && pieces[0].size() >= 64) {
+      std::vector<int> vs = pieces[0];
+      double lo[3] = {HUGE_VAL, HUGE_VAL, HUGE_VAL}, hi[3] = {-HUGE_VAL, -HUGE_VAL, -HUGE_VAL};
+      for (int i : vs)
+        for (int k = 0; k < 3; ++k) {
+          lo[k] = std::min(lo[k], H.X[3 * i + k]);
+          hi[k] = std::max(hi[k], H.X[3 * i + k]);
+        }
+      int ax = 0;
+      for (int k = 1; k < 3; ++k)
+        if (hi[k] - lo[k] > hi[ax] - lo[ax]) ax = k;
+      std::stable_sort(vs.begin(), vs.end(), [&](int u, int v) { return H.X[3 * u + ax] < H.X[3 * v + ax]; });
+      std::vector<int> first(vs.begin(), vs.begin() + vs.size() / 2), second(vs.begin() + vs.size() / 2, vs.end());
+      std::sort(first.begin(), first.end());
+      std::sort(second.begin(), second.end());
+      pieces[0] = first;
+      pieces.insert(pieces.begin() + 1, second);
+    }
+    H.nbody = (int)pieces.size();
     for (int b = 0; b < H.nbody; ++b) {
-      const std::vector<int> &vs = *order[b];
+      const std::vector<int> &vs = pieces[b];
       double c[3] = {0, 0, 0};
       for (int i : vs)
         for (int k = 0; k < 3; ++k) c[k] += H.X[3 * i + k];

@@ -100,7 +100,9 @@ def test_alone_equals_batch_with_bodies():
 
 def _expected_bodies(sc):
     """The coarse space's bodies from scipy's connected components (an independent construction):
-    free vertices joined through tet edges, sets of at least 4, the 4 largest (ties: lowest id)."""
+    free vertices joined through tet edges, sets of at least 4, the 4 largest (ties: lowest id);
+    with a slot left and at least 64 vertices, the largest split at the median of its rest positions
+    along the longest axis of their box (ties: vertex order) into the first two pieces."""
     from scipy.sparse import coo_matrix
     from scipy.sparse.csgraph import connected_components
     kin = np.asarray(sc["kin_group"])
@@ -119,15 +121,22 @@ def _expected_bodies(sc):
     for i in np.where(free)[0]:
         sets.setdefault(lab[i], []).append(i)
     sets = sorted((v for v in sets.values() if len(v) >= 4), key=lambda v: (-len(v), v[0]))[:4]
+    if 0 < len(sets) < 4 and len(sets[0]) >= 64:
+        X = np.asarray(sc["rest_pos"])
+        vs = sets[0]
+        ax = int(np.argmax(X[vs].max(0) - X[vs].min(0)))
+        srt = sorted(vs, key=lambda i: X[i, ax])  # stable: ties keep ascending ids
+        sets[0:1] = [sorted(srt[:len(srt) // 2]), sorted(srt[len(srt) // 2:])]
     vbody = np.full(nv, -1, np.int32)
     for b, vs in enumerate(sets):
         vbody[vs] = b
     return vbody, sets
 
 
-@pytest.mark.parametrize("case", ["cubes5", "cubes2", "grasp"])
+@pytest.mark.parametrize("case", ["cubes5", "cubes2", "bigcubes2", "grasp"])
 def test_bodies_are_the_largest_connected_sets(case):
     sc = {"cubes5": lambda: S.stacked_cubes(5), "cubes2": lambda: S.stacked_cubes(2),
+          "bigcubes2": lambda: S.stacked_cubes(2, cells=3),
           "grasp": lambda: S.superquadric_grasp(0, tet_median=1500.0)}[case]()
     g = G.ipc_create_scene(sc)
     vb, fr = G.ipc_debug_bodies(g)
