@@ -260,7 +260,9 @@ int ipc_prof_pairs(double *out);
 /* IPC_TUNE_COARSE: 1 (default; IPC_COARSE) = two-level PCG: block Jacobi plus
  * an exact solve on the rigid motions (3 translations, 3 rotations) of each
  * body of an environment (its connected sets of free vertices, the 4 largest
- * with at least 4 vertices); 0 = block Jacobi alone.  Unlike the other knobs
+ * with at least 4 vertices; while one of the 4 slots is left, the largest set,
+ * if it has at least 64 vertices, in two halves along its longest axis);
+ * 0 = block Jacobi alone.  Unlike the other knobs
  * it changes the PCG's iterates, within its stopping tolerance; results stay
  * the same alone and in any batch.  While it is on, IPC_TUNE_FUSED_PCG and
  * IPC_TUNE_TAIL_TILES have no effect (those kernels are block Jacobi only).
@@ -435,8 +437,8 @@ int ipc_debug_newton_dir(ipc_scene s, const double *x, double *p, int64_t *pcg_i
 
 /* Coarse space of the two-level PCG as built at creation (a utility for tests;
  * no passage of the paper defines it): vbody[n_verts] receives each vertex's
- * body (0 .. nbody-1; -1 for kinematic vertices and free vertices outside the
- * bodies), frame[4 * nbody] each body's reference point and size (x, y, z, s:
+ * body (0 .. nbody-1, a split largest set taking 0 and 1; -1 for kinematic
+ * vertices and free vertices outside the bodies), frame[4 * nbody] each body's reference point and size (x, y, z, s:
  * the rest centroid of its vertices, summed in vertex order, and the largest
  * rest distance from it).  Either pointer may be null; frame must hold
  * 4 * IPC_COARSE_BODIES doubles.  Returns nbody (0 .. IPC_COARSE_BODIES) or
